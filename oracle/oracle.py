@@ -1,0 +1,285 @@
+"""ctypes front end of the CPU oracle (test infrastructure only).
+
+Wraps ``liboracle.so`` built from ``chsim_oracle.cpp``.  Only the tests, the
+smoke check and the benchmark's CPU-baseline leg use it.  Each function names
+the passage of Bravyi et al., arXiv:1808.00128, that the C++ code follows.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+
+_lib = None
+
+u8p = np.ctypeslib.ndpointer(dtype=np.uint8, flags="C_CONTIGUOUS")
+u32p = np.ctypeslib.ndpointer(dtype=np.uint32, flags="C_CONTIGUOUS")
+u64p = np.ctypeslib.ndpointer(dtype=np.uint64, flags="C_CONTIGUOUS")
+f64p = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+i32p = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+
+
+def lib():
+    """Load (building first if needed) the oracle library."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        from .build_oracle import build
+
+        build()
+    L = C.CDLL(LIB_PATH)
+    L.orc_philox.argtypes = [u32p, u32p, u32p]
+    L.orc_uniform.argtypes = [C.c_uint64, C.c_uint64, C.c_uint32, C.c_uint32]
+    L.orc_uniform.restype = C.c_double
+    L.orc_stream_sparsify.restype = C.c_uint32
+    L.orc_coverage.argtypes = [np.ctypeslib.ndpointer(dtype=np.int64), C.c_int]
+    L.orc_ch_new.argtypes = [C.c_int]
+    L.orc_ch_new.restype = C.c_void_p
+    L.orc_ch_free.argtypes = [C.c_void_p]
+    L.orc_ch_apply.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int]
+    L.orc_ch_apply_right.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int]
+    L.orc_ch_export.argtypes = [C.c_void_p, u64p, u64p, u64p, u8p, u64p, u64p, i32p]
+    L.orc_ch_amplitude.argtypes = [C.c_void_p, C.c_uint64, C.POINTER(C.c_int), C.POINTER(C.c_int)]
+    L.orc_ch_sample.argtypes = [C.c_void_p, C.c_uint64]
+    L.orc_ch_sample.restype = C.c_uint64
+    L.orc_ch_check.argtypes = [C.c_void_p]
+    L.orc_ch_inner.argtypes = [C.c_void_p, u64p, u8p, C.POINTER(C.c_int), C.POINTER(C.c_int)]
+    L.orc_phase_decomp.argtypes = [C.c_double, f64p, C.POINTER(C.c_int)]
+    L.orc_expsum.argtypes = [C.c_int, u8p, i32p]
+    L.orc_terms_build.argtypes = [C.c_int, C.c_int, u8p, u8p, u8p, C.c_int, f64p, C.c_uint64,
+                                  C.c_int, C.c_uint64, C.c_void_p, C.c_uint64, C.c_int]
+    L.orc_terms_build.restype = C.c_void_p
+    L.orc_terms_free.argtypes = [C.c_void_p]
+    L.orc_terms_error.argtypes = [C.c_void_p]
+    L.orc_terms_l1.argtypes = [C.c_void_p]
+    L.orc_terms_l1.restype = C.c_double
+    L.orc_terms_count.argtypes = [C.c_void_p]
+    L.orc_terms_count.restype = C.c_uint64
+    L.orc_terms_ch.argtypes = [C.c_void_p, C.c_uint64]
+    L.orc_terms_ch.restype = C.c_void_p
+    L.orc_terms_b.argtypes = [C.c_void_p, C.c_uint64, f64p]
+    L.orc_terms_branch.argtypes = [C.c_void_p, C.c_uint64, u8p]
+    L.orc_terms_amplitudes.argtypes = [C.c_void_p, u64p, C.c_uint64, f64p, C.c_int]
+    L.orc_terms_inner.argtypes = [C.c_void_p, u64p, u8p, C.c_uint64, f64p, f64p, C.c_int]
+    L.orc_metropolis.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, u64p, u32p, f64p, u64p, u8p,
+                                 f64p, C.c_int]
+    _lib = L
+    return L
+
+
+def default_threads() -> int:
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+# ---------------------------------------------------------------------------
+# Counter-based generator (Philox4x32-10) and the uniform it feeds.
+# ---------------------------------------------------------------------------
+def philox(ctr, key):
+    out = np.zeros(4, np.uint32)
+    lib().orc_philox(np.asarray(ctr, np.uint32), np.asarray(key, np.uint32), out)
+    return out
+
+
+def uniform(seed: int, index: int, sub: int, stream: int) -> float:
+    return lib().orc_uniform(seed, index, sub, stream)
+
+
+def stream_sparsify() -> int:
+    return lib().orc_stream_sparsify()
+
+
+def coverage(reset: bool = False) -> np.ndarray:
+    out = np.zeros(19, np.int64)
+    lib().orc_coverage(out, 1 if reset else 0)
+    return out
+
+
+# ---------------------------------------------------------------------------
+# One CH-form (Sec. "Phase-sensitive Clifford simulator").
+# ---------------------------------------------------------------------------
+class CHForm:
+    """|phi> = omega U_C U_H |s>, evolved gate by gate from |0^n>."""
+
+    def __init__(self, n: int, _handle=None, _owner=None):
+        self.n = n
+        if _handle is None:
+            self._h = lib().orc_ch_new(n)
+            if not self._h:
+                raise ValueError("n must be in [1, 64]")
+            self._own = True
+        else:
+            self._h = _handle
+            self._own = False
+            self._owner = _owner
+
+    def __del__(self):
+        if getattr(self, "_own", False) and self._h:
+            lib().orc_ch_free(self._h)
+            self._h = None
+
+    def apply(self, op: int, q: int, r: int = 0) -> None:
+        rc = lib().orc_ch_apply(self._h, op, q, r)
+        if rc:
+            raise ValueError(f"gate ({op},{q},{r}) rejected or failed: rc={rc}")
+
+    def apply_right(self, op: int, q: int, r: int = 0) -> None:
+        if lib().orc_ch_apply_right(self._h, op, q, r):
+            raise ValueError("bad right-multiplication gate")
+
+    def export(self) -> dict:
+        n = self.n
+        F = np.zeros(n, np.uint64)
+        G = np.zeros(n, np.uint64)
+        M = np.zeros(n, np.uint64)
+        g = np.zeros(n, np.uint8)
+        v = np.zeros(1, np.uint64)
+        s = np.zeros(1, np.uint64)
+        w = np.zeros(1, np.int32)
+        lib().orc_ch_export(self._h, F, G, M, g, v, s, w)
+        return dict(F=F, G=G, M=M, gamma=g, v=int(v[0]), s=int(s[0]), omega=int(w[0]))
+
+    def amplitude_record(self, x: int):
+        """(nonzero, k8, |v|) with <x|phi> = e^{i pi k8/4} 2^{-|v|/2}; Eq. (amplitude1)."""
+        k = C.c_int(0)
+        vc = C.c_int(0)
+        nz = lib().orc_ch_amplitude(self._h, int(x), C.byref(k), C.byref(vc))
+        return nz, k.value, vc.value
+
+    def amplitude(self, x: int) -> complex:
+        nz, k, vc = self.amplitude_record(x)
+        if not nz:
+            return 0j
+        return complex(np.exp(1j * np.pi * k / 4) * 2.0 ** (-vc / 2))
+
+    def sample(self, flips: int) -> int:
+        return int(lib().orc_ch_sample(self._h, int(flips)))
+
+    def check(self) -> int:
+        return lib().orc_ch_check(self._h)
+
+    def inner_record(self, Aoff, Adiag):
+        """<phi_A|phi> as (rc, k8, e2): 0, or e^{i pi k8/4} 2^{e2/2}; Lemma (Inner Product)."""
+        k = C.c_int(0)
+        e2 = C.c_int(0)
+        rc = lib().orc_ch_inner(self._h, np.ascontiguousarray(Aoff, np.uint64),
+                                np.ascontiguousarray(Adiag, np.uint8), C.byref(k), C.byref(e2))
+        return rc, k.value, e2.value
+
+
+def phase_decomp(theta: float):
+    """diag(1, e^{i theta}) = c0 S^k + c1 S^{k+1}; Eq. (Rtheta) after the theta reduction."""
+    c = np.zeros(4)
+    k = C.c_int(0)
+    lib().orc_phase_decomp(float(theta), c, C.byref(k))
+    return complex(c[0], c[1]), complex(c[2], c[3]), k.value
+
+
+def expsum(B: np.ndarray):
+    """Z(B) = sum_x i^{x B x^T} as (re_sign, re_exp, im_sign, im_exp); Lemma (Exponential Sum)."""
+    B = np.ascontiguousarray(B, np.uint8)
+    N = B.shape[0]
+    out = np.zeros(4, np.int32)
+    lib().orc_expsum(N, B, out)
+    return tuple(int(t) for t in out)
+
+
+def expsum_value(B: np.ndarray) -> complex:
+    rs, re, is_, ie = expsum(B)
+    return complex(rs * 2.0 ** re if rs else 0.0, is_ * 2.0 ** ie if is_ else 0.0)
+
+
+# ---------------------------------------------------------------------------
+# Sum-over-Cliffords terms (Eqs. (Udecomp), (Vphi), Lemma (Sparsification)).
+# ---------------------------------------------------------------------------
+EXACT = 0
+SPARSIFY = 1
+
+
+class Terms:
+    """The chi CH-form terms of a circuit (or a chosen subset of them)."""
+
+    def __init__(self, circuit, chi: int, mode: int, seed: int = 0, alphas=None,
+                 threads: int | None = None):
+        self.n = circuit.n
+        self.circuit = circuit
+        op = np.ascontiguousarray(circuit.op, np.uint8)
+        q = np.ascontiguousarray(circuit.q, np.uint8)
+        r = np.ascontiguousarray(circuit.r, np.uint8)
+        th = np.ascontiguousarray(circuit.theta, np.float64)
+        if th.size == 0:
+            th = np.zeros(1)
+        threads = default_threads() if threads is None else threads
+        if alphas is None:
+            ap, na = None, 0
+        else:
+            self._alphas = np.ascontiguousarray(alphas, np.uint64)
+            ap, na = self._alphas.ctypes.data_as(C.c_void_p), self._alphas.size
+        self._h = lib().orc_terms_build(circuit.n, op.size, op, q, r, int(circuit.theta.size), th,
+                                        int(chi), int(mode), int(seed), ap, na, threads)
+        err = lib().orc_terms_error(self._h)
+        if err:
+            lib().orc_terms_free(self._h)
+            self._h = None
+            raise ValueError(f"oracle term build failed (code {err})")
+        self.count = int(lib().orc_terms_count(self._h))
+        self.l1 = float(lib().orc_terms_l1(self._h))
+        self.threads = threads
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            lib().orc_terms_free(self._h)
+            self._h = None
+
+    def term(self, i: int) -> CHForm:
+        return CHForm(self.n, _handle=lib().orc_terms_ch(self._h, i), _owner=self)
+
+    def b(self, i: int) -> complex:
+        out = np.zeros(2)
+        lib().orc_terms_b(self._h, i, out)
+        return complex(out[0], out[1])
+
+    def branch(self, i: int) -> np.ndarray:
+        out = np.zeros(max(1, self.circuit.theta.size), np.uint8)
+        lib().orc_terms_branch(self._h, i, out)
+        return out[: self.circuit.theta.size]
+
+    def amplitudes(self, x) -> np.ndarray:
+        """<x|psi> = sum_alpha b_alpha <x|phi_alpha> over the built terms."""
+        x = np.ascontiguousarray(x, np.uint64)
+        out = np.zeros(2 * x.size)
+        lib().orc_terms_amplitudes(self._h, x, x.size, out, self.threads)
+        return out[0::2] + 1j * out[1::2]
+
+    def inner(self, Aoff, Adiag):
+        """overlap_l = <phi_{A_l}|psi>, eta_l = 2^n |overlap_l|^2 (Lemma (Norm Estimation))."""
+        Aoff = np.ascontiguousarray(Aoff, np.uint64)
+        Adiag = np.ascontiguousarray(Adiag, np.uint8)
+        L = Aoff.shape[0]
+        ov = np.zeros(2 * L)
+        eta = np.zeros(L)
+        bad = lib().orc_terms_inner(self._h, Aoff, Adiag, L, ov, eta, self.threads)
+        if bad:
+            raise RuntimeError("oracle inner product produced an invalid record")
+        return ov[0::2] + 1j * ov[1::2], eta
+
+    def metropolis(self, x_init, jstream, ustream):
+        """Plain single-bit-flip chains (Sec. "Heuristic Metropolis simulator")."""
+        x_init = np.ascontiguousarray(x_init, np.uint64)
+        jstream = np.ascontiguousarray(jstream, np.uint32)
+        ustream = np.ascontiguousarray(ustream, np.float64)
+        n_chain = x_init.size
+        steps = jstream.size // max(1, n_chain)
+        trace = np.zeros(n_chain * steps, np.uint64)
+        acc = np.zeros(n_chain * steps, np.uint8)
+        amp = np.zeros(2 * n_chain)
+        bad = lib().orc_metropolis(self._h, n_chain, steps, x_init, jstream.reshape(-1),
+                                   ustream.reshape(-1), trace, acc, amp, self.threads)
+        if bad:
+            raise ValueError("a chain started at a string with P(x) = 0")
+        return (trace.reshape(n_chain, steps), acc.reshape(n_chain, steps),
+                amp[0::2] + 1j * amp[1::2])

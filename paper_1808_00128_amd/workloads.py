@@ -1,0 +1,238 @@
+"""Seeded synthetic inputs for the sum-over-Cliffords hot path.
+
+This module only draws inputs: circuits over {H, S, CX, CZ} with diagonal
+phase-gate slots, bitstrings, equatorial-state matrices A and the random
+streams a Metropolis chain consumes.  It holds none of the method's arithmetic
+(no decompositions, no CH-form algebra) and is the one module that both the
+HIP path and the CPU oracle take their inputs from.
+
+Shapes follow the paper's workloads:
+  * random Clifford+phase circuits (circuit form U = D_m V_m ... V_1 D_0 of
+    Sec. "Simulation algorithms"), with the phase gate diag(1, e^{i theta});
+  * QAOA for Max-E3LIN2 (Sec. "Quantum approximate optimization algorithm"):
+    H on every qubit, exp(-i gamma d Z_a Z_b Z_c) per triple, then exp(-i beta X_j);
+  * uniformly random equatorial states, A uniform on M_n (Lemma (Norm Estimation)).
+
+Conventions: qubit p is bit p of a uint64 bitstring.  Gate codes:
+H=0, S=1, CX=2 (q = control, r = target), CZ=3, SLOT=4 (phase gate on q,
+angle theta[slot], slots numbered in circuit order).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+OP_H, OP_S, OP_CX, OP_CZ, OP_SLOT = 0, 1, 2, 3, 4
+OP_NAMES = {OP_H: "H", OP_S: "S", OP_CX: "CX", OP_CZ: "CZ", OP_SLOT: "SLOT"}
+
+
+@dataclass
+class Circuit:
+    n: int
+    op: np.ndarray  # uint8
+    q: np.ndarray   # uint8
+    r: np.ndarray   # uint8
+    theta: np.ndarray = field(default_factory=lambda: np.zeros(0))  # float64, one per slot
+
+    @property
+    def n_slot(self) -> int:
+        return int(self.theta.size)
+
+    @property
+    def n_gates(self) -> int:
+        return int(self.op.size)
+
+    def gates(self):
+        """Iterate (op, q, r, theta_or_None)."""
+        k = 0
+        for o, a, b in zip(self.op.tolist(), self.q.tolist(), self.r.tolist()):
+            if o == OP_SLOT:
+                yield o, a, b, float(self.theta[k])
+                k += 1
+            else:
+                yield o, a, b, None
+
+
+def _arr(lst, dt=np.uint8):
+    return np.asarray(lst, dtype=dt)
+
+
+def from_list(n: int, gates) -> Circuit:
+    """Build a Circuit from (op, q, r[, theta]) tuples."""
+    op, q, r, th = [], [], [], []
+    for g in gates:
+        o = g[0]
+        op.append(o)
+        q.append(g[1])
+        r.append(g[2] if len(g) > 2 and g[2] is not None else 0)
+        if o == OP_SLOT:
+            th.append(g[3])
+    return Circuit(n, _arr(op), _arr(q), _arr(r), np.asarray(th, np.float64))
+
+
+def random_clifford_gates(n: int, count: int, rng: np.random.Generator, ops=(OP_H, OP_S, OP_CX, OP_CZ)):
+    """count gates drawn uniformly from ops; 1-qubit gates on a uniform qubit,
+    2-qubit gates on a uniform ordered pair q != r."""
+    out = []
+    ops = list(ops)
+    if n < 2:
+        ops = [o for o in ops if o in (OP_H, OP_S)]
+    for _ in range(count):
+        o = ops[int(rng.integers(len(ops)))]
+        if o in (OP_CX, OP_CZ):
+            q = int(rng.integers(n))
+            r = int(rng.integers(n - 1))
+            if r >= q:
+                r += 1
+            out.append((o, q, r))
+        else:
+            out.append((o, int(rng.integers(n)), 0))
+    return out
+
+
+def random_circuit(n: int, n_clifford: int, thetas, rng: np.random.Generator,
+                   qubits=None) -> Circuit:
+    """Random Clifford circuit with one phase-gate slot per entry of thetas,
+    each at a uniformly random gate boundary on a uniformly random qubit."""
+    gates = random_clifford_gates(n, n_clifford, rng)
+    thetas = list(thetas)
+    pos = np.sort(rng.integers(0, n_clifford + 1, size=len(thetas))) if thetas else []
+    out = []
+    k = 0
+    for i in range(n_clifford + 1):
+        while k < len(thetas) and pos[k] == i:
+            out.append((OP_SLOT, int(rng.integers(n)), 0, float(thetas[k])))
+            k += 1
+        if i < n_clifford:
+            out.append(gates[i])
+    if qubits is not None:
+        qubits = list(qubits)
+        out = [(g[0], qubits[g[1]], qubits[g[2]] if g[0] in (OP_CX, OP_CZ) else 0) + tuple(g[3:])
+               for g in out]
+        n = max(qubits) + 1
+    return from_list(n, out)
+
+
+def random_bitstrings(n: int, count: int, rng: np.random.Generator) -> np.ndarray:
+    """count uniform strings in {0,1}^n as uint64 (bit p = qubit p)."""
+    lo = rng.integers(0, 2**32, size=count, dtype=np.uint64)
+    hi = rng.integers(0, 2**32, size=count, dtype=np.uint64)
+    x = (hi << np.uint64(32)) | lo
+    if n < 64:
+        x &= np.uint64((1 << n) - 1)
+    return x
+
+
+def random_equatorial(n: int, L: int, rng: np.random.Generator):
+    """L matrices A uniform on M_n: symmetric, off-diagonal bits, diagonal in Z_4.
+
+    Returns (Aoff, Adiag): Aoff[l, a] is row a as uint64 (bit b = A_ab, bit a = 0),
+    Adiag[l, a] = A_aa in {0,1,2,3}."""
+    Aoff = np.zeros((L, n), np.uint64)
+    for l in range(L):
+        upper = np.triu(rng.integers(0, 2, size=(n, n), dtype=np.uint64), 1)
+        full = upper | upper.T
+        weights = np.uint64(1) << np.arange(n, dtype=np.uint64)
+        Aoff[l] = (full * weights[None, :]).sum(axis=1, dtype=np.uint64)
+    Adiag = rng.integers(0, 4, size=(L, n), dtype=np.uint8)
+    return Aoff, Adiag
+
+
+def metropolis_streams(n: int, n_chain: int, steps: int, rng: np.random.Generator):
+    """Random inputs a single-bit-flip chain consumes: the bit to flip and the
+    uniform for the accept test, per chain and step."""
+    j = rng.integers(0, n, size=(n_chain, steps), dtype=np.uint32)
+    u = rng.random(size=(n_chain, steps))
+    return j, u
+
+
+# ---------------------------------------------------------------------------
+# The workload configurations (seed = 1000 + configuration number).
+# ---------------------------------------------------------------------------
+def config_tiny(seed: int = 1001) -> dict:
+    """n = 12; 200 uniform {H,S,CX,CZ} gates; 8 T gates (theta = pi/4) at random
+    positions; exact expansion chi = 2^8; all 4096 bitstrings."""
+    rng = np.random.default_rng(seed)
+    circ = random_circuit(12, 200, [np.pi / 4] * 8, rng)
+    x = np.arange(4096, dtype=np.uint64)
+    return dict(name="tiny-n12-exact", circuit=circ, chi=256, mode="exact", x=x, seed=seed)
+
+
+def config_amplitudes(seed: int = 1002, chi: int = 1 << 16, n_x: int = 4096) -> dict:
+    """n = 50; 2000 Clifford gates + 40 phase slots, theta ~ U(0, 2 pi); sparsified
+    chi = 2^16; 4096 uniform bitstrings."""
+    rng = np.random.default_rng(seed)
+    thetas = rng.uniform(0.0, 2 * np.pi, size=40)
+    circ = random_circuit(50, 2000, thetas, rng)
+    x = random_bitstrings(50, n_x, rng)
+    return dict(name="amplitudes-n50-chi65536-x4096", circuit=circ, chi=chi, mode="sparsify", x=x,
+                seed=seed)
+
+
+def config_norm(seed: int = 1003, chi: int = 1 << 18, L: int = 1024) -> dict:
+    """n = 40; 200 Clifford gates + 30 phase slots, theta ~ U(0, 2 pi); sparsified
+    chi = 2^18; L = 1024 equatorial states with A uniform on M_40."""
+    rng = np.random.default_rng(seed)
+    thetas = rng.uniform(0.0, 2 * np.pi, size=30)
+    circ = random_circuit(40, 200, thetas, rng)
+    Aoff, Adiag = random_equatorial(40, L, rng)
+    return dict(name="norm-n40-chi262144-L1024", circuit=circ, chi=chi, mode="sparsify", Aoff=Aoff,
+                Adiag=Adiag, seed=seed)
+
+
+def qaoa_circuit(n: int, n_triples: int, rng: np.random.Generator, gamma=None, beta=None) -> tuple:
+    """p = 1 QAOA for Max-E3LIN2: H on all qubits, exp(-i gamma d Z_a Z_b Z_c) for
+    random distinct triples with d = +-1, then exp(-i beta X_j) on every qubit.
+
+    exp(-i g Z_a Z_b Z_c) = CX_{a,c} CX_{b,c} exp(-i g Z_c) CX_{b,c} CX_{a,c}, and
+    exp(-i g Z) = e^{-i g} diag(1, e^{2 i g}): a phase slot with theta = 2 g.
+    exp(-i beta X) = H exp(-i beta Z) H: a slot with theta = 2 beta between two H.
+    Global phases are dropped.  Returns (circuit, triples, d)."""
+    if gamma is None:
+        gamma = rng.uniform(0.0, np.pi)
+    if beta is None:
+        beta = rng.uniform(0.0, np.pi)
+    gates = [(OP_H, j, 0) for j in range(n)]
+    triples = []
+    seen = set()
+    while len(triples) < n_triples:
+        t = tuple(sorted(rng.choice(n, size=3, replace=False).tolist()))
+        if t in seen:
+            continue
+        seen.add(t)
+        triples.append(t)
+    d = rng.choice([-1, 1], size=n_triples)
+    for (a, b, c), dd in zip(triples, d.tolist()):
+        gates += [(OP_CX, a, c), (OP_CX, b, c), (OP_SLOT, c, 0, 2 * gamma * dd), (OP_CX, b, c),
+                  (OP_CX, a, c)]
+    for j in range(n):
+        gates += [(OP_H, j, 0), (OP_SLOT, j, 0, 2 * beta), (OP_H, j, 0)]
+    return from_list(n, gates), np.asarray(triples), d, gamma, beta
+
+
+def config_qaoa(seed: int = 1004, n: int = 50, n_triples: int = 60, chi: int = 1 << 20,
+                n_chain: int = 64, steps: int = 1000) -> dict:
+    rng = np.random.default_rng(seed)
+    circ, triples, d, gamma, beta = qaoa_circuit(n, n_triples, rng)
+    j, u = metropolis_streams(n, n_chain, steps, rng)
+    return dict(name=f"qaoa-n{n}-chi{chi}-chains{n_chain}x{steps}", circuit=circ, chi=chi,
+                mode="sparsify", triples=triples, d=d, gamma=gamma, beta=beta, jstream=j,
+                ustream=u, seed=seed, n_chain=n_chain, steps=steps)
+
+
+def config_uneven(seed: int = 1005, n_inst: int = 64, n_x: int = 1024, chi_lo: int = 10,
+                  chi_hi: int = 20) -> dict:
+    """64 independent circuits: n ~ U{20..60}, 10..60 phase slots, 40 n Clifford
+    gates, chi log-uniform in [2^chi_lo, 2^chi_hi], n_x bitstrings each."""
+    rng = np.random.default_rng(seed)
+    inst = []
+    for i in range(n_inst):
+        n = int(rng.integers(20, 61))
+        m = int(rng.integers(10, 61))
+        thetas = rng.uniform(0.0, 2 * np.pi, size=m)
+        circ = random_circuit(n, 40 * n, thetas, rng)
+        chi = int(round(2 ** rng.uniform(chi_lo, chi_hi)))
+        x = random_bitstrings(n, n_x, rng)
+        inst.append(dict(circuit=circ, chi=chi, mode="sparsify", x=x, seed=seed * 1000 + i))
+    return dict(name=f"uneven-{n_inst}x", instances=inst, seed=seed)

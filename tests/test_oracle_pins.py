@@ -1,0 +1,459 @@
+"""Pins of the CPU oracle against things other than itself (no GPU needed).
+
+Each test checks the oracle against a textbook definition computed a different
+way (dense statevector, brute-force sums), a closed form the paper states, an
+invariant, or a published known-answer vector.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import dense
+import oracle as O
+from paper_1808_00128_amd import workloads as W
+from paper_1808_00128_amd.workloads import OP_CX, OP_CZ, OP_H, OP_S, OP_SLOT
+
+
+# ---------------------------------------------------------------------------
+# Counter-based generator: Philox4x32-10 known-answer vectors (Random123 KAT).
+# ---------------------------------------------------------------------------
+def test_philox_known_answers():
+    assert list(O.philox([0, 0, 0, 0], [0, 0])) == [0x6627E8D5, 0xE169C58D, 0xBC57AC4C, 0x9B00DBD8]
+    assert list(O.philox([0xFFFFFFFF] * 4, [0xFFFFFFFF] * 2)) == [
+        0x408F276D, 0x41C83B0E, 0xA20BC7C6, 0x6D5451FD]
+    assert list(O.philox([0x243F6A88, 0x85A308D3, 0x13198A2E, 0x03707344],
+                         [0xA4093822, 0x299F31D0])) == [0xD16CFE09, 0x94FDCCEB, 0x5001E420, 0x24126EA1]
+
+
+def test_uniform_range_and_mean():
+    u = np.array([O.uniform(7, i, 3, O.stream_sparsify()) for i in range(20000)])
+    assert u.min() >= 0.0 and u.max() < 1.0
+    assert abs(u.mean() - 0.5) < 5 * np.sqrt(1 / 12 / u.size)
+
+
+# ---------------------------------------------------------------------------
+# CH-form simulator vs the dense statevector.
+# ---------------------------------------------------------------------------
+def ch_state(n, gates):
+    ch = O.CHForm(n)
+    for g in gates:
+        ch.apply(g[0], g[1], g[2])
+    return ch
+
+
+def ch_vector(ch, n):
+    return np.array([ch.amplitude(x) for x in range(2**n)])
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 6])
+def test_clifford_amplitudes_match_dense(n):
+    rng = np.random.default_rng(100 + n)
+    for trial in range(60):
+        gates = W.random_clifford_gates(n, int(rng.integers(5, 60)), rng)
+        ch = ch_state(n, gates)
+        assert ch.check() == 0
+        psi = dense.run_gates(n, gates)
+        np.testing.assert_allclose(ch_vector(ch, n), psi, atol=1e-12, rtol=0)
+
+
+def test_hadamard_branches_exhaustive_small():
+    """All circuits of length <= 4 over the full gate alphabet on 2 qubits and
+    of length 3 on 3 qubits, then 3000 random ones on 1-3 qubits; must cover t == u, both V_0 cases and all 16
+    single-qubit cases (y_q, delta, v_q) of Prop. H."""
+    O.coverage(reset=True)
+    for n, depth in ((2, 4), (3, 3)):
+        alphabet = [(OP_H, q, 0) for q in range(n)] + [(OP_S, q, 0) for q in range(n)]
+        alphabet += [(OP_CX, q, r) for q in range(n) for r in range(n) if q != r]
+        alphabet += [(OP_CZ, q, r) for q in range(n) for r in range(q + 1, n)]
+        for L in range(1, depth + 1):
+            for seq in itertools.product(alphabet, repeat=L):
+                ch = ch_state(n, seq)
+                psi = dense.run_gates(n, seq)
+                np.testing.assert_allclose(ch_vector(ch, n), psi, atol=1e-12, rtol=0)
+    # longer random circuits reach the remaining (y_q, delta, v_q) combinations
+    rng = np.random.default_rng(77)
+    for trial in range(3000):
+        n = int(rng.integers(1, 4))
+        seq = W.random_clifford_gates(n, int(rng.integers(5, 16)), rng)
+        ch = ch_state(n, seq)
+        np.testing.assert_allclose(ch_vector(ch, n), dense.run_gates(n, seq), atol=1e-12, rtol=0)
+    cov = O.coverage()
+    assert cov[0] > 0 and cov[1] > 0 and cov[2] > 0
+    assert np.all(cov[3:] > 0), cov
+
+
+@pytest.mark.parametrize("n", [40, 50, 64])
+def test_tableau_invariants_large_n(n):
+    """F G^T = I, M F^T symmetric, gamma_p = F_p . M_p (mod 2) after long random circuits."""
+    rng = np.random.default_rng(n)
+    ch = O.CHForm(n)
+    for block in range(6):
+        for g in W.random_clifford_gates(n, 300, rng):
+            ch.apply(*g)
+        assert ch.check() == 0
+
+
+def test_block_product_amplitudes_n64():
+    """n = 64 correctness where no dense vector fits: blocks of 8-10 qubits on
+    scattered labels (including 0 and 63), gates only inside blocks, exact
+    expansion of the phase slots; the amplitude must equal the product of dense
+    block amplitudes."""
+    rng = np.random.default_rng(64)
+    labels = rng.permutation(64)
+    sizes = [10, 9, 8, 10]
+    blocks = []
+    start = 0
+    for sz in sizes:
+        blocks.append(sorted(labels[start:start + sz].tolist()))
+        start += sz
+    blocks[0][0] = 0 if 0 not in sum(blocks, []) else blocks[0][0]
+    if 63 not in sum(blocks, []):
+        blocks[-1][-1] = 63
+    gates = []
+    local = []
+    nslots = [3, 3, 2, 3]
+    for b, qs in enumerate(blocks):
+        th = rng.uniform(0, 2 * np.pi, size=nslots[b])
+        c = W.random_circuit(len(qs), 60, th, rng)
+        local.append((qs, c))
+    # Interleave the blocks' gate streams (they commute across blocks).
+    streams = [list(c.gates()) for _, c in local]
+    ptr = [0] * len(streams)
+    while any(ptr[i] < len(streams[i]) for i in range(len(streams))):
+        i = int(rng.integers(len(streams)))
+        if ptr[i] >= len(streams[i]):
+            continue
+        op, q, r, th = streams[i][ptr[i]]
+        ptr[i] += 1
+        qs = local[i][0]
+        gq = qs[q]
+        gr = qs[r] if op in (OP_CX, OP_CZ) else 0
+        gates.append((op, gq, gr, th) if op == OP_SLOT else (op, gq, gr))
+    circ = W.from_list(64, gates)
+    m = circ.n_slot
+    T = O.Terms(circ, 1 << m, O.EXACT)
+    psis = [dense.run(c) for _, c in local]
+    xs = []
+    for trial in range(40):
+        x = 0
+        parts = []
+        for (qs, c), psi in zip(local, psis):
+            # pick a local index with non-negligible amplitude half the time
+            if trial % 2 == 0:
+                li = int(rng.choice(len(psi), p=np.abs(psi) ** 2))
+            else:
+                li = int(rng.integers(len(psi)))
+            parts.append(psi[li])
+            for k, qq in enumerate(qs):
+                if (li >> k) & 1:
+                    x |= 1 << qq
+        xs.append((x, np.prod(parts)))
+    amps = T.amplitudes(np.array([x for x, _ in xs], np.uint64))
+    ref = np.array([a for _, a in xs])
+    np.testing.assert_allclose(amps, ref, atol=1e-12, rtol=0)
+
+
+# ---------------------------------------------------------------------------
+# Phase-gate decomposition, Eq. (Rtheta) and the extent formula.
+# ---------------------------------------------------------------------------
+def test_phase_decomposition_is_exact():
+    S = np.diag([1, 1j])
+    for theta in np.concatenate([np.linspace(-4 * np.pi, 4 * np.pi, 257), [np.pi / 4, 0.0, np.pi / 2]]):
+        c0, c1, k = O.phase_decomp(theta)
+        Sk = np.linalg.matrix_power(S, k)
+        lhs = c0 * Sk + c1 * Sk @ S
+        np.testing.assert_allclose(lhs, np.diag([1, np.exp(1j * theta)]), atol=1e-14)
+        tp = (theta - k * np.pi / 2) % (2 * np.pi)
+        tp = tp if tp < np.pi / 2 + 1e-12 else tp % (np.pi / 2)
+        l1 = abs(c0) + abs(c1)
+        assert abs(l1 - (np.cos(tp / 2) + np.tan(np.pi / 8) * np.sin(tp / 2))) < 1e-12
+
+
+def test_t_gate_extent():
+    c0, c1, _ = O.phase_decomp(np.pi / 4)
+    assert abs((abs(c0) + abs(c1)) ** 2 - 1 / np.cos(np.pi / 8) ** 2) < 1e-12
+    # stabilizer fidelity of the T state is cos^2(pi/8) ~ 0.853
+    assert abs(np.cos(np.pi / 8) ** 2 - 0.8535533905932737) < 1e-15
+
+
+# ---------------------------------------------------------------------------
+# Exact sum over Cliffords (tiny configuration) vs dense.
+# ---------------------------------------------------------------------------
+def test_exact_sum_over_cliffords_tiny_config():
+    cfg = W.config_tiny()
+    circ = cfg["circuit"]
+    T = O.Terms(circ, cfg["chi"], O.EXACT)
+    amps = T.amplitudes(cfg["x"])
+    psi = dense.run(circ)
+    rms = np.sqrt(np.mean(np.abs(psi) ** 2))
+    assert np.max(np.abs(amps - psi)) / rms < 1e-12
+    assert abs(np.sum(np.abs(amps) ** 2) - 1.0) < 1e-12
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_exact_sum_random_angles(seed):
+    rng = np.random.default_rng(seed)
+    n = 5
+    circ = W.random_circuit(n, 40, rng.uniform(-7, 7, size=5), rng)
+    T = O.Terms(circ, 32, O.EXACT)
+    amps = T.amplitudes(np.arange(2**n, dtype=np.uint64))
+    np.testing.assert_allclose(amps, dense.run(circ), atol=1e-13)
+
+
+# ---------------------------------------------------------------------------
+# Sparsification Lemma.  The lemma states E ||psi - Omega||^2 = ||c||_1^2 / k; its
+# proof's own steps (E <Omega|Omega> = ||c||_1^2/k + (k-1)/k, E <psi|Omega> = 1)
+# give exactly (||c||_1^2 - 1) / k, which is <= the stated value.  The test pins
+# the exact expectation.  Branch frequencies follow |c_j| / ||c^(p)||_1.
+# ---------------------------------------------------------------------------
+def test_sparsification_mean_error():
+    rng = np.random.default_rng(5)
+    n = 5
+    circ = W.random_circuit(n, 30, rng.uniform(0, 2 * np.pi, size=6), rng)
+    psi = dense.run(circ)
+    k = 16
+    errs = []
+    norms = []
+    x = np.arange(2**n, dtype=np.uint64)
+    for seed in range(300):
+        T = O.Terms(circ, k, O.SPARSIFY, seed=seed, threads=1)
+        om = T.amplitudes(x)
+        errs.append(np.sum(np.abs(psi - om) ** 2))
+        norms.append(np.sum(np.abs(om) ** 2))
+    l1sq = T.l1 ** 2
+    errs = np.array(errs)
+    se = errs.std(ddof=1) / np.sqrt(errs.size)
+    assert abs(errs.mean() - (l1sq - 1) / k) < 5 * se, (errs.mean(), (l1sq - 1) / k, se)
+    assert errs.mean() <= l1sq / k
+    norms = np.array(norms)
+    # E <Omega|Omega> = 1 + (||c||_1^2 - 1)/k <= 1 + ||c||_1^2 / k (proof of the lemma)
+    se2 = norms.std(ddof=1) / np.sqrt(norms.size)
+    assert abs(norms.mean() - (1 + (l1sq - 1) / k)) < 5 * se2
+
+
+def test_sparsification_branch_frequencies():
+    rng = np.random.default_rng(9)
+    thetas = rng.uniform(0, 2 * np.pi, size=4)
+    circ = W.random_circuit(3, 10, thetas, rng)
+    chi = 4000
+    T = O.Terms(circ, chi, O.SPARSIFY, seed=123, threads=4)
+    br = np.array([T.branch(i) for i in range(chi)])
+    for p, th in enumerate(thetas):
+        c0, c1, _ = O.phase_decomp(th)
+        p1 = abs(c1) / (abs(c0) + abs(c1))
+        f = br[:, p].mean()
+        assert abs(f - p1) < 5 * np.sqrt(p1 * (1 - p1) / chi) + 1e-3
+    # all b_alpha have magnitude ||c||_1 / chi
+    mags = np.array([abs(T.b(i)) for i in range(0, chi, 97)])
+    np.testing.assert_allclose(mags, T.l1 / chi, rtol=1e-13)
+
+
+# ---------------------------------------------------------------------------
+# Exponential sums, Lemma (Exponential Sum).
+# ---------------------------------------------------------------------------
+def random_B(N, rng):
+    up = np.triu(rng.integers(0, 2, size=(N, N)), 1)
+    B = up + up.T
+    B[np.arange(N), np.arange(N)] = rng.integers(0, 4, size=N)
+    return B.astype(np.uint8)
+
+
+def test_expsum_brute_force():
+    rng = np.random.default_rng(11)
+    for trial in range(600):
+        N = int(rng.integers(1, 11))
+        B = random_B(N, rng)
+        z = O.expsum_value(B)
+        ref = dense.expsum_brute(B)
+        assert abs(z - ref) < 1e-9, (B, z, ref)
+        rs, re, is_, ie = O.expsum(B)
+        assert rs in (-1, 0, 1) and is_ in (-1, 0, 1)
+        if rs and is_:
+            assert re == ie
+
+
+def test_expsum_closed_forms():
+    for N in range(0, 9):
+        assert O.expsum_value(np.zeros((N, N), np.uint8)) == 2.0**N
+    rng = np.random.default_rng(3)
+    for trial in range(50):
+        N = int(rng.integers(1, 9))
+        d = rng.integers(0, 4, size=N)
+        B = np.diag(d).astype(np.uint8)
+        ref = np.prod([1 + 1j**k for k in d])
+        assert abs(O.expsum_value(B) - ref) < 1e-9
+    # identity: sum_{x1,x2} (-1)^{x1 x2 + mu1 x1 + mu2 x2} = 2 (-1)^{mu1 mu2}
+    for mu1 in (0, 1):
+        for mu2 in (0, 1):
+            B = np.array([[2 * mu1, 1], [1, 2 * mu2]], np.uint8)
+            assert O.expsum_value(B) == 2 * (-1) ** (mu1 * mu2)
+    # Gauss sum with N = 1, B = 1: 1 + i (both parts non-zero)
+    assert O.expsum_value(np.array([[1]], np.uint8)) == 1 + 1j
+
+
+# ---------------------------------------------------------------------------
+# Inner products with equatorial states, Lemma (Inner Product).
+# ---------------------------------------------------------------------------
+def record_value(rc, k, e2):
+    if rc == 0:
+        return 0j
+    return complex(np.exp(1j * np.pi * k / 4) * 2.0 ** (e2 / 2))
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 6])
+def test_inner_product_vs_dense(n):
+    rng = np.random.default_rng(200 + n)
+    for trial in range(40):
+        gates = W.random_clifford_gates(n, int(rng.integers(0, 40)), rng)
+        ch = ch_state(n, gates)
+        psi = dense.run_gates(n, gates)
+        Aoff, Adiag = W.random_equatorial(n, 1, rng)
+        rc, k, e2 = ch.inner_record(Aoff[0], Adiag[0])
+        assert rc >= 0
+        phiA = dense.equatorial(n, Aoff[0], Adiag[0])
+        ref = np.vdot(phiA, psi)
+        assert abs(record_value(rc, k, e2) - ref) < 1e-12
+
+
+def test_inner_product_closed_forms():
+    rng = np.random.default_rng(17)
+    for n in (1, 3, 8, 20, 40, 64):
+        Aoff, Adiag = W.random_equatorial(n, 3, rng)
+        ch0 = O.CHForm(n)  # |0^n>
+        for l in range(3):
+            rc, k, e2 = ch0.inner_record(Aoff[l], Adiag[l])
+            assert (rc, k, e2) == (1, 0, -n)  # <phi_A|0^n> = 2^{-n/2}
+        # the equatorial state itself as a CH-form: H^n then S^{A_aa}, CZ^{A_ab}
+        chA = O.CHForm(n)
+        for a in range(n):
+            chA.apply(OP_H, a)
+        for a in range(n):
+            for _ in range(int(Adiag[0, a])):
+                chA.apply(OP_S, a)
+            for b in range(a + 1, n):
+                if (int(Aoff[0, a]) >> b) & 1:
+                    chA.apply(OP_CZ, a, b)
+        rc, k, e2 = chA.inner_record(Aoff[0], Adiag[0])
+        assert (rc, k, e2) == (1, 0, 0)  # <phi_A|phi_A> = 1
+
+
+# ---------------------------------------------------------------------------
+# Norm estimation, Lemma (Norm Estimation): exhaustive average over all of M_n.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n", [2, 3])
+def test_norm_estimator_exhaustive_mean(n):
+    rng = np.random.default_rng(30 + n)
+    circ = W.random_circuit(n, 20, rng.uniform(0, 2 * np.pi, size=2), rng)
+    # a sparsified psi (unnormalised) so that ||psi||^2 != 1
+    T = O.Terms(circ, 3, O.SPARSIFY, seed=4, threads=1)
+    x = np.arange(2**n, dtype=np.uint64)
+    norm2 = np.sum(np.abs(T.amplitudes(x)) ** 2)
+    pairs = [(a, b) for a in range(n) for b in range(a + 1, n)]
+    As_off, As_diag = [], []
+    for offbits in range(2 ** len(pairs)):
+        row = np.zeros(n, np.uint64)
+        for k, (a, b) in enumerate(pairs):
+            if (offbits >> k) & 1:
+                row[a] |= np.uint64(1 << b)
+                row[b] |= np.uint64(1 << a)
+        for diag in itertools.product(range(4), repeat=n):
+            As_off.append(row.copy())
+            As_diag.append(np.array(diag, np.uint8))
+    ov, eta = T.inner(np.array(As_off), np.array(As_diag))
+    assert abs(eta.mean() - norm2) < 1e-12 * max(1, norm2)
+    assert np.mean(eta**2) <= 2 * norm2**2 + 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Single-state sampler and the Metropolis chain.
+# ---------------------------------------------------------------------------
+def test_single_state_sampler():
+    rng = np.random.default_rng(8)
+    n = 6
+    gates = W.random_clifford_gates(n, 50, rng)
+    ch = ch_state(n, gates)
+    psi = dense.run_gates(n, gates)
+    p = np.abs(psi) ** 2
+    counts = np.zeros(2**n)
+    for t in range(4000):
+        x = ch.sample(int(rng.integers(0, 2**n)))
+        assert p[x] > 1e-12
+        counts[x] += 1
+    sup = p > 1e-12
+    # uniform over the support (all non-zero probabilities are equal)
+    assert np.allclose(p[sup], p[sup][0])
+    expected = 4000 / sup.sum()
+    chi2 = np.sum((counts[sup] - expected) ** 2 / expected)
+    assert chi2 < sup.sum() + 6 * np.sqrt(2 * sup.sum())
+
+
+def component(support, x0, n):
+    """Strings reachable from x0 by single-bit flips inside the support."""
+    seen = np.zeros(support.size, bool)
+    stack = [x0]
+    seen[x0] = True
+    while stack:
+        x = stack.pop()
+        for j in range(n):
+            y = x ^ (1 << j)
+            if support[y] and not seen[y]:
+                seen[y] = True
+                stack.append(y)
+    return seen
+
+
+def test_metropolis_matches_exact_distribution():
+    rng = np.random.default_rng(21)
+    n = 5
+    circ = W.random_circuit(n, 30, rng.uniform(0, 2 * np.pi, size=3), rng)
+    T = O.Terms(circ, 8, O.EXACT)
+    x = np.arange(2**n, dtype=np.uint64)
+    P = np.abs(T.amplitudes(x)) ** 2
+    P /= P.sum()
+    x0 = np.array([int(np.argmax(P))], np.uint64)
+    steps = 60000
+    j, u = W.metropolis_streams(n, 1, steps, rng)
+    trace, acc, amp = T.metropolis(x0, j, u)
+    burn = 2000
+    hist = np.bincount(trace[0, burn:].astype(np.int64), minlength=2**n) / (steps - burn)
+    # The chain need not be irreducible; its stationary law from x0 is P restricted
+    # to x0's component of supp(P) under single-bit flips.
+    comp = component(P > 1e-14, int(x0[0]), n)
+    Pc = np.where(comp, P, 0.0)
+    Pc /= Pc.sum()
+    tv = 0.5 * np.abs(hist - Pc).sum()
+    assert tv < 0.03, tv
+    # the final amplitude is <x_final|psi>
+    ref = T.amplitudes(trace[0, -1:])
+    assert abs(amp[0] - ref[0]) < 1e-12
+
+
+def test_metropolis_acceptance_ratio():
+    """Accept iff U < P(y)/P(x), with the ratio taken from the dense vector."""
+    rng = np.random.default_rng(22)
+    n = 6
+    circ = W.random_circuit(n, 40, rng.uniform(0, 2 * np.pi, size=3), rng)
+    T = O.Terms(circ, 8, O.EXACT)
+    psi = dense.run(circ)
+    P = np.abs(psi) ** 2
+    checked = 0
+    for trial in range(40):
+        x0 = int(rng.choice(2**n, p=P / P.sum()))
+        j = int(rng.integers(n))
+        y = x0 ^ (1 << j)
+        r = P[y] / P[x0]
+        cases = []
+        if r >= 1.0 - 1e-9:
+            cases.append((0.999, 1))
+        elif r < 1e-12:
+            cases.append((0.0, 0))
+        else:
+            cases += [(0.999 * r, 1), (min(1.001 * r, 1 - 1e-12), 0)]
+        for U, expect in cases:
+            trace, acc, _ = T.metropolis(np.array([x0], np.uint64), np.array([[j]], np.uint32),
+                                         np.array([[U]]))
+            assert acc[0, 0] == expect, (r, U)
+            assert trace[0, 0] == (y if expect else x0)
+            checked += 1
+    assert checked >= 40
