@@ -1,0 +1,198 @@
+/* chsim.h — C ABI of the MI355X (gfx950) sum-over-Cliffords hot path.
+ *
+ * Implements the data-parallel core of Bravyi, Browne, Calpin, Campbell,
+ * Gosset, Howard, "Simulation of quantum circuits by low-rank stabilizer
+ * decompositions" (Quantum 3, 181 (2019), arXiv:1808.00128):
+ *   (a) evolve chi CH-form stabilizer terms through their sampled Clifford
+ *       circuits (Sec. "Phase-sensitive Clifford simulator");
+ *   (b) amplitudes <x|psi> = sum_j b_j <x|phi_j> (Eqs. (amplitude), (amplitude1));
+ *   (c) inner products <phi_A|psi> with equatorial states and the norm
+ *       estimate (Lemmas (Inner Product), (Exponential Sum), (Norm Estimation));
+ *   and the Metropolis chain over n-bit outputs (Sec. "Heuristic Metropolis
+ *   simulator").
+ *
+ * Conventions (shared by every call):
+ *   - qubit p is bit p of a uint64 bitstring; 1 <= n <= 64.
+ *   - a binary matrix row is a uint64 with bit j = entry (p, j).
+ *   - complex numbers are two doubles (re, im).
+ *   - every call returns a chsim_status; on failure nothing is written to
+ *     caller outputs that the status does not describe, and
+ *     chsim_last_error() returns a message (thread-local).
+ *   - the caller owns every pointer it passes; the library reads or writes
+ *     them only during the call.  The library owns all device memory behind
+ *     a chsim_ctx.
+ *   - `stream` is a hipStream_t or NULL (the default stream).  Without
+ *     CHSIM_DEVICE_PTRS, pointer arguments are host pointers and the call
+ *     returns after the results are in host memory.  With CHSIM_DEVICE_PTRS
+ *     they are device pointers on the context's device, and the call only
+ *     enqueues work on `stream`.
+ */
+#ifndef CHSIM_H_INCLUDED
+#define CHSIM_H_INCLUDED
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t chsim_status;
+#define CHSIM_OK 0
+#define CHSIM_EINVAL 1       /* an argument is out of range or inconsistent */
+#define CHSIM_ENOMEM 2       /* device or host allocation failed */
+#define CHSIM_EDEVICE 3      /* a HIP runtime call failed */
+#define CHSIM_EUNSUPPORTED 4 /* valid request outside what this build supports */
+#define CHSIM_ESTATE 5       /* a term violated a CH-form invariant */
+
+/* Gate codes.  CX: q = control, r = target.  SLOT: a non-Clifford gate whose
+ * Clifford decomposition is the instance's slot_decomp[slot]. */
+enum { CHSIM_H = 0, CHSIM_S = 1, CHSIM_CX = 2, CHSIM_CZ = 3, CHSIM_SLOT = 4 };
+
+typedef struct chsim_gate {
+  uint8_t op, q, r, pad;
+  uint32_t slot;
+} chsim_gate;
+
+#define CHSIM_MAX_BRANCH 8
+
+/* Clifford decomposition of one non-Clifford gate, V = sum_j coeff_j K_j
+ * (Eq. (Udecomp) per gate; the lifting lemma gives such decompositions for
+ * diagonal gates).  K_j is the gate sequence gates[off[j] .. off[j+1]),
+ * applied in order (ops in {H, S, CX, CZ}).  1 <= n_branch <= CHSIM_MAX_BRANCH. */
+typedef struct chsim_decomp {
+  uint32_t n_branch;
+  const double* coeff;     /* 2 * n_branch: (re, im) of c_j */
+  const uint32_t* off;     /* n_branch + 1 offsets into gates, off[0] = 0 */
+  const chsim_gate* gates; /* off[n_branch] gates */
+} chsim_decomp;
+
+#define CHSIM_EXACT 0    /* all prod_p n_branch(p) products, b = prod c (Eq. (Vphi)) */
+#define CHSIM_SPARSIFY 1 /* chi i.i.d. draws, Lemma (Sparsification), Eq. (Omega) */
+
+/* One circuit instance: its qubit count, slot decompositions and term set.
+ * EXACT requires chi == prod_p n_branch(p).  SPARSIFY draws, per term alpha and
+ * slot p, a uniform u from Philox4x32-10 with counter (alpha_lo, alpha_hi, p,
+ * 0x53504152) and key (seed_lo, seed_hi) (53 bits: (w0 << 21) | (w1 >> 11));
+ * branch = smallest j with u * W_p < sum_{i<=j} |c_i|, W_p = sum_i |c_i|, and
+ * b_alpha = (prod_p W_p / chi) prod_p c_j / |c_j|. */
+typedef struct chsim_instance {
+  uint32_t n;
+  uint32_t n_slot;
+  const chsim_decomp* slot_decomp; /* n_slot entries (may be NULL if n_slot == 0) */
+  uint64_t chi;
+  uint32_t mode;
+  uint64_t seed;
+} chsim_instance;
+
+typedef struct chsim_ctx chsim_ctx;
+
+/* Flags. */
+#define CHSIM_FP64 0u          /* amplitudes summed in FP64 */
+#define CHSIM_FP32C 1u         /* FP32 with per-block two-sum, FP64 across blocks */
+#define CHSIM_DEVICE_PTRS 0x100u
+
+/* Create a context on HIP device `device` holding n_inst instances; for each,
+ * choose every term's branches and coefficient b_alpha (exact enumeration or
+ * sparsification, see chsim_instance) and set every term to |0^n> (F = G = I,
+ * M = 0, gamma = v = s = 0, omega = 1; CH-form initialisation of the
+ * Clifford-simulator section).  EINVAL: n outside [1, 64], chi = 0, bad
+ * decomposition, EXACT with chi != prod n_branch.  ENOMEM: term store does not
+ * fit.  On failure *ctx is NULL. */
+chsim_status chsim_terms_init(chsim_ctx** ctx, int device, uint32_t n_inst,
+                              const chsim_instance* inst);
+
+/* Re-draw instance `inst`'s terms in place with a new seed (SPARSIFY; EXACT
+ * re-enumerates) and return every term to |0^n>, without reallocating: the
+ * term-generation step of chsim_terms_init on existing storage.  Enqueued on
+ * `stream`. */
+chsim_status chsim_terms_reset(chsim_ctx* ctx, uint32_t inst, uint64_t seed, void* stream);
+
+/* Left-multiply every term of instance `inst` by the gate sequence (Clifford
+ * gates by the rules L[S], L[CZ], L[CX]; H by Eqs. (H1)-(H7) and Prop. H; a
+ * SLOT applies the term's chosen branch K_j of that slot's decomposition).
+ * May be called repeatedly on consecutive circuit segments.  EINVAL: qubit
+ * >= n, q == r on a 2-qubit gate, slot >= n_slot.  ESTATE: a term hit a case
+ * that unitary evolution cannot produce (reported after the call). */
+chsim_status chsim_apply_clifford(chsim_ctx* ctx, uint32_t inst, const chsim_gate* gates,
+                                  size_t n_gates, void* stream);
+
+/* out[2i], out[2i+1] = <x_i|psi>, psi = sum_alpha b_alpha |phi_alpha> (not
+ * normalised), per Eqs. (amplitude), (amplitude1).  flags: CHSIM_FP64 or
+ * CHSIM_FP32C, optionally | CHSIM_DEVICE_PTRS.  EINVAL: a bitstring has a bit
+ * >= n set (checked for host pointers only), n_x == 0. */
+chsim_status chsim_amplitudes(chsim_ctx* ctx, uint32_t inst, const uint64_t* x, size_t n_x,
+                              double* out, uint32_t flags, void* stream);
+
+/* Norm estimation with equatorial states phi_A, A in M_n (Eq. (eqa1)):
+ * A_off[l*n + a] = row a of the off-diagonal part of A_l (bit b = A_ab; bit a
+ * ignored), A_diag[l*n + a] = A_aa in {0..3}.  overlap[2l..2l+1] = <phi_{A_l}|psi>
+ * (Lemma (Inner Product) with the exponential sum of Lemma (Exponential Sum));
+ * eta[l] = 2^n |overlap_l|^2; *eta_mean = mean_l eta[l] (FP64), the estimator of
+ * ||psi||^2 of Lemma (Norm Estimation).  eta and eta_mean may be NULL.
+ * EINVAL: L == 0, asymmetric A (host pointers only).  EUNSUPPORTED: n == 64
+ * with a term whose |v| == 64. */
+chsim_status chsim_inner_products(chsim_ctx* ctx, uint32_t inst, const uint64_t* A_off,
+                                  const uint8_t* A_diag, size_t L, double* overlap, double* eta,
+                                  double* eta_mean, uint32_t flags, void* stream);
+
+/* Start n_chain Metropolis chains at x0[c] (Sec. "Heuristic Metropolis
+ * simulator"): caches, per chain and term, the Pauli Q_x as (u, mu) and
+ * writes amp[2c..2c+1] = <x0_c|psi>.  Requires n <= 62.  EINVAL: some
+ * <x0_c|psi> == 0 (P(x0) must be > 0). */
+chsim_status chsim_metropolis_init(chsim_ctx* ctx, uint32_t inst, uint32_t n_chain,
+                                   const uint64_t* x0, double* amp, uint32_t flags, void* stream);
+
+/* Advance every chain n_steps single-bit-flip steps.  Step t of chain c flips
+ * bit j = j_stream[c*n_steps + t] (< n; checked for host pointers, reduced mod n
+ * on the device for device pointers) and accepts iff
+ * u_stream[c*n_steps + t] < |<y|psi>|^2 / |<x|psi>|^2 (FP64 sums, FP64
+ * ratio).  x_trace[c*n_steps + t] receives the state after step t, accepted[...]
+ * 1/0 (both may be NULL); amp (may be NULL) receives the final <x_c|psi>. */
+chsim_status chsim_metropolis_step(chsim_ctx* ctx, uint32_t inst, uint32_t n_steps,
+                                   const uint32_t* j_stream, const double* u_stream,
+                                   uint64_t* x_trace, uint8_t* accepted, double* amp,
+                                   uint32_t flags, void* stream);
+
+/* Sample one bitstring per request from a single term's |<x|phi_alpha>|^2 (the
+ * three-step sampler of the Clifford-simulator section: w = s, flip w_j where
+ * v_j = 1 and bit j of flips[i] is set, x = w G^T).  Host pointers. */
+chsim_status chsim_sample_terms(chsim_ctx* ctx, uint32_t inst, size_t count,
+                                const uint64_t* alpha, const uint64_t* flips, uint64_t* x_out);
+
+/* Download terms [first, first + count) to host arrays laid out per term:
+ * F, G, M: count*n rows; gamma: count*n; v, s: count; omega: count (Z_8,
+ * omega = e^{i pi k/4}); b: 2*count; branch: count*n_slot.  NULL skips a field. */
+chsim_status chsim_get_terms(chsim_ctx* ctx, uint32_t inst, uint64_t first, uint64_t count,
+                             uint64_t* F, uint64_t* G, uint64_t* M, uint8_t* gamma, uint64_t* v,
+                             uint64_t* s, uint8_t* omega, double* b, uint8_t* branch);
+
+/* Upload terms (same layout as chsim_get_terms; every field required except
+ * branch).  Lets the query kernels run on CH-forms built elsewhere. */
+chsim_status chsim_set_terms(chsim_ctx* ctx, uint32_t inst, uint64_t first, uint64_t count,
+                             const uint64_t* F, const uint64_t* G, const uint64_t* M,
+                             const uint8_t* gamma, const uint64_t* v, const uint64_t* s,
+                             const uint8_t* omega, const double* b);
+
+/* Decomposition of the phase gate diag(1, e^{i theta}) on `qubit`, Eq. (Rtheta)
+ * after writing theta = theta' + k pi/2 with theta' in [0, pi/2):
+ * diag(1, e^{i theta}) = c0 S^k + c1 S^{k+1}, c0 = e^{i theta'/2}(cos - sin)(theta'/2),
+ * c1 = e^{i theta'/2} sqrt(2) e^{-i pi/4} sin(theta'/2).  Writes coeff[4],
+ * off[3] and up to 7 gates into gates[8]; fills *out to point at them. */
+chsim_status chsim_decompose_phase(double theta, uint32_t qubit, double coeff[4], uint32_t off[3],
+                                   chsim_gate gates[8], chsim_decomp* out);
+
+/* Instance metadata: n, chi and ||c||_1 = prod_p W_p. */
+chsim_status chsim_instance_info(chsim_ctx* ctx, uint32_t inst, uint32_t* n, uint64_t* chi,
+                                 double* l1);
+
+/* Release the context and its device memory.  NULL is accepted. */
+chsim_status chsim_destroy(chsim_ctx* ctx);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* chsim_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CHSIM_H_INCLUDED */

@@ -1,0 +1,315 @@
+"""Thin ctypes front end of libchsim.so (the C ABI in include/chsim.h).
+
+Argument marshalling only: every step of the hot path runs in the HIP
+kernels behind the C ABI.  Inputs may be numpy arrays (host pointers) or torch
+tensors on the GPU (device pointers, enqueued on torch's current stream).
+If the library is missing, every entry point raises: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import workloads as W
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libchsim.so")
+
+CHSIM_OK, CHSIM_EINVAL, CHSIM_ENOMEM, CHSIM_EDEVICE, CHSIM_EUNSUPPORTED, CHSIM_ESTATE = range(6)
+STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "EUNSUPPORTED", 5: "ESTATE"}
+CHSIM_EXACT, CHSIM_SPARSIFY = 0, 1
+CHSIM_FP64, CHSIM_FP32C, CHSIM_DEVICE_PTRS = 0, 1, 0x100
+MAX_BRANCH = 8
+
+EXPORTED = [
+    "chsim_terms_init", "chsim_terms_reset", "chsim_apply_clifford", "chsim_amplitudes", "chsim_inner_products",
+    "chsim_metropolis_init", "chsim_metropolis_step", "chsim_sample_terms", "chsim_get_terms",
+    "chsim_set_terms", "chsim_decompose_phase", "chsim_instance_info", "chsim_destroy",
+    "chsim_last_error",
+]
+
+
+class ChsimError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"chsim {STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class Gate(C.Structure):
+    _fields_ = [("op", C.c_uint8), ("q", C.c_uint8), ("r", C.c_uint8), ("pad", C.c_uint8),
+                ("slot", C.c_uint32)]
+
+
+class Decomp(C.Structure):
+    _fields_ = [("n_branch", C.c_uint32), ("coeff", C.POINTER(C.c_double)),
+                ("off", C.POINTER(C.c_uint32)), ("gates", C.POINTER(Gate))]
+
+
+class Instance(C.Structure):
+    _fields_ = [("n", C.c_uint32), ("n_slot", C.c_uint32), ("slot_decomp", C.POINTER(Decomp)),
+                ("chi", C.c_uint64), ("mode", C.c_uint32), ("seed", C.c_uint64)]
+
+
+GATE_DTYPE = np.dtype([("op", "u1"), ("q", "u1"), ("r", "u1"), ("pad", "u1"), ("slot", "<u4")])
+
+_lib = None
+
+
+def lib():
+    """Load libchsim.so; raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                           "(or python paper_1808_00128_amd/build.py)")
+    L = C.CDLL(LIB_PATH)
+    vp, u32, u64, dbl = C.c_void_p, C.c_uint32, C.c_uint64, C.c_double
+    L.chsim_terms_init.argtypes = [C.POINTER(C.c_void_p), C.c_int, u32, C.POINTER(Instance)]
+    L.chsim_terms_reset.argtypes = [vp, u32, u64, vp]
+    L.chsim_apply_clifford.argtypes = [vp, u32, vp, C.c_size_t, vp]
+    L.chsim_amplitudes.argtypes = [vp, u32, vp, C.c_size_t, vp, u32, vp]
+    L.chsim_inner_products.argtypes = [vp, u32, vp, vp, C.c_size_t, vp, vp, vp, u32, vp]
+    L.chsim_metropolis_init.argtypes = [vp, u32, u32, vp, vp, u32, vp]
+    L.chsim_metropolis_step.argtypes = [vp, u32, u32, vp, vp, vp, vp, vp, u32, vp]
+    L.chsim_sample_terms.argtypes = [vp, u32, C.c_size_t, vp, vp, vp]
+    L.chsim_get_terms.argtypes = [vp, u32, u64, u64, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.chsim_set_terms.argtypes = [vp, u32, u64, u64, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.chsim_decompose_phase.argtypes = [dbl, u32, C.POINTER(C.c_double), C.POINTER(C.c_uint32),
+                                        C.POINTER(Gate), C.POINTER(Decomp)]
+    L.chsim_instance_info.argtypes = [vp, u32, C.POINTER(C.c_uint32), C.POINTER(C.c_uint64),
+                                      C.POINTER(C.c_double)]
+    L.chsim_destroy.argtypes = [vp]
+    L.chsim_last_error.restype = C.c_char_p
+    for name in EXPORTED:
+        if name != "chsim_last_error":
+            getattr(L, name).restype = C.c_int32
+    _lib = L
+    return L
+
+
+def _check(status):
+    if status != CHSIM_OK:
+        raise ChsimError(status, lib().chsim_last_error().decode())
+
+
+def _ptr(a):
+    """Pointer and device flag of a numpy array or torch tensor."""
+    if a is None:
+        return None, 0
+    if isinstance(a, np.ndarray):
+        if not a.flags["C_CONTIGUOUS"]:
+            raise ValueError("array must be C-contiguous")
+        return a.ctypes.data_as(C.c_void_p), 0
+    if hasattr(a, "data_ptr"):
+        if not a.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return C.c_void_p(a.data_ptr()), (CHSIM_DEVICE_PTRS if a.is_cuda else 0)
+    raise TypeError(type(a))
+
+
+def _stream(stream):
+    if stream is not None:
+        return C.c_void_p(int(stream))
+    try:
+        import torch
+
+        if torch.cuda.is_available() and torch.cuda.is_initialized():
+            return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    except Exception:  # noqa: BLE001
+        pass
+    return None
+
+
+def gate_array(circuit: W.Circuit) -> np.ndarray:
+    """Circuit -> chsim_gate[] (SLOT entries numbered in order)."""
+    g = np.zeros(circuit.n_gates, GATE_DTYPE)
+    g["op"] = circuit.op
+    g["q"] = circuit.q
+    g["r"] = circuit.r
+    slot = np.cumsum(circuit.op == W.OP_SLOT) - 1
+    g["slot"] = np.where(circuit.op == W.OP_SLOT, slot, 0).astype(np.uint32)
+    return g
+
+
+class PhaseDecomposition:
+    """chsim_decompose_phase output kept alive for the init call."""
+
+    def __init__(self, theta: float, qubit: int):
+        self.coeff = (C.c_double * 4)()
+        self.off = (C.c_uint32 * 3)()
+        self.gates = (Gate * 8)()
+        self.decomp = Decomp()
+        _check(lib().chsim_decompose_phase(float(theta), int(qubit), self.coeff, self.off, self.gates,
+                                           C.byref(self.decomp)))
+
+    @property
+    def c(self):
+        return complex(self.coeff[0], self.coeff[1]), complex(self.coeff[2], self.coeff[3])
+
+
+class Context:
+    """A set of circuit instances and their chi CH-form terms on one GPU."""
+
+    def __init__(self, specs, device: int = 0):
+        """specs: list of dicts with keys circuit, chi, mode ('exact'|'sparsify'), seed."""
+        L = lib()
+        self._keep = []
+        insts = (Instance * len(specs))()
+        self.specs = specs
+        for i, sp in enumerate(specs):
+            circ = sp["circuit"]
+            decs = []
+            slot_qubits = circ.q[circ.op == W.OP_SLOT]
+            for qb, th in zip(slot_qubits.tolist(), circ.theta.tolist()):
+                decs.append(PhaseDecomposition(th, qb))
+            arr = (Decomp * max(1, len(decs)))()
+            for k, d in enumerate(decs):
+                arr[k] = d.decomp
+            self._keep += [decs, arr]
+            mode = CHSIM_EXACT if sp.get("mode", "sparsify") == "exact" else CHSIM_SPARSIFY
+            insts[i] = Instance(circ.n, len(decs), arr, int(sp["chi"]), mode, int(sp.get("seed", 0)))
+        h = C.c_void_p()
+        _check(L.chsim_terms_init(C.byref(h), device, len(specs), insts))
+        self._h = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().chsim_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001
+            pass
+
+    def info(self, inst=0):
+        n = C.c_uint32()
+        chi = C.c_uint64()
+        l1 = C.c_double()
+        _check(lib().chsim_instance_info(self._h, inst, C.byref(n), C.byref(chi), C.byref(l1)))
+        return n.value, chi.value, l1.value
+
+    # ---- step (a) ----
+    def reset(self, seed, inst=0, stream=None):
+        """Re-draw the terms with a new seed and return them to |0^n> (no allocation)."""
+        _check(lib().chsim_terms_reset(self._h, inst, int(seed), _stream(stream)))
+        self.specs[inst] = dict(self.specs[inst], seed=int(seed))
+
+    def apply_gates(self, gates: np.ndarray, inst=0, stream=None):
+        gates = np.ascontiguousarray(gates, GATE_DTYPE)
+        p, _ = _ptr(gates)
+        _check(lib().chsim_apply_clifford(self._h, inst, p, gates.size, _stream(stream)))
+
+    def apply_circuit(self, circuit: W.Circuit, inst=0, stream=None):
+        self.apply_gates(gate_array(circuit), inst, stream)
+
+    # ---- step (b) ----
+    def amplitudes(self, x, inst=0, fp32c=False, out=None, stream=None):
+        """<x_i|psi>.  numpy uint64 in -> numpy complex128 out; a CUDA int64
+        tensor in -> a CUDA float64 tensor [n_x, 2] out (asynchronous)."""
+        flags = CHSIM_FP32C if fp32c else CHSIM_FP64
+        if isinstance(x, np.ndarray):
+            x = np.ascontiguousarray(x, np.uint64)
+            res = np.zeros(2 * x.size)
+            px, _ = _ptr(x)
+            po, _ = _ptr(res)
+            _check(lib().chsim_amplitudes(self._h, inst, px, x.size, po, flags, _stream(stream)))
+            return res[0::2] + 1j * res[1::2]
+        import torch
+
+        if out is None:
+            out = torch.empty((x.numel(), 2), dtype=torch.float64, device=x.device)
+        px, f1 = _ptr(x)
+        po, f2 = _ptr(out)
+        if not (f1 and f2):
+            raise ValueError("torch inputs must be on the GPU")
+        _check(lib().chsim_amplitudes(self._h, inst, px, x.numel(), po, flags | CHSIM_DEVICE_PTRS,
+                                      _stream(stream)))
+        return out
+
+    # ---- step (c) ----
+    def inner_products(self, Aoff, Adiag, inst=0, stream=None):
+        """(overlap complex[L], eta[L], eta_mean) for equatorial states A_l."""
+        Aoff = np.ascontiguousarray(Aoff, np.uint64)
+        Adiag = np.ascontiguousarray(Adiag, np.uint8)
+        L = Aoff.shape[0]
+        ov = np.zeros(2 * L)
+        eta = np.zeros(L)
+        mean = C.c_double()
+        _check(lib().chsim_inner_products(self._h, inst, _ptr(Aoff)[0], _ptr(Adiag)[0], L,
+                                          _ptr(ov)[0], _ptr(eta)[0], C.byref(mean), 0,
+                                          _stream(stream)))
+        return ov[0::2] + 1j * ov[1::2], eta, mean.value
+
+    # ---- Metropolis ----
+    def metropolis_init(self, x0, inst=0, stream=None):
+        x0 = np.ascontiguousarray(x0, np.uint64)
+        amp = np.zeros(2 * x0.size)
+        _check(lib().chsim_metropolis_init(self._h, inst, x0.size, _ptr(x0)[0], _ptr(amp)[0], 0,
+                                           _stream(stream)))
+        self._n_chain = x0.size
+        return amp[0::2] + 1j * amp[1::2]
+
+    def metropolis_step(self, jstream, ustream, inst=0, trace=True, stream=None):
+        """Advance all chains; jstream/ustream are [n_chain, n_steps]."""
+        j = np.ascontiguousarray(jstream, np.uint32)
+        u = np.ascontiguousarray(ustream, np.float64)
+        n_chain, n_steps = j.shape
+        tr = np.zeros((n_chain, n_steps), np.uint64) if trace else None
+        acc = np.zeros((n_chain, n_steps), np.uint8) if trace else None
+        amp = np.zeros(2 * n_chain)
+        _check(lib().chsim_metropolis_step(self._h, inst, n_steps, _ptr(j)[0], _ptr(u)[0],
+                                           _ptr(tr)[0], _ptr(acc)[0], _ptr(amp)[0], 0,
+                                           _stream(stream)))
+        return tr, acc, amp[0::2] + 1j * amp[1::2]
+
+    def metropolis_step_device(self, jstream, ustream, trace=None, accepted=None, amp=None,
+                               inst=0, stream=None):
+        """Device-pointer variant: torch tensors on the GPU; enqueues only."""
+        n_chain, n_steps = jstream.shape
+        args = [_ptr(t)[0] for t in (jstream, ustream, trace, accepted, amp)]
+        _check(lib().chsim_metropolis_step(self._h, inst, n_steps, *args, CHSIM_DEVICE_PTRS,
+                                           _stream(stream)))
+
+    def sample_terms(self, alpha, flips, inst=0):
+        alpha = np.ascontiguousarray(alpha, np.uint64)
+        flips = np.ascontiguousarray(flips, np.uint64)
+        out = np.zeros(alpha.size, np.uint64)
+        _check(lib().chsim_sample_terms(self._h, inst, alpha.size, _ptr(alpha)[0], _ptr(flips)[0],
+                                        _ptr(out)[0]))
+        return out
+
+    # ---- term store access ----
+    def get_terms(self, first, count, inst=0):
+        n, chi, _ = self.info(inst)
+        m = self.specs[inst]["circuit"].n_slot
+        F = np.zeros((count, n), np.uint64)
+        G = np.zeros((count, n), np.uint64)
+        M = np.zeros((count, n), np.uint64)
+        g = np.zeros((count, n), np.uint8)
+        v = np.zeros(count, np.uint64)
+        s = np.zeros(count, np.uint64)
+        w = np.zeros(count, np.uint8)
+        b = np.zeros(2 * count)
+        br = np.zeros((count, max(1, m)), np.uint8)
+        _check(lib().chsim_get_terms(self._h, inst, first, count, *[_ptr(a)[0] for a in
+                                                                  (F, G, M, g, v, s, w, b, br)]))
+        return dict(F=F, G=G, M=M, gamma=g, v=v, s=s, omega=w, b=b[0::2] + 1j * b[1::2],
+                    branch=br[:, :m])
+
+    def set_terms(self, first, F, G, M, gamma, v, s, omega, b, inst=0):
+        count = len(v)
+        arrs = [np.ascontiguousarray(F, np.uint64), np.ascontiguousarray(G, np.uint64),
+                np.ascontiguousarray(M, np.uint64), np.ascontiguousarray(gamma, np.uint8),
+                np.ascontiguousarray(v, np.uint64), np.ascontiguousarray(s, np.uint64),
+                np.ascontiguousarray(omega, np.uint8)]
+        bb = np.zeros(2 * count)
+        bb[0::2] = np.real(b)
+        bb[1::2] = np.imag(b)
+        _check(lib().chsim_set_terms(self._h, inst, first, count, *[_ptr(a)[0] for a in arrs],
+                                     _ptr(bb)[0]))

@@ -1,0 +1,751 @@
+// C ABI of libchsim (declared in include/chsim.h): argument checks, device
+// memory of the term store, host-side decomposition tables, and the calls
+// that launch the kernels.  Every step of the hot path runs in the HIP kernels;
+// this file only validates, allocates, copies and launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "chsim.h"
+#include "internal.hpp"
+
+using namespace chsim;
+
+namespace {
+
+thread_local std::string g_err;
+
+chsim_status fail(chsim_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess) return fail(CHSIM_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+template <typename T>
+struct DevBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  hipError_t ensure(size_t count) {
+    if (count <= n) return hipSuccess;
+    if (p) hipFree(p);
+    p = nullptr;
+    n = 0;
+    hipError_t e = hipMalloc(&p, std::max<size_t>(count, 1) * sizeof(T));
+    if (e == hipSuccess) n = count;
+    return e;
+  }
+  void release() {
+    if (p) hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+};
+
+struct Instance {
+  uint32_t n = 0, n_slot = 0, mode = 0;
+  uint64_t chi = 0, seed = 0;
+  double l1 = 1.0;
+  bool at_zero = true;  // every term is |0^n> and the store holds nothing yet
+  std::vector<SlotTable> slots_h;
+  std::vector<DGate> bgates_h;
+  DevBuf<uint64_t> F, G, M, v, s;
+  DevBuf<uint8_t> gamma, omega, branch;
+  DevBuf<double2> b;
+  DevBuf<SlotTable> slots;
+  DevBuf<DGate> bgates;
+  // metropolis
+  uint32_t n_chain = 0;
+  DevBuf<uint64_t> mstate0, mstate1, mx, mtrace;
+  DevBuf<uint32_t> mparity, mj;
+  DevBuf<double2> mamp, mpartial;
+  DevBuf<double> mu;
+  DevBuf<uint8_t> macc;
+
+  TermsView view() {
+    TermsView t;
+    t.n = n;
+    t.n_slot = n_slot;
+    t.chi = chi;
+    t.F = F.p;
+    t.G = G.p;
+    t.M = M.p;
+    t.gamma = gamma.p;
+    t.v = v.p;
+    t.s = s.p;
+    t.omega = omega.p;
+    t.b = b.p;
+    t.branch = branch.p;
+    return t;
+  }
+  void release() {
+    F.release(); G.release(); M.release(); v.release(); s.release();
+    gamma.release(); omega.release(); branch.release(); b.release();
+    slots.release(); bgates.release();
+    mstate0.release(); mstate1.release(); mx.release(); mtrace.release();
+    mparity.release(); mj.release(); mamp.release(); mpartial.release(); mu.release(); macc.release();
+  }
+};
+
+}  // namespace
+
+struct chsim_ctx {
+  int device = 0;
+  std::vector<Instance> inst;
+  DevBuf<DGate> gates;
+  DevBuf<uint32_t> err;
+  DevBuf<uint64_t> xbuf;
+  DevBuf<double2> partial, out;
+  DevBuf<uint64_t> aoff;
+  DevBuf<uint8_t> adiag;
+  DevBuf<double> eta;
+  DevBuf<double> eta_sum;
+};
+
+namespace {
+
+chsim_status check_ctx(chsim_ctx* ctx, uint32_t inst) {
+  if (!ctx) return fail(CHSIM_EINVAL, "null context");
+  if (inst >= ctx->inst.size()) return fail(CHSIM_EINVAL, "instance %u out of range", inst);
+  return CHSIM_OK;
+}
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+bool valid_clifford(const chsim_gate& g, uint32_t n) {
+  if (g.q >= n) return false;
+  if (g.op == CHSIM_CX || g.op == CHSIM_CZ) return g.r < n && g.r != g.q;
+  return g.op == CHSIM_H || g.op == CHSIM_S;
+}
+
+// Append a gate, folding runs of S on one qubit into one SPOW; gates before
+// index `first` (an earlier branch) are never merged into.
+void push_gate(std::vector<DGate>& out, const chsim_gate& g, size_t first = 0) {
+  if (g.op == CHSIM_S) {
+    if (out.size() > first && (out.back().op == OP_SPOW) && out.back().q == g.q) {
+      out.back().arg = (uint8_t)((out.back().arg + 1) & 3);
+      return;
+    }
+    out.push_back(DGate{OP_SPOW, g.q, 0, 1, 0});
+    return;
+  }
+  out.push_back(DGate{g.op, g.q, g.r, 0, g.slot});
+}
+
+chsim_status build_slots(Instance& I, const chsim_instance& in) {
+  I.slots_h.clear();
+  I.bgates_h.clear();
+  double l1 = 1.0;
+  for (uint32_t p = 0; p < in.n_slot; ++p) {
+    const chsim_decomp& d = in.slot_decomp[p];
+    if (d.n_branch < 1 || d.n_branch > CHSIM_MAX_BRANCH || !d.coeff || !d.off || (!d.gates && d.off[d.n_branch]))
+      return fail(CHSIM_EINVAL, "slot %u: bad decomposition", p);
+    if (d.off[0] != 0) return fail(CHSIM_EINVAL, "slot %u: off[0] must be 0", p);
+    SlotTable st;
+    std::memset(&st, 0, sizeof st);
+    st.n_branch = d.n_branch;
+    double cum = 0.0;
+    for (uint32_t j = 0; j < d.n_branch; ++j) {
+      if (d.off[j + 1] < d.off[j]) return fail(CHSIM_EINVAL, "slot %u: offsets decrease", p);
+      st.goff[j] = (uint32_t)I.bgates_h.size();
+      for (uint32_t k = d.off[j]; k < d.off[j + 1]; ++k) {
+        const chsim_gate& g = d.gates[k];
+        if (!valid_clifford(g, in.n)) return fail(CHSIM_EINVAL, "slot %u branch %u: bad gate %u", p, j, k);
+        push_gate(I.bgates_h, g, st.goff[j]);
+      }
+      const double re = d.coeff[2 * j], im = d.coeff[2 * j + 1];
+      const double w = std::sqrt(re * re + im * im);
+      cum += w;
+      st.cum[j] = cum;
+      st.coef_re[j] = re;
+      st.coef_im[j] = im;
+      st.unit_re[j] = w > 0.0 ? re / w : 0.0;
+      st.unit_im[j] = w > 0.0 ? im / w : 0.0;
+    }
+    st.goff[d.n_branch] = (uint32_t)I.bgates_h.size();
+    st.total = cum;
+    if (!(cum > 0.0) || !std::isfinite(cum)) return fail(CHSIM_EINVAL, "slot %u: zero or non-finite weights", p);
+    l1 *= cum;
+    I.slots_h.push_back(st);
+  }
+  I.l1 = l1;
+  return CHSIM_OK;
+}
+
+// Upload a host or device input array into a device buffer; returns the device pointer.
+template <typename T>
+chsim_status stage_in(DevBuf<T>& buf, const T* src, size_t count, bool device_ptrs, hipStream_t st,
+                      const T** out) {
+  if (device_ptrs) {
+    *out = src;
+    return CHSIM_OK;
+  }
+  HIP_TRY(buf.ensure(count));
+  HIP_TRY(hipMemcpyAsync(buf.p, src, count * sizeof(T), hipMemcpyHostToDevice, st));
+  *out = buf.p;
+  return CHSIM_OK;
+}
+
+chsim_status ensure_materialised(Instance& I, hipStream_t st) {
+  if (!I.at_zero) return CHSIM_OK;
+  HIP_TRY(launch_set_zero(I.view(), st));
+  I.at_zero = false;
+  return CHSIM_OK;
+}
+
+chsim_status check_err_flag(chsim_ctx* ctx, hipStream_t st, const char* what) {
+  uint32_t flag = 0;
+  HIP_TRY(hipMemcpyAsync(&flag, ctx->err.p, sizeof flag, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (flag) return fail(CHSIM_ESTATE, "%s: a term violated a CH-form invariant", what);
+  return CHSIM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* chsim_last_error(void) { return g_err.c_str(); }
+
+chsim_status chsim_terms_init(chsim_ctx** out, int device, uint32_t n_inst,
+                              const chsim_instance* inst) {
+  g_err.clear();
+  if (!out) return fail(CHSIM_EINVAL, "null output pointer");
+  *out = nullptr;
+  if (n_inst == 0 || !inst) return fail(CHSIM_EINVAL, "no instances");
+  // Validate everything before touching a device.
+  for (uint32_t i = 0; i < n_inst; ++i) {
+    const chsim_instance& in = inst[i];
+    if (in.n < 1 || in.n > 64) return fail(CHSIM_EINVAL, "instance %u: n = %u outside [1, 64]", i, in.n);
+    if (in.chi == 0) return fail(CHSIM_EINVAL, "instance %u: chi = 0", i);
+    if (in.n_slot && !in.slot_decomp) return fail(CHSIM_EINVAL, "instance %u: missing decompositions", i);
+    if (in.mode != CHSIM_EXACT && in.mode != CHSIM_SPARSIFY) return fail(CHSIM_EINVAL, "instance %u: bad mode", i);
+    if (in.mode == CHSIM_EXACT) {
+      long double prod = 1.0L;
+      for (uint32_t p = 0; p < in.n_slot; ++p) prod *= in.slot_decomp[p].n_branch;
+      if (prod != (long double)in.chi) return fail(CHSIM_EINVAL, "instance %u: EXACT needs chi = prod n_branch", i);
+    }
+  }
+  int ndev = 0;
+  HIP_TRY(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) return fail(CHSIM_EINVAL, "device %d not present", device);
+  HIP_TRY(hipSetDevice(device));
+  chsim_ctx* ctx = new chsim_ctx();
+  ctx->device = device;
+  ctx->inst.resize(n_inst);
+  auto cleanup = [&](chsim_status st) {
+    chsim_destroy(ctx);
+    return st;
+  };
+  if (ctx->err.ensure(1) != hipSuccess) return cleanup(fail(CHSIM_ENOMEM, "error flag allocation"));
+  for (uint32_t i = 0; i < n_inst; ++i) {
+    const chsim_instance& in = inst[i];
+    Instance& I = ctx->inst[i];
+    I.n = in.n;
+    I.n_slot = in.n_slot;
+    I.chi = in.chi;
+    I.mode = in.mode;
+    I.seed = in.seed;
+    chsim_status st = build_slots(I, in);
+    if (st != CHSIM_OK) return cleanup(st);
+    const size_t rows = (size_t)in.n * in.chi;
+    bool ok = I.F.ensure(rows) == hipSuccess && I.G.ensure(rows) == hipSuccess &&
+              I.M.ensure(rows) == hipSuccess && I.gamma.ensure(rows) == hipSuccess &&
+              I.v.ensure(in.chi) == hipSuccess && I.s.ensure(in.chi) == hipSuccess &&
+              I.omega.ensure(in.chi) == hipSuccess && I.b.ensure(in.chi) == hipSuccess &&
+              I.branch.ensure((size_t)std::max<uint32_t>(in.n_slot, 1) * in.chi) == hipSuccess &&
+              I.slots.ensure(std::max<size_t>(I.slots_h.size(), 1)) == hipSuccess &&
+              I.bgates.ensure(std::max<size_t>(I.bgates_h.size(), 1)) == hipSuccess;
+    if (!ok) return cleanup(fail(CHSIM_ENOMEM, "instance %u: term store (%zu rows) does not fit", i, rows));
+    if (!I.slots_h.empty() &&
+        hipMemcpy(I.slots.p, I.slots_h.data(), I.slots_h.size() * sizeof(SlotTable), hipMemcpyHostToDevice) != hipSuccess)
+      return cleanup(fail(CHSIM_EDEVICE, "slot table upload"));
+    if (!I.bgates_h.empty() &&
+        hipMemcpy(I.bgates.p, I.bgates_h.data(), I.bgates_h.size() * sizeof(DGate), hipMemcpyHostToDevice) != hipSuccess)
+      return cleanup(fail(CHSIM_EDEVICE, "branch gate upload"));
+    const double scale = I.l1 / (double)I.chi;
+    if (launch_choose(I.view(), I.slots.p, I.mode, I.seed, scale, nullptr) != hipSuccess)
+      return cleanup(fail(CHSIM_EDEVICE, "branch choice kernel"));
+    I.at_zero = true;
+  }
+  if (hipDeviceSynchronize() != hipSuccess) return cleanup(fail(CHSIM_EDEVICE, "init synchronize"));
+  *out = ctx;
+  return CHSIM_OK;
+}
+
+chsim_status chsim_terms_reset(chsim_ctx* ctx, uint32_t inst, uint64_t seed, void* stream) {
+  g_err.clear();
+  chsim_status st = check_ctx(ctx, inst);
+  if (st) return st;
+  Instance& I = ctx->inst[inst];
+  HIP_TRY(hipSetDevice(ctx->device));
+  I.seed = seed;
+  const double scale = I.l1 / (double)I.chi;
+  HIP_TRY(launch_choose(I.view(), I.slots.p, I.mode, I.seed, scale, as_stream(stream)));
+  I.at_zero = true;
+  I.n_chain = 0;
+  return CHSIM_OK;
+}
+
+chsim_status chsim_apply_clifford(chsim_ctx* ctx, uint32_t inst, const chsim_gate* gates,
+                                  size_t n_gates, void* stream) {
+  g_err.clear();
+  chsim_status st = check_ctx(ctx, inst);
+  if (st) return st;
+  if (n_gates == 0) return CHSIM_OK;
+  if (!gates) return fail(CHSIM_EINVAL, "null gate list");
+  Instance& I = ctx->inst[inst];
+  std::vector<DGate> dg;
+  dg.reserve(n_gates);
+  for (size_t i = 0; i < n_gates; ++i) {
+    const chsim_gate& g = gates[i];
+    if (g.op == CHSIM_SLOT) {
+      if (g.slot >= I.n_slot) return fail(CHSIM_EINVAL, "gate %zu: slot %u >= n_slot %u", i, g.slot, I.n_slot);
+      dg.push_back(DGate{OP_SLOT, 0, 0, 0, g.slot});
+    } else {
+      if (!valid_clifford(g, I.n)) return fail(CHSIM_EINVAL, "gate %zu: (%u, %u, %u) invalid for n = %u", i, g.op, g.q, g.r, I.n);
+      push_gate(dg, g);
+    }
+  }
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t s = as_stream(stream);
+  HIP_TRY(ctx->gates.ensure(dg.size()));
+  HIP_TRY(hipMemcpyAsync(ctx->gates.p, dg.data(), dg.size() * sizeof(DGate), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemsetAsync(ctx->err.p, 0, sizeof(uint32_t), s));
+  HIP_TRY(launch_evolve(I.view(), ctx->gates.p, (uint32_t)dg.size(), I.slots.p, I.bgates.p, I.at_zero,
+                        ctx->err.p, s));
+  I.at_zero = false;
+  return check_err_flag(ctx, s, "apply_clifford");
+}
+
+chsim_status chsim_amplitudes(chsim_ctx* ctx, uint32_t inst, const uint64_t* x, size_t n_x,
+                              double* out, uint32_t flags, void* stream) {
+  g_err.clear();
+  chsim_status st = check_ctx(ctx, inst);
+  if (st) return st;
+  if (n_x == 0 || !x || !out) return fail(CHSIM_EINVAL, "empty or null bitstring/output arrays");
+  if (n_x > 0xFFFFFFFFull) return fail(CHSIM_EINVAL, "too many bitstrings");
+  Instance& I = ctx->inst[inst];
+  const bool dev = flags & CHSIM_DEVICE_PTRS;
+  if (!dev && I.n < 64) {
+    const uint64_t bad = ~((1ull << I.n) - 1ull);
+    for (size_t i = 0; i < n_x; ++i)
+      if (x[i] & bad) return fail(CHSIM_EINVAL, "bitstring %zu has bits >= n = %u", i, I.n);
+  }
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t s = as_stream(stream);
+  st = ensure_materialised(I, s);
+  if (st) return st;
+  const uint64_t* xd;
+  st = stage_in(ctx->xbuf, x, n_x, dev, s, &xd);
+  if (st) return st;
+  HIP_TRY(ctx->partial.ensure(amp_partial_elems(I.view(), (uint32_t)n_x)));
+  double2* outd;
+  if (dev) outd = reinterpret_cast<double2*>(out);
+  else {
+    HIP_TRY(ctx->out.ensure(n_x));
+    outd = ctx->out.p;
+  }
+  HIP_TRY(launch_amplitudes(I.view(), xd, (uint32_t)n_x, (flags & CHSIM_FP32C) != 0, ctx->partial.p, outd, s));
+  if (!dev) {
+    HIP_TRY(hipMemcpyAsync(out, outd, n_x * sizeof(double2), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+  return CHSIM_OK;
+}
+
+chsim_status chsim_inner_products(chsim_ctx* ctx, uint32_t inst, const uint64_t* A_off,
+                                  const uint8_t* A_diag, size_t L, double* overlap, double* eta,
+                                  double* eta_mean, uint32_t flags, void* stream) {
+  g_err.clear();
+  chsim_status st = check_ctx(ctx, inst);
+  if (st) return st;
+  if (L == 0 || !A_off || !A_diag || !overlap) return fail(CHSIM_EINVAL, "empty or null inputs");
+  Instance& I = ctx->inst[inst];
+  const bool dev = flags & CHSIM_DEVICE_PTRS;
+  const uint32_t n = I.n;
+  if (!dev) {
+    const uint64_t nm = (n == 64) ? ~0ull : ((1ull << n) - 1ull);
+    for (size_t l = 0; l < L; ++l)
+      for (uint32_t a = 0; a < n; ++a) {
+        const uint64_t row = A_off[l * n + a] & ~(1ull << a);
+        if (row & ~nm) return fail(CHSIM_EINVAL, "A_%zu row %u has bits >= n", l, a);
+        if (A_diag[l * n + a] > 3) return fail(CHSIM_EINVAL, "A_%zu diagonal entry %u not in Z_4", l, a);
+        for (uint32_t b = a + 1; b < n; ++b)
+          if (((row >> b) & 1ull) != ((A_off[l * n + b] >> a) & 1ull))
+            return fail(CHSIM_EINVAL, "A_%zu is not symmetric at (%u, %u)", l, a, b);
+      }
+  }
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t s = as_stream(stream);
+  st = ensure_materialised(I, s);
+  if (st) return st;
+  HIP_TRY(hipMemsetAsync(ctx->err.p, 0, sizeof(uint32_t), s));
+  HIP_TRY(ctx->eta_sum.ensure(1));
+  double total = 0.0;
+  // Chunks of equatorial states bound the LDS accumulator of the kernel.
+  const size_t kChunk = 2048;
+  std::vector<double> eta_host;
+  for (size_t l0 = 0; l0 < L; l0 += kChunk) {
+    const uint32_t Lc = (uint32_t)std::min(kChunk, L - l0);
+    const uint64_t* ao;
+    const uint8_t* ad;
+    if (dev) {
+      ao = A_off + l0 * n;
+      ad = A_diag + l0 * n;
+    } else {
+      HIP_TRY(ctx->aoff.ensure((size_t)Lc * n));
+      HIP_TRY(ctx->adiag.ensure((size_t)Lc * n));
+      HIP_TRY(hipMemcpyAsync(ctx->aoff.p, A_off + l0 * n, (size_t)Lc * n * 8, hipMemcpyHostToDevice, s));
+      HIP_TRY(hipMemcpyAsync(ctx->adiag.p, A_diag + l0 * n, (size_t)Lc * n, hipMemcpyHostToDevice, s));
+      ao = ctx->aoff.p;
+      ad = ctx->adiag.p;
+    }
+    uint32_t nb = 0;
+    HIP_TRY(ctx->partial.ensure(inner_partial_elems(I.view(), Lc, &nb)));
+    double2* ovd;
+    double* etad;
+    if (dev) {
+      ovd = reinterpret_cast<double2*>(overlap) + l0;
+      if (eta) etad = eta + l0;
+      else {
+        HIP_TRY(ctx->eta.ensure(Lc));
+        etad = ctx->eta.p;
+      }
+    } else {
+      HIP_TRY(ctx->out.ensure(Lc));
+      HIP_TRY(ctx->eta.ensure(Lc));
+      ovd = ctx->out.p;
+      etad = ctx->eta.p;
+    }
+    HIP_TRY(launch_inner(I.view(), ao, ad, Lc, ctx->partial.p, nb, ovd, etad, ctx->eta_sum.p, ctx->err.p, s));
+    double part = 0.0;
+    HIP_TRY(hipMemcpyAsync(&part, ctx->eta_sum.p, sizeof(double), hipMemcpyDeviceToHost, s));
+    if (!dev) {
+      HIP_TRY(hipMemcpyAsync(overlap + 2 * l0, ovd, (size_t)Lc * sizeof(double2), hipMemcpyDeviceToHost, s));
+      if (eta) HIP_TRY(hipMemcpyAsync(eta + l0, etad, (size_t)Lc * sizeof(double), hipMemcpyDeviceToHost, s));
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    total += part;
+  }
+  if (eta_mean) *eta_mean = total / (double)L;
+  uint32_t flag = 0;
+  HIP_TRY(hipMemcpy(&flag, ctx->err.p, sizeof flag, hipMemcpyDeviceToHost));
+  if (flag) return fail(CHSIM_EUNSUPPORTED, "a term has |v| = 64 (no free index for the Z_2 lift)");
+  return CHSIM_OK;
+}
+
+static MetroView metro_view(Instance& I) {
+  MetroView m;
+  m.n_chain = I.n_chain;
+  m.n_tiles = (uint32_t)((I.chi + kMetroTile - 1) / kMetroTile);
+  m.state[0] = I.mstate0.p;
+  m.state[1] = I.mstate1.p;
+  m.parity = I.mparity.p;
+  m.x = I.mx.p;
+  m.amp = I.mamp.p;
+  m.partial = I.mpartial.p;
+  m.jstream = I.mj.p;
+  m.ustream = I.mu.p;
+  m.trace = nullptr;
+  m.accepted = nullptr;
+  m.n_steps = 0;
+  m.n_qubits = I.n;
+  return m;
+}
+
+chsim_status chsim_metropolis_init(chsim_ctx* ctx, uint32_t inst, uint32_t n_chain,
+                                   const uint64_t* x0, double* amp, uint32_t flags, void* stream) {
+  g_err.clear();
+  chsim_status st = check_ctx(ctx, inst);
+  if (st) return st;
+  Instance& I = ctx->inst[inst];
+  if (n_chain == 0 || !x0) return fail(CHSIM_EINVAL, "no chains");
+  if (I.n > 62) return fail(CHSIM_EUNSUPPORTED, "Metropolis state packs u and mu into 64 bits: needs n <= 62");
+  const bool dev = flags & CHSIM_DEVICE_PTRS;
+  if (!dev && I.n < 64) {
+    const uint64_t bad = ~((1ull << I.n) - 1ull);
+    for (uint32_t c = 0; c < n_chain; ++c)
+      if (x0[c] & bad) return fail(CHSIM_EINVAL, "x0[%u] has bits >= n", c);
+  }
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t s = as_stream(stream);
+  st = ensure_materialised(I, s);
+  if (st) return st;
+  I.n_chain = n_chain;
+  const size_t cells = (size_t)n_chain * I.chi;
+  const uint32_t tiles = (uint32_t)((I.chi + kMetroTile - 1) / kMetroTile);
+  if (I.mstate0.ensure(cells) != hipSuccess || I.mstate1.ensure(cells) != hipSuccess)
+    return fail(CHSIM_ENOMEM, "chain state (%zu words x 2) does not fit", cells);
+  HIP_TRY(I.mparity.ensure(n_chain));
+  HIP_TRY(I.mx.ensure(n_chain));
+  HIP_TRY(I.mamp.ensure(n_chain));
+  HIP_TRY(I.mpartial.ensure((size_t)n_chain * tiles));
+  HIP_TRY(hipMemcpyAsync(I.mx.p, x0, n_chain * 8, dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+  MetroView mv = metro_view(I);
+  HIP_TRY(launch_metro_init(I.view(), mv, s));
+  std::vector<double2> a(n_chain);
+  HIP_TRY(hipMemcpyAsync(a.data(), I.mamp.p, n_chain * sizeof(double2), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  for (uint32_t c = 0; c < n_chain; ++c)
+    if (a[c].x == 0.0 && a[c].y == 0.0) {
+      I.n_chain = 0;
+      return fail(CHSIM_EINVAL, "chain %u starts at a string with <x|psi> = 0", c);
+    }
+  if (amp) {
+    if (dev) HIP_TRY(hipMemcpyAsync(amp, I.mamp.p, n_chain * sizeof(double2), hipMemcpyDeviceToDevice, s));
+    else std::memcpy(amp, a.data(), n_chain * sizeof(double2));
+  }
+  return CHSIM_OK;
+}
+
+chsim_status chsim_metropolis_step(chsim_ctx* ctx, uint32_t inst, uint32_t n_steps,
+                                   const uint32_t* j_stream, const double* u_stream,
+                                   uint64_t* x_trace, uint8_t* accepted, double* amp,
+                                   uint32_t flags, void* stream) {
+  g_err.clear();
+  chsim_status st = check_ctx(ctx, inst);
+  if (st) return st;
+  Instance& I = ctx->inst[inst];
+  if (I.n_chain == 0) return fail(CHSIM_EINVAL, "chains not initialised");
+  if (n_steps == 0) return CHSIM_OK;
+  if (!j_stream || !u_stream) return fail(CHSIM_EINVAL, "null random streams");
+  const bool dev = flags & CHSIM_DEVICE_PTRS;
+  const size_t cnt = (size_t)I.n_chain * n_steps;
+  if (!dev)
+    for (size_t i = 0; i < cnt; ++i)
+      if (j_stream[i] >= I.n) return fail(CHSIM_EINVAL, "j_stream[%zu] = %u >= n", i, j_stream[i]);
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t s = as_stream(stream);
+  MetroView mv = metro_view(I);
+  mv.n_steps = n_steps;
+  const uint32_t* jd;
+  const double* ud;
+  st = stage_in(I.mj, j_stream, cnt, dev, s, &jd);
+  if (st) return st;
+  st = stage_in(I.mu, u_stream, cnt, dev, s, &ud);
+  if (st) return st;
+  mv.jstream = jd;
+  mv.ustream = ud;
+  if (x_trace) {
+    if (dev) mv.trace = x_trace;
+    else {
+      HIP_TRY(I.mtrace.ensure(cnt));
+      mv.trace = I.mtrace.p;
+    }
+  }
+  if (accepted) {
+    if (dev) mv.accepted = accepted;
+    else {
+      HIP_TRY(I.macc.ensure(cnt));
+      mv.accepted = I.macc.p;
+    }
+  }
+  HIP_TRY(launch_metro_steps(I.view(), mv, n_steps, s));
+  if (!dev) {
+    if (x_trace) HIP_TRY(hipMemcpyAsync(x_trace, mv.trace, cnt * 8, hipMemcpyDeviceToHost, s));
+    if (accepted) HIP_TRY(hipMemcpyAsync(accepted, mv.accepted, cnt, hipMemcpyDeviceToHost, s));
+    if (amp) HIP_TRY(hipMemcpyAsync(amp, I.mamp.p, I.n_chain * sizeof(double2), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  } else if (amp) {
+    HIP_TRY(hipMemcpyAsync(amp, I.mamp.p, I.n_chain * sizeof(double2), hipMemcpyDeviceToDevice, s));
+  }
+  return CHSIM_OK;
+}
+
+chsim_status chsim_sample_terms(chsim_ctx* ctx, uint32_t inst, size_t count, const uint64_t* alpha,
+                                const uint64_t* flips, uint64_t* x_out) {
+  g_err.clear();
+  chsim_status st = check_ctx(ctx, inst);
+  if (st) return st;
+  if (count == 0) return CHSIM_OK;
+  if (!alpha || !flips || !x_out) return fail(CHSIM_EINVAL, "null arrays");
+  Instance& I = ctx->inst[inst];
+  for (size_t i = 0; i < count; ++i)
+    if (alpha[i] >= I.chi) return fail(CHSIM_EINVAL, "term index %zu out of range", i);
+  HIP_TRY(hipSetDevice(ctx->device));
+  st = ensure_materialised(I, nullptr);
+  if (st) return st;
+  DevBuf<uint64_t> buf;
+  HIP_TRY(buf.ensure(3 * count));
+  HIP_TRY(hipMemcpy(buf.p, alpha, count * 8, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(buf.p + count, flips, count * 8, hipMemcpyHostToDevice));
+  hipError_t e = launch_sample(I.view(), buf.p, buf.p + count, buf.p + 2 * count, (uint32_t)count, nullptr);
+  if (e == hipSuccess) e = hipMemcpy(x_out, buf.p + 2 * count, count * 8, hipMemcpyDeviceToHost);
+  buf.release();
+  if (e != hipSuccess) return fail(CHSIM_EDEVICE, "sample: %s", hipGetErrorString(e));
+  return CHSIM_OK;
+}
+
+chsim_status chsim_get_terms(chsim_ctx* ctx, uint32_t inst, uint64_t first, uint64_t count,
+                             uint64_t* F, uint64_t* G, uint64_t* M, uint8_t* gamma, uint64_t* v,
+                             uint64_t* s, uint8_t* omega, double* b, uint8_t* branch) {
+  g_err.clear();
+  chsim_status st = check_ctx(ctx, inst);
+  if (st) return st;
+  Instance& I = ctx->inst[inst];
+  if (first > I.chi || count > I.chi - first) return fail(CHSIM_EINVAL, "term range out of bounds");
+  if (count == 0) return CHSIM_OK;
+  HIP_TRY(hipSetDevice(ctx->device));
+  st = ensure_materialised(I, nullptr);
+  if (st) return st;
+  HIP_TRY(hipDeviceSynchronize());
+  const uint32_t n = I.n;
+  // Rows are strided by chi on the device: copy each row's slice, then transpose.
+  auto rows = [&](uint64_t* dst, const uint64_t* src) -> chsim_status {
+    if (!dst) return CHSIM_OK;
+    std::vector<uint64_t> tmp((size_t)n * count);
+    HIP_TRY(hipMemcpy2D(tmp.data(), count * 8, src + first, I.chi * 8, count * 8, n, hipMemcpyDeviceToHost));
+    for (uint32_t p = 0; p < n; ++p)
+      for (uint64_t a = 0; a < count; ++a) dst[a * n + p] = tmp[(size_t)p * count + a];
+    return CHSIM_OK;
+  };
+  if ((st = rows(F, I.F.p))) return st;
+  if ((st = rows(G, I.G.p))) return st;
+  if ((st = rows(M, I.M.p))) return st;
+  if (gamma) {
+    std::vector<uint8_t> tmp((size_t)n * count);
+    HIP_TRY(hipMemcpy2D(tmp.data(), count, I.gamma.p + first, I.chi, count, n, hipMemcpyDeviceToHost));
+    for (uint32_t p = 0; p < n; ++p)
+      for (uint64_t a = 0; a < count; ++a) gamma[a * n + p] = tmp[(size_t)p * count + a];
+  }
+  if (v) HIP_TRY(hipMemcpy(v, I.v.p + first, count * 8, hipMemcpyDeviceToHost));
+  if (s) HIP_TRY(hipMemcpy(s, I.s.p + first, count * 8, hipMemcpyDeviceToHost));
+  if (omega) HIP_TRY(hipMemcpy(omega, I.omega.p + first, count, hipMemcpyDeviceToHost));
+  if (b) HIP_TRY(hipMemcpy(b, I.b.p + first, count * 16, hipMemcpyDeviceToHost));
+  if (branch && I.n_slot) {
+    std::vector<uint8_t> tmp((size_t)I.n_slot * count);
+    HIP_TRY(hipMemcpy2D(tmp.data(), count, I.branch.p + first, I.chi, count, I.n_slot, hipMemcpyDeviceToHost));
+    for (uint32_t p = 0; p < I.n_slot; ++p)
+      for (uint64_t a = 0; a < count; ++a) branch[a * I.n_slot + p] = tmp[(size_t)p * count + a];
+  }
+  return CHSIM_OK;
+}
+
+chsim_status chsim_set_terms(chsim_ctx* ctx, uint32_t inst, uint64_t first, uint64_t count,
+                             const uint64_t* F, const uint64_t* G, const uint64_t* M,
+                             const uint8_t* gamma, const uint64_t* v, const uint64_t* s,
+                             const uint8_t* omega, const double* b) {
+  g_err.clear();
+  chsim_status st = check_ctx(ctx, inst);
+  if (st) return st;
+  Instance& I = ctx->inst[inst];
+  if (first > I.chi || count > I.chi - first) return fail(CHSIM_EINVAL, "term range out of bounds");
+  if (!F || !G || !M || !gamma || !v || !s || !omega || !b) return fail(CHSIM_EINVAL, "null field");
+  if (count == 0) return CHSIM_OK;
+  HIP_TRY(hipSetDevice(ctx->device));
+  st = ensure_materialised(I, nullptr);
+  if (st) return st;
+  HIP_TRY(hipDeviceSynchronize());
+  const uint32_t n = I.n;
+  auto rows = [&](uint64_t* dst, const uint64_t* src) -> chsim_status {
+    std::vector<uint64_t> tmp((size_t)n * count);
+    for (uint32_t p = 0; p < n; ++p)
+      for (uint64_t a = 0; a < count; ++a) tmp[(size_t)p * count + a] = src[a * n + p];
+    HIP_TRY(hipMemcpy2D(dst + first, I.chi * 8, tmp.data(), count * 8, count * 8, n, hipMemcpyHostToDevice));
+    return CHSIM_OK;
+  };
+  if ((st = rows(I.F.p, F))) return st;
+  if ((st = rows(I.G.p, G))) return st;
+  if ((st = rows(I.M.p, M))) return st;
+  {
+    std::vector<uint8_t> tmp((size_t)n * count);
+    for (uint32_t p = 0; p < n; ++p)
+      for (uint64_t a = 0; a < count; ++a) tmp[(size_t)p * count + a] = gamma[a * n + p] & 3;
+    HIP_TRY(hipMemcpy2D(I.gamma.p + first, I.chi, tmp.data(), count, count, n, hipMemcpyHostToDevice));
+  }
+  HIP_TRY(hipMemcpy(I.v.p + first, v, count * 8, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(I.s.p + first, s, count * 8, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(I.omega.p + first, omega, count, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(I.b.p + first, b, count * 16, hipMemcpyHostToDevice));
+  return CHSIM_OK;
+}
+
+chsim_status chsim_decompose_phase(double theta, uint32_t qubit, double coeff[4], uint32_t off[3],
+                                   chsim_gate gates[8], chsim_decomp* out) {
+  g_err.clear();
+  if (!coeff || !off || !gates || !out) return fail(CHSIM_EINVAL, "null output");
+  if (!std::isfinite(theta)) return fail(CHSIM_EINVAL, "theta not finite");
+  if (qubit >= 64) return fail(CHSIM_EINVAL, "qubit >= 64");
+  const double pi = 3.14159265358979323846264338327950288;
+  const double quarter = pi / 2.0;
+  double kf = std::floor(theta / quarter);
+  double tp = theta - kf * quarter;
+  if (tp < 0.0) {
+    tp += quarter;
+    kf -= 1.0;
+  }
+  if (tp >= quarter) {
+    tp -= quarter;
+    kf += 1.0;
+  }
+  const int k = (int)(((long long)kf % 4 + 4) % 4);
+  const double half = tp / 2.0;
+  const double cs = std::cos(half), sn = std::sin(half);
+  // e^{i theta'/2}
+  const double er = std::cos(half), ei = std::sin(half);
+  // c0 = e^{i theta'/2} (cos - sin)
+  coeff[0] = er * (cs - sn);
+  coeff[1] = ei * (cs - sn);
+  // c1 = e^{i theta'/2} sqrt(2) e^{-i pi/4} sin = e^{i theta'/2} (1 - i) sin
+  const double ar = sn, ai = -sn;
+  coeff[2] = er * ar - ei * ai;
+  coeff[3] = er * ai + ei * ar;
+  uint32_t g = 0;
+  off[0] = 0;
+  for (int i = 0; i < k; ++i) gates[g++] = chsim_gate{CHSIM_S, (uint8_t)qubit, 0, 0, 0};
+  off[1] = g;
+  for (int i = 0; i < ((k + 1) & 3); ++i) gates[g++] = chsim_gate{CHSIM_S, (uint8_t)qubit, 0, 0, 0};
+  off[2] = g;
+  out->n_branch = 2;
+  out->coeff = coeff;
+  out->off = off;
+  out->gates = gates;
+  return CHSIM_OK;
+}
+
+chsim_status chsim_instance_info(chsim_ctx* ctx, uint32_t inst, uint32_t* n, uint64_t* chi, double* l1) {
+  g_err.clear();
+  chsim_status st = check_ctx(ctx, inst);
+  if (st) return st;
+  const Instance& I = ctx->inst[inst];
+  if (n) *n = I.n;
+  if (chi) *chi = I.chi;
+  if (l1) *l1 = I.l1;
+  return CHSIM_OK;
+}
+
+chsim_status chsim_destroy(chsim_ctx* ctx) {
+  if (!ctx) return CHSIM_OK;
+  hipSetDevice(ctx->device);
+  hipDeviceSynchronize();
+  for (auto& I : ctx->inst) I.release();
+  ctx->gates.release();
+  ctx->err.release();
+  ctx->xbuf.release();
+  ctx->partial.release();
+  ctx->out.release();
+  ctx->aoff.release();
+  ctx->adiag.release();
+  ctx->eta.release();
+  ctx->eta_sum.release();
+  delete ctx;
+  return CHSIM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,97 @@
+// Internal types shared by the HIP kernels and the C-ABI host code.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "chsim.h"
+
+namespace chsim {
+
+// Device gate codes: the public codes plus SPOW (S applied `arg` times on q),
+// which the host uses for runs of S gates in slot branches.
+enum : uint8_t { OP_H = 0, OP_S = 1, OP_CX = 2, OP_CZ = 3, OP_SLOT = 4, OP_SPOW = 5 };
+
+struct DGate {
+  uint8_t op, q, r, arg;
+  uint32_t slot;
+};
+static_assert(sizeof(DGate) == 8, "DGate is 8 bytes");
+
+// One slot's decomposition as the kernels read it.
+struct SlotTable {
+  uint32_t n_branch;
+  uint32_t goff[CHSIM_MAX_BRANCH + 1];  // branch j = bgates[goff[j] .. goff[j+1])
+  double cum[CHSIM_MAX_BRANCH];         // sum_{i<=j} |c_i|
+  double total;                         // W = sum_i |c_i|
+  double unit_re[CHSIM_MAX_BRANCH];     // c_j / |c_j| (0 if c_j == 0)
+  double unit_im[CHSIM_MAX_BRANCH];
+  double coef_re[CHSIM_MAX_BRANCH];     // c_j
+  double coef_im[CHSIM_MAX_BRANCH];
+};
+
+// Structure-of-arrays term store of one instance.  Row p of term a of F is
+// F[p * chi + a] (rows outer, terms inner: consecutive terms are consecutive
+// words), and likewise G, M and gamma; per-term words v, s, omega, b.
+struct TermsView {
+  uint32_t n;
+  uint32_t n_slot;
+  uint64_t chi;
+  uint64_t* F;
+  uint64_t* G;
+  uint64_t* M;
+  uint8_t* gamma;   // Z_4
+  uint64_t* v;
+  uint64_t* s;
+  uint8_t* omega;   // Z_8
+  double2* b;
+  uint8_t* branch;  // branch[p * chi + a]
+};
+
+// Metropolis chain state (one instance).
+struct MetroView {
+  uint32_t n_chain;
+  uint32_t n_tiles;       // term tiles of kMetroTile terms
+  uint64_t* state[2];     // [n_chain][chi]: u | mu << 62
+  uint32_t* parity;       // per chain: which state buffer is current
+  uint64_t* x;            // per chain
+  double2* amp;           // per chain: <x|psi>
+  double2* partial;       // [n_chain][n_tiles]
+  const uint32_t* jstream;
+  const double* ustream;
+  uint64_t* trace;        // may be null
+  uint8_t* accepted;      // may be null
+  uint32_t n_steps;
+  uint32_t n_qubits;
+};
+
+constexpr int kMetroTile = 256;
+constexpr int kAmpTile = 64;
+
+// ---- launchers (each returns the first HIP error) ----
+hipError_t launch_choose(const TermsView& T, const SlotTable* slots, uint32_t mode, uint64_t seed,
+                         double scale, hipStream_t st);
+hipError_t launch_evolve(const TermsView& T, const DGate* gates, uint32_t n_gates,
+                         const SlotTable* slots, const DGate* bgates, bool from_zero,
+                         uint32_t* err, hipStream_t st);
+hipError_t launch_set_zero(const TermsView& T, hipStream_t st);
+hipError_t launch_sample(const TermsView& T, const uint64_t* alpha, const uint64_t* flips,
+                         uint64_t* x_out, uint32_t count, hipStream_t st);
+
+// Amplitudes: partial[tile * n_x + i] for every 64-term tile, then a reduction.
+size_t amp_partial_elems(const TermsView& T, uint32_t n_x);
+hipError_t launch_amplitudes(const TermsView& T, const uint64_t* x, uint32_t n_x, bool fp32c,
+                             double2* partial, double2* out, hipStream_t st);
+
+// Inner products with equatorial states.
+size_t inner_partial_elems(const TermsView& T, uint32_t L, uint32_t* n_blocks);
+hipError_t launch_inner(const TermsView& T, const uint64_t* Aoff, const uint8_t* Adiag, uint32_t L,
+                        double2* partial, uint32_t n_blocks, double2* overlap, double* eta,
+                        double* eta_sum, uint32_t* err, hipStream_t st);
+
+// Metropolis.
+hipError_t launch_metro_init(const TermsView& T, MetroView& Mv, hipStream_t st);
+hipError_t launch_metro_steps(const TermsView& T, MetroView& Mv, uint32_t n_steps, hipStream_t st);
+
+}  // namespace chsim

@@ -1,0 +1,213 @@
+// Metropolis chain over n-bit outputs (Sec. "Heuristic Metropolis simulator").
+//
+// Each chain c keeps, per term alpha, the Pauli Q_x = i^mu Z(t) X(u) of its
+// current string x, stored as the word u | mu << 62 (t is not needed for the
+// amplitude, and the product with U_C^{-1} X_j U_C is taken on the right:
+// the two factors commute, so Q_x P_j = P_j Q_x).  A step proposes y = x ^ e_j:
+//   u' = u ^ F_j,  mu' = mu + gamma_j + 2 par(u' & M_j),
+// and <y|phi_alpha> follows from (u', mu') as in Eq. (amplitude1), O(1) words
+// per term and chain.  The proposal words are written to the chain's second
+// buffer; accepting the move flips which buffer is current, so no term data
+// is rewritten at accept time.
+//
+// Kernels per step: (1) one thread per term, loop over chains: propose, write
+// the proposal word, and reduce sum_alpha b_alpha <y|phi_alpha> over the
+// 256-term tile in FP64; (2) one workgroup per chain: add the tiles' partials
+// in a fixed order, r = |A(y)|^2 / |A(x)|^2 in FP64, accept iff U < r.
+#include "device_common.hpp"
+#include "internal.hpp"
+
+namespace chsim {
+
+namespace {
+
+struct TermAmpConst {
+  uint64_t s, nv, vs;
+  uint32_t w;
+  double w0r, w0i, w1r, w1i;
+};
+
+__device__ __forceinline__ TermAmpConst load_const(const TermsView& T, uint64_t a) {
+  TermAmpConst c;
+  const uint64_t v = T.v[a], s = T.s[a];
+  const uint32_t n = T.n;
+  const uint64_t nmask = (n == 64) ? ~0ull : ((1ull << n) - 1ull);
+  c.s = s;
+  c.nv = ~v & nmask;
+  c.vs = v & s;
+  c.w = T.omega[a];
+  const double2 b = T.b[a];
+  const int vc = __popcll(v);
+  const double h = 0.70710678118654752440;
+  const double mag = ldexp(1.0, -(vc >> 1)) * ((vc & 1) ? h : 1.0);
+  c.w0r = b.x * mag;
+  c.w0i = b.y * mag;
+  c.w1r = (c.w0r - c.w0i) * h;
+  c.w1i = (c.w0r + c.w0i) * h;
+  return c;
+}
+
+// b <x|phi> from the cached (u, mu).
+__device__ __forceinline__ double2 term_value(const TermAmpConst& c, uint64_t u, uint32_t mu) {
+  if ((u ^ c.s) & c.nv) return make_double2(0.0, 0.0);
+  const uint32_t k = (c.w + 2u * mu + 4u * par64(u & c.vs)) & 7u;
+  double re = (k & 1u) ? c.w1r : c.w0r;
+  double im = (k & 1u) ? c.w1i : c.w0i;
+  const uint32_t m = k >> 1;
+  if (m & 1u) {
+    const double t = re;
+    re = im;
+    im = t;
+  }
+  if ((m ^ (m >> 1)) & 1u) re = -re;
+  if (m & 2u) im = -im;
+  return make_double2(re, im);
+}
+
+constexpr uint64_t kUMask = (1ull << 62) - 1ull;
+
+// Sum of a double2 over the 256-thread block (fixed order); result in thread 0.
+__device__ __forceinline__ double2 block_sum(double2 v, double2* scratch) {
+  for (int m = 32; m >= 1; m >>= 1) {
+    v.x += __shfl_down(v.x, m);
+    v.y += __shfl_down(v.y, m);
+  }
+  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) scratch[wave] = v;
+  __syncthreads();
+  double2 r = make_double2(0.0, 0.0);
+  if (threadIdx.x == 0) {
+    for (int w = 0; w < 4; ++w) {
+      r.x += scratch[w].x;
+      r.y += scratch[w].y;
+    }
+  }
+  return r;
+}
+
+// Initial Q_x for every chain (the O(k n^2) start-up cost) and the tile sums of
+// <x_c|psi>.
+__global__ __launch_bounds__(256) void k_metro_init(TermsView T, MetroView Mv) {
+  __shared__ double2 scratch[4];
+  const uint64_t a = (uint64_t)blockIdx.x * kMetroTile + threadIdx.x;
+  const bool live = a < T.chi;
+  const uint64_t chi = T.chi;
+  TermAmpConst c;
+  if (live) c = load_const(T, a);
+  for (uint32_t ch = 0; ch < Mv.n_chain; ++ch) {
+    const uint32_t n = T.n;
+    const uint64_t x = Mv.x[ch] & ((n == 64) ? ~0ull : ((1ull << n) - 1ull));
+    double2 val = make_double2(0.0, 0.0);
+    if (live) {
+      uint64_t u = 0, xm = x;
+      uint32_t mu = 0;
+      while (xm) {
+        const uint32_t p = (uint32_t)__builtin_ctzll(xm);
+        xm &= xm - 1ull;
+        u ^= T.F[(uint64_t)p * chi + a];
+        mu += T.gamma[(uint64_t)p * chi + a] + 2u * par64(u & T.M[(uint64_t)p * chi + a]);
+      }
+      mu &= 3u;
+      Mv.state[0][(uint64_t)ch * chi + a] = (u & kUMask) | ((uint64_t)mu << 62);
+      val = term_value(c, u, mu);
+    }
+    const double2 tot = block_sum(val, scratch);
+    if (threadIdx.x == 0) Mv.partial[(uint64_t)ch * Mv.n_tiles + blockIdx.x] = tot;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_chain_amp(MetroView Mv) {
+  __shared__ double2 scratch[4];
+  const uint32_t ch = blockIdx.x;
+  double2 acc = make_double2(0.0, 0.0);
+  for (uint32_t t = threadIdx.x; t < Mv.n_tiles; t += 256u) {
+    const double2 v = Mv.partial[(uint64_t)ch * Mv.n_tiles + t];
+    acc.x += v.x;
+    acc.y += v.y;
+  }
+  const double2 tot = block_sum(acc, scratch);
+  if (threadIdx.x == 0) {
+    Mv.amp[ch] = tot;
+    Mv.parity[ch] = 0u;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_metro_propose(TermsView T, MetroView Mv, uint32_t step) {
+  __shared__ double2 scratch[4];
+  const uint64_t a = (uint64_t)blockIdx.x * kMetroTile + threadIdx.x;
+  const bool live = a < T.chi;
+  const uint64_t chi = T.chi;
+  TermAmpConst c;
+  if (live) c = load_const(T, a);
+  for (uint32_t ch = 0; ch < Mv.n_chain; ++ch) {
+    const uint32_t j = uniform32(Mv.jstream[(uint64_t)ch * Mv.n_steps + step] % T.n);
+    const uint32_t cur = uniform32(Mv.parity[ch]);
+    double2 val = make_double2(0.0, 0.0);
+    if (live) {
+      const uint64_t w = Mv.state[cur][(uint64_t)ch * chi + a];
+      const uint64_t off = (uint64_t)j * chi + a;
+      const uint64_t u = (w & kUMask) ^ T.F[off];
+      const uint32_t mu = ((uint32_t)(w >> 62) + T.gamma[off] + 2u * par64(u & T.M[off])) & 3u;
+      Mv.state[cur ^ 1u][(uint64_t)ch * chi + a] = u | ((uint64_t)mu << 62);
+      val = term_value(c, u, mu);
+    }
+    const double2 tot = block_sum(val, scratch);
+    if (threadIdx.x == 0) Mv.partial[(uint64_t)ch * Mv.n_tiles + blockIdx.x] = tot;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_metro_accept(MetroView Mv, uint32_t step) {
+  __shared__ double2 scratch[4];
+  const uint32_t ch = blockIdx.x;
+  double2 acc = make_double2(0.0, 0.0);
+  for (uint32_t t = threadIdx.x; t < Mv.n_tiles; t += 256u) {
+    const double2 v = Mv.partial[(uint64_t)ch * Mv.n_tiles + t];
+    acc.x += v.x;
+    acc.y += v.y;
+  }
+  const double2 ay = block_sum(acc, scratch);
+  if (threadIdx.x == 0) {
+    const uint64_t idx = (uint64_t)ch * Mv.n_steps + step;
+    const double2 ax = Mv.amp[ch];
+    const double px = ax.x * ax.x + ax.y * ax.y;
+    const double py = ay.x * ay.x + ay.y * ay.y;
+    const double r = py / px;
+    const double U = Mv.ustream[idx];
+    const uint32_t acc_ = (px > 0.0) && (r >= 1.0 || U < r);
+    uint64_t x = Mv.x[ch];
+    if (acc_) {
+      x ^= 1ull << (Mv.jstream[idx] % Mv.n_qubits);
+      Mv.x[ch] = x;
+      Mv.amp[ch] = ay;
+      Mv.parity[ch] ^= 1u;
+    }
+    if (Mv.trace) Mv.trace[idx] = x;
+    if (Mv.accepted) Mv.accepted[idx] = (uint8_t)acc_;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_metro_init(const TermsView& T, MetroView& Mv, hipStream_t st) {
+  const uint32_t tiles = Mv.n_tiles;
+  hipLaunchKernelGGL(k_metro_init, dim3(tiles), dim3(kMetroTile), 0, st, T, Mv);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_chain_amp, dim3(Mv.n_chain), dim3(256), 0, st, Mv);
+  return hipGetLastError();
+}
+
+hipError_t launch_metro_steps(const TermsView& T, MetroView& Mv, uint32_t n_steps, hipStream_t st) {
+  for (uint32_t t = 0; t < n_steps; ++t) {
+    hipLaunchKernelGGL(k_metro_propose, dim3(Mv.n_tiles), dim3(kMetroTile), 0, st, T, Mv, t);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_metro_accept, dim3(Mv.n_chain), dim3(256), 0, st, Mv, t);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace chsim

@@ -1,0 +1,342 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Integer results (F, G, M, gamma, v, s, omega, branch choices, chain
+trajectories) must be bit-exact.  Floating point: FP64 amplitudes and
+overlaps within 1e-12 normwise (max |a - a_ref| / RMS |a_ref|), FP32C within
+1e-6.  Every input is seeded; no expected value comes from the GPU.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import dense
+import oracle as O
+from paper_1808_00128_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32 = 1e-6
+
+
+def say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1808_00128_amd import binding
+
+    binding.lib()
+    return binding
+
+
+def normwise(a, ref):
+    rms = np.sqrt(np.mean(np.abs(ref) ** 2))
+    if rms == 0:
+        return float(np.max(np.abs(a)))
+    return float(np.max(np.abs(a - ref)) / rms)
+
+
+def gpu_ctx(B, spec):
+    ctx = B.Context([spec])
+    ctx.apply_circuit(spec["circuit"])
+    return ctx
+
+
+def oracle_mode(spec):
+    return O.EXACT if spec["mode"] == "exact" else O.SPARSIFY
+
+
+def compare_terms(ctx, T, idx):
+    """Bit-exact comparison of GPU terms idx with oracle terms (built for idx)."""
+    n = ctx.info()[0]
+    for k, a in enumerate(idx):
+        g = ctx.get_terms(int(a), 1)
+        o = T.term(k).export()
+        assert np.array_equal(g["F"][0], o["F"]), ("F", a)
+        assert np.array_equal(g["G"][0], o["G"]), ("G", a)
+        assert np.array_equal(g["M"][0], o["M"]), ("M", a)
+        assert np.array_equal(g["gamma"][0], o["gamma"]), ("gamma", a)
+        assert int(g["v"][0]) == o["v"], ("v", a)
+        assert int(g["s"][0]) == o["s"], ("s", a)
+        assert int(g["omega"][0]) == o["omega"], ("omega", a)
+        assert np.array_equal(g["branch"][0], T.branch(k)), ("branch", a)
+        ob = T.b(k)
+        assert abs(g["b"][0] - ob) <= 1e-14 * max(abs(ob), 1e-300), ("b", a)
+    assert n == T.n
+
+
+# ---------------------------------------------------------------------------
+# Step (a): evolution, bit-exact.
+# ---------------------------------------------------------------------------
+CASES = [
+    # (n, clifford gates, slots, chi, mode)
+    (1, 30, 2, 4, "exact"),
+    (2, 60, 3, 8, "exact"),
+    (5, 120, 4, 16, "exact"),
+    (12, 200, 6, 64, "exact"),
+    (31, 400, 10, 300, "sparsify"),
+    (33, 400, 10, 257, "sparsify"),
+    (50, 800, 20, 1000, "sparsify"),
+    (63, 800, 12, 129, "sparsify"),
+    (64, 900, 12, 200, "sparsify"),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[f"n{c[0]}-chi{c[3]}" for c in CASES])
+def test_evolution_bit_exact(B, case):
+    n, ng, m, chi, mode = case
+    rng = np.random.default_rng(7000 + n)
+    circ = W.random_circuit(n, ng, rng.uniform(0, 2 * np.pi, size=m), rng)
+    spec = dict(circuit=circ, chi=chi, mode=mode, seed=31 + n)
+    say(f"evolution n={n} chi={chi} mode={mode}")
+    ctx = gpu_ctx(B, spec)
+    idx = np.arange(chi, dtype=np.uint64) if chi <= 300 else np.unique(
+        np.concatenate([[0, chi - 1], rng.integers(0, chi, size=120)])).astype(np.uint64)
+    T = O.Terms(circ, chi, oracle_mode(spec), seed=spec["seed"], alphas=idx)
+    compare_terms(ctx, T, idx)
+
+
+def test_evolution_in_segments_matches_one_pass(B):
+    """apply_clifford on consecutive segments equals one call on the whole circuit."""
+    rng = np.random.default_rng(5)
+    circ = W.random_circuit(20, 300, rng.uniform(0, 2 * np.pi, size=6), rng)
+    spec = dict(circuit=circ, chi=96, mode="sparsify", seed=3)
+    say("evolution segments")
+    ctx = B.Context([spec])
+    g = B.gate_array(circ)
+    for lo, hi in ((0, 50), (50, 51), (51, 200), (200, g.size)):
+        ctx.apply_gates(g[lo:hi])
+    T = O.Terms(circ, 96, O.SPARSIFY, seed=3)
+    compare_terms(ctx, T, np.arange(96, dtype=np.uint64))
+
+
+# ---------------------------------------------------------------------------
+# Step (b): amplitudes.
+# ---------------------------------------------------------------------------
+def test_tiny_config_amplitudes(B):
+    cfg = W.config_tiny()
+    say("tiny config (n=12, chi=256 exact, all 4096 x)")
+    ctx = gpu_ctx(B, cfg)
+    T = O.Terms(cfg["circuit"], cfg["chi"], O.EXACT)
+    compare_terms(ctx, T, np.arange(cfg["chi"], dtype=np.uint64))
+    ref = T.amplitudes(cfg["x"])
+    psi = dense.run(cfg["circuit"])
+    a64 = ctx.amplitudes(cfg["x"])
+    a32 = ctx.amplitudes(cfg["x"], fp32c=True)
+    assert normwise(a64, ref) < TOL64
+    assert normwise(a64, psi) < TOL64
+    assert normwise(a32, ref) < TOL32
+    assert abs(np.sum(np.abs(a64) ** 2) - 1) < 1e-12
+
+
+@pytest.mark.parametrize("n,chi,n_x", [(1, 3, 2), (7, 65, 1), (20, 1000, 1001), (40, 64, 333),
+                                       (62, 130, 77)])
+def test_amplitudes_ragged(B, n, chi, n_x):
+    rng = np.random.default_rng(100 + n)
+    circ = W.random_circuit(n, 30 * n, rng.uniform(0, 2 * np.pi, size=8), rng)
+    spec = dict(circuit=circ, chi=chi, mode="sparsify", seed=n)
+    say(f"amplitudes ragged n={n} chi={chi} n_x={n_x}")
+    ctx = gpu_ctx(B, spec)
+    T = O.Terms(circ, chi, O.SPARSIFY, seed=n)
+    # half the strings sampled from the terms so that many amplitudes are non-zero
+    alpha = rng.integers(0, chi, size=n_x)
+    flips = W.random_bitstrings(n, n_x, rng)
+    xs = np.array([T.term(int(a)).sample(int(f)) for a, f in zip(alpha, flips)], np.uint64)
+    xs[::2] = W.random_bitstrings(n, n_x, rng)[::2]
+    if n_x > 1:
+        xs[-1] = 0
+    ref = T.amplitudes(xs)
+    a64 = ctx.amplitudes(xs)
+    a32 = ctx.amplitudes(xs, fp32c=True)
+    assert normwise(a64, ref) < TOL64
+    assert normwise(a32, ref) < TOL32
+
+
+def test_amplitudes_empty_circuit_and_chi_one(B):
+    circ = W.from_list(6, [])
+    spec = dict(circuit=circ, chi=1, mode="exact", seed=0)
+    say("empty circuit chi=1")
+    ctx = B.Context([spec])
+    a = ctx.amplitudes(np.arange(64, dtype=np.uint64))
+    expect = np.zeros(64, complex)
+    expect[0] = 1
+    assert np.array_equal(a, expect)
+
+
+def test_amplitudes_n64_block_product(B):
+    """n = 64 where only a product of dense blocks can check the value."""
+    rng = np.random.default_rng(640)
+    labels = rng.permutation(64)
+    blocks = [sorted(labels[i * 16:(i + 1) * 16].tolist()) for i in range(4)]
+    local = []
+    for qs in blocks:
+        sub = W.random_circuit(10, 80, rng.uniform(0, 2 * np.pi, size=3), rng)
+        local.append((qs[:10], sub))
+    gates = []
+    for qs, sub in local:
+        for op, q, r, th in sub.gates():
+            if op == W.OP_SLOT:
+                gates.append((op, qs[q], 0, th))
+            else:
+                gates.append((op, qs[q], qs[r] if op in (W.OP_CX, W.OP_CZ) else 0))
+    circ = W.from_list(64, gates)
+    spec = dict(circuit=circ, chi=1 << circ.n_slot, mode="exact", seed=0)
+    say("n=64 block product")
+    ctx = gpu_ctx(B, spec)
+    psis = [dense.run(sub) for _, sub in local]
+    xs, ref = [], []
+    for t in range(200):
+        x, amp = 0, 1.0 + 0j
+        for (qs, sub), psi in zip(local, psis):
+            li = int(rng.choice(len(psi), p=np.abs(psi) ** 2)) if t % 3 else int(rng.integers(len(psi)))
+            amp *= psi[li]
+            for k, qq in enumerate(qs):
+                if (li >> k) & 1:
+                    x |= 1 << qq
+        xs.append(x)
+        ref.append(amp)
+    xs = np.array(xs, np.uint64)
+    ref = np.array(ref)
+    a64 = ctx.amplitudes(xs)
+    assert np.max(np.abs(a64 - ref)) < 1e-12
+
+
+@pytest.mark.slow
+def test_amplitudes_config_full_size_sampled(B):
+    """n = 50, chi = 2^16, 4096 strings, the benchmark's launch configuration:
+    all strings on the GPU; the oracle checks 256 sampled terms bit-exactly and
+    16 sampled strings over all chi terms."""
+    cfg = W.config_amplitudes()
+    say("full config n=50 chi=65536 x=4096")
+    ctx = gpu_ctx(B, cfg)
+    a64 = ctx.amplitudes(cfg["x"])
+    a32 = ctx.amplitudes(cfg["x"], fp32c=True)
+    assert normwise(a32, a64) < TOL32
+    rng = np.random.default_rng(1)
+    idx = np.unique(np.concatenate([[0, cfg["chi"] - 1], rng.integers(0, cfg["chi"], 254)])).astype(np.uint64)
+    Ts = O.Terms(cfg["circuit"], cfg["chi"], O.SPARSIFY, seed=cfg["seed"], alphas=idx)
+    compare_terms(ctx, Ts, idx)
+    del Ts
+    say("full config: oracle evolves all 65536 terms")
+    T = O.Terms(cfg["circuit"], cfg["chi"], O.SPARSIFY, seed=cfg["seed"])
+    pick = rng.choice(cfg["x"].size, size=16, replace=False)
+    ref = T.amplitudes(cfg["x"][pick])
+    rms = np.sqrt(np.mean(np.abs(a64) ** 2))
+    assert np.max(np.abs(a64[pick] - ref)) / rms < TOL64
+    assert np.max(np.abs(a32[pick] - ref)) / rms < TOL32
+
+
+# ---------------------------------------------------------------------------
+# Step (c): inner products and the norm estimate.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n", [1, 3, 8, 20, 40, 63])
+def test_inner_single_term_values(B, n):
+    """chi = 1 (no slots): the overlap is the pair value <phi_A|phi> itself."""
+    rng = np.random.default_rng(900 + n)
+    circ = W.random_circuit(n, 25 * n + 10, [], rng)
+    spec = dict(circuit=circ, chi=1, mode="exact", seed=0)
+    say(f"inner single term n={n}")
+    ctx = gpu_ctx(B, spec)
+    T = O.Terms(circ, 1, O.EXACT)
+    Aoff, Adiag = W.random_equatorial(n, 40, rng)
+    ov, eta, mean = ctx.inner_products(Aoff, Adiag)
+    ref, eta_ref = T.inner(Aoff, Adiag)
+    np.testing.assert_allclose(ov, ref, rtol=1e-14, atol=0)
+    np.testing.assert_allclose(eta, eta_ref, rtol=1e-13, atol=0)
+
+
+def test_inner_products_small_sum(B):
+    rng = np.random.default_rng(44)
+    circ = W.random_circuit(10, 150, rng.uniform(0, 2 * np.pi, size=8), rng)
+    spec = dict(circuit=circ, chi=300, mode="sparsify", seed=8)
+    say("inner sum n=10 chi=300 L=50")
+    ctx = gpu_ctx(B, spec)
+    T = O.Terms(circ, 300, O.SPARSIFY, seed=8)
+    Aoff, Adiag = W.random_equatorial(10, 50, rng)
+    ov, eta, mean = ctx.inner_products(Aoff, Adiag)
+    ref, eta_ref = T.inner(Aoff, Adiag)
+    assert normwise(ov, ref) < TOL64
+    assert abs(mean - eta_ref.mean()) <= 1e-12 * eta_ref.mean()
+
+
+def test_inner_products_norm_config_subset(B):
+    """Norm-estimation workload (n = 40, 30 slots): the first 4096 terms (same
+    seed, so the same branch choices) against the oracle on 64 states."""
+    cfg = W.config_norm(L=64)
+    spec = dict(cfg, chi=4096)
+    say("norm config subset n=40 chi=4096 L=64")
+    ctx = gpu_ctx(B, spec)
+    T = O.Terms(cfg["circuit"], 4096, O.SPARSIFY, seed=cfg["seed"])
+    ov, eta, mean = ctx.inner_products(cfg["Aoff"], cfg["Adiag"])
+    ref, eta_ref = T.inner(cfg["Aoff"], cfg["Adiag"])
+    assert normwise(ov, ref) < TOL64
+
+
+# ---------------------------------------------------------------------------
+# Metropolis chains: trajectories bit-identical given the same random streams.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n,chi,mode,chains,steps", [(8, 64, "exact", 4, 300),
+                                                     (50, 2048, "sparsify", 8, 120)])
+def test_metropolis_trajectories(B, n, chi, mode, chains, steps):
+    rng = np.random.default_rng(60 + n)
+    if n == 50:
+        circ = W.qaoa_circuit(50, 60, rng)[0]
+    else:
+        circ = W.random_circuit(n, 80, rng.uniform(0, 2 * np.pi, size=6), rng)
+    spec = dict(circuit=circ, chi=chi, mode=mode, seed=n)
+    say(f"metropolis n={n} chi={chi} chains={chains} steps={steps}")
+    ctx = gpu_ctx(B, spec)
+    T = O.Terms(circ, chi, oracle_mode(spec), seed=n)
+    alpha = rng.integers(0, chi, size=chains)
+    flips = W.random_bitstrings(n, chains, rng)
+    x0 = np.array([T.term(int(a)).sample(int(f)) for a, f in zip(alpha, flips)], np.uint64)
+    x0_gpu = ctx.sample_terms(alpha, flips)
+    assert np.array_equal(x0, x0_gpu)
+    a0_ref = T.amplitudes(x0)
+    keep = np.abs(a0_ref) > 0
+    x0 = x0[keep]
+    assert x0.size > 0
+    j, u = W.metropolis_streams(n, x0.size, steps, rng)
+    a0 = ctx.metropolis_init(x0)
+    assert normwise(a0, a0_ref[keep]) < TOL64
+    tr, acc, amp = ctx.metropolis_step(j, u)
+    otr, oacc, oamp = T.metropolis(x0, j, u)
+    assert np.array_equal(tr, otr)
+    assert np.array_equal(acc, oacc)
+    assert normwise(amp, oamp) < 1e-10
+    assert 0 < acc.mean() <= 1
+
+
+def test_metropolis_rejects_zero_probability_start(B):
+    circ = W.from_list(4, [(W.OP_H, 0, 0)])
+    spec = dict(circuit=circ, chi=1, mode="exact", seed=0)
+    say("metropolis zero-probability start")
+    ctx = gpu_ctx(B, spec)
+    with pytest.raises(B.ChsimError) as e:
+        ctx.metropolis_init(np.array([0b10], np.uint64))
+    assert e.value.status == B.CHSIM_EINVAL
+
+
+def test_bad_gates_rejected(B):
+    circ = W.from_list(4, [(W.OP_H, 0, 0)])
+    ctx = B.Context([dict(circuit=circ, chi=2, mode="sparsify", seed=0)])
+    bad = np.zeros(1, B.GATE_DTYPE)
+    bad["op"] = W.OP_CX
+    bad["q"] = 1
+    bad["r"] = 1
+    say("bad gates")
+    with pytest.raises(B.ChsimError):
+        ctx.apply_gates(bad)
+    bad["r"] = 7
+    with pytest.raises(B.ChsimError):
+        ctx.apply_gates(bad)
+    with pytest.raises(B.ChsimError):
+        ctx.amplitudes(np.array([1 << 5], np.uint64))
