@@ -58,6 +58,107 @@ def cpu_baseline(cfg, sample_terms, threads):
                        f"{cfg['x'].size} strings ({t1 - t0:.2f} s evolve, {t2 - t1:.2f} s amplitudes)")
 
 
+def mean_popcount(words):
+    return float(np.mean([bin(int(w)).count("1") for w in np.asarray(words).ravel()]))
+
+
+def bench_norm(torch, B, W, L=1024):
+    """Norm-estimation workload: n = 40, 200 Clifford gates + 30 phase slots,
+    chi = 2^18, L equatorial states; all chi * L inner products per call."""
+    cfg = W.config_norm(L=L)
+    circ = cfg["circuit"]
+    ctx = B.Context([cfg])
+    ctx.set_evolve_lanes(-1)
+    ctx.apply_circuit(circ)
+    ctx.inner_products(cfg["Aoff"][:8], cfg["Adiag"][:8])  # warm-up
+    terms = ctx.get_terms(0, 256)
+    mean_v = mean_popcount(terms["v"])
+    n, chi = circ.n, cfg["chi"]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ov, eta, eta_mean = ctx.inner_products(cfg["Aoff"], cfg["Adiag"])
+    t1 = time.perf_counter()
+    ctx.close()
+    pairs = chi * L
+    ops_pair = 6 * n * n + 2 * (mean_v + 1) ** 2
+    achieved = ops_pair * pairs / (t1 - t0) / 1e12
+    return {"workload": cfg["name"] + ": n=40, 200 Clifford + 30 phase slots, chi=2^18, L=1024",
+            "seconds": t1 - t0, "inner_products_per_s": pairs / (t1 - t0),
+            "eta_mean": eta_mean, "eta_sem": float(np.std(eta, ddof=1) / np.sqrt(L)),
+            "mean_v_weight": mean_v,
+            "roofline": {"bound": "alu", "kernel": "k_inner (one wave per term, lane = row)",
+                         "achieved": round(achieved, 3), "peak": round(INT32_PEAK_OPS / 1e12, 2),
+                         "unit": "TOP/s (int32)", "frac": round(achieved / (INT32_PEAK_OPS / 1e12), 4),
+                         "ops_per_pair": ops_pair}}
+
+
+def start_points(ctx, n, chi, count, rng):
+    """Chain starts: a term drawn uniformly (all |b_alpha| are equal) and a
+    string sampled from it, kept if <x|psi> != 0."""
+    from paper_1808_00128_amd import workloads as W
+
+    xs = []
+    while len(xs) < count:
+        alpha = rng.integers(0, chi, size=4 * count)
+        flips = W.random_bitstrings(n, 4 * count, rng)
+        cand = ctx.sample_terms(alpha, flips)
+        amp = ctx.amplitudes(cand)
+        xs += [int(x) for x, a in zip(cand, amp) if abs(a) > 0]
+    return np.array(xs[:count], np.uint64)
+
+
+def bench_metropolis(torch, B, W, stats, steps=1000, n_chain=64, chi=1 << 20):
+    """QAOA-shaped sampling: n = 50, 60 triples, chi = 2^20, 64 chains x 1000
+    single-bit-flip steps; ESS of the Max-E3LIN2 cost by Wolff's Gamma method."""
+    cfg = W.config_qaoa(chi=chi, n_chain=n_chain, steps=steps)
+    circ = cfg["circuit"]
+    n = circ.n
+    dev = torch.device("cuda:0")
+    ctx = B.Context([cfg])
+    ctx.set_evolve_lanes(-1)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    stream = torch.cuda.current_stream()
+    e0.record(stream)
+    ctx.apply_circuit(circ)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    evolve_ms = e0.elapsed_time(e1)
+    rng = np.random.default_rng(cfg["seed"] + 1)
+    x0 = start_points(ctx, n, chi, n_chain, rng)
+    ctx.metropolis_init(x0)
+    j = torch.from_numpy(cfg["jstream"].astype(np.int32)).to(dev)
+    u = torch.from_numpy(cfg["ustream"]).to(dev)
+    trace = torch.empty((n_chain, steps), dtype=torch.int64, device=dev)
+    acc = torch.empty((n_chain, steps), dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    ctx.metropolis_step_device(j, u, trace, acc)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    tr = trace.cpu().numpy().view(np.uint64)
+    ac = acc.cpu().numpy()
+    ctx.close()
+    burn = steps // 5
+    cost = stats.qaoa_cost(tr[:, burn:], cfg["triples"], cfg["d"])
+    tau, win, tau_err = stats.tau_int(cost)
+    ess = cost.size / (2 * tau)
+    bytes_step = chi * (n_chain * (8 + 8 + 17) + 33)
+    achieved = bytes_step * steps / (ms / 1e3) / 1e9
+    return {"workload": cfg["name"] + ": QAOA p=1 Max-E3LIN2, n=50, 60 triples, gamma,beta~U(0,pi), "
+                        "chi=2^20, 64 chains x 1000 steps, single-bit-flip proposal",
+            "evolve_ms": evolve_ms, "ms_per_step": ms / steps,
+            "chain_steps_per_s": n_chain * steps / (ms / 1e3),
+            "acceptance": float(ac.mean()), "burn_in": burn,
+            "tau_int": tau, "tau_int_err": tau_err, "window": win,
+            "ess": ess, "ess_per_s": ess / (ms / 1e3),
+            "mean_cost": float(cost.mean()),
+            "roofline": {"bound": "hbm", "kernel": "k_metro_propose + k_metro_accept",
+                         "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
+                         "frac": round(achieved / 8000.0, 4), "traffic": None,
+                         "bytes_per_step": bytes_step}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -65,6 +166,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-terms", type=int, default=32768)
+    ap.add_argument("--sections", default="amplitudes,norm,metropolis",
+                    help="comma list: amplitudes (the timed step), norm, metropolis")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one plain 1 GiB device copy first (outside the timed region), so that "
+                         "hardware byte counters can be scaled against a kernel of known traffic")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is design-only",
@@ -83,7 +189,15 @@ def main():
     circ = cfg["circuit"]
     n, chi, xs = circ.n, cfg["chi"], cfg["x"]
     n_x = xs.size
+    if args.copy_calibration:
+        src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     ctx = B.Context([cfg])
+    ctx.set_evolve_lanes(-1)  # autotune the evolution mapping during warmup
     gates = B.gate_array(circ)
     x_dev = torch.from_numpy(xs.view(np.int64)).to(dev)
     out32 = torch.empty((n_x, 2), dtype=torch.float64, device=dev)
@@ -110,8 +224,9 @@ def main():
             phase["evolve"].append(ev[1].elapsed_time(ev[2]))
             phase["amplitudes"].append(ev[2].elapsed_time(ev[3]))
 
-    for i in range(args.warmup):
+    for i in range(max(1, args.warmup)):
         step(i, False)
+    lanes, tune_ms = ctx.evolve_lanes()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
@@ -143,7 +258,7 @@ def main():
     ms_amp = float(np.mean(phase["amplitudes"]))
     ms_reset = float(np.mean(phase["reset"]))
     if ms_ev >= ms_amp:
-        dom, ops, ms = "k_evolve (CH-form evolution, one wave per term)", ops_ev, ms_ev
+        dom, ops, ms = f"k_evolve<{lanes},...> (CH-form evolution, {64 // lanes} terms per wave)", ops_ev, ms_ev
     else:
         dom, ops, ms = "k_amp<float> + k_reduce_tiles (amplitudes, FP32C)", ops_amp, ms_amp
     achieved = ops / (ms / 1e3) / 1e12
@@ -171,16 +286,26 @@ def main():
                    "phase_slots": circ.n_slot, "parallelism": "single GPU"},
         "phases_ms": {"reset": ms_reset, "evolve": ms_ev, "amplitudes_fp32c": ms_amp,
                       "amplitudes_fp64": float(np.mean(fp64_ms))},
+        "evolve_autotune": {"lanes_per_term": lanes, "terms_per_wave": 64 // lanes,
+                            "ms_by_lanes": dict(zip(["8", "16", "32", "64"], tune_ms))},
         "amplitude_kernel_evals_per_s": chi * n_x / (ms_amp / 1e3),
         "evolve_gates_per_s": chi * circ.n_gates / (ms_ev / 1e3),
         "fp32c_vs_fp64_normwise": fp32c_vs_fp64,
         "roofline": roofline,
     }
+    ctx.close()
+    del ctx
+    sections = set(args.sections.split(","))
+    if "norm" in sections:
+        result["norm_estimation"] = bench_norm(torch, B, W)
+    if "metropolis" in sections:
+        from paper_1808_00128_amd import stats
+
+        result["metropolis"] = {"plain": bench_metropolis(torch, B, W, stats)}
     if not args.no_cpu_baseline:
         threads = max(1, min(16, os.cpu_count() or 1))
         result["cpu_baseline"] = cpu_baseline(cfg, args.cpu_sample_terms, threads)
     print(json.dumps(result), flush=True)
-    ctx.close()
 
 
 if __name__ == "__main__":

@@ -182,6 +182,22 @@ chsim_status chsim_set_terms(chsim_ctx* ctx, uint32_t inst, uint64_t first, uint
 chsim_status chsim_decompose_phase(double theta, uint32_t qubit, double coeff[4], uint32_t off[3],
                                    chsim_gate gates[8], chsim_decomp* out);
 
+/* Tuning knobs of one instance; value 0 restores the library default.
+ * EVOLVE_LANES: lanes per term in the evolution kernel (8, 16, 32 or 64; a
+ * wave holds 64 / lanes terms, and each lane holds the smallest power-of-two
+ * number of tableau rows that covers n).  -1 = autotune: the next
+ * chsim_apply_clifford that starts from |0^n> times every shape on the real
+ * gate list (hipEvents), keeps the fastest, and leaves the same terms any
+ * shape would.  Results never depend on the knob.  EUNSUPPORTED: no compiled
+ * kernel for that value and n. */
+#define CHSIM_TUNE_EVOLVE_LANES 1u
+chsim_status chsim_set_tuning(chsim_ctx* ctx, uint32_t inst, uint32_t knob, int32_t value);
+
+/* Current value of a knob and, for EVOLVE_LANES, the autotuner's timings in
+ * ms for lanes 8, 16, 32, 64 (timings_ms[4], 0 where not timed; may be NULL). */
+chsim_status chsim_get_tuning(chsim_ctx* ctx, uint32_t inst, uint32_t knob, int32_t* value,
+                              float* timings_ms);
+
 /* Instance metadata: n, chi and ||c||_1 = prod_p W_p. */
 chsim_status chsim_instance_info(chsim_ctx* ctx, uint32_t inst, uint32_t* n, uint64_t* chi,
                                  double* l1);

@@ -21,12 +21,15 @@ CHSIM_OK, CHSIM_EINVAL, CHSIM_ENOMEM, CHSIM_EDEVICE, CHSIM_EUNSUPPORTED, CHSIM_E
 STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "EUNSUPPORTED", 5: "ESTATE"}
 CHSIM_EXACT, CHSIM_SPARSIFY = 0, 1
 CHSIM_FP64, CHSIM_FP32C, CHSIM_DEVICE_PTRS = 0, 1, 0x100
+CHSIM_TUNE_EVOLVE_LANES = 1
 MAX_BRANCH = 8
 
 EXPORTED = [
     "chsim_terms_init", "chsim_terms_reset", "chsim_apply_clifford", "chsim_amplitudes", "chsim_inner_products",
     "chsim_metropolis_init", "chsim_metropolis_step", "chsim_sample_terms", "chsim_get_terms",
-    "chsim_set_terms", "chsim_decompose_phase", "chsim_instance_info", "chsim_destroy",
+    "chsim_set_terms", "chsim_decompose_phase", "chsim_set_tuning", "chsim_get_tuning",
+    "chsim_instance_info",
+    "chsim_destroy",
     "chsim_last_error",
 ]
 
@@ -79,6 +82,8 @@ def lib():
     L.chsim_set_terms.argtypes = [vp, u32, u64, u64, vp, vp, vp, vp, vp, vp, vp, vp]
     L.chsim_decompose_phase.argtypes = [dbl, u32, C.POINTER(C.c_double), C.POINTER(C.c_uint32),
                                         C.POINTER(Gate), C.POINTER(Decomp)]
+    L.chsim_set_tuning.argtypes = [vp, u32, u32, C.c_int32]
+    L.chsim_get_tuning.argtypes = [vp, u32, u32, C.POINTER(C.c_int32), C.POINTER(C.c_float)]
     L.chsim_instance_info.argtypes = [vp, u32, C.POINTER(C.c_uint32), C.POINTER(C.c_uint64),
                                       C.POINTER(C.c_double)]
     L.chsim_destroy.argtypes = [vp]
@@ -187,6 +192,18 @@ class Context:
         except Exception:  # noqa: BLE001
             pass
 
+    def set_evolve_lanes(self, lanes, inst=0):
+        """Lanes per term of the evolution kernel (8, 16, 32, 64; 0 = default;
+        -1 = autotune at the next evolution from |0^n>)."""
+        _check(lib().chsim_set_tuning(self._h, inst, CHSIM_TUNE_EVOLVE_LANES, int(lanes)))
+
+    def evolve_lanes(self, inst=0):
+        """(lanes in use, autotuner timings in ms for lanes 8, 16, 32, 64)."""
+        v = C.c_int32()
+        t = (C.c_float * 4)()
+        _check(lib().chsim_get_tuning(self._h, inst, CHSIM_TUNE_EVOLVE_LANES, C.byref(v), t))
+        return v.value, list(t)
+
     def info(self, inst=0):
         n = C.c_uint32()
         chi = C.c_uint64()
@@ -272,6 +289,8 @@ class Context:
                                inst=0, stream=None):
         """Device-pointer variant: torch tensors on the GPU; enqueues only."""
         n_chain, n_steps = jstream.shape
+        if jstream.element_size() != 4 or ustream.element_size() != 8:
+            raise ValueError("jstream must be 32-bit integers and ustream float64")
         args = [_ptr(t)[0] for t in (jstream, ustream, trace, accepted, amp)]
         _check(lib().chsim_metropolis_step(self._h, inst, n_steps, *args, CHSIM_DEVICE_PTRS,
                                            _stream(stream)))

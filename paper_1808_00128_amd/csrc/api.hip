@@ -62,13 +62,15 @@ struct Instance {
   uint64_t chi = 0, seed = 0;
   double l1 = 1.0;
   bool at_zero = true;  // every term is |0^n> and the store holds nothing yet
+  EvolveShape shape;    // evolution mapping (0 = default for n)
+  bool autotune = false;  // time every shape at the next from-|0^n> evolution
+  float tuned_ms[4] = {0, 0, 0, 0};  // per lanes 8, 16, 32, 64 (0 = not timed)
   std::vector<SlotTable> slots_h;
   std::vector<DGate> bgates_h;
   DevBuf<uint64_t> F, G, M, v, s;
   DevBuf<uint8_t> gamma, omega, branch;
   DevBuf<double2> b;
   DevBuf<SlotTable> slots;
-  DevBuf<DGate> bgates;
   // metropolis
   uint32_t n_chain = 0;
   DevBuf<uint64_t> mstate0, mstate1, mx, mtrace;
@@ -96,7 +98,7 @@ struct Instance {
   void release() {
     F.release(); G.release(); M.release(); v.release(); s.release();
     gamma.release(); omega.release(); branch.release(); b.release();
-    slots.release(); bgates.release();
+    slots.release();
     mstate0.release(); mstate1.release(); mx.release(); mtrace.release();
     mparity.release(); mj.release(); mamp.release(); mpartial.release(); mu.release(); macc.release();
   }
@@ -141,10 +143,10 @@ void push_gate(std::vector<DGate>& out, const chsim_gate& g, size_t first = 0) {
       out.back().arg = (uint8_t)((out.back().arg + 1) & 3);
       return;
     }
-    out.push_back(DGate{OP_SPOW, g.q, 0, 1, 0});
+    out.push_back(DGate{OP_SPOW, g.q, 0, 1, 0, 0, 0});
     return;
   }
-  out.push_back(DGate{g.op, g.q, g.r, 0, g.slot});
+  out.push_back(DGate{g.op, g.q, g.r, 0, 0, 0, 0});
 }
 
 chsim_status build_slots(Instance& I, const chsim_instance& in) {
@@ -178,6 +180,22 @@ chsim_status build_slots(Instance& I, const chsim_instance& in) {
       st.unit_im[j] = w > 0.0 ? im / w : 0.0;
     }
     st.goff[d.n_branch] = (uint32_t)I.bgates_h.size();
+    // A family of S powers on one qubit (e.g. the phase-gate decomposition)
+    // is applied as a per-term power, so terms never diverge on it.
+    st.spow_q = -1;
+    {
+      int q = -1;
+      bool fam = true;
+      for (uint32_t j = 0; j < d.n_branch && fam; ++j) {
+        const uint32_t len = st.goff[j + 1] - st.goff[j];
+        if (len == 0) { st.spow[j] = 0; continue; }
+        const DGate& g0 = I.bgates_h[st.goff[j]];
+        if (len != 1 || g0.op != OP_SPOW || (q >= 0 && q != g0.q)) { fam = false; break; }
+        q = g0.q;
+        st.spow[j] = g0.arg;
+      }
+      if (fam && q >= 0) st.spow_q = q;
+    }
     st.total = cum;
     if (!(cum > 0.0) || !std::isfinite(cum)) return fail(CHSIM_EINVAL, "slot %u: zero or non-finite weights", p);
     l1 *= cum;
@@ -235,6 +253,7 @@ chsim_status chsim_terms_init(chsim_ctx** out, int device, uint32_t n_inst,
     if (in.chi == 0) return fail(CHSIM_EINVAL, "instance %u: chi = 0", i);
     if (in.n_slot && !in.slot_decomp) return fail(CHSIM_EINVAL, "instance %u: missing decompositions", i);
     if (in.mode != CHSIM_EXACT && in.mode != CHSIM_SPARSIFY) return fail(CHSIM_EINVAL, "instance %u: bad mode", i);
+    if (in.n_slot > 65535) return fail(CHSIM_EUNSUPPORTED, "instance %u: more than 65535 slots", i);
     if (in.mode == CHSIM_EXACT) {
       long double prod = 1.0L;
       for (uint32_t p = 0; p < in.n_slot; ++p) prod *= in.slot_decomp[p].n_branch;
@@ -269,15 +288,11 @@ chsim_status chsim_terms_init(chsim_ctx** out, int device, uint32_t n_inst,
               I.v.ensure(in.chi) == hipSuccess && I.s.ensure(in.chi) == hipSuccess &&
               I.omega.ensure(in.chi) == hipSuccess && I.b.ensure(in.chi) == hipSuccess &&
               I.branch.ensure((size_t)std::max<uint32_t>(in.n_slot, 1) * in.chi) == hipSuccess &&
-              I.slots.ensure(std::max<size_t>(I.slots_h.size(), 1)) == hipSuccess &&
-              I.bgates.ensure(std::max<size_t>(I.bgates_h.size(), 1)) == hipSuccess;
+              I.slots.ensure(std::max<size_t>(I.slots_h.size(), 1)) == hipSuccess;
     if (!ok) return cleanup(fail(CHSIM_ENOMEM, "instance %u: term store (%zu rows) does not fit", i, rows));
     if (!I.slots_h.empty() &&
         hipMemcpy(I.slots.p, I.slots_h.data(), I.slots_h.size() * sizeof(SlotTable), hipMemcpyHostToDevice) != hipSuccess)
       return cleanup(fail(CHSIM_EDEVICE, "slot table upload"));
-    if (!I.bgates_h.empty() &&
-        hipMemcpy(I.bgates.p, I.bgates_h.data(), I.bgates_h.size() * sizeof(DGate), hipMemcpyHostToDevice) != hipSuccess)
-      return cleanup(fail(CHSIM_EDEVICE, "branch gate upload"));
     const double scale = I.l1 / (double)I.chi;
     if (launch_choose(I.view(), I.slots.p, I.mode, I.seed, scale, nullptr) != hipSuccess)
       return cleanup(fail(CHSIM_EDEVICE, "branch choice kernel"));
@@ -316,7 +331,21 @@ chsim_status chsim_apply_clifford(chsim_ctx* ctx, uint32_t inst, const chsim_gat
     const chsim_gate& g = gates[i];
     if (g.op == CHSIM_SLOT) {
       if (g.slot >= I.n_slot) return fail(CHSIM_EINVAL, "gate %zu: slot %u >= n_slot %u", i, g.slot, I.n_slot);
-      dg.push_back(DGate{OP_SLOT, 0, 0, 0, g.slot});
+      const SlotTable& tb = I.slots_h[g.slot];
+      if (tb.spow_q >= 0) {
+        dg.push_back(DGate{OP_SLOT_SPOW, (uint8_t)tb.spow_q, 0, 0, (uint16_t)g.slot, 0, 0});
+      } else {
+        // A general branch list becomes conditional gates: each term applies
+        // only the gates of its own branch.
+        for (uint32_t j = 0; j < tb.n_branch; ++j)
+          for (uint32_t k = tb.goff[j]; k < tb.goff[j + 1]; ++k) {
+            DGate bg = I.bgates_h[k];
+            bg.slot = (uint16_t)g.slot;
+            bg.cond = 1;
+            bg.arg2 = (uint8_t)j;
+            dg.push_back(bg);
+          }
+      }
     } else {
       if (!valid_clifford(g, I.n)) return fail(CHSIM_EINVAL, "gate %zu: (%u, %u, %u) invalid for n = %u", i, g.op, g.q, g.r, I.n);
       push_gate(dg, g);
@@ -327,8 +356,46 @@ chsim_status chsim_apply_clifford(chsim_ctx* ctx, uint32_t inst, const chsim_gat
   HIP_TRY(ctx->gates.ensure(dg.size()));
   HIP_TRY(hipMemcpyAsync(ctx->gates.p, dg.data(), dg.size() * sizeof(DGate), hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemsetAsync(ctx->err.p, 0, sizeof(uint32_t), s));
-  HIP_TRY(launch_evolve(I.view(), ctx->gates.p, (uint32_t)dg.size(), I.slots.p, I.bgates.p, I.at_zero,
-                        ctx->err.p, s));
+  if (I.autotune && I.at_zero) {
+    // Every shape computes the same terms from |0^n>, so timing all of them in
+    // turn leaves the store correct; keep the fastest.
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    const int cand[4] = {8, 16, 32, 64};
+    float best = 0.f;
+    EvolveShape best_shape;
+    for (int ci = 0; ci < 4; ++ci) {
+      EvolveShape sh;
+      sh.lanes = cand[ci];
+      sh.rows = 1;
+      while ((uint32_t)(sh.lanes * sh.rows) < I.n) sh.rows *= 2;
+      I.tuned_ms[ci] = 0.f;
+      if (!evolve_shape_supported(sh, I.n)) continue;
+      HIP_TRY(hipEventRecord(e0, s));
+      HIP_TRY(launch_evolve(I.view(), ctx->gates.p, (uint32_t)dg.size(), I.slots.p, true, ctx->err.p,
+                            sh, s));
+      HIP_TRY(hipEventRecord(e1, s));
+      HIP_TRY(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+      I.tuned_ms[ci] = ms;
+      if (best_shape.lanes == 0 || ms < best) {
+        best = ms;
+        best_shape = sh;
+      }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    I.shape = best_shape;
+    I.autotune = false;
+    // Leave the store as the chosen shape computes it.
+    HIP_TRY(launch_evolve(I.view(), ctx->gates.p, (uint32_t)dg.size(), I.slots.p, true, ctx->err.p,
+                          I.shape, s));
+  } else {
+    HIP_TRY(launch_evolve(I.view(), ctx->gates.p, (uint32_t)dg.size(), I.slots.p, I.at_zero,
+                          ctx->err.p, I.shape, s));
+  }
   I.at_zero = false;
   return check_err_flag(ctx, s, "apply_clifford");
 }
@@ -716,6 +783,50 @@ chsim_status chsim_decompose_phase(double theta, uint32_t qubit, double coeff[4]
   out->coeff = coeff;
   out->off = off;
   out->gates = gates;
+  return CHSIM_OK;
+}
+
+chsim_status chsim_set_tuning(chsim_ctx* ctx, uint32_t inst, uint32_t knob, int32_t value) {
+  g_err.clear();
+  chsim_status st = check_ctx(ctx, inst);
+  if (st) return st;
+  Instance& I = ctx->inst[inst];
+  switch (knob) {
+    case CHSIM_TUNE_EVOLVE_LANES: {
+      I.autotune = false;
+      if (value == 0) {
+        I.shape = EvolveShape();
+        return CHSIM_OK;
+      }
+      if (value == -1) {
+        I.autotune = true;
+        return CHSIM_OK;
+      }
+      EvolveShape s;
+      s.lanes = value;
+      s.rows = 1;
+      while (value > 0 && (uint32_t)(s.lanes * s.rows) < I.n) s.rows *= 2;
+      if (!evolve_shape_supported(s, I.n))
+        return fail(CHSIM_EUNSUPPORTED, "no evolution kernel with %d lanes per term for n = %u", value, I.n);
+      I.shape = s;
+      return CHSIM_OK;
+    }
+    default:
+      return fail(CHSIM_EINVAL, "unknown tuning knob %u", knob);
+  }
+}
+
+chsim_status chsim_get_tuning(chsim_ctx* ctx, uint32_t inst, uint32_t knob, int32_t* value,
+                              float* timings_ms) {
+  g_err.clear();
+  chsim_status st = check_ctx(ctx, inst);
+  if (st) return st;
+  Instance& I = ctx->inst[inst];
+  if (knob != CHSIM_TUNE_EVOLVE_LANES) return fail(CHSIM_EINVAL, "unknown tuning knob %u", knob);
+  EvolveShape sh = I.shape.lanes ? I.shape : evolve_default_shape(I.n);
+  if (value) *value = sh.lanes;
+  if (timings_ms)
+    for (int i = 0; i < 4; ++i) timings_ms[i] = I.tuned_ms[i];
   return CHSIM_OK;
 }
 

@@ -10,12 +10,19 @@
 namespace chsim {
 
 // Device gate codes: the public codes plus SPOW (S applied `arg` times on q),
-// which the host uses for runs of S gates in slot branches.
-enum : uint8_t { OP_H = 0, OP_S = 1, OP_CX = 2, OP_CZ = 3, OP_SLOT = 4, OP_SPOW = 5 };
+// which the host uses for runs of S gates, and SLOT_SPOW (a slot whose
+// branches are all powers of S on qubit q: the power is spow[branch] of the
+// slot's table, per term).
+enum : uint8_t { OP_H = 0, OP_S = 1, OP_CX = 2, OP_CZ = 3, OP_SLOT = 4, OP_SPOW = 5,
+                 OP_SLOT_SPOW = 6 };
 
+// A gate of the flat device list.  `slot` is the slot index for SLOT_SPOW;
+// for a gate of a general slot branch, cond = 1 and the gate applies only to
+// terms whose branch choice of slot `slot` equals `arg2`.
 struct DGate {
   uint8_t op, q, r, arg;
-  uint32_t slot;
+  uint16_t slot;
+  uint8_t cond, arg2;
 };
 static_assert(sizeof(DGate) == 8, "DGate is 8 bytes");
 
@@ -29,6 +36,8 @@ struct SlotTable {
   double unit_im[CHSIM_MAX_BRANCH];
   double coef_re[CHSIM_MAX_BRANCH];     // c_j
   double coef_im[CHSIM_MAX_BRANCH];
+  int32_t spow_q;                       // >= 0: every branch is S^{spow[j]} on this qubit
+  uint8_t spow[CHSIM_MAX_BRANCH];
 };
 
 // Structure-of-arrays term store of one instance.  Row p of term a of F is
@@ -72,9 +81,16 @@ constexpr int kAmpTile = 64;
 // ---- launchers (each returns the first HIP error) ----
 hipError_t launch_choose(const TermsView& T, const SlotTable* slots, uint32_t mode, uint64_t seed,
                          double scale, hipStream_t st);
+// Evolution mapping: `lanes` lanes per term (8, 16, 32 or 64; 64 / lanes terms
+// per wave) and `rows` tableau rows per lane (lanes * rows >= n).  0 = choose.
+struct EvolveShape {
+  int lanes = 0, rows = 0;
+};
+EvolveShape evolve_default_shape(uint32_t n);
+bool evolve_shape_supported(EvolveShape s, uint32_t n);
 hipError_t launch_evolve(const TermsView& T, const DGate* gates, uint32_t n_gates,
-                         const SlotTable* slots, const DGate* bgates, bool from_zero,
-                         uint32_t* err, hipStream_t st);
+                         const SlotTable* slots, bool from_zero, uint32_t* err, EvolveShape shape,
+                         hipStream_t st);
 hipError_t launch_set_zero(const TermsView& T, hipStream_t st);
 hipError_t launch_sample(const TermsView& T, const uint64_t* alpha, const uint64_t* flips,
                          uint64_t* x_out, uint32_t count, hipStream_t st);

@@ -92,15 +92,38 @@ CASES = [
 
 @pytest.mark.parametrize("case", CASES, ids=[f"n{c[0]}-chi{c[3]}" for c in CASES])
 def test_evolution_bit_exact(B, case):
+    """Every evolution shape (lanes per term 8, 16, 32, 64 with enough rows per
+    lane) gives the oracle's terms bit for bit."""
     n, ng, m, chi, mode = case
     rng = np.random.default_rng(7000 + n)
     circ = W.random_circuit(n, ng, rng.uniform(0, 2 * np.pi, size=m), rng)
     spec = dict(circuit=circ, chi=chi, mode=mode, seed=31 + n)
-    say(f"evolution n={n} chi={chi} mode={mode}")
-    ctx = gpu_ctx(B, spec)
     idx = np.arange(chi, dtype=np.uint64) if chi <= 300 else np.unique(
         np.concatenate([[0, chi - 1], rng.integers(0, chi, size=120)])).astype(np.uint64)
     T = O.Terms(circ, chi, oracle_mode(spec), seed=spec["seed"], alphas=idx)
+    for lanes in (8, 16, 32, 64):
+        if lanes * 8 < n:
+            continue
+        say(f"evolution n={n} chi={chi} mode={mode} lanes={lanes}")
+        ctx = B.Context([spec])
+        ctx.set_evolve_lanes(lanes)
+        ctx.apply_circuit(circ)
+        compare_terms(ctx, T, idx)
+        ctx.close()
+
+
+def test_evolution_autotune_keeps_results(B):
+    rng = np.random.default_rng(71)
+    circ = W.random_circuit(40, 500, rng.uniform(0, 2 * np.pi, size=10), rng)
+    spec = dict(circuit=circ, chi=777, mode="sparsify", seed=9)
+    say("evolution autotune n=40 chi=777")
+    ctx = B.Context([spec])
+    ctx.set_evolve_lanes(-1)
+    ctx.apply_circuit(circ)
+    lanes, times = ctx.evolve_lanes()
+    assert lanes in (8, 16, 32, 64) and times[[8, 16, 32, 64].index(lanes)] > 0
+    idx = np.arange(0, 777, 7, dtype=np.uint64)
+    T = O.Terms(circ, 777, O.SPARSIFY, seed=9, alphas=idx)
     compare_terms(ctx, T, idx)
 
 
