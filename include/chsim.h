@@ -154,6 +154,66 @@ chsim_status chsim_metropolis_step(chsim_ctx* ctx, uint32_t inst, uint32_t n_ste
                                    uint64_t* x_trace, uint8_t* accepted, double* amp,
                                    uint32_t flags, void* stream);
 
+/* ---- Learned proposal -------------------------------------------------
+ * A flip-mask proposal from a small network f: {0,1}^n -> R^n (n -> H -> H
+ * -> n, ReLU) on BF16 matrix cores with FP32 accumulation.  Features
+ * s_j = 1 - 2 x_j.  pi_j(x) = clip(sigmoid(f(x)_j), pi_min, pi_max).  The
+ * chain proposes y = x ^ m from the mixture
+ *   q(y|x) = eps [|m| = 1] / n + (1 - eps) prod_j pi_j^{m_j} (1 - pi_j)^{1 - m_j}
+ * and accepts iff U < P(y) q(x|y) / (P(x) q(y|x)) (Metropolis-Hastings with the
+ * exact amplitude ratio of Sec. "Heuristic Metropolis simulator"), so the
+ * stationary law is the paper's P(x).  Parameters are packed in FP32 as
+ * W1 [H][n], b1 [H], W2 [H][H], b2 [H], W3 [n][H], b3 [n]. */
+typedef struct chsim_mlp chsim_mlp;
+
+/* Create a network on the context's device for batches up to max_batch,
+ * initialised from params (packed, see above).  EINVAL: n outside [1, 64],
+ * hidden not a positive multiple of 16 or above 1024, max_batch == 0. */
+chsim_status chsim_mlp_create(chsim_ctx* ctx, uint32_t n, uint32_t hidden, uint32_t max_batch,
+                              const float* params, chsim_mlp** out);
+chsim_status chsim_mlp_destroy(chsim_mlp* mlp);
+/* Copy the FP32 parameters out / in (setting resets the optimiser state). */
+chsim_status chsim_mlp_get_params(chsim_mlp* mlp, float* params);
+chsim_status chsim_mlp_set_params(chsim_mlp* mlp, const float* params);
+/* logits[b*n + j] = f(x_b)_j for batch <= max_batch strings. */
+chsim_status chsim_mlp_forward(chsim_mlp* mlp, const uint64_t* x, uint32_t batch, float* logits,
+                               uint32_t flags, void* stream);
+/* Binary cross-entropy with logits against target flip bits t_b,
+ * L = mean_{b,j} softplus(l_bj) - t_bj l_bj, and its gradient with respect to
+ * every parameter (packed like the parameters; FP32).  Either output may be
+ * NULL. */
+chsim_status chsim_mlp_loss_grad(chsim_mlp* mlp, const uint64_t* x, const uint64_t* target,
+                                 uint32_t batch, double* loss, float* grads, uint32_t flags,
+                                 void* stream);
+/* Adam (beta1 0.9, beta2 0.999, eps 1e-8) over `epochs` passes of
+ * consecutive minibatches of (x, target) pairs; epoch_loss[e] (may be NULL)
+ * receives the mean loss of epoch e. */
+chsim_status chsim_mlp_train(chsim_mlp* mlp, const uint64_t* x, const uint64_t* target,
+                             uint64_t count, uint32_t batch, uint32_t epochs, float lr,
+                             double* epoch_loss, uint32_t flags, void* stream);
+
+/* Random inputs of the learned chain, [chains][steps] (u_bits [chains][steps][n]):
+ * u_mix < eps selects the single flip of bit j; otherwise bit k flips iff
+ * u_bits < pi_k(x); u is the accept uniform. */
+typedef struct chsim_learned_args {
+  float eps, pi_min, pi_max;
+  const double* u_mix;
+  const uint32_t* j;
+  const double* u_bits;
+  const double* u;
+} chsim_learned_args;
+
+/* Advance the chains started by chsim_metropolis_init with the learned
+ * proposal (requires n <= 62 and the network's n equal to the instance's).
+ * Outputs as chsim_metropolis_step, plus n_flips[c*n_steps + t] = |m| (may be
+ * NULL; a step with |m| = 0 leaves the chain in place and counts as
+ * accepted). */
+chsim_status chsim_metropolis_step_learned(chsim_ctx* ctx, uint32_t inst, chsim_mlp* mlp,
+                                           uint32_t n_steps, const chsim_learned_args* args,
+                                           uint64_t* x_trace, uint8_t* accepted,
+                                           uint32_t* n_flips, double* amp, uint32_t flags,
+                                           void* stream);
+
 /* Sample one bitstring per request from a single term's |<x|phi_alpha>|^2 (the
  * three-step sampler of the Clifford-simulator section: w = s, flip w_j where
  * v_j = 1 and bit j of flips[i] is set, x = w G^T).  Host pointers. */

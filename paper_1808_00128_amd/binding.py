@@ -28,8 +28,9 @@ EXPORTED = [
     "chsim_terms_init", "chsim_terms_reset", "chsim_apply_clifford", "chsim_amplitudes", "chsim_inner_products",
     "chsim_metropolis_init", "chsim_metropolis_step", "chsim_sample_terms", "chsim_get_terms",
     "chsim_set_terms", "chsim_decompose_phase", "chsim_set_tuning", "chsim_get_tuning",
-    "chsim_instance_info",
-    "chsim_destroy",
+    "chsim_instance_info", "chsim_destroy", "chsim_mlp_create", "chsim_mlp_destroy",
+    "chsim_mlp_get_params", "chsim_mlp_set_params", "chsim_mlp_forward", "chsim_mlp_loss_grad",
+    "chsim_mlp_train", "chsim_metropolis_step_learned",
     "chsim_last_error",
 ]
 
@@ -53,6 +54,30 @@ class Decomp(C.Structure):
 class Instance(C.Structure):
     _fields_ = [("n", C.c_uint32), ("n_slot", C.c_uint32), ("slot_decomp", C.POINTER(Decomp)),
                 ("chi", C.c_uint64), ("mode", C.c_uint32), ("seed", C.c_uint64)]
+
+
+class LearnedArgs(C.Structure):
+    _fields_ = [("eps", C.c_float), ("pi_min", C.c_float), ("pi_max", C.c_float),
+                ("u_mix", C.c_void_p), ("j", C.c_void_p), ("u_bits", C.c_void_p),
+                ("u", C.c_void_p)]
+
+
+PARAM_ORDER = ("W1", "b1", "W2", "b2", "W3", "b3")
+
+
+def pack_params(params):
+    return np.ascontiguousarray(np.concatenate([np.asarray(params[k], np.float32).ravel()
+                                                for k in PARAM_ORDER]))
+
+
+def unpack_params(flat, n, H):
+    shapes = {"W1": (H, n), "b1": (H,), "W2": (H, H), "b2": (H,), "W3": (n, H), "b3": (n,)}
+    out, off = {}, 0
+    for k in PARAM_ORDER:
+        size = int(np.prod(shapes[k]))
+        out[k] = flat[off:off + size].reshape(shapes[k]).copy()
+        off += size
+    return out
 
 
 GATE_DTYPE = np.dtype([("op", "u1"), ("q", "u1"), ("r", "u1"), ("pad", "u1"), ("slot", "<u4")])
@@ -87,6 +112,15 @@ def lib():
     L.chsim_instance_info.argtypes = [vp, u32, C.POINTER(C.c_uint32), C.POINTER(C.c_uint64),
                                       C.POINTER(C.c_double)]
     L.chsim_destroy.argtypes = [vp]
+    L.chsim_mlp_create.argtypes = [vp, u32, u32, u32, vp, C.POINTER(C.c_void_p)]
+    L.chsim_mlp_destroy.argtypes = [vp]
+    L.chsim_mlp_get_params.argtypes = [vp, vp]
+    L.chsim_mlp_set_params.argtypes = [vp, vp]
+    L.chsim_mlp_forward.argtypes = [vp, vp, u32, vp, u32, vp]
+    L.chsim_mlp_loss_grad.argtypes = [vp, vp, vp, u32, C.POINTER(C.c_double), vp, u32, vp]
+    L.chsim_mlp_train.argtypes = [vp, vp, vp, u64, u32, u32, C.c_float, vp, u32, vp]
+    L.chsim_metropolis_step_learned.argtypes = [vp, u32, vp, u32, C.POINTER(LearnedArgs), vp, vp,
+                                                vp, vp, u32, vp]
     L.chsim_last_error.restype = C.c_char_p
     for name in EXPORTED:
         if name != "chsim_last_error":
@@ -332,3 +366,94 @@ class Context:
         bb[1::2] = np.imag(b)
         _check(lib().chsim_set_terms(self._h, inst, first, count, *[_ptr(a)[0] for a in arrs],
                                      _ptr(bb)[0]))
+
+
+    def metropolis_step_learned(self, mlp, u_mix, j, u_bits, u, eps, pi_min, pi_max, inst=0,
+                                stream=None):
+        """Advance all chains with the learned proposal (host arrays)."""
+        u_mix = np.ascontiguousarray(u_mix, np.float64)
+        j = np.ascontiguousarray(j, np.uint32)
+        u_bits = np.ascontiguousarray(u_bits, np.float64)
+        u = np.ascontiguousarray(u, np.float64)
+        n_chain, n_steps = j.shape
+        keep = (u_mix, j, u_bits, u)
+        a = LearnedArgs(eps, pi_min, pi_max, *[_ptr(t)[0] for t in keep])
+        tr = np.zeros((n_chain, n_steps), np.uint64)
+        acc = np.zeros((n_chain, n_steps), np.uint8)
+        fl = np.zeros((n_chain, n_steps), np.uint32)
+        amp = np.zeros(2 * n_chain)
+        _check(lib().chsim_metropolis_step_learned(self._h, inst, mlp._h, n_steps, C.byref(a),
+                                                   _ptr(tr)[0], _ptr(acc)[0], _ptr(fl)[0],
+                                                   _ptr(amp)[0], 0, _stream(stream)))
+        return tr, acc, fl, amp[0::2] + 1j * amp[1::2]
+
+    def metropolis_step_learned_device(self, mlp, u_mix, j, u_bits, u, eps, pi_min, pi_max,
+                                       trace=None, accepted=None, n_flips=None, inst=0,
+                                       stream=None):
+        """Device-pointer variant (torch tensors on the GPU); enqueues only."""
+        n_chain, n_steps = j.shape
+        keep = (u_mix, j, u_bits, u)
+        a = LearnedArgs(eps, pi_min, pi_max, *[_ptr(t)[0] for t in keep])
+        _check(lib().chsim_metropolis_step_learned(self._h, inst, mlp._h, n_steps, C.byref(a),
+                                                   _ptr(trace)[0], _ptr(accepted)[0],
+                                                   _ptr(n_flips)[0], None, CHSIM_DEVICE_PTRS,
+                                                   _stream(stream)))
+
+
+class MLP:
+    """Proposal network n -> H -> H -> n on the context's GPU (BF16 MFMA)."""
+
+    def __init__(self, ctx: Context, n: int, hidden: int, max_batch: int, params: dict):
+        self.n, self.H, self.cap = n, hidden, max_batch
+        self.ctx = ctx
+        flat = pack_params(params)
+        h = C.c_void_p()
+        _check(lib().chsim_mlp_create(ctx._h, n, hidden, max_batch, _ptr(flat)[0], C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().chsim_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001
+            pass
+
+    def params(self):
+        flat = np.zeros(self._count(), np.float32)
+        _check(lib().chsim_mlp_get_params(self._h, _ptr(flat)[0]))
+        return unpack_params(flat, self.n, self.H)
+
+    def set_params(self, params):
+        flat = pack_params(params)
+        _check(lib().chsim_mlp_set_params(self._h, _ptr(flat)[0]))
+
+    def _count(self):
+        n, H = self.n, self.H
+        return H * n + H + H * H + H + n * H + n
+
+    def forward(self, x):
+        x = np.ascontiguousarray(x, np.uint64)
+        out = np.zeros((x.size, self.n), np.float32)
+        _check(lib().chsim_mlp_forward(self._h, _ptr(x)[0], x.size, _ptr(out)[0], 0, None))
+        return out
+
+    def loss_grad(self, x, target):
+        x = np.ascontiguousarray(x, np.uint64)
+        t = np.ascontiguousarray(target, np.uint64)
+        g = np.zeros(self._count(), np.float32)
+        loss = C.c_double()
+        _check(lib().chsim_mlp_loss_grad(self._h, _ptr(x)[0], _ptr(t)[0], x.size, C.byref(loss),
+                                         _ptr(g)[0], 0, None))
+        return loss.value, unpack_params(g, self.n, self.H)
+
+    def train(self, x, target, batch, epochs, lr):
+        x = np.ascontiguousarray(x, np.uint64)
+        t = np.ascontiguousarray(target, np.uint64)
+        losses = np.zeros(epochs)
+        _check(lib().chsim_mlp_train(self._h, _ptr(x)[0], _ptr(t)[0], x.size, batch, epochs,
+                                     float(lr), _ptr(losses)[0], 0, None))
+        return losses

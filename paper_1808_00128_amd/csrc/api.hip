@@ -14,6 +14,7 @@
 
 #include "chsim.h"
 #include "internal.hpp"
+#include "mlp.hpp"
 
 using namespace chsim;
 
@@ -78,6 +79,11 @@ struct Instance {
   DevBuf<double2> mamp, mpartial;
   DevBuf<double> mu;
   DevBuf<uint8_t> macc;
+  // learned chain
+  DevBuf<uint64_t> ly, lmask;
+  DevBuf<float> logit_x, logit_y;
+  DevBuf<double> lumix, lubits;
+  DevBuf<uint32_t> lj, lflips;
 
   TermsView view() {
     TermsView t;
@@ -101,6 +107,8 @@ struct Instance {
     slots.release();
     mstate0.release(); mstate1.release(); mx.release(); mtrace.release();
     mparity.release(); mj.release(); mamp.release(); mpartial.release(); mu.release(); macc.release();
+    ly.release(); lmask.release(); logit_x.release(); logit_y.release(); lumix.release();
+    lubits.release(); lj.release(); lflips.release();
   }
 };
 
@@ -859,4 +867,283 @@ chsim_status chsim_destroy(chsim_ctx* ctx) {
   return CHSIM_OK;
 }
 
+
 }  // extern "C"
+
+struct chsim_mlp {
+  chsim_ctx* ctx = nullptr;
+  MLPDev d;
+  DevBuf<double> loss;
+  DevBuf<uint64_t> xin, tin;
+  std::vector<void*> owned;
+  ~chsim_mlp() {
+    for (void* q : owned)
+      if (q) hipFree(q);
+    loss.release();
+    xin.release();
+    tin.release();
+  }
+};
+
+namespace {
+
+template <typename T>
+hipError_t mlp_alloc(chsim_mlp* m, T** p, size_t count) {
+  hipError_t e = hipMalloc((void**)p, std::max<size_t>(count, 1) * sizeof(T));
+  if (e == hipSuccess) m->owned.push_back((void*)*p);
+  return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+chsim_status chsim_mlp_create(chsim_ctx* ctx, uint32_t n, uint32_t hidden, uint32_t max_batch,
+                              const float* params, chsim_mlp** out) {
+  g_err.clear();
+  if (!out) return fail(CHSIM_EINVAL, "null output");
+  *out = nullptr;
+  if (!ctx) return fail(CHSIM_EINVAL, "null context");
+  if (n < 1 || n > 64) return fail(CHSIM_EINVAL, "n = %u outside [1, 64]", n);
+  if (hidden == 0 || hidden % 16 || hidden > 1024) return fail(CHSIM_EINVAL, "hidden = %u", hidden);
+  if (max_batch == 0) return fail(CHSIM_EINVAL, "max_batch = 0");
+  if (!params) return fail(CHSIM_EINVAL, "null parameters");
+  HIP_TRY(hipSetDevice(ctx->device));
+  chsim_mlp* m = new chsim_mlp();
+  m->ctx = ctx;
+  MLPDev& d = m->d;
+  d.L.n = n;
+  d.L.H = hidden;
+  d.cap = max_batch;
+  const uint64_t cnt = d.L.count();
+  const size_t B = max_batch, H = hidden;
+  bool ok = mlp_alloc(m, &d.p, cnt) == hipSuccess && mlp_alloc(m, &d.grad, cnt) == hipSuccess &&
+            mlp_alloc(m, &d.adam_m, cnt) == hipSuccess && mlp_alloc(m, &d.adam_v, cnt) == hipSuccess &&
+            mlp_alloc(m, &d.wb, d.L.wb_count()) == hipSuccess &&
+            mlp_alloc(m, &d.a0, B * n) == hipSuccess && mlp_alloc(m, &d.a1, B * H) == hipSuccess &&
+            mlp_alloc(m, &d.a2, B * H) == hipSuccess && mlp_alloc(m, &d.z1, B * H) == hipSuccess &&
+            mlp_alloc(m, &d.z2, B * H) == hipSuccess && mlp_alloc(m, &d.logits, B * n) == hipSuccess &&
+            mlp_alloc(m, &d.gf, B * n) == hipSuccess && mlp_alloc(m, &d.dz1, B * H) == hipSuccess &&
+            mlp_alloc(m, &d.dz2, B * H) == hipSuccess && mlp_alloc(m, &d.gb, B * n) == hipSuccess &&
+            mlp_alloc(m, &d.gz1, B * H) == hipSuccess && mlp_alloc(m, &d.gz2, B * H) == hipSuccess &&
+            m->loss.ensure(1) == hipSuccess;
+  if (!ok) {
+    delete m;
+    return fail(CHSIM_ENOMEM, "network buffers do not fit");
+  }
+  *out = m;
+  chsim_status st = chsim_mlp_set_params(m, params);
+  if (st != CHSIM_OK) {
+    delete m;
+    *out = nullptr;
+  }
+  return st;
+}
+
+chsim_status chsim_mlp_destroy(chsim_mlp* mlp) {
+  if (!mlp) return CHSIM_OK;
+  hipSetDevice(mlp->ctx->device);
+  hipDeviceSynchronize();
+  delete mlp;
+  return CHSIM_OK;
+}
+
+chsim_status chsim_mlp_get_params(chsim_mlp* mlp, float* params) {
+  g_err.clear();
+  if (!mlp || !params) return fail(CHSIM_EINVAL, "null argument");
+  HIP_TRY(hipSetDevice(mlp->ctx->device));
+  HIP_TRY(hipDeviceSynchronize());
+  HIP_TRY(hipMemcpy(params, mlp->d.p, mlp->d.L.count() * sizeof(float), hipMemcpyDeviceToHost));
+  return CHSIM_OK;
+}
+
+chsim_status chsim_mlp_set_params(chsim_mlp* mlp, const float* params) {
+  g_err.clear();
+  if (!mlp || !params) return fail(CHSIM_EINVAL, "null argument");
+  MLPDev& d = mlp->d;
+  HIP_TRY(hipSetDevice(mlp->ctx->device));
+  const size_t bytes = d.L.count() * sizeof(float);
+  HIP_TRY(hipMemcpy(d.p, params, bytes, hipMemcpyHostToDevice));
+  std::vector<float> zero(d.L.count(), 0.f);
+  HIP_TRY(hipMemcpy(d.adam_m, zero.data(), bytes, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(d.adam_v, zero.data(), bytes, hipMemcpyHostToDevice));
+  d.step = 0;
+  HIP_TRY(mlp_refresh(d, nullptr));
+  HIP_TRY(hipDeviceSynchronize());
+  return CHSIM_OK;
+}
+
+chsim_status chsim_mlp_forward(chsim_mlp* mlp, const uint64_t* x, uint32_t batch, float* logits,
+                               uint32_t flags, void* stream) {
+  g_err.clear();
+  if (!mlp || !x || !logits) return fail(CHSIM_EINVAL, "null argument");
+  MLPDev& d = mlp->d;
+  if (batch == 0 || batch > d.cap) return fail(CHSIM_EINVAL, "batch %u outside [1, %u]", batch, d.cap);
+  const bool dev = flags & CHSIM_DEVICE_PTRS;
+  HIP_TRY(hipSetDevice(mlp->ctx->device));
+  hipStream_t s = as_stream(stream);
+  const uint64_t* xd;
+  chsim_status st = stage_in(mlp->xin, x, batch, dev, s, &xd);
+  if (st) return st;
+  float* out = dev ? logits : d.logits;
+  HIP_TRY(mlp_forward(d, xd, batch, out, s));
+  if (!dev) {
+    HIP_TRY(hipMemcpyAsync(logits, out, (size_t)batch * d.L.n * sizeof(float), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+  return CHSIM_OK;
+}
+
+chsim_status chsim_mlp_loss_grad(chsim_mlp* mlp, const uint64_t* x, const uint64_t* target,
+                                 uint32_t batch, double* loss, float* grads, uint32_t flags,
+                                 void* stream) {
+  g_err.clear();
+  if (!mlp || !x || !target) return fail(CHSIM_EINVAL, "null argument");
+  MLPDev& d = mlp->d;
+  if (batch == 0 || batch > d.cap) return fail(CHSIM_EINVAL, "batch %u outside [1, %u]", batch, d.cap);
+  if (flags & CHSIM_DEVICE_PTRS) return fail(CHSIM_EUNSUPPORTED, "host pointers only");
+  HIP_TRY(hipSetDevice(mlp->ctx->device));
+  hipStream_t s = as_stream(stream);
+  const uint64_t *xd, *td;
+  chsim_status st = stage_in(mlp->xin, x, batch, false, s, &xd);
+  if (st) return st;
+  st = stage_in(mlp->tin, target, batch, false, s, &td);
+  if (st) return st;
+  double zero = 0.0;
+  HIP_TRY(hipMemcpyAsync(mlp->loss.p, &zero, sizeof(double), hipMemcpyHostToDevice, s));
+  HIP_TRY(mlp_loss_grad(d, xd, td, batch, mlp->loss.p, s));
+  double lsum = 0.0;
+  HIP_TRY(hipMemcpyAsync(&lsum, mlp->loss.p, sizeof(double), hipMemcpyDeviceToHost, s));
+  if (grads) HIP_TRY(hipMemcpyAsync(grads, d.grad, d.L.count() * sizeof(float), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (loss) *loss = lsum / ((double)batch * d.L.n);
+  return CHSIM_OK;
+}
+
+chsim_status chsim_mlp_train(chsim_mlp* mlp, const uint64_t* x, const uint64_t* target,
+                             uint64_t count, uint32_t batch, uint32_t epochs, float lr,
+                             double* epoch_loss, uint32_t flags, void* stream) {
+  g_err.clear();
+  if (!mlp || !x || !target) return fail(CHSIM_EINVAL, "null argument");
+  MLPDev& d = mlp->d;
+  if (count == 0 || batch == 0 || batch > d.cap) return fail(CHSIM_EINVAL, "bad count or batch");
+  const bool dev = flags & CHSIM_DEVICE_PTRS;
+  HIP_TRY(hipSetDevice(mlp->ctx->device));
+  hipStream_t s = as_stream(stream);
+  const uint64_t *xd, *td;
+  chsim_status st = stage_in(mlp->xin, x, count, dev, s, &xd);
+  if (st) return st;
+  st = stage_in(mlp->tin, target, count, dev, s, &td);
+  if (st) return st;
+  for (uint32_t e = 0; e < epochs; ++e) {
+    double zero = 0.0;
+    HIP_TRY(hipMemcpyAsync(mlp->loss.p, &zero, sizeof(double), hipMemcpyHostToDevice, s));
+    for (uint64_t b0 = 0; b0 < count; b0 += batch) {
+      const uint32_t B = (uint32_t)std::min<uint64_t>(batch, count - b0);
+      HIP_TRY(mlp_loss_grad(d, xd + b0, td + b0, B, mlp->loss.p, s));
+      HIP_TRY(mlp_adam(d, lr, s));
+    }
+    if (epoch_loss) {
+      double lsum = 0.0;
+      HIP_TRY(hipMemcpyAsync(&lsum, mlp->loss.p, sizeof(double), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      epoch_loss[e] = lsum / ((double)count * d.L.n);
+    }
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  return CHSIM_OK;
+}
+
+chsim_status chsim_metropolis_step_learned(chsim_ctx* ctx, uint32_t inst, chsim_mlp* mlp,
+                                           uint32_t n_steps, const chsim_learned_args* args,
+                                           uint64_t* x_trace, uint8_t* accepted,
+                                           uint32_t* n_flips, double* amp, uint32_t flags,
+                                           void* stream) {
+  g_err.clear();
+  chsim_status st = check_ctx(ctx, inst);
+  if (st) return st;
+  Instance& I = ctx->inst[inst];
+  if (!mlp || !args) return fail(CHSIM_EINVAL, "null network or arguments");
+  if (mlp->ctx != ctx) return fail(CHSIM_EINVAL, "network belongs to another context");
+  if (I.n_chain == 0) return fail(CHSIM_EINVAL, "chains not initialised");
+  if (mlp->d.L.n != I.n) return fail(CHSIM_EINVAL, "network n = %u, instance n = %u", mlp->d.L.n, I.n);
+  if (I.n_chain > mlp->d.cap) return fail(CHSIM_EINVAL, "network batch %u < %u chains", mlp->d.cap, I.n_chain);
+  if (!(args->eps >= 0.f && args->eps <= 1.f) || !(args->pi_min > 0.f) || !(args->pi_max < 1.f) ||
+      !(args->pi_min <= args->pi_max))
+    return fail(CHSIM_EINVAL, "eps must be in [0, 1] and 0 < pi_min <= pi_max < 1");
+  if (!args->u_mix || !args->j || !args->u_bits || !args->u) return fail(CHSIM_EINVAL, "null random inputs");
+  if (n_steps == 0) return CHSIM_OK;
+  const bool dev = flags & CHSIM_DEVICE_PTRS;
+  const size_t C = I.n_chain, cnt = C * n_steps;
+  if (!dev)
+    for (size_t i = 0; i < cnt; ++i)
+      if (args->j[i] >= I.n) return fail(CHSIM_EINVAL, "j[%zu] >= n", i);
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t s = as_stream(stream);
+  MetroView mv = metro_view(I);
+  mv.n_steps = n_steps;
+  LearnedView lv;
+  lv.n = I.n;
+  lv.n_chain = I.n_chain;
+  lv.n_steps = n_steps;
+  lv.eps = args->eps;
+  lv.pi_min = args->pi_min;
+  lv.pi_max = args->pi_max;
+  const double *umd, *ubd, *ud;
+  const uint32_t* jd;
+  if ((st = stage_in(I.lumix, args->u_mix, cnt, dev, s, &umd))) return st;
+  if ((st = stage_in(I.lj, args->j, cnt, dev, s, &jd))) return st;
+  if ((st = stage_in(I.lubits, args->u_bits, cnt * I.n, dev, s, &ubd))) return st;
+  if ((st = stage_in(I.mu, args->u, cnt, dev, s, &ud))) return st;
+  lv.u_mix = umd;
+  lv.j = jd;
+  lv.u_bits = ubd;
+  lv.u = ud;
+  HIP_TRY(I.ly.ensure(C));
+  HIP_TRY(I.lmask.ensure(C));
+  HIP_TRY(I.logit_x.ensure(C * I.n));
+  HIP_TRY(I.logit_y.ensure(C * I.n));
+  lv.x = I.mx.p;
+  lv.y = I.ly.p;
+  lv.mask = I.lmask.p;
+  lv.logit_x = I.logit_x.p;
+  lv.logit_y = I.logit_y.p;
+  lv.n_flips = nullptr;
+  if (x_trace) {
+    if (dev) mv.trace = x_trace;
+    else {
+      HIP_TRY(I.mtrace.ensure(cnt));
+      mv.trace = I.mtrace.p;
+    }
+  }
+  if (accepted) {
+    if (dev) mv.accepted = accepted;
+    else {
+      HIP_TRY(I.macc.ensure(cnt));
+      mv.accepted = I.macc.p;
+    }
+  }
+  if (n_flips) {
+    if (dev) lv.n_flips = n_flips;
+    else {
+      HIP_TRY(I.lflips.ensure(cnt));
+      lv.n_flips = I.lflips.p;
+    }
+  }
+  // The network's output at the current states.
+  HIP_TRY(mlp_forward(mlp->d, I.mx.p, I.n_chain, I.logit_x.p, s));
+  HIP_TRY(launch_learned_steps(I.view(), mv, lv, mlp->d, n_steps, s));
+  if (!dev) {
+    if (x_trace) HIP_TRY(hipMemcpyAsync(x_trace, mv.trace, cnt * 8, hipMemcpyDeviceToHost, s));
+    if (accepted) HIP_TRY(hipMemcpyAsync(accepted, mv.accepted, cnt, hipMemcpyDeviceToHost, s));
+    if (n_flips) HIP_TRY(hipMemcpyAsync(n_flips, lv.n_flips, cnt * 4, hipMemcpyDeviceToHost, s));
+    if (amp) HIP_TRY(hipMemcpyAsync(amp, I.mamp.p, C * sizeof(double2), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  } else if (amp) {
+    HIP_TRY(hipMemcpyAsync(amp, I.mamp.p, C * sizeof(double2), hipMemcpyDeviceToDevice, s));
+  }
+  return CHSIM_OK;
+}
+
+}  // extern "C"
+

@@ -1,0 +1,482 @@
+// Learned Metropolis proposal: a small MLP n -> H -> H -> n on BF16 matrix
+// cores, trained by BCE on flip masks, and the Metropolis-Hastings chain that
+// uses it.
+//
+// The paper's sampler (Sec. "Heuristic Metropolis simulator") proposes single
+// bit flips; here the proposal is the mixture
+//   q(y|x) = eps [|m| = 1]/n + (1 - eps) prod_j pi_j(x)^{m_j} (1 - pi_j(x))^{1-m_j},
+// m = x ^ y, pi_j = clip(sigmoid(f(x)_j), pi_min, pi_max), and a move is
+// accepted iff U < P(y) q(x|y) / (P(x) q(y|x)) with the exact amplitude ratio
+// of the sum over Cliffords, so the stationary law is unchanged.
+//
+// Matrix products: v_mfma_f32_16x16x16_bf16 (BF16 operands, FP32 accumulate),
+// 32x32 output tile per 256-thread workgroup (2 x 2 waves, one 16x16 MFMA
+// tile each), operands staged through LDS in BF16 with arbitrary source
+// strides, so forward and backward products use the same kernel.
+#include "device_common.hpp"
+#include "internal.hpp"
+#include "mlp.hpp"
+
+namespace chsim {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x007FFFFFu)) return 0x7FC0;  // NaN
+  u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest, ties to even
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// ---------------------------------------------------------------------------
+// C[M x N] = A[M x K] B[K x N], BF16 operands, FP32 accumulation.
+// A(i, k) = A[i * sai + k * sak], B(k, j) = B[k * sbk + j * sbj].
+// Epilogues:
+//   EPI_STORE: Cf = acc.
+//   EPI_BIAS_RELU: z = acc + bias[j]; Cf = z; Cb = bf16(max(z, 0)).
+//   EPI_BIAS: Cf = acc + bias[j]  (no activation; logits).
+//   EPI_MASK: v = acc * (mask[i][j] > 0); Cf = v; Cb = bf16(v).
+// ---------------------------------------------------------------------------
+enum { EPI_STORE = 0, EPI_BIAS_RELU = 1, EPI_BIAS = 2, EPI_MASK = 3 };
+
+struct GemmArgs {
+  const uint16_t* A;
+  const uint16_t* B;
+  int64_t sai, sak, sbk, sbj;
+  int M, N, K;
+  int epi;
+  const float* bias;
+  const float* mask;  // [M][ldc]
+  float* Cf;          // may be null
+  uint16_t* Cb;       // may be null
+  int ldc;
+};
+
+__global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
+  __shared__ uint16_t As[32][16 + 4];  // [m][k]
+  __shared__ uint16_t Bs[32][16 + 4];  // [n][k]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int m0 = blockIdx.x * 32, n0 = blockIdx.y * 32;
+  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < g.K; k0 += 16) {
+    for (int e = tid; e < 32 * 16; e += 256) {
+      const int i = e >> 4, k = e & 15;
+      const int gi = m0 + i, gk = k0 + k;
+      As[i][k] = (gi < g.M && gk < g.K) ? g.A[gi * g.sai + gk * g.sak] : (uint16_t)0;
+      const int j = e >> 4;  // Bs[n][k]
+      const int gj = n0 + j;
+      Bs[j][k] = (gj < g.N && gk < g.K) ? g.B[(int64_t)gk * g.sbk + (int64_t)gj * g.sbj] : (uint16_t)0;
+    }
+    __syncthreads();
+    // 16x16x16 operand layout: lane l holds A[l % 16][4 (l / 16) .. +3] and
+    // B[4 (l / 16) .. +3][l % 16]; the result C[4 (l / 16) + r][l % 16], r = 0..3.
+    const int r16 = lane & 15, kq = (lane >> 4) * 4;
+    bf16x4 a, b;
+    for (int t = 0; t < 4; ++t) {
+      a[t] = (short)As[wm * 16 + r16][kq + t];
+      b[t] = (short)Bs[wn * 16 + r16][kq + t];
+    }
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+    __syncthreads();
+  }
+  const int col = n0 + wn * 16 + (lane & 15);
+  for (int r = 0; r < 4; ++r) {
+    const int row = m0 + wm * 16 + (lane >> 4) * 4 + r;
+    if (row >= g.M || col >= g.N) continue;
+    float v = acc[r];
+    const int64_t o = (int64_t)row * g.ldc + col;
+    switch (g.epi) {
+      case EPI_BIAS_RELU: {
+        v += g.bias[col];
+        if (g.Cf) g.Cf[o] = v;
+        if (g.Cb) g.Cb[o] = f2bf(v > 0.f ? v : 0.f);
+        break;
+      }
+      case EPI_BIAS:
+        v += g.bias[col];
+        if (g.Cf) g.Cf[o] = v;
+        if (g.Cb) g.Cb[o] = f2bf(v);
+        break;
+      case EPI_MASK:
+        v = g.mask[o] > 0.f ? v : 0.f;
+        if (g.Cf) g.Cf[o] = v;
+        if (g.Cb) g.Cb[o] = f2bf(v);
+        break;
+      default:
+        if (g.Cf) g.Cf[o] = v;
+        if (g.Cb) g.Cb[o] = f2bf(v);
+        break;
+    }
+  }
+}
+
+static hipError_t gemm(const GemmArgs& g, hipStream_t st) {
+  dim3 grid((g.M + 31) / 32, (g.N + 31) / 32);
+  hipLaunchKernelGGL(k_gemm_bf16, grid, dim3(256), 0, st, g);
+  return hipGetLastError();
+}
+
+// s_j = 1 - 2 x_j as BF16, [B][n].
+__global__ __launch_bounds__(256) void k_features(const uint64_t* __restrict__ x, uint32_t B, uint32_t n,
+                                                  uint16_t* __restrict__ a0) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= B * n) return;
+  const uint32_t b = i / n, j = i % n;
+  a0[i] = ((x[b] >> j) & 1ull) ? (uint16_t)0xBF80 /* -1 */ : (uint16_t)0x3F80 /* +1 */;
+}
+
+// g = (sigmoid(l) - t) / (B n); loss partial sums softplus(l) - t l.
+__global__ __launch_bounds__(256) void k_bce_grad(const float* __restrict__ logits,
+                                                  const uint64_t* __restrict__ t, uint32_t B,
+                                                  uint32_t n, float* __restrict__ g,
+                                                  uint16_t* __restrict__ gb,
+                                                  double* __restrict__ loss_acc) {
+  __shared__ double part[256];
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  double lv = 0.0;
+  if (i < B * n) {
+    const uint32_t b = i / n, j = i % n;
+    const float l = logits[i];
+    const float tv = ((t[b] >> j) & 1ull) ? 1.f : 0.f;
+    const float sg = 1.f / (1.f + expf(-l));
+    const float gv = (sg - tv) / (float)(B * n);
+    g[i] = gv;
+    gb[i] = f2bf(gv);
+    const double ld = (double)l;
+    lv = (ld > 0 ? ld + log1p(exp(-ld)) : log1p(exp(ld))) - (double)tv * ld;
+  }
+  part[threadIdx.x] = lv;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicAdd(loss_acc, part[0]);
+}
+
+// db[j] = sum_b d[b][j] (FP32, fixed order).
+__global__ __launch_bounds__(256) void k_colsum(const float* __restrict__ d, uint32_t B, uint32_t N,
+                                                float* __restrict__ db) {
+  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= N) return;
+  float s = 0.f;
+  for (uint32_t b = 0; b < B; ++b) s += d[(uint64_t)b * N + j];
+  db[j] = s;
+}
+
+// Adam on the packed FP32 parameters, then refresh the BF16 weight copies.
+__global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float* __restrict__ g,
+                                              float* __restrict__ m, float* __restrict__ v,
+                                              uint64_t count, float lr, float c1, float c2,
+                                              MLPLayout L, uint16_t* __restrict__ wb) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const float gi = g[i];
+  const float mi = 0.9f * m[i] + 0.1f * gi;
+  const float vi = 0.999f * v[i] + 0.001f * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  const float mh = mi / c1, vh = vi / c2;
+  const float pi = p[i] - lr * mh / (sqrtf(vh) + 1e-8f);
+  p[i] = pi;
+  const int64_t w = L.weight_index(i);
+  if (w >= 0) wb[w] = f2bf(pi);
+}
+
+__global__ __launch_bounds__(256) void k_refresh_bf16(const float* __restrict__ p, uint64_t count,
+                                                      MLPLayout L, uint16_t* __restrict__ wb) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const int64_t w = L.weight_index(i);
+  if (w >= 0) wb[w] = f2bf(p[i]);
+}
+
+// ---------------------------------------------------------------------------
+// Host-side drivers.
+// ---------------------------------------------------------------------------
+hipError_t mlp_refresh(MLPDev& d, hipStream_t st) {
+  const uint64_t cnt = d.L.count();
+  hipLaunchKernelGGL(k_refresh_bf16, dim3((uint32_t)((cnt + 255) / 256)), dim3(256), 0, st, d.p, cnt,
+                     d.L, d.wb);
+  return hipGetLastError();
+}
+
+// Forward for `B` inputs already expanded into d.a0.
+static hipError_t forward_a0(MLPDev& d, uint32_t B, float* logits, hipStream_t st) {
+  const MLPLayout& L = d.L;
+  const int n = (int)L.n, H = (int)L.H;
+  GemmArgs g{};
+  // z1 = a0 W1^T + b1, a1 = bf16(relu(z1))
+  g.A = d.a0; g.sai = n; g.sak = 1;
+  g.B = d.wb + L.wb_W1(); g.sbk = 1; g.sbj = n;
+  g.M = (int)B; g.N = H; g.K = n; g.epi = EPI_BIAS_RELU; g.bias = d.p + L.off_b1();
+  g.Cf = d.z1; g.Cb = d.a1; g.ldc = H;
+  hipError_t e = gemm(g, st);
+  if (e != hipSuccess) return e;
+  // z2 = a1 W2^T + b2, a2 = bf16(relu(z2))
+  g.A = d.a1; g.sai = H; g.sak = 1;
+  g.B = d.wb + L.wb_W2(); g.sbk = 1; g.sbj = H;
+  g.N = H; g.K = H; g.bias = d.p + L.off_b2(); g.Cf = d.z2; g.Cb = d.a2; g.ldc = H;
+  if ((e = gemm(g, st)) != hipSuccess) return e;
+  // logits = a2 W3^T + b3
+  g.A = d.a2; g.sai = H; g.sak = 1;
+  g.B = d.wb + L.wb_W3(); g.sbk = 1; g.sbj = H;
+  g.N = n; g.K = H; g.epi = EPI_BIAS; g.bias = d.p + L.off_b3(); g.Cf = logits; g.Cb = nullptr;
+  g.ldc = n;
+  return gemm(g, st);
+}
+
+hipError_t mlp_forward(MLPDev& d, const uint64_t* x, uint32_t B, float* logits, hipStream_t st) {
+  const uint32_t cnt = B * d.L.n;
+  hipLaunchKernelGGL(k_features, dim3((cnt + 255) / 256), dim3(256), 0, st, x, B, d.L.n, d.a0);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return forward_a0(d, B, logits, st);
+}
+
+hipError_t mlp_loss_grad(MLPDev& d, const uint64_t* x, const uint64_t* t, uint32_t B,
+                         double* loss_acc, hipStream_t st) {
+  const MLPLayout& L = d.L;
+  const int n = (int)L.n, H = (int)L.H;
+  hipError_t e = mlp_forward(d, x, B, d.logits, st);
+  if (e != hipSuccess) return e;
+  const uint32_t cnt = B * L.n;
+  hipLaunchKernelGGL(k_bce_grad, dim3((cnt + 255) / 256), dim3(256), 0, st, d.logits, t, B, L.n,
+                     d.gf, d.gb, loss_acc);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  float* G = d.grad;
+  GemmArgs g{};
+  // dW3[n][H] = gb^T a2
+  g.A = d.gb; g.sai = 1; g.sak = n; g.B = d.a2; g.sbk = H; g.sbj = 1;
+  g.M = n; g.N = H; g.K = (int)B; g.epi = EPI_STORE; g.Cf = G + L.off_W3(); g.Cb = nullptr; g.ldc = H;
+  if ((e = gemm(g, st)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_colsum, dim3((n + 255) / 256), dim3(256), 0, st, d.gf, B, (uint32_t)n,
+                     G + L.off_b3());
+  // dZ2 = (gb W3) * [z2 > 0]
+  g.A = d.gb; g.sai = n; g.sak = 1; g.B = d.wb + L.wb_W3(); g.sbk = H; g.sbj = 1;
+  g.M = (int)B; g.N = H; g.K = n; g.epi = EPI_MASK; g.mask = d.z2; g.Cf = d.dz2; g.Cb = d.gz2; g.ldc = H;
+  if ((e = gemm(g, st)) != hipSuccess) return e;
+  // dW2[H][H] = gz2^T a1
+  g.A = d.gz2; g.sai = 1; g.sak = H; g.B = d.a1; g.sbk = H; g.sbj = 1;
+  g.M = H; g.N = H; g.K = (int)B; g.epi = EPI_STORE; g.Cf = G + L.off_W2(); g.Cb = nullptr; g.ldc = H;
+  if ((e = gemm(g, st)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_colsum, dim3((H + 255) / 256), dim3(256), 0, st, d.dz2, B, (uint32_t)H,
+                     G + L.off_b2());
+  // dZ1 = (gz2 W2) * [z1 > 0]
+  g.A = d.gz2; g.sai = H; g.sak = 1; g.B = d.wb + L.wb_W2(); g.sbk = H; g.sbj = 1;
+  g.M = (int)B; g.N = H; g.K = H; g.epi = EPI_MASK; g.mask = d.z1; g.Cf = d.dz1; g.Cb = d.gz1; g.ldc = H;
+  if ((e = gemm(g, st)) != hipSuccess) return e;
+  // dW1[H][n] = gz1^T a0
+  g.A = d.gz1; g.sai = 1; g.sak = H; g.B = d.a0; g.sbk = n; g.sbj = 1;
+  g.M = H; g.N = n; g.K = (int)B; g.epi = EPI_STORE; g.Cf = G + L.off_W1(); g.Cb = nullptr; g.ldc = n;
+  if ((e = gemm(g, st)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_colsum, dim3((H + 255) / 256), dim3(256), 0, st, d.dz1, B, (uint32_t)H,
+                     G + L.off_b1());
+  return hipGetLastError();
+}
+
+hipError_t mlp_adam(MLPDev& d, float lr, hipStream_t st) {
+  d.step += 1;
+  const float c1 = 1.f - powf(0.9f, (float)d.step);
+  const float c2 = 1.f - powf(0.999f, (float)d.step);
+  const uint64_t cnt = d.L.count();
+  hipLaunchKernelGGL(k_adam, dim3((uint32_t)((cnt + 255) / 256)), dim3(256), 0, st, d.p, d.grad,
+                     d.adam_m, d.adam_v, cnt, lr, c1, c2, d.L, d.wb);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Learned Metropolis chain kernels.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float clip_sigmoid(float l, float lo, float hi) {
+  float p = 1.f / (1.f + expf(-l));
+  return fminf(fmaxf(p, lo), hi);
+}
+
+// log q(y|x) for mask m with flip probabilities from logits l[0..n).
+__device__ double log_q(const float* l, uint64_t m, uint32_t n, float eps, float lo, float hi) {
+  double lp = 0.0;
+  for (uint32_t j = 0; j < n; ++j) {
+    const double p = (double)clip_sigmoid(l[j], lo, hi);
+    lp += ((m >> j) & 1ull) ? log(p) : log1p(-p);
+  }
+  const double single = (__popcll(m) == 1) ? (double)eps / (double)n : 0.0;
+  return log(single + (1.0 - (double)eps) * exp(lp));
+}
+
+// One thread per chain: draw the flip mask of this step from pi(x).
+__global__ void k_learned_mask(LearnedView Lv, uint32_t step) {
+  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= Lv.n_chain) return;
+  const uint32_t n = Lv.n;
+  const uint64_t idx = (uint64_t)c * Lv.n_steps + step;
+  uint64_t m = 0;
+  if (Lv.u_mix[idx] < (double)Lv.eps) {
+    m = 1ull << (Lv.j[idx] % n);
+  } else {
+    const float* lx = Lv.logit_x + (uint64_t)c * n;
+    const double* ub = Lv.u_bits + idx * n;
+    for (uint32_t j = 0; j < n; ++j)
+      if (ub[j] < (double)clip_sigmoid(lx[j], Lv.pi_min, Lv.pi_max)) m |= 1ull << j;
+  }
+  Lv.mask[c] = m;
+  Lv.y[c] = Lv.x[c] ^ m;
+}
+
+// One thread per term, loop over chains: Q_y = Q_x prod_{j in m} P_j (the
+// factors commute), <y|phi_alpha> from (u', mu'), tile sums per chain.
+__global__ __launch_bounds__(256) void k_learned_propose(TermsView T, MetroView Mv,
+                                                         const uint64_t* __restrict__ mask) {
+  __shared__ double2 scratch[4];
+  const uint64_t a = (uint64_t)blockIdx.x * kMetroTile + threadIdx.x;
+  const bool live = a < T.chi;
+  const uint64_t chi = T.chi;
+  const uint32_t n = T.n;
+  uint64_t s = 0, nv = 0, vs = 0;
+  uint32_t w = 0;
+  double w0r = 0, w0i = 0, w1r = 0, w1i = 0;
+  if (live) {
+    const uint64_t v = T.v[a];
+    s = T.s[a];
+    nv = ~v & ((n == 64) ? ~0ull : ((1ull << n) - 1ull));
+    vs = v & s;
+    w = T.omega[a];
+    const double2 b = T.b[a];
+    const int vc = __popcll(v);
+    const double h = 0.70710678118654752440;
+    const double mag = ldexp(1.0, -(vc >> 1)) * ((vc & 1) ? h : 1.0);
+    w0r = b.x * mag;
+    w0i = b.y * mag;
+    w1r = (w0r - w0i) * h;
+    w1i = (w0r + w0i) * h;
+  }
+  for (uint32_t ch = 0; ch < Mv.n_chain; ++ch) {
+    const uint64_t m = uniform64(mask[ch]);
+    double2 val = make_double2(0.0, 0.0);
+    if (m == 0ull) {
+      if (threadIdx.x == 0) Mv.partial[(uint64_t)ch * Mv.n_tiles + blockIdx.x] = val;
+      continue;
+    }
+    const uint32_t cur = uniform32(Mv.parity[ch]);
+    if (live) {
+      const uint64_t wd = Mv.state[cur][(uint64_t)ch * chi + a];
+      uint64_t u = wd & ((1ull << 62) - 1ull);
+      uint32_t mu = (uint32_t)(wd >> 62);
+      uint64_t mm = m;
+      while (mm) {
+        const uint32_t j = (uint32_t)__builtin_ctzll(mm);
+        mm &= mm - 1ull;
+        const uint64_t off = (uint64_t)j * chi + a;
+        u ^= T.F[off];
+        mu += T.gamma[off] + 2u * par64(u & T.M[off]);
+      }
+      mu &= 3u;
+      Mv.state[cur ^ 1u][(uint64_t)ch * chi + a] = u | ((uint64_t)mu << 62);
+      if (!((u ^ s) & nv)) {
+        const uint32_t k = (w + 2u * mu + 4u * par64(u & vs)) & 7u;
+        double re = (k & 1u) ? w1r : w0r, im = (k & 1u) ? w1i : w0i;
+        const uint32_t mq = k >> 1;
+        if (mq & 1u) {
+          const double t = re;
+          re = im;
+          im = t;
+        }
+        if ((mq ^ (mq >> 1)) & 1u) re = -re;
+        if (mq & 2u) im = -im;
+        val = make_double2(re, im);
+      }
+    }
+    for (int o = 32; o >= 1; o >>= 1) {
+      val.x += __shfl_down(val.x, o);
+      val.y += __shfl_down(val.y, o);
+    }
+    __syncthreads();
+    if ((threadIdx.x & 63u) == 0) scratch[threadIdx.x >> 6] = val;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double2 tot = make_double2(0.0, 0.0);
+      for (int q = 0; q < 4; ++q) {
+        tot.x += scratch[q].x;
+        tot.y += scratch[q].y;
+      }
+      Mv.partial[(uint64_t)ch * Mv.n_tiles + blockIdx.x] = tot;
+    }
+  }
+}
+
+// One workgroup per chain: A(y), q(x|y) / q(y|x), accept; on accept adopt y,
+// its amplitude, its logits and the proposal state buffer.
+__global__ __launch_bounds__(256) void k_learned_accept(MetroView Mv, LearnedView Lv, uint32_t step) {
+  __shared__ double part_r[256], part_i[256];
+  const uint32_t ch = blockIdx.x;
+  const uint32_t n = Lv.n;
+  double ar = 0.0, ai = 0.0;
+  for (uint32_t t = threadIdx.x; t < Mv.n_tiles; t += 256u) {
+    const double2 v = Mv.partial[(uint64_t)ch * Mv.n_tiles + t];
+    ar += v.x;
+    ai += v.y;
+  }
+  for (int o = 32; o >= 1; o >>= 1) {
+    ar += __shfl_down(ar, o);
+    ai += __shfl_down(ai, o);
+  }
+  if ((threadIdx.x & 63u) == 0) {
+    part_r[threadIdx.x >> 6] = ar;
+    part_i[threadIdx.x >> 6] = ai;
+  }
+  __syncthreads();
+  __shared__ uint32_t acc_s;
+  if (threadIdx.x == 0) {
+    double yr = 0.0, yi = 0.0;
+    for (int q = 0; q < 4; ++q) {
+      yr += part_r[q];
+      yi += part_i[q];
+    }
+    const uint64_t idx = (uint64_t)ch * Lv.n_steps + step;
+    const uint64_t m = Lv.mask[ch];
+    uint32_t acc = 1u;
+    if (m != 0ull) {
+      const double2 ax = Mv.amp[ch];
+      const double px = ax.x * ax.x + ax.y * ax.y;
+      const double py = yr * yr + yi * yi;
+      const double lq_rev = log_q(Lv.logit_y + (uint64_t)ch * n, m, n, Lv.eps, Lv.pi_min, Lv.pi_max);
+      const double lq_fwd = log_q(Lv.logit_x + (uint64_t)ch * n, m, n, Lv.eps, Lv.pi_min, Lv.pi_max);
+      const double r = (py / px) * exp(lq_rev - lq_fwd);
+      acc = (px > 0.0) && (Lv.u[idx] < r);
+      if (acc) {
+        Mv.x[ch] = Lv.y[ch];
+        Lv.x[ch] = Lv.y[ch];
+        Mv.amp[ch] = make_double2(yr, yi);
+        Mv.parity[ch] ^= 1u;
+      }
+    }
+    acc_s = acc && (m != 0ull);
+    if (Mv.trace) Mv.trace[idx] = Mv.x[ch];
+    if (Mv.accepted) Mv.accepted[idx] = (uint8_t)acc;
+    if (Lv.n_flips) Lv.n_flips[idx] = (uint32_t)__popcll(m);
+  }
+  __syncthreads();
+  if (acc_s)
+    for (uint32_t j = threadIdx.x; j < n; j += 256u)
+      Lv.logit_x[(uint64_t)ch * n + j] = Lv.logit_y[(uint64_t)ch * n + j];
+}
+
+hipError_t launch_learned_steps(const TermsView& T, MetroView& Mv, LearnedView& Lv, MLPDev& d,
+                                uint32_t n_steps, hipStream_t st) {
+  hipError_t e;
+  for (uint32_t t = 0; t < n_steps; ++t) {
+    hipLaunchKernelGGL(k_learned_mask, dim3((Lv.n_chain + 63) / 64), dim3(64), 0, st, Lv, t);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = mlp_forward(d, Lv.y, Lv.n_chain, Lv.logit_y, st)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_learned_propose, dim3(Mv.n_tiles), dim3(kMetroTile), 0, st, T, Mv, Lv.mask);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_learned_accept, dim3(Mv.n_chain), dim3(256), 0, st, Mv, Lv, t);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace chsim

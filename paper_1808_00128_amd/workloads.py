@@ -236,3 +236,33 @@ def config_uneven(seed: int = 1005, n_inst: int = 64, n_x: int = 1024, chi_lo: i
         x = random_bitstrings(n, n_x, rng)
         inst.append(dict(circuit=circ, chi=chi, mode="sparsify", x=x, seed=seed * 1000 + i))
     return dict(name=f"uneven-{n_inst}x", instances=inst, seed=seed)
+
+
+# ---------------------------------------------------------------------------
+# Learned proposal: initial network weights and the random inputs it consumes.
+# ---------------------------------------------------------------------------
+def mlp_init(n: int, hidden: int = 256, seed: int = 7, flip_bias: float = -3.0) -> dict:
+    """Initial parameters of the proposal network n -> hidden -> hidden -> n:
+    weights uniform in +-sqrt(6 / fan_in), hidden biases 0, output bias
+    flip_bias (sigmoid(-3) ~ 0.047 flips per bit before training)."""
+    rng = np.random.default_rng(seed)
+
+    def u(shape, fan_in):
+        b = np.sqrt(6.0 / fan_in)
+        return rng.uniform(-b, b, size=shape).astype(np.float32)
+
+    return {"W1": u((hidden, n), n), "b1": np.zeros(hidden, np.float32),
+            "W2": u((hidden, hidden), hidden), "b2": np.zeros(hidden, np.float32),
+            "W3": (0.1 * u((n, hidden), hidden)).astype(np.float32),
+            "b3": np.full(n, flip_bias, np.float32)}
+
+
+def learned_streams(n: int, n_chain: int, steps: int, rng: np.random.Generator):
+    """Random inputs of the learned proposal per chain and step: the mixture
+    draw, the single-flip bit, one uniform per bit for the flip mask, and the
+    accept uniform."""
+    u_mix = rng.random(size=(n_chain, steps))
+    j = rng.integers(0, n, size=(n_chain, steps), dtype=np.uint32)
+    u_bits = rng.random(size=(n_chain, steps, n))
+    u = rng.random(size=(n_chain, steps))
+    return u_mix, j, u_bits, u

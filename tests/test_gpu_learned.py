@@ -1,0 +1,194 @@
+"""GPU parity of the learned proposal: the BF16 MFMA network against the
+oracle network (same BF16 rounding points, FP32 sums in a different order),
+and the learned Metropolis chain against the oracle chain."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import mlp as OM
+from paper_1808_00128_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1808_00128_amd import binding
+
+    binding.lib()
+    return binding
+
+
+def host_ctx(B, n=8):
+    circ = W.from_list(n, [(W.OP_H, q, 0) for q in range(n)])
+    return B.Context([dict(circuit=circ, chi=1, mode="exact", seed=0)])
+
+
+def varied_params(n, H, seed):
+    p = W.mlp_init(n, H, seed=seed, flip_bias=-1.0)
+    rng = np.random.default_rng(seed + 100)
+    p["b1"] = rng.uniform(-0.3, 0.3, H).astype(np.float32)
+    p["b2"] = rng.uniform(-0.3, 0.3, H).astype(np.float32)
+    p["b3"] = rng.uniform(-2, 0, n).astype(np.float32)
+    p["W3"] = (p["W3"] * 5).astype(np.float32)
+    return p
+
+
+@pytest.mark.parametrize("n,H,batch", [(50, 256, 64), (12, 64, 37), (64, 256, 130), (1, 16, 5)])
+def test_mlp_forward_matches_oracle(B, n, H, batch):
+    say(f"mlp forward n={n} H={H} batch={batch}")
+    ctx = host_ctx(B)
+    p = varied_params(n, H, seed=n)
+    net = B.MLP(ctx, n, H, max(batch, 64), p)
+    ref = OM.MLPRef(p, n, H)
+    x = W.random_bitstrings(n, batch, np.random.default_rng(n))
+    got = net.forward(x)
+    exp, _ = ref.forward(x)
+    exp = np.asarray(exp, np.float32)
+    scale = np.max(np.abs(exp)) + 1e-6
+    assert np.max(np.abs(got - exp)) <= 1e-4 * scale, np.max(np.abs(got - exp)) / scale
+    net.close()
+    ctx.close()
+
+
+@pytest.mark.parametrize("n,H,batch", [(50, 256, 128), (12, 64, 100)])
+def test_mlp_gradients_match_oracle(B, n, H, batch):
+    say(f"mlp gradients n={n} H={H} batch={batch}")
+    ctx = host_ctx(B)
+    p = varied_params(n, H, seed=10 + n)
+    net = B.MLP(ctx, n, H, batch, p)
+    ref = OM.MLPRef(p, n, H)
+    rng = np.random.default_rng(3)
+    x = W.random_bitstrings(n, batch, rng)
+    t = W.random_bitstrings(n, batch, rng) & W.random_bitstrings(n, batch, rng)
+    loss, g = net.loss_grad(x, t)
+    eloss, eg = ref.loss_and_grad(x, t)
+    assert abs(loss - eloss) <= 1e-5 * abs(eloss)
+    for k in OM.PARAM_ORDER:
+        a, e = np.asarray(g[k], np.float64), np.asarray(eg[k], np.float64)
+        assert np.linalg.norm(a - e) <= 3e-3 * np.linalg.norm(e) + 1e-9, (k, np.linalg.norm(a - e) / np.linalg.norm(e))
+        big = np.abs(e) > 1e-2 * np.max(np.abs(e))
+        assert np.all(np.abs(a[big] - e[big]) <= 1e-2 * np.abs(e[big])), k
+    net.close()
+    ctx.close()
+
+
+def test_mlp_training_step_matches_oracle_and_reduces_loss(B):
+    n, H = 20, 64
+    say("mlp training")
+    ctx = host_ctx(B)
+    p = W.mlp_init(n, H, seed=4)
+    net = B.MLP(ctx, n, H, 256, p)
+    ref = OM.MLPRef(p, n, H)
+    rng = np.random.default_rng(5)
+    x = W.random_bitstrings(n, 256, rng)
+    # a learnable target: flip the bits where x has a 1 in a fixed pattern
+    pattern = np.uint64(0b10110011100101001101)
+    t = x & pattern
+    l0 = net.train(x, t, batch=256, epochs=1, lr=1e-3)
+    loss, grads = ref.loss_and_grad(x, t)
+    ref.adam_step(grads, 1e-3)
+    got = net.params()
+    for k in OM.PARAM_ORDER:
+        # one Adam step moves every weight by ~lr; compare the moves
+        d_gpu = got[k] - p[k]
+        d_ref = ref.p[k] - p[k]
+        agree = np.mean(np.sign(d_gpu) == np.sign(d_ref))
+        assert agree > 0.97, (k, agree)
+    losses = net.train(x, t, batch=64, epochs=60, lr=3e-3)
+    assert losses[-1] < 0.5 * l0[0], (l0, losses[-5:])
+    net.close()
+    ctx.close()
+
+
+def chain_setup(B, n, chi, mode, seed):
+    rng = np.random.default_rng(seed)
+    circ = W.random_circuit(n, 10 * n, rng.uniform(0, 2 * np.pi, size=5), rng)
+    spec = dict(circuit=circ, chi=chi, mode=mode, seed=seed)
+    ctx = B.Context([spec])
+    ctx.apply_circuit(circ)
+    T = O.Terms(circ, chi, O.EXACT if mode == "exact" else O.SPARSIFY, seed=seed)
+    return ctx, T, rng
+
+
+def start_states(T, n, count, rng, chi):
+    xs = []
+    while len(xs) < count:
+        a = int(rng.integers(chi))
+        x = T.term(a).sample(int(W.random_bitstrings(n, 1, rng)[0]))
+        if abs(T.amplitudes(np.array([x], np.uint64))[0]) > 0:
+            xs.append(x)
+    return np.array(xs, np.uint64)
+
+
+def test_learned_chain_eps_one_equals_plain_chain(B):
+    n, chi = 8, 32
+    say("learned chain eps=1")
+    ctx, T, rng = chain_setup(B, n, chi, "exact", 11)
+    x0 = start_states(T, n, 4, rng, chi)
+    net = B.MLP(ctx, n, 32, 64, W.mlp_init(n, 32))
+    u_mix, j, u_bits, u = W.learned_streams(n, 4, 150, rng)
+    ctx.metropolis_init(x0)
+    tr, acc, fl, amp = ctx.metropolis_step_learned(net, u_mix, j, u_bits, u, 1.0, 0.01, 0.5)
+    otr, oacc, oamp = T.metropolis(x0, j, u)
+    assert np.array_equal(tr, otr) and np.array_equal(acc, oacc)
+    assert np.all(fl == 1)
+
+
+def test_learned_chain_matches_oracle_until_near_tie(B):
+    n, chi = 8, 32
+    say("learned chain eps=0.2 vs oracle")
+    ctx, T, rng = chain_setup(B, n, chi, "exact", 12)
+    p = varied_params(n, 32, seed=2)
+    net = B.MLP(ctx, n, 32, 64, p)
+    ref = OM.MLPRef(p, n, 32)
+    C_, steps = 4, 120
+    x0 = start_states(T, n, C_, rng, chi)
+    u_mix, j, u_bits, u = W.learned_streams(n, C_, steps, rng)
+    ctx.metropolis_init(x0)
+    tr, acc, fl, amp = ctx.metropolis_step_learned(net, u_mix, j, u_bits, u, 0.2, 0.01, 0.5)
+    otr, oacc, ofl, tie = OM.learned_chain(T, ref, x0, u_mix, j, u_bits, u, 0.2, 0.01, 0.5)
+    compared = 0
+    for c in range(C_):
+        k = int(tie[c])
+        assert np.array_equal(tr[c, :k], otr[c, :k]), c
+        assert np.array_equal(acc[c, :k], oacc[c, :k]), c
+        assert np.array_equal(fl[c, :k], ofl[c, :k]), c
+        compared += k
+    assert compared >= 0.9 * C_ * steps
+    assert fl.mean() > 1.0  # multi-bit moves happen
+
+
+def test_learned_chain_stationary_law(B):
+    """The corrected chain samples P: TV to the exact law at n = 8."""
+    n, chi = 8, 64
+    say("learned chain stationarity")
+    rng = np.random.default_rng(13)
+    circ = W.qaoa_circuit(n, 6, rng)[0]
+    spec = dict(circuit=circ, chi=chi, mode="sparsify", seed=13)
+    ctx = B.Context([spec])
+    ctx.apply_circuit(circ)
+    T = O.Terms(circ, chi, O.SPARSIFY, seed=13)
+    P = np.abs(T.amplitudes(np.arange(2**n, dtype=np.uint64))) ** 2
+    P /= P.sum()
+    p = W.mlp_init(n, 32, flip_bias=-1.5)
+    net = B.MLP(ctx, n, 32, 64, p)
+    C_, steps = 32, 6000
+    x0 = np.array(rng.choice(2**n, size=C_, p=P), np.uint64)
+    u_mix, j, u_bits, u = W.learned_streams(n, C_, steps, rng)
+    ctx.metropolis_init(x0)
+    tr, acc, fl, amp = ctx.metropolis_step_learned(net, u_mix, j, u_bits, u, 0.2, 0.02, 0.5)
+    from paper_1808_00128_amd import stats
+    tv = stats.total_variation(tr[:, 500:].ravel(), P)
+    assert tv < 0.05, tv
