@@ -159,6 +159,159 @@ def bench_metropolis(torch, B, W, stats, steps=1000, n_chain=64, chi=1 << 20):
                          "bytes_per_step": bytes_step}}
 
 
+def run_plain(torch, ctx, x0, jstream, ustream):
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    n_chain, steps = jstream.shape
+    ctx.metropolis_init(x0)
+    j = torch.from_numpy(jstream.astype(np.int32)).to(dev)
+    u = torch.from_numpy(ustream).to(dev)
+    trace = torch.empty((n_chain, steps), dtype=torch.int64, device=dev)
+    acc = torch.empty((n_chain, steps), dtype=torch.uint8, device=dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    ctx.metropolis_step_device(j, u, trace, acc)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return trace.cpu().numpy().view(np.uint64), acc.cpu().numpy(), e0.elapsed_time(e1)
+
+
+def run_learned(torch, ctx, net, x0, streams, eps, pi_min, pi_max):
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    u_mix, jj, u_bits, uu = streams
+    n_chain, steps = jj.shape
+    ctx.metropolis_init(x0)
+    t_umix = torch.from_numpy(u_mix).to(dev)
+    t_j = torch.from_numpy(jj.astype(np.int32)).to(dev)
+    t_ub = torch.from_numpy(np.ascontiguousarray(u_bits)).to(dev)
+    t_u = torch.from_numpy(uu).to(dev)
+    trace = torch.empty((n_chain, steps), dtype=torch.int64, device=dev)
+    acc = torch.empty((n_chain, steps), dtype=torch.uint8, device=dev)
+    flips = torch.empty((n_chain, steps), dtype=torch.int32, device=dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    ctx.metropolis_step_learned_device(net, t_umix, t_j, t_ub, t_u, eps, pi_min, pi_max, trace, acc,
+                                       flips)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return (trace.cpu().numpy().view(np.uint64), acc.cpu().numpy(), flips.cpu().numpy(),
+            e0.elapsed_time(e1))
+
+
+def train_proposal(B, W, ctx, n, trace, burn, delta, epochs=20, hidden=256, batch=1024, lr=1e-3):
+    """Pairs (x_t, x_t ^ x_{t+delta}) from plain chains after burn-in."""
+    xt = trace[:, burn:-delta].ravel()
+    tgt = trace[:, burn:-delta].ravel() ^ trace[:, burn + delta:].ravel()
+    net = B.MLP(ctx, n, hidden, max(batch, trace.shape[0]), W.mlp_init(n, hidden))
+    t0 = time.perf_counter()
+    losses = net.train(xt, tgt, batch=batch, epochs=epochs, lr=lr)
+    t1 = time.perf_counter()
+    return net, {"pairs": int(xt.size), "delta": int(delta), "epochs": epochs, "batch": batch,
+                 "lr": lr, "seconds": t1 - t0, "loss_first": float(losses[0]),
+                 "loss_last": float(losses[-1])}
+
+
+def chain_report(stats, trace, acc, ms, burn, obs, flips=None):
+    tau, win, err = stats.tau_int(obs)
+    ess = obs.size / (2 * tau)
+    out = {"ms_per_step": ms / trace.shape[1], "acceptance": float(acc.mean()), "tau_int": tau,
+           "tau_int_err": err, "ess": ess, "ess_per_s": ess / (ms / 1e3)}
+    if flips is not None:
+        out["mean_flips"] = float(flips[:, burn:].mean())
+    return out
+
+
+def bench_learned(torch, B, W, stats, steps=1000, n_chain=64, chi=1 << 20, eps=0.1,
+                  pi_min=0.002, pi_max=0.5):
+    """QAOA n = 50, chi = 2^20: plain chains, proposal trained on them, learned chains."""
+    cfg = W.config_qaoa(chi=chi, n_chain=n_chain, steps=steps)
+    circ = cfg["circuit"]
+    n = circ.n
+    ctx = B.Context([cfg])
+    ctx.set_evolve_lanes(-1)
+    ctx.apply_circuit(circ)
+    rng = np.random.default_rng(cfg["seed"] + 1)
+    x0 = start_points(ctx, n, chi, n_chain, rng)
+    burn = steps // 5
+    tr, ac, ms = run_plain(torch, ctx, x0, cfg["jstream"], cfg["ustream"])
+    cost = stats.qaoa_cost(tr[:, burn:], cfg["triples"], cfg["d"])
+    plain = chain_report(stats, tr, ac, ms, burn, cost)
+    bytes_step = chi * (n_chain * (8 + 8 + 17) + 33)
+    achieved = bytes_step * steps / (ms / 1e3) / 1e9
+    plain["roofline"] = {"bound": "hbm", "kernel": "k_metro_propose + k_metro_accept",
+                         "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
+                         "frac": round(achieved / 8000.0, 4), "traffic": None,
+                         "bytes_per_step": bytes_step}
+    delta = max(1, int(round(plain["tau_int"])))
+    net, train = train_proposal(B, W, ctx, n, tr, burn, delta)
+    streams = W.learned_streams(n, n_chain, steps, np.random.default_rng(cfg["seed"] + 2))
+    ltr, lac, lfl, lms = run_learned(torch, ctx, net, x0, streams, eps, pi_min, pi_max)
+    lcost = stats.qaoa_cost(ltr[:, burn:], cfg["triples"], cfg["d"])
+    learned = chain_report(stats, ltr, lac, lms, burn, lcost, lfl)
+    lbytes = chi * (n_chain * (16 + float(lfl.mean()) * 17) + 33)
+    lach = lbytes * steps / (lms / 1e3) / 1e9
+    learned["roofline"] = {"bound": "hbm", "kernel": "k_learned_propose + network + accept",
+                           "achieved": round(lach, 1), "peak": 8000.0, "unit": "GB/s",
+                           "frac": round(lach / 8000.0, 4), "traffic": None,
+                           "bytes_per_step": lbytes}
+    net.close()
+    ctx.close()
+    return {"plain": dict(plain, mean_cost=float(cost.mean())),
+            "learned": dict(learned, mean_cost=float(lcost.mean()), eps=eps, pi_min=pi_min,
+                            pi_max=pi_max, network="50-256-256-50 ReLU, BF16 MFMA", training=train),
+            "ess_per_s_learned_over_plain": learned["ess_per_s"] / plain["ess_per_s"]}
+
+
+def bench_matched_tv(torch, B, W, stats, n=12, triples=16, chi=1 << 16, n_chain=64, steps=3200,
+                     eps=0.1, pi_min=0.002, pi_max=0.5, target=0.05):
+    """n = 12 twin of the QAOA workload: steps and seconds until the pooled
+    samples of 64 chains are within `target` total variation of the exact law
+    (all 4096 amplitudes), plain vs learned proposal."""
+    rng = np.random.default_rng(2012)
+    circ = W.qaoa_circuit(n, triples, rng)[0]
+    spec = dict(circuit=circ, chi=chi, mode="sparsify", seed=2012)
+    ctx = B.Context([spec])
+    ctx.apply_circuit(circ)
+    P = np.abs(ctx.amplitudes(np.arange(2**n, dtype=np.uint64))) ** 2
+    P /= P.sum()
+    x0 = np.array(rng.choice(2**n, size=n_chain, p=P), np.uint64)  # start in equilibrium
+    j, u = W.metropolis_streams(n, n_chain, steps, rng)
+    tr, ac, ms = run_plain(torch, ctx, x0, j, u)
+    obs = tr.astype(np.float64)
+    tau, _, _ = stats.tau_int(np.array([bin(int(v)).count("1") for v in tr.ravel()],
+                                       np.float64).reshape(tr.shape))
+    net, train = train_proposal(B, W, ctx, n, tr, 0, max(1, int(round(tau))), epochs=30, hidden=128)
+    streams = W.learned_streams(n, n_chain, steps, rng)
+    ltr, lac, lfl, lms = run_learned(torch, ctx, net, x0, streams, eps, pi_min, pi_max)
+    net.close()
+    ctx.close()
+    checkpoints = [25, 50, 100, 200, 400, 800, 1600, 3200]
+
+    def curve(t):
+        return {c: stats.total_variation(t[:, :c].ravel(), P) for c in checkpoints if c <= steps}
+
+    cp, cl = curve(tr), curve(ltr)
+
+    def first(c):
+        hit = [k for k, v in c.items() if v <= target]
+        return min(hit) if hit else None
+
+    sp, sl = first(cp), first(cl)
+    per_p, per_l = ms / steps, lms / steps
+    return {"workload": f"qaoa-n{n}-{triples}triples-chi{chi}, {n_chain} chains started from P",
+            "tv_target": target,
+            "plain": {"tv_by_steps": cp, "steps_to_target": sp, "ms_per_step": per_p,
+                      "seconds_to_target": (sp * per_p / 1e3) if sp else None,
+                      "acceptance": float(ac.mean())},
+            "learned": {"tv_by_steps": cl, "steps_to_target": sl, "ms_per_step": per_l,
+                        "seconds_to_target": (sl * per_l / 1e3) if sl else None,
+                        "acceptance": float(lac.mean()), "mean_flips": float(lfl.mean()),
+                        "training": train}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -301,7 +454,8 @@ def main():
     if "metropolis" in sections:
         from paper_1808_00128_amd import stats
 
-        result["metropolis"] = {"plain": bench_metropolis(torch, B, W, stats)}
+        result["metropolis"] = bench_learned(torch, B, W, stats)
+        result["metropolis"]["matched_tv"] = bench_matched_tv(torch, B, W, stats)
     if not args.no_cpu_baseline:
         threads = max(1, min(16, os.cpu_count() or 1))
         result["cpu_baseline"] = cpu_baseline(cfg, args.cpu_sample_terms, threads)
