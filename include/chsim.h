@@ -124,6 +124,27 @@ chsim_status chsim_apply_clifford(chsim_ctx* ctx, uint32_t inst, const chsim_gat
 chsim_status chsim_amplitudes(chsim_ctx* ctx, uint32_t inst, const uint64_t* x, size_t n_x,
                               double* out, uint32_t flags, void* stream);
 
+/* One request of a batched amplitude call: out[2i], out[2i+1] = <x_i|psi_inst>
+ * for i < n_x.  x and out are host or device pointers as the call's flags say;
+ * requests may name the same instance; output arrays must not overlap. */
+typedef struct chsim_amp_request {
+  uint32_t inst;
+  uint32_t reserved;
+  const uint64_t* x;
+  size_t n_x;
+  double* out;
+} chsim_amp_request;
+
+/* chsim_amplitudes for several requests in one launch (instances of
+ * different n, chi and bitstring counts share one persistent grid that pulls
+ * (request, term range, bitstring chunk) work items), same formula, flags and
+ * results as one call per request.  Host bitstring arrays are checked as in
+ * chsim_amplitudes.  EINVAL: n_req == 0, a request with a bad instance, a null
+ * array or n_x == 0.  The plan is cached in the context: a context must not be
+ * used from two streams at once. */
+chsim_status chsim_amplitudes_batch(chsim_ctx* ctx, const chsim_amp_request* reqs, size_t n_req,
+                                    uint32_t flags, void* stream);
+
 /* Norm estimation with equatorial states phi_A, A in M_n (Eq. (eqa1)):
  * A_off[l*n + a] = row a of the off-diagonal part of A_l (bit b = A_ab; bit a
  * ignored), A_diag[l*n + a] = A_aa in {0..3}.  overlap[2l..2l+1] = <phi_{A_l}|psi>

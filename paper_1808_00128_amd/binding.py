@@ -25,7 +25,8 @@ CHSIM_TUNE_EVOLVE_LANES = 1
 MAX_BRANCH = 8
 
 EXPORTED = [
-    "chsim_terms_init", "chsim_terms_reset", "chsim_apply_clifford", "chsim_amplitudes", "chsim_inner_products",
+    "chsim_terms_init", "chsim_terms_reset", "chsim_apply_clifford", "chsim_amplitudes",
+    "chsim_amplitudes_batch", "chsim_inner_products",
     "chsim_metropolis_init", "chsim_metropolis_step", "chsim_sample_terms", "chsim_get_terms",
     "chsim_set_terms", "chsim_decompose_phase", "chsim_set_tuning", "chsim_get_tuning",
     "chsim_instance_info", "chsim_destroy", "chsim_mlp_create", "chsim_mlp_destroy",
@@ -54,6 +55,11 @@ class Decomp(C.Structure):
 class Instance(C.Structure):
     _fields_ = [("n", C.c_uint32), ("n_slot", C.c_uint32), ("slot_decomp", C.POINTER(Decomp)),
                 ("chi", C.c_uint64), ("mode", C.c_uint32), ("seed", C.c_uint64)]
+
+
+class AmpRequest(C.Structure):
+    _fields_ = [("inst", C.c_uint32), ("reserved", C.c_uint32), ("x", C.c_void_p),
+                ("n_x", C.c_size_t), ("out", C.c_void_p)]
 
 
 class LearnedArgs(C.Structure):
@@ -282,6 +288,38 @@ class Context:
         _check(lib().chsim_amplitudes(self._h, inst, px, x.numel(), po, flags | CHSIM_DEVICE_PTRS,
                                       _stream(stream)))
         return out
+
+    def amplitudes_batch(self, requests, fp32c=False, stream=None):
+        """Several (inst, x) requests in one launch.  All numpy uint64 -> list
+        of numpy complex128; all CUDA int64 tensors -> list of CUDA float64
+        tensors [n_x, 2] (asynchronous)."""
+        flags = CHSIM_FP32C if fp32c else CHSIM_FP64
+        reqs = (AmpRequest * len(requests))()
+        keep, outs = [], []
+        host = all(isinstance(x, np.ndarray) for _, x in requests)
+        if not host:
+            import torch
+        for k, (inst, x) in enumerate(requests):
+            if host:
+                x = np.ascontiguousarray(x, np.uint64)
+                o = np.zeros(2 * x.size)
+                n_x = x.size
+            else:
+                o = torch.empty((x.numel(), 2), dtype=torch.float64, device=x.device)
+                n_x = x.numel()
+            px, f1 = _ptr(x)
+            po, f2 = _ptr(o)
+            if not host and not (f1 and f2):
+                raise ValueError("torch inputs must be on the GPU")
+            keep.append(x)
+            outs.append(o)
+            reqs[k] = AmpRequest(inst, 0, px.value, n_x, po.value)
+        if not host:
+            flags |= CHSIM_DEVICE_PTRS
+        _check(lib().chsim_amplitudes_batch(self._h, reqs, len(requests), flags, _stream(stream)))
+        if host:
+            return [o[0::2] + 1j * o[1::2] for o in outs]
+        return outs
 
     # ---- step (c) ----
     def inner_products(self, Aoff, Adiag, inst=0, stream=None):

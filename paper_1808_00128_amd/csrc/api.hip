@@ -125,6 +125,13 @@ struct chsim_ctx {
   DevBuf<uint8_t> adiag;
   DevBuf<double> eta;
   DevBuf<double> eta_sum;
+  // Amplitude work queue: device copies of the last plan, and its host key.
+  DevBuf<AmpInst> amp_insts;
+  DevBuf<AmpItem> amp_items;
+  DevBuf<uint64_t> amp_prefix;
+  DevBuf<uint32_t> amp_counter;
+  std::vector<AmpInst> amp_key;
+  uint32_t amp_n_items = 0;
 };
 
 namespace {
@@ -408,6 +415,83 @@ chsim_status chsim_apply_clifford(chsim_ctx* ctx, uint32_t inst, const chsim_gat
   return check_err_flag(ctx, s, "apply_clifford");
 }
 
+namespace {
+
+constexpr uint32_t kAmpTargetItems = 2048;  // work items per launch to aim for
+
+struct AmpReq {
+  uint32_t inst;
+  const uint64_t* x;  // device
+  uint32_t n_x;
+  double2* out;       // device
+};
+
+// Plan, upload the plan if it differs from the last one, and launch.
+chsim_status run_amplitudes(chsim_ctx* ctx, const std::vector<AmpReq>& reqs, bool fp32c, hipStream_t s) {
+  std::vector<AmpRequestPlan> plan;
+  uint32_t n_max = 1;
+  uint64_t total_x = 0;
+  for (const auto& r : reqs) {
+    const Instance& I = ctx->inst[r.inst];
+    plan.push_back(AmpRequestPlan{I.n, r.n_x, I.chi});
+    n_max = std::max(n_max, I.n);
+    total_x += r.n_x;
+  }
+  std::vector<AmpItem> items;
+  std::vector<uint32_t> tpr, nr;
+  amp_plan(plan, kAmpTargetItems, items, tpr, nr);
+  size_t part = 0;
+  for (size_t q = 0; q < reqs.size(); ++q) part += (size_t)nr[q] * reqs[q].n_x;
+  HIP_TRY(ctx->partial.ensure(part));
+  std::vector<AmpInst> insts(reqs.size());
+  std::vector<uint64_t> prefix(reqs.size() + 1, 0);
+  size_t off = 0;
+  for (size_t q = 0; q < reqs.size(); ++q) {
+    AmpInst a;
+    std::memset(&a, 0, sizeof a);
+    a.T = ctx->inst[reqs[q].inst].view();
+    a.x = reqs[q].x;
+    a.partial = ctx->partial.p + off;
+    a.out = reqs[q].out;
+    a.n_x = reqs[q].n_x;
+    a.tiles_per_range = tpr[q];
+    a.n_ranges = nr[q];
+    insts[q] = a;
+    off += (size_t)nr[q] * reqs[q].n_x;
+    prefix[q + 1] = prefix[q] + reqs[q].n_x;
+  }
+  const bool same = insts.size() == ctx->amp_key.size() &&
+                    std::memcmp(insts.data(), ctx->amp_key.data(), insts.size() * sizeof(AmpInst)) == 0;
+  if (!same) {
+    HIP_TRY(ctx->amp_insts.ensure(insts.size()));
+    HIP_TRY(ctx->amp_items.ensure(items.size()));
+    HIP_TRY(ctx->amp_prefix.ensure(prefix.size()));
+    HIP_TRY(ctx->amp_counter.ensure(1));
+    HIP_TRY(hipMemcpyAsync(ctx->amp_insts.p, insts.data(), insts.size() * sizeof(AmpInst),
+                           hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(ctx->amp_items.p, items.data(), items.size() * sizeof(AmpItem),
+                           hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(ctx->amp_prefix.p, prefix.data(), prefix.size() * sizeof(uint64_t),
+                           hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));  // the host vectors die with this call
+    ctx->amp_key = insts;
+    ctx->amp_n_items = (uint32_t)items.size();
+  }
+  HIP_TRY(launch_amp_items(ctx->amp_insts.p, ctx->amp_items.p, ctx->amp_n_items, ctx->amp_counter.p,
+                           n_max, fp32c, ctx->amp_prefix.p, (uint32_t)reqs.size(), total_x, s));
+  return CHSIM_OK;
+}
+
+chsim_status check_bits(const Instance& I, const uint64_t* x, size_t n_x, size_t req) {
+  if (I.n >= 64) return CHSIM_OK;
+  const uint64_t bad = ~((1ull << I.n) - 1ull);
+  for (size_t i = 0; i < n_x; ++i)
+    if (x[i] & bad) return fail(CHSIM_EINVAL, "request %zu: bitstring %zu has bits >= n = %u", req, i, I.n);
+  return CHSIM_OK;
+}
+
+}  // namespace
+
 chsim_status chsim_amplitudes(chsim_ctx* ctx, uint32_t inst, const uint64_t* x, size_t n_x,
                               double* out, uint32_t flags, void* stream) {
   g_err.clear();
@@ -417,11 +501,7 @@ chsim_status chsim_amplitudes(chsim_ctx* ctx, uint32_t inst, const uint64_t* x, 
   if (n_x > 0xFFFFFFFFull) return fail(CHSIM_EINVAL, "too many bitstrings");
   Instance& I = ctx->inst[inst];
   const bool dev = flags & CHSIM_DEVICE_PTRS;
-  if (!dev && I.n < 64) {
-    const uint64_t bad = ~((1ull << I.n) - 1ull);
-    for (size_t i = 0; i < n_x; ++i)
-      if (x[i] & bad) return fail(CHSIM_EINVAL, "bitstring %zu has bits >= n = %u", i, I.n);
-  }
+  if (!dev && (st = check_bits(I, x, n_x, 0))) return st;
   HIP_TRY(hipSetDevice(ctx->device));
   hipStream_t s = as_stream(stream);
   st = ensure_materialised(I, s);
@@ -429,16 +509,66 @@ chsim_status chsim_amplitudes(chsim_ctx* ctx, uint32_t inst, const uint64_t* x, 
   const uint64_t* xd;
   st = stage_in(ctx->xbuf, x, n_x, dev, s, &xd);
   if (st) return st;
-  HIP_TRY(ctx->partial.ensure(amp_partial_elems(I.view(), (uint32_t)n_x)));
   double2* outd;
   if (dev) outd = reinterpret_cast<double2*>(out);
   else {
     HIP_TRY(ctx->out.ensure(n_x));
     outd = ctx->out.p;
   }
-  HIP_TRY(launch_amplitudes(I.view(), xd, (uint32_t)n_x, (flags & CHSIM_FP32C) != 0, ctx->partial.p, outd, s));
+  st = run_amplitudes(ctx, {AmpReq{inst, xd, (uint32_t)n_x, outd}}, (flags & CHSIM_FP32C) != 0, s);
+  if (st) return st;
   if (!dev) {
     HIP_TRY(hipMemcpyAsync(out, outd, n_x * sizeof(double2), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+  return CHSIM_OK;
+}
+
+chsim_status chsim_amplitudes_batch(chsim_ctx* ctx, const chsim_amp_request* reqs, size_t n_req,
+                                    uint32_t flags, void* stream) {
+  g_err.clear();
+  if (!ctx) return fail(CHSIM_EINVAL, "null context");
+  if (n_req == 0 || !reqs) return fail(CHSIM_EINVAL, "empty or null request array");
+  if (n_req > 0xFFFFFFFFull) return fail(CHSIM_EINVAL, "too many requests");
+  const bool dev = flags & CHSIM_DEVICE_PTRS;
+  size_t total = 0;
+  for (size_t q = 0; q < n_req; ++q) {
+    const chsim_amp_request& r = reqs[q];
+    if (r.inst >= ctx->inst.size()) return fail(CHSIM_EINVAL, "request %zu: instance %u out of range", q, r.inst);
+    if (r.n_x == 0 || !r.x || !r.out) return fail(CHSIM_EINVAL, "request %zu: empty or null arrays", q);
+    if (r.n_x > 0xFFFFFFFFull) return fail(CHSIM_EINVAL, "request %zu: too many bitstrings", q);
+    if (!dev) {
+      chsim_status st = check_bits(ctx->inst[r.inst], r.x, r.n_x, q);
+      if (st) return st;
+    }
+    total += r.n_x;
+  }
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t s = as_stream(stream);
+  for (size_t q = 0; q < n_req; ++q) {
+    chsim_status st = ensure_materialised(ctx->inst[reqs[q].inst], s);
+    if (st) return st;
+  }
+  std::vector<AmpReq> rq(n_req);
+  if (dev) {
+    for (size_t q = 0; q < n_req; ++q)
+      rq[q] = AmpReq{reqs[q].inst, reqs[q].x, (uint32_t)reqs[q].n_x, reinterpret_cast<double2*>(reqs[q].out)};
+  } else {
+    HIP_TRY(ctx->xbuf.ensure(total));
+    HIP_TRY(ctx->out.ensure(total));
+    size_t off = 0;
+    for (size_t q = 0; q < n_req; ++q) {
+      HIP_TRY(hipMemcpyAsync(ctx->xbuf.p + off, reqs[q].x, reqs[q].n_x * sizeof(uint64_t),
+                             hipMemcpyHostToDevice, s));
+      rq[q] = AmpReq{reqs[q].inst, ctx->xbuf.p + off, (uint32_t)reqs[q].n_x, ctx->out.p + off};
+      off += reqs[q].n_x;
+    }
+  }
+  chsim_status st = run_amplitudes(ctx, rq, (flags & CHSIM_FP32C) != 0, s);
+  if (st) return st;
+  if (!dev) {
+    for (size_t q = 0; q < n_req; ++q)
+      HIP_TRY(hipMemcpyAsync(reqs[q].out, rq[q].out, reqs[q].n_x * sizeof(double2), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
   }
   return CHSIM_OK;
@@ -858,6 +988,10 @@ chsim_status chsim_destroy(chsim_ctx* ctx) {
   ctx->err.release();
   ctx->xbuf.release();
   ctx->partial.release();
+  ctx->amp_insts.release();
+  ctx->amp_items.release();
+  ctx->amp_prefix.release();
+  ctx->amp_counter.release();
   ctx->out.release();
   ctx->aoff.release();
   ctx->adiag.release();

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <vector>
 
 #include "chsim.h"
 
@@ -95,10 +96,38 @@ hipError_t launch_set_zero(const TermsView& T, hipStream_t st);
 hipError_t launch_sample(const TermsView& T, const uint64_t* alpha, const uint64_t* flips,
                          uint64_t* x_out, uint32_t count, hipStream_t st);
 
-// Amplitudes: partial[tile * n_x + i] for every 64-term tile, then a reduction.
-size_t amp_partial_elems(const TermsView& T, uint32_t n_x);
-hipError_t launch_amplitudes(const TermsView& T, const uint64_t* x, uint32_t n_x, bool fp32c,
-                             double2* partial, double2* out, hipStream_t st);
+// Amplitudes.  One request = one instance's terms and its bitstrings; the
+// request's terms are cut into ranges of `tiles_per_range` 64-term tiles and
+// its bitstrings into chunks, and each (range, chunk) is one work item that a
+// persistent workgroup pulls from a queue.  partial[range * n_x + i] holds the
+// range's sum; a second kernel adds the ranges in a fixed order into out.
+struct AmpInst {
+  TermsView T;
+  const uint64_t* x;
+  double2* partial;  // [n_ranges][n_x]
+  double2* out;      // [n_x]
+  uint32_t n_x;
+  uint32_t tiles_per_range;
+  uint32_t n_ranges;
+  uint32_t pad;
+};
+struct AmpItem {
+  uint32_t inst, range, x0, x1;
+};
+struct AmpRequestPlan {
+  uint32_t n;
+  uint32_t n_x;
+  uint64_t chi;
+};
+// Cut the requests into work items (sorted by estimated cost, largest first).
+void amp_plan(const std::vector<AmpRequestPlan>& reqs, uint32_t target_items,
+              std::vector<AmpItem>& items, std::vector<uint32_t>& tiles_per_range,
+              std::vector<uint32_t>& n_ranges);
+// Reset the queue counter, run the persistent kernel, reduce.  prefix_d[q] =
+// bitstrings of requests before q (n_inst + 1 entries).
+hipError_t launch_amp_items(const AmpInst* insts_d, const AmpItem* items_d, uint32_t n_items,
+                            uint32_t* counter, uint32_t n_max, bool fp32c, const uint64_t* prefix_d,
+                            uint32_t n_inst, uint64_t total_x, hipStream_t st);
 
 // Inner products with equatorial states.
 size_t inner_partial_elems(const TermsView& T, uint32_t L, uint32_t* n_blocks);

@@ -257,6 +257,93 @@ def test_amplitudes_config_full_size_sampled(B):
     assert np.max(np.abs(a32[pick] - ref)) / rms < TOL32
 
 
+def _instance_with_strings(B, n, chi, n_x, seed, rng):
+    circ = W.random_circuit(n, 30 * n, rng.uniform(0, 2 * np.pi, size=6), rng)
+    spec = dict(circuit=circ, chi=chi, mode="sparsify", seed=seed)
+    T = O.Terms(circ, chi, O.SPARSIFY, seed=seed)
+    alpha = rng.integers(0, chi, size=n_x)
+    flips = W.random_bitstrings(n, n_x, rng)
+    xs = np.array([T.term(int(a)).sample(int(f)) for a, f in zip(alpha, flips)], np.uint64)
+    xs[::3] = W.random_bitstrings(n, n_x, rng)[::3]
+    return spec, T, xs
+
+
+def test_amplitudes_batch_mixed_instances(B):
+    """One batched launch over instances of different n, chi and string
+    counts (one instance requested twice) against the oracle, host and device
+    pointers."""
+    import torch
+
+    rng = np.random.default_rng(700)
+    shapes = [(1, 3, 2), (7, 65, 1), (20, 1000, 1001), (40, 64, 333), (62, 130, 77), (33, 3000, 600)]
+    specs, Ts, xss = [], [], []
+    for k, (n, chi, n_x) in enumerate(shapes):
+        sp, T, xs = _instance_with_strings(B, n, chi, n_x, 700 + k, rng)
+        specs.append(sp)
+        Ts.append(T)
+        xss.append(xs)
+    say("batched amplitudes: 6 mixed instances")
+    ctx = B.Context(specs)
+    for k, sp in enumerate(specs):
+        ctx.apply_circuit(sp["circuit"], inst=k)
+    reqs = [(k, xss[k]) for k in range(len(shapes))] + [(2, xss[2][::-1].copy())]
+    refs = [T.amplitudes(xs) for T, xs in zip(Ts, xss)] + [Ts[2].amplitudes(xss[2][::-1].copy())]
+    a64 = ctx.amplitudes_batch(reqs)
+    a32 = ctx.amplitudes_batch(reqs, fp32c=True)
+    for k in range(len(reqs)):
+        assert normwise(a64[k], refs[k]) < TOL64, k
+        assert normwise(a32[k], refs[k]) < TOL32, k
+    dev = ctx.amplitudes_batch([(k, torch.from_numpy(x.view(np.int64)).cuda()) for k, x in reqs])
+    torch.cuda.synchronize()
+    for k in range(len(reqs)):
+        d = dev[k].cpu().numpy()
+        assert normwise(d[:, 0] + 1j * d[:, 1], refs[k]) < TOL64, k
+    # a single-request batch and the plain call agree with the oracle alike
+    one = ctx.amplitudes_batch([(5, xss[5])])[0]
+    assert normwise(one, refs[5]) < TOL64
+
+
+def test_amplitudes_batch_rejects_bad_requests(B):
+    circ = W.from_list(4, [(W.OP_H, 0, 0)])
+    ctx = B.Context([dict(circuit=circ, chi=1, mode="exact", seed=0)])
+    with pytest.raises(B.ChsimError, match="EINVAL"):
+        ctx.amplitudes_batch([(1, np.zeros(3, np.uint64))])
+    with pytest.raises(B.ChsimError, match="EINVAL"):
+        ctx.amplitudes_batch([(0, np.array([1 << 4], np.uint64))])
+    with pytest.raises(B.ChsimError, match="EINVAL"):
+        ctx.amplitudes_batch([(0, np.zeros(0, np.uint64))])
+
+
+@pytest.mark.slow
+def test_amplitudes_batch_uneven_config(B):
+    """64 instances (n 20..60, chi 2^10..2^20, 1024 strings each) in one
+    launch: the smallest-chi instances against the oracle on sampled strings,
+    FP32C against FP64 everywhere."""
+    cfg = W.config_uneven()
+    insts = cfg["instances"]
+    say("uneven config: evolve 64 instances")
+    ctx = B.Context(insts)
+    for k, sp in enumerate(insts):
+        ctx.apply_circuit(sp["circuit"], inst=k)
+    reqs = [(k, sp["x"]) for k, sp in enumerate(insts)]
+    say("uneven config: batched amplitudes")
+    a64 = ctx.amplitudes_batch(reqs)
+    a32 = ctx.amplitudes_batch(reqs, fp32c=True)
+    for k in range(len(insts)):
+        assert normwise(a32[k], a64[k]) < TOL32, k
+    rng = np.random.default_rng(5)
+    small = np.argsort([sp["chi"] for sp in insts])[:6]
+    for k in small:
+        sp = insts[k]
+        say(f"uneven config: oracle instance {k} n={sp['circuit'].n} chi={sp['chi']}")
+        T = O.Terms(sp["circuit"], sp["chi"], O.SPARSIFY, seed=sp["seed"])
+        pick = rng.choice(sp["x"].size, size=64, replace=False)
+        ref = T.amplitudes(sp["x"][pick])
+        rms = np.sqrt(np.mean(np.abs(a64[k]) ** 2))
+        assert np.max(np.abs(a64[k][pick] - ref)) / rms < TOL64, k
+        assert np.max(np.abs(a32[k][pick] - ref)) / rms < TOL32, k
+
+
 # ---------------------------------------------------------------------------
 # Step (c): inner products and the norm estimate.
 # ---------------------------------------------------------------------------

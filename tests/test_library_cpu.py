@@ -76,6 +76,7 @@ def test_terms_init_rejects_bad_instances(n, chi, mode):
 def test_null_context_rejected():
     L = B.lib()
     assert L.chsim_amplitudes(None, 0, None, 0, None, 0, None) == B.CHSIM_EINVAL
+    assert L.chsim_amplitudes_batch(None, None, 0, 0, None) == B.CHSIM_EINVAL
     assert L.chsim_destroy(None) == B.CHSIM_OK
 
 
