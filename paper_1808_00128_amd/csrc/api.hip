@@ -63,6 +63,7 @@ struct Instance {
   uint64_t chi = 0, seed = 0;
   double l1 = 1.0;
   bool at_zero = true;  // every term is |0^n> and the store holds nothing yet
+  bool amp_ready = false;  // the amplitude prologue output matches the terms
   EvolveShape shape;    // evolution mapping (0 = default for n)
   bool autotune = false;  // time every shape at the next from-|0^n> evolution
   float tuned_ms[4] = {0, 0, 0, 0};  // per lanes 8, 16, 32, 64 (0 = not timed)
@@ -72,6 +73,9 @@ struct Instance {
   DevBuf<uint8_t> gamma, omega, branch;
   DevBuf<double2> b;
   DevBuf<SlotTable> slots;
+  // amplitude prologue output
+  DevBuf<uint64_t> acrow;
+  DevBuf<AmpTerm> acst;
   // metropolis
   uint32_t n_chain = 0;
   DevBuf<uint64_t> mstate0, mstate1, mx, mtrace;
@@ -105,6 +109,7 @@ struct Instance {
     F.release(); G.release(); M.release(); v.release(); s.release();
     gamma.release(); omega.release(); branch.release(); b.release();
     slots.release();
+    acrow.release(); acst.release();
     mstate0.release(); mstate1.release(); mx.release(); mtrace.release();
     mparity.release(); mj.release(); mamp.release(); mpartial.release(); mu.release(); macc.release();
     ly.release(); lmask.release(); logit_x.release(); logit_y.release(); lumix.release();
@@ -238,6 +243,7 @@ chsim_status ensure_materialised(Instance& I, hipStream_t st) {
   if (!I.at_zero) return CHSIM_OK;
   HIP_TRY(launch_set_zero(I.view(), st));
   I.at_zero = false;
+  I.amp_ready = false;
   return CHSIM_OK;
 }
 
@@ -328,6 +334,7 @@ chsim_status chsim_terms_reset(chsim_ctx* ctx, uint32_t inst, uint64_t seed, voi
   const double scale = I.l1 / (double)I.chi;
   HIP_TRY(launch_choose(I.view(), I.slots.p, I.mode, I.seed, scale, as_stream(stream)));
   I.at_zero = true;
+  I.amp_ready = false;
   I.n_chain = 0;
   return CHSIM_OK;
 }
@@ -412,6 +419,7 @@ chsim_status chsim_apply_clifford(chsim_ctx* ctx, uint32_t inst, const chsim_gat
                           ctx->err.p, I.shape, s));
   }
   I.at_zero = false;
+  I.amp_ready = false;
   return check_err_flag(ctx, s, "apply_clifford");
 }
 
@@ -426,15 +434,27 @@ struct AmpReq {
   double2* out;       // device
 };
 
+// Run the amplitude prologue of an instance if its terms changed since.
+chsim_status ensure_amp_prep(Instance& I, hipStream_t s) {
+  if (I.amp_ready) return CHSIM_OK;
+  HIP_TRY(I.acrow.ensure((size_t)I.n * I.chi));
+  HIP_TRY(I.acst.ensure(I.chi));
+  HIP_TRY(launch_amp_prep(I.view(), I.acrow.p, I.acst.p, s));
+  I.amp_ready = true;
+  return CHSIM_OK;
+}
+
 // Plan, upload the plan if it differs from the last one, and launch.
 chsim_status run_amplitudes(chsim_ctx* ctx, const std::vector<AmpReq>& reqs, bool fp32c, hipStream_t s) {
+  for (const auto& r : reqs) {
+    chsim_status st = ensure_amp_prep(ctx->inst[r.inst], s);
+    if (st) return st;
+  }
   std::vector<AmpRequestPlan> plan;
-  uint32_t n_max = 1;
   uint64_t total_x = 0;
   for (const auto& r : reqs) {
     const Instance& I = ctx->inst[r.inst];
     plan.push_back(AmpRequestPlan{I.n, r.n_x, I.chi});
-    n_max = std::max(n_max, I.n);
     total_x += r.n_x;
   }
   std::vector<AmpItem> items;
@@ -449,7 +469,10 @@ chsim_status run_amplitudes(chsim_ctx* ctx, const std::vector<AmpReq>& reqs, boo
   for (size_t q = 0; q < reqs.size(); ++q) {
     AmpInst a;
     std::memset(&a, 0, sizeof a);
-    a.T = ctx->inst[reqs[q].inst].view();
+    Instance& I = ctx->inst[reqs[q].inst];
+    a.T = I.view();
+    a.crow = I.acrow.p;
+    a.cst = I.acst.p;
     a.x = reqs[q].x;
     a.partial = ctx->partial.p + off;
     a.out = reqs[q].out;
@@ -478,7 +501,7 @@ chsim_status run_amplitudes(chsim_ctx* ctx, const std::vector<AmpReq>& reqs, boo
     ctx->amp_n_items = (uint32_t)items.size();
   }
   HIP_TRY(launch_amp_items(ctx->amp_insts.p, ctx->amp_items.p, ctx->amp_n_items, ctx->amp_counter.p,
-                           n_max, fp32c, ctx->amp_prefix.p, (uint32_t)reqs.size(), total_x, s));
+                           fp32c, ctx->amp_prefix.p, (uint32_t)reqs.size(), total_x, s));
   return CHSIM_OK;
 }
 
@@ -878,6 +901,7 @@ chsim_status chsim_set_terms(chsim_ctx* ctx, uint32_t inst, uint64_t first, uint
   HIP_TRY(hipMemcpy(I.s.p + first, s, count * 8, hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(I.omega.p + first, omega, count, hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(I.b.p + first, b, count * 16, hipMemcpyHostToDevice));
+  I.amp_ready = false;
   return CHSIM_OK;
 }
 

@@ -96,13 +96,25 @@ hipError_t launch_set_zero(const TermsView& T, hipStream_t st);
 hipError_t launch_sample(const TermsView& T, const uint64_t* alpha, const uint64_t* flips,
                          uint64_t* x_out, uint32_t count, hipStream_t st);
 
-// Amplitudes.  One request = one instance's terms and its bitstrings; the
-// request's terms are cut into ranges of `tiles_per_range` 64-term tiles and
-// its bitstrings into chunks, and each (range, chunk) is one work item that a
-// persistent workgroup pulls from a queue.  partial[range * n_x + i] holds the
-// range's sum; a second kernel adds the ranges in a fixed order into out.
+// Amplitudes.  Per-term values the amplitude kernel reads, computed by a
+// prologue kernel from the term store: ~v masked to n bits, s & ~v, the
+// gamma low-bit plane, omega and b_alpha 2^{-|v|/2} (w0) and w0 e^{i pi/4} (w1).
+struct AmpTerm {
+  uint64_t nv, snv, glo;
+  uint32_t w, pad;
+  double w0r, w0i, w1r, w1i;
+};
+static_assert(sizeof(AmpTerm) == 64, "AmpTerm is 64 bytes");
+
+// One request = one instance's terms and its bitstrings; the request's terms
+// are cut into ranges of `tiles_per_range` 8-term tiles and its bitstrings
+// into chunks, and each (range, chunk) is one work item that a persistent
+// workgroup pulls from a queue.  partial[range * n_x + i] holds the range's
+// sum; a second kernel adds the ranges in a fixed order into out.
 struct AmpInst {
   TermsView T;
+  const uint64_t* crow;  // [n][chi] rows of the quadratic form (prologue output)
+  const AmpTerm* cst;    // [chi]
   const uint64_t* x;
   double2* partial;  // [n_ranges][n_x]
   double2* out;      // [n_x]
@@ -119,6 +131,7 @@ struct AmpRequestPlan {
   uint32_t n_x;
   uint64_t chi;
 };
+hipError_t launch_amp_prep(const TermsView& T, uint64_t* crow, AmpTerm* cst, hipStream_t st);
 // Cut the requests into work items (sorted by estimated cost, largest first).
 void amp_plan(const std::vector<AmpRequestPlan>& reqs, uint32_t target_items,
               std::vector<AmpItem>& items, std::vector<uint32_t>& tiles_per_range,
@@ -126,8 +139,8 @@ void amp_plan(const std::vector<AmpRequestPlan>& reqs, uint32_t target_items,
 // Reset the queue counter, run the persistent kernel, reduce.  prefix_d[q] =
 // bitstrings of requests before q (n_inst + 1 entries).
 hipError_t launch_amp_items(const AmpInst* insts_d, const AmpItem* items_d, uint32_t n_items,
-                            uint32_t* counter, uint32_t n_max, bool fp32c, const uint64_t* prefix_d,
-                            uint32_t n_inst, uint64_t total_x, hipStream_t st);
+                            uint32_t* counter, bool fp32c, const uint64_t* prefix_d, uint32_t n_inst,
+                            uint64_t total_x, hipStream_t st);
 
 // Inner products with equatorial states.
 size_t inner_partial_elems(const TermsView& T, uint32_t L, uint32_t* n_blocks);
