@@ -431,6 +431,7 @@ def main():
     for i in range(max(1, args.warmup)):
         step(i, False)
     lanes, tune_ms = ctx.evolve_lanes()
+    pf_mode, pf_levels, pf_frac = ctx.prefix_share()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
@@ -490,8 +491,10 @@ def main():
                    "phase_slots": circ.n_slot, "parallelism": "single GPU"},
         "phases_ms": {"reset": ms_reset, "evolve": ms_ev, "amplitudes_fp32c": ms_amp,
                       "amplitudes_fp64": float(np.mean(fp64_ms))},
+        "evolve_prefix_share": {"mode": pf_mode, "checkpoint_levels": pf_levels,
+                                "estimated_work_fraction": round(pf_frac, 4)},
         "evolve_autotune": {"lanes_per_term": lanes, "terms_per_wave": 64 // lanes,
-                            "ms_by_lanes": dict(zip(["8", "16", "32", "64"], tune_ms))},
+                            "ms_by_lanes": dict(zip(["4", "8", "16", "32", "64"], tune_ms))},
         "amplitude_kernel_evals_per_s": chi * n_x / (ms_amp / 1e3),
         "evolve_gates_per_s": chi * circ.n_gates / (ms_ev / 1e3),
         "fp32c_vs_fp64_normwise": fp32c_vs_fp64,

@@ -264,18 +264,30 @@ chsim_status chsim_decompose_phase(double theta, uint32_t qubit, double coeff[4]
                                    chsim_gate gates[8], chsim_decomp* out);
 
 /* Tuning knobs of one instance; value 0 restores the library default.
- * EVOLVE_LANES: lanes per term in the evolution kernel (8, 16, 32 or 64; a
- * wave holds 64 / lanes terms, and each lane holds the smallest power-of-two
- * number of tableau rows that covers n).  -1 = autotune: the next
+ * EVOLVE_LANES: lanes per term in the evolution kernel (4, 8, 16, 32 or 64;
+ * a wave holds 64 / lanes terms, and each lane holds ceil(n / lanes) tableau
+ * rows; lanes * ceil(n / lanes) must not exceed 64).  -1 = autotune: the next
  * chsim_apply_clifford that starts from |0^n> times every shape on the real
  * gate list (hipEvents), keeps the fastest, and leaves the same terms any
  * shape would.  Results never depend on the knob.  EUNSUPPORTED: no compiled
  * kernel for that value and n. */
 #define CHSIM_TUNE_EVOLVE_LANES 1u
+/* PREFIX_SHARE: an evolution from |0^n> runs the gates before a checkpoint
+ * slot once per distinct choice of branches up to that slot (terms that
+ * agree on those choices have identical CH forms there) and continues every
+ * term from its prefix's state; results are bit-identical to evolving each
+ * term alone.  0 = off, 1 = auto (default: checkpoint slots chosen from the
+ * slots' branch weights, chi and the gate mix to minimise estimated work;
+ * none when it would not pay), 2 = checkpoint wherever it removes any work
+ * (for testing).  EINVAL: value outside 0..2. */
+#define CHSIM_TUNE_PREFIX_SHARE 2u
 chsim_status chsim_set_tuning(chsim_ctx* ctx, uint32_t inst, uint32_t knob, int32_t value);
 
-/* Current value of a knob and, for EVOLVE_LANES, the autotuner's timings in
- * ms for lanes 8, 16, 32, 64 (timings_ms[4], 0 where not timed; may be NULL). */
+/* Current value of a knob.  For EVOLVE_LANES, timings_ms[5] receives the
+ * autotuner's timings in ms for lanes 4, 8, 16, 32, 64 (0 where not timed);
+ * for PREFIX_SHARE, timings_ms[0] = checkpoint levels of the last planned
+ * evolution and timings_ms[1] = its estimated work relative to evolving
+ * every term alone.  timings_ms may be NULL. */
 chsim_status chsim_get_tuning(chsim_ctx* ctx, uint32_t inst, uint32_t knob, int32_t* value,
                               float* timings_ms);
 

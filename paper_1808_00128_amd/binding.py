@@ -22,6 +22,7 @@ STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "EUNSUPPORTE
 CHSIM_EXACT, CHSIM_SPARSIFY = 0, 1
 CHSIM_FP64, CHSIM_FP32C, CHSIM_DEVICE_PTRS = 0, 1, 0x100
 CHSIM_TUNE_EVOLVE_LANES = 1
+CHSIM_TUNE_PREFIX_SHARE = 2
 MAX_BRANCH = 8
 
 EXPORTED = [
@@ -237,10 +238,21 @@ class Context:
         -1 = autotune at the next evolution from |0^n>)."""
         _check(lib().chsim_set_tuning(self._h, inst, CHSIM_TUNE_EVOLVE_LANES, int(lanes)))
 
-    def evolve_lanes(self, inst=0):
-        """(lanes in use, autotuner timings in ms for lanes 8, 16, 32, 64)."""
+    def set_prefix_share(self, mode, inst=0):
+        """Shared-prefix evolution: 0 off, 1 auto (default), 2 whenever it saves work."""
+        _check(lib().chsim_set_tuning(self._h, inst, CHSIM_TUNE_PREFIX_SHARE, int(mode)))
+
+    def prefix_share(self, inst=0):
+        """(mode, checkpoint levels of the last plan, estimated work fraction)."""
         v = C.c_int32()
-        t = (C.c_float * 4)()
+        t = (C.c_float * 5)()
+        _check(lib().chsim_get_tuning(self._h, inst, CHSIM_TUNE_PREFIX_SHARE, C.byref(v), t))
+        return v.value, int(t[0]), float(t[1])
+
+    def evolve_lanes(self, inst=0):
+        """(lanes in use, autotuner timings in ms for lanes 4, 8, 16, 32, 64)."""
+        v = C.c_int32()
+        t = (C.c_float * 5)()
         _check(lib().chsim_get_tuning(self._h, inst, CHSIM_TUNE_EVOLVE_LANES, C.byref(v), t))
         return v.value, list(t)
 

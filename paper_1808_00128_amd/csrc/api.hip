@@ -66,7 +66,7 @@ struct Instance {
   bool amp_ready = false;  // the amplitude prologue output matches the terms
   EvolveShape shape;    // evolution mapping (0 = default for n)
   bool autotune = false;  // time every shape at the next from-|0^n> evolution
-  float tuned_ms[4] = {0, 0, 0, 0};  // per lanes 8, 16, 32, 64 (0 = not timed)
+  float tuned_ms[5] = {0, 0, 0, 0, 0};  // per lanes 4, 8, 16, 32, 64 (0 = not timed)
   std::vector<SlotTable> slots_h;
   std::vector<DGate> bgates_h;
   DevBuf<uint64_t> F, G, M, v, s;
@@ -76,6 +76,17 @@ struct Instance {
   // amplitude prologue output
   DevBuf<uint64_t> acrow;
   DevBuf<AmpTerm> acst;
+  // shared-prefix evolution: knob, cached plan of the last gate list
+  int prefix_mode = 1;  // 0 off, 1 auto, 2 always when it saves any work
+  bool plan_valid = false;
+  uint64_t plan_key = 0;
+  std::vector<uint32_t> plan_cut;       // gate position after each checkpoint level
+  std::vector<uint32_t> plan_span_off;  // level k's slots: [span_off[k], span_off[k+1])
+  std::vector<uint16_t> plan_slot_h;
+  std::vector<uint8_t> plan_width_h;
+  double plan_frac = 1.0;               // estimated work relative to per-term evolution
+  DevBuf<uint16_t> plan_slot;
+  DevBuf<uint8_t> plan_width;
   // metropolis
   uint32_t n_chain = 0;
   DevBuf<uint64_t> mstate0, mstate1, mx, mtrace;
@@ -110,6 +121,7 @@ struct Instance {
     gamma.release(); omega.release(); branch.release(); b.release();
     slots.release();
     acrow.release(); acst.release();
+    plan_slot.release(); plan_width.release();
     mstate0.release(); mstate1.release(); mx.release(); mtrace.release();
     mparity.release(); mj.release(); mamp.release(); mpartial.release(); mu.release(); macc.release();
     ly.release(); lmask.release(); logit_x.release(); logit_y.release(); lumix.release();
@@ -137,6 +149,11 @@ struct chsim_ctx {
   DevBuf<uint32_t> amp_counter;
   std::vector<AmpInst> amp_key;
   uint32_t amp_n_items = 0;
+  // Shared-prefix evolution scratch (sized for the largest instance).
+  DevBuf<uint64_t> pf_table;
+  DevBuf<uint32_t> pf_ids, pf_slotof, pf_id[2], pf_rep, pf_parent, pf_count;
+  DevBuf<uint64_t> ck_F[2], ck_G[2], ck_M[2], ck_v[2], ck_s[2];
+  DevBuf<uint8_t> ck_gamma[2], ck_omega[2];
 };
 
 namespace {
@@ -339,6 +356,274 @@ chsim_status chsim_terms_reset(chsim_ctx* ctx, uint32_t inst, uint64_t seed, voi
   return CHSIM_OK;
 }
 
+namespace {
+
+// ---- shared-prefix evolution: plan ----------------------------------------
+// Relative cost of a gate in the evolution kernel (an H touches every row).
+double gate_weight(const DGate& g) {
+  switch (g.op) {
+    case OP_H: return 8.0;
+    case OP_CX: return 1.5;
+    case OP_CZ: return 1.2;
+    default: return 1.0;
+  }
+}
+
+uint32_t branch_bits(uint32_t nb) {
+  uint32_t b = 0;
+  while ((1u << b) < nb) ++b;
+  return b;
+}
+
+// Expected number of distinct branch prefixes after each slot occurrence
+// among chi terms.  EXACT enumerates every combination; SPARSIFY draws each
+// slot's branch j with probability |c_j| / W independently, so
+// E[#distinct] = sum over prefixes of 1 - (1 - P)^chi: prefixes of
+// probability >= eps are kept explicitly, lighter ones are counted as chi P
+// (each sample in them ends up distinct), and once the explicit list grows
+// large every later level is taken as saturated.
+std::vector<double> estimate_distinct(const Instance& I, const std::vector<uint16_t>& occ) {
+  const double chi = (double)I.chi;
+  std::vector<double> D(occ.size() + 1, chi);
+  D[0] = 1.0;
+  if (I.mode == CHSIM_EXACT) {
+    double prod = 1.0;
+    for (size_t j = 0; j < occ.size(); ++j) {
+      prod *= (double)I.slots_h[occ[j]].n_branch;
+      D[j + 1] = std::min(chi, prod);
+    }
+    return D;
+  }
+  const double eps = 4.0 / chi;
+  const size_t kMaxList = (size_t)1 << 18;
+  std::vector<double> P{1.0}, next;
+  double pruned = 0.0;
+  for (size_t j = 0; j < occ.size(); ++j) {
+    const SlotTable& st = I.slots_h[occ[j]];
+    next.clear();
+    double prev_cum = 0.0;
+    for (uint32_t b = 0; b < st.n_branch; ++b) {
+      const double pb = (st.cum[b] - prev_cum) / st.total;
+      prev_cum = st.cum[b];
+      if (!(pb > 0.0)) continue;
+      for (double x : P) {
+        const double y = x * pb;
+        if (y >= eps) next.push_back(y);
+        else pruned += y;
+      }
+    }
+    P.swap(next);
+    double d = chi * pruned;
+    for (double x : P) d += -std::expm1(chi * std::log1p(-std::min(x, 1.0 - 1e-16)));
+    D[j + 1] = std::min(chi, d);
+    if (P.size() > kMaxList) break;  // later levels stay at chi
+  }
+  return D;
+}
+
+// Choose checkpoint levels (slot occurrences) minimising the estimated cost:
+// sum over spans of (distinct states at the span's end) x (gate weight of the
+// span) + a fixed cost per level, plus chi x (weight after the last level).
+void plan_prefix(Instance& I, const std::vector<DGate>& dg) {
+  I.plan_cut.clear();
+  I.plan_span_off.assign(1, 0);
+  I.plan_slot_h.clear();
+  I.plan_width_h.clear();
+  I.plan_frac = 1.0;
+  // Slot occurrences: a SLOT_SPOW gate, or a run of conditional gates of one slot.
+  std::vector<uint16_t> occ;
+  std::vector<uint32_t> end;
+  for (size_t i = 0; i < dg.size(); ++i) {
+    const DGate& g = dg[i];
+    const bool is_slot = g.op == OP_SLOT_SPOW || g.cond;
+    if (!is_slot) continue;
+    const bool cont = !end.empty() && end.back() == i && dg[i - 1].cond && g.cond && occ.back() == g.slot;
+    if (cont) end.back() = (uint32_t)(i + 1);
+    else {
+      occ.push_back(g.slot);
+      end.push_back((uint32_t)(i + 1));
+    }
+  }
+  const size_t m = occ.size();
+  if (m == 0 || I.prefix_mode == 0) return;
+  std::vector<double> Wc(dg.size() + 1, 0.0);
+  for (size_t i = 0; i < dg.size(); ++i) Wc[i + 1] = Wc[i] + gate_weight(dg[i]);
+  std::vector<double> G(m + 1, 0.0);
+  for (size_t j = 0; j < m; ++j) G[j + 1] = Wc[end[j]];
+  const double Gt = Wc[dg.size()];
+  const double chi = (double)I.chi;
+  const std::vector<double> D = estimate_distinct(I, occ);
+  // Fixed cost of a level in weighted term-gates: a few small launches and a
+  // pass over chi terms; a checkpoint state costs one write and one read.
+  const bool force = I.prefix_mode == 2;
+  const double c_level = force ? 0.0 : 1.8e6 + 1.2 * chi;
+  const double c_state = force ? 0.0 : 16.0;
+  std::vector<uint32_t> bits(m + 1, 0);
+  for (size_t j = 0; j < m; ++j) bits[j + 1] = bits[j] + branch_bits(I.slots_h[occ[j]].n_branch);
+  const double inf = 1e300;
+  std::vector<double> best(m + 1, inf);
+  std::vector<int> from(m + 1, -1);
+  best[0] = 0.0;
+  for (size_t j = 1; j <= m; ++j)
+    for (size_t i = 0; i < j; ++i) {
+      if (best[i] >= inf || bits[j] - bits[i] > 32) continue;
+      const double c = best[i] + D[j] * (G[j] - G[i]) + c_level + c_state * D[j];
+      if (c < best[j]) {
+        best[j] = c;
+        from[j] = (int)i;
+      }
+    }
+  size_t last = 0;
+  double total = chi * Gt;
+  for (size_t i = 1; i <= m; ++i) {
+    if (best[i] >= inf) continue;
+    const double c = best[i] + chi * (Gt - G[i]);
+    if (c < total) {
+      total = c;
+      last = i;
+    }
+  }
+  if (last == 0) return;
+  std::vector<size_t> levels;
+  for (size_t j = last; j != 0; j = (size_t)from[j]) levels.push_back(j);
+  std::reverse(levels.begin(), levels.end());
+  size_t prev = 0;
+  for (size_t j : levels) {
+    for (size_t t = prev; t < j; ++t) {
+      I.plan_slot_h.push_back(occ[t]);
+      I.plan_width_h.push_back((uint8_t)branch_bits(I.slots_h[occ[t]].n_branch));
+    }
+    I.plan_span_off.push_back((uint32_t)I.plan_slot_h.size());
+    I.plan_cut.push_back(end[j - 1]);
+    prev = j;
+  }
+  I.plan_frac = Gt > 0 ? total / (chi * Gt) : 1.0;
+}
+
+uint64_t gates_key(const Instance& I, const std::vector<DGate>& dg) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](const void* p, size_t len) {
+    const uint8_t* b = static_cast<const uint8_t*>(p);
+    for (size_t i = 0; i < len; ++i) h = (h ^ b[i]) * 1099511628211ull;
+  };
+  mix(dg.data(), dg.size() * sizeof(DGate));
+  mix(&I.chi, sizeof I.chi);
+  mix(&I.mode, sizeof I.mode);
+  mix(&I.prefix_mode, sizeof I.prefix_mode);
+  return h;
+}
+
+// ---- shared-prefix evolution: run ------------------------------------------
+TermsView ckpt_view(chsim_ctx* ctx, const Instance& I, int k) {
+  TermsView t;
+  std::memset(&t, 0, sizeof t);
+  t.n = I.n;
+  t.n_slot = I.n_slot;
+  t.chi = I.chi;
+  t.F = ctx->ck_F[k].p;
+  t.G = ctx->ck_G[k].p;
+  t.M = ctx->ck_M[k].p;
+  t.gamma = ctx->ck_gamma[k].p;
+  t.v = ctx->ck_v[k].p;
+  t.s = ctx->ck_s[k].p;
+  t.omega = ctx->ck_omega[k].p;
+  return t;
+}
+
+// Evolve every term of I through the device gate list (ctx->gates, dg on the
+// host), from |0^n> or from the stored terms.
+chsim_status evolve_all(chsim_ctx* ctx, Instance& I, const std::vector<DGate>& dg, EvolveShape shape,
+                        bool from_zero, hipStream_t s) {
+  const uint32_t ng = (uint32_t)dg.size();
+  if (!from_zero || I.prefix_mode == 0) {
+    HIP_TRY(launch_evolve(I.view(), ctx->gates.p, ng, I.slots.p, from_zero, ctx->err.p, shape, s));
+    return CHSIM_OK;
+  }
+  const uint64_t key = gates_key(I, dg);
+  if (!I.plan_valid || I.plan_key != key) {
+    plan_prefix(I, dg);
+    I.plan_key = key;
+    I.plan_valid = true;
+    if (!I.plan_cut.empty()) {
+      HIP_TRY(I.plan_slot.ensure(I.plan_slot_h.size()));
+      HIP_TRY(I.plan_width.ensure(I.plan_width_h.size()));
+      HIP_TRY(hipMemcpy(I.plan_slot.p, I.plan_slot_h.data(), I.plan_slot_h.size() * sizeof(uint16_t),
+                        hipMemcpyHostToDevice));
+      HIP_TRY(hipMemcpy(I.plan_width.p, I.plan_width_h.data(), I.plan_width_h.size(), hipMemcpyHostToDevice));
+    }
+  }
+  const size_t K = I.plan_cut.size();
+  if (K == 0) {
+    HIP_TRY(launch_evolve(I.view(), ctx->gates.p, ng, I.slots.p, true, ctx->err.p, shape, s));
+    return CHSIM_OK;
+  }
+  const uint64_t chi = I.chi, n = I.n;
+  uint64_t ts = 1;
+  while (ts < 2 * chi) ts <<= 1;
+  HIP_TRY(ctx->pf_table.ensure(ts));
+  HIP_TRY(ctx->pf_ids.ensure(ts));
+  HIP_TRY(ctx->pf_slotof.ensure(chi));
+  HIP_TRY(ctx->pf_rep.ensure(chi));
+  HIP_TRY(ctx->pf_parent.ensure(chi));
+  HIP_TRY(ctx->pf_count.ensure(K));
+  for (int k = 0; k < 2; ++k) {
+    HIP_TRY(ctx->pf_id[k].ensure(chi));
+    HIP_TRY(ctx->ck_F[k].ensure(n * chi));
+    HIP_TRY(ctx->ck_G[k].ensure(n * chi));
+    HIP_TRY(ctx->ck_M[k].ensure(n * chi));
+    HIP_TRY(ctx->ck_gamma[k].ensure(n * chi));
+    HIP_TRY(ctx->ck_v[k].ensure(chi));
+    HIP_TRY(ctx->ck_s[k].ensure(chi));
+    HIP_TRY(ctx->ck_omega[k].ensure(chi));
+  }
+  const uint32_t* prev_id = nullptr;
+  uint32_t g0 = 0;
+  for (size_t k = 0; k < K; ++k) {
+    PrefixLevelArgs A;
+    A.branch = I.branch.p;
+    A.chi = chi;
+    A.slot = I.plan_slot.p + I.plan_span_off[k];
+    A.width = I.plan_width.p + I.plan_span_off[k];
+    A.n_span = I.plan_span_off[k + 1] - I.plan_span_off[k];
+    A.prev_id = prev_id;
+    A.table = ctx->pf_table.p;
+    A.table_mask = ts - 1;
+    A.ids = ctx->pf_ids.p;
+    A.slot_of = ctx->pf_slotof.p;
+    A.counter = ctx->pf_count.p + k;
+    A.id_out = ctx->pf_id[k % 2].p;
+    A.rep = ctx->pf_rep.p;
+    A.parent = ctx->pf_parent.p;
+    HIP_TRY(launch_prefix_level(A, s));
+    EvolveJob J;
+    J.src = ckpt_view(ctx, I, (int)((k + 1) % 2));
+    J.dst = ckpt_view(ctx, I, (int)(k % 2));
+    J.src_idx = ctx->pf_parent.p;
+    J.br_idx = ctx->pf_rep.p;
+    J.branch = I.branch.p;
+    J.chi_br = chi;
+    J.count_dev = ctx->pf_count.p + k;
+    J.count = chi;
+    const uint32_t g1 = I.plan_cut[k];
+    HIP_TRY(launch_evolve_job(J, ctx->gates.p + g0, g1 - g0, I.slots.p, k == 0, ctx->err.p, shape, s));
+    prev_id = ctx->pf_id[k % 2].p;
+    g0 = g1;
+  }
+  EvolveJob J;
+  J.src = ckpt_view(ctx, I, (int)((K - 1) % 2));
+  J.dst = I.view();
+  J.src_idx = prev_id;
+  J.br_idx = nullptr;
+  J.branch = I.branch.p;
+  J.chi_br = chi;
+  J.count_dev = nullptr;
+  J.count = chi;
+  HIP_TRY(launch_evolve_job(J, ctx->gates.p + g0, ng - g0, I.slots.p, false, ctx->err.p, shape, s));
+  return CHSIM_OK;
+}
+
+}  // namespace
+
 chsim_status chsim_apply_clifford(chsim_ctx* ctx, uint32_t inst, const chsim_gate* gates,
                                   size_t n_gates, void* stream) {
   g_err.clear();
@@ -384,19 +669,16 @@ chsim_status chsim_apply_clifford(chsim_ctx* ctx, uint32_t inst, const chsim_gat
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
-    const int cand[4] = {8, 16, 32, 64};
+    const int cand[5] = {4, 8, 16, 32, 64};
     float best = 0.f;
     EvolveShape best_shape;
-    for (int ci = 0; ci < 4; ++ci) {
-      EvolveShape sh;
-      sh.lanes = cand[ci];
-      sh.rows = 1;
-      while ((uint32_t)(sh.lanes * sh.rows) < I.n) sh.rows *= 2;
+    for (int ci = 0; ci < 5; ++ci) {
+      const EvolveShape sh = evolve_shape_for(I.n, cand[ci]);
       I.tuned_ms[ci] = 0.f;
       if (!evolve_shape_supported(sh, I.n)) continue;
       HIP_TRY(hipEventRecord(e0, s));
-      HIP_TRY(launch_evolve(I.view(), ctx->gates.p, (uint32_t)dg.size(), I.slots.p, true, ctx->err.p,
-                            sh, s));
+      st = evolve_all(ctx, I, dg, sh, true, s);
+      if (st) return st;
       HIP_TRY(hipEventRecord(e1, s));
       HIP_TRY(hipEventSynchronize(e1));
       float ms = 0.f;
@@ -412,11 +694,11 @@ chsim_status chsim_apply_clifford(chsim_ctx* ctx, uint32_t inst, const chsim_gat
     I.shape = best_shape;
     I.autotune = false;
     // Leave the store as the chosen shape computes it.
-    HIP_TRY(launch_evolve(I.view(), ctx->gates.p, (uint32_t)dg.size(), I.slots.p, true, ctx->err.p,
-                          I.shape, s));
+    st = evolve_all(ctx, I, dg, I.shape, true, s);
+    if (st) return st;
   } else {
-    HIP_TRY(launch_evolve(I.view(), ctx->gates.p, (uint32_t)dg.size(), I.slots.p, I.at_zero,
-                          ctx->err.p, I.shape, s));
+    st = evolve_all(ctx, I, dg, I.shape, I.at_zero, s);
+    if (st) return st;
   }
   I.at_zero = false;
   I.amp_ready = false;
@@ -964,13 +1246,16 @@ chsim_status chsim_set_tuning(chsim_ctx* ctx, uint32_t inst, uint32_t knob, int3
         I.autotune = true;
         return CHSIM_OK;
       }
-      EvolveShape s;
-      s.lanes = value;
-      s.rows = 1;
-      while (value > 0 && (uint32_t)(s.lanes * s.rows) < I.n) s.rows *= 2;
+      const EvolveShape s = evolve_shape_for(I.n, value);
       if (!evolve_shape_supported(s, I.n))
         return fail(CHSIM_EUNSUPPORTED, "no evolution kernel with %d lanes per term for n = %u", value, I.n);
       I.shape = s;
+      return CHSIM_OK;
+    }
+    case CHSIM_TUNE_PREFIX_SHARE: {
+      if (value < 0 || value > 2) return fail(CHSIM_EINVAL, "prefix-share mode %d not in 0..2", value);
+      I.prefix_mode = value;
+      I.plan_valid = false;
       return CHSIM_OK;
     }
     default:
@@ -984,11 +1269,19 @@ chsim_status chsim_get_tuning(chsim_ctx* ctx, uint32_t inst, uint32_t knob, int3
   chsim_status st = check_ctx(ctx, inst);
   if (st) return st;
   Instance& I = ctx->inst[inst];
+  if (knob == CHSIM_TUNE_PREFIX_SHARE) {
+    if (value) *value = I.prefix_mode;
+    if (timings_ms) {
+      timings_ms[0] = I.plan_valid ? (float)I.plan_cut.size() : 0.f;
+      timings_ms[1] = I.plan_valid ? (float)I.plan_frac : 1.f;
+    }
+    return CHSIM_OK;
+  }
   if (knob != CHSIM_TUNE_EVOLVE_LANES) return fail(CHSIM_EINVAL, "unknown tuning knob %u", knob);
   EvolveShape sh = I.shape.lanes ? I.shape : evolve_default_shape(I.n);
   if (value) *value = sh.lanes;
   if (timings_ms)
-    for (int i = 0; i < 4; ++i) timings_ms[i] = I.tuned_ms[i];
+    for (int i = 0; i < 5; ++i) timings_ms[i] = I.tuned_ms[i];
   return CHSIM_OK;
 }
 
@@ -1016,6 +1309,22 @@ chsim_status chsim_destroy(chsim_ctx* ctx) {
   ctx->amp_items.release();
   ctx->amp_prefix.release();
   ctx->amp_counter.release();
+  ctx->pf_table.release();
+  ctx->pf_ids.release();
+  ctx->pf_slotof.release();
+  ctx->pf_rep.release();
+  ctx->pf_parent.release();
+  ctx->pf_count.release();
+  for (int k = 0; k < 2; ++k) {
+    ctx->pf_id[k].release();
+    ctx->ck_F[k].release();
+    ctx->ck_G[k].release();
+    ctx->ck_M[k].release();
+    ctx->ck_v[k].release();
+    ctx->ck_s[k].release();
+    ctx->ck_gamma[k].release();
+    ctx->ck_omega[k].release();
+  }
   ctx->out.release();
   ctx->aoff.release();
   ctx->adiag.release();

@@ -82,17 +82,67 @@ constexpr int kAmpTile = 64;
 // ---- launchers (each returns the first HIP error) ----
 hipError_t launch_choose(const TermsView& T, const SlotTable* slots, uint32_t mode, uint64_t seed,
                          double scale, hipStream_t st);
-// Evolution mapping: `lanes` lanes per term (8, 16, 32 or 64; 64 / lanes terms
-// per wave) and `rows` tableau rows per lane (lanes * rows >= n).  0 = choose.
+// Evolution mapping: `lanes` lanes per term (4, 8, 16, 32 or 64; 64 / lanes
+// terms per wave) and `rows` = ceil(n / lanes) tableau rows per lane.  0 = choose.
 struct EvolveShape {
   int lanes = 0, rows = 0;
 };
+EvolveShape evolve_shape_for(uint32_t n, int lanes);
 EvolveShape evolve_default_shape(uint32_t n);
 bool evolve_shape_supported(EvolveShape s, uint32_t n);
+// One evolution launch: count work items (or *count_dev of them, count being
+// the grid's bound); item i starts from |0^n> (from_zero) or from state
+// src_idx[i] (i if null) of src, takes its branch choices from column
+// br_idx[i] (i if null) of branch [slot][chi_br], and writes state i of dst.
+// src may equal dst when src_idx is null (in-place update).
+struct EvolveJob {
+  TermsView src, dst;
+  const uint32_t* src_idx;
+  const uint32_t* br_idx;
+  const uint8_t* branch;
+  uint64_t chi_br;
+  const uint32_t* count_dev;
+  uint64_t count;
+};
+hipError_t launch_evolve_job(const EvolveJob& J, const DGate* gates, uint32_t n_gates,
+                             const SlotTable* slots, bool from_zero, uint32_t* err, EvolveShape shape,
+                             hipStream_t st);
+hipError_t launch_evolve_l4(int rows, const EvolveJob& J, const DGate* gates, uint32_t n_gates,
+                            const SlotTable* slots, bool from_zero, uint32_t* err, hipStream_t st);
+hipError_t launch_evolve_l8(int rows, const EvolveJob& J, const DGate* gates, uint32_t n_gates,
+                            const SlotTable* slots, bool from_zero, uint32_t* err, hipStream_t st);
+hipError_t launch_evolve_wide(int lanes, int rows, const EvolveJob& J, const DGate* gates,
+                              uint32_t n_gates, const SlotTable* slots, bool from_zero,
+                              uint32_t* err, hipStream_t st);
 hipError_t launch_evolve(const TermsView& T, const DGate* gates, uint32_t n_gates,
                          const SlotTable* slots, bool from_zero, uint32_t* err, EvolveShape shape,
                          hipStream_t st);
 hipError_t launch_set_zero(const TermsView& T, hipStream_t st);
+
+// One checkpoint level of shared-prefix evolution.  For every term a < chi:
+// key = (prev_id[a] (0 if null) << 32) | the branch choices of the n_span
+// slots slot[i] packed at width[i] bits each (at most 32 bits in all);
+// id_out[a] = rank of the key among the distinct keys (ids 0 .. *counter - 1,
+// arbitrary order), rep[id] = some term with that key, parent[id] = its
+// prev_id.  table has table_mask + 1 >= 2 chi entries; ids and slot_of are
+// scratch of table and chi entries.
+struct PrefixLevelArgs {
+  const uint8_t* branch;  // [slot][chi]
+  uint64_t chi;
+  const uint16_t* slot;
+  const uint8_t* width;
+  uint32_t n_span;
+  const uint32_t* prev_id;
+  uint64_t* table;
+  uint64_t table_mask;
+  uint32_t* ids;
+  uint32_t* slot_of;
+  uint32_t* counter;
+  uint32_t* id_out;
+  uint32_t* rep;
+  uint32_t* parent;
+};
+hipError_t launch_prefix_level(const PrefixLevelArgs& A, hipStream_t st);
 hipError_t launch_sample(const TermsView& T, const uint64_t* alpha, const uint64_t* flips,
                          uint64_t* x_out, uint32_t count, hipStream_t st);
 

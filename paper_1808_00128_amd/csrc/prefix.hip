@@ -1,0 +1,91 @@
+// Shared-prefix evolution support: distinct branch prefixes at checkpoint
+// levels.
+//
+// Every term is the same Clifford circuit with the slots' branch choices
+// substituted (Sec. "Sum-over-Cliffords", Sparsification Lemma: i.i.d.
+// choices per slot), so two terms that agree on the choices of the first j
+// slots have bit-identical CH forms after the gates before slot j + 1: the
+// update rules are deterministic functions of the state and the gate.  The
+// evolution therefore runs once per distinct prefix up to a checkpoint
+// level, and each term continues from its prefix's state.
+//
+// Level k's prefix id of term a is the rank of the pair (level k-1 id,
+// branch bits of the slots between the two levels) among the distinct pairs:
+// an open-addressing hash table of 64-bit keys assigns ids (in an arbitrary
+// order; ids only address checkpoint states).
+#include "device_common.hpp"
+#include "internal.hpp"
+
+namespace chsim {
+
+namespace {
+
+constexpr uint64_t kEmpty = ~0ull;
+
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  // splitmix64 finaliser
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+__global__ __launch_bounds__(256) void k_prefix_clear(PrefixLevelArgs A) {
+  const uint64_t h = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (h <= A.table_mask) A.table[h] = kEmpty;
+  if (h == 0) *A.counter = 0u;
+}
+
+__global__ __launch_bounds__(256) void k_prefix_insert(PrefixLevelArgs A) {
+  const uint64_t a = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= A.chi) return;
+  uint32_t bits = 0, sh = 0;
+  for (uint32_t i = 0; i < A.n_span; ++i) {
+    if (A.width[i] == 0) continue;  // a one-branch slot carries no choice
+    bits |= (uint32_t)A.branch[(uint64_t)A.slot[i] * A.chi + a] << sh;
+    sh += A.width[i];
+  }
+  const uint64_t prev = A.prev_id ? (uint64_t)A.prev_id[a] : 0ull;
+  const uint64_t key = (prev << 32) | bits;  // prev < 2^32 - 1, so key != kEmpty
+  uint64_t h = mix64(key) & A.table_mask;
+  // The table has at least twice as many entries as keys: a free or
+  // matching entry is always reached within table_mask + 1 probes.
+  for (uint64_t probe = 0; probe <= A.table_mask; ++probe) {
+    const uint64_t old = atomicCAS((unsigned long long*)&A.table[h], (unsigned long long)kEmpty,
+                                   (unsigned long long)key);
+    if (old == kEmpty || old == key) break;
+    h = (h + 1) & A.table_mask;
+  }
+  A.slot_of[a] = (uint32_t)h;
+}
+
+__global__ __launch_bounds__(256) void k_prefix_assign(PrefixLevelArgs A) {
+  const uint64_t h = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (h > A.table_mask) return;
+  if (A.table[h] != kEmpty) A.ids[h] = atomicAdd(A.counter, 1u);
+}
+
+// Term a's id, the representative term of each id (any term with that
+// prefix: they all carry the same choices on the slots seen so far) and the
+// id's parent at the previous level.
+__global__ __launch_bounds__(256) void k_prefix_map(PrefixLevelArgs A) {
+  const uint64_t a = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= A.chi) return;
+  const uint32_t id = A.ids[A.slot_of[a]];
+  A.id_out[a] = id;
+  A.rep[id] = (uint32_t)a;
+  A.parent[id] = A.prev_id ? A.prev_id[a] : 0u;
+}
+
+}  // namespace
+
+hipError_t launch_prefix_level(const PrefixLevelArgs& A, hipStream_t st) {
+  const uint64_t ts = A.table_mask + 1ull;
+  const uint32_t tb = (uint32_t)((ts + 255) / 256), cb = (uint32_t)((A.chi + 255) / 256);
+  hipLaunchKernelGGL(k_prefix_clear, dim3(tb), dim3(256), 0, st, A);
+  hipLaunchKernelGGL(k_prefix_insert, dim3(cb), dim3(256), 0, st, A);
+  hipLaunchKernelGGL(k_prefix_assign, dim3(tb), dim3(256), 0, st, A);
+  hipLaunchKernelGGL(k_prefix_map, dim3(cb), dim3(256), 0, st, A);
+  return hipGetLastError();
+}
+
+}  // namespace chsim

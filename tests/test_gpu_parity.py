@@ -92,8 +92,8 @@ CASES = [
 
 @pytest.mark.parametrize("case", CASES, ids=[f"n{c[0]}-chi{c[3]}" for c in CASES])
 def test_evolution_bit_exact(B, case):
-    """Every evolution shape (lanes per term 8, 16, 32, 64 with enough rows per
-    lane) gives the oracle's terms bit for bit."""
+    """Every evolution shape (lanes per term 4, 8, 16, 32, 64 with ceil(n / lanes)
+    rows per lane) gives the oracle's terms bit for bit."""
     n, ng, m, chi, mode = case
     rng = np.random.default_rng(7000 + n)
     circ = W.random_circuit(n, ng, rng.uniform(0, 2 * np.pi, size=m), rng)
@@ -101,15 +101,68 @@ def test_evolution_bit_exact(B, case):
     idx = np.arange(chi, dtype=np.uint64) if chi <= 300 else np.unique(
         np.concatenate([[0, chi - 1], rng.integers(0, chi, size=120)])).astype(np.uint64)
     T = O.Terms(circ, chi, oracle_mode(spec), seed=spec["seed"], alphas=idx)
-    for lanes in (8, 16, 32, 64):
-        if lanes * 8 < n:
-            continue
+    for lanes in (4, 8, 16, 32, 64):
         say(f"evolution n={n} chi={chi} mode={mode} lanes={lanes}")
         ctx = B.Context([spec])
         ctx.set_evolve_lanes(lanes)
         ctx.apply_circuit(circ)
         compare_terms(ctx, T, idx)
         ctx.close()
+
+
+PREFIX_CASES = [
+    # (n, clifford gates, slots, chi, mode)
+    (12, 200, 6, 64, "exact"),
+    (20, 300, 12, 500, "sparsify"),
+    (50, 800, 20, 1000, "sparsify"),
+    (64, 600, 40, 2000, "sparsify"),
+]
+
+
+@pytest.mark.parametrize("case", PREFIX_CASES, ids=[f"n{c[0]}-chi{c[3]}" for c in PREFIX_CASES])
+def test_evolution_prefix_share_bit_exact(B, case):
+    """Shared-prefix evolution (checkpoints forced) gives the oracle's terms
+    bit for bit, and the same store as evolving every term alone."""
+    n, ng, m, chi, mode = case
+    rng = np.random.default_rng(9100 + n)
+    circ = W.random_circuit(n, ng, rng.uniform(0, 2 * np.pi, size=m), rng)
+    spec = dict(circuit=circ, chi=chi, mode=mode, seed=77 + n)
+    idx = np.arange(chi, dtype=np.uint64) if chi <= 300 else np.unique(
+        np.concatenate([[0, chi - 1], rng.integers(0, chi, size=150)])).astype(np.uint64)
+    T = O.Terms(circ, chi, oracle_mode(spec), seed=spec["seed"], alphas=idx)
+    say(f"prefix share n={n} chi={chi} mode={mode}")
+    shared = B.Context([spec])
+    shared.set_prefix_share(2)
+    shared.apply_circuit(circ)
+    mode_v, levels, frac = shared.prefix_share()
+    assert mode_v == 2 and levels >= 1 and frac < 1.0, (levels, frac)
+    compare_terms(shared, T, idx)
+    plain = B.Context([spec])
+    plain.set_prefix_share(0)
+    plain.apply_circuit(circ)
+    a = shared.get_terms(0, chi)
+    b = plain.get_terms(0, chi)
+    for key in a:
+        assert np.array_equal(a[key], b[key]), key
+    x = W.random_bitstrings(n, 64, rng)
+    assert normwise(shared.amplitudes(x), T.amplitudes(x) if chi <= 300 else plain.amplitudes(x)) < TOL64
+
+
+def test_evolution_prefix_share_then_segments(B):
+    """A shared-prefix first segment followed by per-term segments."""
+    rng = np.random.default_rng(91)
+    circ = W.random_circuit(30, 400, rng.uniform(0, 2 * np.pi, size=16), rng)
+    spec = dict(circuit=circ, chi=700, mode="sparsify", seed=5)
+    say("prefix share + segments")
+    ctx = B.Context([spec])
+    ctx.set_prefix_share(2)
+    g = B.gate_array(circ)
+    cut = [0, 150, 151, 300, g.size]
+    for a, b in zip(cut[:-1], cut[1:]):
+        ctx.apply_gates(g[a:b])
+    idx = np.arange(0, 700, 5, dtype=np.uint64)
+    T = O.Terms(circ, 700, O.SPARSIFY, seed=5, alphas=idx)
+    compare_terms(ctx, T, idx)
 
 
 def test_evolution_autotune_keeps_results(B):
@@ -121,7 +174,7 @@ def test_evolution_autotune_keeps_results(B):
     ctx.set_evolve_lanes(-1)
     ctx.apply_circuit(circ)
     lanes, times = ctx.evolve_lanes()
-    assert lanes in (8, 16, 32, 64) and times[[8, 16, 32, 64].index(lanes)] > 0
+    assert lanes in (4, 8, 16, 32, 64) and times[[4, 8, 16, 32, 64].index(lanes)] > 0
     idx = np.arange(0, 777, 7, dtype=np.uint64)
     T = O.Terms(circ, 777, O.SPARSIFY, seed=9, alphas=idx)
     compare_terms(ctx, T, idx)
