@@ -28,11 +28,12 @@ INT32_PEAK_OPS = 256 * 64 * 2.4e9
 HBM_PEAK_BPS = 8.0e12
 
 
-def algorithmic_ops_evolve(circuit, n):
-    """Int32 operations per term for the evolution on bit-packed rows:
-    S 3, CZ 4, CX 12, H 28 n + 40 (a slot applies its branch: S powers, 3)."""
-    per = {0: 28 * n + 40, 1: 3, 2: 12, 3: 4, 4: 3}
-    return float(sum(per[int(o)] for o in circuit.op))
+def algorithmic_ops_evolve(stats, n):
+    """Int32 operations of one evolution on bit-packed rows, from the gate
+    applications it executed (per term, or per shared prefix state):
+    S-type 3, CZ 4, CX 12, H 28 n + 40, a general-branch gate 12."""
+    return float(stats["H"] * (28 * n + 40) + stats["CX"] * 12 + stats["CZ"] * 4 + stats["S"] * 3
+                 + stats["cond"] * 12)
 
 
 def algorithmic_ops_amp(xs):
@@ -457,7 +458,8 @@ def main():
     rms = float(np.sqrt(np.mean(np.abs(c64) ** 2)))
     fp32c_vs_fp64 = float(np.max(np.abs(c32 - c64)) / rms) if rms > 0 else 0.0
 
-    ops_ev = algorithmic_ops_evolve(circ, n) * chi
+    ev_stats = ctx.evolution_stats()
+    ops_ev = algorithmic_ops_evolve(ev_stats, n)
     ops_amp = algorithmic_ops_amp(xs) * chi * n_x
     ms_ev = float(np.mean(phase["evolve"]))
     ms_amp = float(np.mean(phase["amplitudes"]))
@@ -492,7 +494,10 @@ def main():
         "phases_ms": {"reset": ms_reset, "evolve": ms_ev, "amplitudes_fp32c": ms_amp,
                       "amplitudes_fp64": float(np.mean(fp64_ms))},
         "evolve_prefix_share": {"mode": pf_mode, "checkpoint_levels": pf_levels,
-                                "estimated_work_fraction": round(pf_frac, 4)},
+                                "estimated_work_fraction": round(pf_frac, 4),
+                                "distinct_prefixes": ev_stats["distinct"],
+                                "gate_applications": {k: ev_stats[k] for k in ("H", "CX", "CZ", "S", "cond")},
+                                "per_term_gate_applications": chi * circ.n_gates},
         "evolve_autotune": {"lanes_per_term": lanes, "terms_per_wave": 64 // lanes,
                             "ms_by_lanes": dict(zip(["4", "8", "16", "32", "64"], tune_ms))},
         "amplitude_kernel_evals_per_s": chi * n_x / (ms_amp / 1e3),

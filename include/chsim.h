@@ -286,10 +286,20 @@ chsim_status chsim_set_tuning(chsim_ctx* ctx, uint32_t inst, uint32_t knob, int3
 /* Current value of a knob.  For EVOLVE_LANES, timings_ms[5] receives the
  * autotuner's timings in ms for lanes 4, 8, 16, 32, 64 (0 where not timed);
  * for PREFIX_SHARE, timings_ms[0] = checkpoint levels of the last planned
- * evolution and timings_ms[1] = its estimated work relative to evolving
+ * evolution and timings_ms[1] = its estimated cost relative to evolving
  * every term alone.  timings_ms may be NULL. */
 chsim_status chsim_get_tuning(chsim_ctx* ctx, uint32_t inst, uint32_t knob, int32_t* value,
                               float* timings_ms);
+
+/* Work of the last chsim_apply_clifford on instance inst, in gate
+ * applications (one gate on one term or on one shared prefix state):
+ * apps[0] H, apps[1] CX, apps[2] CZ, apps[3] S, runs of S and slot powers of
+ * S, apps[4] gates of general slot branches (each counted on every item,
+ * applied or not).  *levels (may be NULL) = checkpoint levels used, and
+ * distinct[k] (may be NULL; k < max_levels) = distinct branch prefixes at
+ * level k.  Waits for the device.  EINVAL: apps NULL. */
+chsim_status chsim_evolution_stats(chsim_ctx* ctx, uint32_t inst, uint64_t apps[5], uint32_t* levels,
+                                   uint64_t* distinct, uint32_t max_levels);
 
 /* Instance metadata: n, chi and ||c||_1 = prod_p W_p. */
 chsim_status chsim_instance_info(chsim_ctx* ctx, uint32_t inst, uint32_t* n, uint64_t* chi,

@@ -30,7 +30,7 @@ EXPORTED = [
     "chsim_amplitudes_batch", "chsim_inner_products",
     "chsim_metropolis_init", "chsim_metropolis_step", "chsim_sample_terms", "chsim_get_terms",
     "chsim_set_terms", "chsim_decompose_phase", "chsim_set_tuning", "chsim_get_tuning",
-    "chsim_instance_info", "chsim_destroy", "chsim_mlp_create", "chsim_mlp_destroy",
+    "chsim_instance_info", "chsim_evolution_stats", "chsim_destroy", "chsim_mlp_create", "chsim_mlp_destroy",
     "chsim_mlp_get_params", "chsim_mlp_set_params", "chsim_mlp_forward", "chsim_mlp_loss_grad",
     "chsim_mlp_train", "chsim_metropolis_step_learned",
     "chsim_last_error",
@@ -248,6 +248,16 @@ class Context:
         t = (C.c_float * 5)()
         _check(lib().chsim_get_tuning(self._h, inst, CHSIM_TUNE_PREFIX_SHARE, C.byref(v), t))
         return v.value, int(t[0]), float(t[1])
+
+    def evolution_stats(self, inst=0, max_levels=64):
+        """Gate applications of the last evolution by kind (H, CX, CZ, S-type,
+        general-branch) and the distinct prefix counts per checkpoint level."""
+        apps = (C.c_uint64 * 5)()
+        lv = C.c_uint32()
+        dist = (C.c_uint64 * max_levels)()
+        _check(lib().chsim_evolution_stats(self._h, inst, apps, C.byref(lv), dist, max_levels))
+        return dict(H=apps[0], CX=apps[1], CZ=apps[2], S=apps[3], cond=apps[4],
+                    levels=lv.value, distinct=list(dist)[:min(lv.value, max_levels)])
 
     def evolve_lanes(self, inst=0):
         """(lanes in use, autotuner timings in ms for lanes 4, 8, 16, 32, 64)."""

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -81,12 +82,22 @@ struct Instance {
   bool plan_valid = false;
   uint64_t plan_key = 0;
   std::vector<uint32_t> plan_cut;       // gate position after each checkpoint level
+  std::vector<int> plan_lanes;          // mapping of each checkpoint span (0: the instance's)
   std::vector<uint32_t> plan_span_off;  // level k's slots: [span_off[k], span_off[k+1])
   std::vector<uint16_t> plan_slot_h;
   std::vector<uint8_t> plan_width_h;
   double plan_frac = 1.0;               // estimated work relative to per-term evolution
   DevBuf<uint16_t> plan_slot;
   DevBuf<uint8_t> plan_width;
+  DevBuf<uint32_t> plan_count;  // distinct prefixes per level of the last run
+  // gate applications of the last evolution: per span, gate counts by kind
+  // and the item count (fixed, or plan_count[level] when level >= 0)
+  struct SpanStat {
+    int level;
+    uint64_t items;
+    uint64_t kinds[5];
+  };
+  std::vector<SpanStat> last_spans;
   // metropolis
   uint32_t n_chain = 0;
   DevBuf<uint64_t> mstate0, mstate1, mx, mtrace;
@@ -121,7 +132,7 @@ struct Instance {
     gamma.release(); omega.release(); branch.release(); b.release();
     slots.release();
     acrow.release(); acst.release();
-    plan_slot.release(); plan_width.release();
+    plan_slot.release(); plan_width.release(); plan_count.release();
     mstate0.release(); mstate1.release(); mx.release(); mtrace.release();
     mparity.release(); mj.release(); mamp.release(); mpartial.release(); mu.release(); macc.release();
     ly.release(); lmask.release(); logit_x.release(); logit_y.release(); lumix.release();
@@ -149,9 +160,13 @@ struct chsim_ctx {
   DevBuf<uint32_t> amp_counter;
   std::vector<AmpInst> amp_key;
   uint32_t amp_n_items = 0;
+  // Slot occurrences of the last gate list: first gate index and slot.
+  std::vector<uint32_t> occ_start;
+  std::vector<uint32_t> slotseq_h;
+  DevBuf<uint32_t> slotseq;
   // Shared-prefix evolution scratch (sized for the largest instance).
   DevBuf<uint64_t> pf_table;
-  DevBuf<uint32_t> pf_ids, pf_slotof, pf_id[2], pf_rep, pf_parent, pf_count;
+  DevBuf<uint32_t> pf_ids, pf_slotof, pf_id[2], pf_rep, pf_parent;
   DevBuf<uint64_t> ck_F[2], ck_G[2], ck_M[2], ck_v[2], ck_s[2];
   DevBuf<uint8_t> ck_gamma[2], ck_omega[2];
 };
@@ -176,7 +191,7 @@ bool valid_clifford(const chsim_gate& g, uint32_t n) {
 // index `first` (an earlier branch) are never merged into.
 void push_gate(std::vector<DGate>& out, const chsim_gate& g, size_t first = 0) {
   if (g.op == CHSIM_S) {
-    if (out.size() > first && (out.back().op == OP_SPOW) && out.back().q == g.q) {
+    if (out.size() > first && out.back().op == OP_SPOW && out.back().q == g.q && out.back().cond == 0) {
       out.back().arg = (uint8_t)((out.back().arg + 1) & 3);
       return;
     }
@@ -359,14 +374,27 @@ chsim_status chsim_terms_reset(chsim_ctx* ctx, uint32_t inst, uint64_t seed, voi
 namespace {
 
 // ---- shared-prefix evolution: plan ----------------------------------------
-// Relative cost of a gate in the evolution kernel (an H touches every row).
-double gate_weight(const DGate& g) {
-  switch (g.op) {
-    case OP_H: return 8.0;
-    case OP_CX: return 1.5;
-    case OP_CZ: return 1.2;
-    default: return 1.0;
-  }
+// Evolution-kernel cost per gate, measured on MI355X at n = 50: the latency
+// of one gate for a lone wave, and the time per gate for 65536 items at full
+// occupancy, in microseconds, by kind (H, CX, CZ, S-type), for the packed
+// mapping (8 lanes per term) and the whole-wave mapping (64 lanes per term).
+struct GateCost {
+  double lat[4], thr[4];
+};
+constexpr GateCost kCostPacked = {{0.91, 0.61, 0.53, 0.52}, {4.29, 2.49, 2.10, 2.03}};
+constexpr GateCost kCostWave = {{0.41, 0.30, 0.30, 0.27}, {10.0, 5.94, 4.59, 4.83}};
+constexpr double kLevelCostUs = 30.0;  // prefix-id kernels and a launch per level
+
+int gate_kind(const DGate& g) {
+  return g.op == OP_H ? 0 : g.op == OP_CX ? 1 : g.op == OP_CZ ? 2 : 3;
+}
+
+// Estimated time of `items` work items through gates with `cnt[kind]` gates
+// of each kind; the row count scales the per-item throughput term.
+double span_us(const GateCost& c, const double cnt[4], double items, double row_scale) {
+  double t = 0.0;
+  for (int k = 0; k < 4; ++k) t += cnt[k] * std::max(c.lat[k], items * c.thr[k] * row_scale / 65536.0);
+  return t;
 }
 
 uint32_t branch_bits(uint32_t nb) {
@@ -421,11 +449,15 @@ std::vector<double> estimate_distinct(const Instance& I, const std::vector<uint1
   return D;
 }
 
-// Choose checkpoint levels (slot occurrences) minimising the estimated cost:
-// sum over spans of (distinct states at the span's end) x (gate weight of the
-// span) + a fixed cost per level, plus chi x (weight after the last level).
+// Choose checkpoint levels (slot occurrences) and the mapping of each span
+// to minimise the estimated time: a span from level i to level j runs the
+// gates between them on the (estimated) distinct prefixes at j, bounded
+// below by the latency of the gates for a lone wave; every level adds a
+// fixed cost; the last span runs chi terms.  Mode 2 drops the fixed cost and
+// takes any plan that saves work, so that small tests exercise the path.
 void plan_prefix(Instance& I, const std::vector<DGate>& dg) {
   I.plan_cut.clear();
+  I.plan_lanes.clear();
   I.plan_span_off.assign(1, 0);
   I.plan_slot_h.clear();
   I.plan_width_h.clear();
@@ -435,29 +467,42 @@ void plan_prefix(Instance& I, const std::vector<DGate>& dg) {
   std::vector<uint32_t> end;
   for (size_t i = 0; i < dg.size(); ++i) {
     const DGate& g = dg[i];
-    const bool is_slot = g.op == OP_SLOT_SPOW || g.cond;
-    if (!is_slot) continue;
-    const bool cont = !end.empty() && end.back() == i && dg[i - 1].cond && g.cond && occ.back() == g.slot;
-    if (cont) end.back() = (uint32_t)(i + 1);
-    else {
+    if (g.cond & kSlotStart) {
       occ.push_back(g.slot);
       end.push_back((uint32_t)(i + 1));
+    } else if ((g.cond & kCondApply) && !end.empty() && end.back() == i) {
+      end.back() = (uint32_t)(i + 1);
     }
   }
   const size_t m = occ.size();
   if (m == 0 || I.prefix_mode == 0) return;
-  std::vector<double> Wc(dg.size() + 1, 0.0);
-  for (size_t i = 0; i < dg.size(); ++i) Wc[i + 1] = Wc[i] + gate_weight(dg[i]);
-  std::vector<double> G(m + 1, 0.0);
-  for (size_t j = 0; j < m; ++j) G[j + 1] = Wc[end[j]];
-  const double Gt = Wc[dg.size()];
+  // Cumulative gate counts by kind at each level boundary.
+  std::vector<std::array<double, 4>> C(m + 1), Cw(dg.size() + 1);
+  Cw[0] = {0, 0, 0, 0};
+  for (size_t i = 0; i < dg.size(); ++i) {
+    Cw[i + 1] = Cw[i];
+    Cw[i + 1][gate_kind(dg[i])] += 1.0;
+  }
+  C[0] = Cw[0];
+  for (size_t j = 0; j < m; ++j) C[j + 1] = Cw[end[j]];
+  const std::array<double, 4> Ct = Cw[dg.size()];
   const double chi = (double)I.chi;
+  const double rows = (double)I.n / 50.0;  // the table was measured at n = 50
   const std::vector<double> D = estimate_distinct(I, occ);
-  // Fixed cost of a level in weighted term-gates: a few small launches and a
-  // pass over chi terms; a checkpoint state costs one write and one read.
   const bool force = I.prefix_mode == 2;
-  const double c_level = force ? 0.0 : 1.8e6 + 1.2 * chi;
-  const double c_state = force ? 0.0 : 16.0;
+  auto seg = [&](size_t i, size_t j, double items, int* lanes) {
+    double cnt[4];
+    for (int k = 0; k < 4; ++k) cnt[k] = (j <= m ? C[j][k] : Ct[k]) - C[i][k];
+    const double tp = span_us(kCostPacked, cnt, items, rows);
+    const double tw = span_us(kCostWave, cnt, items, rows);
+    if (lanes) *lanes = tw < tp ? 64 : 0;
+    return std::min(tp, tw);
+  };
+  auto work = [&](size_t i, size_t j, double items) {  // weighted gate applications
+    double w = 0;
+    for (int k = 0; k < 4; ++k) w += ((j <= m ? C[j][k] : Ct[k]) - C[i][k]) * (k == 0 ? 8.0 : 1.0);
+    return w * items;
+  };
   std::vector<uint32_t> bits(m + 1, 0);
   for (size_t j = 0; j < m; ++j) bits[j + 1] = bits[j] + branch_bits(I.slots_h[occ[j]].n_branch);
   const double inf = 1e300;
@@ -467,17 +512,18 @@ void plan_prefix(Instance& I, const std::vector<DGate>& dg) {
   for (size_t j = 1; j <= m; ++j)
     for (size_t i = 0; i < j; ++i) {
       if (best[i] >= inf || bits[j] - bits[i] > 32) continue;
-      const double c = best[i] + D[j] * (G[j] - G[i]) + c_level + c_state * D[j];
+      const double c = best[i] + (force ? work(i, j, D[j]) : seg(i, j, D[j], nullptr) + kLevelCostUs);
       if (c < best[j]) {
         best[j] = c;
         from[j] = (int)i;
       }
     }
+  const double plain = force ? work(0, m + 1, chi) : seg(0, m + 1, chi, nullptr);
   size_t last = 0;
-  double total = chi * Gt;
+  double total = plain;
   for (size_t i = 1; i <= m; ++i) {
     if (best[i] >= inf) continue;
-    const double c = best[i] + chi * (Gt - G[i]);
+    const double c = best[i] + (force ? work(i, m + 1, chi) : seg(i, m + 1, chi, nullptr));
     if (c < total) {
       total = c;
       last = i;
@@ -495,9 +541,12 @@ void plan_prefix(Instance& I, const std::vector<DGate>& dg) {
     }
     I.plan_span_off.push_back((uint32_t)I.plan_slot_h.size());
     I.plan_cut.push_back(end[j - 1]);
+    int lanes = 0;
+    seg(prev, j, D[j], &lanes);
+    I.plan_lanes.push_back(lanes);
     prev = j;
   }
-  I.plan_frac = Gt > 0 ? total / (chi * Gt) : 1.0;
+  I.plan_frac = plain > 0 ? total / plain : 1.0;
 }
 
 uint64_t gates_key(const Instance& I, const std::vector<DGate>& dg) {
@@ -532,11 +581,36 @@ TermsView ckpt_view(chsim_ctx* ctx, const Instance& I, int k) {
 
 // Evolve every term of I through the device gate list (ctx->gates, dg on the
 // host), from |0^n> or from the stored terms.
+Instance::SpanStat span_stat(const std::vector<DGate>& dg, uint32_t g0, uint32_t g1, int level,
+                             uint64_t items) {
+  Instance::SpanStat st;
+  st.level = level;
+  st.items = items;
+  for (auto& k : st.kinds) k = 0;
+  for (uint32_t i = g0; i < g1; ++i) {
+    const DGate& g = dg[i];
+    const int kind = (g.cond & kCondApply) ? 4 : g.op == OP_H ? 0 : g.op == OP_CX ? 1 : g.op == OP_CZ ? 2 : 3;
+    ++st.kinds[kind];
+  }
+  return st;
+}
+
 chsim_status evolve_all(chsim_ctx* ctx, Instance& I, const std::vector<DGate>& dg, EvolveShape shape,
                         bool from_zero, hipStream_t s) {
   const uint32_t ng = (uint32_t)dg.size();
+  const uint32_t n_occ_all = (uint32_t)ctx->occ_start.size();
+  // Slot occurrences whose first gate lies in [g0, g1).
+  auto occ_range = [&](uint32_t g0, uint32_t g1, uint32_t* first) {
+    const auto b = std::lower_bound(ctx->occ_start.begin(), ctx->occ_start.end(), g0);
+    const auto e = std::lower_bound(ctx->occ_start.begin(), ctx->occ_start.end(), g1);
+    *first = (uint32_t)(b - ctx->occ_start.begin());
+    return (uint32_t)(e - b);
+  };
+  I.last_spans.clear();
   if (!from_zero || I.prefix_mode == 0) {
-    HIP_TRY(launch_evolve(I.view(), ctx->gates.p, ng, I.slots.p, from_zero, ctx->err.p, shape, s));
+    I.last_spans.push_back(span_stat(dg, 0, ng, -1, I.chi));
+    HIP_TRY(launch_evolve(I.view(), ctx->gates.p, ng, ctx->slotseq.p, n_occ_all, from_zero, ctx->err.p,
+                          shape, s));
     return CHSIM_OK;
   }
   const uint64_t key = gates_key(I, dg);
@@ -554,7 +628,8 @@ chsim_status evolve_all(chsim_ctx* ctx, Instance& I, const std::vector<DGate>& d
   }
   const size_t K = I.plan_cut.size();
   if (K == 0) {
-    HIP_TRY(launch_evolve(I.view(), ctx->gates.p, ng, I.slots.p, true, ctx->err.p, shape, s));
+    I.last_spans.push_back(span_stat(dg, 0, ng, -1, I.chi));
+    HIP_TRY(launch_evolve(I.view(), ctx->gates.p, ng, ctx->slotseq.p, n_occ_all, true, ctx->err.p, shape, s));
     return CHSIM_OK;
   }
   const uint64_t chi = I.chi, n = I.n;
@@ -565,7 +640,7 @@ chsim_status evolve_all(chsim_ctx* ctx, Instance& I, const std::vector<DGate>& d
   HIP_TRY(ctx->pf_slotof.ensure(chi));
   HIP_TRY(ctx->pf_rep.ensure(chi));
   HIP_TRY(ctx->pf_parent.ensure(chi));
-  HIP_TRY(ctx->pf_count.ensure(K));
+  HIP_TRY(I.plan_count.ensure(K));
   for (int k = 0; k < 2; ++k) {
     HIP_TRY(ctx->pf_id[k].ensure(chi));
     HIP_TRY(ctx->ck_F[k].ensure(n * chi));
@@ -590,7 +665,7 @@ chsim_status evolve_all(chsim_ctx* ctx, Instance& I, const std::vector<DGate>& d
     A.table_mask = ts - 1;
     A.ids = ctx->pf_ids.p;
     A.slot_of = ctx->pf_slotof.p;
-    A.counter = ctx->pf_count.p + k;
+    A.counter = I.plan_count.p + k;
     A.id_out = ctx->pf_id[k % 2].p;
     A.rep = ctx->pf_rep.p;
     A.parent = ctx->pf_parent.p;
@@ -602,10 +677,15 @@ chsim_status evolve_all(chsim_ctx* ctx, Instance& I, const std::vector<DGate>& d
     J.br_idx = ctx->pf_rep.p;
     J.branch = I.branch.p;
     J.chi_br = chi;
-    J.count_dev = ctx->pf_count.p + k;
+    J.count_dev = I.plan_count.p + k;
     J.count = chi;
     const uint32_t g1 = I.plan_cut[k];
-    HIP_TRY(launch_evolve_job(J, ctx->gates.p + g0, g1 - g0, I.slots.p, k == 0, ctx->err.p, shape, s));
+    uint32_t o0 = 0;
+    J.n_occ = occ_range(g0, g1, &o0);
+    J.slot_seq = ctx->slotseq.p + o0;
+    I.last_spans.push_back(span_stat(dg, g0, g1, (int)k, 0));
+    const EvolveShape span_shape = I.plan_lanes[k] ? evolve_shape_for(I.n, I.plan_lanes[k]) : shape;
+    HIP_TRY(launch_evolve_job(J, ctx->gates.p + g0, g1 - g0, k == 0, ctx->err.p, span_shape, s));
     prev_id = ctx->pf_id[k % 2].p;
     g0 = g1;
   }
@@ -618,7 +698,11 @@ chsim_status evolve_all(chsim_ctx* ctx, Instance& I, const std::vector<DGate>& d
   J.chi_br = chi;
   J.count_dev = nullptr;
   J.count = chi;
-  HIP_TRY(launch_evolve_job(J, ctx->gates.p + g0, ng - g0, I.slots.p, false, ctx->err.p, shape, s));
+  uint32_t o0 = 0;
+  J.n_occ = occ_range(g0, ng, &o0);
+  J.slot_seq = ctx->slotseq.p + o0;
+  I.last_spans.push_back(span_stat(dg, g0, ng, -1, chi));
+  HIP_TRY(launch_evolve_job(J, ctx->gates.p + g0, ng - g0, false, ctx->err.p, shape, s));
   return CHSIM_OK;
 }
 
@@ -640,17 +724,22 @@ chsim_status chsim_apply_clifford(chsim_ctx* ctx, uint32_t inst, const chsim_gat
       if (g.slot >= I.n_slot) return fail(CHSIM_EINVAL, "gate %zu: slot %u >= n_slot %u", i, g.slot, I.n_slot);
       const SlotTable& tb = I.slots_h[g.slot];
       if (tb.spow_q >= 0) {
-        dg.push_back(DGate{OP_SLOT_SPOW, (uint8_t)tb.spow_q, 0, 0, (uint16_t)g.slot, 0, 0});
+        uint32_t packed = 0;  // branch j -> S^{spow[j]}, two bits each
+        for (uint32_t j = 0; j < tb.n_branch; ++j) packed |= (uint32_t)(tb.spow[j] & 3u) << (2 * j);
+        dg.push_back(DGate{OP_SLOT_SPOW, (uint8_t)tb.spow_q, (uint8_t)(packed & 0xffu), (uint8_t)(packed >> 8),
+                           (uint16_t)g.slot, kSlotStart, 0});
       } else {
         // A general branch list becomes conditional gates: each term applies
         // only the gates of its own branch.
+        bool first = true;
         for (uint32_t j = 0; j < tb.n_branch; ++j)
           for (uint32_t k = tb.goff[j]; k < tb.goff[j + 1]; ++k) {
             DGate bg = I.bgates_h[k];
             bg.slot = (uint16_t)g.slot;
-            bg.cond = 1;
+            bg.cond = (uint8_t)(kCondApply | (first ? kSlotStart : 0));
             bg.arg2 = (uint8_t)j;
             dg.push_back(bg);
+            first = false;
           }
       }
     } else {
@@ -662,6 +751,17 @@ chsim_status chsim_apply_clifford(chsim_ctx* ctx, uint32_t inst, const chsim_gat
   hipStream_t s = as_stream(stream);
   HIP_TRY(ctx->gates.ensure(dg.size()));
   HIP_TRY(hipMemcpyAsync(ctx->gates.p, dg.data(), dg.size() * sizeof(DGate), hipMemcpyHostToDevice, s));
+  ctx->occ_start.clear();
+  ctx->slotseq_h.clear();
+  for (size_t i = 0; i < dg.size(); ++i)
+    if (dg[i].cond & kSlotStart) {
+      ctx->occ_start.push_back((uint32_t)i);
+      ctx->slotseq_h.push_back(dg[i].slot);
+    }
+  HIP_TRY(ctx->slotseq.ensure(ctx->slotseq_h.size()));
+  if (!ctx->slotseq_h.empty())
+    HIP_TRY(hipMemcpyAsync(ctx->slotseq.p, ctx->slotseq_h.data(), ctx->slotseq_h.size() * sizeof(uint32_t),
+                           hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemsetAsync(ctx->err.p, 0, sizeof(uint32_t), s));
   if (I.autotune && I.at_zero) {
     // Every shape computes the same terms from |0^n>, so timing all of them in
@@ -1285,6 +1385,32 @@ chsim_status chsim_get_tuning(chsim_ctx* ctx, uint32_t inst, uint32_t knob, int3
   return CHSIM_OK;
 }
 
+chsim_status chsim_evolution_stats(chsim_ctx* ctx, uint32_t inst, uint64_t apps[5], uint32_t* levels,
+                                   uint64_t* distinct, uint32_t max_levels) {
+  g_err.clear();
+  chsim_status st = check_ctx(ctx, inst);
+  if (st) return st;
+  if (!apps) return fail(CHSIM_EINVAL, "null output");
+  Instance& I = ctx->inst[inst];
+  uint32_t K = 0;
+  for (const auto& sp : I.last_spans) K = std::max<uint32_t>(K, (uint32_t)(sp.level + 1));
+  std::vector<uint32_t> counts(K, 0);
+  if (K) {
+    HIP_TRY(hipSetDevice(ctx->device));
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipMemcpy(counts.data(), I.plan_count.p, K * sizeof(uint32_t), hipMemcpyDeviceToHost));
+  }
+  for (int k = 0; k < 5; ++k) apps[k] = 0;
+  for (const auto& sp : I.last_spans) {
+    const uint64_t items = sp.level >= 0 ? counts[sp.level] : sp.items;
+    for (int k = 0; k < 5; ++k) apps[k] += items * sp.kinds[k];
+  }
+  if (levels) *levels = K;
+  if (distinct)
+    for (uint32_t k = 0; k < std::min(K, max_levels); ++k) distinct[k] = counts[k];
+  return CHSIM_OK;
+}
+
 chsim_status chsim_instance_info(chsim_ctx* ctx, uint32_t inst, uint32_t* n, uint64_t* chi, double* l1) {
   g_err.clear();
   chsim_status st = check_ctx(ctx, inst);
@@ -1309,12 +1435,12 @@ chsim_status chsim_destroy(chsim_ctx* ctx) {
   ctx->amp_items.release();
   ctx->amp_prefix.release();
   ctx->amp_counter.release();
+  ctx->slotseq.release();
   ctx->pf_table.release();
   ctx->pf_ids.release();
   ctx->pf_slotof.release();
   ctx->pf_rep.release();
   ctx->pf_parent.release();
-  ctx->pf_count.release();
   for (int k = 0; k < 2; ++k) {
     ctx->pf_id[k].release();
     ctx->ck_F[k].release();

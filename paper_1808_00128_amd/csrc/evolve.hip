@@ -86,20 +86,19 @@ bool evolve_shape_supported(EvolveShape s, uint32_t n) {
   return lanes_ok && s.rows >= 1 && (uint32_t)(s.lanes * s.rows) >= n && s.lanes * s.rows <= 64;
 }
 
-hipError_t launch_evolve_job(const EvolveJob& J, const DGate* gates, uint32_t n_gates,
-                             const SlotTable* slots, bool from_zero, uint32_t* err, EvolveShape shape,
-                             hipStream_t st) {
+hipError_t launch_evolve_job(const EvolveJob& J, const DGate* gates, uint32_t n_gates, bool from_zero,
+                             uint32_t* err, EvolveShape shape, hipStream_t st) {
   const uint32_t n = J.dst.n;
   if (shape.lanes == 0) shape = evolve_default_shape(n);
   if (!evolve_shape_supported(shape, n)) return hipErrorInvalidValue;
-  if (shape.lanes == 4) return launch_evolve_l4(shape.rows, J, gates, n_gates, slots, from_zero, err, st);
-  if (shape.lanes == 8) return launch_evolve_l8(shape.rows, J, gates, n_gates, slots, from_zero, err, st);
-  return launch_evolve_wide(shape.lanes, shape.rows, J, gates, n_gates, slots, from_zero, err, st);
+  if (shape.lanes == 4) return launch_evolve_l4(shape.rows, J, gates, n_gates, from_zero, err, st);
+  if (shape.lanes == 8) return launch_evolve_l8(shape.rows, J, gates, n_gates, from_zero, err, st);
+  return launch_evolve_wide(shape.lanes, shape.rows, J, gates, n_gates, from_zero, err, st);
 }
 
 hipError_t launch_evolve(const TermsView& T, const DGate* gates, uint32_t n_gates,
-                         const SlotTable* slots, bool from_zero, uint32_t* err, EvolveShape shape,
-                         hipStream_t st) {
+                         const uint32_t* slot_seq, uint32_t n_occ, bool from_zero, uint32_t* err,
+                         EvolveShape shape, hipStream_t st) {
   EvolveJob J;
   J.src = T;
   J.dst = T;
@@ -109,7 +108,9 @@ hipError_t launch_evolve(const TermsView& T, const DGate* gates, uint32_t n_gate
   J.chi_br = T.chi;
   J.count_dev = nullptr;
   J.count = T.chi;
-  return launch_evolve_job(J, gates, n_gates, slots, from_zero, err, shape, st);
+  J.slot_seq = slot_seq;
+  J.n_occ = n_occ;
+  return launch_evolve_job(J, gates, n_gates, from_zero, err, shape, st);
 }
 
 // Materialise |0^n> for every term (used when terms are read before any gate).

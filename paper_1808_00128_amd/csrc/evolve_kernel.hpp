@@ -61,45 +61,47 @@ struct Lane {
   uint32_t li, base;  // lane index in the group, first lane of the group
 };
 
-// L[S_q]^pw (pw may differ between groups): M_q ^= G_q pw times, gamma_q -= pw.
+// Left rules L[S]^pw, L[CZ], L[CX] in one shape: the gate decides (on the
+// scalar unit) which rows are read and broadcast in the group and what is
+// XORed into rows q and r; the writes themselves are unconditional, so the
+// row arrays are never modified on divergent or per-gate paths (that would
+// make the compiler copy whole arrays at every join).
+//   S^pw on q:   M_q ^= G_q pw times, gamma_q -= pw
+//   CZ_{q,r}:    M_q ^= G_r, M_r ^= G_q
+//   CX_{q,r}:    gamma_q += gamma_r + 2 (M_q . F_r) (M_q before the update),
+//                G_r ^= G_q, F_q ^= F_r, M_q ^= M_r
+// `on` is false for terms that skip the gate (a branch of another choice).
 template <int LPT, int RPL>
-__device__ __forceinline__ void sw_spow(SubCH<LPT, RPL>& c, Lane L, uint32_t q, uint32_t pw) {
-  const uint32_t own = (L.li == q % LPT) ? 1u : 0u;
-  const uint64_t odd = 0ull - (uint64_t)(pw & own & 1u);
-  const uint32_t sub = pw & (0u - own);
-  const uint32_t k = uniform32(q / LPT);
-  c.M[k] ^= c.G[k] & odd;
-  c.g[k] = (c.g[k] - sub) & 3u;
-}
-
-// L[CZ_{q,r}]: M_q ^= G_r, M_r ^= G_q.
-template <int LPT, int RPL>
-__device__ __forceinline__ void sw_cz(SubCH<LPT, RPL>& c, Lane L, uint32_t q, uint32_t r) {
+__device__ __forceinline__ void sw_left(SubCH<LPT, RPL>& c, Lane L, uint32_t op, uint32_t q,
+                                        uint32_t r, uint32_t pw, bool on) {
   const uint32_t kq = uniform32(q / LPT), kr = uniform32(r / LPT);
-  const uint64_t Gq = gb64<LPT>(c.G[kq], q % LPT, L.base);
-  const uint64_t Gr = gb64<LPT>(c.G[kr], r % LPT, L.base);
-  const uint64_t oq = 0ull - (uint64_t)(L.li == q % LPT);
-  const uint64_t orr = 0ull - (uint64_t)(L.li == r % LPT);
-  c.M[kq] ^= Gr & oq;
-  c.M[kr] ^= Gq & orr;
-}
-
-// L[CX_{q,r}]: gamma_q += gamma_r + 2 (M_q . F_r) with M_q before its update;
-// G_r ^= G_q; F_q ^= F_r; M_q ^= M_r.
-template <int LPT, int RPL>
-__device__ __forceinline__ void sw_cx(SubCH<LPT, RPL>& c, Lane L, uint32_t q, uint32_t r) {
-  const uint32_t kq = uniform32(q / LPT), kr = uniform32(r / LPT);
-  const uint64_t Fr = gb64<LPT>(c.F[kr], r % LPT, L.base);
-  const uint64_t Mr = gb64<LPT>(c.M[kr], r % LPT, L.base);
-  const uint32_t gr = gb32<LPT>(c.g[kr], r % LPT, L.base);
-  const uint64_t Gq = gb64<LPT>(c.G[kq], q % LPT, L.base);
-  const uint64_t oq = 0ull - (uint64_t)(L.li == q % LPT);
-  const uint64_t orr = 0ull - (uint64_t)(L.li == r % LPT);
-  const uint64_t Mq = c.M[kq];
-  c.g[kq] = (c.g[kq] + ((gr + 2u * par64(Mq & Fr)) & (uint32_t)oq)) & 3u;
-  c.F[kq] ^= Fr & oq;
-  c.M[kq] = Mq ^ (Mr & oq);
-  c.G[kr] ^= Gq & orr;
+  const uint64_t oq = 0ull - (uint64_t)(on && L.li == q % LPT);
+  const uint64_t orr = 0ull - (uint64_t)(on && L.li == r % LPT);
+  uint64_t dFq = 0, dMq = 0, dGr = 0, dMr = 0;
+  uint32_t dgq = 0;
+  if (op == OP_CX) {
+    const uint64_t Fr = gb64<LPT>(c.F[kr], r % LPT, L.base);
+    const uint64_t Mr = gb64<LPT>(c.M[kr], r % LPT, L.base);
+    const uint32_t gr = gb32<LPT>(c.g[kr], r % LPT, L.base);
+    const uint64_t Gq = gb64<LPT>(c.G[kq], q % LPT, L.base);
+    dFq = Fr & oq;
+    dMq = Mr & oq;
+    dgq = (gr + 2u * par64(c.M[kq] & Fr)) & (uint32_t)oq;
+    dGr = Gq & orr;
+  } else if (op == OP_CZ) {
+    const uint64_t Gq = gb64<LPT>(c.G[kq], q % LPT, L.base);
+    const uint64_t Gr = gb64<LPT>(c.G[kr], r % LPT, L.base);
+    dMq = Gr & oq;
+    dMr = Gq & orr;
+  } else {
+    dMq = c.G[kq] & oq & (0ull - (uint64_t)(pw & 1u));
+    dgq = (0u - pw) & (uint32_t)oq;
+  }
+  c.F[kq] ^= dFq;
+  c.M[kq] ^= dMq;
+  c.g[kq] = (c.g[kq] + dgq) & 3u;
+  c.G[kr] ^= dGr;
+  c.M[kr] ^= dMr;
 }
 
 // Hadamard on qubit p: Eqs. (H2), (H4), the t = u case, and Prop. H with
@@ -194,14 +196,14 @@ __device__ __forceinline__ void sw_h(SubCH<LPT, RPL>& c, Lane L, uint32_t p) {
 // choices from term br_idx[i] of the term store, and leaves its result in
 // state i of J.dst (see EvolveJob).
 // ---------------------------------------------------------------------------
+constexpr uint32_t kGateChunk = 2048;  // gates staged in LDS at a time (16 KiB)
+
 template <int LPT, int RPL, bool kFromZero>
 __global__ __launch_bounds__(256) void k_evolve(EvolveJob J, const DGate* __restrict__ gates,
-                                                uint32_t n_gates,
-                                                const SlotTable* __restrict__ slots,
-                                                uint32_t* __restrict__ err) {
+                                                uint32_t n_gates, uint32_t* __restrict__ err) {
   constexpr int kTermsPerBlock = 256 / LPT;
   const uint64_t count = J.count_dev ? (uint64_t)*J.count_dev : J.count;
-  if ((uint64_t)blockIdx.x * kTermsPerBlock >= count) return;  // no barrier in this kernel
+  if ((uint64_t)blockIdx.x * kTermsPerBlock >= count) return;  // whole block: no barrier skipped
   const uint32_t lane = threadIdx.x & 63u;
   Lane L;
   L.li = lane & (LPT - 1);
@@ -252,24 +254,41 @@ __global__ __launch_bounds__(256) void k_evolve(EvolveJob J, const DGate* __rest
   }
   c.err = 0u;
   // One flat gate list: slot gates are SLOT_SPOW (a per-term power of S) or
-  // conditional gates of a general branch.  Gate fields are wave-uniform.
-  for (uint32_t i = 0; i < n_gates; ++i) {
-    const DGate gt = gates[i];
-    const uint32_t op = uniform32(gt.op), q = uniform32(gt.q), r = uniform32(gt.r);
-    uint32_t pw = 1u;
-    if (op == OP_SLOT_SPOW) pw = slots[gt.slot].spow[branch[(uint64_t)gt.slot * chb + ba]];
-    else if (op == OP_SPOW) pw = uniform32(gt.arg);
-    bool on = true;
-    if (gt.cond) on = branch[(uint64_t)gt.slot * chb + ba] == gt.arg2;
-    if (on) {
-      switch (op) {
-        case OP_H: sw_h(c, L, q); break;
-        case OP_S:
-        case OP_SPOW:
-        case OP_SLOT_SPOW: sw_spow(c, L, q, pw); break;
-        case OP_CX: sw_cx(c, L, q, r); break;
-        case OP_CZ: sw_cz(c, L, q, r); break;
-        default: break;
+  // conditional gates of a general branch.  A gate is two 32-bit words read
+  // on the scalar unit (wave-uniform); the term's branch choice for the next
+  // slot occurrence is loaded one occurrence ahead.
+  const uint2* __restrict__ g2 = reinterpret_cast<const uint2*>(gates);
+  const uint32_t* __restrict__ seq = J.slot_seq;
+  const uint32_t n_occ = J.n_occ;
+  uint32_t next_b = n_occ ? (uint32_t)branch[(uint64_t)seq[0] * chb + ba] : 0u;
+  uint32_t cur_b = 0u, occ = 1u;
+  // The gate list goes through LDS in chunks (one barrier pair per chunk);
+  // every wave reads gate i + 1 while it applies gate i.
+  __shared__ uint2 sg[kGateChunk];
+  for (uint32_t c0 = 0; c0 < n_gates; c0 += kGateChunk) {
+    const uint32_t cn = min((uint32_t)kGateChunk, n_gates - c0);
+    __syncthreads();
+    for (uint32_t t = threadIdx.x; t < cn; t += 256u) sg[t] = g2[c0 + t];
+    __syncthreads();
+    uint2 nxt = sg[0];
+    for (uint32_t i = 0; i < cn; ++i) {
+      const uint32_t w0 = uniform32(nxt.x), w1 = uniform32(nxt.y);
+      nxt = sg[i + 1 < cn ? i + 1 : i];
+      const uint32_t op = w0 & 0xffu, q = (w0 >> 8) & 0xffu, r = (w0 >> 16) & 0xffu;
+      const uint32_t cond = (w1 >> 16) & 0xffu;
+      if (cond & kSlotStart) {
+        cur_b = next_b;
+        if (occ < n_occ) next_b = (uint32_t)branch[(uint64_t)seq[occ] * chb + ba];
+        ++occ;
+      }
+      uint32_t pw = 1u;
+      if (op == OP_SLOT_SPOW) pw = ((w0 >> 16) >> (2u * cur_b)) & 3u;
+      else if (op == OP_SPOW) pw = w0 >> 24;
+      const bool on = !(cond & kCondApply) || cur_b == (w1 >> 24);
+      if (op == OP_H) {
+        if (on) sw_h(c, L, q);
+      } else {
+        sw_left(c, L, op, q, op == OP_CX || op == OP_CZ ? r : q, pw, on);
       }
     }
   }
@@ -296,17 +315,17 @@ __global__ __launch_bounds__(256) void k_evolve(EvolveJob J, const DGate* __rest
 }
 
 template <int LPT, int RPL>
-hipError_t launch_evolve_t(const EvolveJob& J, const DGate* gates, uint32_t n_gates,
-                           const SlotTable* slots, bool from_zero, uint32_t* err, hipStream_t st) {
+hipError_t launch_evolve_t(const EvolveJob& J, const DGate* gates, uint32_t n_gates, bool from_zero,
+                           uint32_t* err, hipStream_t st) {
   constexpr int kTermsPerBlock = 256 / LPT;
   const uint32_t blocks = (uint32_t)((J.count + kTermsPerBlock - 1) / kTermsPerBlock);
   if (blocks == 0) return hipSuccess;
   if (from_zero)
     hipLaunchKernelGGL((k_evolve<LPT, RPL, true>), dim3(blocks), dim3(256), 0, st, J, gates, n_gates,
-                       slots, err);
+                       err);
   else
     hipLaunchKernelGGL((k_evolve<LPT, RPL, false>), dim3(blocks), dim3(256), 0, st, J, gates,
-                       n_gates, slots, err);
+                       n_gates, err);
   return hipGetLastError();
 }
 

@@ -4,11 +4,10 @@
 namespace chsim {
 
 hipError_t launch_evolve_wide(int lanes, int rows, const EvolveJob& J, const DGate* gates,
-                              uint32_t n_gates, const SlotTable* slots, bool from_zero,
-                              uint32_t* err, hipStream_t st) {
+                              uint32_t n_gates, bool from_zero, uint32_t* err, hipStream_t st) {
 #define CHSIM_CASE(LN, R)                                                              \
   if (lanes == LN && rows == R)                                                        \
-    return launch_evolve_t<LN, R>(J, gates, n_gates, slots, from_zero, err, st);
+    return launch_evolve_t<LN, R>(J, gates, n_gates, from_zero, err, st);
   CHSIM_CASE(16, 1) CHSIM_CASE(16, 2) CHSIM_CASE(16, 3) CHSIM_CASE(16, 4)
   CHSIM_CASE(32, 1) CHSIM_CASE(32, 2)
   CHSIM_CASE(64, 1)

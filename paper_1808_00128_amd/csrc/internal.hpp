@@ -17,15 +17,20 @@ namespace chsim {
 enum : uint8_t { OP_H = 0, OP_S = 1, OP_CX = 2, OP_CZ = 3, OP_SLOT = 4, OP_SPOW = 5,
                  OP_SLOT_SPOW = 6 };
 
-// A gate of the flat device list.  `slot` is the slot index for SLOT_SPOW;
-// for a gate of a general slot branch, cond = 1 and the gate applies only to
-// terms whose branch choice of slot `slot` equals `arg2`.
+// A gate of the flat device list (8 bytes, read by the kernels as two
+// 32-bit words on the scalar unit).  `slot` is the slot index of a slot
+// gate.  SLOT_SPOW: the slot's branches are powers of S on qubit q; branch j
+// applies S^{(r | arg << 8) >> 2j & 3}.  A gate of a general slot branch has
+// kCondApply in cond and applies only to terms whose choice for the slot is
+// arg2.  kSlotStart in cond marks the first gate of a slot occurrence, where
+// the term's branch choice for that slot is needed.
 struct DGate {
   uint8_t op, q, r, arg;
   uint16_t slot;
   uint8_t cond, arg2;
 };
 static_assert(sizeof(DGate) == 8, "DGate is 8 bytes");
+constexpr uint8_t kCondApply = 1, kSlotStart = 2;
 
 // One slot's decomposition as the kernels read it.
 struct SlotTable {
@@ -95,6 +100,9 @@ bool evolve_shape_supported(EvolveShape s, uint32_t n);
 // src_idx[i] (i if null) of src, takes its branch choices from column
 // br_idx[i] (i if null) of branch [slot][chi_br], and writes state i of dst.
 // src may equal dst when src_idx is null (in-place update).
+// slot_seq[k] is the slot of the k-th slot occurrence of the launch's gates
+// (n_occ of them): the kernel prefetches each term's choice one occurrence
+// ahead.
 struct EvolveJob {
   TermsView src, dst;
   const uint32_t* src_idx;
@@ -103,20 +111,20 @@ struct EvolveJob {
   uint64_t chi_br;
   const uint32_t* count_dev;
   uint64_t count;
+  const uint32_t* slot_seq;
+  uint32_t n_occ;
 };
-hipError_t launch_evolve_job(const EvolveJob& J, const DGate* gates, uint32_t n_gates,
-                             const SlotTable* slots, bool from_zero, uint32_t* err, EvolveShape shape,
-                             hipStream_t st);
+hipError_t launch_evolve_job(const EvolveJob& J, const DGate* gates, uint32_t n_gates, bool from_zero,
+                             uint32_t* err, EvolveShape shape, hipStream_t st);
 hipError_t launch_evolve_l4(int rows, const EvolveJob& J, const DGate* gates, uint32_t n_gates,
-                            const SlotTable* slots, bool from_zero, uint32_t* err, hipStream_t st);
+                            bool from_zero, uint32_t* err, hipStream_t st);
 hipError_t launch_evolve_l8(int rows, const EvolveJob& J, const DGate* gates, uint32_t n_gates,
-                            const SlotTable* slots, bool from_zero, uint32_t* err, hipStream_t st);
+                            bool from_zero, uint32_t* err, hipStream_t st);
 hipError_t launch_evolve_wide(int lanes, int rows, const EvolveJob& J, const DGate* gates,
-                              uint32_t n_gates, const SlotTable* slots, bool from_zero,
-                              uint32_t* err, hipStream_t st);
+                              uint32_t n_gates, bool from_zero, uint32_t* err, hipStream_t st);
 hipError_t launch_evolve(const TermsView& T, const DGate* gates, uint32_t n_gates,
-                         const SlotTable* slots, bool from_zero, uint32_t* err, EvolveShape shape,
-                         hipStream_t st);
+                         const uint32_t* slot_seq, uint32_t n_occ, bool from_zero, uint32_t* err,
+                         EvolveShape shape, hipStream_t st);
 hipError_t launch_set_zero(const TermsView& T, hipStream_t st);
 
 // One checkpoint level of shared-prefix evolution.  For every term a < chi:

@@ -50,18 +50,31 @@ __global__ __launch_bounds__(256) void k_prefix_insert(PrefixLevelArgs A) {
   // The table has at least twice as many entries as keys: a free or
   // matching entry is always reached within table_mask + 1 probes.
   for (uint64_t probe = 0; probe <= A.table_mask; ++probe) {
-    const uint64_t old = atomicCAS((unsigned long long*)&A.table[h], (unsigned long long)kEmpty,
-                                   (unsigned long long)key);
-    if (old == kEmpty || old == key) break;
+    // Many terms share a key: look before the atomic.
+    const uint64_t seen = __atomic_load_n(&A.table[h], __ATOMIC_RELAXED);
+    if (seen == key) break;
+    if (seen == kEmpty) {
+      const uint64_t old = atomicCAS((unsigned long long*)&A.table[h], (unsigned long long)kEmpty,
+                                     (unsigned long long)key);
+      if (old == kEmpty || old == key) break;
+    }
     h = (h + 1) & A.table_mask;
   }
   A.slot_of[a] = (uint32_t)h;
 }
 
+// One atomic per wave: the wave's occupied entries take consecutive ids.
 __global__ __launch_bounds__(256) void k_prefix_assign(PrefixLevelArgs A) {
   const uint64_t h = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (h > A.table_mask) return;
-  if (A.table[h] != kEmpty) A.ids[h] = atomicAdd(A.counter, 1u);
+  const bool occ = h <= A.table_mask && A.table[h] != kEmpty;
+  const uint64_t m = ballot64(occ);
+  if (m == 0ull) return;
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t leader = (uint32_t)__builtin_ctzll(m);
+  uint32_t base = 0;
+  if (lane == leader) base = atomicAdd(A.counter, (uint32_t)__popcll(m));
+  base = (uint32_t)__builtin_amdgcn_readlane((int)base, (int)leader);
+  if (occ) A.ids[h] = base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
 }
 
 // Term a's id, the representative term of each id (any term with that
