@@ -108,59 +108,10 @@ def start_points(ctx, n, chi, count, rng):
     return np.array(xs[:count], np.uint64)
 
 
-def bench_metropolis(torch, B, W, stats, steps=1000, n_chain=64, chi=1 << 20):
-    """QAOA-shaped sampling: n = 50, 60 triples, chi = 2^20, 64 chains x 1000
-    single-bit-flip steps; ESS of the Max-E3LIN2 cost by Wolff's Gamma method."""
-    cfg = W.config_qaoa(chi=chi, n_chain=n_chain, steps=steps)
-    circ = cfg["circuit"]
-    n = circ.n
-    dev = torch.device("cuda:0")
-    ctx = B.Context([cfg])
-    ctx.set_evolve_lanes(-1)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    stream = torch.cuda.current_stream()
-    e0.record(stream)
-    ctx.apply_circuit(circ)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    evolve_ms = e0.elapsed_time(e1)
-    rng = np.random.default_rng(cfg["seed"] + 1)
-    x0 = start_points(ctx, n, chi, n_chain, rng)
-    ctx.metropolis_init(x0)
-    j = torch.from_numpy(cfg["jstream"].astype(np.int32)).to(dev)
-    u = torch.from_numpy(cfg["ustream"]).to(dev)
-    trace = torch.empty((n_chain, steps), dtype=torch.int64, device=dev)
-    acc = torch.empty((n_chain, steps), dtype=torch.uint8, device=dev)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    ctx.metropolis_step_device(j, u, trace, acc)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
-    tr = trace.cpu().numpy().view(np.uint64)
-    ac = acc.cpu().numpy()
-    ctx.close()
-    burn = steps // 5
-    cost = stats.qaoa_cost(tr[:, burn:], cfg["triples"], cfg["d"])
-    tau, win, tau_err = stats.tau_int(cost)
-    ess = cost.size / (2 * tau)
-    bytes_step = chi * (n_chain * (8 + 8 + 17) + 33)
-    achieved = bytes_step * steps / (ms / 1e3) / 1e9
-    return {"workload": cfg["name"] + ": QAOA p=1 Max-E3LIN2, n=50, 60 triples, gamma,beta~U(0,pi), "
-                        "chi=2^20, 64 chains x 1000 steps, single-bit-flip proposal",
-            "evolve_ms": evolve_ms, "ms_per_step": ms / steps,
-            "chain_steps_per_s": n_chain * steps / (ms / 1e3),
-            "acceptance": float(ac.mean()), "burn_in": burn,
-            "tau_int": tau, "tau_int_err": tau_err, "window": win,
-            "ess": ess, "ess_per_s": ess / (ms / 1e3),
-            "mean_cost": float(cost.mean()),
-            "roofline": {"bound": "hbm", "kernel": "k_metro_propose + k_metro_accept",
-                         "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
-                         "frac": round(achieved / 8000.0, 4), "traffic": None,
-                         "bytes_per_step": bytes_step}}
-
-
-def run_plain(torch, ctx, x0, jstream, ustream):
+def run_plain(torch, ctx, x0, jstream, ustream, graph=None):
+    """The chains' steps launched kernel by kernel (timed); with a dict in
+    `graph`, the same steps again from a recorded HIP graph: time of the
+    replay and whether the trajectories agree."""
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
     n_chain, steps = jstream.shape
@@ -175,7 +126,23 @@ def run_plain(torch, ctx, x0, jstream, ustream):
     ctx.metropolis_step_device(j, u, trace, acc)
     e1.record(stream)
     torch.cuda.synchronize()
-    return trace.cpu().numpy().view(np.uint64), acc.cpu().numpy(), e0.elapsed_time(e1)
+    ms = e0.elapsed_time(e1)
+    tr, ac = trace.cpu().numpy().view(np.uint64), acc.cpu().numpy()
+    if graph is not None:
+        trace2 = torch.empty_like(trace)
+        acc2 = torch.empty_like(acc)
+        same = True
+        for rep in range(2):  # the first call records the graph, the second replays it
+            ctx.metropolis_init(x0)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            ctx.metropolis_step_device(j, u, trace2, acc2, graph=True)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            same = same and bool(torch.equal(trace, trace2)) and bool(torch.equal(acc, acc2))
+        graph.update(ms_per_step_graph=e0.elapsed_time(e1) / steps, ms_per_step_launches=ms / steps,
+                     trajectories_equal=same)
+    return tr, ac, ms
 
 
 def run_learned(torch, ctx, net, x0, streams, eps, pi_min, pi_max):
@@ -215,6 +182,13 @@ def train_proposal(B, W, ctx, n, trace, burn, delta, epochs=20, hidden=256, batc
                  "loss_last": float(losses[-1])}
 
 
+def chain_step_bytes(chi, n, n_chain):
+    """HBM bytes of one chain step: per term, its n rows (F_p, M_p 8 B each,
+    gamma_p 1 B) read once for all chains, each chain's cached word read and
+    the proposal word written (16 B), and the term's constants (33 B)."""
+    return float(chi * (17 * n + 16 * n_chain + 33))
+
+
 def chain_report(stats, trace, acc, ms, burn, obs, flips=None):
     tau, win, err = stats.tau_int(obs)
     ess = obs.size / (2 * tau)
@@ -237,12 +211,14 @@ def bench_learned(torch, B, W, stats, steps=1000, n_chain=64, chi=1 << 20, eps=0
     rng = np.random.default_rng(cfg["seed"] + 1)
     x0 = start_points(ctx, n, chi, n_chain, rng)
     burn = steps // 5
-    tr, ac, ms = run_plain(torch, ctx, x0, cfg["jstream"], cfg["ustream"])
+    graph = {}
+    tr, ac, ms = run_plain(torch, ctx, x0, cfg["jstream"], cfg["ustream"], graph=graph)
     cost = stats.qaoa_cost(tr[:, burn:], cfg["triples"], cfg["d"])
     plain = chain_report(stats, tr, ac, ms, burn, cost)
-    bytes_step = chi * (n_chain * (8 + 8 + 17) + 33)
+    plain["hip_graph"] = graph
+    bytes_step = chain_step_bytes(chi, n, n_chain)
     achieved = bytes_step * steps / (ms / 1e3) / 1e9
-    plain["roofline"] = {"bound": "hbm", "kernel": "k_metro_propose + k_metro_accept",
+    plain["roofline"] = {"bound": "hbm", "kernel": "k_propose<single flip> + k_metro_accept",
                          "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
                          "frac": round(achieved / 8000.0, 4), "traffic": None,
                          "bytes_per_step": bytes_step}
@@ -252,9 +228,9 @@ def bench_learned(torch, B, W, stats, steps=1000, n_chain=64, chi=1 << 20, eps=0
     ltr, lac, lfl, lms = run_learned(torch, ctx, net, x0, streams, eps, pi_min, pi_max)
     lcost = stats.qaoa_cost(ltr[:, burn:], cfg["triples"], cfg["d"])
     learned = chain_report(stats, ltr, lac, lms, burn, lcost, lfl)
-    lbytes = chi * (n_chain * (16 + float(lfl.mean()) * 17) + 33)
+    lbytes = chain_step_bytes(chi, n, n_chain)
     lach = lbytes * steps / (lms / 1e3) / 1e9
-    learned["roofline"] = {"bound": "hbm", "kernel": "k_learned_propose + network + accept",
+    learned["roofline"] = {"bound": "hbm", "kernel": "k_propose<masks> + network + accept",
                            "achieved": round(lach, 1), "peak": 8000.0, "unit": "GB/s",
                            "frac": round(lach / 8000.0, 4), "traffic": None,
                            "bytes_per_step": lbytes}
@@ -267,10 +243,11 @@ def bench_learned(torch, B, W, stats, steps=1000, n_chain=64, chi=1 << 20, eps=0
 
 
 def bench_matched_tv(torch, B, W, stats, n=12, triples=16, chi=1 << 16, n_chain=64, steps=3200,
-                     eps=0.1, pi_min=0.002, pi_max=0.5, target=0.05):
+                     eps=0.1, pi_min=0.002, pi_max=0.5, target=0.10):
     """n = 12 twin of the QAOA workload: steps and seconds until the pooled
     samples of 64 chains are within `target` total variation of the exact law
-    (all 4096 amplitudes), plain vs learned proposal."""
+    (all 4096 amplitudes), plain vs learned proposal.  `iid_floor` is the TV of
+    the same number of independent exact samples: no chain can go below it."""
     rng = np.random.default_rng(2012)
     circ = W.qaoa_circuit(n, triples, rng)[0]
     spec = dict(circuit=circ, chi=chi, mode="sparsify", seed=2012)
@@ -280,8 +257,8 @@ def bench_matched_tv(torch, B, W, stats, n=12, triples=16, chi=1 << 16, n_chain=
     P /= P.sum()
     x0 = np.array(rng.choice(2**n, size=n_chain, p=P), np.uint64)  # start in equilibrium
     j, u = W.metropolis_streams(n, n_chain, steps, rng)
-    tr, ac, ms = run_plain(torch, ctx, x0, j, u)
-    obs = tr.astype(np.float64)
+    graph = {}
+    tr, ac, ms = run_plain(torch, ctx, x0, j, u, graph=graph)
     tau, _, _ = stats.tau_int(np.array([bin(int(v)).count("1") for v in tr.ravel()],
                                        np.float64).reshape(tr.shape))
     net, train = train_proposal(B, W, ctx, n, tr, 0, max(1, int(round(tau))), epochs=30, hidden=128)
@@ -295,6 +272,8 @@ def bench_matched_tv(torch, B, W, stats, n=12, triples=16, chi=1 << 16, n_chain=
         return {c: stats.total_variation(t[:, :c].ravel(), P) for c in checkpoints if c <= steps}
 
     cp, cl = curve(tr), curve(ltr)
+    iid = rng.choice(2**n, size=(n_chain, steps), p=P).astype(np.uint64)
+    floor = curve(iid)
 
     def first(c):
         hit = [k for k, v in c.items() if v <= target]
@@ -303,10 +282,10 @@ def bench_matched_tv(torch, B, W, stats, n=12, triples=16, chi=1 << 16, n_chain=
     sp, sl = first(cp), first(cl)
     per_p, per_l = ms / steps, lms / steps
     return {"workload": f"qaoa-n{n}-{triples}triples-chi{chi}, {n_chain} chains started from P",
-            "tv_target": target,
+            "tv_target": target, "iid_floor": floor,
             "plain": {"tv_by_steps": cp, "steps_to_target": sp, "ms_per_step": per_p,
                       "seconds_to_target": (sp * per_p / 1e3) if sp else None,
-                      "acceptance": float(ac.mean())},
+                      "acceptance": float(ac.mean()), "hip_graph": graph},
             "learned": {"tv_by_steps": cl, "steps_to_target": sl, "ms_per_step": per_l,
                         "seconds_to_target": (sl * per_l / 1e3) if sl else None,
                         "acceptance": float(lac.mean()), "mean_flips": float(lfl.mean()),

@@ -91,6 +91,10 @@ typedef struct chsim_ctx chsim_ctx;
 #define CHSIM_FP64 0u          /* amplitudes summed in FP64 */
 #define CHSIM_FP32C 1u         /* FP32 with per-block two-sum, FP64 across blocks */
 #define CHSIM_DEVICE_PTRS 0x100u
+/* chsim_metropolis_step: record the n_steps steps' kernel launches once in a
+ * HIP graph and replay it while the call's sizes and buffers stay the same
+ * (one graph launch per call instead of two kernel launches per step). */
+#define CHSIM_GRAPH 0x200u
 
 /* Create a context on HIP device `device` holding n_inst instances; for each,
  * choose every term's branches and coefficient b_alpha (exact enumeration or
@@ -169,7 +173,10 @@ chsim_status chsim_metropolis_init(chsim_ctx* ctx, uint32_t inst, uint32_t n_cha
  * on the device for device pointers) and accepts iff
  * u_stream[c*n_steps + t] < |<y|psi>|^2 / |<x|psi>|^2 (FP64 sums, FP64
  * ratio).  x_trace[c*n_steps + t] receives the state after step t, accepted[...]
- * 1/0 (both may be NULL); amp (may be NULL) receives the final <x_c|psi>. */
+ * 1/0 (both may be NULL); amp (may be NULL) receives the final <x_c|psi>.
+ * flags: CHSIM_DEVICE_PTRS, CHSIM_GRAPH (same results, launched from a cached
+ * graph of the n_steps steps; the graph is kept per instance until the
+ * buffers, n_steps or the chains change, or the context is destroyed). */
 chsim_status chsim_metropolis_step(chsim_ctx* ctx, uint32_t inst, uint32_t n_steps,
                                    const uint32_t* j_stream, const double* u_stream,
                                    uint64_t* x_trace, uint8_t* accepted, double* amp,

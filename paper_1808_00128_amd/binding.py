@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(PKG, "libchsim.so")
 CHSIM_OK, CHSIM_EINVAL, CHSIM_ENOMEM, CHSIM_EDEVICE, CHSIM_EUNSUPPORTED, CHSIM_ESTATE = range(6)
 STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "EUNSUPPORTED", 5: "ESTATE"}
 CHSIM_EXACT, CHSIM_SPARSIFY = 0, 1
-CHSIM_FP64, CHSIM_FP32C, CHSIM_DEVICE_PTRS = 0, 1, 0x100
+CHSIM_FP64, CHSIM_FP32C, CHSIM_DEVICE_PTRS, CHSIM_GRAPH = 0, 1, 0x100, 0x200
 CHSIM_TUNE_EVOLVE_LANES = 1
 CHSIM_TUNE_PREFIX_SHARE = 2
 MAX_BRANCH = 8
@@ -366,8 +366,9 @@ class Context:
         self._n_chain = x0.size
         return amp[0::2] + 1j * amp[1::2]
 
-    def metropolis_step(self, jstream, ustream, inst=0, trace=True, stream=None):
-        """Advance all chains; jstream/ustream are [n_chain, n_steps]."""
+    def metropolis_step(self, jstream, ustream, inst=0, trace=True, stream=None, graph=False):
+        """Advance all chains; jstream/ustream are [n_chain, n_steps]; graph=True
+        replays the steps from a cached HIP graph."""
         j = np.ascontiguousarray(jstream, np.uint32)
         u = np.ascontiguousarray(ustream, np.float64)
         n_chain, n_steps = j.shape
@@ -375,19 +376,19 @@ class Context:
         acc = np.zeros((n_chain, n_steps), np.uint8) if trace else None
         amp = np.zeros(2 * n_chain)
         _check(lib().chsim_metropolis_step(self._h, inst, n_steps, _ptr(j)[0], _ptr(u)[0],
-                                           _ptr(tr)[0], _ptr(acc)[0], _ptr(amp)[0], 0,
-                                           _stream(stream)))
+                                           _ptr(tr)[0], _ptr(acc)[0], _ptr(amp)[0],
+                                           CHSIM_GRAPH if graph else 0, _stream(stream)))
         return tr, acc, amp[0::2] + 1j * amp[1::2]
 
     def metropolis_step_device(self, jstream, ustream, trace=None, accepted=None, amp=None,
-                               inst=0, stream=None):
+                               inst=0, stream=None, graph=False):
         """Device-pointer variant: torch tensors on the GPU; enqueues only."""
         n_chain, n_steps = jstream.shape
         if jstream.element_size() != 4 or ustream.element_size() != 8:
             raise ValueError("jstream must be 32-bit integers and ustream float64")
         args = [_ptr(t)[0] for t in (jstream, ustream, trace, accepted, amp)]
-        _check(lib().chsim_metropolis_step(self._h, inst, n_steps, *args, CHSIM_DEVICE_PTRS,
-                                           _stream(stream)))
+        flags = CHSIM_DEVICE_PTRS | (CHSIM_GRAPH if graph else 0)
+        _check(lib().chsim_metropolis_step(self._h, inst, n_steps, *args, flags, _stream(stream)))
 
     def sample_terms(self, alpha, flips, inst=0):
         alpha = np.ascontiguousarray(alpha, np.uint64)

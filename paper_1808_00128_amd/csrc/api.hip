@@ -98,6 +98,11 @@ struct Instance {
     uint64_t kinds[5];
   };
   std::vector<SpanStat> last_spans;
+  // Metropolis steps recorded as a graph, and what they were recorded with.
+  hipGraphExec_t metro_exec = nullptr;
+  MetroView metro_key{};
+  TermsView metro_tkey{};
+  uint32_t metro_steps = 0;
   // metropolis
   uint32_t n_chain = 0;
   DevBuf<uint64_t> mstate0, mstate1, mx, mtrace;
@@ -128,6 +133,8 @@ struct Instance {
     return t;
   }
   void release() {
+    if (metro_exec) hipGraphExecDestroy(metro_exec);
+    metro_exec = nullptr;
     F.release(); G.release(); M.release(); v.release(); s.release();
     gamma.release(); omega.release(); branch.release(); b.release();
     slots.release();
@@ -160,6 +167,7 @@ struct chsim_ctx {
   DevBuf<uint32_t> amp_counter;
   std::vector<AmpInst> amp_key;
   uint32_t amp_n_items = 0;
+  hipStream_t cap_stream = nullptr;  // stream the Metropolis graphs are recorded on
   // Slot occurrences of the last gate list: first gate index and slot.
   std::vector<uint32_t> occ_start;
   std::vector<uint32_t> slotseq_h;
@@ -1166,7 +1174,32 @@ chsim_status chsim_metropolis_step(chsim_ctx* ctx, uint32_t inst, uint32_t n_ste
       mv.accepted = I.macc.p;
     }
   }
-  HIP_TRY(launch_metro_steps(I.view(), mv, n_steps, s));
+  if (flags & CHSIM_GRAPH) {
+    const TermsView tv = I.view();
+    const bool same = I.metro_exec && I.metro_steps == n_steps &&
+                      std::memcmp(&I.metro_key, &mv, sizeof mv) == 0 &&
+                      std::memcmp(&I.metro_tkey, &tv, sizeof tv) == 0;
+    if (!same) {
+      if (I.metro_exec) HIP_TRY(hipGraphExecDestroy(I.metro_exec));
+      I.metro_exec = nullptr;
+      if (!ctx->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+      hipGraph_t g = nullptr;
+      HIP_TRY(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+      const hipError_t le = launch_metro_steps(tv, mv, n_steps, ctx->cap_stream);
+      const hipError_t ce = hipStreamEndCapture(ctx->cap_stream, &g);
+      HIP_TRY(le);
+      HIP_TRY(ce);
+      const hipError_t ie = hipGraphInstantiate(&I.metro_exec, g, nullptr, nullptr, 0);
+      hipGraphDestroy(g);
+      HIP_TRY(ie);
+      I.metro_key = mv;
+      I.metro_tkey = tv;
+      I.metro_steps = n_steps;
+    }
+    HIP_TRY(hipGraphLaunch(I.metro_exec, s));
+  } else {
+    HIP_TRY(launch_metro_steps(I.view(), mv, n_steps, s));
+  }
   if (!dev) {
     if (x_trace) HIP_TRY(hipMemcpyAsync(x_trace, mv.trace, cnt * 8, hipMemcpyDeviceToHost, s));
     if (accepted) HIP_TRY(hipMemcpyAsync(accepted, mv.accepted, cnt, hipMemcpyDeviceToHost, s));
@@ -1427,6 +1460,8 @@ chsim_status chsim_destroy(chsim_ctx* ctx) {
   hipSetDevice(ctx->device);
   hipDeviceSynchronize();
   for (auto& I : ctx->inst) I.release();
+  if (ctx->cap_stream) hipStreamDestroy(ctx->cap_stream);
+  ctx->cap_stream = nullptr;
   ctx->gates.release();
   ctx->err.release();
   ctx->xbuf.release();

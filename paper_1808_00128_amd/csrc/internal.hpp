@@ -209,5 +209,8 @@ hipError_t launch_inner(const TermsView& T, const uint64_t* Aoff, const uint8_t*
 // Metropolis.
 hipError_t launch_metro_init(const TermsView& T, MetroView& Mv, hipStream_t st);
 hipError_t launch_metro_steps(const TermsView& T, MetroView& Mv, uint32_t n_steps, hipStream_t st);
+// One proposal step for every chain with flip masks mask[c] (0: no move).
+hipError_t launch_propose(const TermsView& T, MetroView& Mv, const uint64_t* mask, uint32_t step,
+                          hipStream_t st);
 
 }  // namespace chsim

@@ -10,10 +10,11 @@
 // buffer; accepting the move flips which buffer is current, so no term data
 // is rewritten at accept time.
 //
-// Kernels per step: (1) one thread per term, loop over chains: propose, write
-// the proposal word, and reduce sum_alpha b_alpha <y|phi_alpha> over the
-// 256-term tile in FP64; (2) one workgroup per chain: add the tiles' partials
-// in a fixed order, r = |A(y)|^2 / |A(x)|^2 in FP64, accept iff U < r.
+// Kernels per step: (1) k_propose: lanes over terms, the tile's rows staged
+// in LDS, waves over chains: propose, write the proposal word, and reduce
+// sum_alpha b_alpha <y|phi_alpha> over the 256-term tile in FP64; (2) one
+// workgroup per chain: add the tiles' partials in a fixed order,
+// r = |A(y)|^2 / |A(x)|^2 in FP64, accept iff U < r.
 #include "device_common.hpp"
 #include "internal.hpp"
 
@@ -133,28 +134,140 @@ __global__ __launch_bounds__(256) void k_chain_amp(MetroView Mv) {
   }
 }
 
-__global__ __launch_bounds__(256) void k_metro_propose(TermsView T, MetroView Mv, uint32_t step) {
-  __shared__ double2 scratch[4];
-  const uint64_t a = (uint64_t)blockIdx.x * kMetroTile + threadIdx.x;
-  const bool live = a < T.chi;
+
+// Proposal step y = x ^ m for every chain, per term: Q_y = Q_x prod_{j in m} P_j
+// (right products), the new cached (u, mu) into the other state buffer, and
+// sum_a b_a <y|phi_a> per chain over the block's 256 terms.  The block walks
+// its tile in sub-tiles of 64 terms: the rows F_p, M_p, gamma_p of the
+// sub-tile are staged in LDS once ([p][term], so a wave reading row j for its
+// 64 terms is conflict-free), and wave w of 8 takes the chains c = w,
+// w + 8, ...; a chain's mask is wave-uniform, so the loop over its set bits does not
+// diverge and each term's rows leave HBM once per step for all chains.  The
+// masks are an array (learned proposal) or the single flips e_{j % n} of the
+// chains' j stream at `step` (the paper's chain).
+constexpr uint32_t kSub = 64;
+constexpr int kCW = 8;           // chains per wave in one pass
+constexpr uint32_t kPWaves = 8;  // waves per block: kPWaves * kCW = 64 chains per pass
+constexpr uint32_t kPThreads = 64 * kPWaves;
+constexpr int kStage = (int)((64 * kSub + kPThreads - 1) / kPThreads);  // staging loads per thread
+static_assert(kStage % 2 == 0, "staged in two halves");
+
+template <bool kSingle>
+__global__ __launch_bounds__(kPThreads) void k_propose(TermsView T, MetroView Mv,
+                                                       const uint64_t* __restrict__ mask,
+                                                       uint32_t step) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  const uint32_t n = T.n;
+  uint64_t* sF = reinterpret_cast<uint64_t*>(smem);  // [n][64]
+  uint64_t* sM = sF + (size_t)n * kSub;               // [n][64]
+  uint8_t* sG = reinterpret_cast<uint8_t*>(sM + (size_t)n * kSub);  // [n][64]
+  const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = uniform32(tid >> 6);
   const uint64_t chi = T.chi;
-  TermAmpConst c;
-  if (live) c = load_const(T, a);
-  for (uint32_t ch = 0; ch < Mv.n_chain; ++ch) {
-    const uint32_t j = uniform32(Mv.jstream[(uint64_t)ch * Mv.n_steps + step] % T.n);
-    const uint32_t cur = uniform32(Mv.parity[ch]);
-    double2 val = make_double2(0.0, 0.0);
-    if (live) {
-      const uint64_t w = Mv.state[cur][(uint64_t)ch * chi + a];
-      const uint64_t off = (uint64_t)j * chi + a;
-      const uint64_t u = (w & kUMask) ^ T.F[off];
-      const uint32_t mu = ((uint32_t)(w >> 62) + T.gamma[off] + 2u * par64(u & T.M[off])) & 3u;
-      Mv.state[cur ^ 1u][(uint64_t)ch * chi + a] = u | ((uint64_t)mu << 62);
-      val = term_value(c, u, mu);
+  for (uint32_t cg = 0; cg < Mv.n_chain; cg += kPWaves * kCW) {
+    // This wave's chains in the pass: cg + wave + kPWaves k, k < kCW (wave-uniform).
+    uint64_t m[kCW];
+    uint32_t cur[kCW];
+    double accr[kCW], acci[kCW];
+#pragma unroll
+    for (int k = 0; k < kCW; ++k) {
+      const uint32_t ch = cg + wave + kPWaves * (uint32_t)k;
+      m[k] = 0ull;
+      if (ch < Mv.n_chain) {
+        if (kSingle) m[k] = 1ull << (uniform32(Mv.jstream[(uint64_t)ch * Mv.n_steps + step]) % n);
+        else m[k] = uniform64(mask[ch]);
+      }
+      cur[k] = ch < Mv.n_chain ? uniform32(Mv.parity[ch]) : 0u;
+      accr[k] = 0.0;
+      acci[k] = 0.0;
     }
-    const double2 tot = block_sum(val, scratch);
-    if (threadIdx.x == 0) Mv.partial[(uint64_t)ch * Mv.n_tiles + blockIdx.x] = tot;
+    for (uint32_t sub = 0; sub < kMetroTile / kSub; ++sub) {
+      const uint64_t base = (uint64_t)blockIdx.x * kMetroTile + (uint64_t)sub * kSub;
+      if (base >= chi) break;  // block-uniform
+      __syncthreads();         // the previous sub-tile's readers are done
+      // The thread's share of the sub-tile is staged in two halves; within a
+      // half every load is issued before the first store to LDS.
+#pragma unroll
+      for (int half = 0; half < 2; ++half) {
+        uint64_t rf[kStage / 2], rm[kStage / 2];
+        uint32_t rg[kStage / 2];
+#pragma unroll
+        for (int r = 0; r < kStage / 2; ++r) {
+          const uint32_t i = tid + (uint32_t)(half * (kStage / 2) + r) * kPThreads;
+          const uint32_t p = i / kSub, t = i % kSub;
+          const uint64_t at = base + t;
+          const bool in = i < n * kSub && at < chi;
+          rf[r] = in ? T.F[(uint64_t)p * chi + at] : 0ull;
+          rm[r] = in ? T.M[(uint64_t)p * chi + at] : 0ull;
+          rg[r] = in ? T.gamma[(uint64_t)p * chi + at] : 0u;
+        }
+#pragma unroll
+        for (int r = 0; r < kStage / 2; ++r) {
+          const uint32_t i = tid + (uint32_t)(half * (kStage / 2) + r) * kPThreads;
+          if (i < n * kSub) {
+            sF[i] = rf[r];
+            sM[i] = rm[r];
+            sG[i] = (uint8_t)rg[r];
+          }
+        }
+      }
+      const uint64_t a = base + lane;
+      const bool live = a < chi;
+      // Every state word of this wave's chains is requested before any is used.
+      uint64_t st[kCW];
+#pragma unroll
+      for (int k = 0; k < kCW; ++k) {
+        const uint32_t ch = cg + wave + kPWaves * (uint32_t)k;
+        st[k] = (live && m[k] != 0ull) ? Mv.state[cur[k]][(uint64_t)ch * chi + a] : 0ull;
+      }
+      TermAmpConst c{};
+      if (live) c = load_const(T, a);
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < kCW; ++k) {
+        if (m[k] == 0ull || !live) continue;  // y = x, no such chain, or past chi
+        const uint32_t ch = cg + wave + kPWaves * (uint32_t)k;
+        uint64_t u = st[k] & kUMask;
+        uint32_t mu = (uint32_t)(st[k] >> 62);
+        uint64_t mm = m[k];
+        while (mm) {
+          const uint32_t j = (uint32_t)__builtin_ctzll(mm);
+          mm &= mm - 1ull;
+          u ^= sF[j * kSub + lane];
+          mu += (uint32_t)sG[j * kSub + lane] + 2u * par64(u & sM[j * kSub + lane]);
+        }
+        mu &= 3u;
+        Mv.state[cur[k] ^ 1u][(uint64_t)ch * chi + a] = u | ((uint64_t)mu << 62);
+        const double2 val = term_value(c, u, mu);
+        accr[k] += val.x;
+        acci[k] += val.y;
+      }
+    }
+    // One reduction over the lanes (terms) per chain.
+#pragma unroll
+    for (int k = 0; k < kCW; ++k) {
+      const uint32_t ch = cg + wave + kPWaves * (uint32_t)k;
+      if (ch >= Mv.n_chain) continue;  // wave-uniform
+      double re = accr[k], im = acci[k];
+      for (int o = 32; o >= 1; o >>= 1) {
+        re += __shfl_xor(re, o);
+        im += __shfl_xor(im, o);
+      }
+      if (lane == 0) Mv.partial[(uint64_t)ch * Mv.n_tiles + blockIdx.x] = make_double2(re, im);
+    }
   }
+}
+
+template <bool kSingle>
+hipError_t launch_propose_t(const TermsView& T, MetroView& Mv, const uint64_t* mask, uint32_t step,
+                            hipStream_t st) {
+  const size_t sm = (size_t)T.n * kSub * 17;
+  if (sm > 64 * 1024) {
+    const hipError_t e = hipFuncSetAttribute((const void*)k_propose<kSingle>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_propose<kSingle>, dim3(Mv.n_tiles), dim3(kPThreads), sm, st, T, Mv, mask, step);
+  return hipGetLastError();
 }
 
 __global__ __launch_bounds__(256) void k_metro_accept(MetroView Mv, uint32_t step) {
@@ -200,14 +313,18 @@ hipError_t launch_metro_init(const TermsView& T, MetroView& Mv, hipStream_t st) 
 
 hipError_t launch_metro_steps(const TermsView& T, MetroView& Mv, uint32_t n_steps, hipStream_t st) {
   for (uint32_t t = 0; t < n_steps; ++t) {
-    hipLaunchKernelGGL(k_metro_propose, dim3(Mv.n_tiles), dim3(kMetroTile), 0, st, T, Mv, t);
-    hipError_t e = hipGetLastError();
+    hipError_t e = launch_propose_t<true>(T, Mv, nullptr, t, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_metro_accept, dim3(Mv.n_chain), dim3(256), 0, st, Mv, t);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+hipError_t launch_propose(const TermsView& T, MetroView& Mv, const uint64_t* mask, uint32_t step,
+                          hipStream_t st) {
+  return launch_propose_t<false>(T, Mv, mask, step, st);
 }
 
 }  // namespace chsim

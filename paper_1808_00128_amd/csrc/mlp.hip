@@ -328,87 +328,6 @@ __global__ void k_learned_mask(LearnedView Lv, uint32_t step) {
 
 // One thread per term, loop over chains: Q_y = Q_x prod_{j in m} P_j (the
 // factors commute), <y|phi_alpha> from (u', mu'), tile sums per chain.
-__global__ __launch_bounds__(256) void k_learned_propose(TermsView T, MetroView Mv,
-                                                         const uint64_t* __restrict__ mask) {
-  __shared__ double2 scratch[4];
-  const uint64_t a = (uint64_t)blockIdx.x * kMetroTile + threadIdx.x;
-  const bool live = a < T.chi;
-  const uint64_t chi = T.chi;
-  const uint32_t n = T.n;
-  uint64_t s = 0, nv = 0, vs = 0;
-  uint32_t w = 0;
-  double w0r = 0, w0i = 0, w1r = 0, w1i = 0;
-  if (live) {
-    const uint64_t v = T.v[a];
-    s = T.s[a];
-    nv = ~v & ((n == 64) ? ~0ull : ((1ull << n) - 1ull));
-    vs = v & s;
-    w = T.omega[a];
-    const double2 b = T.b[a];
-    const int vc = __popcll(v);
-    const double h = 0.70710678118654752440;
-    const double mag = ldexp(1.0, -(vc >> 1)) * ((vc & 1) ? h : 1.0);
-    w0r = b.x * mag;
-    w0i = b.y * mag;
-    w1r = (w0r - w0i) * h;
-    w1i = (w0r + w0i) * h;
-  }
-  for (uint32_t ch = 0; ch < Mv.n_chain; ++ch) {
-    const uint64_t m = uniform64(mask[ch]);
-    double2 val = make_double2(0.0, 0.0);
-    if (m == 0ull) {
-      if (threadIdx.x == 0) Mv.partial[(uint64_t)ch * Mv.n_tiles + blockIdx.x] = val;
-      continue;
-    }
-    const uint32_t cur = uniform32(Mv.parity[ch]);
-    if (live) {
-      const uint64_t wd = Mv.state[cur][(uint64_t)ch * chi + a];
-      uint64_t u = wd & ((1ull << 62) - 1ull);
-      uint32_t mu = (uint32_t)(wd >> 62);
-      uint64_t mm = m;
-      while (mm) {
-        const uint32_t j = (uint32_t)__builtin_ctzll(mm);
-        mm &= mm - 1ull;
-        const uint64_t off = (uint64_t)j * chi + a;
-        u ^= T.F[off];
-        mu += T.gamma[off] + 2u * par64(u & T.M[off]);
-      }
-      mu &= 3u;
-      Mv.state[cur ^ 1u][(uint64_t)ch * chi + a] = u | ((uint64_t)mu << 62);
-      if (!((u ^ s) & nv)) {
-        const uint32_t k = (w + 2u * mu + 4u * par64(u & vs)) & 7u;
-        double re = (k & 1u) ? w1r : w0r, im = (k & 1u) ? w1i : w0i;
-        const uint32_t mq = k >> 1;
-        if (mq & 1u) {
-          const double t = re;
-          re = im;
-          im = t;
-        }
-        if ((mq ^ (mq >> 1)) & 1u) re = -re;
-        if (mq & 2u) im = -im;
-        val = make_double2(re, im);
-      }
-    }
-    for (int o = 32; o >= 1; o >>= 1) {
-      val.x += __shfl_down(val.x, o);
-      val.y += __shfl_down(val.y, o);
-    }
-    __syncthreads();
-    if ((threadIdx.x & 63u) == 0) scratch[threadIdx.x >> 6] = val;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double2 tot = make_double2(0.0, 0.0);
-      for (int q = 0; q < 4; ++q) {
-        tot.x += scratch[q].x;
-        tot.y += scratch[q].y;
-      }
-      Mv.partial[(uint64_t)ch * Mv.n_tiles + blockIdx.x] = tot;
-    }
-  }
-}
-
-// One workgroup per chain: A(y), q(x|y) / q(y|x), accept; on accept adopt y,
-// its amplitude, its logits and the proposal state buffer.
 __global__ __launch_bounds__(256) void k_learned_accept(MetroView Mv, LearnedView Lv, uint32_t step) {
   __shared__ double part_r[256], part_i[256];
   const uint32_t ch = blockIdx.x;
@@ -471,8 +390,7 @@ hipError_t launch_learned_steps(const TermsView& T, MetroView& Mv, LearnedView& 
     hipLaunchKernelGGL(k_learned_mask, dim3((Lv.n_chain + 63) / 64), dim3(64), 0, st, Lv, t);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = mlp_forward(d, Lv.y, Lv.n_chain, Lv.logit_y, st)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_learned_propose, dim3(Mv.n_tiles), dim3(kMetroTile), 0, st, T, Mv, Lv.mask);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = launch_propose(T, Mv, Lv.mask, 0, st)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_learned_accept, dim3(Mv.n_chain), dim3(256), 0, st, Mv, Lv, t);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }

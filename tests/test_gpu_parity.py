@@ -478,6 +478,56 @@ def test_metropolis_trajectories(B, n, chi, mode, chains, steps):
     assert 0 < acc.mean() <= 1
 
 
+def test_metropolis_graph_replays_match_eager_and_oracle(B):
+    """The steps recorded as a HIP graph, replayed four times with eager work
+    (amplitudes, eager steps on another instance) and synchronisations in
+    between: every replay equals the eager chain and the oracle chain."""
+    import torch
+
+    n, chi, chains, steps = 10, 96, 8, 40
+    rng = np.random.default_rng(61)
+    circ = W.random_circuit(n, 80, rng.uniform(0, 2 * np.pi, size=6), rng)
+    spec = dict(circuit=circ, chi=chi, mode="sparsify", seed=3)
+    say("metropolis graph replays")
+    ctx = B.Context([spec, spec])
+    ctx.apply_circuit(circ, inst=0)
+    ctx.apply_circuit(circ, inst=1)
+    T = O.Terms(circ, chi, O.SPARSIFY, seed=3)
+    x0 = []
+    while len(x0) < chains:
+        a = int(rng.integers(chi))
+        x = T.term(a).sample(int(W.random_bitstrings(n, 1, rng)[0]))
+        if abs(T.amplitudes(np.array([x], np.uint64))[0]) > 0:
+            x0.append(x)
+    x0 = np.array(x0, np.uint64)
+    ctx.metropolis_init(x0, inst=0)
+    ctx.metropolis_init(x0, inst=1)
+    dev = torch.device("cuda:0")
+    jd = torch.empty((chains, steps), dtype=torch.int32, device=dev)
+    ud = torch.empty((chains, steps), dtype=torch.float64, device=dev)
+    trd = torch.empty((chains, steps), dtype=torch.int64, device=dev)
+    acd = torch.empty((chains, steps), dtype=torch.uint8, device=dev)
+    ampd = torch.empty((chains, 2), dtype=torch.float64, device=dev)
+    ox = x0
+    for rep in range(4):
+        j, u = W.metropolis_streams(n, chains, steps, rng)
+        jd.copy_(torch.from_numpy(j.astype(np.int32)))
+        ud.copy_(torch.from_numpy(u))
+        ctx.metropolis_step_device(jd, ud, trd, acd, ampd, inst=0, graph=True)
+        torch.cuda.synchronize()
+        tr_e, acc_e, amp_e = ctx.metropolis_step(j, u, inst=1)   # eager, host pointers
+        ctx.amplitudes(W.random_bitstrings(n, 33, rng), inst=0)  # unrelated eager work
+        torch.cuda.synchronize()
+        tr_g = trd.cpu().numpy().view(np.uint64)
+        acc_g = acd.cpu().numpy()
+        amp_g = ampd.cpu().numpy()
+        otr, oacc, oamp = T.metropolis(ox, j, u)
+        ox = otr[:, -1].copy()
+        assert np.array_equal(tr_g, tr_e) and np.array_equal(acc_g, acc_e), rep
+        assert np.array_equal(amp_g[:, 0] + 1j * amp_g[:, 1], amp_e), rep
+        assert np.array_equal(tr_g, otr) and np.array_equal(acc_g, oacc), rep
+
+
 def test_metropolis_rejects_zero_probability_start(B):
     circ = W.from_list(4, [(W.OP_H, 0, 0)])
     spec = dict(circuit=circ, chi=1, mode="exact", seed=0)
