@@ -681,6 +681,8 @@ chsim_status evolve_all(chsim_ctx* ctx, Instance& I, const std::vector<DGate>& d
     EvolveJob J;
     J.src = ckpt_view(ctx, I, (int)((k + 1) % 2));
     J.dst = ckpt_view(ctx, I, (int)(k % 2));
+    J.src_rs = J.dst_rs = 1;  // checkpoint states: rows of a state contiguous
+    J.src_is = J.dst_is = n;
     J.src_idx = ctx->pf_parent.p;
     J.br_idx = ctx->pf_rep.p;
     J.branch = I.branch.p;
@@ -700,6 +702,10 @@ chsim_status evolve_all(chsim_ctx* ctx, Instance& I, const std::vector<DGate>& d
   EvolveJob J;
   J.src = ckpt_view(ctx, I, (int)((K - 1) % 2));
   J.dst = I.view();
+  J.src_rs = 1;
+  J.src_is = n;
+  J.dst_rs = chi;
+  J.dst_is = 1;
   J.src_idx = prev_id;
   J.br_idx = nullptr;
   J.branch = I.branch.p;

@@ -102,6 +102,8 @@ hipError_t launch_evolve(const TermsView& T, const DGate* gates, uint32_t n_gate
   EvolveJob J;
   J.src = T;
   J.dst = T;
+  J.src_rs = J.dst_rs = T.chi;
+  J.src_is = J.dst_is = 1;
   J.src_idx = nullptr;
   J.br_idx = nullptr;
   J.branch = T.branch;

@@ -218,7 +218,7 @@ __global__ __launch_bounds__(256) void k_evolve(EvolveJob J, const DGate* __rest
   const uint64_t it = live ? item : 0;
   const uint64_t sa = J.src_idx ? (uint64_t)J.src_idx[it] : it;   // input state
   const uint64_t ba = J.br_idx ? (uint64_t)J.br_idx[it] : it;     // branch choices
-  const uint64_t chs = J.src.chi, chb = J.chi_br;
+  const uint64_t srs = J.src_rs, sis = J.src_is, chb = J.chi_br;
   const uint8_t* __restrict__ branch = J.branch;
   const uint32_t n = J.dst.n;
   uint64_t F[RPL], G[RPL], M[RPL];
@@ -236,7 +236,7 @@ __global__ __launch_bounds__(256) void k_evolve(EvolveJob J, const DGate* __rest
       c.M[j] = 0ull;
       c.g[j] = 0u;
     } else {
-      const uint64_t off = (uint64_t)p * chs + sa;
+      const uint64_t off = (uint64_t)p * srs + sa * sis;
       c.F[j] = act ? J.src.F[off] : 0ull;
       c.G[j] = act ? J.src.G[off] : 0ull;
       c.M[j] = act ? J.src.M[off] : 0ull;
@@ -293,12 +293,12 @@ __global__ __launch_bounds__(256) void k_evolve(EvolveJob J, const DGate* __rest
     }
   }
   if (live) {
-    const uint64_t chd = J.dst.chi;
+    const uint64_t drs = J.dst_rs, dis = J.dst_is;
 #pragma unroll
     for (int j = 0; j < RPL; ++j) {
       const uint32_t p = L.li + (uint32_t)j * LPT;
       if (p < n) {
-        const uint64_t off = (uint64_t)p * chd + item;
+        const uint64_t off = (uint64_t)p * drs + item * dis;
         J.dst.F[off] = c.F[j];
         J.dst.G[off] = c.G[j];
         J.dst.M[off] = c.M[j];

@@ -103,8 +103,13 @@ bool evolve_shape_supported(EvolveShape s, uint32_t n);
 // slot_seq[k] is the slot of the k-th slot occurrence of the launch's gates
 // (n_occ of them): the kernel prefetches each term's choice one occurrence
 // ahead.
+// Row p of state k of src sits at p * src_rs + k * src_is (term store:
+// rs = chi, is = 1; checkpoint stores: rs = 1, is = n, a state's rows
+// contiguous so that a gathered state is read in whole cache lines), and
+// likewise for dst.
 struct EvolveJob {
   TermsView src, dst;
+  uint64_t src_rs, src_is, dst_rs, dst_is;
   const uint32_t* src_idx;
   const uint32_t* br_idx;
   const uint8_t* branch;
