@@ -13,6 +13,7 @@ on the library's stream, the roofline of the dominant kernel, the FP64 path,
 and the CPU oracle timed on a bounded sample of the same workload.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -59,6 +60,36 @@ def cpu_baseline(cfg, sample_terms, threads):
                        f"{cfg['x'].size} strings ({t1 - t0:.2f} s evolve, {t2 - t1:.2f} s amplitudes)")
 
 
+def kernel_sources_sha256():
+    """Hash of the library's kernel and ABI sources (counter-derived traffic is
+    only reported while it still describes the code being run)."""
+    csrc = os.path.join(ROOT, "paper_1808_00128_amd", "csrc")
+    files = sorted(os.path.join(csrc, f) for f in os.listdir(csrc) if f.endswith((".hip", ".hpp")))
+    files.append(os.path.join(ROOT, "include", "chsim.h"))
+    h = hashlib.sha256()
+    for f in files:
+        with open(f, "rb") as fh:
+            h.update(os.path.basename(f).encode())
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def counter_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 byte
+    counters (profiles/traffic_counters.json), or None if the kernel sources
+    changed since they were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic_counters.json")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("sources_sha256") != kernel_sources_sha256():
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    return None if k is None else float(k["bytes_per_launch"])
+
+
 def mean_popcount(words):
     return float(np.mean([bin(int(w)).count("1") for w in np.asarray(words).ravel()]))
 
@@ -90,7 +121,7 @@ def bench_norm(torch, B, W, L=1024):
             "roofline": {"bound": "alu", "kernel": "k_inner (one wave per term, lane = row)",
                          "achieved": round(achieved, 3), "peak": round(INT32_PEAK_OPS / 1e12, 2),
                          "unit": "TOP/s (int32)", "frac": round(achieved / (INT32_PEAK_OPS / 1e12), 4),
-                         "ops_per_pair": ops_pair}}
+                         "traffic": counter_traffic("k_inner"), "ops_per_pair": ops_pair}}
 
 
 def start_points(ctx, n, chi, count, rng):
@@ -445,12 +476,15 @@ def main():
     ms_reset = float(np.mean(phase["reset"]))
     if ms_ev >= ms_amp:
         dom, ops, ms = f"k_evolve<{lanes},...> (CH-form evolution, {64 // lanes} terms per wave)", ops_ev, ms_ev
+        traffic = counter_traffic("k_evolve")
     else:
         dom, ops, ms = "k_amp<float> + k_reduce_ranges (amplitudes, FP32C)", ops_amp, ms_amp
+        traffic = counter_traffic("k_amp<float>")
     achieved = ops / (ms / 1e3) / 1e12
     roofline = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3),
                 "peak": round(INT32_PEAK_OPS / 1e12, 2), "unit": "TOP/s (int32)",
-                "frac": round(achieved / (INT32_PEAK_OPS / 1e12), 4), "traffic": None,
+                "frac": round(achieved / (INT32_PEAK_OPS / 1e12), 4), "traffic": traffic,
+                "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x 2 + WRITE_SIZE)",
                 "ops_per_launch": ops, "ms_per_launch": round(ms, 4)}
 
     result = {
