@@ -60,34 +60,41 @@ def cpu_baseline(cfg, sample_terms, threads):
                        f"{cfg['x'].size} strings ({t1 - t0:.2f} s evolve, {t2 - t1:.2f} s amplitudes)")
 
 
-def kernel_sources_sha256():
-    """Hash of the library's kernel and ABI sources (counter-derived traffic is
+# Sources each counter-measured kernel is built from (its launch planning in
+# api.hip included): the recorded bytes stay valid while these files are unchanged.
+KERNEL_SOURCES = {
+    "k_evolve": ["evolve_kernel.hpp", "evolve.hip", "evolve_l4.hip", "evolve_l8.hip",
+                 "evolve_wide.hip", "prefix.hip", "device_common.hpp", "internal.hpp", "api.hip"],
+    "k_amp<float>": ["amplitude.hip", "device_common.hpp", "internal.hpp", "api.hip"],
+    "k_inner": ["inner.hip", "device_common.hpp", "internal.hpp", "api.hip"],
+}
+
+
+def kernel_sources_sha256(kernel):
+    """Hash of the sources `kernel` is built from (counter-derived traffic is
     only reported while it still describes the code being run)."""
     csrc = os.path.join(ROOT, "paper_1808_00128_amd", "csrc")
-    files = sorted(os.path.join(csrc, f) for f in os.listdir(csrc) if f.endswith((".hip", ".hpp")))
-    files.append(os.path.join(ROOT, "include", "chsim.h"))
     h = hashlib.sha256()
-    for f in files:
-        with open(f, "rb") as fh:
-            h.update(os.path.basename(f).encode())
+    for f in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode())
             h.update(fh.read())
     return h.hexdigest()
 
 
 def counter_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 byte
-    counters (profiles/traffic_counters.json), or None if the kernel sources
-    changed since they were taken."""
+    counters (profiles/traffic_counters.json), or None if its sources changed
+    since they were taken."""
     path = os.path.join(ROOT, "profiles", "traffic_counters.json")
     try:
         with open(path) as fh:
-            rec = json.load(fh)
+            k = json.load(fh).get("kernels", {}).get(kernel)
     except (OSError, ValueError):
         return None
-    if rec.get("sources_sha256") != kernel_sources_sha256():
+    if k is None or k.get("sources_sha256") != kernel_sources_sha256(kernel):
         return None
-    k = rec.get("kernels", {}).get(kernel)
-    return None if k is None else float(k["bytes_per_launch"])
+    return float(k["bytes_per_launch"])
 
 
 def mean_popcount(words):
