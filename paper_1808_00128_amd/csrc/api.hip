@@ -1551,7 +1551,8 @@ chsim_status chsim_mlp_create(chsim_ctx* ctx, uint32_t n, uint32_t hidden, uint3
   d.cap = max_batch;
   const uint64_t cnt = d.L.count();
   const size_t B = max_batch, H = hidden;
-  bool ok = mlp_alloc(m, &d.p, cnt) == hipSuccess && mlp_alloc(m, &d.grad, cnt) == hipSuccess &&
+  d.part_cap = (uint64_t)1 << 19;
+  bool ok = mlp_alloc(m, &d.part, d.part_cap) == hipSuccess && mlp_alloc(m, &d.p, cnt) == hipSuccess && mlp_alloc(m, &d.grad, cnt) == hipSuccess &&
             mlp_alloc(m, &d.adam_m, cnt) == hipSuccess && mlp_alloc(m, &d.adam_v, cnt) == hipSuccess &&
             mlp_alloc(m, &d.wb, d.L.wb_count()) == hipSuccess &&
             mlp_alloc(m, &d.a0, B * n) == hipSuccess && mlp_alloc(m, &d.a1, B * H) == hipSuccess &&

@@ -13,6 +13,8 @@
 // 32x32 output tile per 256-thread workgroup (2 x 2 waves, one 16x16 MFMA
 // tile each), operands staged through LDS in BF16 with arbitrary source
 // strides, so forward and backward products use the same kernel.
+#include <algorithm>
+
 #include "device_common.hpp"
 #include "internal.hpp"
 #include "mlp.hpp"
@@ -38,8 +40,21 @@ __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint
 //   EPI_BIAS_RELU: z = acc + bias[j]; Cf = z; Cb = bf16(max(z, 0)).
 //   EPI_BIAS: Cf = acc + bias[j]  (no activation; logits).
 //   EPI_MASK: v = acc * (mask[i][j] > 0); Cf = v; Cb = bf16(v).
+//
+// 32 x 32 output tile per 256-thread workgroup (2 x 2 waves, one 16 x 16
+// MFMA tile each), K staged 64 at a time through LDS (four MFMAs per wave per
+// stage) with the next stage's global loads issued before the MFMAs.  Each
+// operand is read with the lanes running along whichever index has unit
+// stride.  Products with few output tiles and a long K (the weight gradients,
+// K = batch) split K over gridDim.z into FP32 partials that a second kernel
+// sums in a fixed order before the epilogue, so results do not depend on
+// scheduling.
 // ---------------------------------------------------------------------------
 enum { EPI_STORE = 0, EPI_BIAS_RELU = 1, EPI_BIAS = 2, EPI_MASK = 3 };
+
+constexpr int kGT = 32;       // output tile edge
+constexpr int kGK = 64;       // K per LDS stage
+constexpr int kGRow = kGK + 4;  // LDS row pitch (elements)
 
 struct GemmArgs {
   const uint16_t* A;
@@ -52,70 +67,141 @@ struct GemmArgs {
   float* Cf;          // may be null
   uint16_t* Cb;       // may be null
   int ldc;
+  int kc;             // K extent of one split (multiple of kGK)
+  float* part;        // [splits][M][N] partial sums when gridDim.z > 1
 };
 
+__device__ __forceinline__ void gemm_epilogue(const GemmArgs& g, int row, int col, float v) {
+  const int64_t o = (int64_t)row * g.ldc + col;
+  switch (g.epi) {
+    case EPI_BIAS_RELU:
+      v += g.bias[col];
+      if (g.Cf) g.Cf[o] = v;
+      if (g.Cb) g.Cb[o] = f2bf(v > 0.f ? v : 0.f);
+      break;
+    case EPI_BIAS:
+      v += g.bias[col];
+      if (g.Cf) g.Cf[o] = v;
+      if (g.Cb) g.Cb[o] = f2bf(v);
+      break;
+    case EPI_MASK:
+      v = g.mask[o] > 0.f ? v : 0.f;
+      if (g.Cf) g.Cf[o] = v;
+      if (g.Cb) g.Cb[o] = f2bf(v);
+      break;
+    default:
+      if (g.Cf) g.Cf[o] = v;
+      if (g.Cb) g.Cb[o] = f2bf(v);
+      break;
+  }
+}
+
+// Element q of this thread's share of a [32 rows][64 k] operand stage: with
+// k_fast the 64 lanes of a wave cover one row's 64 k; otherwise two k's of
+// all 32 rows.
+__device__ __forceinline__ void stage_index(int q, bool k_fast, int& i, int& k) {
+  const int e = (int)threadIdx.x + 256 * q;
+  if (k_fast) {
+    i = e >> 6;
+    k = e & 63;
+  } else {
+    k = e >> 5;
+    i = e & 31;
+  }
+}
+
+__device__ __forceinline__ void stage_load(const uint16_t* __restrict__ P, int64_t s_row, int64_t s_k,
+                                           int rows, int r0, int k0, int kend, bool k_fast,
+                                           uint16_t (&v)[8]) {
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    int i, k;
+    stage_index(q, k_fast, i, k);
+    const int gi = r0 + i, gk = k0 + k;
+    v[q] = (gi < rows && gk < kend) ? P[(int64_t)gi * s_row + (int64_t)gk * s_k] : (uint16_t)0;
+  }
+}
+
+__device__ __forceinline__ void stage_store(uint16_t (*S)[kGRow], bool k_fast, const uint16_t (&v)[8]) {
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    int i, k;
+    stage_index(q, k_fast, i, k);
+    S[i][k] = v[q];
+  }
+}
+
 __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
-  __shared__ uint16_t As[32][16 + 4];  // [m][k]
-  __shared__ uint16_t Bs[32][16 + 4];  // [n][k]
+  __shared__ __align__(16) uint16_t As[kGT][kGRow];  // [m][k]
+  __shared__ __align__(16) uint16_t Bs[kGT][kGRow];  // [n][k]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const int m0 = blockIdx.x * 32, n0 = blockIdx.y * 32;
+  const int m0 = blockIdx.x * kGT, n0 = blockIdx.y * kGT;
+  const int kbeg = blockIdx.z * g.kc;
+  const int kend = min(g.K, kbeg + g.kc);
+  const bool a_kf = g.sak == 1, b_kf = g.sbk == 1;
+  uint16_t va[8], vb[8];
+  stage_load(g.A, g.sai, g.sak, g.M, m0, kbeg, kend, a_kf, va);
+  stage_load(g.B, g.sbj, g.sbk, g.N, n0, kbeg, kend, b_kf, vb);
+  // 16x16x16 operand layout: lane l holds A[l % 16][4 (l / 16) .. +3] and
+  // B[4 (l / 16) .. +3][l % 16]; the result C[4 (l / 16) + r][l % 16], r = 0..3.
+  const int r16 = lane & 15, kq = (lane >> 4) * 4;
   f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < g.K; k0 += 16) {
-    for (int e = tid; e < 32 * 16; e += 256) {
-      const int i = e >> 4, k = e & 15;
-      const int gi = m0 + i, gk = k0 + k;
-      As[i][k] = (gi < g.M && gk < g.K) ? g.A[gi * g.sai + gk * g.sak] : (uint16_t)0;
-      const int j = e >> 4;  // Bs[n][k]
-      const int gj = n0 + j;
-      Bs[j][k] = (gj < g.N && gk < g.K) ? g.B[(int64_t)gk * g.sbk + (int64_t)gj * g.sbj] : (uint16_t)0;
-    }
+  for (int k0 = kbeg; k0 < kend; k0 += kGK) {
     __syncthreads();
-    // 16x16x16 operand layout: lane l holds A[l % 16][4 (l / 16) .. +3] and
-    // B[4 (l / 16) .. +3][l % 16]; the result C[4 (l / 16) + r][l % 16], r = 0..3.
-    const int r16 = lane & 15, kq = (lane >> 4) * 4;
-    bf16x4 a, b;
-    for (int t = 0; t < 4; ++t) {
-      a[t] = (short)As[wm * 16 + r16][kq + t];
-      b[t] = (short)Bs[wn * 16 + r16][kq + t];
-    }
-    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+    stage_store(As, a_kf, va);
+    stage_store(Bs, b_kf, vb);
     __syncthreads();
+    if (k0 + kGK < kend) {
+      stage_load(g.A, g.sai, g.sak, g.M, m0, k0 + kGK, kend, a_kf, va);
+      stage_load(g.B, g.sbj, g.sbk, g.N, n0, k0 + kGK, kend, b_kf, vb);
+    }
+#pragma unroll
+    for (int kk = 0; kk < kGK; kk += 16) {
+      const bf16x4 a = *reinterpret_cast<const bf16x4*>(&As[wm * 16 + r16][kk + kq]);
+      const bf16x4 b = *reinterpret_cast<const bf16x4*>(&Bs[wn * 16 + r16][kk + kq]);
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+    }
   }
   const int col = n0 + wn * 16 + (lane & 15);
   for (int r = 0; r < 4; ++r) {
     const int row = m0 + wm * 16 + (lane >> 4) * 4 + r;
     if (row >= g.M || col >= g.N) continue;
-    float v = acc[r];
-    const int64_t o = (int64_t)row * g.ldc + col;
-    switch (g.epi) {
-      case EPI_BIAS_RELU: {
-        v += g.bias[col];
-        if (g.Cf) g.Cf[o] = v;
-        if (g.Cb) g.Cb[o] = f2bf(v > 0.f ? v : 0.f);
-        break;
-      }
-      case EPI_BIAS:
-        v += g.bias[col];
-        if (g.Cf) g.Cf[o] = v;
-        if (g.Cb) g.Cb[o] = f2bf(v);
-        break;
-      case EPI_MASK:
-        v = g.mask[o] > 0.f ? v : 0.f;
-        if (g.Cf) g.Cf[o] = v;
-        if (g.Cb) g.Cb[o] = f2bf(v);
-        break;
-      default:
-        if (g.Cf) g.Cf[o] = v;
-        if (g.Cb) g.Cb[o] = f2bf(v);
-        break;
-    }
+    if (gridDim.z == 1)
+      gemm_epilogue(g, row, col, acc[r]);
+    else
+      g.part[((int64_t)blockIdx.z * g.M + row) * g.N + col] = acc[r];
   }
 }
 
-static hipError_t gemm(const GemmArgs& g, hipStream_t st) {
-  dim3 grid((g.M + 31) / 32, (g.N + 31) / 32);
-  hipLaunchKernelGGL(k_gemm_bf16, grid, dim3(256), 0, st, g);
+// Sum of the K-split partials in split order, then the epilogue.
+__global__ __launch_bounds__(256) void k_gemm_splitk(GemmArgs g, int splits) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t mn = (int64_t)g.M * g.N;
+  if (e >= mn) return;
+  float v = 0.f;
+  for (int z = 0; z < splits; ++z) v += g.part[z * mn + e];
+  gemm_epilogue(g, (int)(e / g.N), (int)(e % g.N), v);
+}
+
+static hipError_t gemm(GemmArgs g, const MLPDev& d, hipStream_t st) {
+  const int bm = (g.M + kGT - 1) / kGT, bn = (g.N + kGT - 1) / kGT;
+  const int blocks = bm * bn;
+  const int n_kt = (g.K + kGK - 1) / kGK;
+  int splits = 1;
+  if (blocks < 128 && n_kt > 4) {
+    splits = std::min((256 + blocks - 1) / blocks, n_kt / 2);
+    while (splits > 1 && (uint64_t)splits * g.M * g.N > d.part_cap) --splits;
+  }
+  const int kt_per = (n_kt + splits - 1) / splits;
+  g.kc = kt_per * kGK;
+  splits = (n_kt + kt_per - 1) / kt_per;
+  g.part = d.part;
+  hipLaunchKernelGGL(k_gemm_bf16, dim3(bm, bn, splits), dim3(256), 0, st, g);
+  if (splits > 1) {
+    const int64_t mn = (int64_t)g.M * g.N;
+    hipLaunchKernelGGL(k_gemm_splitk, dim3((uint32_t)((mn + 255) / 256)), dim3(256), 0, st, g, splits);
+  }
   return hipGetLastError();
 }
 
@@ -157,14 +243,40 @@ __global__ __launch_bounds__(256) void k_bce_grad(const float* __restrict__ logi
   if (threadIdx.x == 0) atomicAdd(loss_acc, part[0]);
 }
 
-// db[j] = sum_b d[b][j] (FP32, fixed order).
-__global__ __launch_bounds__(256) void k_colsum(const float* __restrict__ d, uint32_t B, uint32_t N,
-                                                float* __restrict__ db) {
+// db[j] = sum_b d[b][j] (FP32, fixed order) in two passes: split y of
+// k_colsum_part sums rows [y R, (y + 1) R) with 4 row groups of 64 columns per
+// workgroup; k_colsum_fin adds the splits in order.
+__global__ __launch_bounds__(256) void k_colsum_part(const float* __restrict__ d, uint32_t B, uint32_t N,
+                                                     uint32_t R, float* __restrict__ part) {
+  __shared__ float red[4][64];
+  const uint32_t c = threadIdx.x & 63u, grp = threadIdx.x >> 6;
+  const uint32_t j = blockIdx.x * 64u + c;
+  const uint32_t b0 = blockIdx.y * R, b1 = min(B, b0 + R);
+  float s = 0.f;
+  if (j < N)
+    for (uint32_t b = b0 + grp; b < b1; b += 4u) s += d[(uint64_t)b * N + j];
+  red[grp][c] = s;
+  __syncthreads();
+  if (grp == 0 && j < N) part[(uint64_t)blockIdx.y * N + j] = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
+}
+
+__global__ __launch_bounds__(256) void k_colsum_fin(const float* __restrict__ part, uint32_t splits,
+                                                    uint32_t N, float* __restrict__ db) {
   const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= N) return;
   float s = 0.f;
-  for (uint32_t b = 0; b < B; ++b) s += d[(uint64_t)b * N + j];
+  for (uint32_t z = 0; z < splits; ++z) s += part[(uint64_t)z * N + j];
   db[j] = s;
+}
+
+static hipError_t colsum(const MLPDev& d, const float* src, uint32_t B, uint32_t N, float* db,
+                         hipStream_t st) {
+  uint32_t splits = std::min<uint32_t>(32u, (B + 63u) / 64u);
+  while (splits > 1 && (uint64_t)splits * N > d.part_cap) --splits;
+  const uint32_t R = (B + splits - 1) / splits;
+  hipLaunchKernelGGL(k_colsum_part, dim3((N + 63) / 64, splits), dim3(256), 0, st, src, B, N, R, d.part);
+  hipLaunchKernelGGL(k_colsum_fin, dim3((N + 255) / 256), dim3(256), 0, st, d.part, splits, N, db);
+  return hipGetLastError();
 }
 
 // Adam on the packed FP32 parameters, then refresh the BF16 weight copies.
@@ -214,19 +326,19 @@ static hipError_t forward_a0(MLPDev& d, uint32_t B, float* logits, hipStream_t s
   g.B = d.wb + L.wb_W1(); g.sbk = 1; g.sbj = n;
   g.M = (int)B; g.N = H; g.K = n; g.epi = EPI_BIAS_RELU; g.bias = d.p + L.off_b1();
   g.Cf = d.z1; g.Cb = d.a1; g.ldc = H;
-  hipError_t e = gemm(g, st);
+  hipError_t e = gemm(g, d, st);
   if (e != hipSuccess) return e;
   // z2 = a1 W2^T + b2, a2 = bf16(relu(z2))
   g.A = d.a1; g.sai = H; g.sak = 1;
   g.B = d.wb + L.wb_W2(); g.sbk = 1; g.sbj = H;
   g.N = H; g.K = H; g.bias = d.p + L.off_b2(); g.Cf = d.z2; g.Cb = d.a2; g.ldc = H;
-  if ((e = gemm(g, st)) != hipSuccess) return e;
+  if ((e = gemm(g, d, st)) != hipSuccess) return e;
   // logits = a2 W3^T + b3
   g.A = d.a2; g.sai = H; g.sak = 1;
   g.B = d.wb + L.wb_W3(); g.sbk = 1; g.sbj = H;
   g.N = n; g.K = H; g.epi = EPI_BIAS; g.bias = d.p + L.off_b3(); g.Cf = logits; g.Cb = nullptr;
   g.ldc = n;
-  return gemm(g, st);
+  return gemm(g, d, st);
 }
 
 hipError_t mlp_forward(MLPDev& d, const uint64_t* x, uint32_t B, float* logits, hipStream_t st) {
@@ -252,30 +364,26 @@ hipError_t mlp_loss_grad(MLPDev& d, const uint64_t* x, const uint64_t* t, uint32
   // dW3[n][H] = gb^T a2
   g.A = d.gb; g.sai = 1; g.sak = n; g.B = d.a2; g.sbk = H; g.sbj = 1;
   g.M = n; g.N = H; g.K = (int)B; g.epi = EPI_STORE; g.Cf = G + L.off_W3(); g.Cb = nullptr; g.ldc = H;
-  if ((e = gemm(g, st)) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_colsum, dim3((n + 255) / 256), dim3(256), 0, st, d.gf, B, (uint32_t)n,
-                     G + L.off_b3());
+  if ((e = gemm(g, d, st)) != hipSuccess) return e;
+  if ((e = colsum(d, d.gf, B, (uint32_t)n, G + L.off_b3(), st)) != hipSuccess) return e;
   // dZ2 = (gb W3) * [z2 > 0]
   g.A = d.gb; g.sai = n; g.sak = 1; g.B = d.wb + L.wb_W3(); g.sbk = H; g.sbj = 1;
   g.M = (int)B; g.N = H; g.K = n; g.epi = EPI_MASK; g.mask = d.z2; g.Cf = d.dz2; g.Cb = d.gz2; g.ldc = H;
-  if ((e = gemm(g, st)) != hipSuccess) return e;
+  if ((e = gemm(g, d, st)) != hipSuccess) return e;
   // dW2[H][H] = gz2^T a1
   g.A = d.gz2; g.sai = 1; g.sak = H; g.B = d.a1; g.sbk = H; g.sbj = 1;
   g.M = H; g.N = H; g.K = (int)B; g.epi = EPI_STORE; g.Cf = G + L.off_W2(); g.Cb = nullptr; g.ldc = H;
-  if ((e = gemm(g, st)) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_colsum, dim3((H + 255) / 256), dim3(256), 0, st, d.dz2, B, (uint32_t)H,
-                     G + L.off_b2());
+  if ((e = gemm(g, d, st)) != hipSuccess) return e;
+  if ((e = colsum(d, d.dz2, B, (uint32_t)H, G + L.off_b2(), st)) != hipSuccess) return e;
   // dZ1 = (gz2 W2) * [z1 > 0]
   g.A = d.gz2; g.sai = H; g.sak = 1; g.B = d.wb + L.wb_W2(); g.sbk = H; g.sbj = 1;
   g.M = (int)B; g.N = H; g.K = H; g.epi = EPI_MASK; g.mask = d.z1; g.Cf = d.dz1; g.Cb = d.gz1; g.ldc = H;
-  if ((e = gemm(g, st)) != hipSuccess) return e;
+  if ((e = gemm(g, d, st)) != hipSuccess) return e;
   // dW1[H][n] = gz1^T a0
   g.A = d.gz1; g.sai = 1; g.sak = H; g.B = d.a0; g.sbk = n; g.sbj = 1;
   g.M = H; g.N = n; g.K = (int)B; g.epi = EPI_STORE; g.Cf = G + L.off_W1(); g.Cb = nullptr; g.ldc = n;
-  if ((e = gemm(g, st)) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_colsum, dim3((H + 255) / 256), dim3(256), 0, st, d.dz1, B, (uint32_t)H,
-                     G + L.off_b1());
-  return hipGetLastError();
+  if ((e = gemm(g, d, st)) != hipSuccess) return e;
+  return colsum(d, d.dz1, B, (uint32_t)H, G + L.off_b1(), st);
 }
 
 hipError_t mlp_adam(MLPDev& d, float lr, hipStream_t st) {
@@ -296,13 +404,14 @@ __device__ __forceinline__ float clip_sigmoid(float l, float lo, float hi) {
   return fminf(fmaxf(p, lo), hi);
 }
 
-// log q(y|x) for mask m with flip probabilities from logits l[0..n).
-__device__ double log_q(const float* l, uint64_t m, uint32_t n, float eps, float lo, float hi) {
-  double lp = 0.0;
-  for (uint32_t j = 0; j < n; ++j) {
-    const double p = (double)clip_sigmoid(l[j], lo, hi);
-    lp += ((m >> j) & 1ull) ? log(p) : log1p(-p);
-  }
+// Term j of log prod_j pi_j^{m_j} (1 - pi_j)^{1 - m_j} for logit l.
+__device__ __forceinline__ double log_q_bit(float l, bool flip, float lo, float hi) {
+  const double p = (double)clip_sigmoid(l, lo, hi);
+  return flip ? log(p) : log1p(-p);
+}
+
+// log q(y|x) of the mixture from the product's log lp for mask m.
+__device__ __forceinline__ double log_q_mix(double lp, uint64_t m, uint32_t n, float eps) {
   const double single = (__popcll(m) == 1) ? (double)eps / (double)n : 0.0;
   return log(single + (1.0 - (double)eps) * exp(lp));
 }
@@ -348,34 +457,49 @@ __global__ __launch_bounds__(256) void k_learned_accept(MetroView Mv, LearnedVie
   }
   __syncthreads();
   __shared__ uint32_t acc_s;
-  if (threadIdx.x == 0) {
-    double yr = 0.0, yi = 0.0;
-    for (int q = 0; q < 4; ++q) {
-      yr += part_r[q];
-      yi += part_i[q];
-    }
-    const uint64_t idx = (uint64_t)ch * Lv.n_steps + step;
+  if (threadIdx.x < 64) {
+    // Wave 0: lane j < n takes bit j of both proposal densities, then lane 0
+    // decides.
+    const uint32_t lane = threadIdx.x;
     const uint64_t m = Lv.mask[ch];
-    uint32_t acc = 1u;
-    if (m != 0ull) {
-      const double2 ax = Mv.amp[ch];
-      const double px = ax.x * ax.x + ax.y * ax.y;
-      const double py = yr * yr + yi * yi;
-      const double lq_rev = log_q(Lv.logit_y + (uint64_t)ch * n, m, n, Lv.eps, Lv.pi_min, Lv.pi_max);
-      const double lq_fwd = log_q(Lv.logit_x + (uint64_t)ch * n, m, n, Lv.eps, Lv.pi_min, Lv.pi_max);
-      const double r = (py / px) * exp(lq_rev - lq_fwd);
-      acc = (px > 0.0) && (Lv.u[idx] < r);
-      if (acc) {
-        Mv.x[ch] = Lv.y[ch];
-        Lv.x[ch] = Lv.y[ch];
-        Mv.amp[ch] = make_double2(yr, yi);
-        Mv.parity[ch] ^= 1u;
-      }
+    double lrev = 0.0, lfwd = 0.0;
+    if (m != 0ull && lane < n) {
+      const bool f = (m >> lane) & 1ull;
+      lrev = log_q_bit(Lv.logit_y[(uint64_t)ch * n + lane], f, Lv.pi_min, Lv.pi_max);
+      lfwd = log_q_bit(Lv.logit_x[(uint64_t)ch * n + lane], f, Lv.pi_min, Lv.pi_max);
     }
-    acc_s = acc && (m != 0ull);
-    if (Mv.trace) Mv.trace[idx] = Mv.x[ch];
-    if (Mv.accepted) Mv.accepted[idx] = (uint8_t)acc;
-    if (Lv.n_flips) Lv.n_flips[idx] = (uint32_t)__popcll(m);
+    for (int o = 32; o >= 1; o >>= 1) {
+      lrev += __shfl_xor(lrev, o);
+      lfwd += __shfl_xor(lfwd, o);
+    }
+    if (lane == 0) {
+      double yr = 0.0, yi = 0.0;
+      for (int q = 0; q < 4; ++q) {
+        yr += part_r[q];
+        yi += part_i[q];
+      }
+      const uint64_t idx = (uint64_t)ch * Lv.n_steps + step;
+      uint32_t acc = 1u;
+      if (m != 0ull) {
+        const double2 ax = Mv.amp[ch];
+        const double px = ax.x * ax.x + ax.y * ax.y;
+        const double py = yr * yr + yi * yi;
+        const double lq_rev = log_q_mix(lrev, m, n, Lv.eps);
+        const double lq_fwd = log_q_mix(lfwd, m, n, Lv.eps);
+        const double r = (py / px) * exp(lq_rev - lq_fwd);
+        acc = (px > 0.0) && (Lv.u[idx] < r);
+        if (acc) {
+          Mv.x[ch] = Lv.y[ch];
+          Lv.x[ch] = Lv.y[ch];
+          Mv.amp[ch] = make_double2(yr, yi);
+          Mv.parity[ch] ^= 1u;
+        }
+      }
+      acc_s = acc && (m != 0ull);
+      if (Mv.trace) Mv.trace[idx] = Mv.x[ch];
+      if (Mv.accepted) Mv.accepted[idx] = (uint8_t)acc;
+      if (Lv.n_flips) Lv.n_flips[idx] = (uint32_t)__popcll(m);
+    }
   }
   __syncthreads();
   if (acc_s)

@@ -47,6 +47,9 @@ struct MLPDev {
   float *z1 = nullptr, *z2 = nullptr, *logits = nullptr;
   float *gf = nullptr, *dz1 = nullptr, *dz2 = nullptr;
   uint16_t *gb = nullptr, *gz1 = nullptr, *gz2 = nullptr;
+  // FP32 partial sums of K-split products and column sums
+  float* part = nullptr;
+  uint64_t part_cap = 0;
 };
 
 struct LearnedView {
