@@ -65,6 +65,8 @@ def cpu_baseline(cfg, sample_terms, threads):
 KERNEL_SOURCES = {
     "k_evolve": ["evolve_kernel.hpp", "evolve.hip", "evolve_l4.hip", "evolve_l8.hip",
                  "evolve_wide.hip", "prefix.hip", "device_common.hpp", "internal.hpp", "api.hip"],
+    "k_evolve_lds": ["evolve_lds.hip", "evolve.hip", "prefix.hip", "device_common.hpp", "internal.hpp",
+                     "api.hip"],
     "k_amp<float>": ["amplitude.hip", "device_common.hpp", "internal.hpp", "api.hip"],
     "k_inner": ["inner.hip", "device_common.hpp", "internal.hpp", "api.hip"],
 }
@@ -95,6 +97,13 @@ def counter_traffic(kernel):
     if k is None or k.get("sources_sha256") != kernel_sources_sha256(kernel):
         return None
     return float(k["bytes_per_launch"])
+
+
+def shape_name(value):
+    """Evolution mapping of a lanes value: lanes per term and where the rows live."""
+    lanes = value & 0xff
+    where = "LDS" if value & 0x100 else "registers"
+    return f"{lanes} lanes/term, rows in {where}"
 
 
 def mean_popcount(words):
@@ -482,8 +491,8 @@ def main():
     ms_amp = float(np.mean(phase["amplitudes"]))
     ms_reset = float(np.mean(phase["reset"]))
     if ms_ev >= ms_amp:
-        dom, ops, ms = f"k_evolve<{lanes},...> (CH-form evolution, {64 // lanes} terms per wave)", ops_ev, ms_ev
-        traffic = counter_traffic("k_evolve")
+        dom, ops, ms = f"{'k_evolve_lds' if lanes & B.CHSIM_EVOLVE_LDS else 'k_evolve'}<{lanes & 0xff},...> (CH-form evolution, {shape_name(lanes)})", ops_ev, ms_ev
+        traffic = counter_traffic("k_evolve_lds" if lanes & B.CHSIM_EVOLVE_LDS else "k_evolve")
     else:
         dom, ops, ms = "k_amp<float> + k_reduce_ranges (amplitudes, FP32C)", ops_amp, ms_amp
         traffic = counter_traffic("k_amp<float>")
@@ -518,8 +527,9 @@ def main():
                                 "distinct_prefixes": ev_stats["distinct"],
                                 "gate_applications": {k: ev_stats[k] for k in ("H", "CX", "CZ", "S", "cond")},
                                 "per_term_gate_applications": chi * circ.n_gates},
-        "evolve_autotune": {"lanes_per_term": lanes, "terms_per_wave": 64 // lanes,
-                            "ms_by_lanes": dict(zip(["4", "8", "16", "32", "64"], tune_ms))},
+        "evolve_autotune": {"shape": shape_name(lanes), "terms_per_wave": 64 // (lanes & 0xff),
+                            "ms_by_shape": {shape_name(v): round(t, 4)
+                                            for v, t in zip(B.TUNE_SHAPES, tune_ms)}},
         "amplitude_kernel_evals_per_s": chi * n_x / (ms_amp / 1e3),
         "evolve_gates_per_s": chi * circ.n_gates / (ms_ev / 1e3),
         "fp32c_vs_fp64_normwise": fp32c_vs_fp64,

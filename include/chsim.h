@@ -273,12 +273,15 @@ chsim_status chsim_decompose_phase(double theta, uint32_t qubit, double coeff[4]
 /* Tuning knobs of one instance; value 0 restores the library default.
  * EVOLVE_LANES: lanes per term in the evolution kernel (4, 8, 16, 32 or 64;
  * a wave holds 64 / lanes terms, and each lane holds ceil(n / lanes) tableau
- * rows; lanes * ceil(n / lanes) must not exceed 64).  -1 = autotune: the next
- * chsim_apply_clifford that starts from |0^n> times every shape on the real
- * gate list (hipEvents), keeps the fastest, and leaves the same terms any
- * shape would.  Results never depend on the knob.  EUNSUPPORTED: no compiled
- * kernel for that value and n. */
+ * rows in registers; lanes * ceil(n / lanes) must not exceed 64), or
+ * lanes | CHSIM_EVOLVE_LDS with lanes 4, 8 or 16 (lanes * 16 >= n): the rows
+ * of every term stay in LDS and the lanes of a term share them.  -1 =
+ * autotune: the next chsim_apply_clifford that starts from |0^n> times every
+ * shape on the real gate list (hipEvents), keeps the fastest, and leaves the
+ * same terms any shape would.  Results never depend on the knob.
+ * EUNSUPPORTED: no compiled kernel for that value and n. */
 #define CHSIM_TUNE_EVOLVE_LANES 1u
+#define CHSIM_EVOLVE_LDS 0x100
 /* PREFIX_SHARE: an evolution from |0^n> runs the gates before a checkpoint
  * slot once per distinct choice of branches up to that slot (terms that
  * agree on those choices have identical CH forms there) and continues every
@@ -290,8 +293,9 @@ chsim_status chsim_decompose_phase(double theta, uint32_t qubit, double coeff[4]
 #define CHSIM_TUNE_PREFIX_SHARE 2u
 chsim_status chsim_set_tuning(chsim_ctx* ctx, uint32_t inst, uint32_t knob, int32_t value);
 
-/* Current value of a knob.  For EVOLVE_LANES, timings_ms[5] receives the
- * autotuner's timings in ms for lanes 4, 8, 16, 32, 64 (0 where not timed);
+/* Current value of a knob.  For EVOLVE_LANES, timings_ms[8] receives the
+ * autotuner's timings in ms for lanes 4, 8, 16, 32, 64 with rows in
+ * registers and lanes 4, 8, 16 with rows in LDS (0 where not timed);
  * for PREFIX_SHARE, timings_ms[0] = checkpoint levels of the last planned
  * evolution and timings_ms[1] = its estimated cost relative to evolving
  * every term alone.  timings_ms may be NULL. */

@@ -23,6 +23,9 @@ CHSIM_EXACT, CHSIM_SPARSIFY = 0, 1
 CHSIM_FP64, CHSIM_FP32C, CHSIM_DEVICE_PTRS, CHSIM_GRAPH = 0, 1, 0x100, 0x200
 CHSIM_TUNE_EVOLVE_LANES = 1
 CHSIM_TUNE_PREFIX_SHARE = 2
+CHSIM_EVOLVE_LDS = 0x100
+# evolution shapes the autotuner times, in the order of its timings
+TUNE_SHAPES = (4, 8, 16, 32, 64, 4 | CHSIM_EVOLVE_LDS, 8 | CHSIM_EVOLVE_LDS, 16 | CHSIM_EVOLVE_LDS)
 MAX_BRANCH = 8
 
 EXPORTED = [
@@ -234,7 +237,8 @@ class Context:
             pass
 
     def set_evolve_lanes(self, lanes, inst=0):
-        """Lanes per term of the evolution kernel (8, 16, 32, 64; 0 = default;
+        """Lanes per term of the evolution kernel (4, 8, 16, 32, 64 with rows in
+        registers; 4, 8, 16 | CHSIM_EVOLVE_LDS with rows in LDS; 0 = default;
         -1 = autotune at the next evolution from |0^n>)."""
         _check(lib().chsim_set_tuning(self._h, inst, CHSIM_TUNE_EVOLVE_LANES, int(lanes)))
 
@@ -260,9 +264,9 @@ class Context:
                     levels=lv.value, distinct=list(dist)[:min(lv.value, max_levels)])
 
     def evolve_lanes(self, inst=0):
-        """(lanes in use, autotuner timings in ms for lanes 4, 8, 16, 32, 64)."""
+        """(lanes value in use, autotuner timings in ms for each of TUNE_SHAPES)."""
         v = C.c_int32()
-        t = (C.c_float * 5)()
+        t = (C.c_float * len(TUNE_SHAPES))()
         _check(lib().chsim_get_tuning(self._h, inst, CHSIM_TUNE_EVOLVE_LANES, C.byref(v), t))
         return v.value, list(t)
 

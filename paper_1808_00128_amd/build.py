@@ -25,13 +25,22 @@ FLAGS = [
 ]
 
 
+# The evolution kernels pick a tableau row by a chain of scalar branches with a
+# compile-time register index in each case; sinking the identical cases into
+# one block would turn that back into a dynamic index into stack memory.
+EXTRA_FLAGS = {
+    name: ["-mllvm", "-simplifycfg-sink-common=false"]
+    for name in ("evolve_l4.hip", "evolve_l8.hip", "evolve_wide.hip")
+}
+
+
 def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 
 def _compile(src, verbose):
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
+    cmd = [HIPCC, *FLAGS, *EXTRA_FLAGS.get(os.path.basename(src), []), "-c", src, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

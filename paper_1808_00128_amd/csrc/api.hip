@@ -59,6 +59,21 @@ struct DevBuf {
   }
 };
 
+// Evolution shapes the autotuner times, in the order of the reported
+// timings: lanes per term (| CHSIM_EVOLVE_LDS for rows in LDS).
+constexpr int kTuneShapes = 8;
+constexpr int kTuneLanes[kTuneShapes] = {4, 8, 16, 32, 64, 4 | CHSIM_EVOLVE_LDS, 8 | CHSIM_EVOLVE_LDS,
+                                         16 | CHSIM_EVOLVE_LDS};
+
+// EvolveShape of a tuning value (lanes, with CHSIM_EVOLVE_LDS for LDS rows).
+EvolveShape shape_of_value(uint32_t n, int value) {
+  EvolveShape s = evolve_shape_for(n, value & ~CHSIM_EVOLVE_LDS);
+  s.lds = (value & CHSIM_EVOLVE_LDS) != 0;
+  return s;
+}
+
+int value_of_shape(EvolveShape s) { return s.lanes | (s.lds ? CHSIM_EVOLVE_LDS : 0); }
+
 struct Instance {
   uint32_t n = 0, n_slot = 0, mode = 0;
   uint64_t chi = 0, seed = 0;
@@ -67,7 +82,7 @@ struct Instance {
   bool amp_ready = false;  // the amplitude prologue output matches the terms
   EvolveShape shape;    // evolution mapping (0 = default for n)
   bool autotune = false;  // time every shape at the next from-|0^n> evolution
-  float tuned_ms[5] = {0, 0, 0, 0, 0};  // per lanes 4, 8, 16, 32, 64 (0 = not timed)
+  float tuned_ms[kTuneShapes] = {};     // per tuned shape, kTuneLanes order (0 = not timed)
   std::vector<SlotTable> slots_h;
   std::vector<DGate> bgates_h;
   DevBuf<uint64_t> F, G, M, v, s;
@@ -783,11 +798,10 @@ chsim_status chsim_apply_clifford(chsim_ctx* ctx, uint32_t inst, const chsim_gat
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
-    const int cand[5] = {4, 8, 16, 32, 64};
     float best = 0.f;
     EvolveShape best_shape;
-    for (int ci = 0; ci < 5; ++ci) {
-      const EvolveShape sh = evolve_shape_for(I.n, cand[ci]);
+    for (int ci = 0; ci < kTuneShapes; ++ci) {
+      const EvolveShape sh = shape_of_value(I.n, kTuneLanes[ci]);
       I.tuned_ms[ci] = 0.f;
       if (!evolve_shape_supported(sh, I.n)) continue;
       HIP_TRY(hipEventRecord(e0, s));
@@ -1385,9 +1399,9 @@ chsim_status chsim_set_tuning(chsim_ctx* ctx, uint32_t inst, uint32_t knob, int3
         I.autotune = true;
         return CHSIM_OK;
       }
-      const EvolveShape s = evolve_shape_for(I.n, value);
-      if (!evolve_shape_supported(s, I.n))
-        return fail(CHSIM_EUNSUPPORTED, "no evolution kernel with %d lanes per term for n = %u", value, I.n);
+      const EvolveShape s = shape_of_value(I.n, value);
+      if (value < 0 || !evolve_shape_supported(s, I.n))
+        return fail(CHSIM_EUNSUPPORTED, "no evolution kernel for lanes value %d and n = %u", value, I.n);
       I.shape = s;
       return CHSIM_OK;
     }
@@ -1418,9 +1432,9 @@ chsim_status chsim_get_tuning(chsim_ctx* ctx, uint32_t inst, uint32_t knob, int3
   }
   if (knob != CHSIM_TUNE_EVOLVE_LANES) return fail(CHSIM_EINVAL, "unknown tuning knob %u", knob);
   EvolveShape sh = I.shape.lanes ? I.shape : evolve_default_shape(I.n);
-  if (value) *value = sh.lanes;
+  if (value) *value = value_of_shape(sh);
   if (timings_ms)
-    for (int i = 0; i < 5; ++i) timings_ms[i] = I.tuned_ms[i];
+    for (int i = 0; i < kTuneShapes; ++i) timings_ms[i] = I.tuned_ms[i];
   return CHSIM_OK;
 }
 

@@ -80,8 +80,12 @@ EvolveShape evolve_shape_for(uint32_t n, int lanes) {
 EvolveShape evolve_default_shape(uint32_t n) { return evolve_shape_for(n, n <= 16 ? 4 : 8); }
 
 // Instantiated shapes: lanes in {4, 8, 16, 32, 64} with rows = ceil(n / lanes)
-// and lanes * rows <= 64.
+// and lanes * rows <= 64; rows in LDS: lanes in {4, 8, 16} (gamma of a lane's
+// rows packed in 16 bits).
 bool evolve_shape_supported(EvolveShape s, uint32_t n) {
+  if (s.lds)
+    return (s.lanes == 4 || s.lanes == 8 || s.lanes == 16) && n >= 1 && n <= 64 &&
+           (uint32_t)s.lanes * 16u >= n;
   const bool lanes_ok = s.lanes == 4 || s.lanes == 8 || s.lanes == 16 || s.lanes == 32 || s.lanes == 64;
   return lanes_ok && s.rows >= 1 && (uint32_t)(s.lanes * s.rows) >= n && s.lanes * s.rows <= 64;
 }
@@ -91,6 +95,7 @@ hipError_t launch_evolve_job(const EvolveJob& J, const DGate* gates, uint32_t n_
   const uint32_t n = J.dst.n;
   if (shape.lanes == 0) shape = evolve_default_shape(n);
   if (!evolve_shape_supported(shape, n)) return hipErrorInvalidValue;
+  if (shape.lds) return launch_evolve_lds(shape.lanes, J, gates, n_gates, from_zero, err, st);
   if (shape.lanes == 4) return launch_evolve_l4(shape.rows, J, gates, n_gates, from_zero, err, st);
   if (shape.lanes == 8) return launch_evolve_l8(shape.rows, J, gates, n_gates, from_zero, err, st);
   return launch_evolve_wide(shape.lanes, shape.rows, J, gates, n_gates, from_zero, err, st);

@@ -9,14 +9,16 @@
 //
 // Left rules L[S], L[CZ], L[CX] of the Clifford-simulator section touch one
 // or two rows.  The row's register index is the same for every term of the
-// wave (the gate is), so it is dispatched on the scalar unit and only that
-// register is read or written; the row travels inside the group by
-// ds_bpermute (readlane for a whole-wave group).  The Hadamard update of
+// wave (the gate is), so a scalar branch picks it and only that register is
+// read or written; the row travels inside the group by ds_bpermute (readlane
+// for a whole-wave group).  The Hadamard update of
 // Eqs. (H1)-(H7) with Prop. H broadcasts row p, computes t, u, alpha, beta
 // once per lane, and applies V_C to every row at once: each batch of
 // commuting right rules (CX_{q,i} for i in a set W, CZ_{q,i} for i in V_1)
 // collapses to a parity and a masked XOR per row.
 #pragma once
+
+#include <type_traits>
 
 #include "device_common.hpp"
 #include "internal.hpp"
@@ -61,11 +63,28 @@ struct Lane {
   uint32_t li, base;  // lane index in the group, first lane of the group
 };
 
-// Left rules L[S]^pw, L[CZ], L[CX] in one shape: the gate decides (on the
-// scalar unit) which rows are read and broadcast in the group and what is
-// XORed into rows q and r; the writes themselves are unconditional, so the
-// row arrays are never modified on divergent or per-gate paths (that would
-// make the compiler copy whole arrays at every join).
+// Runs fn(j) with the compile-time register index j == k (k wave-uniform)
+// behind a chain of scalar branches.  Every row-array access is static, so
+// the arrays stay individual registers; the empty asm keeps each case a
+// branch target instead of a select over every register.
+template <int J, int RPL, typename Fn>
+__device__ __forceinline__ void at_row_from(uint32_t k, Fn& fn) {
+  if constexpr (J < RPL) {
+    if (k == (uint32_t)J) {
+      asm volatile("");
+      fn(std::integral_constant<int, J>{});
+    } else {
+      at_row_from<J + 1, RPL>(k, fn);
+    }
+  }
+}
+template <int RPL, typename Fn>
+__device__ __forceinline__ void at_row(uint32_t k, Fn&& fn) {
+  at_row_from<0, RPL>(k, fn);
+}
+
+// Left rules L[S]^pw, L[CZ], L[CX]: rows q and r are read at their register
+// index, broadcast in the group, and the lanes holding q or r update them.
 //   S^pw on q:   M_q ^= G_q pw times, gamma_q -= pw
 //   CZ_{q,r}:    M_q ^= G_r, M_r ^= G_q
 //   CX_{q,r}:    gamma_q += gamma_r + 2 (M_q . F_r) (M_q before the update),
@@ -77,31 +96,45 @@ __device__ __forceinline__ void sw_left(SubCH<LPT, RPL>& c, Lane L, uint32_t op,
   const uint32_t kq = uniform32(q / LPT), kr = uniform32(r / LPT);
   const uint64_t oq = 0ull - (uint64_t)(on && L.li == q % LPT);
   const uint64_t orr = 0ull - (uint64_t)(on && L.li == r % LPT);
-  uint64_t dFq = 0, dMq = 0, dGr = 0, dMr = 0;
-  uint32_t dgq = 0;
   if (op == OP_CX) {
-    const uint64_t Fr = gb64<LPT>(c.F[kr], r % LPT, L.base);
-    const uint64_t Mr = gb64<LPT>(c.M[kr], r % LPT, L.base);
-    const uint32_t gr = gb32<LPT>(c.g[kr], r % LPT, L.base);
-    const uint64_t Gq = gb64<LPT>(c.G[kq], q % LPT, L.base);
-    dFq = Fr & oq;
-    dMq = Mr & oq;
-    dgq = (gr + 2u * par64(c.M[kq] & Fr)) & (uint32_t)oq;
-    dGr = Gq & orr;
+    uint64_t Fr = 0, Mr = 0, Gq = 0, Mq = 0;
+    uint32_t gr = 0;
+    at_row<RPL>(kr, [&](auto j) {
+      Fr = c.F[j];
+      Mr = c.M[j];
+      gr = c.g[j];
+    });
+    at_row<RPL>(kq, [&](auto j) {
+      Gq = c.G[j];
+      Mq = c.M[j];
+    });
+    Fr = gb64<LPT>(Fr, r % LPT, L.base);
+    Mr = gb64<LPT>(Mr, r % LPT, L.base);
+    gr = gb32<LPT>(gr, r % LPT, L.base);
+    Gq = gb64<LPT>(Gq, q % LPT, L.base);
+    const uint32_t dg = (gr + 2u * par64(Mq & Fr)) & (uint32_t)oq;
+    at_row<RPL>(kq, [&](auto j) {
+      c.F[j] ^= Fr & oq;
+      c.M[j] ^= Mr & oq;
+      c.g[j] = (c.g[j] + dg) & 3u;
+    });
+    at_row<RPL>(kr, [&](auto j) { c.G[j] ^= Gq & orr; });
   } else if (op == OP_CZ) {
-    const uint64_t Gq = gb64<LPT>(c.G[kq], q % LPT, L.base);
-    const uint64_t Gr = gb64<LPT>(c.G[kr], r % LPT, L.base);
-    dMq = Gr & oq;
-    dMr = Gq & orr;
+    uint64_t Gq = 0, Gr = 0;
+    at_row<RPL>(kq, [&](auto j) { Gq = c.G[j]; });
+    at_row<RPL>(kr, [&](auto j) { Gr = c.G[j]; });
+    Gq = gb64<LPT>(Gq, q % LPT, L.base);
+    Gr = gb64<LPT>(Gr, r % LPT, L.base);
+    at_row<RPL>(kq, [&](auto j) { c.M[j] ^= Gr & oq; });
+    at_row<RPL>(kr, [&](auto j) { c.M[j] ^= Gq & orr; });
   } else {
-    dMq = c.G[kq] & oq & (0ull - (uint64_t)(pw & 1u));
-    dgq = (0u - pw) & (uint32_t)oq;
+    const uint64_t odd = oq & (0ull - (uint64_t)(pw & 1u));
+    const uint32_t dg = (0u - pw) & (uint32_t)oq;
+    at_row<RPL>(kq, [&](auto j) {
+      c.M[j] ^= c.G[j] & odd;
+      c.g[j] = (c.g[j] + dg) & 3u;
+    });
   }
-  c.F[kq] ^= dFq;
-  c.M[kq] ^= dMq;
-  c.g[kq] = (c.g[kq] + dgq) & 3u;
-  c.G[kr] ^= dGr;
-  c.M[kr] ^= dMr;
 }
 
 // Hadamard on qubit p: Eqs. (H2), (H4), the t = u case, and Prop. H with
@@ -109,10 +142,18 @@ __device__ __forceinline__ void sw_left(SubCH<LPT, RPL>& c, Lane L, uint32_t op,
 template <int LPT, int RPL>
 __device__ __forceinline__ void sw_h(SubCH<LPT, RPL>& c, Lane L, uint32_t p) {
   const uint32_t sp = p % LPT, kp = uniform32(p / LPT);
-  const uint64_t Fp = gb64<LPT>(c.F[kp], sp, L.base);
-  const uint64_t Gp = gb64<LPT>(c.G[kp], sp, L.base);
-  const uint64_t Mp = gb64<LPT>(c.M[kp], sp, L.base);
-  const uint32_t gp = gb32<LPT>(c.g[kp], sp, L.base);
+  uint64_t Fp = 0, Gp = 0, Mp = 0;
+  uint32_t gp = 0;
+  at_row<RPL>(kp, [&](auto j) {
+    Fp = c.F[j];
+    Gp = c.G[j];
+    Mp = c.M[j];
+    gp = c.g[j];
+  });
+  Fp = gb64<LPT>(Fp, sp, L.base);
+  Gp = gb64<LPT>(Gp, sp, L.base);
+  Mp = gb64<LPT>(Mp, sp, L.base);
+  gp = gb32<LPT>(gp, sp, L.base);
   const uint64_t v = c.v, s = c.s, nv = ~v;
   const uint64_t t = s ^ (Gp & v);
   const uint64_t u = s ^ (Fp & nv) ^ (Mp & v);

@@ -89,8 +89,10 @@ hipError_t launch_choose(const TermsView& T, const SlotTable* slots, uint32_t mo
                          double scale, hipStream_t st);
 // Evolution mapping: `lanes` lanes per term (4, 8, 16, 32 or 64; 64 / lanes
 // terms per wave) and `rows` = ceil(n / lanes) tableau rows per lane.  0 = choose.
+// lds: rows resident in LDS (evolve_lds.hip) instead of registers.
 struct EvolveShape {
   int lanes = 0, rows = 0;
+  bool lds = false;
 };
 EvolveShape evolve_shape_for(uint32_t n, int lanes);
 EvolveShape evolve_default_shape(uint32_t n);
@@ -127,6 +129,8 @@ hipError_t launch_evolve_l8(int rows, const EvolveJob& J, const DGate* gates, ui
                             bool from_zero, uint32_t* err, hipStream_t st);
 hipError_t launch_evolve_wide(int lanes, int rows, const EvolveJob& J, const DGate* gates,
                               uint32_t n_gates, bool from_zero, uint32_t* err, hipStream_t st);
+hipError_t launch_evolve_lds(int lanes, const EvolveJob& J, const DGate* gates, uint32_t n_gates,
+                             bool from_zero, uint32_t* err, hipStream_t st);
 hipError_t launch_evolve(const TermsView& T, const DGate* gates, uint32_t n_gates,
                          const uint32_t* slot_seq, uint32_t n_occ, bool from_zero, uint32_t* err,
                          EvolveShape shape, hipStream_t st);

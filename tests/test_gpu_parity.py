@@ -93,7 +93,8 @@ CASES = [
 @pytest.mark.parametrize("case", CASES, ids=[f"n{c[0]}-chi{c[3]}" for c in CASES])
 def test_evolution_bit_exact(B, case):
     """Every evolution shape (lanes per term 4, 8, 16, 32, 64 with ceil(n / lanes)
-    rows per lane) gives the oracle's terms bit for bit."""
+    rows per lane in registers; 4, 8, 16 lanes with the rows in LDS) gives the
+    oracle's terms bit for bit."""
     n, ng, m, chi, mode = case
     rng = np.random.default_rng(7000 + n)
     circ = W.random_circuit(n, ng, rng.uniform(0, 2 * np.pi, size=m), rng)
@@ -101,8 +102,10 @@ def test_evolution_bit_exact(B, case):
     idx = np.arange(chi, dtype=np.uint64) if chi <= 300 else np.unique(
         np.concatenate([[0, chi - 1], rng.integers(0, chi, size=120)])).astype(np.uint64)
     T = O.Terms(circ, chi, oracle_mode(spec), seed=spec["seed"], alphas=idx)
-    for lanes in (4, 8, 16, 32, 64):
-        say(f"evolution n={n} chi={chi} mode={mode} lanes={lanes}")
+    for lanes in B.TUNE_SHAPES:
+        if lanes & B.CHSIM_EVOLVE_LDS and (lanes & 0xff) * 16 < n:
+            continue
+        say(f"evolution n={n} chi={chi} mode={mode} lanes={lanes:#x}")
         ctx = B.Context([spec])
         ctx.set_evolve_lanes(lanes)
         ctx.apply_circuit(circ)
@@ -144,6 +147,18 @@ def test_evolution_prefix_share_bit_exact(B, case):
     b = plain.get_terms(0, chi)
     for key in a:
         assert np.array_equal(a[key], b[key]), key
+    for lanes in (4 | B.CHSIM_EVOLVE_LDS, 16 | B.CHSIM_EVOLVE_LDS):
+        if (lanes & 0xff) * 16 < n:
+            continue
+        say(f"prefix share n={n} chi={chi} rows in LDS lanes={lanes & 0xff}")
+        lds = B.Context([spec])
+        lds.set_prefix_share(2)
+        lds.set_evolve_lanes(lanes)
+        lds.apply_circuit(circ)
+        c = lds.get_terms(0, chi)
+        for key in a:
+            assert np.array_equal(c[key], b[key]), (lanes, key)
+        lds.close()
     x = W.random_bitstrings(n, 64, rng)
     assert normwise(shared.amplitudes(x), T.amplitudes(x) if chi <= 300 else plain.amplitudes(x)) < TOL64
 
@@ -174,7 +189,7 @@ def test_evolution_autotune_keeps_results(B):
     ctx.set_evolve_lanes(-1)
     ctx.apply_circuit(circ)
     lanes, times = ctx.evolve_lanes()
-    assert lanes in (4, 8, 16, 32, 64) and times[[4, 8, 16, 32, 64].index(lanes)] > 0
+    assert lanes in B.TUNE_SHAPES and times[B.TUNE_SHAPES.index(lanes)] > 0
     idx = np.arange(0, 777, 7, dtype=np.uint64)
     T = O.Terms(circ, 777, O.SPARSIFY, seed=9, alphas=idx)
     compare_terms(ctx, T, idx)
