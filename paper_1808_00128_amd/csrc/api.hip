@@ -399,22 +399,42 @@ namespace {
 // ---- shared-prefix evolution: plan ----------------------------------------
 // Evolution-kernel cost per gate, measured on MI355X at n = 50: the latency
 // of one gate for a lone wave, and the time per gate for 65536 items at full
-// occupancy, in microseconds, by kind (H, CX, CZ, S-type), for the packed
-// mapping (8 lanes per term) and the whole-wave mapping (64 lanes per term).
+// occupancy, in microseconds, by kind (H, CX, CZ, S-type); `cap` is how many
+// items the chip holds at once at n = 50 (0: not bounded below 65536), so a
+// launch of slightly more items than that takes a second, nearly empty round.
 struct GateCost {
   double lat[4], thr[4];
+  double cap;
 };
-constexpr GateCost kCostPacked = {{0.91, 0.61, 0.53, 0.52}, {4.29, 2.49, 2.10, 2.03}};
-constexpr GateCost kCostWave = {{0.41, 0.30, 0.30, 0.27}, {10.0, 5.94, 4.59, 4.83}};
-constexpr double kLevelCostUs = 30.0;  // prefix-id kernels and a launch per level
+constexpr GateCost kCostReg8 = {{0.87, 0.76, 0.67, 0.46}, {4.23, 2.52, 2.21, 1.57}, 0};
+constexpr GateCost kCostReg16 = {{0.70, 0.55, 0.50, 0.40}, {4.10, 2.70, 2.40, 1.80}, 0};
+constexpr GateCost kCostWave = {{0.46, 0.38, 0.35, 0.31}, {10.3, 6.82, 5.82, 5.08}, 0};
+constexpr GateCost kCostLds4 = {{2.3, 0.39, 0.31, 0.30}, {6.30, 0.79, 0.61, 0.63}, 0};
+constexpr GateCost kCostLds8 = {{1.5, 0.39, 0.30, 0.31}, {5.30, 0.95, 0.72, 0.74}, 0};
+constexpr GateCost kCostLds16 = {{1.05, 0.38, 0.30, 0.29}, {6.10, 1.38, 1.07, 1.11}, 0};
+constexpr double kLevelCostUs = 45.0;  // prefix-id kernels and a launch per level
+
+// Cost table of the mapping a span would run with (the whole-wave mapping
+// for lanes = 64, the register tables otherwise).
+const GateCost& cost_of(EvolveShape s) {
+  if (s.lds) return s.lanes == 4 ? kCostLds4 : s.lanes == 8 ? kCostLds8 : kCostLds16;
+  if (s.lanes == 64 || s.lanes == 32) return kCostWave;
+  return s.lanes >= 16 ? kCostReg16 : kCostReg8;
+}
 
 int gate_kind(const DGate& g) {
   return g.op == OP_H ? 0 : g.op == OP_CX ? 1 : g.op == OP_CZ ? 2 : 3;
 }
 
 // Estimated time of `items` work items through gates with `cnt[kind]` gates
-// of each kind; the row count scales the per-item throughput term.
+// of each kind; the row count scales the per-item throughput term and the
+// capacity (rows held on chip), and items beyond the capacity are charged
+// whole rounds.
 double span_us(const GateCost& c, const double cnt[4], double items, double row_scale) {
+  if (c.cap > 0) {
+    const double cap = c.cap / row_scale;
+    if (items > cap) items = std::ceil(items / cap) * cap;
+  }
   double t = 0.0;
   for (int k = 0; k < 4; ++k) t += cnt[k] * std::max(c.lat[k], items * c.thr[k] * row_scale / 65536.0);
   return t;
@@ -478,7 +498,7 @@ std::vector<double> estimate_distinct(const Instance& I, const std::vector<uint1
 // below by the latency of the gates for a lone wave; every level adds a
 // fixed cost; the last span runs chi terms.  Mode 2 drops the fixed cost and
 // takes any plan that saves work, so that small tests exercise the path.
-void plan_prefix(Instance& I, const std::vector<DGate>& dg) {
+void plan_prefix(Instance& I, const std::vector<DGate>& dg, EvolveShape shape) {
   I.plan_cut.clear();
   I.plan_lanes.clear();
   I.plan_span_off.assign(1, 0);
@@ -516,7 +536,7 @@ void plan_prefix(Instance& I, const std::vector<DGate>& dg) {
   auto seg = [&](size_t i, size_t j, double items, int* lanes) {
     double cnt[4];
     for (int k = 0; k < 4; ++k) cnt[k] = (j <= m ? C[j][k] : Ct[k]) - C[i][k];
-    const double tp = span_us(kCostPacked, cnt, items, rows);
+    const double tp = span_us(cost_of(shape), cnt, items, rows);
     const double tw = span_us(kCostWave, cnt, items, rows);
     if (lanes) *lanes = tw < tp ? 64 : 0;
     return std::min(tp, tw);
@@ -620,6 +640,7 @@ Instance::SpanStat span_stat(const std::vector<DGate>& dg, uint32_t g0, uint32_t
 
 chsim_status evolve_all(chsim_ctx* ctx, Instance& I, const std::vector<DGate>& dg, EvolveShape shape,
                         bool from_zero, hipStream_t s) {
+  if (shape.lanes == 0) shape = evolve_default_shape(I.n);
   const uint32_t ng = (uint32_t)dg.size();
   const uint32_t n_occ_all = (uint32_t)ctx->occ_start.size();
   // Slot occurrences whose first gate lies in [g0, g1).
@@ -636,9 +657,9 @@ chsim_status evolve_all(chsim_ctx* ctx, Instance& I, const std::vector<DGate>& d
                           shape, s));
     return CHSIM_OK;
   }
-  const uint64_t key = gates_key(I, dg);
+  const uint64_t key = gates_key(I, dg) ^ ((uint64_t)(shape.lanes | (shape.lds ? 0x100 : 0)) << 48);
   if (!I.plan_valid || I.plan_key != key) {
-    plan_prefix(I, dg);
+    plan_prefix(I, dg, shape);
     I.plan_key = key;
     I.plan_valid = true;
     if (!I.plan_cut.empty()) {

@@ -77,7 +77,12 @@ EvolveShape evolve_shape_for(uint32_t n, int lanes) {
   return s;
 }
 
-EvolveShape evolve_default_shape(uint32_t n) { return evolve_shape_for(n, n <= 16 ? 4 : 8); }
+// Default: rows in LDS, 8 lanes per term (4 for n <= 16).
+EvolveShape evolve_default_shape(uint32_t n) {
+  EvolveShape s = evolve_shape_for(n, n <= 16 ? 4 : 8);
+  s.lds = true;
+  return s;
+}
 
 // Instantiated shapes: lanes in {4, 8, 16, 32, 64} with rows = ceil(n / lanes)
 // and lanes * rows <= 64; rows in LDS: lanes in {4, 8, 16} (gamma of a lane's
