@@ -713,6 +713,7 @@ chsim_status evolve_all(chsim_ctx* ctx, Instance& I, const std::vector<DGate>& d
     A.id_out = ctx->pf_id[k % 2].p;
     A.rep = ctx->pf_rep.p;
     A.parent = ctx->pf_parent.p;
+    A.first_counters = k == 0 ? (uint32_t)K : 0u;
     HIP_TRY(launch_prefix_level(A, s));
     EvolveJob J;
     J.src = ckpt_view(ctx, I, (int)((k + 1) % 2));

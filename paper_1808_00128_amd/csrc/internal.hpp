@@ -158,6 +158,7 @@ struct PrefixLevelArgs {
   uint32_t* id_out;
   uint32_t* rep;
   uint32_t* parent;
+  uint32_t first_counters;  // > 0 at the first level: clear the table and this many counters
 };
 hipError_t launch_prefix_level(const PrefixLevelArgs& A, hipStream_t st);
 hipError_t launch_sample(const TermsView& T, const uint64_t* alpha, const uint64_t* flips,

@@ -29,10 +29,13 @@ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
   return z ^ (z >> 31);
 }
 
+// Before the first level: an empty table and zero id counters for every
+// level (later levels find the table emptied by the previous level's
+// k_prefix_assign).
 __global__ __launch_bounds__(256) void k_prefix_clear(PrefixLevelArgs A) {
   const uint64_t h = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (h <= A.table_mask) A.table[h] = kEmpty;
-  if (h == 0) *A.counter = 0u;
+  if (h < A.first_counters) A.counter[h] = 0u;
 }
 
 __global__ __launch_bounds__(256) void k_prefix_insert(PrefixLevelArgs A) {
@@ -63,18 +66,32 @@ __global__ __launch_bounds__(256) void k_prefix_insert(PrefixLevelArgs A) {
   A.slot_of[a] = (uint32_t)h;
 }
 
-// One atomic per wave: the wave's occupied entries take consecutive ids.
-__global__ __launch_bounds__(256) void k_prefix_assign(PrefixLevelArgs A) {
+// One atomic per workgroup: the occupied entries of a workgroup take
+// consecutive ids, in wave order and lane order within a wave.  Each entry
+// is emptied once read, which leaves the table clear for the next level.
+constexpr uint32_t kAssignThreads = 1024;
+
+__global__ __launch_bounds__(kAssignThreads) void k_prefix_assign(PrefixLevelArgs A) {
+  __shared__ uint32_t wave_cnt[kAssignThreads / 64];
+  __shared__ uint32_t block_base;
   const uint64_t h = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool occ = h <= A.table_mask && A.table[h] != kEmpty;
+  if (occ) A.table[h] = kEmpty;
   const uint64_t m = ballot64(occ);
-  if (m == 0ull) return;
-  const uint32_t lane = threadIdx.x & 63u;
-  const uint32_t leader = (uint32_t)__builtin_ctzll(m);
-  uint32_t base = 0;
-  if (lane == leader) base = atomicAdd(A.counter, (uint32_t)__popcll(m));
-  base = (uint32_t)__builtin_amdgcn_readlane((int)base, (int)leader);
-  if (occ) A.ids[h] = base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+  if (lane == 0) wave_cnt[wave] = (uint32_t)__popcll(m);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t run = 0;
+    for (uint32_t k = 0; k < kAssignThreads / 64; ++k) {
+      const uint32_t c = wave_cnt[k];
+      wave_cnt[k] = run;
+      run += c;
+    }
+    block_base = run ? atomicAdd(A.counter, run) : 0u;
+  }
+  __syncthreads();
+  if (occ) A.ids[h] = block_base + wave_cnt[wave] + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
 }
 
 // Term a's id, the representative term of each id (any term with that
@@ -94,9 +111,11 @@ __global__ __launch_bounds__(256) void k_prefix_map(PrefixLevelArgs A) {
 hipError_t launch_prefix_level(const PrefixLevelArgs& A, hipStream_t st) {
   const uint64_t ts = A.table_mask + 1ull;
   const uint32_t tb = (uint32_t)((ts + 255) / 256), cb = (uint32_t)((A.chi + 255) / 256);
-  hipLaunchKernelGGL(k_prefix_clear, dim3(tb), dim3(256), 0, st, A);
+  if (A.first_counters)
+    hipLaunchKernelGGL(k_prefix_clear, dim3(tb), dim3(256), 0, st, A);
   hipLaunchKernelGGL(k_prefix_insert, dim3(cb), dim3(256), 0, st, A);
-  hipLaunchKernelGGL(k_prefix_assign, dim3(tb), dim3(256), 0, st, A);
+  hipLaunchKernelGGL(k_prefix_assign, dim3((uint32_t)((ts + kAssignThreads - 1) / kAssignThreads)),
+                     dim3(kAssignThreads), 0, st, A);
   hipLaunchKernelGGL(k_prefix_map, dim3(cb), dim3(256), 0, st, A);
   return hipGetLastError();
 }
