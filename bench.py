@@ -68,7 +68,7 @@ KERNEL_SOURCES = {
     "k_evolve_lds": ["evolve_lds.hip", "evolve.hip", "prefix.hip", "device_common.hpp", "internal.hpp",
                      "api.hip"],
     "k_amp<float>": ["amplitude.hip", "device_common.hpp", "internal.hpp", "api.hip"],
-    "k_inner": ["inner.hip", "device_common.hpp", "internal.hpp", "api.hip"],
+    "k_inner_pairs": ["inner.hip", "device_common.hpp", "internal.hpp", "api.hip"],
 }
 
 
@@ -134,10 +134,10 @@ def bench_norm(torch, B, W, L=1024):
             "seconds": t1 - t0, "inner_products_per_s": pairs / (t1 - t0),
             "eta_mean": eta_mean, "eta_sem": float(np.std(eta, ddof=1) / np.sqrt(L)),
             "mean_v_weight": mean_v,
-            "roofline": {"bound": "alu", "kernel": "k_inner (one wave per term, lane = row)",
+            "roofline": {"bound": "alu", "kernel": "k_inner_prep + k_inner_pairs (lane = equatorial state)",
                          "achieved": round(achieved, 3), "peak": round(INT32_PEAK_OPS / 1e12, 2),
                          "unit": "TOP/s (int32)", "frac": round(achieved / (INT32_PEAK_OPS / 1e12), 4),
-                         "traffic": counter_traffic("k_inner"), "ops_per_pair": ops_pair}}
+                         "traffic": counter_traffic("k_inner_pairs"), "ops_per_pair": ops_pair}}
 
 
 def start_points(ctx, n, chi, count, rng):

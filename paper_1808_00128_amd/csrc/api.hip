@@ -171,7 +171,7 @@ struct chsim_ctx {
   DevBuf<uint32_t> err;
   DevBuf<uint64_t> xbuf;
   DevBuf<double2> partial, out;
-  DevBuf<uint64_t> aoff;
+  DevBuf<uint64_t> aoff, inner_work;
   DevBuf<uint8_t> adiag;
   DevBuf<double> eta;
   DevBuf<double> eta_sum;
@@ -1076,8 +1076,9 @@ chsim_status chsim_inner_products(chsim_ctx* ctx, uint32_t inst, const uint64_t*
       ao = ctx->aoff.p;
       ad = ctx->adiag.p;
     }
-    uint32_t nb = 0;
-    HIP_TRY(ctx->partial.ensure(inner_partial_elems(I.view(), Lc, &nb)));
+    const InnerPlan ip = inner_plan(I.view(), Lc);
+    HIP_TRY(ctx->partial.ensure(ip.partial_elems));
+    HIP_TRY(ctx->inner_work.ensure(ip.work_words));
     double2* ovd;
     double* etad;
     if (dev) {
@@ -1093,7 +1094,8 @@ chsim_status chsim_inner_products(chsim_ctx* ctx, uint32_t inst, const uint64_t*
       ovd = ctx->out.p;
       etad = ctx->eta.p;
     }
-    HIP_TRY(launch_inner(I.view(), ao, ad, Lc, ctx->partial.p, nb, ovd, etad, ctx->eta_sum.p, ctx->err.p, s));
+    HIP_TRY(launch_inner(I.view(), ao, ad, Lc, ip, ctx->partial.p, ctx->inner_work.p, ovd, etad, ctx->eta_sum.p,
+                         ctx->err.p, s));
     double part = 0.0;
     HIP_TRY(hipMemcpyAsync(&part, ctx->eta_sum.p, sizeof(double), hipMemcpyDeviceToHost, s));
     if (!dev) {
@@ -1530,6 +1532,7 @@ chsim_status chsim_destroy(chsim_ctx* ctx) {
   }
   ctx->out.release();
   ctx->aoff.release();
+  ctx->inner_work.release();
   ctx->adiag.release();
   ctx->eta.release();
   ctx->eta_sum.release();

@@ -10,16 +10,22 @@
 // variables with the identity sum_{x1,x2} (-1)^{x1 x2 + mu1 x1 + mu2 x2} =
 // 2 (-1)^{mu1 mu2} (Eq. (eq5)).
 //
-// Mapping: one wave per term, lane a holds row a of every n x n bit matrix.
-// K = G^T X G splits into Y = G^T X (row a = XOR of the rows X_c with c in
-// column a of G) and K = Y G (row a = XOR of the rows G_d with d in row a of
-// Y); the rows of the other operand come by readlane.  The diagonal mod 4
-// uses popcounts of G's column against X's diagonal bit-planes and the parity
-// of the strictly-upper part.  The elimination keeps the symmetric Z_2
-// adjacency S in the lanes (lane c = row c); a pivot pair (a, b) is found by
-// ballot + find-first-set, and the rank-2 update S_c ^= [c in m1] m2 ^
-// [c in m2] m1 is one masked XOR per lane.  K_J is computed once per term and
-// every equatorial state reuses it (K is linear in A + J).
+// Mapping.  A per-term prologue (one wave per term, lane = row) stores the
+// term's rows and columns of G and K_J = G^T J G with the vectors the pair
+// step needs; K_J is shared by every equatorial state since K is linear in
+// A + J.  The pair kernel gives each lane one equatorial state A (64 per
+// wave) and walks the terms, so everything that depends only on the term is
+// wave-uniform:
+//   Z_c = A_c G and W_c = U_c G (U = strictly upper part of A) by lookup in
+//   tables of XORs of G's rows, four rows per table (Four Russians);
+//   K_A restricted to supp(v): row a = XOR of Z_c over c with G_ca = 1;
+//   diag(K_A) mod 4 = G-column popcounts against A's diagonal planes plus
+//   2 (XOR_c G_c & W_c);  (s K_A) = XOR_c G_c [A_c . y] and
+//   s K_A s^T = y^T A y mod 4 with y = G s.
+// Each lane then eliminates its own Z_2 form (rows in LDS, pivots chosen
+// per lane) and adds b_alpha <phi_A|phi_alpha> to its state's sum.
+#include <algorithm>
+
 #include "device_common.hpp"
 #include "internal.hpp"
 
@@ -62,95 +68,7 @@ __device__ __forceinline__ void conj_gxg(uint64_t G, uint64_t Gt, uint64_t Xoff,
 struct InnerRec {
   uint32_t nonzero, k8;
   int e2;
-  uint32_t bad;
 };
-
-// Evaluate one pair from the term's K (lane rows).  Wave-uniform result:
-// <phi_A|phi> = 0 or e^{i pi k8/4} 2^{e2/2} (omega included).
-__device__ __forceinline__ InnerRec pair_record(uint64_t Koff, uint32_t Kdiag, uint64_t v,
-                                                uint64_t s, uint32_t omega, uint32_t lane,
-                                                uint32_t n) {
-  InnerRec rec{0u, 0u, 0, 0u};
-  const bool act = lane < n;
-  const uint64_t lb = 1ull << lane;
-  const uint32_t sl = (uint32_t)((s >> lane) & 1ull);
-  const uint64_t Krow = act ? (Koff | ((uint64_t)(Kdiag & 1u) << lane)) : 0ull;
-  // (sK)_a = par(s & K_a) (K symmetric); s K s^T mod 4.
-  const uint32_t skl = par64(s & Krow);
-  const uint64_t upper = (lane == 63u) ? 0ull : (~0ull << (lane + 1u));
-  const uint64_t kdlo = ballot64(act && (Kdiag & 1u)), kdhi = ballot64(act && (Kdiag & 2u));
-  const uint64_t pairs = ballot64(act && sl && par64(Koff & s & upper));
-  const uint32_t sks =
-      ((uint32_t)__popcll(s & kdlo) + 2u * (uint32_t)__popcll(s & kdhi) + 2u * (uint32_t)__popcll(pairs)) & 3u;
-  const uint32_t sv = par64(s & v);
-  // B on supp(v): diagonal K_aa + 2 (s_a + (sK)_a), off-diagonal K_ab.
-  const bool inv = act && ((v >> lane) & 1ull);
-  const uint32_t Bd = (Kdiag + 2u * (sl ^ skl)) & 3u;
-  // Z_2 lift (Eq. (Q)): kappa_a = B_aa & 1, lambda_a = B_aa >> 1; extra variable e.
-  const uint64_t kap = ballot64(inv && (Bd & 1u));
-  const uint64_t lam = ballot64(inv && (Bd & 2u));
-  if (v == ~0ull) {
-    rec.bad = 1u;
-    return rec;
-  }
-  const uint32_t e = (uint32_t)__builtin_ctzll(~v);
-  const uint64_t eb = 1ull << e;
-  uint64_t S = 0;
-  if (inv) S = (((Koff & v) ^ (((Bd & 1u) ? kap : 0ull))) & ~lb) | ((uint64_t)(Bd & 1u) << e);
-  if (lane == e) S = kap;
-  uint64_t lr = lam, li = lam | eb;  // linear parts for Re (x_e coefficient 0) and Im (1)
-  uint64_t rem = v | eb;
-  uint32_t sr = 0, si = 0, nel = 0;
-  for (;;) {
-    const uint64_t nz = ballot64(S != 0ull);
-    if (!nz) break;
-    const uint32_t a = (uint32_t)__builtin_ctzll(nz);
-    const uint64_t Sa = rl64(S, a);
-    const uint32_t b = (uint32_t)__builtin_ctzll(Sa);
-    const uint64_t Sb = rl64(S, b);
-    const uint64_t ab = (1ull << a) | (1ull << b);
-    const uint64_t m1 = Sa & ~ab, m2 = Sb & ~ab;
-    S ^= (m2 & bitmask64(m1, lane)) ^ (m1 & bitmask64(m2, lane));
-    S &= ~ab;
-    if (lane == a || lane == b) S = 0ull;
-    {
-      const uint64_t la = (lr >> a) & 1ull, lbb = (lr >> b) & 1ull;
-      sr ^= (uint32_t)(la & lbb);
-      lr ^= (m2 & (0ull - la)) ^ (m1 & (0ull - lbb)) ^ (m1 & m2);
-      lr &= ~ab;
-    }
-    {
-      const uint64_t la = (li >> a) & 1ull, lbb = (li >> b) & 1ull;
-      si ^= (uint32_t)(la & lbb);
-      li ^= (m2 & (0ull - la)) ^ (m1 & (0ull - lbb)) ^ (m1 & m2);
-      li &= ~ab;
-    }
-    rem &= ~ab;
-    ++nel;
-  }
-  const int r = __popcll(rem);
-  const bool re_nz = (lr & rem) == 0ull, im_nz = (li & rem) == 0ull;
-  // Re Z = (-1)^sr 2^{nel + r - 1}, Im Z likewise; both non-zero only with equal exponents.
-  const int ez0 = (int)nel + r - 1;
-  if (!re_nz && !im_nz) return rec;
-  uint32_t kz;
-  int ez;
-  if (re_nz && im_nz) {
-    kz = sr ? (si ? 5u : 3u) : (si ? 7u : 1u);
-    ez = 2 * ez0 + 1;
-  } else if (re_nz) {
-    kz = sr ? 4u : 0u;
-    ez = 2 * ez0;
-  } else {
-    kz = si ? 6u : 2u;
-    ez = 2 * ez0;
-  }
-  const uint32_t kin = (2u * sks + 4u * sv + kz) & 7u;
-  rec.nonzero = 1u;
-  rec.k8 = (omega - kin) & 7u;  // <phi_A|omega phi> = omega conj(<phi|phi_A>)
-  rec.e2 = ez - (int)(n + (uint32_t)__popcll(v));
-  return rec;
-}
 
 __device__ __forceinline__ double2 rec_value(const InnerRec& r, double2 b) {
   const double h = 0.70710678118654752440;
@@ -171,73 +89,259 @@ __device__ __forceinline__ double2 rec_value(const InnerRec& r, double2 b) {
   return make_double2(mag * (b.x * cr - b.y * ci), mag * (b.x * ci + b.y * cr));
 }
 
-__global__ __launch_bounds__(256) void k_inner(TermsView Tv, const uint64_t* __restrict__ Aoff,
-                                               const uint8_t* __restrict__ Adiag, uint32_t L,
-                                               double2* __restrict__ partial,
-                                               uint32_t* __restrict__ err) {
-  extern __shared__ __align__(16) double2 acc[];  // [kWaves][L]
+// Per-term record (words): G rows [0, n), G columns [n, 2n), K_J off-diagonal
+// rows [2n, 3n), then diag(K_J) low and high bit planes, (s K_J) with the
+// diagonal low bits, y = G s, and s K_J s^T mod 4.
+__host__ __device__ constexpr uint32_t inner_rec_words(uint32_t n) { return 3u * n + 5u; }
+
+__global__ __launch_bounds__(256) void k_inner_prep(TermsView Tv, uint64_t* __restrict__ rec) {
   const uint32_t tid = threadIdx.x, lane = tid & 63u;
-  const uint32_t wave = uniform32(tid >> 6);
-  double2* my = acc + (size_t)wave * L;
-  for (uint32_t l = lane; l < L; l += 64u) my[l] = make_double2(0.0, 0.0);
   const uint32_t n = Tv.n;
   const bool act = lane < n;
+  const uint64_t term = (uint64_t)blockIdx.x * kWaves + uniform32(tid >> 6);
+  if (term >= Tv.chi) return;  // whole wave
   const uint64_t chi = Tv.chi;
+  const uint64_t off = (uint64_t)lane * chi + term;
+  const uint64_t F = act ? Tv.F[off] : 0ull;
+  const uint64_t G = act ? Tv.G[off] : 0ull;
+  const uint64_t M = act ? Tv.M[off] : 0ull;
+  const uint32_t g = act ? Tv.gamma[off] : 0u;
+  const uint64_t s = uniform64(Tv.s[term]);
+  // Column `lane` of G.
+  uint64_t Gt = 0;
+  for (uint32_t a = 0; a < n; ++a) {
+    const uint64_t col = ballot64(((G >> a) & 1ull) != 0ull);
+    if (lane == a) Gt = col;
+  }
+  // J: diag gamma, J_ab = par(M_a & F_b) for a != b.
+  uint64_t Joff = 0;
+  for (uint32_t bb = 0; bb < n; ++bb) {
+    const uint64_t Fb = rl64(F, bb);
+    Joff |= (uint64_t)par64(M & Fb) << bb;
+  }
+  uint64_t KJoff;
+  uint32_t KJdiag;
+  conj_gxg(G, Gt, Joff, g, lane, n, KJoff, KJdiag);
+  const uint64_t lb = 1ull << lane;
+  const uint64_t Krow = act ? (KJoff | ((uint64_t)(KJdiag & 1u) << lane)) : 0ull;
+  const uint64_t kdlo = ballot64(act && (KJdiag & 1u)), kdhi = ballot64(act && (KJdiag & 2u));
+  const uint64_t skj = ballot64(act && par64(s & Krow));
+  const uint64_t upper = (lane == 63u) ? 0ull : (~0ull << (lane + 1u));
+  const uint64_t pairs = ballot64(act && ((s >> lane) & 1ull) && par64(KJoff & s & upper));
+  const uint32_t sks = ((uint32_t)__popcll(s & kdlo) + 2u * (uint32_t)__popcll(s & kdhi) +
+                        2u * (uint32_t)__popcll(pairs)) & 3u;
+  const uint64_t y = ballot64(act && par64(G & s));
+  uint64_t* r = rec + term * inner_rec_words(n);
+  if (act) {
+    r[lane] = G;
+    r[n + lane] = Gt;
+    r[2u * n + lane] = KJoff & ~lb;
+  }
+  if (lane == 0) {
+    r[3u * n] = kdlo;
+    r[3u * n + 1u] = kdhi;
+    r[3u * n + 2u] = skj;
+    r[3u * n + 3u] = y;
+    r[3u * n + 4u] = sks;
+  }
+}
+
+// A as 64-state columns: at[c][l] = row c of A_l with its diagonal low bit
+// at c, and the diagonal bit planes of every state (zero past L).
+__global__ __launch_bounds__(256) void k_inner_atrans(const uint64_t* __restrict__ Aoff,
+                                                      const uint8_t* __restrict__ Adiag, uint32_t n,
+                                                      uint32_t L, uint32_t Lp, uint64_t* __restrict__ at,
+                                                      uint64_t* __restrict__ planes) {
+  const uint32_t l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= Lp) return;
+  uint64_t lo = 0, hi = 0;
+  for (uint32_t c = 0; c < n; ++c) {
+    uint64_t row = 0;
+    if (l < L) {
+      const uint32_t d = Adiag[(uint64_t)l * n + c];
+      row = (Aoff[(uint64_t)l * n + c] & ~(1ull << c)) | ((uint64_t)(d & 1u) << c);
+      lo |= (uint64_t)(d & 1u) << c;
+      hi |= (uint64_t)((d >> 1) & 1u) << c;
+    }
+    at[(uint64_t)c * Lp + l] = row;
+  }
+  planes[l] = lo;
+  planes[Lp + l] = hi;
+}
+
+// One wave per (term group, batch of 64 states); lane = state.
+template <int NMAX>
+__global__ __launch_bounds__(64) void k_inner_pairs(TermsView Tv, const uint64_t* __restrict__ rec,
+                                                    const uint64_t* __restrict__ at,
+                                                    const uint64_t* __restrict__ planes, uint32_t L,
+                                                    uint32_t Lp, double2* __restrict__ partial,
+                                                    uint32_t* __restrict__ err) {
+  extern __shared__ __align__(16) uint64_t lds_w[];
+  const uint32_t n = Tv.n;
+  const uint32_t nch = (n + 3u) / 4u;
+  uint64_t* const gtab = lds_w;              // [nch][16] XORs of G's rows
+  uint64_t* const Srow = lds_w + 16u * 16u;  // [n + 1][64] elimination rows, lane-minor
+  const uint32_t lane = threadIdx.x;
+  const uint32_t l = blockIdx.y * 64u + lane;
+  const uint64_t adlo = planes[l], adhi = planes[Lp + l];
+  const uint64_t* __restrict__ atl = at + l;
+  const uint32_t R = inner_rec_words(n);
+  double accr = 0.0, acci = 0.0;
   uint32_t bad = 0;
-  for (uint64_t term = (uint64_t)blockIdx.x * kWaves + wave; term < chi;
-       term += (uint64_t)gridDim.x * kWaves) {
-    const uint64_t off = (uint64_t)lane * chi + term;
-    const uint64_t F = act ? Tv.F[off] : 0ull;
-    const uint64_t G = act ? Tv.G[off] : 0ull;
-    const uint64_t M = act ? Tv.M[off] : 0ull;
-    const uint32_t g = act ? Tv.gamma[off] : 0u;
+  for (uint64_t term = blockIdx.x; term < Tv.chi; term += gridDim.x) {
+    const uint64_t* r = rec + term * R;
+    // Row c of G, column c of G, row c of K_J: lane c holds them.
+    const uint64_t Gl = lane < n ? r[lane] : 0ull;
+    const uint64_t Gtl = lane < n ? r[n + lane] : 0ull;
+    const uint64_t KJl = lane < n ? r[2u * n + lane] : 0ull;
+    const uint64_t kjdlo = uniform64(r[3u * n]), kjdhi = uniform64(r[3u * n + 1u]);
+    const uint64_t skj = uniform64(r[3u * n + 2u]), y = uniform64(r[3u * n + 3u]);
+    const uint32_t sksj = uniform32((uint32_t)r[3u * n + 4u]);
     const uint64_t v = uniform64(Tv.v[term]), s = uniform64(Tv.s[term]);
     const uint32_t omega = uniform32(Tv.omega[term]);
-    const double2 b = Tv.b[term];
-    // Column `lane` of G.
-    uint64_t Gt = 0;
-    for (uint32_t a = 0; a < n; ++a) {
-      const uint64_t col = ballot64(((G >> a) & 1ull) != 0ull);
-      if (lane == a) Gt = col;
+    const double2 bb = Tv.b[term];
+    if (v == ~0ull) {
+      bad = 1u;
+      continue;
     }
-    // J: diag gamma, J_ab = par(M_a & F_b) for a != b.
-    uint64_t Joff = 0;
-    for (uint32_t bb = 0; bb < n; ++bb) {
-      const uint64_t Fb = rl64(F, bb);
-      Joff |= (uint64_t)par64(M & Fb) << bb;
-    }
-    uint64_t KJoff;
-    uint32_t KJdiag;
-    conj_gxg(G, Gt, Joff, g, lane, n, KJoff, KJdiag);
-    for (uint32_t l = 0; l < L; ++l) {
-      const uint64_t Ao = act ? Aoff[(uint64_t)l * n + lane] : 0ull;
-      const uint32_t Ad = act ? Adiag[(uint64_t)l * n + lane] : 0u;
-      uint64_t KAoff;
-      uint32_t KAdiag;
-      conj_gxg(G, Gt, Ao, Ad, lane, n, KAoff, KAdiag);
-      const uint64_t Koff = KJoff ^ KAoff;
-      const uint32_t Kdiag = (KJdiag + KAdiag) & 3u;
-      const InnerRec rec = pair_record(Koff, Kdiag, v, s, omega, lane, n);
-      bad |= rec.bad;
-      if (rec.nonzero && lane == 0u) {
-        const double2 val = rec_value(rec, b);
-        double2 cur = my[l];
-        cur.x += val.x;
-        cur.y += val.y;
-        my[l] = cur;
+    // Lookup tables: gtab[k][e] = XOR of G rows 4k + i over the bits i of e.
+    for (uint32_t k = 0; k < nch; ++k) {
+      uint64_t t = 0;
+      for (uint32_t i = 0; i < 4u; ++i) {
+        const uint32_t row = 4u * k + i;
+        if (row < n) t ^= rl64(Gl, row) & (0ull - (uint64_t)((lane >> i) & 1u));
       }
+      if (lane < 16u) gtab[k * 16u + lane] = t;
+    }
+    __builtin_amdgcn_wave_barrier();
+    // One pass over A's rows.
+    uint64_t Sacc[NMAX];
+#pragma unroll
+    for (int a = 0; a < NMAX; ++a) Sacc[a] = 0ull;
+    uint64_t D = 0, sKA = 0, tU = 0;
+    for (uint32_t c = 0; c < n; ++c) {
+      const uint64_t Gc = rl64(Gl, c);
+      const uint64_t Ac = atl[(uint64_t)c * Lp];
+      const uint64_t upc = (c == 63u) ? 0ull : (~0ull << (c + 1u));
+      const uint64_t Uc = Ac & upc;
+      // Z_c = A_c G and W_c = U_c G, chunks from the top: above c the two
+      // nibbles agree, the chunk holding c differs, below it U_c is zero.
+      uint64_t Z = 0, W = 0;
+      for (uint32_t k = nch; k-- > 0;) {
+        const uint32_t lo = 4u * k;
+        const uint64_t tz = gtab[k * 16u + (uint32_t)((Ac >> lo) & 15ull)];
+        Z ^= tz;
+        if (lo > c) {
+          W ^= tz;
+        } else if (lo + 4u > c) {
+          W ^= gtab[k * 16u + (uint32_t)((Uc >> lo) & 15ull)];
+        }
+      }
+      D ^= Gc & W;
+      sKA ^= Gc & (0ull - (uint64_t)par64(Ac & y));
+      if ((y >> c) & 1ull) tU ^= Uc & y;
+      const uint64_t Zv = Z & v, Gcv = Gc & v;
+#pragma unroll
+      for (int a = 0; a < NMAX; ++a) Sacc[a] ^= Zv & (0ull - ((Gcv >> a) & 1ull));
+    }
+    // B on supp(v): Bd_a = K_aa + 2 (s_a + (sK)_a) with K = K_J + K_A.
+    const uint64_t skl = skj ^ sKA;
+    uint64_t kap = 0, lam = 0;
+    for (uint64_t m = v; m; m &= m - 1ull) {
+      const uint32_t a = (uint32_t)__builtin_ctzll(m);
+      const uint64_t ga = rl64(Gtl, a);
+      const uint32_t kd = (uint32_t)((kjdlo >> a) & 1ull) + 2u * (uint32_t)((kjdhi >> a) & 1ull) +
+                          (uint32_t)__popcll(ga & adlo) + 2u * (uint32_t)__popcll(ga & adhi) +
+                          2u * (uint32_t)((D >> a) & 1ull);
+      const uint32_t bd = (kd + 2u * (uint32_t)(((s ^ skl) >> a) & 1ull)) & 3u;
+      kap |= (uint64_t)(bd & 1u) << a;
+      lam |= (uint64_t)(bd >> 1) << a;
+    }
+    const uint32_t sks = (sksj + (uint32_t)__popcll(y & adlo) + 2u * (uint32_t)__popcll(y & adhi) +
+                          2u * par64(tU)) & 3u;
+    const uint32_t sv = par64(s & v);
+    // Z_2 form of Eq. (Q) on supp(v) and one extra variable e.
+    const uint32_t e = (uint32_t)__builtin_ctzll(~v);
+    const uint64_t eb = 1ull << e;
+    uint64_t nz = 0;
+#pragma unroll
+    for (int a = 0; a < NMAX; ++a) {
+      if ((uint32_t)a < n && ((v >> a) & 1ull)) {
+        const uint64_t odd = (kap >> a) & 1ull;
+        const uint64_t row = ((((rl64(KJl, (uint32_t)a) ^ Sacc[a]) & v) ^ (kap & (0ull - odd))) &
+                              ~(1ull << a)) | (odd << e);
+        Srow[(uint32_t)a * 64u + lane] = row;
+        nz |= (uint64_t)(row != 0ull) << a;
+      }
+    }
+    Srow[e * 64u + lane] = kap;
+    nz |= (uint64_t)(kap != 0ull) << e;
+    const uint64_t Rset = v | eb;
+    uint64_t lr = lam, li = lam | eb, rem = Rset;
+    uint32_t sr = 0, si = 0, nel = 0;
+    // Eliminate a pair (a, b) with S_ab = 1 at a time (Eq. (eq5)); pivots per lane.
+    while (nz != 0ull) {
+      const uint32_t a = (uint32_t)__builtin_ctzll(nz);
+      const uint64_t Sa = Srow[a * 64u + lane];
+      const uint32_t b = (uint32_t)__builtin_ctzll(Sa);
+      const uint64_t Sb = Srow[b * 64u + lane];
+      const uint64_t ab = (1ull << a) | (1ull << b);
+      const uint64_t m1 = Sa & ~ab, m2 = Sb & ~ab;
+      nz = 0;
+      for (uint64_t m = Rset; m; m &= m - 1ull) {
+        const uint32_t c = (uint32_t)__builtin_ctzll(m);
+        uint64_t x = Srow[c * 64u + lane];
+        x ^= (m2 & (0ull - ((m1 >> c) & 1ull))) ^ (m1 & (0ull - ((m2 >> c) & 1ull)));
+        x &= ~ab;
+        if (c == a || c == b) x = 0ull;
+        Srow[c * 64u + lane] = x;
+        nz |= (uint64_t)(x != 0ull) << c;
+      }
+      {
+        const uint64_t la = (lr >> a) & 1ull, lbb = (lr >> b) & 1ull;
+        sr ^= (uint32_t)(la & lbb);
+        lr ^= (m2 & (0ull - la)) ^ (m1 & (0ull - lbb)) ^ (m1 & m2);
+        lr &= ~ab;
+      }
+      {
+        const uint64_t la = (li >> a) & 1ull, lbb = (li >> b) & 1ull;
+        si ^= (uint32_t)(la & lbb);
+        li ^= (m2 & (0ull - la)) ^ (m1 & (0ull - lbb)) ^ (m1 & m2);
+        li &= ~ab;
+      }
+      rem &= ~ab;
+      ++nel;
+    }
+    __builtin_amdgcn_wave_barrier();
+    const int rr = __popcll(rem);
+    const bool re_nz = (lr & rem) == 0ull, im_nz = (li & rem) == 0ull;
+    // Re Z = (-1)^sr 2^{nel + r - 1}, Im Z likewise; both non-zero only with equal exponents.
+    if (l < L && (re_nz || im_nz)) {
+      const int ez0 = (int)nel + rr - 1;
+      uint32_t kz;
+      int ez;
+      if (re_nz && im_nz) {
+        kz = sr ? (si ? 5u : 3u) : (si ? 7u : 1u);
+        ez = 2 * ez0 + 1;
+      } else if (re_nz) {
+        kz = sr ? 4u : 0u;
+        ez = 2 * ez0;
+      } else {
+        kz = si ? 6u : 2u;
+        ez = 2 * ez0;
+      }
+      const uint32_t kin = (2u * sks + 4u * sv + kz) & 7u;
+      InnerRec rc;
+      rc.nonzero = 1u;
+      rc.k8 = (omega - kin) & 7u;  // <phi_A|omega phi> = omega conj(<phi|phi_A>)
+      rc.e2 = ez - (int)(n + (uint32_t)__popcll(v));
+      const double2 val = rec_value(rc, bb);
+      accr += val.x;
+      acci += val.y;
     }
   }
   if (bad && lane == 0u) atomicOr(err, 1u);
-  __syncthreads();
-  for (uint32_t l = tid; l < L; l += 256u) {
-    double re = 0.0, im = 0.0;
-    for (int w = 0; w < kWaves; ++w) {
-      re += acc[(size_t)w * L + l].x;
-      im += acc[(size_t)w * L + l].y;
-    }
-    partial[(uint64_t)blockIdx.x * L + l] = make_double2(re, im);
-  }
+  if (l < L) partial[(uint64_t)blockIdx.x * L + l] = make_double2(accr, acci);
 }
 
 __global__ __launch_bounds__(256) void k_inner_reduce(const double2* __restrict__ partial,
@@ -273,26 +377,42 @@ __global__ __launch_bounds__(256) void k_eta_sum(const double* __restrict__ eta,
 
 }  // namespace
 
-size_t inner_partial_elems(const TermsView& T, uint32_t L, uint32_t* n_blocks) {
-  uint64_t waves = T.chi;
-  uint64_t blocks = (waves + kWaves - 1) / kWaves;
-  if (blocks > 2048) blocks = 2048;
-  *n_blocks = (uint32_t)blocks;
-  return (size_t)blocks * L;
+constexpr uint32_t kTermGroups = 512;  // waves per batch of 64 states, each over chi / 512 terms
+
+InnerPlan inner_plan(const TermsView& T, uint32_t L) {
+  InnerPlan P;
+  P.Lp = (L + 63u) / 64u * 64u;
+  P.n_batches = P.Lp / 64u;
+  P.n_groups = (uint32_t)std::min<uint64_t>(kTermGroups, T.chi);
+  P.partial_elems = (size_t)P.n_groups * L;
+  P.work_words = (size_t)T.chi * inner_rec_words(T.n) + (size_t)T.n * P.Lp + 2u * (size_t)P.Lp;
+  return P;
 }
 
 hipError_t launch_inner(const TermsView& T, const uint64_t* Aoff, const uint8_t* Adiag, uint32_t L,
-                        double2* partial, uint32_t n_blocks, double2* overlap, double* eta,
-                        double* eta_sum, uint32_t* err, hipStream_t st) {
-  const size_t sm = (size_t)kWaves * L * sizeof(double2);
-  if (sm > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_inner, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
-    if (e != hipSuccess) return e;
-  }
-  hipLaunchKernelGGL(k_inner, dim3(n_blocks), dim3(256), sm, st, T, Aoff, Adiag, L, partial, err);
+                        const InnerPlan& P, double2* partial, uint64_t* work, double2* overlap,
+                        double* eta, double* eta_sum, uint32_t* err, hipStream_t st) {
+  const uint32_t n = T.n;
+  uint64_t* rec = work;
+  uint64_t* at = rec + (size_t)T.chi * inner_rec_words(n);
+  uint64_t* planes = at + (size_t)n * P.Lp;
+  hipLaunchKernelGGL(k_inner_prep, dim3((uint32_t)((T.chi + kWaves - 1) / kWaves)), dim3(64 * kWaves), 0, st,
+                     T, rec);
+  hipLaunchKernelGGL(k_inner_atrans, dim3((P.Lp + 255u) / 256u), dim3(256), 0, st, Aoff, Adiag, n, L, P.Lp,
+                     at, planes);
+  const size_t sm = (size_t)(16u * 16u + (n + 1u) * 64u) * sizeof(uint64_t);
+  const dim3 grid(P.n_groups, P.n_batches);
+  if (n <= 16)
+    hipLaunchKernelGGL(k_inner_pairs<16>, grid, dim3(64), sm, st, T, rec, at, planes, L, P.Lp, partial, err);
+  else if (n <= 32)
+    hipLaunchKernelGGL(k_inner_pairs<32>, grid, dim3(64), sm, st, T, rec, at, planes, L, P.Lp, partial, err);
+  else if (n <= 48)
+    hipLaunchKernelGGL(k_inner_pairs<48>, grid, dim3(64), sm, st, T, rec, at, planes, L, P.Lp, partial, err);
+  else
+    hipLaunchKernelGGL(k_inner_pairs<64>, grid, dim3(64), sm, st, T, rec, at, planes, L, P.Lp, partial, err);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_inner_reduce, dim3((L + 255) / 256), dim3(256), 0, st, partial, n_blocks, L,
+  hipLaunchKernelGGL(k_inner_reduce, dim3((L + 255) / 256), dim3(256), 0, st, partial, P.n_groups, L,
                      T.n, overlap, eta);
   e = hipGetLastError();
   if (e != hipSuccess) return e;

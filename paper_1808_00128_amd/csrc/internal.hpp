@@ -210,11 +210,17 @@ hipError_t launch_amp_items(const AmpInst* insts_d, const AmpItem* items_d, uint
                             uint32_t* counter, bool fp32c, const uint64_t* prefix_d, uint32_t n_inst,
                             uint64_t total_x, hipStream_t st);
 
-// Inner products with equatorial states.
-size_t inner_partial_elems(const TermsView& T, uint32_t L, uint32_t* n_blocks);
+// Inner products with equatorial states: L states in batches of 64 (Lp =
+// L rounded up), partial sums per term group, and a device workspace of
+// work_words 8-byte words (per-term records and A rearranged by state).
+struct InnerPlan {
+  uint32_t Lp, n_batches, n_groups;
+  size_t partial_elems, work_words;
+};
+InnerPlan inner_plan(const TermsView& T, uint32_t L);
 hipError_t launch_inner(const TermsView& T, const uint64_t* Aoff, const uint8_t* Adiag, uint32_t L,
-                        double2* partial, uint32_t n_blocks, double2* overlap, double* eta,
-                        double* eta_sum, uint32_t* err, hipStream_t st);
+                        const InnerPlan& P, double2* partial, uint64_t* work, double2* overlap,
+                        double* eta, double* eta_sum, uint32_t* err, hipStream_t st);
 
 // Metropolis.
 hipError_t launch_metro_init(const TermsView& T, MetroView& Mv, hipStream_t st);

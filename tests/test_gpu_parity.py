@@ -415,11 +415,13 @@ def test_amplitudes_batch_uneven_config(B):
 # ---------------------------------------------------------------------------
 # Step (c): inner products and the norm estimate.
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("n", [1, 3, 8, 20, 40, 63])
+@pytest.mark.parametrize("n", [1, 3, 8, 16, 17, 20, 33, 40, 48, 49, 63, 64])
 def test_inner_single_term_values(B, n):
-    """chi = 1 (no slots): the overlap is the pair value <phi_A|phi> itself."""
+    """chi = 1 (no slots): the overlap is the pair value <phi_A|phi> itself.
+    At n = 64 a short circuit leaves v with a free index (|v| = 64 is
+    rejected, see the next test)."""
     rng = np.random.default_rng(900 + n)
-    circ = W.random_circuit(n, 25 * n + 10, [], rng)
+    circ = W.random_circuit(n, 25 * n + 10 if n < 64 else 60, [], rng)
     spec = dict(circuit=circ, chi=1, mode="exact", seed=0)
     say(f"inner single term n={n}")
     ctx = gpu_ctx(B, spec)
@@ -429,6 +431,32 @@ def test_inner_single_term_values(B, n):
     ref, eta_ref = T.inner(Aoff, Adiag)
     np.testing.assert_allclose(ov, ref, rtol=1e-14, atol=0)
     np.testing.assert_allclose(eta, eta_ref, rtol=1e-13, atol=0)
+
+
+def test_inner_rejects_full_v(B):
+    """n = 64 with every qubit in v: no free index for the Z_2 lift."""
+    n = 64
+    circ = W.from_list(n, [(W.OP_H, q, 0) for q in range(n)])
+    ctx = gpu_ctx(B, dict(circuit=circ, chi=1, mode="exact", seed=0))
+    Aoff, Adiag = W.random_equatorial(n, 3, np.random.default_rng(1))
+    with pytest.raises(B.ChsimError, match="EUNSUPPORTED"):
+        ctx.inner_products(Aoff, Adiag)
+
+
+def test_inner_products_state_batches(B):
+    """L = 130 states: two full batches of 64 and a ragged one, over several
+    term groups."""
+    rng = np.random.default_rng(45)
+    circ = W.random_circuit(27, 300, rng.uniform(0, 2 * np.pi, size=6), rng)
+    spec = dict(circuit=circ, chi=700, mode="sparsify", seed=12)
+    say("inner batches n=27 chi=700 L=130")
+    ctx = gpu_ctx(B, spec)
+    T = O.Terms(circ, 700, O.SPARSIFY, seed=12)
+    Aoff, Adiag = W.random_equatorial(27, 130, rng)
+    ov, eta, mean = ctx.inner_products(Aoff, Adiag)
+    ref, eta_ref = T.inner(Aoff, Adiag)
+    assert normwise(ov, ref) < TOL64
+    np.testing.assert_allclose(eta, eta_ref, rtol=1e-9, atol=1e-12 * eta_ref.max())
 
 
 def test_inner_products_small_sum(B):
