@@ -177,6 +177,7 @@ __global__ __launch_bounds__(64) void k_inner_pairs(TermsView Tv, const uint64_t
                                                     uint32_t Lp, double2* __restrict__ partial,
                                                     uint32_t* __restrict__ err) {
   extern __shared__ __align__(16) uint64_t lds_w[];
+  constexpr uint32_t kChunks = (NMAX + 3) / 4;
   const uint32_t n = Tv.n;
   const uint32_t nch = (n + 3u) / 4u;
   uint64_t* const gtab = lds_w;              // [nch][16] XORs of G's rows
@@ -219,30 +220,37 @@ __global__ __launch_bounds__(64) void k_inner_pairs(TermsView Tv, const uint64_t
 #pragma unroll
     for (int a = 0; a < NMAX; ++a) Sacc[a] = 0ull;
     uint64_t D = 0, sKA = 0, tU = 0;
+    uint64_t Anext = atl[0];
     for (uint32_t c = 0; c < n; ++c) {
       const uint64_t Gc = rl64(Gl, c);
-      const uint64_t Ac = atl[(uint64_t)c * Lp];
+      const uint64_t Ac = Anext;
+      if (c + 1u < n) Anext = atl[(uint64_t)(c + 1u) * Lp];  // next row in flight
       const uint64_t upc = (c == 63u) ? 0ull : (~0ull << (c + 1u));
       const uint64_t Uc = Ac & upc;
-      // Z_c = A_c G and W_c = U_c G, chunks from the top: above c the two
-      // nibbles agree, the chunk holding c differs, below it U_c is zero.
-      uint64_t Z = 0, W = 0;
-      for (uint32_t k = nch; k-- > 0;) {
-        const uint32_t lo = 4u * k;
-        const uint64_t tz = gtab[k * 16u + (uint32_t)((Ac >> lo) & 15ull)];
-        Z ^= tz;
-        if (lo > c) {
-          W ^= tz;
-        } else if (lo + 4u > c) {
-          W ^= gtab[k * 16u + (uint32_t)((Uc >> lo) & 15ull)];
-        }
+      // Z_c = A_c G and W_c = U_c G from the tables: every chunk's lookup is
+      // issued at once; above the chunk holding c the nibbles of A_c and U_c
+      // agree, that chunk takes a lookup of its own, below it U_c is zero.
+      const uint32_t kc = c >> 2;
+      uint64_t tz[kChunks];
+#pragma unroll
+      for (uint32_t k = 0; k < kChunks; ++k)
+        tz[k] = k < nch ? gtab[k * 16u + (uint32_t)((Ac >> (4u * k)) & 15ull)] : 0ull;
+      uint64_t W = gtab[kc * 16u + (uint32_t)((Uc >> (4u * kc)) & 15ull)];
+      uint64_t Z = 0;
+#pragma unroll
+      for (uint32_t k = 0; k < kChunks; ++k) {
+        Z ^= tz[k];
+        W ^= tz[k] & (0ull - (uint64_t)(k > kc));
       }
       D ^= Gc & W;
       sKA ^= Gc & (0ull - (uint64_t)par64(Ac & y));
       if ((y >> c) & 1ull) tU ^= Uc & y;
+      // K_A rows on supp(v): S_a ^= Z_c & v for the a in supp(v) with G_ca = 1
+      // (a uniform test per row: only those rows do any vector work).
       const uint64_t Zv = Z & v, Gcv = Gc & v;
 #pragma unroll
-      for (int a = 0; a < NMAX; ++a) Sacc[a] ^= Zv & (0ull - ((Gcv >> a) & 1ull));
+      for (int a = 0; a < NMAX; ++a)
+        if ((Gcv >> a) & 1ull) Sacc[a] ^= Zv;
     }
     // B on supp(v): Bd_a = K_aa + 2 (s_a + (sK)_a) with K = K_J + K_A.
     const uint64_t skl = skj ^ sKA;
@@ -263,7 +271,6 @@ __global__ __launch_bounds__(64) void k_inner_pairs(TermsView Tv, const uint64_t
     // Z_2 form of Eq. (Q) on supp(v) and one extra variable e.
     const uint32_t e = (uint32_t)__builtin_ctzll(~v);
     const uint64_t eb = 1ull << e;
-    uint64_t nz = 0;
 #pragma unroll
     for (int a = 0; a < NMAX; ++a) {
       if ((uint32_t)a < n && ((v >> a) & 1ull)) {
@@ -271,50 +278,58 @@ __global__ __launch_bounds__(64) void k_inner_pairs(TermsView Tv, const uint64_t
         const uint64_t row = ((((rl64(KJl, (uint32_t)a) ^ Sacc[a]) & v) ^ (kap & (0ull - odd))) &
                               ~(1ull << a)) | (odd << e);
         Srow[(uint32_t)a * 64u + lane] = row;
-        nz |= (uint64_t)(row != 0ull) << a;
       }
     }
     Srow[e * 64u + lane] = kap;
-    nz |= (uint64_t)(kap != 0ull) << e;
     const uint64_t Rset = v | eb;
-    uint64_t lr = lam, li = lam | eb, rem = Rset;
+    uint64_t lr = lam, li = lam | eb, rem = Rset, iso = 0;
     uint32_t sr = 0, si = 0, nel = 0;
-    // Eliminate a pair (a, b) with S_ab = 1 at a time (Eq. (eq5)); pivots per lane.
-    while (nz != 0ull) {
-      const uint32_t a = (uint32_t)__builtin_ctzll(nz);
-      const uint64_t Sa = Srow[a * 64u + lane];
-      const uint32_t b = (uint32_t)__builtin_ctzll(Sa);
-      const uint64_t Sb = Srow[b * 64u + lane];
-      const uint64_t ab = (1ull << a) | (1ull << b);
-      const uint64_t m1 = Sa & ~ab, m2 = Sb & ~ab;
-      nz = 0;
-      for (uint64_t m = Rset; m; m &= m - 1ull) {
-        const uint32_t c = (uint32_t)__builtin_ctzll(m);
-        uint64_t x = Srow[c * 64u + lane];
-        x ^= (m2 & (0ull - ((m1 >> c) & 1ull))) ^ (m1 & (0ull - ((m2 >> c) & 1ull)));
-        x &= ~ab;
-        if (c == a || c == b) x = 0ull;
-        Srow[c * 64u + lane] = x;
-        nz |= (uint64_t)(x != 0ull) << c;
+    // Eliminate a pair (a, b) with S_ab = 1 at a time (Eq. (eq5)); pivots per
+    // lane.  A variable whose row is zero has no neighbour and never gains
+    // one (S stays symmetric and an update only joins neighbours of the
+    // pair), and its linear coefficients no longer change: it is set aside.
+    for (;;) {
+      uint32_t a = 0;
+      uint64_t Sa = 0;
+      while (rem != 0ull) {
+        a = (uint32_t)__builtin_ctzll(rem);
+        Sa = Srow[a * 64u + lane];
+        if (Sa != 0ull) break;
+        iso |= 1ull << a;
+        rem &= ~(1ull << a);
       }
-      {
-        const uint64_t la = (lr >> a) & 1ull, lbb = (lr >> b) & 1ull;
-        sr ^= (uint32_t)(la & lbb);
-        lr ^= (m2 & (0ull - la)) ^ (m1 & (0ull - lbb)) ^ (m1 & m2);
-        lr &= ~ab;
+      if (!__builtin_amdgcn_ballot_w64(rem != 0ull)) break;
+      if (rem != 0ull) {
+        const uint32_t b = (uint32_t)__builtin_ctzll(Sa);
+        const uint64_t Sb = Srow[b * 64u + lane];
+        const uint64_t ab = (1ull << a) | (1ull << b);
+        const uint64_t m1 = Sa & ~ab, m2 = Sb & ~ab;
+        for (uint64_t m = Rset; m; m &= m - 1ull) {
+          const uint32_t c = (uint32_t)__builtin_ctzll(m);
+          const uint64_t t = (((m1 >> c) & 1ull) ? m2 : 0ull) ^ (((m2 >> c) & 1ull) ? m1 : 0ull);
+          Srow[c * 64u + lane] = (Srow[c * 64u + lane] ^ t) & ~ab;
+        }
+        Srow[a * 64u + lane] = 0ull;
+        Srow[b * 64u + lane] = 0ull;
+        {
+          const uint64_t la = (lr >> a) & 1ull, lbb = (lr >> b) & 1ull;
+          sr ^= (uint32_t)(la & lbb);
+          lr ^= (m2 & (0ull - la)) ^ (m1 & (0ull - lbb)) ^ (m1 & m2);
+          lr &= ~ab;
+        }
+        {
+          const uint64_t la = (li >> a) & 1ull, lbb = (li >> b) & 1ull;
+          si ^= (uint32_t)(la & lbb);
+          li ^= (m2 & (0ull - la)) ^ (m1 & (0ull - lbb)) ^ (m1 & m2);
+          li &= ~ab;
+        }
+        rem &= ~ab;
+        ++nel;
       }
-      {
-        const uint64_t la = (li >> a) & 1ull, lbb = (li >> b) & 1ull;
-        si ^= (uint32_t)(la & lbb);
-        li ^= (m2 & (0ull - la)) ^ (m1 & (0ull - lbb)) ^ (m1 & m2);
-        li &= ~ab;
-      }
-      rem &= ~ab;
-      ++nel;
     }
     __builtin_amdgcn_wave_barrier();
-    const int rr = __popcll(rem);
-    const bool re_nz = (lr & rem) == 0ull, im_nz = (li & rem) == 0ull;
+    const int rr = __popcll(iso);
+    const bool re_nz = (lr & iso) == 0ull, im_nz = (li & iso) == 0ull;
     // Re Z = (-1)^sr 2^{nel + r - 1}, Im Z likewise; both non-zero only with equal exponents.
     if (l < L && (re_nz || im_nz)) {
       const int ez0 = (int)nel + rr - 1;
@@ -402,14 +417,24 @@ hipError_t launch_inner(const TermsView& T, const uint64_t* Aoff, const uint8_t*
                      at, planes);
   const size_t sm = (size_t)(16u * 16u + (n + 1u) * 64u) * sizeof(uint64_t);
   const dim3 grid(P.n_groups, P.n_batches);
-  if (n <= 16)
-    hipLaunchKernelGGL(k_inner_pairs<16>, grid, dim3(64), sm, st, T, rec, at, planes, L, P.Lp, partial, err);
-  else if (n <= 32)
-    hipLaunchKernelGGL(k_inner_pairs<32>, grid, dim3(64), sm, st, T, rec, at, planes, L, P.Lp, partial, err);
-  else if (n <= 48)
-    hipLaunchKernelGGL(k_inner_pairs<48>, grid, dim3(64), sm, st, T, rec, at, planes, L, P.Lp, partial, err);
-  else
-    hipLaunchKernelGGL(k_inner_pairs<64>, grid, dim3(64), sm, st, T, rec, at, planes, L, P.Lp, partial, err);
+  switch ((n + 7u) / 8u) {
+#define CHSIM_INNER_CASE(k)                                                                          \
+  case k:                                                                                            \
+    hipLaunchKernelGGL(k_inner_pairs<8 * k>, grid, dim3(64), sm, st, T, rec, at, planes, L, P.Lp, partial, \
+                       err);                                                                         \
+    break;
+    CHSIM_INNER_CASE(1)
+    CHSIM_INNER_CASE(2)
+    CHSIM_INNER_CASE(3)
+    CHSIM_INNER_CASE(4)
+    CHSIM_INNER_CASE(5)
+    CHSIM_INNER_CASE(6)
+    CHSIM_INNER_CASE(7)
+    CHSIM_INNER_CASE(8)
+#undef CHSIM_INNER_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_inner_reduce, dim3((L + 255) / 256), dim3(256), 0, st, partial, P.n_groups, L,
