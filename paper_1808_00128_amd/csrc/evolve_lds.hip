@@ -57,6 +57,7 @@ __global__ __launch_bounds__(256) void k_evolve_lds(EvolveJob J, const DGate* __
   uint64_t* const RG = RF + (size_t)n * T;
   uint64_t* const RM = RG + (size_t)n * T;
   const uint32_t rpl = (n + LPT - 1) / LPT;
+  const uint32_t nfull = n / LPT, ntail = n % LPT;
   // This lane's rows p = li + j LPT: word j * 64 from these.
   uint64_t* const LF = RF + (size_t)li * T;
   uint64_t* const LG = RG + (size_t)li * T;
@@ -166,8 +167,7 @@ __global__ __launch_bounds__(256) void k_evolve_lds(EvolveJob J, const DGate* __
           dw = ph + (dp == 1u ? 1u : (dp == 3u ? 7u : 0u));
         }
         uint32_t fbits = 0u;  // F_{p,q} after V_C for the lane's rows, if a
-        for (uint32_t j = 0; j < rpl; ++j) {
-          if (li + j * LPT >= n) break;
+        auto row = [&](uint32_t j) {
           uint64_t F = LF[j * 64u], G = LG[j * 64u], M = LM[j * 64u];
           if (use0) {
             // R[CX_{q,i}], i in W: G_{.,q} ^= G_{.,i}; F_{.,i} ^= F_{.,q}; M_{.,q} ^= M_{.,i}.
@@ -194,7 +194,12 @@ __global__ __launch_bounds__(256) void k_evolve_lds(EvolveJob J, const DGate* __
           LF[j * 64u] = F;
           LG[j * 64u] = G;
           LM[j * 64u] = M;
-        }
+        };
+        // Rows j < n / LPT exist in every lane (no per-lane bound in the loop);
+        // row n / LPT only in lanes li < n % LPT.
+#pragma unroll 2
+        for (uint32_t j = 0; j < nfull; ++j) row(j);
+        if (li < ntail) row(nfull);
         // gamma -= 1 on the rows in fbits: low bit flips, high bit borrows.
         gw ^= fbits ^ ((fbits & ~gw) << 16);
         s = (y & ~qb) | ((uint64_t)cc << qh);
