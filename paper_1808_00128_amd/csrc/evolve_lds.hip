@@ -21,7 +21,6 @@
 namespace chsim {
 namespace {
 
-constexpr uint32_t kLdsChunk = 256;  // gates staged in LDS at a time (2 KiB)
 constexpr uint32_t kLdsWaves = 4;    // waves per workgroup
 
 // Value held by lane `src` of the caller's term (lane src T + tw).
@@ -48,12 +47,11 @@ __global__ __launch_bounds__(256) void k_evolve_lds(EvolveJob J, const DGate* __
   const uint64_t count = J.count_dev ? (uint64_t)*J.count_dev : J.count;
   if ((uint64_t)blockIdx.x * kTermsPerBlock >= count) return;  // whole block: no barrier skipped
   extern __shared__ __align__(16) uint64_t lds_words[];
-  uint2* sg = reinterpret_cast<uint2*>(lds_words);
   const uint32_t n = J.dst.n;
   const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
   const uint32_t tw = lane % T, li = lane / T;
   // Row p of matrix m of this lane's term: region[(m n + p) T + tw].
-  uint64_t* const RF = lds_words + kLdsChunk + (size_t)wave * 3u * n * T + tw;
+  uint64_t* const RF = lds_words + (size_t)wave * 3u * n * T + tw;
   uint64_t* const RG = RF + (size_t)n * T;
   uint64_t* const RM = RG + (size_t)n * T;
   const uint32_t rpl = (n + LPT - 1) / LPT;
@@ -105,137 +103,133 @@ __global__ __launch_bounds__(256) void k_evolve_lds(EvolveJob J, const DGate* __
   const uint32_t n_occ = J.n_occ;
   uint32_t next_b = n_occ ? (uint32_t)branch[(uint64_t)seq[0] * chb + ba] : 0u;
   uint32_t cur_b = 0u, occ = 1u;
-  for (uint32_t c0 = 0; c0 < n_gates; c0 += kLdsChunk) {
-    const uint32_t cn = min(kLdsChunk, n_gates - c0);
-    __syncthreads();
-    for (uint32_t t = threadIdx.x; t < cn; t += 256u) sg[t] = g2[c0 + t];
-    __syncthreads();
-    uint2 nxt = sg[0];
-    for (uint32_t i = 0; i < cn; ++i) {
-      const uint32_t w0 = uniform32(nxt.x), w1 = uniform32(nxt.y);
-      nxt = sg[i + 1 < cn ? i + 1 : i];
-      const uint32_t op = w0 & 0xffu, q = (w0 >> 8) & 0xffu;
-      const uint32_t cond = (w1 >> 16) & 0xffu;
-      if (cond & kSlotStart) {
-        cur_b = next_b;
-        if (occ < n_occ) next_b = (uint32_t)branch[(uint64_t)seq[occ] * chb + ba];
-        ++occ;
-      }
-      const bool on = !(cond & kCondApply) || cur_b == (w1 >> 24);
-      const uint32_t kq = q / LPT, lq = q % LPT;
-      if (op == OP_H) {
-        if (!on) continue;
-        // Hadamard on qubit q (the gate's p): Eqs. (H2), (H4), the t = u case,
-        // Prop. H with V_C applied to the lane's rows.
-        const uint64_t Fp = RF[q * T], Gp = RG[q * T], Mp = RM[q * T];
-        const uint32_t gp = gam_get(grp32<T>(gw, lq, tw), kq);
-        const uint64_t nv = ~v;
-        const uint64_t t = s ^ (Gp & v);
-        const uint64_t u = s ^ (Fp & nv) ^ (Mp & v);
-        const uint32_t alpha = par64(Gp & nv & s);
-        const uint32_t beta = par64(Mp & nv & s) ^ par64(Fp & v & (Mp ^ s));
-        const uint32_t delta = (gp + 2u * (alpha + beta)) & 3u;
-        if (t == u) {
-          // omega' = 2^{-1/2} (-1)^alpha (1 + i^delta), delta odd.
-          if (!(delta & 1u)) e = 1u;
-          w = (w + 4u * alpha + (delta == 1u ? 1u : 7u)) & 7u;
-          s = t;
-          continue;
-        }
-        const uint64_t d = t ^ u, V0 = d & nv, V1 = d & v;
-        const bool use0 = V0 != 0ull;
-        const uint32_t qh = (uint32_t)__builtin_ctzll(use0 ? V0 : V1);
-        const uint64_t qb = 1ull << qh;
-        const uint64_t W = (use0 ? V0 : V1) & ~qb;
-        const uint32_t tq = (uint32_t)((t >> qh) & 1ull);
-        const uint64_t y = tq ? (u ^ qb) : t;  // y and z differ only in bit qh; y_qh = t_qh
-        const uint32_t vq = (uint32_t)((v >> qh) & 1ull);
-        // H^{v_q}(|y_q> + i^delta |1 - y_q>) = 2^{1/2} e^{i pi dw/4} S^a H^b |c>; for
-        // y_q = 1 factor out i^delta and use |0> + i^{-delta} |1>.
-        const uint32_t dp = tq ? ((4u - delta) & 3u) : delta;
-        const uint32_t ph = (2u * delta * tq) & 7u;
-        uint32_t a, b, cc, dw;
-        if (!vq) {
-          b = 1u;
-          a = dp & 1u;
-          cc = dp >> 1;
-          dw = ph;
-        } else {
-          b = dp & 1u;
-          a = dp & 1u;
-          cc = (dp == 2u || dp == 1u) ? 1u : 0u;
-          dw = ph + (dp == 1u ? 1u : (dp == 3u ? 7u : 0u));
-        }
-        uint32_t fbits = 0u;  // F_{p,q} after V_C for the lane's rows, if a
-        auto row = [&](uint32_t j) {
-          uint64_t F = LF[j * 64u], G = LG[j * 64u], M = LM[j * 64u];
-          if (use0) {
-            // R[CX_{q,i}], i in W: G_{.,q} ^= G_{.,i}; F_{.,i} ^= F_{.,q}; M_{.,q} ^= M_{.,i}.
-            // R[CZ_{q,i}], i in V_1: M_{.,q} ^= F_{.,i}; M_{.,i} ^= F_{.,q}; gamma += 2 F_{.,q} F_{.,i}.
-            const uint64_t fq = (F >> qh) & 1ull;
-            G ^= (uint64_t)par64(G & W) << qh;
-            F ^= W & (0ull - fq);
-            const uint32_t pv1 = par64(F & V1);
-            M ^= ((uint64_t)(par64(M & W) ^ pv1) << qh) ^ (V1 & (0ull - fq));
-            gw ^= ((uint32_t)fq & pv1) << (16u + j);
-          } else {
-            // R[CX_{i,q}], i in W: G_{.,i} ^= G_{.,q}; F_{.,q} ^= F_{.,i}; M_{.,i} ^= M_{.,q}.
-            const uint64_t gq = (G >> qh) & 1ull, mq = (M >> qh) & 1ull;
-            G ^= W & (0ull - gq);
-            F ^= (uint64_t)par64(F & W) << qh;
-            M ^= W & (0ull - mq);
-          }
-          if (a) {
-            // R[S_q]: M_{.,q} ^= F_{.,q}; gamma -= F_{.,q}.
-            const uint64_t fq = (F >> qh) & 1ull;
-            M ^= fq << qh;
-            fbits |= (uint32_t)fq << j;
-          }
-          LF[j * 64u] = F;
-          LG[j * 64u] = G;
-          LM[j * 64u] = M;
-        };
-        // Rows j < n / LPT exist in every lane (no per-lane bound in the loop);
-        // row n / LPT only in lanes li < n % LPT.
-#pragma unroll 2
-        for (uint32_t j = 0; j < nfull; ++j) row(j);
-        if (li < ntail) row(nfull);
-        // gamma -= 1 on the rows in fbits: low bit flips, high bit borrows.
-        gw ^= fbits ^ ((fbits & ~gw) << 16);
-        s = (y & ~qb) | ((uint64_t)cc << qh);
-        v = (v & ~qb) | ((uint64_t)b << qh);
-        w = (w + 4u * alpha + dw) & 7u;
+  // Gates are two 32-bit words read on the scalar unit, the next one in
+  // flight while the current one is applied.
+  uint2 nxt = n_gates ? g2[0] : make_uint2(0u, 0u);
+  for (uint32_t i = 0; i < n_gates; ++i) {
+    const uint32_t w0 = uniform32(nxt.x), w1 = uniform32(nxt.y);
+    nxt = g2[i + 1 < n_gates ? i + 1 : i];
+    const uint32_t op = w0 & 0xffu, q = (w0 >> 8) & 0xffu;
+    const uint32_t cond = (w1 >> 16) & 0xffu;
+    if (cond & kSlotStart) {
+      cur_b = next_b;
+      if (occ < n_occ) next_b = (uint32_t)branch[(uint64_t)seq[occ] * chb + ba];
+      ++occ;
+    }
+    const bool on = !(cond & kCondApply) || cur_b == (w1 >> 24);
+    const uint32_t kq = q / LPT, lq = q % LPT;
+    if (op == OP_H) {
+      if (!on) continue;
+      // Hadamard on qubit q (the gate's p): Eqs. (H2), (H4), the t = u case,
+      // Prop. H with V_C applied to the lane's rows.
+      const uint64_t Fp = RF[q * T], Gp = RG[q * T], Mp = RM[q * T];
+      const uint32_t gp = gam_get(grp32<T>(gw, lq, tw), kq);
+      const uint64_t nv = ~v;
+      const uint64_t t = s ^ (Gp & v);
+      const uint64_t u = s ^ (Fp & nv) ^ (Mp & v);
+      const uint32_t alpha = par64(Gp & nv & s);
+      const uint32_t beta = par64(Mp & nv & s) ^ par64(Fp & v & (Mp ^ s));
+      const uint32_t delta = (gp + 2u * (alpha + beta)) & 3u;
+      if (t == u) {
+        // omega' = 2^{-1/2} (-1)^alpha (1 + i^delta), delta odd.
+        if (!(delta & 1u)) e = 1u;
+        w = (w + 4u * alpha + (delta == 1u ? 1u : 7u)) & 7u;
+        s = t;
         continue;
       }
-      const bool wq = on && li == lq;
-      if (op == OP_CX || op == OP_CZ) {
-        const uint32_t r = (w0 >> 16) & 0xffu;
-        const uint32_t kr = r / LPT, lr = r % LPT;
-        const bool wr = on && li == lr;
-        if (op == OP_CX) {
-          // gamma_q += gamma_r + 2 (M_q . F_r); G_r ^= G_q; F_q ^= F_r; M_q ^= M_r.
-          const uint32_t gr = gam_get(grp32<T>(gw, lr, tw), kr);
-          if (wq) {
-            const uint64_t Fr = RF[r * T], Mr = RM[r * T];
-            const uint64_t Fq = RF[q * T], Mq = RM[q * T];
-            RF[q * T] = Fq ^ Fr;
-            RM[q * T] = Mq ^ Mr;
-            gw = gam_add(gw, kq, gr + 2u * par64(Mq & Fr));
-          }
-          if (wr) RG[r * T] ^= RG[q * T];
-        } else {
-          // M_q ^= G_r, M_r ^= G_q.
-          if (wq) RM[q * T] ^= RG[r * T];
-          if (wr) RM[r * T] ^= RG[q * T];
-        }
-      } else if (wq) {
-        // S^pw on q: M_q ^= G_q pw times, gamma_q -= pw.
-        uint32_t pw = 1u;
-        if (op == OP_SLOT_SPOW) pw = ((w0 >> 16) >> (2u * cur_b)) & 3u;
-        else if (op == OP_SPOW) pw = w0 >> 24;
-        if (pw & 1u) RM[q * T] ^= RG[q * T];
-        gw = gam_add(gw, kq, (4u - pw) & 3u);
+      const uint64_t d = t ^ u, V0 = d & nv, V1 = d & v;
+      const bool use0 = V0 != 0ull;
+      const uint32_t qh = (uint32_t)__builtin_ctzll(use0 ? V0 : V1);
+      const uint64_t qb = 1ull << qh;
+      const uint64_t W = (use0 ? V0 : V1) & ~qb;
+      const uint32_t tq = (uint32_t)((t >> qh) & 1ull);
+      const uint64_t y = tq ? (u ^ qb) : t;  // y and z differ only in bit qh; y_qh = t_qh
+      const uint32_t vq = (uint32_t)((v >> qh) & 1ull);
+      // H^{v_q}(|y_q> + i^delta |1 - y_q>) = 2^{1/2} e^{i pi dw/4} S^a H^b |c>; for
+      // y_q = 1 factor out i^delta and use |0> + i^{-delta} |1>.
+      const uint32_t dp = tq ? ((4u - delta) & 3u) : delta;
+      const uint32_t ph = (2u * delta * tq) & 7u;
+      uint32_t a, b, cc, dw;
+      if (!vq) {
+        b = 1u;
+        a = dp & 1u;
+        cc = dp >> 1;
+        dw = ph;
+      } else {
+        b = dp & 1u;
+        a = dp & 1u;
+        cc = (dp == 2u || dp == 1u) ? 1u : 0u;
+        dw = ph + (dp == 1u ? 1u : (dp == 3u ? 7u : 0u));
       }
+      uint32_t fbits = 0u;  // F_{p,q} after V_C for the lane's rows, if a
+      auto row = [&](uint32_t j) {
+        uint64_t F = LF[j * 64u], G = LG[j * 64u], M = LM[j * 64u];
+        if (use0) {
+          // R[CX_{q,i}], i in W: G_{.,q} ^= G_{.,i}; F_{.,i} ^= F_{.,q}; M_{.,q} ^= M_{.,i}.
+          // R[CZ_{q,i}], i in V_1: M_{.,q} ^= F_{.,i}; M_{.,i} ^= F_{.,q}; gamma += 2 F_{.,q} F_{.,i}.
+          const uint64_t fq = (F >> qh) & 1ull;
+          G ^= (uint64_t)par64(G & W) << qh;
+          F ^= W & (0ull - fq);
+          const uint32_t pv1 = par64(F & V1);
+          M ^= ((uint64_t)(par64(M & W) ^ pv1) << qh) ^ (V1 & (0ull - fq));
+          gw ^= ((uint32_t)fq & pv1) << (16u + j);
+        } else {
+          // R[CX_{i,q}], i in W: G_{.,i} ^= G_{.,q}; F_{.,q} ^= F_{.,i}; M_{.,i} ^= M_{.,q}.
+          const uint64_t gq = (G >> qh) & 1ull, mq = (M >> qh) & 1ull;
+          G ^= W & (0ull - gq);
+          F ^= (uint64_t)par64(F & W) << qh;
+          M ^= W & (0ull - mq);
+        }
+        if (a) {
+          // R[S_q]: M_{.,q} ^= F_{.,q}; gamma -= F_{.,q}.
+          const uint64_t fq = (F >> qh) & 1ull;
+          M ^= fq << qh;
+          fbits |= (uint32_t)fq << j;
+        }
+        LF[j * 64u] = F;
+        LG[j * 64u] = G;
+        LM[j * 64u] = M;
+      };
+      // Rows j < n / LPT exist in every lane (no per-lane bound in the loop);
+      // row n / LPT only in lanes li < n % LPT.
+#pragma unroll 2
+      for (uint32_t j = 0; j < nfull; ++j) row(j);
+      if (li < ntail) row(nfull);
+      // gamma -= 1 on the rows in fbits: low bit flips, high bit borrows.
+      gw ^= fbits ^ ((fbits & ~gw) << 16);
+      s = (y & ~qb) | ((uint64_t)cc << qh);
+      v = (v & ~qb) | ((uint64_t)b << qh);
+      w = (w + 4u * alpha + dw) & 7u;
+      continue;
+    }
+    const bool wq = on && li == lq;
+    if (op == OP_CX || op == OP_CZ) {
+      const uint32_t r = (w0 >> 16) & 0xffu;
+      const uint32_t kr = r / LPT, lr = r % LPT;
+      const bool wr = on && li == lr;
+      if (op == OP_CX) {
+        // gamma_q += gamma_r + 2 (M_q . F_r); G_r ^= G_q; F_q ^= F_r; M_q ^= M_r.
+        const uint32_t gr = gam_get(grp32<T>(gw, lr, tw), kr);
+        if (wq) {
+          const uint64_t Fr = RF[r * T], Mr = RM[r * T];
+          const uint64_t Fq = RF[q * T], Mq = RM[q * T];
+          RF[q * T] = Fq ^ Fr;
+          RM[q * T] = Mq ^ Mr;
+          gw = gam_add(gw, kq, gr + 2u * par64(Mq & Fr));
+        }
+        if (wr) RG[r * T] ^= RG[q * T];
+      } else {
+        // M_q ^= G_r, M_r ^= G_q.
+        if (wq) RM[q * T] ^= RG[r * T];
+        if (wr) RM[r * T] ^= RG[q * T];
+      }
+    } else if (wq) {
+      // S^pw on q: M_q ^= G_q pw times, gamma_q -= pw.
+      uint32_t pw = 1u;
+      if (op == OP_SLOT_SPOW) pw = ((w0 >> 16) >> (2u * cur_b)) & 3u;
+      else if (op == OP_SPOW) pw = w0 >> 24;
+      if (pw & 1u) RM[q * T] ^= RG[q * T];
+      gw = gam_add(gw, kq, (4u - pw) & 3u);
     }
   }
   if (live) {
@@ -265,7 +259,7 @@ hipError_t launch_lds_t(const EvolveJob& J, const DGate* gates, uint32_t n_gates
   constexpr uint32_t kTermsPerBlock = kLdsWaves * T;
   const uint32_t blocks = (uint32_t)((J.count + kTermsPerBlock - 1) / kTermsPerBlock);
   if (blocks == 0) return hipSuccess;
-  const size_t smem = (size_t)kLdsChunk * sizeof(uint2) + (size_t)kLdsWaves * 3u * J.dst.n * T * sizeof(uint64_t);
+  const size_t smem = (size_t)kLdsWaves * 3u * J.dst.n * T * sizeof(uint64_t);
   static bool attr_set[2] = {false, false};
   const void* fn = from_zero ? reinterpret_cast<const void*>(&k_evolve_lds<LPT, true>)
                              : reinterpret_cast<const void*>(&k_evolve_lds<LPT, false>);
