@@ -399,19 +399,16 @@ namespace {
 // ---- shared-prefix evolution: plan ----------------------------------------
 // Evolution-kernel cost per gate, measured on MI355X at n = 50: the latency
 // of one gate for a lone wave, and the time per gate for 65536 items at full
-// occupancy, in microseconds, by kind (H, CX, CZ, S-type); `cap` is how many
-// items the chip holds at once at n = 50 (0: not bounded below 65536), so a
-// launch of slightly more items than that takes a second, nearly empty round.
+// occupancy, in microseconds, by kind (H, CX, CZ, S-type).
 struct GateCost {
   double lat[4], thr[4];
-  double cap;
 };
-constexpr GateCost kCostReg8 = {{0.87, 0.76, 0.67, 0.46}, {4.23, 2.52, 2.21, 1.57}, 0};
-constexpr GateCost kCostReg16 = {{0.70, 0.55, 0.50, 0.40}, {4.10, 2.70, 2.40, 1.80}, 0};
-constexpr GateCost kCostWave = {{0.46, 0.38, 0.35, 0.31}, {10.3, 6.82, 5.82, 5.08}, 0};
-constexpr GateCost kCostLds4 = {{2.3, 0.39, 0.31, 0.30}, {6.30, 0.79, 0.61, 0.63}, 0};
-constexpr GateCost kCostLds8 = {{1.5, 0.39, 0.30, 0.31}, {5.30, 0.95, 0.72, 0.74}, 0};
-constexpr GateCost kCostLds16 = {{1.05, 0.38, 0.30, 0.29}, {6.10, 1.38, 1.07, 1.11}, 0};
+constexpr GateCost kCostReg8 = {{0.87, 0.76, 0.67, 0.46}, {4.23, 2.52, 2.21, 1.57}};
+constexpr GateCost kCostReg16 = {{0.70, 0.55, 0.50, 0.40}, {4.10, 2.70, 2.40, 1.80}};
+constexpr GateCost kCostWave = {{0.45, 0.39, 0.35, 0.31}, {10.3, 6.77, 5.79, 5.05}};
+constexpr GateCost kCostLds4 = {{2.39, 0.40, 0.30, 0.30}, {5.27, 0.81, 0.63, 0.64}};
+constexpr GateCost kCostLds8 = {{1.51, 0.39, 0.30, 0.29}, {4.71, 0.95, 0.77, 0.79}};
+constexpr GateCost kCostLds16 = {{1.08, 0.39, 0.30, 0.29}, {5.89, 1.44, 1.21, 1.25}};
 constexpr double kLevelCostUs = 45.0;  // prefix-id kernels and a launch per level
 
 // Cost table of the mapping a span would run with (the whole-wave mapping
@@ -427,16 +424,21 @@ int gate_kind(const DGate& g) {
 }
 
 // Estimated time of `items` work items through gates with `cnt[kind]` gates
-// of each kind; the row count scales the per-item throughput term and the
-// capacity (rows held on chip), and items beyond the capacity are charged
-// whole rounds.
-double span_us(const GateCost& c, const double cnt[4], double items, double row_scale) {
-  if (c.cap > 0) {
-    const double cap = c.cap / row_scale;
-    if (items > cap) items = std::ceil(items / cap) * cap;
+// of each kind; the row count scales the per-item throughput term.  A
+// mapping that holds at most `cap` items on the chip at once runs whole
+// rounds of cap items at full throughput and a last partial round, which is
+// charged like a launch of that many items alone (latency-bound when small).
+double span_us(const GateCost& c, const double cnt[4], double items, double row_scale, double cap) {
+  double full = 0.0, rest = items;
+  if (cap > 0 && items > cap) {
+    full = std::floor(items / cap) * cap;
+    rest = items - full;
   }
   double t = 0.0;
-  for (int k = 0; k < 4; ++k) t += cnt[k] * std::max(c.lat[k], items * c.thr[k] * row_scale / 65536.0);
+  for (int k = 0; k < 4; ++k) {
+    const double per = c.thr[k] * row_scale / 65536.0;
+    t += cnt[k] * (full * per + (rest > 0 ? std::max(c.lat[k], rest * per) : 0.0));
+  }
   return t;
 }
 
@@ -531,13 +533,14 @@ void plan_prefix(Instance& I, const std::vector<DGate>& dg, EvolveShape shape) {
   const std::array<double, 4> Ct = Cw[dg.size()];
   const double chi = (double)I.chi;
   const double rows = (double)I.n / 50.0;  // the table was measured at n = 50
+  const double cap = (double)evolve_capacity(shape, I.n);
   const std::vector<double> D = estimate_distinct(I, occ);
   const bool force = I.prefix_mode == 2;
   auto seg = [&](size_t i, size_t j, double items, int* lanes) {
     double cnt[4];
     for (int k = 0; k < 4; ++k) cnt[k] = (j <= m ? C[j][k] : Ct[k]) - C[i][k];
-    const double tp = span_us(cost_of(shape), cnt, items, rows);
-    const double tw = span_us(kCostWave, cnt, items, rows);
+    const double tp = span_us(cost_of(shape), cnt, items, rows, cap);
+    const double tw = span_us(kCostWave, cnt, items, rows, 0.0);
     if (lanes) *lanes = tw < tp ? 64 : 0;
     return std::min(tp, tw);
   };

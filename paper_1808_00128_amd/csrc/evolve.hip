@@ -84,6 +84,10 @@ EvolveShape evolve_default_shape(uint32_t n) {
   return s;
 }
 
+uint64_t evolve_capacity(EvolveShape s, uint32_t n) {
+  return s.lds ? evolve_lds_capacity(s.lanes, n) : 0u;
+}
+
 // Instantiated shapes: lanes in {4, 8, 16, 32, 64} with rows = ceil(n / lanes)
 // and lanes * rows <= 64; rows in LDS: lanes in {4, 8, 16} (gamma of a lane's
 // rows packed in 16 bits).

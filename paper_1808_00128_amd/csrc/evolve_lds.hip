@@ -277,6 +277,16 @@ hipError_t launch_lds_t(const EvolveJob& J, const DGate* gates, uint32_t n_gates
 
 }  // namespace
 
+uint64_t evolve_lds_capacity(int lanes, uint32_t n) {
+  int dev = 0, cus = 0;
+  hipGetDevice(&dev);
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
+  const uint64_t T = 64u / (uint32_t)lanes;
+  const uint64_t wg_bytes = (uint64_t)kLdsWaves * 3u * n * T * sizeof(uint64_t);
+  const uint64_t per_cu = wg_bytes ? (160u * 1024u) / wg_bytes : 0u;
+  return per_cu * kLdsWaves * T * (uint64_t)cus;
+}
+
 hipError_t launch_evolve_lds(int lanes, const EvolveJob& J, const DGate* gates, uint32_t n_gates,
                              bool from_zero, uint32_t* err, hipStream_t st) {
   switch (lanes) {

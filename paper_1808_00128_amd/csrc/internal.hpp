@@ -96,6 +96,8 @@ struct EvolveShape {
 };
 EvolveShape evolve_shape_for(uint32_t n, int lanes);
 EvolveShape evolve_default_shape(uint32_t n);
+// Items a mapping holds on the chip at once (0: not bounded by LDS).
+uint64_t evolve_capacity(EvolveShape s, uint32_t n);
 bool evolve_shape_supported(EvolveShape s, uint32_t n);
 // One evolution launch: count work items (or *count_dev of them, count being
 // the grid's bound); item i starts from |0^n> (from_zero) or from state
@@ -131,6 +133,7 @@ hipError_t launch_evolve_wide(int lanes, int rows, const EvolveJob& J, const DGa
                               uint32_t n_gates, bool from_zero, uint32_t* err, hipStream_t st);
 hipError_t launch_evolve_lds(int lanes, const EvolveJob& J, const DGate* gates, uint32_t n_gates,
                              bool from_zero, uint32_t* err, hipStream_t st);
+uint64_t evolve_lds_capacity(int lanes, uint32_t n);
 hipError_t launch_evolve(const TermsView& T, const DGate* gates, uint32_t n_gates,
                          const uint32_t* slot_seq, uint32_t n_occ, bool from_zero, uint32_t* err,
                          EvolveShape shape, hipStream_t st);
