@@ -10,9 +10,10 @@
 // buffer; accepting the move flips which buffer is current, so no term data
 // is rewritten at accept time.
 //
-// Kernels per step: (1) k_propose: lanes over terms, the tile's rows staged
-// in LDS, waves over chains: propose, write the proposal word, and reduce
-// sum_alpha b_alpha <y|phi_alpha> over the 256-term tile in FP64; (2) one
+// Kernels per step: (1) k_propose_gather (single flips: each chain gathers
+// its one row) or k_propose (flip masks: the tile's rows staged in LDS):
+// lanes over terms, waves over chains: propose, write the proposal word, and
+// reduce sum_alpha b_alpha <y|phi_alpha> over the 256-term tile in FP64; (2) one
 // workgroup per chain: add the tiles' partials in a fixed order,
 // r = |A(y)|^2 / |A(x)|^2 in FP64, accept iff U < r.
 #include "device_common.hpp"
@@ -257,16 +258,79 @@ __global__ __launch_bounds__(kPThreads) void k_propose(TermsView T, MetroView Mv
   }
 }
 
+// Single-flip proposal step without LDS: lanes over terms, waves over
+// chains; each chain gathers the words of its flipped row F_j, M_j, gamma_j
+// straight from the term store (rows that several chains flip are served by
+// L2), so no barrier separates loading from computing and only the touched
+// rows are read.  Each lane adds its terms of the 256-term tile in the same
+// order, and the lane sums are reduced with the same butterfly, as k_propose.
+constexpr uint32_t kGWaves = 4;
+constexpr uint32_t kGSub = kMetroTile / 64;  // 64-term sub-tiles per tile
+
+__global__ __launch_bounds__(64 * kGWaves) void k_propose_gather(TermsView T, MetroView Mv,
+                                                                 uint32_t step) {
+  const uint32_t lane = threadIdx.x & 63u, wave = uniform32(threadIdx.x >> 6);
+  const uint32_t n = T.n;
+  const uint64_t chi = T.chi;
+  const uint64_t tile0 = (uint64_t)blockIdx.x * kMetroTile;
+  TermAmpConst c[kGSub];
+  bool live[kGSub];
+#pragma unroll
+  for (uint32_t sb = 0; sb < kGSub; ++sb) {
+    const uint64_t a = tile0 + sb * 64u + lane;
+    live[sb] = a < chi;
+    c[sb] = TermAmpConst{};
+    if (live[sb]) c[sb] = load_const(T, a);
+  }
+  for (uint32_t ch = wave; ch < Mv.n_chain; ch += kGWaves) {
+    const uint64_t m = 1ull << (uniform32(Mv.jstream[(uint64_t)ch * Mv.n_steps + step]) % n);
+    const uint32_t cur = uniform32(Mv.parity[ch]);
+    double re = 0.0, im = 0.0;
+    {
+      uint64_t st[kGSub];
+#pragma unroll
+      for (uint32_t sb = 0; sb < kGSub; ++sb)
+        st[sb] = live[sb] ? Mv.state[cur][(uint64_t)ch * chi + tile0 + sb * 64u + lane] : 0ull;
+#pragma unroll
+      for (uint32_t sb = 0; sb < kGSub; ++sb) {
+        if (!live[sb]) continue;
+        const uint64_t a = tile0 + sb * 64u + lane;
+        uint64_t u = st[sb] & kUMask;
+        uint32_t mu = (uint32_t)(st[sb] >> 62);
+        const uint64_t off = (uint64_t)__builtin_ctzll(m) * chi + a;
+        u ^= T.F[off];
+        mu += (uint32_t)T.gamma[off] + 2u * par64(u & T.M[off]);
+        mu &= 3u;
+        Mv.state[cur ^ 1u][(uint64_t)ch * chi + a] = u | ((uint64_t)mu << 62);
+        const double2 val = term_value(c[sb], u, mu);
+        re += val.x;
+        im += val.y;
+      }
+    }
+    for (int o = 32; o >= 1; o >>= 1) {
+      re += __shfl_xor(re, o);
+      im += __shfl_xor(im, o);
+    }
+    if (lane == 0) Mv.partial[(uint64_t)ch * Mv.n_tiles + blockIdx.x] = make_double2(re, im);
+  }
+}
+
+// Single flips gather their one row per chain; flip masks (several rows per
+// chain) read the tile's rows once through LDS.
 template <bool kSingle>
 hipError_t launch_propose_t(const TermsView& T, MetroView& Mv, const uint64_t* mask, uint32_t step,
                             hipStream_t st) {
+  if (kSingle) {
+    hipLaunchKernelGGL(k_propose_gather, dim3(Mv.n_tiles), dim3(64 * kGWaves), 0, st, T, Mv, step);
+    return hipGetLastError();
+  }
   const size_t sm = (size_t)T.n * kSub * 17;
   if (sm > 64 * 1024) {
-    const hipError_t e = hipFuncSetAttribute((const void*)k_propose<kSingle>,
+    const hipError_t e = hipFuncSetAttribute((const void*)k_propose<false>,
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_propose<kSingle>, dim3(Mv.n_tiles), dim3(kPThreads), sm, st, T, Mv, mask, step);
+  hipLaunchKernelGGL(k_propose<false>, dim3(Mv.n_tiles), dim3(kPThreads), sm, st, T, Mv, mask, step);
   return hipGetLastError();
 }
 
