@@ -24,14 +24,22 @@
 // and 64-bit XORs per (term, x) instead of a loop over the set bits of x.
 // The table for u has s folded into chunk 0 and is masked with ~v, so the
 // zero test is u == 0; a wave skips the phase work of a term for which all
-// its lanes' amplitudes vanish.
+// its lanes' amplitudes vanish.  Only the n - |v| positions outside v matter
+// in u; when n - |v| <= 64 - n the prologue gathers them, in increasing
+// order, into bits n, n + 1, ... of the c_q rows (gathering is linear, so a
+// table of the combined rows yields both sums at once) and such a packed
+// term has one table: the zero test reads the bits above n, and x & w never
+// sees them.  Deep circuits leave |v| close to n, so most terms are packed
+// and take half the lookups.
 //
 // Work items (request, range of 8-term tiles, chunk of 512 bitstrings) are
 // pulled from a queue by a persistent grid, so one launch serves any mix of
-// instances.  Each lane sums its bitstrings' values over the item's terms
-// (FP32 with a two-sum compensation term, or FP64), the item writes one
-// partial per bitstring, and a second kernel adds the ranges in FP64 in a
-// fixed order.
+// instances.  Per tile, the terms' constants are staged in LDS beside the
+// tables, with the eight values a term can take (omega folded in), so a
+// lane's value is one more lookup.  Each lane sums its bitstrings' values
+// over the item's terms (FP32: plain within a tile, the tile sums with a
+// two-sum compensation term; or FP64), the item writes one partial per
+// bitstring, and a second kernel adds the ranges in FP64 in a fixed order.
 #include <algorithm>
 #include <vector>
 
@@ -49,6 +57,14 @@ constexpr int kXPL = 2;                   // bitstrings per lane
 constexpr uint32_t kXChunk = 256 * kXPL;  // bitstrings per work item
 static_assert(kTT * 2 * kMaxCh == 256, "one builder thread per (term, table, chunk)");
 
+// Bits of a at the set positions of m, packed in increasing order into the
+// low popcount(m) bits.
+__device__ __forceinline__ uint64_t gather_bits(uint64_t a, uint64_t m) {
+  uint64_t r = 0;
+  for (uint32_t k = 0; m != 0ull; ++k, m &= m - 1ull) r |= ((a >> __builtin_ctzll(m)) & 1ull) << k;
+  return r;
+}
+
 __device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
   s = a + b;
   const float bb = s - a;
@@ -58,18 +74,25 @@ __device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
 template <typename T>
 struct Acc;
 
-// FP32 with a running compensation term per component.
+// FP32: the terms of one 8-term tile are added plainly (term), and the tile
+// sum joins a running sum with a compensation term per component (flush).
 template <>
 struct Acc<float> {
   float sr = 0.f, er = 0.f, si = 0.f, ei = 0.f;
-  __device__ __forceinline__ void add(float r, float i) {
+  float br = 0.f, bi = 0.f;
+  __device__ __forceinline__ void term(float r, float i) {
+    br += r;
+    bi += i;
+  }
+  __device__ __forceinline__ void flush() {
     float s, e;
-    two_sum(sr, r, s, e);
+    two_sum(sr, br, s, e);
     sr = s;
     er += e;
-    two_sum(si, i, s, e);
+    two_sum(si, bi, s, e);
     si = s;
     ei += e;
+    br = bi = 0.f;
   }
   __device__ __forceinline__ double2 value() const {
     return make_double2((double)sr + (double)er, (double)si + (double)ei);
@@ -79,48 +102,68 @@ struct Acc<float> {
 template <>
 struct Acc<double> {
   double sr = 0.0, si = 0.0;
-  __device__ __forceinline__ void add(double r, double i) {
+  __device__ __forceinline__ void term(double r, double i) {
     sr += r;
     si += i;
   }
+  __device__ __forceinline__ void flush() {}
   __device__ __forceinline__ double2 value() const { return make_double2(sr, si); }
 };
 
-// Prologue: per term, the rows c_q of B (stored like F: c[q * chi + a]) and
-// the constants.  One thread per term; F rows of the 64-term tile are parked
-// in LDS, each lane reading only its own column.
-__global__ __launch_bounds__(64) void k_amp_prep(TermsView T, uint64_t* __restrict__ crow,
-                                                 AmpTerm* __restrict__ cst) {
+// Per-term constants of one tile, staged in LDS next to the tables: the gamma
+// low-bit plane, whether the term is packed, and the nine values a term can
+// add, ph[k] = b_alpha 2^{-|v|/2} e^{i pi (k + omega) / 4} for k = 0..7 and
+// ph[8] = 0, so that a lane picks its value with one lookup.
+template <typename T>
+struct TileTerm {
+  uint64_t glo;
+  uint32_t packed, pad;
+  T ph[9][2];
+};
+
+// Prologue: per term, the rows c_q of B (stored like F: c[q * chi + a]), for
+// a packed term with F_q gathered from the ~v positions above bit n, and the
+// constants.  Four threads per term, thread (quarter, lane) of a 256-thread
+// block taking rows q = quarter (mod 4) of term 64 block + lane; F rows of the
+// 64 terms are parked in LDS.
+constexpr uint32_t kPrepTerms = 64;
+__global__ __launch_bounds__(256) void k_amp_prep(TermsView T, uint64_t* __restrict__ crow,
+                                                  AmpTerm* __restrict__ cst) {
   extern __shared__ __align__(16) uint8_t smem[];
   uint64_t* Fs = reinterpret_cast<uint64_t*>(smem);  // [n][64]
-  const uint32_t lane = threadIdx.x;
+  const uint32_t lane = threadIdx.x % kPrepTerms, quarter = threadIdx.x / kPrepTerms;
   const uint64_t chi = T.chi;
-  const uint64_t a = (uint64_t)blockIdx.x * 64u + lane;
-  if (a >= chi) return;  // no barrier below: lanes only touch their own column
+  const uint64_t a = (uint64_t)blockIdx.x * kPrepTerms + lane;
+  const bool on = a < chi;
   const uint32_t n = T.n;
+  if (on)
+    for (uint32_t p = quarter; p < n; p += 4) Fs[p * kPrepTerms + lane] = T.F[(uint64_t)p * chi + a];
+  __syncthreads();
+  if (!on) return;
   const uint64_t xm = (n == 64) ? ~0ull : ((1ull << n) - 1ull);
-  for (uint32_t p = 0; p < n; ++p) Fs[p * 64u + lane] = T.F[(uint64_t)p * chi + a];
   const uint64_t v = T.v[a], s = T.s[a];
   const uint64_t vs = v & s;
-  uint64_t glo = 0, ghi = 0;
-  for (uint32_t p = 0; p < n; ++p) {
-    const uint32_t g = T.gamma[(uint64_t)p * chi + a];
-    glo |= (uint64_t)(g & 1u) << p;
-    ghi |= (uint64_t)((g >> 1) & 1u) << p;
-  }
-  for (uint32_t q = 0; q < n; ++q) {
+  const uint64_t nv = ~v & xm;
+  const uint32_t nfree = (uint32_t)__popcll(nv);
+  const bool packed = nfree <= 64u - n;  // n + nfree <= 64; nfree > 0 implies n < 64
+  for (uint32_t q = quarter; q < n; q += 4) {
     const uint64_t Mq = T.M[(uint64_t)q * chi + a];
+    const uint32_t ghi_q = (T.gamma[(uint64_t)q * chi + a] >> 1) & 1u;
     uint64_t col = 0;
-    for (uint32_t p = 0; p <= q; ++p) col |= (uint64_t)par64(Fs[p * 64u + lane] & Mq) << p;
-    col ^= (uint64_t)(((uint32_t)(ghi >> q) & 1u) ^ par64(Fs[q * 64u + lane] & vs)) << q;
+    for (uint32_t p = 0; p <= q; ++p) col |= (uint64_t)par64(Fs[p * kPrepTerms + lane] & Mq) << p;
+    col ^= (uint64_t)(ghi_q ^ par64(Fs[q * kPrepTerms + lane] & vs)) << q;
+    if (packed && nfree != 0u) col |= gather_bits(Fs[q * kPrepTerms + lane], nv) << n;
     crow[(uint64_t)q * chi + a] = col;
   }
+  if (quarter != 0) return;
+  uint64_t glo = 0;
+  for (uint32_t p = 0; p < n; ++p) glo |= (uint64_t)(T.gamma[(uint64_t)p * chi + a] & 1u) << p;
   AmpTerm c;
-  c.nv = ~v & xm;
-  c.snv = s & c.nv;
+  c.nv = nv;
+  c.snv = !packed ? (s & nv) : (nfree != 0u ? gather_bits(s, nv) << n : 0ull);
   c.glo = glo;
   c.w = T.omega[a];
-  c.pad = 0;
+  c.packed = packed ? 1u : 0u;
   const double2 b = T.b[a];
   const int vc = __popcll(v);
   const double h = 0.70710678118654752440;
@@ -134,24 +177,51 @@ __global__ __launch_bounds__(64) void k_amp_prep(TermsView T, uint64_t* __restri
 
 // Build the tables of terms base .. base + kTT - 1.  Thread (t, kind, c)
 // builds chunk c of term t's table `kind` (0: u from F with s folded into
-// chunk 0 and masked with ~v; 1: w from the c rows), 16 entries by the
+// chunk 0 and masked with ~v, not built for a packed term; 1: w from the c
+// rows, for a packed term with the gathered s folded into chunk 0), 16 entries by the
 // recurrence e[j] = e[j & (j - 1)] ^ row[ctz j].  Entry e of chunk c sits at
 // word c * 16 + (e ^ c): the 16 lanes writing one entry index of 16 chunks,
 // and the lanes reading 16 different entries of one chunk, hit distinct banks.
-__device__ __forceinline__ void build_tables(uint64_t* tab, const AmpInst& I, uint64_t base,
-                                             uint32_t nch, uint32_t tid) {
+template <typename T>
+__device__ __forceinline__ void build_tables(uint64_t* tab, TileTerm<T>* tt, const AmpInst& I,
+                                             uint64_t base, uint32_t nch, uint32_t tid) {
   const uint32_t t = tid >> 5, kind = (tid >> 4) & 1u, c = tid & 15u;
   const uint64_t chi = I.T.chi;
   const uint64_t a = base + t;
-  if (c >= nch || a >= chi) return;
+  if (a >= chi) return;
+  const AmpTerm& C = I.cst[a];
+  if (kind == 1 && c < 9) {
+    // Value k of the term: w0 (k even) or w1 (k odd) times i^(k >> 1), with
+    // k counted from omega; exact in T (a rounding, then a swap and signs).
+    T re = (T)0, im = (T)0;
+    if (c < 8) {
+      const uint32_t k = (c + C.w) & 7u;
+      re = (k & 1u) ? (T)C.w1r : (T)C.w0r;
+      im = (k & 1u) ? (T)C.w1i : (T)C.w0i;
+      const uint32_t m = k >> 1;
+      if (m & 1u) {
+        const T tmp = re;
+        re = im;
+        im = tmp;
+      }
+      if ((m ^ (m >> 1)) & 1u) re = -re;
+      if (m & 2u) im = -im;
+    }
+    tt[t].ph[c][0] = re;
+    tt[t].ph[c][1] = im;
+    if (c == 0) {
+      tt[t].glo = C.glo;
+      tt[t].packed = C.packed;
+    }
+  }
+  if (c >= nch) return;
   const uint32_t n = I.T.n;
   const uint64_t* rows = kind ? I.crow : I.T.F;
+  if (kind == 0 && C.packed) return;
   uint64_t r[4];
   uint64_t mask = ~0ull, e0 = 0;
-  if (kind == 0) {
-    mask = I.cst[a].nv;
-    e0 = (c == 0) ? I.cst[a].snv : 0ull;
-  }
+  if (kind == 0) mask = C.nv;
+  if (kind == 0 || C.packed) e0 = (c == 0) ? C.snv : 0ull;
 #pragma unroll
   for (int b = 0; b < 4; ++b) {
     const uint32_t p = 4u * c + (uint32_t)b;
@@ -167,10 +237,19 @@ __device__ __forceinline__ void build_tables(uint64_t* tab, const AmpInst& I, ui
 }
 
 // Terms of one tile against the lane's kXPL bitstrings.  off[j][c] is the
-// swizzled word offset of chunk c's entry for bitstring j.
+// swizzled word offset of chunk c's entry for bitstring j; hi masks the bits
+// above n, where a packed term keeps its zero test.
+template <typename T>
+__device__ __forceinline__ void add_term(const TileTerm<T>& K, uint64_t glo, uint64_t x, uint64_t w,
+                                         bool nz, Acc<T>& acc) {
+  const uint32_t k = (2u * (uint32_t)__popcll(x & glo) + 4u * (uint32_t)__popcll(x & w)) & 7u;
+  const uint32_t idx = nz ? k : 8u;
+  acc.term(K.ph[idx][0], K.ph[idx][1]);
+}
+
 template <typename T, int NCH>
-__device__ __forceinline__ void run_tile(const uint64_t* tab, const AmpTerm* __restrict__ cst,
-                                         uint64_t base, uint32_t tcount,
+__device__ __forceinline__ void run_tile(const uint64_t* tab, const TileTerm<T>* tt,
+                                         uint32_t tcount, uint64_t hi,
                                          const uint32_t (&off)[kXPL][kMaxCh],
                                          const uint64_t (&x)[kXPL], const bool (&live)[kXPL],
                                          Acc<T> (&acc)[kXPL]) {
@@ -179,36 +258,35 @@ __device__ __forceinline__ void run_tile(const uint64_t* tab, const AmpTerm* __r
     if ((uint32_t)t >= tcount) break;
     const uint64_t* tu = tab + (t * 2) * kTabWords;
     const uint64_t* tw = tu + kTabWords;
+    const TileTerm<T>& K = tt[t];
+    const uint64_t glo = uniform64(K.glo);
+    if (uniform32(K.packed)) {
 #pragma unroll
-    for (int j = 0; j < kXPL; ++j) {
-      uint64_t u = 0;
+      for (int j = 0; j < kXPL; ++j) {
+        uint64_t w = 0;
 #pragma unroll
-      for (int c = 0; c < NCH; ++c) u ^= tu[off[j][c]];
-      const bool nz = live[j] && u == 0ull;
-      if (__ballot(nz) == 0ull) continue;
-      uint64_t w = 0;
-#pragma unroll
-      for (int c = 0; c < NCH; ++c) w ^= tw[off[j][c]];
-      const AmpTerm& C = cst[base + (uint32_t)t];
-      const uint32_t k =
-          (C.w + 2u * (uint32_t)__popcll(x[j] & C.glo) + 4u * (uint32_t)__popcll(x[j] & w)) & 7u;
-      T re = (k & 1u) ? (T)C.w1r : (T)C.w0r;
-      T im = (k & 1u) ? (T)C.w1i : (T)C.w0i;
-      const uint32_t m = k >> 1;  // multiply by i^m
-      if (m & 1u) {
-        const T tmp = re;
-        re = im;
-        im = tmp;
+        for (int c = 0; c < NCH; ++c) w ^= tw[off[j][c]];
+        const bool nz = live[j] && (w & hi) == 0ull;
+        if (__ballot(nz) == 0ull) continue;
+        add_term<T>(K, glo, x[j], w, nz, acc[j]);
       }
-      if ((m ^ (m >> 1)) & 1u) re = -re;
-      if (m & 2u) im = -im;
-      if (!nz) {
-        re = (T)0;
-        im = (T)0;
+    } else {
+#pragma unroll
+      for (int j = 0; j < kXPL; ++j) {
+        uint64_t u = 0;
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) u ^= tu[off[j][c]];
+        const bool nz = live[j] && u == 0ull;
+        if (__ballot(nz) == 0ull) continue;
+        uint64_t w = 0;
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) w ^= tw[off[j][c]];
+        add_term<T>(K, glo, x[j], w, nz, acc[j]);
       }
-      acc[j].add(re, im);
     }
   }
+#pragma unroll
+  for (int j = 0; j < kXPL; ++j) acc[j].flush();
 }
 
 template <typename T>
@@ -216,6 +294,7 @@ __global__ __launch_bounds__(256) void k_amp(const AmpInst* __restrict__ insts,
                                              const AmpItem* __restrict__ items, uint32_t n_items,
                                              uint32_t* __restrict__ counter) {
   __shared__ __align__(16) uint64_t tab[kTT * 2 * kTabWords];  // 32 KiB
+  __shared__ __align__(16) TileTerm<T> tt[kTT];
   __shared__ uint32_t s_item;
   const uint32_t tid = threadIdx.x;
 
@@ -254,12 +333,12 @@ __global__ __launch_bounds__(256) void k_amp(const AmpInst* __restrict__ insts,
       const uint64_t base = tile * kTT;
       const uint32_t tcount = (uint32_t)std::min<uint64_t>((uint64_t)kTT, chi - base);
       __syncthreads();  // the previous tile's readers are done
-      build_tables(tab, I, base, nch, tid);
+      build_tables<T>(tab, tt, I, base, nch, tid);
       __syncthreads();
       switch (nch) {
 #define CHSIM_AMP_CASE(K)                                         \
   case K:                                                         \
-    run_tile<T, K>(tab, I.cst, base, tcount, off, x, live, acc); \
+    run_tile<T, K>(tab, tt, tcount, ~xmask, off, x, live, acc); \
     break;
         CHSIM_AMP_CASE(1) CHSIM_AMP_CASE(2) CHSIM_AMP_CASE(3) CHSIM_AMP_CASE(4)
         CHSIM_AMP_CASE(5) CHSIM_AMP_CASE(6) CHSIM_AMP_CASE(7) CHSIM_AMP_CASE(8)
@@ -280,36 +359,55 @@ __global__ __launch_bounds__(256) void k_amp(const AmpInst* __restrict__ insts,
 
 __global__ void k_reset_counter(uint32_t* counter) { *counter = 0u; }
 
-// out[i] = sum over tile ranges of partial[range][i], FP64, fixed order; one
-// thread per (request, bitstring) over all requests.
+// out[i] = sum over tile ranges of partial[range][i], FP64, in a fixed order:
+// a 256-thread block takes 16 bitstrings (over all requests) and 16 slices of
+// their ranges; a thread sums its slice in range order, and the slice sums
+// are added in slice order.
+constexpr uint32_t kRedX = 16, kRedSlices = 16;
 __global__ __launch_bounds__(256) void k_reduce_ranges(const AmpInst* __restrict__ insts,
                                                        const uint64_t* __restrict__ prefix,
                                                        uint32_t n_inst) {
-  const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= prefix[n_inst]) return;
-  uint32_t lo = 0, hi = n_inst;
-  while (hi - lo > 1) {
-    const uint32_t mid = (lo + hi) / 2;
-    if (prefix[mid] <= g) lo = mid;
-    else hi = mid;
-  }
-  const AmpInst& I = insts[lo];
-  const uint64_t i = g - prefix[lo];
+  __shared__ double2 part[kRedSlices][kRedX];
+  const uint32_t xl = threadIdx.x % kRedX, sl = threadIdx.x / kRedX;
+  const uint64_t g = (uint64_t)blockIdx.x * kRedX + xl;
+  const bool on = g < prefix[n_inst];
+  uint32_t lo = 0;
+  uint64_t i = 0;
   double r = 0.0, im = 0.0;
-  for (uint32_t t = 0; t < I.n_ranges; ++t) {
-    const double2 v = I.partial[(uint64_t)t * I.n_x + i];
-    r += v.x;
-    im += v.y;
+  if (on) {
+    uint32_t hi = n_inst;
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) / 2;
+      if (prefix[mid] <= g) lo = mid;
+      else hi = mid;
+    }
+    const AmpInst& I = insts[lo];
+    i = g - prefix[lo];
+    const uint32_t r0 = (uint32_t)((uint64_t)I.n_ranges * sl / kRedSlices);
+    const uint32_t r1 = (uint32_t)((uint64_t)I.n_ranges * (sl + 1) / kRedSlices);
+    for (uint32_t t = r0; t < r1; ++t) {
+      const double2 v = I.partial[(uint64_t)t * I.n_x + i];
+      r += v.x;
+      im += v.y;
+    }
   }
-  I.out[i] = make_double2(r, im);
+  part[sl][xl] = make_double2(r, im);
+  __syncthreads();
+  if (sl != 0 || !on) return;
+  double sr = 0.0, si = 0.0;
+  for (uint32_t k = 0; k < kRedSlices; ++k) {
+    sr += part[k][xl].x;
+    si += part[k][xl].y;
+  }
+  insts[lo].out[i] = make_double2(sr, si);
 }
 
 }  // namespace
 
 hipError_t launch_amp_prep(const TermsView& T, uint64_t* crow, AmpTerm* cst, hipStream_t st) {
-  const uint32_t blocks = (uint32_t)((T.chi + 63) / 64);
-  const size_t sm = (size_t)T.n * 64 * sizeof(uint64_t);
-  hipLaunchKernelGGL(k_amp_prep, dim3(blocks), dim3(64), sm, st, T, crow, cst);
+  const uint32_t blocks = (uint32_t)((T.chi + kPrepTerms - 1) / kPrepTerms);
+  const size_t sm = (size_t)T.n * kPrepTerms * sizeof(uint64_t);
+  hipLaunchKernelGGL(k_amp_prep, dim3(blocks), dim3(256), sm, st, T, crow, cst);
   return hipGetLastError();
 }
 
@@ -374,7 +472,7 @@ hipError_t launch_amp_items(const AmpInst* insts_d, const AmpItem* items_d, uint
   else
     hipLaunchKernelGGL(k_amp<double>, dim3(grid), dim3(256), 0, st, insts_d, items_d, n_items, counter);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  const uint32_t blocks = (uint32_t)((total_x + 255) / 256);
+  const uint32_t blocks = (uint32_t)((total_x + kRedX - 1) / kRedX);
   hipLaunchKernelGGL(k_reduce_ranges, dim3(blocks), dim3(256), 0, st, insts_d, prefix_d, n_inst);
   return hipGetLastError();
 }

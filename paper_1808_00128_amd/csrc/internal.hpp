@@ -168,11 +168,15 @@ hipError_t launch_sample(const TermsView& T, const uint64_t* alpha, const uint64
                          uint64_t* x_out, uint32_t count, hipStream_t st);
 
 // Amplitudes.  Per-term values the amplitude kernel reads, computed by a
-// prologue kernel from the term store: ~v masked to n bits, s & ~v, the
-// gamma low-bit plane, omega and b_alpha 2^{-|v|/2} (w0) and w0 e^{i pi/4} (w1).
+// prologue kernel from the term store: ~v masked to n bits, the value folded
+// into entry 0 of the first chunk table of the zero test (s & ~v, or, for a
+// packed term, s gathered from the ~v positions and shifted above bit n), the
+// gamma low-bit plane, omega, whether the term is packed (its zero test rides
+// in the high bits of the quadratic-form rows) and b_alpha 2^{-|v|/2} (w0)
+// and w0 e^{i pi/4} (w1).
 struct AmpTerm {
   uint64_t nv, snv, glo;
-  uint32_t w, pad;
+  uint32_t w, packed;
   double w0r, w0i, w1r, w1i;
 };
 static_assert(sizeof(AmpTerm) == 64, "AmpTerm is 64 bytes");

@@ -300,6 +300,53 @@ def test_amplitudes_n64_block_product(B):
     assert np.max(np.abs(a64 - ref)) < 1e-12
 
 
+def _support_circuit(n, k, extra_h, rng):
+    """H on k random qubits, then 10 n gates from {S, CX, CZ} with extra_h
+    (phase slot, H) pairs: |v| = k before the pairs, and each pair may raise it
+    depending on the slot's branch, so |v| varies across the terms."""
+    gates = [(W.OP_H, int(q), 0) for q in rng.permutation(n)[:k]]
+    body = W.random_clifford_gates(n, 10 * n, rng, ops=(W.OP_S, W.OP_CX, W.OP_CZ))
+    pos = set(rng.choice(len(body), size=extra_h, replace=False).tolist()) if extra_h else set()
+    for i, g in enumerate(body):
+        if i in pos:
+            q = int(rng.integers(n))
+            gates.append((W.OP_SLOT, q, 0, float(rng.uniform(0, 2 * np.pi))))
+            gates.append((W.OP_H, q, 0))
+        gates.append(g)
+    return W.from_list(n, gates)
+
+
+# A term's zero test packs into the quadratic-form rows when n - |v| <= 64 - n,
+# i.e. |v| >= 2n - 64; (n, k, extra_h, expected packed terms: "all", "none", "some").
+@pytest.mark.parametrize("n,k,extra_h,packed", [(40, 14, 4, "all"), (40, 8, 4, "none"),
+                                                (33, 0, 4, "all"), (33, 0, 1, "none"),
+                                                (63, 62, 2, "some"), (64, 64, 0, "all"),
+                                                (64, 63, 3, "none")])
+def test_amplitudes_support_sizes(B, n, k, extra_h, packed):
+    """Terms with |v| on both sides of the packing limit 2n - 64, alone and
+    mixed in one tile, against the oracle."""
+    rng = np.random.default_rng(n * 100 + k + extra_h)
+    circ = _support_circuit(n, k, extra_h, rng)
+    chi = 77
+    spec = dict(circuit=circ, chi=chi, mode="sparsify", seed=k)
+    T = O.Terms(circ, chi, O.SPARSIFY, seed=k)
+    vs = np.array([bin(T.term(i).export()["v"]).count("1") for i in range(chi)])
+    n_packed = int(np.sum(vs >= 2 * n - 64))
+    assert {"all": n_packed == chi, "none": n_packed == 0, "some": 0 < n_packed < chi}[packed], vs
+    say(f"amplitudes support n={n} k={k} extra_h={extra_h} packed={n_packed}/{chi}")
+    ctx = gpu_ctx(B, spec)
+    alpha = rng.integers(0, chi, size=300)
+    flips = W.random_bitstrings(n, 300, rng)
+    xs = np.array([T.term(int(a)).sample(int(f)) for a, f in zip(alpha, flips)], np.uint64)
+    xs[::5] = W.random_bitstrings(n, 300, rng)[::5]
+    ref = T.amplitudes(xs)
+    assert np.max(np.abs(ref)) > 0
+    a64 = ctx.amplitudes(xs)
+    a32 = ctx.amplitudes(xs, fp32c=True)
+    assert normwise(a64, ref) < TOL64
+    assert normwise(a32, ref) < TOL32
+
+
 @pytest.mark.slow
 def test_amplitudes_config_full_size_sampled(B):
     """n = 50, chi = 2^16, 4096 strings, the benchmark's launch configuration:
