@@ -39,6 +39,11 @@ __device__ __forceinline__ uint32_t gam_add(uint32_t gw, uint32_t j, uint32_t a)
   return gw ^ (a0 << j) ^ ((a1 ^ (lo & a0)) << (16u + j));
 }
 
+// All ones if bit b (< 32) of x is set, else zero.
+__device__ __forceinline__ uint32_t bit_mask(uint32_t x, uint32_t b) {
+  return (uint32_t)__builtin_amdgcn_sbfe((int)x, b, 1u);
+}
+
 template <int LPT, bool kFromZero>
 __global__ __launch_bounds__(256) void k_evolve_lds(EvolveJob J, const DGate* __restrict__ gates,
                                                     uint32_t n_gates, uint32_t* __restrict__ err) {
@@ -162,33 +167,54 @@ __global__ __launch_bounds__(256) void k_evolve_lds(EvolveJob J, const DGate* __
         dw = ph + (dp == 1u ? 1u : (dp == 3u ? 7u : 0u));
       }
       uint32_t fbits = 0u;  // F_{p,q} after V_C for the lane's rows, if a
+      // Rows are updated as 32-bit halves: qs, hq locate bit qh, a mask is
+      // all ones or zero by a sign-extending bit-field extract.
+      const uint32_t qs = qh & 31u;
+      const bool hq = qh >= 32u;
+      const uint32_t qbl = hq ? 0u : (1u << qs), qbh = hq ? (1u << qs) : 0u;
+      const uint32_t Wl = (uint32_t)W, Wh = (uint32_t)(W >> 32);
+      const uint32_t V1l = (uint32_t)V1, V1h = (uint32_t)(V1 >> 32);
       auto row = [&](uint32_t j) {
-        uint64_t F = LF[j * 64u], G = LG[j * 64u], M = LM[j * 64u];
+        const uint64_t F = LF[j * 64u], G = LG[j * 64u], M = LM[j * 64u];
+        uint32_t Fl = (uint32_t)F, Fh = (uint32_t)(F >> 32);
+        uint32_t Gl = (uint32_t)G, Gh = (uint32_t)(G >> 32);
+        uint32_t Ml = (uint32_t)M, Mh = (uint32_t)(M >> 32);
         if (use0) {
           // R[CX_{q,i}], i in W: G_{.,q} ^= G_{.,i}; F_{.,i} ^= F_{.,q}; M_{.,q} ^= M_{.,i}.
           // R[CZ_{q,i}], i in V_1: M_{.,q} ^= F_{.,i}; M_{.,i} ^= F_{.,q}; gamma += 2 F_{.,q} F_{.,i}.
-          const uint64_t fq = (F >> qh) & 1ull;
-          G ^= (uint64_t)par64(G & W) << qh;
-          F ^= W & (0ull - fq);
-          const uint32_t pv1 = par64(F & V1);
-          M ^= ((uint64_t)(par64(M & W) ^ pv1) << qh) ^ (V1 & (0ull - fq));
-          gw ^= ((uint32_t)fq & pv1) << (16u + j);
+          const uint32_t mf = bit_mask(hq ? Fh : Fl, qs);
+          const uint32_t mg = bit_mask((uint32_t)__popc(Gl & Wl) + (uint32_t)__popc(Gh & Wh), 0u);
+          Gl ^= qbl & mg;
+          Gh ^= qbh & mg;
+          Fl ^= Wl & mf;
+          Fh ^= Wh & mf;
+          const uint32_t c = (uint32_t)__popc(Fl & V1l) + (uint32_t)__popc(Fh & V1h);
+          const uint32_t mm = bit_mask(c + (uint32_t)__popc(Ml & Wl) + (uint32_t)__popc(Mh & Wh), 0u);
+          Ml ^= (qbl & mm) ^ (V1l & mf);
+          Mh ^= (qbh & mm) ^ (V1h & mf);
+          gw ^= (mf & c & 1u) << (16u + j);
         } else {
           // R[CX_{i,q}], i in W: G_{.,i} ^= G_{.,q}; F_{.,q} ^= F_{.,i}; M_{.,i} ^= M_{.,q}.
-          const uint64_t gq = (G >> qh) & 1ull, mq = (M >> qh) & 1ull;
-          G ^= W & (0ull - gq);
-          F ^= (uint64_t)par64(F & W) << qh;
-          M ^= W & (0ull - mq);
+          const uint32_t mg = bit_mask(hq ? Gh : Gl, qs), mm = bit_mask(hq ? Mh : Ml, qs);
+          const uint32_t mf = bit_mask((uint32_t)__popc(Fl & Wl) + (uint32_t)__popc(Fh & Wh), 0u);
+          Gl ^= Wl & mg;
+          Gh ^= Wh & mg;
+          Fl ^= qbl & mf;
+          Fh ^= qbh & mf;
+          Ml ^= Wl & mm;
+          Mh ^= Wh & mm;
         }
         if (a) {
           // R[S_q]: M_{.,q} ^= F_{.,q}; gamma -= F_{.,q}.
-          const uint64_t fq = (F >> qh) & 1ull;
-          M ^= fq << qh;
-          fbits |= (uint32_t)fq << j;
+          const uint32_t fb = ((hq ? Fh : Fl) >> qs) & 1u;
+          const uint32_t mfb = 0u - fb;
+          Ml ^= qbl & mfb;
+          Mh ^= qbh & mfb;
+          fbits |= fb << j;
         }
-        LF[j * 64u] = F;
-        LG[j * 64u] = G;
-        LM[j * 64u] = M;
+        LF[j * 64u] = ((uint64_t)Fh << 32) | Fl;
+        LG[j * 64u] = ((uint64_t)Gh << 32) | Gl;
+        LM[j * 64u] = ((uint64_t)Mh << 32) | Ml;
       };
       // Rows j < n / LPT exist in every lane (no per-lane bound in the loop);
       // row n / LPT only in lanes li < n % LPT.
