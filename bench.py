@@ -402,6 +402,10 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 1 GiB device copy first (outside the timed region), so that "
                          "hardware byte counters can be scaled against a kernel of known traffic")
+    ap.add_argument("--evolve-lanes", type=lambda v: int(v, 0), default=-1,
+                    help="evolution mapping: -1 autotunes during warmup (default); otherwise a lanes "
+                         "value (e.g. 0x108 = 8 lanes per term, rows in LDS), so that counter runs "
+                         "repeat the launches of a timed run")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is design-only",
@@ -428,7 +432,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     ctx = B.Context([cfg])
-    ctx.set_evolve_lanes(-1)  # autotune the evolution mapping during warmup
+    ctx.set_evolve_lanes(args.evolve_lanes)  # -1: autotune the mapping during warmup
     gates = B.gate_array(circ)
     x_dev = torch.from_numpy(xs.view(np.int64)).to(dev)
     out32 = torch.empty((n_x, 2), dtype=torch.float64, device=dev)
