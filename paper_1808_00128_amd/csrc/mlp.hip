@@ -52,6 +52,10 @@ __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint
 // ---------------------------------------------------------------------------
 enum { EPI_STORE = 0, EPI_BIAS_RELU = 1, EPI_BIAS = 2, EPI_MASK = 3 };
 
+// Small batches (inference in the chain, up to kFusedMaxBatch rows) take one
+// fused kernel for the whole network instead of features + three products.
+constexpr uint32_t kFusedMaxBatch = 256;
+
 constexpr int kGT = 32;       // output tile edge
 constexpr int kGK = 64;       // K per LDS stage
 constexpr int kGRow = kGK + 4;  // LDS row pitch (elements)
@@ -341,7 +345,11 @@ static hipError_t forward_a0(MLPDev& d, uint32_t B, float* logits, hipStream_t s
   return gemm(g, d, st);
 }
 
+static bool fused_ok(const MLPDev& d);
+static hipError_t fused_forward(MLPDev& d, const uint64_t* x, uint32_t B, float* logits, hipStream_t st);
+
 hipError_t mlp_forward(MLPDev& d, const uint64_t* x, uint32_t B, float* logits, hipStream_t st) {
+  if (fused_ok(d) && B <= kFusedMaxBatch) return fused_forward(d, x, B, logits, st);
   const uint32_t cnt = B * d.L.n;
   hipLaunchKernelGGL(k_features, dim3((cnt + 255) / 256), dim3(256), 0, st, x, B, d.L.n, d.a0);
   hipError_t e = hipGetLastError();
@@ -416,10 +424,9 @@ __device__ __forceinline__ double log_q_mix(double lp, uint64_t m, uint32_t n, f
   return log(single + (1.0 - (double)eps) * exp(lp));
 }
 
-// One thread per chain: draw the flip mask of this step from pi(x).
-__global__ void k_learned_mask(LearnedView Lv, uint32_t step) {
-  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= Lv.n_chain) return;
+// Flip mask of chain c at this step, drawn from pi(x); also stores the mask
+// and the proposal y = x ^ m.
+__device__ __forceinline__ uint64_t draw_mask(const LearnedView& Lv, uint32_t c, uint32_t step) {
   const uint32_t n = Lv.n;
   const uint64_t idx = (uint64_t)c * Lv.n_steps + step;
   uint64_t m = 0;
@@ -431,8 +438,141 @@ __global__ void k_learned_mask(LearnedView Lv, uint32_t step) {
     for (uint32_t j = 0; j < n; ++j)
       if (ub[j] < (double)clip_sigmoid(lx[j], Lv.pi_min, Lv.pi_max)) m |= 1ull << j;
   }
+  const uint64_t y = Lv.x[c] ^ m;
   Lv.mask[c] = m;
-  Lv.y[c] = Lv.x[c] ^ m;
+  Lv.y[c] = y;
+  return y;
+}
+
+// One thread per chain: draw the flip mask of this step from pi(x).
+__global__ void k_learned_mask(LearnedView Lv, uint32_t step) {
+  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= Lv.n_chain) return;
+  draw_mask(Lv, c, step);
+}
+
+// ---------------------------------------------------------------------------
+// The whole network for up to 16 rows per 1024-thread workgroup: features,
+// then the three layers with the activations in LDS and the BF16 weights
+// read from L2.  Each output 16 x 16 tile takes the same MFMAs over the same
+// k blocks (to the next multiple of 64, zero-padded) as k_gemm_bf16, and the
+// same epilogues, so the values equal the three-product path bit for bit.
+// kDraw: the rows are chains; draw their masks first and evaluate the
+// network at the proposals y (logits to logit_y).  Otherwise the rows are
+// x[0..B) and the activations are also stored for the backward pass.
+// ---------------------------------------------------------------------------
+constexpr int kFR = 16;                 // rows per workgroup
+constexpr int kFWaves = 16;             // waves per workgroup (one 16-column tile each)
+constexpr int kFMaxH = 256;             // widest hidden layer of the fused path
+constexpr int kFP0 = 64 + 4;            // LDS pitch of the features (elements)
+constexpr int kFPH = kFMaxH + 4;        // LDS pitch of a hidden activation
+
+static bool fused_ok(const MLPDev& d) { return d.L.H <= (uint32_t)kFMaxH && d.L.n <= 64; }
+
+// One layer: out[r][j] = act(sum_k A[r][k] W[j][k] + bias[j]) for the
+// workgroup's 16 rows; wave w takes the output tiles w, w + kFWaves, ...
+__device__ __forceinline__ void fused_layer(const uint16_t* As, int pa, int K,
+                                            const uint16_t* __restrict__ W, int N,
+                                            const float* __restrict__ bias, int epi, uint16_t* Os,
+                                            int po, float* zf, uint16_t* zb, float* out, int ldo,
+                                            int rows) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r16 = lane & 15, kq = (lane >> 4) * 4;
+  const int kb_n = ((K + kGK - 1) / kGK) * (kGK / 16);  // 16-wide k blocks
+  const bool vec = (K % 4) == 0;                        // rows of W 8-byte aligned
+  for (int ct = wave; ct * 16 < N; ct += kFWaves) {
+    const int col = ct * 16 + r16;
+    bf16x4 b[kFMaxH / 16];
+#pragma unroll
+    for (int kb = 0; kb < kFMaxH / 16; ++kb) {
+      const int k = kb * 16 + kq;
+      bf16x4 v = {0, 0, 0, 0};
+      if (kb < kb_n && col < N && k < K) {
+        const uint16_t* w = W + (int64_t)col * K + k;
+        if (vec) {
+          v = *reinterpret_cast<const bf16x4*>(w);
+        } else {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) v[i] = (k + i < K) ? (short)w[i] : (short)0;
+        }
+      }
+      b[kb] = v;
+    }
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kb = 0; kb < kFMaxH / 16; ++kb) {
+      if (kb < kb_n) {  // kb_n is wave-uniform
+        const bf16x4 a = *reinterpret_cast<const bf16x4*>(&As[r16 * pa + kb * 16 + kq]);
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b[kb], acc, 0, 0, 0);
+      }
+    }
+    if (col >= N) continue;
+    const float bj = bias[col];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = (lane >> 4) * 4 + r;
+      const float v = acc[r] + bj;
+      if (epi == EPI_BIAS_RELU) {
+        const uint16_t a = f2bf(v > 0.f ? v : 0.f);
+        Os[row * po + col] = a;
+        if (row < rows && zf) zf[(int64_t)row * ldo + col] = v;
+        if (row < rows && zb) zb[(int64_t)row * ldo + col] = a;
+      } else if (row < rows) {
+        out[(int64_t)row * ldo + col] = v;
+      }
+    }
+  }
+}
+
+template <bool kDraw>
+__global__ __launch_bounds__(64 * kFWaves) void k_mlp_fused(MLPDev d, const uint64_t* __restrict__ x,
+                                                   uint32_t B, float* __restrict__ logits,
+                                                   LearnedView Lv, uint32_t step) {
+  __shared__ __align__(16) uint16_t A0[kFR * kFP0];
+  __shared__ __align__(16) uint16_t A1[kFR * kFPH];
+  __shared__ __align__(16) uint16_t A2[kFR * kFPH];
+  __shared__ uint64_t sx[kFR];
+  const MLPLayout& L = d.L;
+  const int n = (int)L.n, H = (int)L.H;
+  const uint32_t r0 = blockIdx.x * kFR;
+  const int rows = (int)min((uint32_t)kFR, B - r0);
+  const uint32_t tid = threadIdx.x;
+  if (tid < (uint32_t)kFR) {
+    uint64_t v = 0;
+    if ((int)tid < rows) v = kDraw ? draw_mask(Lv, r0 + tid, step) : x[r0 + tid];
+    sx[tid] = v;
+  }
+  // Zero the hidden activations' padding columns (read as zero k blocks).
+  for (uint32_t e = tid; e < (uint32_t)(kFR * kFPH); e += 64u * kFWaves) {
+    A1[e] = 0;
+    A2[e] = 0;
+  }
+  __syncthreads();
+  for (uint32_t e = tid; e < (uint32_t)(kFR * 64); e += 64u * kFWaves) {
+    const int r = (int)(e / 64), k = (int)(e % 64);
+    uint16_t f = 0;
+    if (k < n && r < rows) f = ((sx[r] >> k) & 1ull) ? (uint16_t)0xBF80 /* -1 */ : (uint16_t)0x3F80;
+    A0[r * kFP0 + k] = f;
+    if (!kDraw && k < n && r < rows) d.a0[(int64_t)(r0 + r) * n + k] = f;
+  }
+  __syncthreads();
+  const int64_t o = (int64_t)r0 * H;
+  fused_layer(A0, kFP0, n, d.wb + L.wb_W1(), H, d.p + L.off_b1(), EPI_BIAS_RELU, A1, kFPH,
+              kDraw ? nullptr : d.z1 + o, kDraw ? nullptr : d.a1 + o, nullptr, H, rows);
+  __syncthreads();
+  fused_layer(A1, kFPH, H, d.wb + L.wb_W2(), H, d.p + L.off_b2(), EPI_BIAS_RELU, A2, kFPH,
+              kDraw ? nullptr : d.z2 + o, kDraw ? nullptr : d.a2 + o, nullptr, H, rows);
+  __syncthreads();
+  float* out = kDraw ? Lv.logit_y + (int64_t)r0 * n : logits + (int64_t)r0 * n;
+  fused_layer(A2, kFPH, H, d.wb + L.wb_W3(), n, d.p + L.off_b3(), EPI_BIAS, nullptr, 0, nullptr,
+              nullptr, out, n, rows);
+}
+
+static hipError_t fused_forward(MLPDev& d, const uint64_t* x, uint32_t B, float* logits, hipStream_t st) {
+  if (B == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mlp_fused<false>, dim3((B + kFR - 1) / kFR), dim3(64 * kFWaves), 0, st, d, x, B, logits,
+                     LearnedView{}, 0u);
+  return hipGetLastError();
 }
 
 // One thread per term, loop over chains: Q_y = Q_x prod_{j in m} P_j (the
@@ -510,10 +650,18 @@ __global__ __launch_bounds__(256) void k_learned_accept(MetroView Mv, LearnedVie
 hipError_t launch_learned_steps(const TermsView& T, MetroView& Mv, LearnedView& Lv, MLPDev& d,
                                 uint32_t n_steps, hipStream_t st) {
   hipError_t e;
+  const bool fused = fused_ok(d);
   for (uint32_t t = 0; t < n_steps; ++t) {
-    hipLaunchKernelGGL(k_learned_mask, dim3((Lv.n_chain + 63) / 64), dim3(64), 0, st, Lv, t);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    if ((e = mlp_forward(d, Lv.y, Lv.n_chain, Lv.logit_y, st)) != hipSuccess) return e;
+    if (fused) {
+      // Masks, proposals and the network at the proposals in one kernel.
+      hipLaunchKernelGGL(k_mlp_fused<true>, dim3((Lv.n_chain + kFR - 1) / kFR), dim3(64 * kFWaves), 0, st, d,
+                         nullptr, Lv.n_chain, nullptr, Lv, t);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    } else {
+      hipLaunchKernelGGL(k_learned_mask, dim3((Lv.n_chain + 63) / 64), dim3(64), 0, st, Lv, t);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      if ((e = mlp_forward(d, Lv.y, Lv.n_chain, Lv.logit_y, st)) != hipSuccess) return e;
+    }
     if ((e = launch_propose(T, Mv, Lv.mask, 0, st)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_learned_accept, dim3(Mv.n_chain), dim3(256), 0, st, Mv, Lv, t);
     if ((e = hipGetLastError()) != hipSuccess) return e;

@@ -62,6 +62,23 @@ def test_mlp_forward_matches_oracle(B, n, H, batch):
     ctx.close()
 
 
+@pytest.mark.parametrize("n,H", [(50, 256), (13, 48)])
+def test_mlp_fused_forward_equals_product_path(B, n, H):
+    """Batches up to 256 rows run the fused one-kernel network, larger ones
+    the three BF16 products; the shared rows agree bit for bit (same MFMAs
+    over the same k blocks, same epilogues)."""
+    say(f"mlp fused vs products n={n} H={H}")
+    ctx = host_ctx(B)
+    p = varied_params(n, H, seed=3 + n)
+    net = B.MLP(ctx, n, H, 300, p)
+    x = W.random_bitstrings(n, 300, np.random.default_rng(7 + n))
+    big = net.forward(x)          # 300 rows: products
+    small = net.forward(x[:201])  # 201 rows: fused
+    assert np.array_equal(big[:201], small)
+    net.close()
+    ctx.close()
+
+
 @pytest.mark.parametrize("n,H,batch", [(50, 256, 128), (12, 64, 100)])
 def test_mlp_gradients_match_oracle(B, n, H, batch):
     say(f"mlp gradients n={n} H={H} batch={batch}")
