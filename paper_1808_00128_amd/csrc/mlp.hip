@@ -537,10 +537,33 @@ __global__ __launch_bounds__(64 * kFWaves) void k_mlp_fused(MLPDev d, const uint
   const uint32_t r0 = blockIdx.x * kFR;
   const int rows = (int)min((uint32_t)kFR, B - r0);
   const uint32_t tid = threadIdx.x;
-  if (tid < (uint32_t)kFR) {
-    uint64_t v = 0;
-    if ((int)tid < rows) v = kDraw ? draw_mask(Lv, r0 + tid, step) : x[r0 + tid];
-    sx[tid] = v;
+  if (kDraw) {
+    // Wave r draws the mask of row r: lane j decides bit j (the comparisons
+    // of draw_mask), one ballot assembles the mask.
+    static_assert(kFWaves == kFR, "one wave per row");
+    const uint32_t r = tid >> 6, lane = tid & 63u;
+    uint64_t y = 0;
+    if ((int)r < rows) {
+      const uint32_t c = r0 + r;
+      const uint64_t idx = (uint64_t)c * Lv.n_steps + step;
+      uint64_t m;
+      if (Lv.u_mix[idx] < (double)Lv.eps) {
+        m = 1ull << (Lv.j[idx] % (uint32_t)n);
+      } else {
+        const bool bit = (int)lane < n &&
+                         Lv.u_bits[idx * n + lane] <
+                             (double)clip_sigmoid(Lv.logit_x[(uint64_t)c * n + lane], Lv.pi_min, Lv.pi_max);
+        m = __ballot(bit);
+      }
+      y = Lv.x[c] ^ m;
+      if (lane == 0) {
+        Lv.mask[c] = m;
+        Lv.y[c] = y;
+      }
+    }
+    if (lane == 0) sx[r] = y;
+  } else if (tid < (uint32_t)kFR) {
+    sx[tid] = (int)tid < rows ? x[r0 + tid] : 0ull;
   }
   // Zero the hidden activations' padding columns (read as zero k blocks).
   for (uint32_t e = tid; e < (uint32_t)(kFR * kFPH); e += 64u * kFWaves) {
