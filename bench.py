@@ -265,7 +265,7 @@ def bench_learned(torch, B, W, stats, steps=1000, n_chain=64, chi=1 << 20, eps=0
     plain["hip_graph"] = graph
     bytes_step = chain_step_bytes(chi, n, n_chain)
     achieved = bytes_step * steps / (ms / 1e3) / 1e9
-    plain["roofline"] = {"bound": "hbm", "kernel": "k_propose<single flip> + k_metro_accept",
+    plain["roofline"] = {"bound": "hbm", "kernel": "k_propose_gather (single flips) + k_metro_accept",
                          "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
                          "frac": round(achieved / 8000.0, 4), "traffic": None,
                          "bytes_per_step": bytes_step}
@@ -277,7 +277,7 @@ def bench_learned(torch, B, W, stats, steps=1000, n_chain=64, chi=1 << 20, eps=0
     learned = chain_report(stats, ltr, lac, lms, burn, lcost, lfl)
     lbytes = chain_step_bytes(chi, n, n_chain)
     lach = lbytes * steps / (lms / 1e3) / 1e9
-    learned["roofline"] = {"bound": "hbm", "kernel": "k_propose<masks> + network + accept",
+    learned["roofline"] = {"bound": "hbm", "kernel": "k_propose<masks> + k_mlp_fused (masks and network) + k_learned_accept",
                            "achieved": round(lach, 1), "peak": 8000.0, "unit": "GB/s",
                            "frac": round(lach / 8000.0, 4), "traffic": None,
                            "bytes_per_step": lbytes}
