@@ -37,6 +37,23 @@ def algorithmic_ops_evolve(stats, n):
                  + stats["cond"] * 12)
 
 
+# MI355X LDS: 256 CUs x 128 B/clk x 2.4 GHz.
+LDS_PEAK_BPS = 256 * 128 * 2.4e9
+
+
+def amp_lds_bytes_per_pair(n, v_words):
+    """LDS bytes the amplitude kernel reads per (term, x): 8-byte table
+    lookups, ceil(n / 4) for a term whose zero test is packed into its
+    quadratic-form rows (n - |v| <= 64 - n), twice that otherwise, plus one
+    lookup of the term's value; returned with the packed fraction of the
+    sampled terms."""
+    vc = np.array([bin(int(w)).count("1") for w in np.asarray(v_words).ravel()])
+    packed = (n - vc) <= (64 - n)
+    nch = (n + 3) // 4
+    per = np.where(packed, nch, 2 * nch) + 1
+    return 8.0 * float(np.mean(per)), float(np.mean(packed))
+
+
 def algorithmic_ops_amp(xs):
     """Int32 operations per (term, x): 6 per set bit (XOR, AND, POPCOUNT on
     64-bit words) + 20 for the zero test and the phase."""
@@ -372,7 +389,10 @@ def bench_uneven(torch, B, W, steps=2, warmup=1):
             t_batch.append(ev[1].elapsed_time(ev[2]))
             t_single.append(ev[2].elapsed_time(ev[3]))
     evals = float(sum(sp["chi"] * sp["x"].size for sp in insts))
-    ops = sum(algorithmic_ops_amp(sp["x"]) * sp["chi"] * sp["x"].size for sp in insts)
+    lds = 0.0
+    for k, sp in enumerate(insts):
+        per, _ = amp_lds_bytes_per_pair(sp["circuit"].n, ctx.get_terms(0, min(sp["chi"], 512), inst=k)["v"])
+        lds += per * sp["chi"] * sp["x"].size
     ms_b = float(np.mean(t_batch))
     ms_s = float(np.mean(t_single))
     ms_e = float(np.mean(t_ev))
@@ -384,9 +404,9 @@ def bench_uneven(torch, B, W, steps=2, warmup=1):
             "ms_evolve_all": ms_e, "ms_amplitudes_batched": ms_b, "ms_amplitudes_per_instance": ms_s,
             "evals_per_s_batched": evals / (ms_b / 1e3), "evals_per_s_per_instance": evals / (ms_s / 1e3),
             "evals_per_s_step": evals / ((ms_e + ms_b) / 1e3),
-            "amplitude_roofline": {"bound": "alu", "achieved": ops / (ms_b / 1e3) / 1e12,
-                                   "peak": INT32_PEAK_OPS / 1e12, "unit": "TOP/s (int32)",
-                                   "frac": ops / (ms_b / 1e3) / INT32_PEAK_OPS},
+            "amplitude_roofline": {"bound": "lds", "achieved": lds / (ms_b / 1e3) / 1e12,
+                                   "peak": LDS_PEAK_BPS / 1e12, "unit": "TB/s (LDS table reads)",
+                                   "frac": lds / (ms_b / 1e3) / LDS_PEAK_BPS},
             "finite": ok}
 
 
@@ -489,6 +509,7 @@ def main():
     fp32c_vs_fp64 = float(np.max(np.abs(c32 - c64)) / rms) if rms > 0 else 0.0
 
     ev_stats = ctx.evolution_stats()
+    lds_pair, packed_frac = amp_lds_bytes_per_pair(n, ctx.get_terms(0, min(chi, 4096))["v"])
     ops_ev = algorithmic_ops_evolve(ev_stats, n)
     ops_amp = algorithmic_ops_amp(xs) * chi * n_x
     ms_ev = float(np.mean(phase["evolve"]))
@@ -538,6 +559,12 @@ def main():
         "evolve_gates_per_s": chi * circ.n_gates / (ms_ev / 1e3),
         "fp32c_vs_fp64_normwise": fp32c_vs_fp64,
         "roofline": roofline,
+        "amplitude_roofline": {"bound": "lds", "kernel": "k_amp<float> (with k_amp_prep, k_reduce_ranges)",
+                               "achieved": round(lds_pair * chi * n_x / (ms_amp / 1e3) / 1e12, 3),
+                               "peak": round(LDS_PEAK_BPS / 1e12, 2), "unit": "TB/s (LDS table reads)",
+                               "frac": round(lds_pair * chi * n_x / (ms_amp / 1e3) / LDS_PEAK_BPS, 4),
+                               "lds_bytes_per_pair": lds_pair, "packed_fraction": packed_frac,
+                               "paper_ops_per_s": round(ops_amp / (ms_amp / 1e3) / 1e12, 3)},
     }
     ctx.close()
     del ctx
