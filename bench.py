@@ -81,9 +81,10 @@ def cpu_baseline(cfg, sample_terms, threads):
 # api.hip included): the recorded bytes stay valid while these files are unchanged.
 KERNEL_SOURCES = {
     "k_evolve": ["evolve_kernel.hpp", "evolve.hip", "evolve_l4.hip", "evolve_l8.hip",
-                 "evolve_wide.hip", "prefix.hip", "device_common.hpp", "internal.hpp", "api.hip"],
-    "k_evolve_lds": ["evolve_lds.hip", "evolve.hip", "prefix.hip", "device_common.hpp", "internal.hpp",
-                     "api.hip"],
+                 "evolve_wide.hip", "evolve_w64.hip", "prefix.hip", "device_common.hpp", "internal.hpp",
+                 "api.hip"],
+    "k_evolve_lds": ["evolve_lds.hip", "evolve_w64.hip", "evolve.hip", "prefix.hip", "device_common.hpp",
+                     "internal.hpp", "api.hip"],
     "k_amp<float>": ["amplitude.hip", "device_common.hpp", "internal.hpp", "api.hip"],
     "k_inner_pairs": ["inner.hip", "device_common.hpp", "internal.hpp", "api.hip"],
 }

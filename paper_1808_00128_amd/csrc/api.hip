@@ -405,10 +405,10 @@ struct GateCost {
 };
 constexpr GateCost kCostReg8 = {{0.87, 0.76, 0.67, 0.46}, {4.23, 2.52, 2.21, 1.57}};
 constexpr GateCost kCostReg16 = {{0.70, 0.55, 0.50, 0.40}, {4.10, 2.70, 2.40, 1.80}};
-constexpr GateCost kCostWave = {{0.45, 0.39, 0.35, 0.31}, {10.3, 6.77, 5.79, 5.05}};
-constexpr GateCost kCostLds4 = {{2.39, 0.40, 0.30, 0.30}, {5.27, 0.81, 0.63, 0.64}};
-constexpr GateCost kCostLds8 = {{1.51, 0.39, 0.30, 0.29}, {4.71, 0.95, 0.77, 0.79}};
-constexpr GateCost kCostLds16 = {{1.08, 0.39, 0.30, 0.29}, {5.89, 1.44, 1.21, 1.25}};
+constexpr GateCost kCostWave = {{0.47, 0.28, 0.28, 0.29}, {11.9, 5.04, 4.18, 4.32}};
+constexpr GateCost kCostLds4 = {{2.32, 0.39, 0.30, 0.30}, {5.19, 0.80, 0.62, 0.63}};
+constexpr GateCost kCostLds8 = {{1.48, 0.39, 0.30, 0.30}, {4.67, 0.95, 0.77, 0.78}};
+constexpr GateCost kCostLds16 = {{1.05, 0.39, 0.30, 0.29}, {5.80, 1.43, 1.21, 1.26}};
 constexpr double kLevelCostUs = 45.0;  // prefix-id kernels and a launch per level
 
 // Cost table of the mapping a span would run with (the whole-wave mapping

@@ -107,6 +107,7 @@ hipError_t launch_evolve_job(const EvolveJob& J, const DGate* gates, uint32_t n_
   if (shape.lds) return launch_evolve_lds(shape.lanes, J, gates, n_gates, from_zero, err, st);
   if (shape.lanes == 4) return launch_evolve_l4(shape.rows, J, gates, n_gates, from_zero, err, st);
   if (shape.lanes == 8) return launch_evolve_l8(shape.rows, J, gates, n_gates, from_zero, err, st);
+  if (shape.lanes == 64) return launch_evolve_w64(J, gates, n_gates, from_zero, err, st);
   return launch_evolve_wide(shape.lanes, shape.rows, J, gates, n_gates, from_zero, err, st);
 }
 

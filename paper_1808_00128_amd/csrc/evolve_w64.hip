@@ -1,0 +1,237 @@
+// CH-form evolution with one term per wave and one tableau row per lane
+// (step (a) of the hot path; the same gates and rules as evolve_kernel.hpp).
+//
+// Lane p holds row p (F_p, G_p, M_p, gamma_p; zero for p >= n).  A left rule
+// reads rows q and r with v_readlane into scalar registers and the lanes
+// p = q, r update their own row; the Hadamard update (Eqs. (H1)-(H7),
+// Prop. H) takes row q the same way, computes t, u, alpha, beta and the case
+// of Prop. H on the scalar unit (v, s, omega live there), and every lane
+// applies the batch of commuting right rules of V_C to its row.  With one
+// term per wave every branch is uniform, so a gate costs only its own
+// instructions: this mapping serves spans with few items, where the time is
+// the latency of one wave's gate chain.
+#include "device_common.hpp"
+#include "internal.hpp"
+
+namespace chsim {
+namespace {
+
+constexpr uint32_t kW64Chunk = 2048;  // gates staged in LDS at a time (16 KiB)
+
+// All ones if bit b (< 32) of x is set, else zero.
+__device__ __forceinline__ uint32_t bmask(uint32_t x, uint32_t b) {
+  return (uint32_t)__builtin_amdgcn_sbfe((int)x, b, 1u);
+}
+
+template <bool kFromZero>
+__global__ __launch_bounds__(256) void k_evolve_w64(EvolveJob J, const DGate* __restrict__ gates,
+                                                    uint32_t n_gates, uint32_t* __restrict__ err) {
+  const uint64_t count = J.count_dev ? (uint64_t)*J.count_dev : J.count;
+  if ((uint64_t)blockIdx.x * 4u >= count) return;  // whole block: no barrier skipped
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t wave = uniform32(threadIdx.x >> 6);
+  const uint64_t item = (uint64_t)blockIdx.x * 4u + wave;
+  const bool live = item < count;
+  // A dead wave (ragged last block) evolves a copy of item 0 and stores nothing.
+  const uint64_t it = live ? item : 0;
+  const uint64_t sa = uniform64(J.src_idx ? (uint64_t)J.src_idx[it] : it);  // input state
+  const uint64_t ba = uniform64(J.br_idx ? (uint64_t)J.br_idx[it] : it);    // branch choices
+  const uint64_t chb = J.chi_br;
+  const uint8_t* __restrict__ branch = J.branch;
+  const uint32_t n = J.dst.n;
+  const bool act = lane < n;
+  uint64_t F, G, M;
+  uint32_t g;
+  uint64_t v, s;
+  uint32_t w;
+  if (kFromZero) {
+    F = act ? (1ull << lane) : 0ull;
+    G = F;
+    M = 0ull;
+    g = 0u;
+    v = 0ull;
+    s = 0ull;
+    w = 0u;
+  } else {
+    const uint64_t off = (uint64_t)lane * J.src_rs + sa * J.src_is;
+    F = act ? J.src.F[off] : 0ull;
+    G = act ? J.src.G[off] : 0ull;
+    M = act ? J.src.M[off] : 0ull;
+    g = act ? (uint32_t)J.src.gamma[off] : 0u;
+    v = uniform64(J.src.v[sa]);
+    s = uniform64(J.src.s[sa]);
+    w = uniform32(J.src.omega[sa]);
+  }
+  uint32_t e = 0u;
+  const uint32_t* __restrict__ seq = J.slot_seq;
+  const uint32_t n_occ = J.n_occ;
+  uint32_t next_b = n_occ ? uniform32(branch[(uint64_t)seq[0] * chb + ba]) : 0u;
+  uint32_t cur_b = 0u, occ = 1u;
+  const uint2* __restrict__ g2 = reinterpret_cast<const uint2*>(gates);
+  __shared__ uint2 sg[kW64Chunk];
+  for (uint32_t c0 = 0; c0 < n_gates; c0 += kW64Chunk) {
+    const uint32_t cn = min(kW64Chunk, n_gates - c0);
+    __syncthreads();
+    for (uint32_t t = threadIdx.x; t < cn; t += 256u) sg[t] = g2[c0 + t];
+    __syncthreads();
+    uint2 nxt = sg[0];
+    for (uint32_t i = 0; i < cn; ++i) {
+      const uint32_t w0 = uniform32(nxt.x), w1 = uniform32(nxt.y);
+      nxt = sg[i + 1 < cn ? i + 1 : i];
+      const uint32_t op = w0 & 0xffu, q = (w0 >> 8) & 0xffu, r = (w0 >> 16) & 0xffu;
+      const uint32_t cond = (w1 >> 16) & 0xffu;
+      if (cond & kSlotStart) {
+        cur_b = next_b;
+        if (occ < n_occ) next_b = uniform32(branch[(uint64_t)seq[occ] * chb + ba]);
+        ++occ;
+      }
+      const bool on = !(cond & kCondApply) || cur_b == (w1 >> 24);
+      if (!on) continue;
+      if (op == OP_H) {
+        // Hadamard on qubit q: Eqs. (H2), (H4), the t = u case, Prop. H.
+        const uint64_t Fp = rl64(F, q), Gp = rl64(G, q), Mp = rl64(M, q);
+        const uint32_t gp = rl32(g, q);
+        const uint64_t nv = ~v;
+        const uint64_t t = s ^ (Gp & v);
+        const uint64_t u = s ^ (Fp & nv) ^ (Mp & v);
+        const uint32_t alpha = par64(Gp & nv & s);
+        const uint32_t beta = par64(Mp & nv & s) ^ par64(Fp & v & (Mp ^ s));
+        const uint32_t delta = (gp + 2u * (alpha + beta)) & 3u;
+        if (t == u) {
+          // omega' = 2^{-1/2} (-1)^alpha (1 + i^delta), delta odd.
+          if (!(delta & 1u)) e = 1u;
+          w = (w + 4u * alpha + (delta == 1u ? 1u : 7u)) & 7u;
+          s = t;
+          continue;
+        }
+        const uint64_t d = t ^ u, V0 = d & nv, V1 = d & v;
+        const bool use0 = V0 != 0ull;
+        const uint32_t qh = (uint32_t)__builtin_ctzll(use0 ? V0 : V1);
+        const uint64_t qb = 1ull << qh;
+        const uint64_t W = (use0 ? V0 : V1) & ~qb;
+        // The lane's row as 32-bit halves; qs, hq locate bit qh.
+        const uint32_t qs = qh & 31u;
+        const bool hq = qh >= 32u;
+        const uint32_t qbl = (uint32_t)qb, qbh = (uint32_t)(qb >> 32);
+        const uint32_t Wl = (uint32_t)W, Wh = (uint32_t)(W >> 32);
+        uint32_t Fl = (uint32_t)F, Fh = (uint32_t)(F >> 32);
+        uint32_t Gl = (uint32_t)G, Gh = (uint32_t)(G >> 32);
+        uint32_t Ml = (uint32_t)M, Mh = (uint32_t)(M >> 32);
+        if (use0) {
+          // R[CX_{q,i}], i in W: G_{.,q} ^= G_{.,i}; F_{.,i} ^= F_{.,q}; M_{.,q} ^= M_{.,i}.
+          // R[CZ_{q,i}], i in V_1: M_{.,q} ^= F_{.,i}; M_{.,i} ^= F_{.,q}; gamma += 2 F_{.,q} F_{.,i}.
+          const uint32_t V1l = (uint32_t)V1, V1h = (uint32_t)(V1 >> 32);
+          const uint32_t mf = bmask(hq ? Fh : Fl, qs);
+          const uint32_t mg = bmask((uint32_t)__popc(Gl & Wl) + (uint32_t)__popc(Gh & Wh), 0u);
+          Gl ^= qbl & mg;
+          Gh ^= qbh & mg;
+          Fl ^= Wl & mf;
+          Fh ^= Wh & mf;
+          const uint32_t c = (uint32_t)__popc(Fl & V1l) + (uint32_t)__popc(Fh & V1h);
+          const uint32_t mm = bmask(c + (uint32_t)__popc(Ml & Wl) + (uint32_t)__popc(Mh & Wh), 0u);
+          Ml ^= (qbl & mm) ^ (V1l & mf);
+          Mh ^= (qbh & mm) ^ (V1h & mf);
+          g = (g + 2u * (mf & c & 1u)) & 3u;
+        } else {
+          // R[CX_{i,q}], i in W: G_{.,i} ^= G_{.,q}; F_{.,q} ^= F_{.,i}; M_{.,i} ^= M_{.,q}.
+          const uint32_t mg = bmask(hq ? Gh : Gl, qs), mm = bmask(hq ? Mh : Ml, qs);
+          const uint32_t mf = bmask((uint32_t)__popc(Fl & Wl) + (uint32_t)__popc(Fh & Wh), 0u);
+          Gl ^= Wl & mg;
+          Gh ^= Wh & mg;
+          Fl ^= qbl & mf;
+          Fh ^= qbh & mf;
+          Ml ^= Wl & mm;
+          Mh ^= Wh & mm;
+        }
+        const uint32_t tq = (uint32_t)((t >> qh) & 1ull);
+        const uint64_t y = tq ? (u ^ qb) : t;  // y and z differ only in bit qh; y_qh = t_qh
+        const uint32_t vq = (uint32_t)((v >> qh) & 1ull);
+        // H^{v_q}(|y_q> + i^delta |1 - y_q>) = 2^{1/2} e^{i pi dw/4} S^a H^b |c>; for
+        // y_q = 1 factor out i^delta and use |0> + i^{-delta} |1>.
+        const uint32_t dp = tq ? ((4u - delta) & 3u) : delta;
+        const uint32_t ph = (2u * delta * tq) & 7u;
+        uint32_t a, b, cc, dw;
+        if (!vq) {
+          b = 1u;
+          a = dp & 1u;
+          cc = dp >> 1;
+          dw = ph;
+        } else {
+          b = dp & 1u;
+          a = dp & 1u;
+          cc = (dp == 2u || dp == 1u) ? 1u : 0u;
+          dw = ph + (dp == 1u ? 1u : (dp == 3u ? 7u : 0u));
+        }
+        if (a) {
+          // R[S_q]: M_{.,q} ^= F_{.,q}; gamma -= F_{.,q}.
+          const uint32_t fb = ((hq ? Fh : Fl) >> qs) & 1u;
+          const uint32_t mfb = 0u - fb;
+          Ml ^= qbl & mfb;
+          Mh ^= qbh & mfb;
+          g = (g - fb) & 3u;
+        }
+        F = ((uint64_t)Fh << 32) | Fl;
+        G = ((uint64_t)Gh << 32) | Gl;
+        M = ((uint64_t)Mh << 32) | Ml;
+        s = (y & ~qb) | ((uint64_t)cc << qh);
+        v = (v & ~qb) | ((uint64_t)b << qh);
+        w = (w + 4u * alpha + dw) & 7u;
+      } else if (op == OP_CX) {
+        // gamma_q += gamma_r + 2 (M_q . F_r) (M_q before the update);
+        // G_r ^= G_q; F_q ^= F_r; M_q ^= M_r.
+        const uint64_t Fr = rl64(F, r), Mr = rl64(M, r), Gq = rl64(G, q), Mq = rl64(M, q);
+        const uint32_t gr = rl32(g, r);
+        if (lane == q) {
+          g = (g + gr + 2u * par64(Mq & Fr)) & 3u;
+          F ^= Fr;
+          M ^= Mr;
+        }
+        if (lane == r) G ^= Gq;
+      } else if (op == OP_CZ) {
+        // M_q ^= G_r, M_r ^= G_q.
+        const uint64_t Gq = rl64(G, q), Gr = rl64(G, r);
+        if (lane == q) M ^= Gr;
+        if (lane == r) M ^= Gq;
+      } else {
+        // S^pw on q: M_q ^= G_q pw times, gamma_q -= pw.
+        uint32_t pw = 1u;
+        if (op == OP_SLOT_SPOW) pw = ((w0 >> 16) >> (2u * cur_b)) & 3u;
+        else if (op == OP_SPOW) pw = w0 >> 24;
+        if (lane == q) {
+          if (pw & 1u) M ^= G;
+          g = (g - pw) & 3u;
+        }
+      }
+    }
+  }
+  if (live) {
+    if (act) {
+      const uint64_t off = (uint64_t)lane * J.dst_rs + item * J.dst_is;
+      J.dst.F[off] = F;
+      J.dst.G[off] = G;
+      J.dst.M[off] = M;
+      J.dst.gamma[off] = (uint8_t)g;
+    }
+    if (lane == 0) {
+      J.dst.v[item] = v;
+      J.dst.s[item] = s;
+      J.dst.omega[item] = (uint8_t)w;
+      if (e) atomicOr(err, 1u);
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_evolve_w64(const EvolveJob& J, const DGate* gates, uint32_t n_gates, bool from_zero,
+                             uint32_t* err, hipStream_t st) {
+  const uint32_t blocks = (uint32_t)((J.count + 3) / 4);
+  if (blocks == 0) return hipSuccess;
+  if (from_zero)
+    hipLaunchKernelGGL(k_evolve_w64<true>, dim3(blocks), dim3(256), 0, st, J, gates, n_gates, err);
+  else
+    hipLaunchKernelGGL(k_evolve_w64<false>, dim3(blocks), dim3(256), 0, st, J, gates, n_gates, err);
+  return hipGetLastError();
+}
+
+}  // namespace chsim

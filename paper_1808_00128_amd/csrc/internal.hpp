@@ -133,6 +133,8 @@ hipError_t launch_evolve_wide(int lanes, int rows, const EvolveJob& J, const DGa
                               uint32_t n_gates, bool from_zero, uint32_t* err, hipStream_t st);
 hipError_t launch_evolve_lds(int lanes, const EvolveJob& J, const DGate* gates, uint32_t n_gates,
                              bool from_zero, uint32_t* err, hipStream_t st);
+hipError_t launch_evolve_w64(const EvolveJob& J, const DGate* gates, uint32_t n_gates, bool from_zero,
+                             uint32_t* err, hipStream_t st);
 uint64_t evolve_lds_capacity(int lanes, uint32_t n);
 hipError_t launch_evolve(const TermsView& T, const DGate* gates, uint32_t n_gates,
                          const uint32_t* slot_seq, uint32_t n_occ, bool from_zero, uint32_t* err,
