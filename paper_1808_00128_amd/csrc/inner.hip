@@ -31,6 +31,11 @@
 
 namespace chsim {
 
+// All ones if bit b (< 32) of x is set, else zero.
+__device__ __forceinline__ uint32_t bit_mask32(uint32_t x, uint32_t b) {
+  return (uint32_t)__builtin_amdgcn_sbfe((int)x, b, 1u);
+}
+
 namespace {
 
 constexpr int kWaves = 4;
@@ -304,10 +309,25 @@ __global__ __launch_bounds__(64) void k_inner_pairs(TermsView Tv, const uint64_t
         const uint64_t Sb = Srow[b * 64u + lane];
         const uint64_t ab = (1ull << a) | (1ull << b);
         const uint64_t m1 = Sa & ~ab, m2 = Sb & ~ab;
-        for (uint64_t m = Rset; m; m &= m - 1ull) {
-          const uint32_t c = (uint32_t)__builtin_ctzll(m);
-          const uint64_t t = (((m1 >> c) & 1ull) ? m2 : 0ull) ^ (((m2 >> c) & 1ull) ? m1 : 0ull);
-          Srow[c * 64u + lane] = (Srow[c * 64u + lane] ^ t) & ~ab;
+        // Row c ^= (S_ac ? row b : 0) ^ (S_bc ? row a : 0), outside a, b; on
+        // 32-bit halves, the tests as sign-extending bit-field extracts (c is
+        // wave-uniform, so rows c < 32 and c >= 32 take separate loops).
+        const uint32_t m1l = (uint32_t)m1, m1h = (uint32_t)(m1 >> 32);
+        const uint32_t m2l = (uint32_t)m2, m2h = (uint32_t)(m2 >> 32);
+        const uint32_t nabl = ~(uint32_t)ab, nabh = ~(uint32_t)(ab >> 32);
+        auto upd = [&](uint32_t c, uint32_t k1, uint32_t k2) {
+          const uint64_t S = Srow[c * 64u + lane];
+          const uint32_t Sl = ((uint32_t)S ^ (m2l & k1) ^ (m1l & k2)) & nabl;
+          const uint32_t Sh = ((uint32_t)(S >> 32) ^ (m2h & k1) ^ (m1h & k2)) & nabh;
+          Srow[c * 64u + lane] = ((uint64_t)Sh << 32) | Sl;
+        };
+        for (uint32_t m = (uint32_t)Rset; m; m &= m - 1u) {
+          const uint32_t c = (uint32_t)__builtin_ctz(m);
+          upd(c, bit_mask32(m1l, c), bit_mask32(m2l, c));
+        }
+        for (uint32_t m = (uint32_t)(Rset >> 32); m; m &= m - 1u) {
+          const uint32_t c = (uint32_t)__builtin_ctz(m);
+          upd(32u + c, bit_mask32(m1h, c), bit_mask32(m2h, c));
         }
         Srow[a * 64u + lane] = 0ull;
         Srow[b * 64u + lane] = 0ull;
