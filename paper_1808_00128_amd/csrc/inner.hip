@@ -184,8 +184,7 @@ __global__ __launch_bounds__(64) void k_inner_pairs(TermsView Tv, const uint64_t
   extern __shared__ __align__(16) uint64_t lds_w[];
   constexpr uint32_t kChunks = (NMAX + 3) / 4;
   const uint32_t n = Tv.n;
-  const uint32_t nch = (n + 3u) / 4u;
-  uint64_t* const gtab = lds_w;              // [nch][16] XORs of G's rows
+  uint64_t* const gtab = lds_w;              // [kChunks][16] XORs of G's rows
   uint64_t* const Srow = lds_w + 16u * 16u;  // [n + 1][64] elimination rows, lane-minor
   const uint32_t lane = threadIdx.x;
   const uint32_t l = blockIdx.y * 64u + lane;
@@ -210,8 +209,9 @@ __global__ __launch_bounds__(64) void k_inner_pairs(TermsView Tv, const uint64_t
       bad = 1u;
       continue;
     }
-    // Lookup tables: gtab[k][e] = XOR of G rows 4k + i over the bits i of e.
-    for (uint32_t k = 0; k < nch; ++k) {
+    // Lookup tables: gtab[k][e] = XOR of G rows 4k + i over the bits i of e
+    // (zero for chunks at or past n, so every chunk of NMAX can be looked up).
+    for (uint32_t k = 0; k < kChunks; ++k) {
       uint64_t t = 0;
       for (uint32_t i = 0; i < 4u; ++i) {
         const uint32_t row = 4u * k + i;
@@ -238,8 +238,7 @@ __global__ __launch_bounds__(64) void k_inner_pairs(TermsView Tv, const uint64_t
       const uint32_t kc = c >> 2;
       uint64_t tz[kChunks];
 #pragma unroll
-      for (uint32_t k = 0; k < kChunks; ++k)
-        tz[k] = k < nch ? gtab[k * 16u + (uint32_t)((Ac >> (4u * k)) & 15ull)] : 0ull;
+      for (uint32_t k = 0; k < kChunks; ++k) tz[k] = gtab[k * 16u + (uint32_t)((Ac >> (4u * k)) & 15ull)];
       uint64_t W = gtab[kc * 16u + (uint32_t)((Uc >> (4u * kc)) & 15ull)];
       uint64_t Z = 0;
 #pragma unroll
