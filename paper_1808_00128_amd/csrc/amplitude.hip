@@ -458,13 +458,25 @@ hipError_t launch_amp_items(const AmpInst* insts_d, const AmpItem* items_d, uint
   hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, st, counter);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  int dev = 0, cus = 256;
+  // Compute units and resident workgroups per unit, queried once per device.
+  constexpr int kMaxDev = 64;
+  static int cached_cus[kMaxDev] = {}, cached_per_cu[kMaxDev][2] = {};
+  int dev = 0;
   hipGetDevice(&dev);
-  hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  const void* fn = fp32c ? (const void*)k_amp<float> : (const void*)k_amp<double>;
-  int per_cu = 1;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, 0);
-  if (e != hipSuccess || per_cu < 1) per_cu = 1;
+  const int di = (dev >= 0 && dev < kMaxDev) ? dev : 0;
+  int cus = cached_cus[di];
+  if (cus <= 0) {
+    cus = 256;
+    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    cached_cus[di] = cus;
+  }
+  int per_cu = cached_per_cu[di][fp32c ? 1 : 0];
+  if (per_cu <= 0) {
+    const void* fn = fp32c ? (const void*)k_amp<float> : (const void*)k_amp<double>;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, 0);
+    if (e != hipSuccess || per_cu < 1) per_cu = 1;
+    cached_per_cu[di][fp32c ? 1 : 0] = per_cu;
+  }
   uint32_t grid = (uint32_t)std::min<uint64_t>((uint64_t)n_items, (uint64_t)cus * per_cu);
   if (grid == 0) grid = 1;
   if (fp32c)

@@ -183,6 +183,16 @@ struct chsim_ctx {
   std::vector<AmpInst> amp_key;
   uint32_t amp_n_items = 0;
   hipStream_t cap_stream = nullptr;  // stream the Metropolis graphs are recorded on
+  // The last gate list as given (instance, raw gates) and as converted; a call
+  // with the same list reuses the conversion and the device copy.
+  uint32_t dg_inst = UINT32_MAX;
+  std::vector<chsim_gate> dg_in;
+  std::vector<DGate> dg;
+  uint64_t dg_hash = 0;
+  // Amplitude plan of the last request shapes (n, n_x, chi per request).
+  std::vector<uint64_t> amp_shape_key;
+  std::vector<AmpItem> amp_items_h;
+  std::vector<uint32_t> amp_tpr, amp_nr;
   // Slot occurrences of the last gate list: first gate index and slot.
   std::vector<uint32_t> occ_start;
   std::vector<uint32_t> slotseq_h;
@@ -595,16 +605,27 @@ void plan_prefix(Instance& I, const std::vector<DGate>& dg, EvolveShape shape) {
   I.plan_frac = plain > 0 ? total / plain : 1.0;
 }
 
-uint64_t gates_key(const Instance& I, const std::vector<DGate>& dg) {
+// 64-bit words of the gate list (8 bytes per gate) mixed one at a time.
+uint64_t dg_hash(const std::vector<DGate>& dg) {
   uint64_t h = 1469598103934665603ull;
-  auto mix = [&](const void* p, size_t len) {
-    const uint8_t* b = static_cast<const uint8_t*>(p);
-    for (size_t i = 0; i < len; ++i) h = (h ^ b[i]) * 1099511628211ull;
+  for (const DGate& g : dg) {
+    uint64_t w;
+    std::memcpy(&w, &g, sizeof w);
+    h = (h ^ w) * 0x9E3779B97F4A7C15ull;
+    h ^= h >> 29;
+  }
+  return h;
+}
+
+uint64_t gates_key(const Instance& I, uint64_t gate_hash) {
+  uint64_t h = gate_hash;
+  auto mix = [&](uint64_t w) {
+    h = (h ^ w) * 0x9E3779B97F4A7C15ull;
+    h ^= h >> 29;
   };
-  mix(dg.data(), dg.size() * sizeof(DGate));
-  mix(&I.chi, sizeof I.chi);
-  mix(&I.mode, sizeof I.mode);
-  mix(&I.prefix_mode, sizeof I.prefix_mode);
+  mix(I.chi);
+  mix((uint64_t)I.mode);
+  mix((uint64_t)I.prefix_mode);
   return h;
 }
 
@@ -660,7 +681,7 @@ chsim_status evolve_all(chsim_ctx* ctx, Instance& I, const std::vector<DGate>& d
                           shape, s));
     return CHSIM_OK;
   }
-  const uint64_t key = gates_key(I, dg) ^ ((uint64_t)(shape.lanes | (shape.lds ? 0x100 : 0)) << 48);
+  const uint64_t key = gates_key(I, ctx->dg_hash) ^ ((uint64_t)(shape.lanes | (shape.lds ? 0x100 : 0)) << 48);
   if (!I.plan_valid || I.plan_key != key) {
     plan_prefix(I, dg, shape);
     I.plan_key = key;
@@ -770,52 +791,64 @@ chsim_status chsim_apply_clifford(chsim_ctx* ctx, uint32_t inst, const chsim_gat
   if (n_gates == 0) return CHSIM_OK;
   if (!gates) return fail(CHSIM_EINVAL, "null gate list");
   Instance& I = ctx->inst[inst];
-  std::vector<DGate> dg;
-  dg.reserve(n_gates);
-  for (size_t i = 0; i < n_gates; ++i) {
-    const chsim_gate& g = gates[i];
-    if (g.op == CHSIM_SLOT) {
-      if (g.slot >= I.n_slot) return fail(CHSIM_EINVAL, "gate %zu: slot %u >= n_slot %u", i, g.slot, I.n_slot);
-      const SlotTable& tb = I.slots_h[g.slot];
-      if (tb.spow_q >= 0) {
-        uint32_t packed = 0;  // branch j -> S^{spow[j]}, two bits each
-        for (uint32_t j = 0; j < tb.n_branch; ++j) packed |= (uint32_t)(tb.spow[j] & 3u) << (2 * j);
-        dg.push_back(DGate{OP_SLOT_SPOW, (uint8_t)tb.spow_q, (uint8_t)(packed & 0xffu), (uint8_t)(packed >> 8),
-                           (uint16_t)g.slot, kSlotStart, 0});
-      } else {
-        // A general branch list becomes conditional gates: each term applies
-        // only the gates of its own branch.
-        bool first = true;
-        for (uint32_t j = 0; j < tb.n_branch; ++j)
-          for (uint32_t k = tb.goff[j]; k < tb.goff[j + 1]; ++k) {
-            DGate bg = I.bgates_h[k];
-            bg.slot = (uint16_t)g.slot;
-            bg.cond = (uint8_t)(kCondApply | (first ? kSlotStart : 0));
-            bg.arg2 = (uint8_t)j;
-            dg.push_back(bg);
-            first = false;
-          }
-      }
-    } else {
-      if (!valid_clifford(g, I.n)) return fail(CHSIM_EINVAL, "gate %zu: (%u, %u, %u) invalid for n = %u", i, g.op, g.q, g.r, I.n);
-      push_gate(dg, g);
-    }
-  }
   HIP_TRY(hipSetDevice(ctx->device));
   hipStream_t s = as_stream(stream);
-  HIP_TRY(ctx->gates.ensure(dg.size()));
-  HIP_TRY(hipMemcpyAsync(ctx->gates.p, dg.data(), dg.size() * sizeof(DGate), hipMemcpyHostToDevice, s));
-  ctx->occ_start.clear();
-  ctx->slotseq_h.clear();
-  for (size_t i = 0; i < dg.size(); ++i)
-    if (dg[i].cond & kSlotStart) {
-      ctx->occ_start.push_back((uint32_t)i);
-      ctx->slotseq_h.push_back(dg[i].slot);
+  // The same list as the last call (same instance): its conversion and its
+  // device copy are still current.
+  const bool same = ctx->dg_inst == inst && ctx->dg_in.size() == n_gates &&
+                    std::memcmp(ctx->dg_in.data(), gates, n_gates * sizeof(chsim_gate)) == 0;
+  std::vector<DGate>& dg = ctx->dg;
+  if (!same) {
+    ctx->dg_inst = UINT32_MAX;  // invalid until the new list is converted and uploaded
+    dg.clear();
+    dg.reserve(n_gates);
+    for (size_t i = 0; i < n_gates; ++i) {
+      const chsim_gate& g = gates[i];
+      if (g.op == CHSIM_SLOT) {
+        if (g.slot >= I.n_slot) return fail(CHSIM_EINVAL, "gate %zu: slot %u >= n_slot %u", i, g.slot, I.n_slot);
+        const SlotTable& tb = I.slots_h[g.slot];
+        if (tb.spow_q >= 0) {
+          uint32_t packed = 0;  // branch j -> S^{spow[j]}, two bits each
+          for (uint32_t j = 0; j < tb.n_branch; ++j) packed |= (uint32_t)(tb.spow[j] & 3u) << (2 * j);
+          dg.push_back(DGate{OP_SLOT_SPOW, (uint8_t)tb.spow_q, (uint8_t)(packed & 0xffu), (uint8_t)(packed >> 8),
+                             (uint16_t)g.slot, kSlotStart, 0});
+        } else {
+          // A general branch list becomes conditional gates: each term applies
+          // only the gates of its own branch.
+          bool first = true;
+          for (uint32_t j = 0; j < tb.n_branch; ++j)
+            for (uint32_t k = tb.goff[j]; k < tb.goff[j + 1]; ++k) {
+              DGate bg = I.bgates_h[k];
+              bg.slot = (uint16_t)g.slot;
+              bg.cond = (uint8_t)(kCondApply | (first ? kSlotStart : 0));
+              bg.arg2 = (uint8_t)j;
+              dg.push_back(bg);
+              first = false;
+            }
+        }
+      } else {
+        if (!valid_clifford(g, I.n))
+          return fail(CHSIM_EINVAL, "gate %zu: (%u, %u, %u) invalid for n = %u", i, g.op, g.q, g.r, I.n);
+        push_gate(dg, g);
+      }
     }
-  HIP_TRY(ctx->slotseq.ensure(ctx->slotseq_h.size()));
-  if (!ctx->slotseq_h.empty())
-    HIP_TRY(hipMemcpyAsync(ctx->slotseq.p, ctx->slotseq_h.data(), ctx->slotseq_h.size() * sizeof(uint32_t),
-                           hipMemcpyHostToDevice, s));
+    HIP_TRY(ctx->gates.ensure(dg.size()));
+    HIP_TRY(hipMemcpyAsync(ctx->gates.p, dg.data(), dg.size() * sizeof(DGate), hipMemcpyHostToDevice, s));
+    ctx->occ_start.clear();
+    ctx->slotseq_h.clear();
+    for (size_t i = 0; i < dg.size(); ++i)
+      if (dg[i].cond & kSlotStart) {
+        ctx->occ_start.push_back((uint32_t)i);
+        ctx->slotseq_h.push_back(dg[i].slot);
+      }
+    HIP_TRY(ctx->slotseq.ensure(ctx->slotseq_h.size()));
+    if (!ctx->slotseq_h.empty())
+      HIP_TRY(hipMemcpyAsync(ctx->slotseq.p, ctx->slotseq_h.data(), ctx->slotseq_h.size() * sizeof(uint32_t),
+                             hipMemcpyHostToDevice, s));
+    ctx->dg_hash = dg_hash(dg);
+    ctx->dg_in.assign(gates, gates + n_gates);
+    ctx->dg_inst = inst;
+  }
   HIP_TRY(hipMemsetAsync(ctx->err.p, 0, sizeof(uint32_t), s));
   if (I.autotune && I.at_zero) {
     // Every shape computes the same terms from |0^n>, so timing all of them in
@@ -892,9 +925,21 @@ chsim_status run_amplitudes(chsim_ctx* ctx, const std::vector<AmpReq>& reqs, boo
     plan.push_back(AmpRequestPlan{I.n, r.n_x, I.chi});
     total_x += r.n_x;
   }
-  std::vector<AmpItem> items;
-  std::vector<uint32_t> tpr, nr;
-  amp_plan(plan, kAmpTargetItems, items, tpr, nr);
+  // The plan depends on the requests' shapes only; reuse the last one.
+  std::vector<uint64_t> shape_key;
+  shape_key.reserve(3 * plan.size());
+  for (const auto& p : plan) {
+    shape_key.push_back(p.n);
+    shape_key.push_back(p.n_x);
+    shape_key.push_back(p.chi);
+  }
+  if (shape_key != ctx->amp_shape_key) {
+    amp_plan(plan, kAmpTargetItems, ctx->amp_items_h, ctx->amp_tpr, ctx->amp_nr);
+    ctx->amp_shape_key = shape_key;
+  }
+  const std::vector<AmpItem>& items = ctx->amp_items_h;
+  const std::vector<uint32_t>& tpr = ctx->amp_tpr;
+  const std::vector<uint32_t>& nr = ctx->amp_nr;
   size_t part = 0;
   for (size_t q = 0; q < reqs.size(); ++q) part += (size_t)nr[q] * reqs[q].n_x;
   HIP_TRY(ctx->partial.ensure(part));
