@@ -370,6 +370,7 @@ def bench_uneven(torch, B, W, steps=2, warmup=1):
     xs = [torch.from_numpy(sp["x"].view(np.int64)).to(dev) for sp in insts]
     for k in range(len(insts)):
         ctx.set_evolve_lanes(-1, inst=k)
+    ctx.set_amp_strings(-1)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
     t_ev, t_batch, t_single = [], [], []
     outs = None
@@ -398,6 +399,7 @@ def bench_uneven(torch, B, W, steps=2, warmup=1):
     ms_s = float(np.mean(t_single))
     ms_e = float(np.mean(t_ev))
     ok = all(bool(torch.isfinite(o).all()) for o in outs)
+    amp_strings, _ = ctx.amp_strings()
     ctx.close()
     return {"workload": cfg["name"] + ": 64 circuits, n~U{20..60}, 40n Clifford gates + 10..60 phase "
                                       "slots, chi log-uniform 2^10..2^20 (sparsified), 1024 uniform x each",
@@ -405,6 +407,7 @@ def bench_uneven(torch, B, W, steps=2, warmup=1):
             "ms_evolve_all": ms_e, "ms_amplitudes_batched": ms_b, "ms_amplitudes_per_instance": ms_s,
             "evals_per_s_batched": evals / (ms_b / 1e3), "evals_per_s_per_instance": evals / (ms_s / 1e3),
             "evals_per_s_step": evals / ((ms_e + ms_b) / 1e3),
+            "amplitude_strings_per_item": amp_strings,
             "amplitude_roofline": {"bound": "lds", "achieved": lds / (ms_b / 1e3) / 1e12,
                                    "peak": LDS_PEAK_BPS / 1e12, "unit": "TB/s (LDS table reads)",
                                    "frac": lds / (ms_b / 1e3) / LDS_PEAK_BPS},
@@ -454,6 +457,7 @@ def main():
         del src, dst
     ctx = B.Context([cfg])
     ctx.set_evolve_lanes(args.evolve_lanes)  # -1: autotune the mapping during warmup
+    ctx.set_amp_strings(-1)  # autotune bitstrings per work item at the first amplitude call
     gates = B.gate_array(circ)
     x_dev = torch.from_numpy(xs.view(np.int64)).to(dev)
     out32 = torch.empty((n_x, 2), dtype=torch.float64, device=dev)
@@ -483,6 +487,7 @@ def main():
     for i in range(max(1, args.warmup)):
         step(i, False)
     lanes, tune_ms = ctx.evolve_lanes()
+    amp_strings, amp_tune_ms = ctx.amp_strings()
     pf_mode, pf_levels, pf_frac = ctx.prefix_share()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -556,6 +561,8 @@ def main():
         "evolve_autotune": {"shape": shape_name(lanes), "terms_per_wave": 64 // (lanes & 0xff),
                             "ms_by_shape": {shape_name(v): round(t, 4)
                                             for v, t in zip(B.TUNE_SHAPES, tune_ms)}},
+        "amplitude_autotune": {"strings_per_item": amp_strings,
+                               "ms_by_value": {"256": round(amp_tune_ms[0], 4), "512": round(amp_tune_ms[1], 4)}},
         "amplitude_kernel_evals_per_s": chi * n_x / (ms_amp / 1e3),
         "evolve_gates_per_s": chi * circ.n_gates / (ms_ev / 1e3),
         "fp32c_vs_fp64_normwise": fp32c_vs_fp64,

@@ -291,11 +291,20 @@ chsim_status chsim_decompose_phase(double theta, uint32_t qubit, double coeff[4]
  * none when it would not pay), 2 = checkpoint wherever it removes any work
  * (for testing).  EINVAL: value outside 0..2. */
 #define CHSIM_TUNE_PREFIX_SHARE 2u
+/* AMP_STRINGS: bitstrings per work item of the amplitude kernel, 256 or 512
+ * (1 or 2 per lane of a 256-lane workgroup; default 512), for every
+ * amplitude launch of the context (inst only selects a valid instance).  -1 =
+ * autotune: the next chsim_amplitudes or chsim_amplitudes_batch call runs
+ * twice per value (the second run timed with hipEvents) and keeps the
+ * faster; every run leaves correct outputs.  Results agree to rounding across values (the
+ * terms are cut into ranges that may differ).  EUNSUPPORTED: another value. */
+#define CHSIM_TUNE_AMP_STRINGS 3u
 chsim_status chsim_set_tuning(chsim_ctx* ctx, uint32_t inst, uint32_t knob, int32_t value);
 
 /* Current value of a knob.  For EVOLVE_LANES, timings_ms[8] receives the
  * autotuner's timings in ms for lanes 4, 8, 16, 32, 64 with rows in
- * registers and lanes 4, 8, 16 with rows in LDS (0 where not timed);
+ * registers and lanes 4, 8, 16 with rows in LDS (0 where not timed); for
+ * AMP_STRINGS, timings_ms[0..1] = the autotuner's timings for 256 and 512;
  * for PREFIX_SHARE, timings_ms[0] = checkpoint levels of the last planned
  * evolution and timings_ms[1] = its estimated cost relative to evolving
  * every term alone.  timings_ms may be NULL. */

@@ -23,6 +23,7 @@ CHSIM_EXACT, CHSIM_SPARSIFY = 0, 1
 CHSIM_FP64, CHSIM_FP32C, CHSIM_DEVICE_PTRS, CHSIM_GRAPH = 0, 1, 0x100, 0x200
 CHSIM_TUNE_EVOLVE_LANES = 1
 CHSIM_TUNE_PREFIX_SHARE = 2
+CHSIM_TUNE_AMP_STRINGS = 3
 CHSIM_EVOLVE_LDS = 0x100
 # evolution shapes the autotuner times, in the order of its timings
 TUNE_SHAPES = (4, 8, 16, 32, 64, 4 | CHSIM_EVOLVE_LDS, 8 | CHSIM_EVOLVE_LDS, 16 | CHSIM_EVOLVE_LDS)
@@ -245,6 +246,18 @@ class Context:
     def set_prefix_share(self, mode, inst=0):
         """Shared-prefix evolution: 0 off, 1 auto (default), 2 whenever it saves work."""
         _check(lib().chsim_set_tuning(self._h, inst, CHSIM_TUNE_PREFIX_SHARE, int(mode)))
+
+    def set_amp_strings(self, value):
+        """Bitstrings per work item of the amplitude kernel (256 or 512; 0 =
+        default; -1 = autotune at the next amplitude call), for the context."""
+        _check(lib().chsim_set_tuning(self._h, 0, CHSIM_TUNE_AMP_STRINGS, int(value)))
+
+    def amp_strings(self):
+        """(bitstrings per work item in use, autotuner timings in ms for 256 and 512)."""
+        v = C.c_int32()
+        t = (C.c_float * 2)()
+        _check(lib().chsim_get_tuning(self._h, 0, CHSIM_TUNE_AMP_STRINGS, C.byref(v), t))
+        return v.value, list(t)
 
     def prefix_share(self, inst=0):
         """(mode, checkpoint levels of the last plan, estimated work fraction)."""

@@ -53,9 +53,8 @@ namespace {
 constexpr int kTT = 8;                    // terms per table tile
 constexpr int kMaxCh = 16;                // 4-bit chunks of a 64-bit string
 constexpr int kTabWords = kMaxCh * 16;    // one table (u or w) of one term, in 64-bit words
-constexpr int kXPL = 2;                   // bitstrings per lane
-constexpr uint32_t kXChunk = 256 * kXPL;  // bitstrings per work item
 static_assert(kTT * 2 * kMaxCh == 256, "one builder thread per (term, table, chunk)");
+// Bitstrings per lane XPL (1 or 2): a work item holds 256 XPL bitstrings.
 
 // Bits of a at the set positions of m, packed in increasing order into the
 // low popcount(m) bits.
@@ -236,7 +235,7 @@ __device__ __forceinline__ void build_tables(uint64_t* tab, TileTerm<T>* tt, con
   for (int j = 0; j < 16; ++j) dst[(uint32_t)j ^ c] = e[j];
 }
 
-// Terms of one tile against the lane's kXPL bitstrings.  off[j][c] is the
+// Terms of one tile against the lane's XPL bitstrings.  off[j][c] is the
 // swizzled word offset of chunk c's entry for bitstring j; hi masks the bits
 // above n, where a packed term keeps its zero test.
 template <typename T>
@@ -247,12 +246,12 @@ __device__ __forceinline__ void add_term(const TileTerm<T>& K, uint64_t glo, uin
   acc.term(K.ph[idx][0], K.ph[idx][1]);
 }
 
-template <typename T, int NCH>
+template <typename T, int NCH, int XPL>
 __device__ __forceinline__ void run_tile(const uint64_t* tab, const TileTerm<T>* tt,
                                          uint32_t tcount, uint64_t hi,
-                                         const uint32_t (&off)[kXPL][kMaxCh],
-                                         const uint64_t (&x)[kXPL], const bool (&live)[kXPL],
-                                         Acc<T> (&acc)[kXPL]) {
+                                         const uint32_t (&off)[XPL][kMaxCh],
+                                         const uint64_t (&x)[XPL], const bool (&live)[XPL],
+                                         Acc<T> (&acc)[XPL]) {
 #pragma unroll
   for (int t = 0; t < kTT; ++t) {
     if ((uint32_t)t >= tcount) break;
@@ -262,7 +261,7 @@ __device__ __forceinline__ void run_tile(const uint64_t* tab, const TileTerm<T>*
     const uint64_t glo = uniform64(K.glo);
     if (uniform32(K.packed)) {
 #pragma unroll
-      for (int j = 0; j < kXPL; ++j) {
+      for (int j = 0; j < XPL; ++j) {
         uint64_t w = 0;
 #pragma unroll
         for (int c = 0; c < NCH; ++c) w ^= tw[off[j][c]];
@@ -272,7 +271,7 @@ __device__ __forceinline__ void run_tile(const uint64_t* tab, const TileTerm<T>*
       }
     } else {
 #pragma unroll
-      for (int j = 0; j < kXPL; ++j) {
+      for (int j = 0; j < XPL; ++j) {
         uint64_t u = 0;
 #pragma unroll
         for (int c = 0; c < NCH; ++c) u ^= tu[off[j][c]];
@@ -286,10 +285,10 @@ __device__ __forceinline__ void run_tile(const uint64_t* tab, const TileTerm<T>*
     }
   }
 #pragma unroll
-  for (int j = 0; j < kXPL; ++j) acc[j].flush();
+  for (int j = 0; j < XPL; ++j) acc[j].flush();
 }
 
-template <typename T>
+template <typename T, int XPL>
 __global__ __launch_bounds__(256) void k_amp(const AmpInst* __restrict__ insts,
                                              const AmpItem* __restrict__ items, uint32_t n_items,
                                              uint32_t* __restrict__ counter) {
@@ -312,12 +311,12 @@ __global__ __launch_bounds__(256) void k_amp(const AmpInst* __restrict__ insts,
     const uint32_t nch = (n + 3u) / 4u;
     const uint64_t xmask = (n == 64) ? ~0ull : ((1ull << n) - 1ull);
 
-    uint64_t x[kXPL];
-    bool live[kXPL];
-    uint32_t off[kXPL][kMaxCh];
-    Acc<T> acc[kXPL];
+    uint64_t x[XPL];
+    bool live[XPL];
+    uint32_t off[XPL][kMaxCh];
+    Acc<T> acc[XPL];
 #pragma unroll
-    for (int j = 0; j < kXPL; ++j) {
+    for (int j = 0; j < XPL; ++j) {
       const uint32_t xi = item.x0 + (uint32_t)j * 256u + tid;
       live[j] = xi < item.x1;
       x[j] = live[j] ? (I.x[xi] & xmask) : 0ull;  // bits >= n never index a row
@@ -338,7 +337,7 @@ __global__ __launch_bounds__(256) void k_amp(const AmpInst* __restrict__ insts,
       switch (nch) {
 #define CHSIM_AMP_CASE(K)                                         \
   case K:                                                         \
-    run_tile<T, K>(tab, tt, tcount, ~xmask, off, x, live, acc); \
+    run_tile<T, K, XPL>(tab, tt, tcount, ~xmask, off, x, live, acc); \
     break;
         CHSIM_AMP_CASE(1) CHSIM_AMP_CASE(2) CHSIM_AMP_CASE(3) CHSIM_AMP_CASE(4)
         CHSIM_AMP_CASE(5) CHSIM_AMP_CASE(6) CHSIM_AMP_CASE(7) CHSIM_AMP_CASE(8)
@@ -350,7 +349,7 @@ __global__ __launch_bounds__(256) void k_amp(const AmpInst* __restrict__ insts,
       }
     }
 #pragma unroll
-    for (int j = 0; j < kXPL; ++j) {
+    for (int j = 0; j < XPL; ++j) {
       const uint32_t xi = item.x0 + (uint32_t)j * 256u + tid;
       if (live[j]) I.partial[(uint64_t)item.range * I.n_x + xi] = acc[j].value();
     }
@@ -411,9 +410,10 @@ hipError_t launch_amp_prep(const TermsView& T, uint64_t* crow, AmpTerm* cst, hip
   return hipGetLastError();
 }
 
-void amp_plan(const std::vector<AmpRequestPlan>& reqs, uint32_t target_items,
+void amp_plan(const std::vector<AmpRequestPlan>& reqs, uint32_t target_items, uint32_t xpl,
               std::vector<AmpItem>& items, std::vector<uint32_t>& tiles_per_range,
               std::vector<uint32_t>& n_ranges) {
+  const uint32_t kXChunk = 256u * xpl;  // bitstrings per work item
   uint64_t total_tiles = 0, chunks_total = 0;
   for (const auto& r : reqs) {
     total_tiles += (r.chi + kTT - 1) / kTT;
@@ -453,14 +453,19 @@ void amp_plan(const std::vector<AmpRequestPlan>& reqs, uint32_t target_items,
 }
 
 hipError_t launch_amp_items(const AmpInst* insts_d, const AmpItem* items_d, uint32_t n_items,
-                            uint32_t* counter, bool fp32c, const uint64_t* prefix_d, uint32_t n_inst,
-                            uint64_t total_x, hipStream_t st) {
+                            uint32_t* counter, bool fp32c, uint32_t xpl, const uint64_t* prefix_d,
+                            uint32_t n_inst, uint64_t total_x, hipStream_t st) {
+  if (xpl != 1u && xpl != 2u) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, st, counter);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  // Kernel variant (FP32C or FP64, 1 or 2 bitstrings per lane).
+  const int var = (fp32c ? 2 : 0) + (int)(xpl - 1u);
+  const void* fns[4] = {(const void*)k_amp<double, 1>, (const void*)k_amp<double, 2>,
+                        (const void*)k_amp<float, 1>, (const void*)k_amp<float, 2>};
   // Compute units and resident workgroups per unit, queried once per device.
   constexpr int kMaxDev = 64;
-  static int cached_cus[kMaxDev] = {}, cached_per_cu[kMaxDev][2] = {};
+  static int cached_cus[kMaxDev] = {}, cached_per_cu[kMaxDev][4] = {};
   int dev = 0;
   hipGetDevice(&dev);
   const int di = (dev >= 0 && dev < kMaxDev) ? dev : 0;
@@ -470,19 +475,20 @@ hipError_t launch_amp_items(const AmpInst* insts_d, const AmpItem* items_d, uint
     hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     cached_cus[di] = cus;
   }
-  int per_cu = cached_per_cu[di][fp32c ? 1 : 0];
+  int per_cu = cached_per_cu[di][var];
   if (per_cu <= 0) {
-    const void* fn = fp32c ? (const void*)k_amp<float> : (const void*)k_amp<double>;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fns[var], 256, 0);
     if (e != hipSuccess || per_cu < 1) per_cu = 1;
-    cached_per_cu[di][fp32c ? 1 : 0] = per_cu;
+    cached_per_cu[di][var] = per_cu;
   }
   uint32_t grid = (uint32_t)std::min<uint64_t>((uint64_t)n_items, (uint64_t)cus * per_cu);
   if (grid == 0) grid = 1;
-  if (fp32c)
-    hipLaunchKernelGGL(k_amp<float>, dim3(grid), dim3(256), 0, st, insts_d, items_d, n_items, counter);
-  else
-    hipLaunchKernelGGL(k_amp<double>, dim3(grid), dim3(256), 0, st, insts_d, items_d, n_items, counter);
+  switch (var) {
+    case 0: hipLaunchKernelGGL((k_amp<double, 1>), dim3(grid), dim3(256), 0, st, insts_d, items_d, n_items, counter); break;
+    case 1: hipLaunchKernelGGL((k_amp<double, 2>), dim3(grid), dim3(256), 0, st, insts_d, items_d, n_items, counter); break;
+    case 2: hipLaunchKernelGGL((k_amp<float, 1>), dim3(grid), dim3(256), 0, st, insts_d, items_d, n_items, counter); break;
+    default: hipLaunchKernelGGL((k_amp<float, 2>), dim3(grid), dim3(256), 0, st, insts_d, items_d, n_items, counter); break;
+  }
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const uint32_t blocks = (uint32_t)((total_x + kRedX - 1) / kRedX);
   hipLaunchKernelGGL(k_reduce_ranges, dim3(blocks), dim3(256), 0, st, insts_d, prefix_d, n_inst);

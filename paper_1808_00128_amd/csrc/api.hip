@@ -189,10 +189,17 @@ struct chsim_ctx {
   std::vector<chsim_gate> dg_in;
   std::vector<DGate> dg;
   uint64_t dg_hash = 0;
-  // Amplitude plan of the last request shapes (n, n_x, chi per request).
+  // Amplitude plan of the last request shapes (n, n_x, chi per request) and
+  // bitstrings per lane it was cut for.
   std::vector<uint64_t> amp_shape_key;
+  uint32_t amp_plan_xpl = 0, amp_key_xpl = 0;
   std::vector<AmpItem> amp_items_h;
   std::vector<uint32_t> amp_tpr, amp_nr;
+  // Bitstrings per lane of the amplitude kernel (work items of 256 xpl
+  // bitstrings); amp_tune: time both on the next call and keep the faster.
+  uint32_t amp_xpl = 2;
+  bool amp_tune = false;
+  float amp_tune_ms[2] = {0.f, 0.f};
   // Slot occurrences of the last gate list: first gate index and slot.
   std::vector<uint32_t> occ_start;
   std::vector<uint32_t> slotseq_h;
@@ -913,7 +920,8 @@ chsim_status ensure_amp_prep(Instance& I, hipStream_t s) {
 }
 
 // Plan, upload the plan if it differs from the last one, and launch.
-chsim_status run_amplitudes(chsim_ctx* ctx, const std::vector<AmpReq>& reqs, bool fp32c, hipStream_t s) {
+chsim_status run_amplitudes_xpl(chsim_ctx* ctx, const std::vector<AmpReq>& reqs, bool fp32c, uint32_t xpl,
+                                hipStream_t s) {
   for (const auto& r : reqs) {
     chsim_status st = ensure_amp_prep(ctx->inst[r.inst], s);
     if (st) return st;
@@ -933,9 +941,10 @@ chsim_status run_amplitudes(chsim_ctx* ctx, const std::vector<AmpReq>& reqs, boo
     shape_key.push_back(p.n_x);
     shape_key.push_back(p.chi);
   }
-  if (shape_key != ctx->amp_shape_key) {
-    amp_plan(plan, kAmpTargetItems, ctx->amp_items_h, ctx->amp_tpr, ctx->amp_nr);
+  if (shape_key != ctx->amp_shape_key || xpl != ctx->amp_plan_xpl) {
+    amp_plan(plan, kAmpTargetItems, xpl, ctx->amp_items_h, ctx->amp_tpr, ctx->amp_nr);
     ctx->amp_shape_key = shape_key;
+    ctx->amp_plan_xpl = xpl;
   }
   const std::vector<AmpItem>& items = ctx->amp_items_h;
   const std::vector<uint32_t>& tpr = ctx->amp_tpr;
@@ -963,7 +972,7 @@ chsim_status run_amplitudes(chsim_ctx* ctx, const std::vector<AmpReq>& reqs, boo
     off += (size_t)nr[q] * reqs[q].n_x;
     prefix[q + 1] = prefix[q] + reqs[q].n_x;
   }
-  const bool same = insts.size() == ctx->amp_key.size() &&
+  const bool same = insts.size() == ctx->amp_key.size() && ctx->amp_key_xpl == xpl &&
                     std::memcmp(insts.data(), ctx->amp_key.data(), insts.size() * sizeof(AmpInst)) == 0;
   if (!same) {
     HIP_TRY(ctx->amp_insts.ensure(insts.size()));
@@ -978,10 +987,45 @@ chsim_status run_amplitudes(chsim_ctx* ctx, const std::vector<AmpReq>& reqs, boo
                            hipMemcpyHostToDevice, s));
     HIP_TRY(hipStreamSynchronize(s));  // the host vectors die with this call
     ctx->amp_key = insts;
+    ctx->amp_key_xpl = xpl;
     ctx->amp_n_items = (uint32_t)items.size();
   }
   HIP_TRY(launch_amp_items(ctx->amp_insts.p, ctx->amp_items.p, ctx->amp_n_items, ctx->amp_counter.p,
-                           fp32c, ctx->amp_prefix.p, (uint32_t)reqs.size(), total_x, s));
+                           fp32c, xpl, ctx->amp_prefix.p, (uint32_t)reqs.size(), total_x, s));
+  return CHSIM_OK;
+}
+
+// With the autotuner armed, run the call twice per bitstrings-per-lane value
+// (the first run plans and uploads the work items; every run leaves correct
+// outputs), time the second with hipEvents, keep the faster.
+chsim_status run_amplitudes(chsim_ctx* ctx, const std::vector<AmpReq>& reqs, bool fp32c, hipStream_t s) {
+  if (!ctx->amp_tune) return run_amplitudes_xpl(ctx, reqs, fp32c, ctx->amp_xpl, s);
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  uint32_t best = 2;
+  for (uint32_t xpl = 1; xpl <= 2; ++xpl) {
+    chsim_status st = run_amplitudes_xpl(ctx, reqs, fp32c, xpl, s);
+    if (!st) {
+      HIP_TRY(hipEventRecord(e0, s));
+      st = run_amplitudes_xpl(ctx, reqs, fp32c, xpl, s);
+    }
+    if (st) {
+      hipEventDestroy(e0);
+      hipEventDestroy(e1);
+      return st;
+    }
+    HIP_TRY(hipEventRecord(e1, s));
+    HIP_TRY(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    ctx->amp_tune_ms[xpl - 1] = ms;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  best = ctx->amp_tune_ms[0] < ctx->amp_tune_ms[1] ? 1u : 2u;
+  ctx->amp_xpl = best;
+  ctx->amp_tune = false;
   return CHSIM_OK;
 }
 
@@ -1483,6 +1527,17 @@ chsim_status chsim_set_tuning(chsim_ctx* ctx, uint32_t inst, uint32_t knob, int3
       I.plan_valid = false;
       return CHSIM_OK;
     }
+    case CHSIM_TUNE_AMP_STRINGS: {
+      if (value == -1) {
+        ctx->amp_tune = true;
+        return CHSIM_OK;
+      }
+      if (value != 0 && value != 256 && value != 512)
+        return fail(CHSIM_EUNSUPPORTED, "no amplitude kernel for %d bitstrings per work item", value);
+      ctx->amp_tune = false;
+      ctx->amp_xpl = value == 256 ? 1u : 2u;
+      return CHSIM_OK;
+    }
     default:
       return fail(CHSIM_EINVAL, "unknown tuning knob %u", knob);
   }
@@ -1499,6 +1554,14 @@ chsim_status chsim_get_tuning(chsim_ctx* ctx, uint32_t inst, uint32_t knob, int3
     if (timings_ms) {
       timings_ms[0] = I.plan_valid ? (float)I.plan_cut.size() : 0.f;
       timings_ms[1] = I.plan_valid ? (float)I.plan_frac : 1.f;
+    }
+    return CHSIM_OK;
+  }
+  if (knob == CHSIM_TUNE_AMP_STRINGS) {
+    if (value) *value = (int32_t)(256u * ctx->amp_xpl);
+    if (timings_ms) {
+      timings_ms[0] = ctx->amp_tune_ms[0];
+      timings_ms[1] = ctx->amp_tune_ms[1];
     }
     return CHSIM_OK;
   }

@@ -209,15 +209,16 @@ struct AmpRequestPlan {
   uint64_t chi;
 };
 hipError_t launch_amp_prep(const TermsView& T, uint64_t* crow, AmpTerm* cst, hipStream_t st);
-// Cut the requests into work items (sorted by estimated cost, largest first).
-void amp_plan(const std::vector<AmpRequestPlan>& reqs, uint32_t target_items,
+// Cut the requests into work items of 256 xpl bitstrings (xpl = 1 or 2, the
+// bitstrings per lane of the kernel) sorted by estimated cost, largest first.
+void amp_plan(const std::vector<AmpRequestPlan>& reqs, uint32_t target_items, uint32_t xpl,
               std::vector<AmpItem>& items, std::vector<uint32_t>& tiles_per_range,
               std::vector<uint32_t>& n_ranges);
 // Reset the queue counter, run the persistent kernel, reduce.  prefix_d[q] =
 // bitstrings of requests before q (n_inst + 1 entries).
 hipError_t launch_amp_items(const AmpInst* insts_d, const AmpItem* items_d, uint32_t n_items,
-                            uint32_t* counter, bool fp32c, const uint64_t* prefix_d, uint32_t n_inst,
-                            uint64_t total_x, hipStream_t st);
+                            uint32_t* counter, bool fp32c, uint32_t xpl, const uint64_t* prefix_d,
+                            uint32_t n_inst, uint64_t total_x, hipStream_t st);
 
 // Inner products with equatorial states: L states in batches of 64 (Lp =
 // L rounded up), partial sums per term group, and a device workspace of

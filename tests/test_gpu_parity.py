@@ -347,6 +347,32 @@ def test_amplitudes_support_sizes(B, n, k, extra_h, packed):
     assert normwise(a32, ref) < TOL32
 
 
+def test_amplitudes_strings_per_item_and_autotune(B):
+    """256 and 512 bitstrings per work item, and the autotuner's pick, all
+    match the oracle; the autotuner reports both timings."""
+    rng = np.random.default_rng(77)
+    circ = W.random_circuit(30, 600, rng.uniform(0, 2 * np.pi, size=8), rng)
+    spec = dict(circuit=circ, chi=1500, mode="sparsify", seed=9)
+    say("amplitudes strings per item 256 / 512 / autotune")
+    ctx = gpu_ctx(B, spec)
+    T = O.Terms(circ, 1500, O.SPARSIFY, seed=9)
+    alpha = rng.integers(0, 1500, size=700)
+    flips = W.random_bitstrings(30, 700, rng)
+    xs = np.array([T.term(int(a)).sample(int(f)) for a, f in zip(alpha, flips)], np.uint64)
+    ref = T.amplitudes(xs)
+    for v in (256, 512, -1):
+        ctx.set_amp_strings(v)
+        a64 = ctx.amplitudes(xs)
+        a32 = ctx.amplitudes(xs, fp32c=True)
+        assert normwise(a64, ref) < TOL64, v
+        assert normwise(a32, ref) < TOL32, v
+    used, ms = ctx.amp_strings()
+    assert used in (256, 512)
+    assert ms[0] > 0 and ms[1] > 0
+    with pytest.raises(Exception):
+        ctx.set_amp_strings(384)
+
+
 @pytest.mark.slow
 def test_amplitudes_config_full_size_sampled(B):
     """n = 50, chi = 2^16, 4096 strings, the benchmark's launch configuration:
