@@ -174,12 +174,24 @@ __global__ __launch_bounds__(256) void k_evolve_lds(EvolveJob J, const DGate* __
       const uint32_t qbl = hq ? 0u : (1u << qs), qbh = hq ? (1u << qs) : 0u;
       const uint32_t Wl = (uint32_t)W, Wh = (uint32_t)(W >> 32);
       const uint32_t V1l = (uint32_t)V1, V1h = (uint32_t)(V1 >> 32);
+      // When no term of the wave in the V_0 case has W != 0 (|v| close to n
+      // leaves V_0 with at most one bit), R[CX_{q,i}] is empty for all of
+      // them and their rows take only R[CZ_{q,i}] (wave-uniform test).
+      const bool w_empty = __ballot(use0 && W != 0ull) == 0ull;
       auto row = [&](uint32_t j) {
         const uint64_t F = LF[j * 64u], G = LG[j * 64u], M = LM[j * 64u];
         uint32_t Fl = (uint32_t)F, Fh = (uint32_t)(F >> 32);
         uint32_t Gl = (uint32_t)G, Gh = (uint32_t)(G >> 32);
         uint32_t Ml = (uint32_t)M, Mh = (uint32_t)(M >> 32);
-        if (use0) {
+        if (use0 && w_empty) {
+          // R[CZ_{q,i}], i in V_1: M_{.,q} ^= F_{.,i}; M_{.,i} ^= F_{.,q}; gamma += 2 F_{.,q} F_{.,i}.
+          const uint32_t mf = bit_mask(hq ? Fh : Fl, qs);
+          const uint32_t c = (uint32_t)__popc(Fl & V1l) + (uint32_t)__popc(Fh & V1h);
+          const uint32_t mm = bit_mask(c, 0u);
+          Ml ^= (qbl & mm) ^ (V1l & mf);
+          Mh ^= (qbh & mm) ^ (V1h & mf);
+          gw ^= (mf & c & 1u) << (16u + j);
+        } else if (use0) {
           // R[CX_{q,i}], i in W: G_{.,q} ^= G_{.,i}; F_{.,i} ^= F_{.,q}; M_{.,q} ^= M_{.,i}.
           // R[CZ_{q,i}], i in V_1: M_{.,q} ^= F_{.,i}; M_{.,i} ^= F_{.,q}; gamma += 2 F_{.,q} F_{.,i}.
           const uint32_t mf = bit_mask(hq ? Fh : Fl, qs);

@@ -117,7 +117,16 @@ __global__ __launch_bounds__(256) void k_evolve_w64(EvolveJob J, const DGate* __
         uint32_t Fl = (uint32_t)F, Fh = (uint32_t)(F >> 32);
         uint32_t Gl = (uint32_t)G, Gh = (uint32_t)(G >> 32);
         uint32_t Ml = (uint32_t)M, Mh = (uint32_t)(M >> 32);
-        if (use0) {
+        if (use0 && W == 0ull) {
+          // W empty (V_0 = {q}): only R[CZ_{q,i}], i in V_1.
+          const uint32_t V1l = (uint32_t)V1, V1h = (uint32_t)(V1 >> 32);
+          const uint32_t mf = bmask(hq ? Fh : Fl, qs);
+          const uint32_t c = (uint32_t)__popc(Fl & V1l) + (uint32_t)__popc(Fh & V1h);
+          const uint32_t mm = bmask(c, 0u);
+          Ml ^= (qbl & mm) ^ (V1l & mf);
+          Mh ^= (qbh & mm) ^ (V1h & mf);
+          g = (g + 2u * (mf & c & 1u)) & 3u;
+        } else if (use0) {
           // R[CX_{q,i}], i in W: G_{.,q} ^= G_{.,i}; F_{.,i} ^= F_{.,q}; M_{.,q} ^= M_{.,i}.
           // R[CZ_{q,i}], i in V_1: M_{.,q} ^= F_{.,i}; M_{.,i} ^= F_{.,q}; gamma += 2 F_{.,q} F_{.,i}.
           const uint32_t V1l = (uint32_t)V1, V1h = (uint32_t)(V1 >> 32);
