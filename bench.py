@@ -525,7 +525,7 @@ def main():
         dom, ops, ms = f"{'k_evolve_lds' if lanes & B.CHSIM_EVOLVE_LDS else 'k_evolve'}<{lanes & 0xff},...> (CH-form evolution, {shape_name(lanes)})", ops_ev, ms_ev
         traffic = counter_traffic("k_evolve_lds" if lanes & B.CHSIM_EVOLVE_LDS else "k_evolve")
     else:
-        dom, ops, ms = "k_amp<float> + k_reduce_ranges (amplitudes, FP32C)", ops_amp, ms_amp
+        dom, ops, ms = f"k_amp<float, {amp_strings // 256}> + k_reduce_ranges (amplitudes, FP32C)", ops_amp, ms_amp
         traffic = counter_traffic("k_amp<float>")
     achieved = ops / (ms / 1e3) / 1e12
     roofline = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3),
@@ -567,7 +567,8 @@ def main():
         "evolve_gates_per_s": chi * circ.n_gates / (ms_ev / 1e3),
         "fp32c_vs_fp64_normwise": fp32c_vs_fp64,
         "roofline": roofline,
-        "amplitude_roofline": {"bound": "lds", "kernel": "k_amp<float> (with k_amp_prep, k_reduce_ranges)",
+        "amplitude_roofline": {"bound": "lds",
+                               "kernel": f"k_amp<float, {amp_strings // 256}> (with k_amp_prep, k_reduce_ranges)",
                                "achieved": round(lds_pair * chi * n_x / (ms_amp / 1e3) / 1e12, 3),
                                "peak": round(LDS_PEAK_BPS / 1e12, 2), "unit": "TB/s (LDS table reads)",
                                "frac": round(lds_pair * chi * n_x / (ms_amp / 1e3) / LDS_PEAK_BPS, 4),
