@@ -267,6 +267,7 @@ __global__ __launch_bounds__(kPThreads) void k_propose(TermsView T, MetroView Mv
 constexpr uint32_t kGWaves = 4;
 constexpr uint32_t kGSub = kMetroTile / 64;  // 64-term sub-tiles per tile
 
+template <int CP>
 __global__ __launch_bounds__(64 * kGWaves) void k_propose_gather(TermsView T, MetroView Mv,
                                                                  uint32_t step) {
   const uint32_t lane = threadIdx.x & 63u, wave = uniform32(threadIdx.x >> 6);
@@ -282,36 +283,53 @@ __global__ __launch_bounds__(64 * kGWaves) void k_propose_gather(TermsView T, Me
     c[sb] = TermAmpConst{};
     if (live[sb]) c[sb] = load_const(T, a);
   }
-  for (uint32_t ch = wave; ch < Mv.n_chain; ch += kGWaves) {
-    const uint64_t m = 1ull << (uniform32(Mv.jstream[(uint64_t)ch * Mv.n_steps + step]) % n);
-    const uint32_t cur = uniform32(Mv.parity[ch]);
-    double re = 0.0, im = 0.0;
-    {
-      uint64_t st[kGSub];
+  // CP chains per pass: all their state words and rows are requested before
+  // any is combined (more loads in flight when the grid is small).
+  for (uint32_t c0 = wave; c0 < Mv.n_chain; c0 += (uint32_t)CP * kGWaves) {
+    uint64_t st[CP][kGSub], Fr[CP][kGSub], Mr[CP][kGSub];
+    uint32_t gr[CP][kGSub], cur[CP];
 #pragma unroll
-      for (uint32_t sb = 0; sb < kGSub; ++sb)
-        st[sb] = live[sb] ? Mv.state[cur][(uint64_t)ch * chi + tile0 + sb * 64u + lane] : 0ull;
+    for (int h = 0; h < CP; ++h) {
+      const bool on = c0 + (uint32_t)h * kGWaves < Mv.n_chain;  // wave-uniform
+      const uint32_t ch = on ? c0 + (uint32_t)h * kGWaves : c0;
+      const uint32_t j = uniform32(Mv.jstream[(uint64_t)ch * Mv.n_steps + step]) % n;
+      cur[h] = uniform32(Mv.parity[ch]);
+#pragma unroll
+      for (uint32_t sb = 0; sb < kGSub; ++sb) {
+        const uint64_t a = tile0 + sb * 64u + lane;
+        const bool ld = on && live[sb];
+        const uint64_t off = (uint64_t)j * chi + a;
+        st[h][sb] = ld ? Mv.state[cur[h]][(uint64_t)ch * chi + a] : 0ull;
+        Fr[h][sb] = ld ? T.F[off] : 0ull;
+        Mr[h][sb] = ld ? T.M[off] : 0ull;
+        gr[h][sb] = ld ? (uint32_t)T.gamma[off] : 0u;
+      }
+    }
+#pragma unroll
+    for (int h = 0; h < CP; ++h) {
+      const uint32_t ch = c0 + (uint32_t)h * kGWaves;
+      if (ch >= Mv.n_chain) break;
+      double re = 0.0, im = 0.0;
 #pragma unroll
       for (uint32_t sb = 0; sb < kGSub; ++sb) {
         if (!live[sb]) continue;
         const uint64_t a = tile0 + sb * 64u + lane;
-        uint64_t u = st[sb] & kUMask;
-        uint32_t mu = (uint32_t)(st[sb] >> 62);
-        const uint64_t off = (uint64_t)__builtin_ctzll(m) * chi + a;
-        u ^= T.F[off];
-        mu += (uint32_t)T.gamma[off] + 2u * par64(u & T.M[off]);
+        uint64_t u = st[h][sb] & kUMask;
+        uint32_t mu = (uint32_t)(st[h][sb] >> 62);
+        u ^= Fr[h][sb];
+        mu += gr[h][sb] + 2u * par64(u & Mr[h][sb]);
         mu &= 3u;
-        Mv.state[cur ^ 1u][(uint64_t)ch * chi + a] = u | ((uint64_t)mu << 62);
+        Mv.state[cur[h] ^ 1u][(uint64_t)ch * chi + a] = u | ((uint64_t)mu << 62);
         const double2 val = term_value(c[sb], u, mu);
         re += val.x;
         im += val.y;
       }
+      for (int o = 32; o >= 1; o >>= 1) {
+        re += __shfl_xor(re, o);
+        im += __shfl_xor(im, o);
+      }
+      if (lane == 0) Mv.partial[(uint64_t)ch * Mv.n_tiles + blockIdx.x] = make_double2(re, im);
     }
-    for (int o = 32; o >= 1; o >>= 1) {
-      re += __shfl_xor(re, o);
-      im += __shfl_xor(im, o);
-    }
-    if (lane == 0) Mv.partial[(uint64_t)ch * Mv.n_tiles + blockIdx.x] = make_double2(re, im);
   }
 }
 
@@ -321,7 +339,11 @@ template <bool kSingle>
 hipError_t launch_propose_t(const TermsView& T, MetroView& Mv, const uint64_t* mask, uint32_t step,
                             hipStream_t st) {
   if (kSingle) {
-    hipLaunchKernelGGL(k_propose_gather, dim3(Mv.n_tiles), dim3(64 * kGWaves), 0, st, T, Mv, step);
+    // Small grids (fewer than 2048 tiles) take two chains per pass per wave.
+    if (Mv.n_tiles < 2048u)
+      hipLaunchKernelGGL(k_propose_gather<2>, dim3(Mv.n_tiles), dim3(64 * kGWaves), 0, st, T, Mv, step);
+    else
+      hipLaunchKernelGGL(k_propose_gather<1>, dim3(Mv.n_tiles), dim3(64 * kGWaves), 0, st, T, Mv, step);
     return hipGetLastError();
   }
   const size_t sm = (size_t)T.n * kSub * 17;
