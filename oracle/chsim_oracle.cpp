@@ -44,6 +44,7 @@
 //   * Exponential sum outputs Re and Im as 0 or +-2^e (signs in {-1,0,1}).
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <complex>
 #include <cstdint>
@@ -359,7 +360,7 @@ struct CH {
 };
 
 // Gate codes of the circuit interface.
-enum { OP_H = 0, OP_S = 1, OP_CX = 2, OP_CZ = 3, OP_SLOT = 4 };
+enum { OP_H = 0, OP_S = 1, OP_CX = 2, OP_CZ = 3, OP_SLOT = 4, OP_CCZ = 5 };
 
 static int ch_apply(CH& c, int op, int q, int r) {
   if (q < 0 || q >= c.n) return 1;
@@ -399,10 +400,48 @@ static void phase_decomp(double theta, cplx* c0, cplx* c1, int* k) {
 // random Omega = (||c||_1 / k) sum_alpha omega_alpha (Eq. (Omega)).
 // ---------------------------------------------------------------------------
 struct Slot {
-  int qubit;
-  cplx c[2];
-  int spow[2];  // S power applied by each branch
+  int nb = 0;                                // number of branches j
+  cplx c[8];                                 // coefficient c_j
+  std::vector<std::array<int, 3>> k[8];      // Clifford K_j as (op, q, r), applied in order
 };
+
+// Slot for diag(1, e^{i theta}) on qubit q: branch 0 = S^k, branch 1 = S^{k+1}.
+static void phase_slot(double theta, int q, Slot* sl) {
+  int k;
+  phase_decomp(theta, &sl->c[0], &sl->c[1], &k);
+  sl->nb = 2;
+  for (int j = 0; j < 2; ++j) {
+    sl->k[j].clear();
+    for (int a = 0; a < (k + j) % 4; ++a) sl->k[j].push_back({OP_S, q, 0});
+  }
+}
+
+// CCZ on qubits (a, b, c) by the lifting lemma, Eq. (CCZ decomposition):
+// CCZ = (1/6) [ I + CZ_ab + CZ_ac + CZ_bc + CZ_ab CZ_ac Z_a + CZ_ab CZ_bc Z_b
+//               + CZ_ac CZ_bc Z_c - CZ_ab CZ_ac CZ_bc Z_a Z_b Z_c ],
+// branches in that order, Z = S S.  The paper prints the prefactor 2/9; with
+// 2/9 the sum is 4/3 on |000>, while 1/6 gives CCZ exactly and
+// ||c||_1^2 = (8/6)^2 = 16/9, the paper's value of xi(CCZ), and matches its
+// state decomposition |CCZ> = (1/6) sum_Q Q |+++>.
+static void ccz_slot(int a, int b, int c, Slot* sl) {
+  sl->nb = 8;
+  const int pair[3][2] = {{a, b}, {a, c}, {b, c}};
+  // cz[j]: which of the pairs (ab, ac, bc) branch j applies; zq[j]: qubits with Z.
+  const int cz[8] = {0, 1, 2, 4, 1 | 2, 1 | 4, 2 | 4, 1 | 2 | 4};
+  const int zq[8][3] = {{-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1},
+                        {a, -1, -1},  {b, -1, -1},  {c, -1, -1},  {a, b, c}};
+  for (int j = 0; j < 8; ++j) {
+    sl->c[j] = cplx(j == 7 ? -1.0 / 6.0 : 1.0 / 6.0, 0.0);
+    sl->k[j].clear();
+    for (int e = 0; e < 3; ++e)
+      if (cz[j] >> e & 1) sl->k[j].push_back({OP_CZ, pair[e][0], pair[e][1]});
+    for (int e = 0; e < 3; ++e)
+      if (zq[j][e] >= 0) {
+        sl->k[j].push_back({OP_S, zq[j][e], 0});
+        sl->k[j].push_back({OP_S, zq[j][e], 0});
+      }
+  }
+}
 
 struct Terms {
   int n = 0;
@@ -423,10 +462,13 @@ static void choose_branches(const Terms& T, uint64_t alpha, std::vector<uint8_t>
   size_t m = T.slots.size();
   br.assign(m, 0);
   if (T.mode == 0) {
-    // Exact expansion: alpha's binary digits pick the branch of each slot.
+    // Exact expansion: alpha's digits in the mixed radix (nb_0, nb_1, ...),
+    // slot 0 least significant, pick the branch of each slot; b = prod_p c_j.
     b = 1.0;
+    uint64_t rem = alpha;
     for (size_t p = 0; p < m; ++p) {
-      br[p] = (uint8_t)((alpha >> p) & 1);
+      br[p] = (uint8_t)(rem % (uint64_t)T.slots[p].nb);
+      rem /= (uint64_t)T.slots[p].nb;
       b *= T.slots[p].c[br[p]];
     }
   } else {
@@ -436,14 +478,20 @@ static void choose_branches(const Terms& T, uint64_t alpha, std::vector<uint8_t>
     cplx ph = 1.0;
     for (size_t p = 0; p < m; ++p) {
       const Slot& sl = T.slots[p];
-      double w0 = std::sqrt(sl.c[0].real() * sl.c[0].real() + sl.c[0].imag() * sl.c[0].imag());
-      double w1 = std::sqrt(sl.c[1].real() * sl.c[1].real() + sl.c[1].imag() * sl.c[1].imag());
-      double W = w0 + w1;
+      double w[8], W = 0.0;
+      for (int j = 0; j < sl.nb; ++j) {
+        w[j] = std::sqrt(sl.c[j].real() * sl.c[j].real() + sl.c[j].imag() * sl.c[j].imag());
+        W += w[j];
+      }
       double u = uniform53(T.seed, alpha, (uint32_t)p, kStreamSparsify);
-      int j = (u * W < w0) ? 0 : 1;
+      int j = sl.nb - 1;
+      double cum = 0.0;
+      for (int i = 0; i + 1 < sl.nb; ++i) {
+        cum += w[i];
+        if (u * W < cum) { j = i; break; }
+      }
       br[p] = (uint8_t)j;
-      double wj = j ? w1 : w0;
-      ph *= sl.c[j] / wj;
+      ph *= sl.c[j] / w[j];
     }
     b = (T.l1 / (double)T.chi) * ph;
   }
@@ -453,10 +501,12 @@ static void evolve_term(const Terms& T, const std::vector<uint8_t>& br, CH& c, i
   c.reset();
   size_t slot = 0;
   for (size_t g = 0; g < T.op.size(); ++g) {
-    if (T.op[g] == OP_SLOT) {
-      const Slot& sl = T.slots[slot];
-      int pw = sl.spow[br[slot]];
-      for (int a = 0; a < pw; ++a) c.L_S(sl.qubit);
+    if (T.op[g] == OP_SLOT || T.op[g] == OP_CCZ) {
+      for (const auto& k : T.slots[slot].k[br[slot]])
+        if (ch_apply(c, k[0], k[1], k[2])) {
+          *err = 1;
+          return;
+        }
       ++slot;
     } else if (ch_apply(c, T.op[g], T.q[g], T.r[g])) {
       *err = 1;
@@ -736,11 +786,13 @@ void orc_expsum(int N, const uint8_t* B, int* out4) {
 }
 
 // ---- sum-over-Cliffords terms ----
-// Circuit: n_gates entries (op, q, r); SLOT entries consume theta[] in order.
+// Circuit: n_gates entries (op, q, r, t).  Slots are the SLOT entries (phase
+// gate on q, consuming theta[] in order) and the CCZ entries (qubits q, r, t),
+// numbered together in circuit order; a CCZ slot's theta entry is unused.
 // alphas: the term indices to build (NULL = all chi terms).
 void* orc_terms_build(int n, int n_gates, const uint8_t* op, const uint8_t* q, const uint8_t* r,
-                      int n_slot, const double* theta, uint64_t chi, int mode, uint64_t seed,
-                      const uint64_t* alphas, uint64_t n_alpha, int threads) {
+                      const uint8_t* t, int n_slot, const double* theta, uint64_t chi, int mode,
+                      uint64_t seed, const uint64_t* alphas, uint64_t n_alpha, int threads) {
   Terms* T = new Terms();
   T->n = n;
   T->chi = chi;
@@ -751,23 +803,31 @@ void* orc_terms_build(int n, int n_gates, const uint8_t* op, const uint8_t* q, c
     T->op.push_back(op[g]);
     T->q.push_back(q[g]);
     T->r.push_back(r[g]);
-    if (op[g] == OP_SLOT) {
+    if (op[g] == OP_SLOT || op[g] == OP_CCZ) {
       if (slot_seen >= n_slot) { T->error = 1; return T; }
       Slot sl;
-      sl.qubit = q[g];
-      int k;
-      phase_decomp(theta[slot_seen], &sl.c[0], &sl.c[1], &k);
-      sl.spow[0] = k;
-      sl.spow[1] = (k + 1) % 4;
+      if (op[g] == OP_SLOT) {
+        phase_slot(theta[slot_seen], q[g], &sl);
+      } else {
+        int a = q[g], b = r[g], c = t ? t[g] : 0;
+        if (a >= n || b >= n || c >= n || a == b || a == c || b == c) { T->error = 1; return T; }
+        ccz_slot(a, b, c, &sl);
+      }
       T->slots.push_back(sl);
       ++slot_seen;
     }
   }
   if (slot_seen != n_slot) { T->error = 1; return T; }
   double l1 = 1.0;
-  for (const Slot& sl : T->slots) l1 *= std::abs(sl.c[0]) + std::abs(sl.c[1]);
+  long double prod = 1.0L;
+  for (const Slot& sl : T->slots) {
+    double W = 0.0;
+    for (int j = 0; j < sl.nb; ++j) W += std::abs(sl.c[j]);
+    l1 *= W;
+    prod *= (long double)sl.nb;
+  }
   T->l1 = l1;
-  if (mode == 0 && (n_slot >= 64 || chi != ((uint64_t)1 << n_slot))) { T->error = 2; return T; }
+  if (mode == 0 && prod != (long double)chi) { T->error = 2; return T; }
   uint64_t cnt = alphas ? n_alpha : chi;
   T->index.resize(cnt);
   for (uint64_t i = 0; i < cnt; ++i) T->index[i] = alphas ? alphas[i] : i;
@@ -783,6 +843,27 @@ void* orc_terms_build(int n, int n_gates, const uint8_t* op, const uint8_t* q, c
   for (uint64_t i = 0; i < cnt; ++i)
     if (errs[i]) T->error = 3;
   return T;
+}
+// The CCZ decomposition table: coeff[2j], coeff[2j+1] = (re, im) of c_j; branch j
+// is gates[off[j] .. off[j+1]) with gate i = (op, q, r) in gates[3i .. 3i+2].
+// Returns the total gate count (gates must hold 3 * 32 ints).
+int orc_ccz_decomp(int a, int b, int c, double* coeff, uint32_t* off, int32_t* gates) {
+  Slot sl;
+  ccz_slot(a, b, c, &sl);
+  int cnt = 0;
+  off[0] = 0;
+  for (int j = 0; j < sl.nb; ++j) {
+    coeff[2 * j] = sl.c[j].real();
+    coeff[2 * j + 1] = sl.c[j].imag();
+    for (const auto& k : sl.k[j]) {
+      gates[3 * cnt] = k[0];
+      gates[3 * cnt + 1] = k[1];
+      gates[3 * cnt + 2] = k[2];
+      ++cnt;
+    }
+    off[j + 1] = (uint32_t)cnt;
+  }
+  return cnt;
 }
 void orc_terms_free(void* h) { delete (Terms*)h; }
 int orc_terms_error(void* h) { return ((Terms*)h)->error; }

@@ -51,8 +51,10 @@ def lib():
     L.orc_ch_inner.argtypes = [C.c_void_p, u64p, u8p, C.POINTER(C.c_int), C.POINTER(C.c_int)]
     L.orc_phase_decomp.argtypes = [C.c_double, f64p, C.POINTER(C.c_int)]
     L.orc_expsum.argtypes = [C.c_int, u8p, i32p]
-    L.orc_terms_build.argtypes = [C.c_int, C.c_int, u8p, u8p, u8p, C.c_int, f64p, C.c_uint64,
+    L.orc_terms_build.argtypes = [C.c_int, C.c_int, u8p, u8p, u8p, u8p, C.c_int, f64p, C.c_uint64,
                                   C.c_int, C.c_uint64, C.c_void_p, C.c_uint64, C.c_int]
+    L.orc_ccz_decomp.argtypes = [C.c_int, C.c_int, C.c_int, f64p, u32p, i32p]
+    L.orc_ccz_decomp.restype = C.c_int
     L.orc_terms_build.restype = C.c_void_p
     L.orc_terms_free.argtypes = [C.c_void_p]
     L.orc_terms_error.argtypes = [C.c_void_p]
@@ -179,6 +181,20 @@ def phase_decomp(theta: float):
     return complex(c[0], c[1]), complex(c[2], c[3]), k.value
 
 
+def ccz_decomp(a: int, b: int, c: int):
+    """CCZ_{abc} = sum_j c_j K_j by the lifting lemma, Eq. (CCZ decomposition).
+
+    Returns (coeffs, branches): coeffs[j] complex, branches[j] the list of
+    (op, q, r) gates of K_j in order."""
+    coeff = np.zeros(16)
+    off = np.zeros(9, np.uint32)
+    gates = np.zeros(96, np.int32)
+    lib().orc_ccz_decomp(int(a), int(b), int(c), coeff, off, gates)
+    g = gates.reshape(-1, 3)
+    branches = [[tuple(int(v) for v in g[i]) for i in range(off[j], off[j + 1])] for j in range(8)]
+    return coeff[0::2] + 1j * coeff[1::2], branches
+
+
 def expsum(B: np.ndarray):
     """Z(B) = sum_x i^{x B x^T} as (re_sign, re_exp, im_sign, im_exp); Lemma (Exponential Sum)."""
     B = np.ascontiguousarray(B, np.uint8)
@@ -210,6 +226,7 @@ class Terms:
         op = np.ascontiguousarray(circuit.op, np.uint8)
         q = np.ascontiguousarray(circuit.q, np.uint8)
         r = np.ascontiguousarray(circuit.r, np.uint8)
+        t = np.ascontiguousarray(circuit.third(), np.uint8)
         th = np.ascontiguousarray(circuit.theta, np.float64)
         if th.size == 0:
             th = np.zeros(1)
@@ -219,7 +236,7 @@ class Terms:
         else:
             self._alphas = np.ascontiguousarray(alphas, np.uint64)
             ap, na = self._alphas.ctypes.data_as(C.c_void_p), self._alphas.size
-        self._h = lib().orc_terms_build(circuit.n, op.size, op, q, r, int(circuit.theta.size), th,
+        self._h = lib().orc_terms_build(circuit.n, op.size, op, q, r, t, int(circuit.theta.size), th,
                                         int(chi), int(mode), int(seed), ap, na, threads)
         err = lib().orc_terms_error(self._h)
         if err:

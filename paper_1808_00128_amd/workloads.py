@@ -15,7 +15,9 @@ Shapes follow the paper's workloads:
 
 Conventions: qubit p is bit p of a uint64 bitstring.  Gate codes:
 H=0, S=1, CX=2 (q = control, r = target), CZ=3, SLOT=4 (phase gate on q,
-angle theta[slot], slots numbered in circuit order).
+angle theta[slot]), CCZ=5 (doubly controlled Z on q, r, t).  SLOT and CCZ
+entries are the circuit's non-Clifford slots, numbered together in circuit
+order; a CCZ slot's theta entry is unused (0).
 """
 from __future__ import annotations
 
@@ -23,8 +25,8 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-OP_H, OP_S, OP_CX, OP_CZ, OP_SLOT = 0, 1, 2, 3, 4
-OP_NAMES = {OP_H: "H", OP_S: "S", OP_CX: "CX", OP_CZ: "CZ", OP_SLOT: "SLOT"}
+OP_H, OP_S, OP_CX, OP_CZ, OP_SLOT, OP_CCZ = 0, 1, 2, 3, 4, 5
+OP_NAMES = {OP_H: "H", OP_S: "S", OP_CX: "CX", OP_CZ: "CZ", OP_SLOT: "SLOT", OP_CCZ: "CCZ"}
 
 
 @dataclass
@@ -34,6 +36,7 @@ class Circuit:
     q: np.ndarray   # uint8
     r: np.ndarray   # uint8
     theta: np.ndarray = field(default_factory=lambda: np.zeros(0))  # float64, one per slot
+    t: np.ndarray = field(default_factory=lambda: np.zeros(0, np.uint8))  # third qubit of CCZ (else 0)
 
     @property
     def n_slot(self) -> int:
@@ -43,12 +46,24 @@ class Circuit:
     def n_gates(self) -> int:
         return int(self.op.size)
 
+    def third(self) -> np.ndarray:
+        """Third qubit of every gate (0 where the gate has none)."""
+        return self.t if self.t.size == self.op.size else np.zeros(self.op.size, np.uint8)
+
+    def slot_ops(self) -> np.ndarray:
+        """Op code (SLOT or CCZ) of each slot, in slot order."""
+        return self.op[(self.op == OP_SLOT) | (self.op == OP_CCZ)]
+
     def gates(self):
-        """Iterate (op, q, r, theta_or_None)."""
+        """Iterate (op, q, r, extra): extra is theta for SLOT, the third qubit
+        for CCZ, None otherwise."""
         k = 0
-        for o, a, b in zip(self.op.tolist(), self.q.tolist(), self.r.tolist()):
+        for o, a, b, c in zip(self.op.tolist(), self.q.tolist(), self.r.tolist(), self.third().tolist()):
             if o == OP_SLOT:
                 yield o, a, b, float(self.theta[k])
+                k += 1
+            elif o == OP_CCZ:
+                yield o, a, b, int(c)
                 k += 1
             else:
                 yield o, a, b, None
@@ -59,16 +74,19 @@ def _arr(lst, dt=np.uint8):
 
 
 def from_list(n: int, gates) -> Circuit:
-    """Build a Circuit from (op, q, r[, theta]) tuples."""
-    op, q, r, th = [], [], [], []
+    """Build a Circuit from (op, q, r[, theta]) tuples; a CCZ is (CCZ, q, r, t)."""
+    op, q, r, t, th = [], [], [], [], []
     for g in gates:
         o = g[0]
         op.append(o)
         q.append(g[1])
         r.append(g[2] if len(g) > 2 and g[2] is not None else 0)
+        t.append(g[3] if o == OP_CCZ else 0)
         if o == OP_SLOT:
             th.append(g[3])
-    return Circuit(n, _arr(op), _arr(q), _arr(r), np.asarray(th, np.float64))
+        elif o == OP_CCZ:
+            th.append(0.0)
+    return Circuit(n, _arr(op), _arr(q), _arr(r), np.asarray(th, np.float64), _arr(t))
 
 
 def random_clifford_gates(n: int, count: int, rng: np.random.Generator, ops=(OP_H, OP_S, OP_CX, OP_CZ)):
@@ -219,6 +237,60 @@ def config_qaoa(seed: int = 1004, n: int = 50, n_triples: int = 60, chi: int = 1
     return dict(name=f"qaoa-n{n}-chi{chi}-chains{n_chain}x{steps}", circuit=circ, chi=chi,
                 mode="sparsify", triples=triples, d=d, gamma=gamma, beta=beta, jstream=j,
                 ustream=u, seed=seed, n_chain=n_chain, steps=steps)
+
+
+def hidden_shift_circuit(n: int, n_ccz: int, rng: np.random.Generator, n_cz: int | None = None,
+                         n_z: int | None = None) -> tuple:
+    """Hidden shift for a Maiorana-McFarland bent function (Sec. "The hidden
+    shift algorithm"; Roetteler's construction), with CCZ as the non-Clifford gate.
+
+    n = 2m qubits: x = qubits 0..m-1, y = qubits m..2m-1.  f(x, y) = x.y + g(y)
+    with g a random cubic form: n_ccz / 2 products y_a y_b y_c (CCZ), n_cz
+    products y_a y_b (CZ) and n_z linear terms (Z = S S).  Its dual is
+    f~(x, y) = x.y + g(x).  Circuit: H^n, X^s O_f X^s, H^n, O_f~, H^n (X = H S S H),
+    whose output is exactly |s>.  Returns (circuit, s) with s a uint64."""
+    if n % 2 or n < 6 or n_ccz % 2:
+        raise ValueError("hidden shift needs even n >= 6 and an even CCZ count")
+    m = n // 2
+    n_cz = m if n_cz is None else n_cz
+    n_z = m // 2 if n_z is None else n_z
+    triples = [tuple(sorted(rng.choice(m, size=3, replace=False).tolist())) for _ in range(n_ccz // 2)]
+    pairs = [tuple(sorted(rng.choice(m, size=2, replace=False).tolist())) for _ in range(n_cz)]
+    lin = rng.integers(0, m, size=n_z).tolist()
+    s_bits = rng.integers(0, 2, size=n).tolist()
+    s = sum(int(b) << i for i, b in enumerate(s_bits))
+
+    def g_on(base):
+        out = [(OP_CCZ, base + a, base + b, base + c) for a, b, c in triples]
+        out += [(OP_CZ, base + a, base + b) for a, b in pairs]
+        for a in lin:
+            out += [(OP_S, base + a, 0), (OP_S, base + a, 0)]
+        return out
+
+    def x_shift():
+        out = []
+        for i, b in enumerate(s_bits):
+            if b:
+                out += [(OP_H, i, 0), (OP_S, i, 0), (OP_S, i, 0), (OP_H, i, 0)]
+        return out
+
+    inner = [(OP_CZ, i, m + i) for i in range(m)]
+    hs = [(OP_H, i, 0) for i in range(n)]
+    gates = hs + x_shift() + g_on(m) + inner + x_shift() + hs + g_on(0) + inner + hs
+    return from_list(n, gates), s
+
+
+def config_hidden_shift(seed: int = 1006, n: int = 40, n_ccz: int = 16, delta: float = 0.3,
+                        n_x: int = 4096) -> dict:
+    """n = 40 hidden-shift circuit with n_ccz CCZ gates, sparsified with the
+    paper's term count for target error delta, chi = floor(((3/4)^-u / delta)^2);
+    the bitstrings are s followed by n_x - 1 uniform strings."""
+    rng = np.random.default_rng(seed)
+    circ, s = hidden_shift_circuit(n, n_ccz, rng)
+    chi = int(np.floor(((4.0 / 3.0) ** n_ccz / delta) ** 2))
+    x = np.concatenate([np.asarray([s], np.uint64), random_bitstrings(n, n_x - 1, rng)])
+    return dict(name=f"hidden-shift-n{n}-ccz{n_ccz}-chi{chi}-x{n_x}", circuit=circ, chi=chi,
+                mode="sparsify", x=x, s=s, seed=seed, n_ccz=n_ccz, delta=delta)
 
 
 def config_uneven(seed: int = 1005, n_inst: int = 64, n_x: int = 1024, chi_lo: int = 10,

@@ -5,7 +5,7 @@ the basis index, gates applied by index arithmetic.
 """
 import numpy as np
 
-from paper_1808_00128_amd.workloads import OP_CX, OP_CZ, OP_H, OP_S, OP_SLOT
+from paper_1808_00128_amd.workloads import OP_CCZ, OP_CX, OP_CZ, OP_H, OP_S, OP_SLOT
 
 
 def zero_state(n):
@@ -30,6 +30,10 @@ def apply(psi, n, op, q, r=0, theta=None):
         return psi[idx ^ (bq << r)]
     if op == OP_SLOT:
         return psi * np.where(bq == 1, np.exp(1j * theta), 1.0)
+    if op == OP_CCZ:  # theta carries the third qubit
+        br = (idx >> r) & 1
+        bt = (idx >> theta) & 1
+        return psi * np.where((bq & br & bt) == 1, -1.0, 1.0)
     raise ValueError(op)
 
 

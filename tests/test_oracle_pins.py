@@ -457,3 +457,104 @@ def test_metropolis_acceptance_ratio():
             assert trace[0, 0] == (y if expect else x0)
             checked += 1
     assert checked >= 40
+
+
+# ---------------------------------------------------------------------------
+# CCZ by the lifting lemma, Eq. (CCZ decomposition), and hidden-shift circuits
+# (Sec. "The hidden shift algorithm").
+# ---------------------------------------------------------------------------
+def _golden(name):
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "ccz_constants.json")) as f:
+        v = json.load(f)[name]["value"]
+    return v[0] / v[1]
+
+
+def _diag_of(n, gates):
+    """Diagonal of a diagonal Clifford circuit, by the dense simulator on the all-ones vector."""
+    d = np.ones(2**n, np.complex128)
+    for g in gates:
+        d = dense.apply(d, n, g[0], g[1], g[2])
+    return d
+
+
+@pytest.mark.parametrize("qubits", [(0, 1, 2), (4, 1, 3), (2, 0, 1)])
+def test_ccz_decomposition_is_exact(qubits):
+    n = 5
+    a, b, c = qubits
+    coeff, branches = O.ccz_decomp(a, b, c)
+    assert len(branches) == 8
+    total = np.zeros(2**n, np.complex128)
+    for cj, K in zip(coeff, branches):
+        assert all(op in (OP_S, OP_CZ) for op, _, _ in K)  # diagonal Cliffords only
+        total += cj * _diag_of(n, K)
+    want = dense.apply(np.ones(2**n, np.complex128), n, W.OP_CCZ, a, b, c)  # textbook CCZ
+    np.testing.assert_allclose(total, want, atol=1e-15)
+
+
+def test_ccz_extent_and_fidelity_match_paper():
+    coeff, _ = O.ccz_decomp(0, 1, 2)
+    l1 = np.sum(np.abs(coeff))
+    assert abs(l1**2 - _golden("ccz_extent")) < 1e-14
+    assert abs(np.abs(coeff[0]) - _golden("ccz_state_decomposition_coefficient")) < 1e-15
+    plus = np.full(8, 1 / np.sqrt(8))
+    ccz = dense.apply(plus.astype(np.complex128), 3, W.OP_CCZ, 0, 1, 2)
+    ov = np.vdot(plus, ccz)
+    assert abs(ov - _golden("ccz_plus_overlap")) < 1e-15
+    assert abs(abs(ov) ** 2 - _golden("ccz_stabilizer_fidelity")) < 1e-15
+    # xi(CCZ) = 1 / F(CCZ) for this Clifford magic state
+    assert abs(l1**2 * _golden("ccz_stabilizer_fidelity") - 1.0) < 1e-14
+
+
+@pytest.mark.parametrize("n,u,seed", [(6, 2, 0), (10, 4, 1), (12, 2, 2), (8, 4, 3)])
+def test_hidden_shift_exact_sum_returns_the_shift(n, u, seed):
+    rng = np.random.default_rng(seed)
+    circ, s = W.hidden_shift_circuit(n, u, rng)
+    psi = dense.run(circ)
+    assert abs(psi[s] - 1.0) < 1e-12  # the algorithm's output is exactly |s>
+    T = O.Terms(circ, 8**u, O.EXACT)
+    assert abs(T.l1 - (4.0 / 3.0) ** u) < 1e-12
+    amps = T.amplitudes(np.arange(2**n, dtype=np.uint64))
+    want = np.zeros(2**n, np.complex128)
+    want[s] = 1.0
+    np.testing.assert_allclose(amps, want, atol=1e-12)
+
+
+def test_mixed_slots_exact_sum_matches_dense():
+    """Phase slots and CCZ slots in one circuit: mixed-radix exact enumeration."""
+    rng = np.random.default_rng(11)
+    n = 6
+    g = W.random_clifford_gates(n, 60, rng)
+    gates = g[:20] + [(W.OP_CCZ, 0, 3, 5)] + g[20:40] + [(OP_SLOT, 2, 0, 0.7)] + g[40:] + [
+        (W.OP_CCZ, 4, 1, 2), (OP_SLOT, 5, 0, -2.1)]
+    circ = W.from_list(n, gates)
+    T = O.Terms(circ, 8 * 2 * 8 * 2, O.EXACT)
+    amps = T.amplitudes(np.arange(2**n, dtype=np.uint64))
+    np.testing.assert_allclose(amps, dense.run(circ), atol=1e-12)
+    with pytest.raises(ValueError):
+        O.Terms(circ, 2**4, O.EXACT)  # chi must be the product of the branch counts
+
+
+def test_ccz_sparsified_branch_law_and_error_bound():
+    """Sparsification (Lemma (Sparsification)) with 8-branch slots: branch j is
+    drawn with probability |c_j| / ||c||_1 (1/8 each) and E||Omega - psi||^2 <=
+    ||c||_1^2 / k for normalised psi."""
+    rng = np.random.default_rng(4)
+    n, u = 10, 4
+    circ, s = W.hidden_shift_circuit(n, u, rng)
+    chi = 4096
+    T = O.Terms(circ, chi, O.SPARSIFY, seed=99)
+    br = np.stack([T.branch(i) for i in range(chi)])
+    for p in range(u):
+        cnt = np.bincount(br[:, p], minlength=8)
+        assert np.all(np.abs(cnt - chi / 8) < 5 * np.sqrt(chi * (1 / 8) * (7 / 8)))
+    # b_alpha = (||c||_1 / chi) * prod sign: the last branch carries the minus sign
+    for i in range(64):
+        sign = (-1) ** int(np.sum(br[i] == 7))
+        assert abs(T.b(i) - sign * T.l1 / chi) < 1e-15
+    amps = T.amplitudes(np.arange(2**n, dtype=np.uint64))
+    psi = dense.run(circ)
+    err2 = np.sum(np.abs(amps - psi) ** 2)
+    assert err2 < 5 * T.l1**2 / chi
+    assert abs(amps[s] - 1.0) < 0.2
