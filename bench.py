@@ -414,6 +414,80 @@ def bench_uneven(torch, B, W, steps=2, warmup=1):
             "finite": ok}
 
 
+def bench_hidden_shift(torch, B, W, steps=5, warmup=2):
+    """Hidden-shift circuit with CCZ gates (n = 40, 16 CCZ, chi = floor(((4/3)^16 /
+    0.3)^2) sparsified terms): each CCZ is a slot of eight diagonal Clifford
+    branches (Eq. (CCZ decomposition)).  Strings: s and 4095 draws from the
+    terms' own output distributions (uniform strings would give exactly zero
+    amplitude for nearly every term).  Times evolution, FP32C and FP64 amplitudes."""
+    cfg = W.config_hidden_shift()
+    circ = cfg["circuit"]
+    n, chi = circ.n, cfg["chi"]
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    ctx = B.Context([cfg])
+    ctx.set_evolve_lanes(-1)
+    ctx.set_amp_strings(-1)
+    gates = B.gate_array(circ)
+    ctx.apply_gates(gates)
+    rng = np.random.default_rng(cfg["seed"] + 1)
+    n_x = cfg["x"].size
+    alpha = rng.integers(0, chi, size=n_x - 1).astype(np.uint64)
+    xs = np.concatenate([[cfg["s"]], ctx.sample_terms(alpha, W.random_bitstrings(n, n_x - 1, rng))]).astype(np.uint64)
+    x_dev = torch.from_numpy(xs.view(np.int64)).to(dev)
+    out32 = torch.empty((n_x, 2), dtype=torch.float64, device=dev)
+    out64 = torch.empty((n_x, 2), dtype=torch.float64, device=dev)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    t_ev, t_32, t_64 = [], [], []
+    for i in range(warmup + steps):
+        ev[0].record(stream)
+        ctx.reset(cfg["seed"])
+        ctx.apply_gates(gates)
+        ev[1].record(stream)
+        ctx.amplitudes(x_dev, fp32c=True, out=out32)
+        ev[2].record(stream)
+        ctx.amplitudes(x_dev, fp32c=False, out=out64)
+        ev[3].record(stream)
+        torch.cuda.synchronize()
+        if i >= warmup:
+            t_ev.append(ev[0].elapsed_time(ev[1]))
+            t_32.append(ev[1].elapsed_time(ev[2]))
+            t_64.append(ev[2].elapsed_time(ev[3]))
+    st = ctx.evolution_stats()
+    lanes, _ = ctx.evolve_lanes()
+    pf_mode, pf_levels, pf_frac = ctx.prefix_share()
+    a64 = out64.cpu().numpy()
+    a32 = out32.cpu().numpy()
+    c64 = a64[:, 0] + 1j * a64[:, 1]
+    c32 = a32[:, 0] + 1j * a32[:, 1]
+    rms = float(np.sqrt(np.mean(np.abs(c64) ** 2)))
+    ctx.close()
+    ms_ev, ms_32, ms_64 = float(np.mean(t_ev)), float(np.mean(t_32)), float(np.mean(t_64))
+    # A CCZ slot is six conditional gates (its branches' net gates): CZ_ab, CZ_ac,
+    # CZ_bc, each applied by four of the eight equally weighted branches, and
+    # S^2 on a, b, c, each applied by two: 1.5 CZ (4 ops) + 0.75 S-type (3 ops)
+    # = 8.25 int32 ops per CCZ per evolved state.
+    ops_ev = float(st["H"] * (28 * n + 40) + st["CX"] * 12 + st["CZ"] * 4 + st["S"] * 3
+                   + st["cond"] / 6 * 8.25)
+    evals = float(chi * n_x)
+    achieved = ops_ev / (ms_ev / 1e3) / 1e12
+    return {"workload": cfg["name"] + f": n={n}, {cfg['n_ccz']} CCZ (8 Clifford branches each), "
+                                      f"{int((circ.op != W.OP_CCZ).sum())} Clifford gates, chi={chi} sparsified "
+                                      "(delta=0.3), s + 4095 strings drawn from the terms",
+            "chi": chi, "n_x": n_x, "ms_evolve": ms_ev, "ms_amplitudes_fp32c": ms_32,
+            "ms_amplitudes_fp64": ms_64, "evals_per_s_fp32c": evals / (ms_32 / 1e3),
+            "evals_per_s_step": evals / ((ms_ev + ms_32) / 1e3),
+            "amplitude_at_s": [float(c64[0].real), float(c64[0].imag)],
+            "fp32c_vs_fp64_normwise": float(np.max(np.abs(c32 - c64)) / rms) if rms > 0 else 0.0,
+            "evolve_shape": shape_name(lanes),
+            "evolve_prefix_share": {"mode": pf_mode, "checkpoint_levels": pf_levels,
+                                    "estimated_work_fraction": round(pf_frac, 4), "distinct_prefixes": st["distinct"],
+                                    "gate_applications": {k: st[k] for k in ("H", "CX", "CZ", "S", "cond")}},
+            "evolve_roofline": {"bound": "alu", "achieved": round(achieved, 3),
+                                "peak": round(INT32_PEAK_OPS / 1e12, 2), "unit": "TOP/s (int32)",
+                                "frac": round(achieved / (INT32_PEAK_OPS / 1e12), 4), "ops_per_launch": ops_ev}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -421,8 +495,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-terms", type=int, default=32768)
-    ap.add_argument("--sections", default="amplitudes,norm,metropolis,uneven",
-                    help="comma list: amplitudes (the timed step), norm, metropolis, uneven")
+    ap.add_argument("--sections", default="amplitudes,norm,metropolis,uneven,hidden_shift",
+                    help="comma list: amplitudes (the timed step), norm, metropolis, uneven, hidden_shift")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 1 GiB device copy first (outside the timed region), so that "
                          "hardware byte counters can be scaled against a kernel of known traffic")
@@ -582,6 +656,8 @@ def main():
         result["norm_estimation"] = bench_norm(torch, B, W)
     if "uneven" in sections:
         result["uneven_batch"] = bench_uneven(torch, B, W)
+    if "hidden_shift" in sections:
+        result["hidden_shift_ccz"] = bench_hidden_shift(torch, B, W)
     if "metropolis" in sections:
         from paper_1808_00128_amd import stats
 

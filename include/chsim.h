@@ -71,7 +71,9 @@ typedef struct chsim_decomp {
 #define CHSIM_SPARSIFY 1 /* chi i.i.d. draws, Lemma (Sparsification), Eq. (Omega) */
 
 /* One circuit instance: its qubit count, slot decompositions and term set.
- * EXACT requires chi == prod_p n_branch(p).  SPARSIFY draws, per term alpha and
+ * EXACT requires chi == prod_p n_branch(p); term alpha takes for slot p the
+ * branch given by digit p of alpha in the mixed radix (n_branch(0),
+ * n_branch(1), ...), slot 0 least significant.  SPARSIFY draws, per term alpha and
  * slot p, a uniform u from Philox4x32-10 with counter (alpha_lo, alpha_hi, p,
  * 0x53504152) and key (seed_lo, seed_hi) (53 bits: (w0 << 21) | (w1 >> 11));
  * branch = smallest j with u * W_p < sum_{i<=j} |c_i|, W_p = sum_i |c_i|, and
@@ -269,6 +271,18 @@ chsim_status chsim_set_terms(chsim_ctx* ctx, uint32_t inst, uint64_t first, uint
  * off[3] and up to 7 gates into gates[8]; fills *out to point at them. */
 chsim_status chsim_decompose_phase(double theta, uint32_t qubit, double coeff[4], uint32_t off[3],
                                    chsim_gate gates[8], chsim_decomp* out);
+
+/* Decomposition of CCZ on qubits (a, b, c) into eight diagonal Clifford
+ * branches by the lifting lemma, Eq. (CCZ decomposition), in the order of the
+ * paper's sum: I, CZ_ab, CZ_ac, CZ_bc, CZ_ab CZ_ac Z_a, CZ_ab CZ_bc Z_b,
+ * CZ_ac CZ_bc Z_c (c_j = 1/6 each) and CZ_ab CZ_ac CZ_bc Z_a Z_b Z_c
+ * (c_7 = -1/6), with Z written as S S.  The paper prints the prefactor 2/9;
+ * only 1/6 makes the sum equal CCZ, and it gives ||c||_1^2 = 16/9 = xi(CCZ)
+ * as the paper states.  Writes coeff[16], off[9] and 24 gates into gates[24]
+ * (caller-owned); fills *out to point at them.  EINVAL: a null output, a
+ * qubit >= 64 or two equal qubits.  Host only; no device work. */
+chsim_status chsim_decompose_ccz(uint32_t a, uint32_t b, uint32_t c, double coeff[16], uint32_t off[9],
+                                 chsim_gate gates[24], chsim_decomp* out);
 
 /* Tuning knobs of one instance; value 0 restores the library default.
  * EVOLVE_LANES: lanes per term in the evolution kernel (4, 8, 16, 32 or 64;

@@ -33,7 +33,7 @@ EXPORTED = [
     "chsim_terms_init", "chsim_terms_reset", "chsim_apply_clifford", "chsim_amplitudes",
     "chsim_amplitudes_batch", "chsim_inner_products",
     "chsim_metropolis_init", "chsim_metropolis_step", "chsim_sample_terms", "chsim_get_terms",
-    "chsim_set_terms", "chsim_decompose_phase", "chsim_set_tuning", "chsim_get_tuning",
+    "chsim_set_terms", "chsim_decompose_phase", "chsim_decompose_ccz", "chsim_set_tuning", "chsim_get_tuning",
     "chsim_instance_info", "chsim_evolution_stats", "chsim_destroy", "chsim_mlp_create", "chsim_mlp_destroy",
     "chsim_mlp_get_params", "chsim_mlp_set_params", "chsim_mlp_forward", "chsim_mlp_loss_grad",
     "chsim_mlp_train", "chsim_metropolis_step_learned",
@@ -118,6 +118,8 @@ def lib():
     L.chsim_set_terms.argtypes = [vp, u32, u64, u64, vp, vp, vp, vp, vp, vp, vp, vp]
     L.chsim_decompose_phase.argtypes = [dbl, u32, C.POINTER(C.c_double), C.POINTER(C.c_uint32),
                                         C.POINTER(Gate), C.POINTER(Decomp)]
+    L.chsim_decompose_ccz.argtypes = [u32, u32, u32, C.POINTER(C.c_double), C.POINTER(C.c_uint32),
+                                      C.POINTER(Gate), C.POINTER(Decomp)]
     L.chsim_set_tuning.argtypes = [vp, u32, u32, C.c_int32]
     L.chsim_get_tuning.argtypes = [vp, u32, u32, C.POINTER(C.c_int32), C.POINTER(C.c_float)]
     L.chsim_instance_info.argtypes = [vp, u32, C.POINTER(C.c_uint32), C.POINTER(C.c_uint64),
@@ -174,13 +176,15 @@ def _stream(stream):
 
 
 def gate_array(circuit: W.Circuit) -> np.ndarray:
-    """Circuit -> chsim_gate[] (SLOT entries numbered in order)."""
+    """Circuit -> chsim_gate[]: SLOT and CCZ entries become CHSIM_SLOT gates,
+    numbered together in circuit order."""
     g = np.zeros(circuit.n_gates, GATE_DTYPE)
-    g["op"] = circuit.op
+    is_slot = (circuit.op == W.OP_SLOT) | (circuit.op == W.OP_CCZ)
+    g["op"] = np.where(is_slot, W.OP_SLOT, circuit.op)
     g["q"] = circuit.q
     g["r"] = circuit.r
-    slot = np.cumsum(circuit.op == W.OP_SLOT) - 1
-    g["slot"] = np.where(circuit.op == W.OP_SLOT, slot, 0).astype(np.uint32)
+    slot = np.cumsum(is_slot) - 1
+    g["slot"] = np.where(is_slot, slot, 0).astype(np.uint32)
     return g
 
 
@@ -200,6 +204,38 @@ class PhaseDecomposition:
         return complex(self.coeff[0], self.coeff[1]), complex(self.coeff[2], self.coeff[3])
 
 
+class CCZDecomposition:
+    """chsim_decompose_ccz output kept alive for the init call."""
+
+    def __init__(self, a: int, b: int, c: int):
+        self.coeff = (C.c_double * 16)()
+        self.off = (C.c_uint32 * 9)()
+        self.gates = (Gate * 24)()
+        self.decomp = Decomp()
+        _check(lib().chsim_decompose_ccz(int(a), int(b), int(c), self.coeff, self.off, self.gates,
+                                         C.byref(self.decomp)))
+
+    @property
+    def c(self):
+        return [complex(self.coeff[2 * j], self.coeff[2 * j + 1]) for j in range(8)]
+
+    def branches(self):
+        return [[(self.gates[k].op, self.gates[k].q, self.gates[k].r) for k in range(self.off[j], self.off[j + 1])]
+                for j in range(8)]
+
+
+def slot_decompositions(circ: W.Circuit) -> list:
+    """One decomposition per slot of the circuit, in slot order."""
+    decs = []
+    third = circ.third()
+    for o, q, r, t, in zip(circ.op.tolist(), circ.q.tolist(), circ.r.tolist(), third.tolist()):
+        if o == W.OP_SLOT:
+            decs.append(PhaseDecomposition(circ.theta[len(decs)], q))
+        elif o == W.OP_CCZ:
+            decs.append(CCZDecomposition(q, r, t))
+    return decs
+
+
 class Context:
     """A set of circuit instances and their chi CH-form terms on one GPU."""
 
@@ -211,10 +247,7 @@ class Context:
         self.specs = specs
         for i, sp in enumerate(specs):
             circ = sp["circuit"]
-            decs = []
-            slot_qubits = circ.q[circ.op == W.OP_SLOT]
-            for qb, th in zip(slot_qubits.tolist(), circ.theta.tolist()):
-                decs.append(PhaseDecomposition(th, qb))
+            decs = slot_decompositions(circ)
             arr = (Decomp * max(1, len(decs)))()
             for k, d in enumerate(decs):
                 arr[k] = d.decomp

@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <map>
 #include <vector>
 
 #include "chsim.h"
@@ -84,6 +85,10 @@ struct Instance {
   bool autotune = false;  // time every shape at the next from-|0^n> evolution
   float tuned_ms[kTuneShapes] = {};     // per tuned shape, kTuneLanes order (0 = not timed)
   std::vector<SlotTable> slots_h;
+  // Per slot: when every branch is diagonal (powers of S and CZ), the union of
+  // the branches' net gates, each with the mask of branches that apply it
+  // (empty otherwise).
+  std::vector<std::vector<DGate>> diag_h;
   std::vector<DGate> bgates_h;
   DevBuf<uint64_t> F, G, M, v, s;
   DevBuf<uint8_t> gamma, omega, branch;
@@ -241,9 +246,38 @@ void push_gate(std::vector<DGate>& out, const chsim_gate& g, size_t first = 0) {
   out.push_back(DGate{g.op, g.q, g.r, 0, 0, 0, 0});
 }
 
+// Branches made only of S powers and CZ gates act on a CH form through L[S]
+// (M_q ^= G_q, gamma_q -= 1) and L[CZ] (M_q ^= G_r, M_r ^= G_q), which commute
+// and leave F, G, v, s and omega alone, so a branch is fixed by its net S
+// power per qubit (mod 4) and its CZ parity per pair.  Each distinct net gate
+// becomes one conditional gate whose mask holds the branches that apply it.
+void merge_diagonal_branches(const Instance& I, const SlotTable& st, std::vector<DGate>& out) {
+  std::map<std::pair<uint32_t, uint32_t>, uint8_t> mask;  // (q, r) -> branches; r = 64 + power for S^power
+  for (uint32_t j = 0; j < st.n_branch; ++j) {
+    std::map<uint32_t, uint32_t> pw;
+    std::map<std::pair<uint32_t, uint32_t>, uint32_t> cz;
+    for (uint32_t k = st.goff[j]; k < st.goff[j + 1]; ++k) {
+      const DGate& g = I.bgates_h[k];
+      if (g.op == OP_SPOW) pw[g.q] += g.arg;
+      else if (g.op == OP_CZ) cz[{std::min(g.q, g.r), std::max(g.q, g.r)}] ^= 1u;
+      else return;  // not diagonal: keep the per-branch gate lists
+    }
+    for (const auto& e : cz)
+      if (e.second) mask[e.first] |= (uint8_t)(1u << j);
+    for (const auto& e : pw)
+      if (e.second & 3u) mask[{e.first, 64u + (e.second & 3u)}] |= (uint8_t)(1u << j);
+  }
+  for (const auto& e : mask) {
+    const uint32_t q = e.first.first, r = e.first.second;
+    if (r >= 64) out.push_back(DGate{OP_SPOW, (uint8_t)q, 0, (uint8_t)(r - 64), 0, kCondApply, e.second});
+    else out.push_back(DGate{OP_CZ, (uint8_t)q, (uint8_t)r, 0, 0, kCondApply, e.second});
+  }
+}
+
 chsim_status build_slots(Instance& I, const chsim_instance& in) {
   I.slots_h.clear();
   I.bgates_h.clear();
+  I.diag_h.clear();
   double l1 = 1.0;
   for (uint32_t p = 0; p < in.n_slot; ++p) {
     const chsim_decomp& d = in.slot_decomp[p];
@@ -290,6 +324,8 @@ chsim_status build_slots(Instance& I, const chsim_instance& in) {
     }
     st.total = cum;
     if (!(cum > 0.0) || !std::isfinite(cum)) return fail(CHSIM_EINVAL, "slot %u: zero or non-finite weights", p);
+    I.diag_h.emplace_back();
+    if (st.spow_q < 0) merge_diagonal_branches(I, st, I.diag_h.back());
     l1 *= cum;
     I.slots_h.push_back(st);
   }
@@ -819,6 +855,15 @@ chsim_status chsim_apply_clifford(chsim_ctx* ctx, uint32_t inst, const chsim_gat
           for (uint32_t j = 0; j < tb.n_branch; ++j) packed |= (uint32_t)(tb.spow[j] & 3u) << (2 * j);
           dg.push_back(DGate{OP_SLOT_SPOW, (uint8_t)tb.spow_q, (uint8_t)(packed & 0xffu), (uint8_t)(packed >> 8),
                              (uint16_t)g.slot, kSlotStart, 0});
+        } else if (!I.diag_h[g.slot].empty()) {
+          // Diagonal branches: one conditional gate per distinct net gate.
+          bool first = true;
+          for (DGate bg : I.diag_h[g.slot]) {
+            bg.slot = (uint16_t)g.slot;
+            bg.cond = (uint8_t)(kCondApply | (first ? kSlotStart : 0));
+            dg.push_back(bg);
+            first = false;
+          }
         } else {
           // A general branch list becomes conditional gates: each term applies
           // only the gates of its own branch.
@@ -828,7 +873,7 @@ chsim_status chsim_apply_clifford(chsim_ctx* ctx, uint32_t inst, const chsim_gat
               DGate bg = I.bgates_h[k];
               bg.slot = (uint16_t)g.slot;
               bg.cond = (uint8_t)(kCondApply | (first ? kSlotStart : 0));
-              bg.arg2 = (uint8_t)j;
+              bg.arg2 = (uint8_t)(1u << j);
               dg.push_back(bg);
               first = false;
             }
@@ -1493,6 +1538,45 @@ chsim_status chsim_decompose_phase(double theta, uint32_t qubit, double coeff[4]
   for (int i = 0; i < ((k + 1) & 3); ++i) gates[g++] = chsim_gate{CHSIM_S, (uint8_t)qubit, 0, 0, 0};
   off[2] = g;
   out->n_branch = 2;
+  out->coeff = coeff;
+  out->off = off;
+  out->gates = gates;
+  return CHSIM_OK;
+}
+
+chsim_status chsim_decompose_ccz(uint32_t a, uint32_t b, uint32_t c, double coeff[16], uint32_t off[9],
+                                 chsim_gate gates[24], chsim_decomp* out) {
+  g_err.clear();
+  if (!coeff || !off || !gates || !out) return fail(CHSIM_EINVAL, "null output");
+  if (a >= 64 || b >= 64 || c >= 64) return fail(CHSIM_EINVAL, "qubit >= 64");
+  if (a == b || a == c || b == c) return fail(CHSIM_EINVAL, "CCZ qubits must be distinct");
+  // The group of CCZ X_j CCZ^dag has generators X_c CZ_ab, X_b CZ_ac, X_a CZ_bc.
+  // Branch j keeps a subset of them (the X parts act trivially on |+++>):
+  // CZ on the pair of every kept generator, Z (= S S) on every qubit that two
+  // kept pairs share, and a minus sign when all three are kept.  Subsets in the
+  // order of the paper's sum: {}, {ab}, {ac}, {bc}, {ab,ac}, {ab,bc}, {ac,bc}, all.
+  const uint32_t pq[3][2] = {{a, b}, {a, c}, {b, c}};
+  static const uint8_t kKeep[8] = {0, 1, 2, 4, 3, 5, 6, 7};
+  uint32_t g = 0;
+  off[0] = 0;
+  for (int j = 0; j < 8; ++j) {
+    const uint8_t keep = kKeep[j];
+    for (int e = 0; e < 3; ++e)
+      if (keep >> e & 1) gates[g++] = chsim_gate{CHSIM_CZ, (uint8_t)pq[e][0], (uint8_t)pq[e][1], 0, 0};
+    const uint32_t qs[3] = {a, b, c};
+    for (uint32_t x : qs) {
+      int uses = 0;
+      for (int e = 0; e < 3; ++e) uses += (keep >> e & 1) && (pq[e][0] == x || pq[e][1] == x);
+      if (uses >= 2) {
+        gates[g++] = chsim_gate{CHSIM_S, (uint8_t)x, 0, 0, 0};
+        gates[g++] = chsim_gate{CHSIM_S, (uint8_t)x, 0, 0, 0};
+      }
+    }
+    off[j + 1] = g;
+    coeff[2 * j] = keep == 7 ? -1.0 / 6.0 : 1.0 / 6.0;
+    coeff[2 * j + 1] = 0.0;
+  }
+  out->n_branch = 8;
   out->coeff = coeff;
   out->off = off;
   out->gates = gates;

@@ -325,7 +325,7 @@ __global__ __launch_bounds__(256) void k_evolve(EvolveJob J, const DGate* __rest
       uint32_t pw = 1u;
       if (op == OP_SLOT_SPOW) pw = ((w0 >> 16) >> (2u * cur_b)) & 3u;
       else if (op == OP_SPOW) pw = w0 >> 24;
-      const bool on = !(cond & kCondApply) || cur_b == (w1 >> 24);
+      const bool on = !(cond & kCondApply) || ((w1 >> 24) >> cur_b & 1u);
       if (op == OP_H) {
         if (on) sw_h(c, L, q);
       } else {

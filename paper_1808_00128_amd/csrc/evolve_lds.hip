@@ -121,7 +121,7 @@ __global__ __launch_bounds__(256) void k_evolve_lds(EvolveJob J, const DGate* __
       if (occ < n_occ) next_b = (uint32_t)branch[(uint64_t)seq[occ] * chb + ba];
       ++occ;
     }
-    const bool on = !(cond & kCondApply) || cur_b == (w1 >> 24);
+    const bool on = !(cond & kCondApply) || ((w1 >> 24) >> cur_b & 1u);
     const uint32_t kq = q / LPT, lq = q % LPT;
     if (op == OP_H) {
       if (!on) continue;

@@ -85,7 +85,7 @@ __global__ __launch_bounds__(256) void k_evolve_w64(EvolveJob J, const DGate* __
         if (occ < n_occ) next_b = uniform32(branch[(uint64_t)seq[occ] * chb + ba]);
         ++occ;
       }
-      const bool on = !(cond & kCondApply) || cur_b == (w1 >> 24);
+      const bool on = !(cond & kCondApply) || ((w1 >> 24) >> cur_b & 1u);
       if (!on) continue;
       if (op == OP_H) {
         // Hadamard on qubit q: Eqs. (H2), (H4), the t = u case, Prop. H.

@@ -21,8 +21,9 @@ enum : uint8_t { OP_H = 0, OP_S = 1, OP_CX = 2, OP_CZ = 3, OP_SLOT = 4, OP_SPOW 
 // 32-bit words on the scalar unit).  `slot` is the slot index of a slot
 // gate.  SLOT_SPOW: the slot's branches are powers of S on qubit q; branch j
 // applies S^{(r | arg << 8) >> 2j & 3}.  A gate of a general slot branch has
-// kCondApply in cond and applies only to terms whose choice for the slot is
-// arg2.  kSlotStart in cond marks the first gate of a slot occurrence, where
+// kCondApply in cond and applies only to terms whose choice j for the slot
+// has bit j set in arg2 (a branch mask: one bit for a gate of one branch's
+// list, several for a net gate shared by diagonal branches).  kSlotStart in cond marks the first gate of a slot occurrence, where
 // the term's branch choice for that slot is needed.
 struct DGate {
   uint8_t op, q, r, arg;

@@ -1,0 +1,167 @@
+"""GPU parity for circuits with CCZ gates (lifting-lemma decomposition into
+eight diagonal Clifford branches, Eq. (CCZ decomposition)), through the C ABI
+against the CPU oracle.
+
+Terms are bit-exact (F, G, M, gamma, v, s, omega, branch choices); amplitudes
+within 1e-12 (FP64) and 1e-6 (FP32C) normwise.  The hidden-shift circuits
+(Sec. "The hidden shift algorithm") add a closed form: with every term kept
+their output is exactly |s>.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1808_00128_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32 = 1e-6
+
+
+def say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1808_00128_amd import binding
+
+    binding.lib()
+    return binding
+
+
+def normwise(a, ref):
+    rms = np.sqrt(np.mean(np.abs(ref) ** 2))
+    return float(np.max(np.abs(a - ref)) / rms)
+
+
+def compare_terms(ctx, T, idx):
+    for k, a in enumerate(idx):
+        g = ctx.get_terms(int(a), 1)
+        o = T.term(k).export()
+        for f in ("F", "G", "M", "gamma"):
+            assert np.array_equal(g[f][0], o[f]), (f, a)
+        for f in ("v", "s", "omega"):
+            assert int(g[f][0]) == o[f], (f, a)
+        assert np.array_equal(g["branch"][0], T.branch(k)), ("branch", a)
+        ob = T.b(k)
+        assert abs(g["b"][0] - ob) <= 1e-14 * abs(ob), ("b", a)
+
+
+def _sample_idx(chi, count, rng):
+    if chi <= count:
+        return np.arange(chi, dtype=np.uint64)
+    return np.unique(np.concatenate([[0, chi - 1], rng.integers(0, chi, size=count)])).astype(np.uint64)
+
+
+def test_hidden_shift_exact_every_shape(B):
+    """n = 10, four CCZ (4096 terms, exact): every evolution shape and the
+    shared-prefix modes give the oracle's terms; the amplitudes of all 1024
+    strings are the oracle's and the closed form delta_{x,s}."""
+    rng = np.random.default_rng(21)
+    n, u = 10, 4
+    circ, s = W.hidden_shift_circuit(n, u, rng)
+    chi = 8**u
+    spec = dict(circuit=circ, chi=chi, mode="exact", seed=0)
+    idx = _sample_idx(chi, 160, rng)
+    T = O.Terms(circ, chi, O.EXACT, alphas=idx)
+    xs = np.arange(2**n, dtype=np.uint64)
+    want = np.zeros(2**n, np.complex128)
+    want[s] = 1.0
+    Tall = O.Terms(circ, chi, O.EXACT)
+    ref = Tall.amplitudes(xs)
+    for lanes in B.TUNE_SHAPES:
+        if lanes & B.CHSIM_EVOLVE_LDS and (lanes & 0xff) * 16 < n:
+            continue
+        for share in (0, 2):
+            say(f"ccz hidden shift n={n} u={u} lanes={lanes:#x} share={share}")
+            ctx = B.Context([spec])
+            ctx.set_evolve_lanes(lanes)
+            ctx.set_prefix_share(share)
+            ctx.apply_circuit(circ)
+            compare_terms(ctx, T, idx)
+            a64 = ctx.amplitudes(xs)
+            a32 = ctx.amplitudes(xs, fp32c=True)
+            assert normwise(a64, ref) < TOL64
+            assert normwise(a32, ref) < TOL32
+            assert np.max(np.abs(a64 - want)) < 1e-12
+            ctx.close()
+
+
+@pytest.mark.parametrize("n,chi,share", [(7, 2 * 8 * 2 * 8 * 2, 1), (40, 3001, 2), (64, 777, 0)])
+def test_mixed_phase_and_ccz_slots(B, n, chi, share):
+    """Phase slots and CCZ slots interleaved in a random Clifford circuit;
+    exact (mixed radix 2, 8, 2, 8, 2) at n = 7, sparsified above."""
+    rng = np.random.default_rng(300 + n)
+    g = W.random_clifford_gates(n, 30 * n if n > 7 else 150, rng)
+    cut = np.sort(rng.integers(0, len(g), size=5))
+    gates, k = [], 0
+    for i, gg in enumerate(g):
+        while k < 5 and cut[k] == i:
+            if k % 2:
+                q = rng.choice(n, size=3, replace=False).tolist()
+                gates.append((W.OP_CCZ, q[0], q[1], q[2]))
+            else:
+                gates.append((W.OP_SLOT, int(rng.integers(n)), 0, float(rng.uniform(0, 2 * np.pi))))
+            k += 1
+        gates.append(gg)
+    circ = W.from_list(n, gates)
+    mode = "exact" if n == 7 else "sparsify"
+    spec = dict(circuit=circ, chi=chi, mode=mode, seed=5 + n)
+    om = O.EXACT if mode == "exact" else O.SPARSIFY
+    idx = _sample_idx(chi, 200, rng)
+    T = O.Terms(circ, chi, om, seed=spec["seed"], alphas=idx)
+    say(f"mixed slots n={n} chi={chi} share={share}")
+    ctx = B.Context([spec])
+    ctx.set_prefix_share(share)
+    ctx.apply_circuit(circ)
+    compare_terms(ctx, T, idx)
+    Tall = O.Terms(circ, chi, om, seed=spec["seed"])
+    xs = W.random_bitstrings(n, 64, rng)
+    # strings from the terms' own supports, so the amplitudes are not all zero
+    al = rng.integers(0, chi, size=64).astype(np.uint64)
+    xs = np.concatenate([xs, ctx.sample_terms(al, W.random_bitstrings(n, 64, rng))])
+    ref = Tall.amplitudes(xs)
+    assert normwise(ctx.amplitudes(xs), ref) < TOL64
+    assert normwise(ctx.amplitudes(xs, fp32c=True), ref) < TOL32
+    ctx.close()
+
+
+def test_hidden_shift_config_full_size_sampled(B):
+    """n = 40, sixteen CCZ, chi = floor(((4/3)^16 / 0.3)^2) sparsified terms,
+    4096 strings, the benchmark's launch configuration: 256 sampled terms
+    bit-exact; 16 strings (s among them) over all chi terms against the oracle."""
+    cfg = W.config_hidden_shift()
+    chi = cfg["chi"]
+    say(f"hidden shift full config {cfg['name']}")
+    ctx = B.Context([cfg])
+    ctx.apply_circuit(cfg["circuit"])
+    rng = np.random.default_rng(2)
+    idx = _sample_idx(chi, 254, rng)
+    Ts = O.Terms(cfg["circuit"], chi, O.SPARSIFY, seed=cfg["seed"], alphas=idx)
+    compare_terms(ctx, Ts, idx)
+    del Ts
+    al = rng.integers(0, chi, size=cfg["x"].size - 1).astype(np.uint64)
+    xs = np.concatenate([[cfg["s"]], ctx.sample_terms(al, W.random_bitstrings(40, al.size, rng))]).astype(np.uint64)
+    a64 = ctx.amplitudes(xs)
+    a32 = ctx.amplitudes(xs, fp32c=True)
+    assert normwise(a32, a64) < TOL32
+    say("hidden shift full config: oracle evolves all terms")
+    T = O.Terms(cfg["circuit"], chi, O.SPARSIFY, seed=cfg["seed"])
+    pick = np.concatenate([[0], rng.choice(np.arange(1, xs.size), size=15, replace=False)])
+    ref = T.amplitudes(xs[pick])
+    rms = np.sqrt(np.mean(np.abs(a64) ** 2))
+    assert np.max(np.abs(a64[pick] - ref)) / rms < TOL64
+    assert np.max(np.abs(a32[pick] - ref)) / rms < TOL32
+    # chi was chosen for ||Omega - psi|| ~ delta = 0.3 (Lemma (Sparsification));
+    # <s|psi> = 1, so the estimate of <s|psi> sits within that distance.
+    assert abs(a64[0] - 1.0) < 2 * cfg["delta"]
+    ctx.close()

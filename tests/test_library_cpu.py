@@ -9,6 +9,8 @@ import os
 import re
 
 import numpy as np
+
+import dense
 import pytest
 
 import oracle as O
@@ -54,6 +56,43 @@ def test_decompose_phase_rejects_bad_input():
         B.PhaseDecomposition(float("nan"), 0)
     with pytest.raises(B.ChsimError):
         B.PhaseDecomposition(0.3, 64)
+
+
+@pytest.mark.parametrize("qubits", [(0, 1, 2), (7, 2, 5), (63, 0, 31)])
+def test_decompose_ccz_is_exact_and_matches_oracle(qubits):
+    a, b, c = qubits
+    d = B.CCZDecomposition(a, b, c)
+    assert d.decomp.n_branch == 8 and d.off[8] == 24
+    got = d.branches()
+    oc, ob = O.ccz_decomp(a, b, c)
+    np.testing.assert_array_equal(np.array(d.c), oc)  # same order, same doubles
+    for j in range(8):
+        assert sorted(got[j]) == sorted(ob[j])  # diagonal gates: order within a branch is free
+    # sum_j c_j K_j = CCZ on the three qubits (relabelled 0, 1, 2; dense)
+    lab = {a: 0, b: 1, c: 2}
+    total = np.zeros(8, np.complex128)
+    for cj, K in zip(d.c, got):
+        diag = np.ones(8, np.complex128)
+        for op, q, r in K:
+            diag = dense.apply(diag, 3, op, lab[q], lab.get(r, 0))
+        total += cj * diag
+    np.testing.assert_allclose(total, [1, 1, 1, 1, 1, 1, 1, -1], atol=1e-15)
+
+
+def test_decompose_ccz_rejects_bad_input():
+    for args in [(0, 0, 1), (1, 2, 2), (3, 4, 3), (64, 0, 1), (0, 1, 99)]:
+        with pytest.raises(B.ChsimError):
+            B.CCZDecomposition(*args)
+
+
+def test_gate_array_numbers_phase_and_ccz_slots_together():
+    circ = B.W.from_list(6, [(B.W.OP_H, 0, 0), (B.W.OP_CCZ, 0, 1, 2), (B.W.OP_SLOT, 3, 0, 0.4),
+                             (B.W.OP_CX, 1, 4), (B.W.OP_CCZ, 5, 3, 1)])
+    g = B.gate_array(circ)
+    assert g["op"].tolist() == [B.W.OP_H, B.W.OP_SLOT, B.W.OP_SLOT, B.W.OP_CX, B.W.OP_SLOT]
+    assert g["slot"].tolist() == [0, 0, 1, 0, 2]
+    decs = B.slot_decompositions(circ)
+    assert [type(x).__name__ for x in decs] == ["CCZDecomposition", "PhaseDecomposition", "CCZDecomposition"]
 
 
 def make_instance(n, chi, mode=B.CHSIM_SPARSIFY, n_slot=0):
