@@ -244,6 +244,7 @@ class Terms:
             self._h = None
             raise ValueError(f"oracle term build failed (code {err})")
         self.count = int(lib().orc_terms_count(self._h))
+        self.chi = int(chi)
         self.l1 = float(lib().orc_terms_l1(self._h))
         self.threads = threads
 
@@ -283,6 +284,18 @@ class Terms:
         if bad:
             raise RuntimeError("oracle inner product produced an invalid record")
         return ov[0::2] + 1j * ov[1::2], eta
+
+    def sparsification_bound(self, Aoff, Adiag):
+        """Lemma (Sparsification tail bound), Eq. (event): ||psi - Omega||^2 <=
+        <Omega|Omega> - 1 + delta^2 for chi = ||c||_1^2 / delta^2, with
+        <Omega|Omega> estimated by norm estimation (Lemma (Norm Estimation))
+        over the given equatorial states.  Returns (estimate, standard error,
+        delta^2, bound)."""
+        _, eta = self.inner(Aoff, Adiag)
+        est = float(np.mean(eta))
+        sem = float(np.std(eta, ddof=1) / np.sqrt(eta.size))
+        delta2 = self.l1**2 / self.chi
+        return est, sem, delta2, est - 1.0 + delta2
 
     def metropolis(self, x_init, jstream, ustream):
         """Plain single-bit-flip chains (Sec. "Heuristic Metropolis simulator")."""

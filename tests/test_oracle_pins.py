@@ -558,3 +558,84 @@ def test_ccz_sparsified_branch_law_and_error_bound():
     err2 = np.sum(np.abs(amps - psi) ** 2)
     assert err2 < 5 * T.l1**2 / chi
     assert abs(amps[s] - 1.0) < 0.2
+
+
+# ---------------------------------------------------------------------------
+# Sparsification tail bound, Lemma (Sparsification tail bound).
+# ---------------------------------------------------------------------------
+def _all_equatorial(n):
+    """Every A in M_n: symmetric off-diagonal bits and a diagonal in Z_4."""
+    pairs = [(a, b) for a in range(n) for b in range(a + 1, n)]
+    offs, diags = [], []
+    for bits in range(2 ** len(pairs)):
+        row = [0] * n
+        for k, (a, b) in enumerate(pairs):
+            if bits >> k & 1:
+                row[a] |= 1 << b
+                row[b] |= 1 << a
+        for d in itertools.product(range(4), repeat=n):
+            offs.append(list(row))
+            diags.append(list(d))
+    return np.array(offs, np.uint64), np.array(diags, np.uint8)
+
+
+def _dense_omega(T, circ):
+    """Omega = sum_alpha b_alpha K_alpha |0^n>, each term's Clifford circuit run
+    densely (slot p replaced by its chosen branch's gates)."""
+    n = circ.n
+    ops = circ.slot_ops()
+    omega = np.zeros(2**n, np.complex128)
+    for i in range(T.count):
+        br = T.branch(i)
+        gates, p = [], 0
+        for op, q, r, extra in circ.gates():
+            if op == OP_SLOT:
+                _, _, k = O.phase_decomp(extra)
+                gates += [(OP_S, q, 0)] * ((k + br[p]) % 4)
+                p += 1
+            elif op == W.OP_CCZ:
+                _, branches = O.ccz_decomp(q, r, extra)
+                gates += branches[br[p]]
+                p += 1
+            else:
+                gates.append((op, q, r))
+        assert p == len(ops)
+        omega += T.b(i) * dense.run_gates(n, gates)
+    return omega
+
+
+def test_sparsification_bound_exhaustive_states_n3():
+    """With every A in M_3 the norm estimate is exactly <Omega|Omega> (dense),
+    and the bound is that value - 1 + ||c||_1^2 / chi."""
+    rng = np.random.default_rng(8)
+    circ = W.from_list(3, [(OP_H, 0, 0), (OP_H, 1, 0), (OP_SLOT, 0, 0, 0.9), (OP_CX, 0, 2), (OP_H, 2, 0),
+                           (W.OP_CCZ, 0, 1, 2), (OP_H, 1, 0), (OP_SLOT, 2, 0, 2.3), (OP_CZ, 1, 2)])
+    chi = 40
+    T = O.Terms(circ, chi, O.SPARSIFY, seed=int(rng.integers(1 << 30)))
+    Aoff, Adiag = _all_equatorial(3)
+    est, sem, delta2, bound = T.sparsification_bound(Aoff, Adiag)
+    omega = _dense_omega(T, circ)
+    assert abs(est - np.vdot(omega, omega).real) < 1e-12
+    assert abs(delta2 - T.l1**2 / chi) < 1e-15
+    assert abs(bound - (est - 1 + delta2)) < 1e-15
+    assert sem > 0
+
+
+def test_sparsification_expected_norm_excess():
+    """Eq. (expomega): E[<Omega|Omega> - 1] <= delta^2 = ||c||_1^2 / k, over 300
+    seeds (exact norms from all 2^n amplitudes)."""
+    rng = np.random.default_rng(12)
+    n, k = 4, 12
+    circ = W.random_circuit(n, 40, [0.7, 2.0, 4.4], rng)
+    circ = W.from_list(n, list(circ.gates())[:20] + [(W.OP_CCZ, 0, 1, 3)] + list(circ.gates())[20:])
+    xs = np.arange(2**n, dtype=np.uint64)
+    excess = []
+    for seed in range(300):
+        T = O.Terms(circ, k, O.SPARSIFY, seed=seed, threads=1)
+        a = T.amplitudes(xs)
+        excess.append(np.sum(np.abs(a) ** 2) - 1.0)
+    excess = np.array(excess)
+    delta2 = T.l1**2 / k
+    assert excess.mean() <= delta2 + 4 * excess.std(ddof=1) / np.sqrt(excess.size)
+    # and the mean is (||c||_1^2 - 1) / k, the exact value the lemma's proof gives (below the stated bound)
+    assert abs(excess.mean() - (T.l1**2 - 1) / k) < 4 * excess.std(ddof=1) / np.sqrt(excess.size)
