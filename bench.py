@@ -456,6 +456,13 @@ def bench_hidden_shift(torch, B, W, steps=5, warmup=2):
     st = ctx.evolution_stats()
     lanes, _ = ctx.evolve_lanes()
     pf_mode, pf_levels, pf_frac = ctx.prefix_share()
+    # Sparsification tail bound: <Omega|Omega> by norm estimation over 1024
+    # equatorial states, delta^2 = ||c||_1^2 / chi.
+    Aoff, Adiag = W.random_equatorial(n, 1024, rng)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    est, sem, delta2, bound = ctx.sparsification_bound(Aoff, Adiag)
+    t_bound = time.perf_counter() - t0
     a64 = out64.cpu().numpy()
     a32 = out32.cpu().numpy()
     c64 = a64[:, 0] + 1j * a64[:, 1]
@@ -478,6 +485,11 @@ def bench_hidden_shift(torch, B, W, steps=5, warmup=2):
             "ms_amplitudes_fp64": ms_64, "evals_per_s_fp32c": evals / (ms_32 / 1e3),
             "evals_per_s_step": evals / ((ms_ev + ms_32) / 1e3),
             "amplitude_at_s": [float(c64[0].real), float(c64[0].imag)],
+            "sparsification_bound": {"omega_norm2_estimate": est, "omega_norm2_sem": sem, "delta2": delta2,
+                                     "bound_psi_minus_omega_sq": bound,
+                                     # psi = |s>: ||psi - Omega||^2 = <Omega|Omega> - 2 Re<s|Omega> + 1
+                                     "psi_minus_omega_sq_from_estimate": est - 2 * float(c64[0].real) + 1,
+                                     "equatorial_states": 1024, "seconds": t_bound},
             "fp32c_vs_fp64_normwise": float(np.max(np.abs(c32 - c64)) / rms) if rms > 0 else 0.0,
             "evolve_shape": shape_name(lanes),
             "evolve_prefix_share": {"mode": pf_mode, "checkpoint_levels": pf_levels,

@@ -163,6 +163,20 @@ chsim_status chsim_inner_products(chsim_ctx* ctx, uint32_t inst, const uint64_t*
                                   const uint8_t* A_diag, size_t L, double* overlap, double* eta,
                                   double* eta_mean, uint32_t flags, void* stream);
 
+/* Sparsification tail bound (Lemma (Sparsification tail bound), Eq. (event)):
+ * for a normalised psi and chi >= ||c||_1^2 / delta^2 sparsified terms,
+ * ||psi - Omega||^2 <= <Omega|Omega> - 1 + delta^2 with probability at least
+ * 1 - 2 exp(-delta^2 / (8 F(psi))).  <Omega|Omega> is estimated by norm
+ * estimation over the L equatorial states given (same layout and checks as
+ * chsim_inner_products, host arrays only) and delta^2 = ||c||_1^2 / chi.
+ * Writes out[0] = the estimate of <Omega|Omega> (mean of eta_l),
+ * out[1] = its standard error over the L states, out[2] = delta^2,
+ * out[3] = out[0] - 1 + out[2], the bound on ||psi - Omega||^2.  Synchronous.
+ * EINVAL: an EXACT instance (Omega = psi), L < 2, a null output, or the
+ * errors of chsim_inner_products. */
+chsim_status chsim_sparsification_bound(chsim_ctx* ctx, uint32_t inst, const uint64_t* A_off,
+                                        const uint8_t* A_diag, size_t L, double out[4], void* stream);
+
 /* Start n_chain Metropolis chains at x0[c] (Sec. "Heuristic Metropolis
  * simulator"): caches, per chain and term, the Pauli Q_x as (u, mu) and
  * writes amp[2c..2c+1] = <x0_c|psi>.  Requires n <= 62.  EINVAL: some

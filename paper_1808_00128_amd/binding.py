@@ -31,7 +31,7 @@ MAX_BRANCH = 8
 
 EXPORTED = [
     "chsim_terms_init", "chsim_terms_reset", "chsim_apply_clifford", "chsim_amplitudes",
-    "chsim_amplitudes_batch", "chsim_inner_products",
+    "chsim_amplitudes_batch", "chsim_inner_products", "chsim_sparsification_bound",
     "chsim_metropolis_init", "chsim_metropolis_step", "chsim_sample_terms", "chsim_get_terms",
     "chsim_set_terms", "chsim_decompose_phase", "chsim_decompose_ccz", "chsim_set_tuning", "chsim_get_tuning",
     "chsim_instance_info", "chsim_evolution_stats", "chsim_destroy", "chsim_mlp_create", "chsim_mlp_destroy",
@@ -111,6 +111,7 @@ def lib():
     L.chsim_apply_clifford.argtypes = [vp, u32, vp, C.c_size_t, vp]
     L.chsim_amplitudes.argtypes = [vp, u32, vp, C.c_size_t, vp, u32, vp]
     L.chsim_inner_products.argtypes = [vp, u32, vp, vp, C.c_size_t, vp, vp, vp, u32, vp]
+    L.chsim_sparsification_bound.argtypes = [vp, u32, vp, vp, C.c_size_t, C.POINTER(C.c_double), vp]
     L.chsim_metropolis_init.argtypes = [vp, u32, u32, vp, vp, u32, vp]
     L.chsim_metropolis_step.argtypes = [vp, u32, u32, vp, vp, vp, vp, vp, u32, vp]
     L.chsim_sample_terms.argtypes = [vp, u32, C.c_size_t, vp, vp, vp]
@@ -406,6 +407,16 @@ class Context:
                                           _ptr(ov)[0], _ptr(eta)[0], C.byref(mean), 0,
                                           _stream(stream)))
         return ov[0::2] + 1j * ov[1::2], eta, mean.value
+
+    def sparsification_bound(self, Aoff, Adiag, inst=0, stream=None):
+        """(<Omega|Omega> estimate, its standard error, delta^2, bound on
+        ||psi - Omega||^2) from chsim_sparsification_bound."""
+        Aoff = np.ascontiguousarray(Aoff, np.uint64)
+        Adiag = np.ascontiguousarray(Adiag, np.uint8)
+        out = (C.c_double * 4)()
+        _check(lib().chsim_sparsification_bound(self._h, inst, _ptr(Aoff)[0], _ptr(Adiag)[0], Aoff.shape[0],
+                                                out, _stream(stream)))
+        return tuple(out)
 
     # ---- Metropolis ----
     def metropolis_init(self, x0, inst=0, stream=None):

@@ -1683,6 +1683,30 @@ chsim_status chsim_evolution_stats(chsim_ctx* ctx, uint32_t inst, uint64_t apps[
   return CHSIM_OK;
 }
 
+chsim_status chsim_sparsification_bound(chsim_ctx* ctx, uint32_t inst, const uint64_t* A_off,
+                                        const uint8_t* A_diag, size_t L, double out[4], void* stream) {
+  g_err.clear();
+  chsim_status st = check_ctx(ctx, inst);
+  if (st) return st;
+  if (!out) return fail(CHSIM_EINVAL, "null output");
+  const Instance& I = ctx->inst[inst];
+  if (I.mode != CHSIM_SPARSIFY) return fail(CHSIM_EINVAL, "the bound is for a sparsified instance");
+  if (L < 2) return fail(CHSIM_EINVAL, "need at least two equatorial states");
+  std::vector<double> ov(2 * L), eta(L);
+  double mean = 0.0;
+  st = chsim_inner_products(ctx, inst, A_off, A_diag, L, ov.data(), eta.data(), &mean, 0u, stream);
+  if (st) return st;
+  // Standard error of the mean of the L estimates eta_l (two-pass variance).
+  double ss = 0.0;
+  for (size_t l = 0; l < L; ++l) ss += (eta[l] - mean) * (eta[l] - mean);
+  const double delta2 = I.l1 * I.l1 / (double)I.chi;  // chi = ||c||_1^2 / delta^2
+  out[0] = mean;
+  out[1] = std::sqrt(ss / (double)(L - 1) / (double)L);
+  out[2] = delta2;
+  out[3] = mean - 1.0 + delta2;
+  return CHSIM_OK;
+}
+
 chsim_status chsim_instance_info(chsim_ctx* ctx, uint32_t inst, uint32_t* n, uint64_t* chi, double* l1) {
   g_err.clear();
   chsim_status st = check_ctx(ctx, inst);

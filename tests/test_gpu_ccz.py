@@ -165,3 +165,41 @@ def test_hidden_shift_config_full_size_sampled(B):
     # <s|psi> = 1, so the estimate of <s|psi> sits within that distance.
     assert abs(a64[0] - 1.0) < 2 * cfg["delta"]
     ctx.close()
+
+
+@pytest.mark.parametrize("case", ["random-n10", "hidden-shift-n40"])
+def test_sparsification_bound_matches_oracle(B, case):
+    """chsim_sparsification_bound (norm estimate of <Omega|Omega>, its standard
+    error, delta^2 = ||c||_1^2 / chi, the bound) against the oracle's."""
+    rng = np.random.default_rng(61)
+    if case == "random-n10":
+        circ = W.random_circuit(10, 150, rng.uniform(0, 2 * np.pi, size=8), rng)
+        spec = dict(circuit=circ, chi=300, mode="sparsify", seed=4)
+        L = 50
+    else:
+        cfg = W.config_hidden_shift()
+        circ = cfg["circuit"]
+        spec = dict(cfg, chi=4096)
+        L = 64
+    n = circ.n
+    Aoff, Adiag = W.random_equatorial(n, L, rng)
+    say(f"sparsification bound {case} chi={spec['chi']} L={L}")
+    ctx = B.Context([spec])
+    ctx.apply_circuit(circ)
+    got = ctx.sparsification_bound(Aoff, Adiag)
+    T = O.Terms(circ, spec["chi"], O.SPARSIFY, seed=spec["seed"])
+    ref = T.sparsification_bound(Aoff, Adiag)
+    assert abs(got[0] - ref[0]) <= 1e-12 * abs(ref[0])
+    assert abs(got[1] - ref[1]) <= 1e-9 * abs(ref[1])
+    assert abs(got[2] - ref[2]) <= 1e-14 * ref[2]
+    assert abs(got[3] - ref[3]) <= 1e-12 * max(abs(ref[0]), 1.0)
+    with pytest.raises(B.ChsimError):
+        ctx.sparsification_bound(Aoff[:1], Adiag[:1])
+    ctx.close()
+    exact = dict(circuit=W.random_circuit(5, 30, [0.3, 1.1], rng), chi=4, mode="exact", seed=0)
+    ctx = B.Context([exact])
+    ctx.apply_circuit(exact["circuit"])
+    A2 = W.random_equatorial(5, 4, rng)
+    with pytest.raises(B.ChsimError):
+        ctx.sparsification_bound(*A2)
+    ctx.close()
