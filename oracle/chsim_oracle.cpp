@@ -217,6 +217,13 @@ struct CH {
       return;
     }
     int delta = (gamma[p] + 2 * (alpha + beta)) % 4;
+    superpose(t, u, alpha, delta);
+  }
+
+  // CH form of (-1)^alpha 2^{-1/2} U_C U_H (|t> + i^delta |u>) for t != u, by
+  // Proposition H and its proof (the second half of the Hadamard update).
+  void superpose(const std::vector<uint8_t>& t, const std::vector<uint8_t>& u, int alpha, int delta) {
+    const cplx I(0.0, 1.0);
     // Proof of Prop. H: subsets V_0, V_1 and the C-type circuit V_C.
     std::vector<int> V0, V1;
     for (int i = 0; i < n; ++i)
@@ -269,6 +276,32 @@ struct CH {
     s = y;
     s[q] = (uint8_t)fc;
     v[q] = (uint8_t)fb;  // W_H = U_H H_q^{b xor v_q}
+  }
+
+  // ---- projective gate (I + (-1)^bit Z_q) / 2, end of Sec. "Phase-sensitive
+  // Clifford simulator" ----
+  // Gamma U_C U_H |s> = (1/2) U_C U_H (I + Q) |s> with Q = U_H^-1 U_C^-1 P U_C U_H.
+  // U_C^-1 Z_q U_C = Z(G_q) (Eq. (tableaux)); conjugating by U_H = H(v) turns the
+  // Z on qubits with v_j = 1 into X: Q = (-1)^bit X(G_q & v) Z(G_q & ~v), so
+  // (I + Q)|s> = |s> + i^delta |t>, t = s + (G_q & v), i^delta = (-1)^{bit + (G_q & ~v).s}.
+  // Returns 1: state unchanged (t = s, i^delta = 1); 0: the projection is zero
+  // (t = s, i^delta = -1); 2: the state becomes 2^{-1/2} times the CH form of
+  // 2^{-1/2} U_C U_H (|s> + i^delta |t>) (Prop. H, as for the Hadamard).
+  int project_z(int q, int bit) {
+    std::vector<uint8_t> t(n);
+    int sign = bit;
+    bool same = true;
+    for (int j = 0; j < n; ++j) {
+      int gq = g(q, j);
+      t[j] = s[j] ^ (gq & v[j]);
+      if (t[j] != s[j]) same = false;
+      sign += gq * (1 - v[j]) * s[j];
+    }
+    sign %= 2;
+    if (same) return sign ? 0 : 1;
+    std::vector<uint8_t> s0 = s;
+    superpose(s0, t, 0, 2 * sign);
+    return 2;
   }
 
   // ---- amplitude <x|phi>, Eqs. (amplitude), (amplitude1) ----
@@ -865,6 +898,33 @@ int orc_ccz_decomp(int a, int b, int c, double* coeff, uint32_t* off, int32_t* g
   }
   return cnt;
 }
+// Apply prod_j (I + (-1)^{bits[j]} Z_{qubits[j]}) / 2 to every built term in order:
+// each CH form is updated and b_alpha scaled by 2^{-1/2} per code-2 step or set
+// to zero.  Returns the number of terms whose CH form went invalid (0 expected).
+int orc_terms_project(void* h, int w, const int32_t* qubits, const uint8_t* bits, int threads) {
+  Terms* T = (Terms*)h;
+  std::vector<int> bad(T->ch.size(), 0);
+  parallel_for(T->ch.size(), threads, [&](size_t a, int) {
+    for (int j = 0; j < w; ++j) {
+      if (T->b[a] == cplx(0.0, 0.0)) break;  // already projected away
+      int code = T->ch[a].project_z(qubits[j], bits[j]);
+      if (T->ch[a].error) { bad[a] = 1; return; }
+      if (code == 0) T->b[a] = 0.0;
+      else if (code == 2) T->b[a] *= 1.0 / std::sqrt(2.0);
+    }
+  });
+  int nb = 0;
+  for (int x : bad) nb += x;
+  return nb;
+}
+// One CH form: returns the code of project_z (and -1 on an invalid state).
+int orc_ch_project(void* h, int q, int bit) {
+  CH* c = (CH*)h;
+  int code = c->project_z(q, bit);
+  return c->error ? -1 : code;
+}
+// Copy of a term set (same circuit, same built terms).
+void* orc_terms_clone(void* h) { return new Terms(*(Terms*)h); }
 void orc_terms_free(void* h) { delete (Terms*)h; }
 int orc_terms_error(void* h) { return ((Terms*)h)->error; }
 double orc_terms_l1(void* h) { return ((Terms*)h)->l1; }

@@ -54,6 +54,10 @@ def lib():
     L.orc_terms_build.argtypes = [C.c_int, C.c_int, u8p, u8p, u8p, u8p, C.c_int, f64p, C.c_uint64,
                                   C.c_int, C.c_uint64, C.c_void_p, C.c_uint64, C.c_int]
     L.orc_ccz_decomp.argtypes = [C.c_int, C.c_int, C.c_int, f64p, u32p, i32p]
+    L.orc_terms_project.argtypes = [C.c_void_p, C.c_int, i32p, u8p, C.c_int]
+    L.orc_ch_project.argtypes = [C.c_void_p, C.c_int, C.c_int]
+    L.orc_terms_clone.argtypes = [C.c_void_p]
+    L.orc_terms_clone.restype = C.c_void_p
     L.orc_ccz_decomp.restype = C.c_int
     L.orc_terms_build.restype = C.c_void_p
     L.orc_terms_free.argtypes = [C.c_void_p]
@@ -157,6 +161,15 @@ class CHForm:
         if not nz:
             return 0j
         return complex(np.exp(1j * np.pi * k / 4) * 2.0 ** (-vc / 2))
+
+    def project(self, q: int, bit: int) -> int:
+        """(I + (-1)^bit Z_q) / 2 in place (end of Sec. "Phase-sensitive Clifford
+        simulator"): returns 1 (state unchanged), 0 (projected to zero) or 2 (the
+        state is now 2^{-1/2} times this CH form)."""
+        code = lib().orc_ch_project(self._h, int(q), int(bit))
+        if code < 0:
+            raise RuntimeError("projection produced an invalid CH form")
+        return code
 
     def sample(self, flips: int) -> int:
         return int(lib().orc_ch_sample(self._h, int(flips)))
@@ -284,6 +297,49 @@ class Terms:
         if bad:
             raise RuntimeError("oracle inner product produced an invalid record")
         return ov[0::2] + 1j * ov[1::2], eta
+
+    def clone(self) -> "Terms":
+        """An independent copy of the built terms (CH forms, b, branches)."""
+        c = Terms.__new__(Terms)
+        c.__dict__.update({k: v for k, v in self.__dict__.items() if k != "_h"})
+        c._h = lib().orc_terms_clone(self._h)
+        return c
+
+    def project(self, qubits, bits) -> None:
+        """Apply prod_j (I + (-1)^{bits_j} Z_{qubits_j}) / 2 to every term: CH forms
+        updated, b_alpha scaled by 2^{-1/2} or set to zero (Sec. "Phase-sensitive
+        Clifford simulator", projective gates)."""
+        qs = np.ascontiguousarray(qubits, np.int32)
+        bs = np.ascontiguousarray(bits, np.uint8)
+        if lib().orc_terms_project(self._h, qs.size, qs, bs, self.threads):
+            raise RuntimeError("projection produced an invalid CH form")
+
+    def sample_marginal(self, qubits, Aoff, Adiag, u):
+        """Chain-rule sampling of the listed qubits' bits (Sec. "Fast norm
+        estimation", sampling paragraph): P_w(x_1..x_w) = ||Pi psi||^2 / ||psi||^2
+        with Pi = prod_j (I + (-1)^{x_j} Z_j) / 2, and the bits drawn one by one
+        from P_j(x_j | x_1..x_{j-1}).  Each conditional is
+        e(x_1..x_{j-1}, 0) / (e(.., 0) + e(.., 1)), e the norm estimate (mean of
+        eta over the given equatorial states) of the projected terms; 1/2 when
+        both are zero.  Bit j is 0 iff u[j] < that probability.  Returns
+        (bits, probability of each chosen bit, the estimates e(.., 0), e(.., 1))."""
+        bits, probs, e0s, e1s = [], [], [], []
+        for j in range(len(qubits)):
+            est = []
+            for b in (0, 1):
+                c = self.clone()
+                c.project(qubits[: j + 1], bits + [b])
+                _, eta = c.inner(Aoff, Adiag)
+                est.append(float(np.mean(eta)))
+                del c
+            tot = est[0] + est[1]
+            p0 = est[0] / tot if tot > 0 else 0.5
+            x = 0 if u[j] < p0 else 1
+            bits.append(x)
+            probs.append(p0 if x == 0 else 1.0 - p0)
+            e0s.append(est[0])
+            e1s.append(est[1])
+        return bits, probs, e0s, e1s
 
     def sparsification_bound(self, Aoff, Adiag):
         """Lemma (Sparsification tail bound), Eq. (event): ||psi - Omega||^2 <=

@@ -639,3 +639,77 @@ def test_sparsification_expected_norm_excess():
     assert excess.mean() <= delta2 + 4 * excess.std(ddof=1) / np.sqrt(excess.size)
     # and the mean is (||c||_1^2 - 1) / k, the exact value the lemma's proof gives (below the stated bound)
     assert abs(excess.mean() - (T.l1**2 - 1) / k) < 4 * excess.std(ddof=1) / np.sqrt(excess.size)
+
+
+# ---------------------------------------------------------------------------
+# Projective gates (I + (-1)^b Z_q) / 2 and chain-rule marginals.
+# ---------------------------------------------------------------------------
+def test_projector_matches_dense():
+    rng = np.random.default_rng(3)
+    cover = {0: 0, 1: 0, 2: 0}
+    for _ in range(400):
+        n = int(rng.integers(1, 7))
+        g = W.random_clifford_gates(n, int(rng.integers(0, 40)), rng)
+        ch = O.CHForm(n)
+        for gg in g:
+            ch.apply(*gg)
+        psi = dense.run_gates(n, g)
+        q, b = int(rng.integers(n)), int(rng.integers(2))
+        code = ch.project(q, b)
+        cover[code] += 1
+        idx = np.arange(2**n)
+        want = psi * (((idx >> q) & 1) == b)
+        got = np.array([ch.amplitude(int(x)) for x in idx]) * {0: 0.0, 1: 1.0, 2: 2**-0.5}[code]
+        np.testing.assert_allclose(got, want, atol=1e-13)
+        assert ch.check() == 0
+    assert min(cover.values()) >= 40  # zeroed, unchanged and superposed states all occur
+
+
+def _dense_marginal(psi, n, qubits, bits):
+    idx = np.arange(2**n)
+    keep = np.ones(2**n, bool)
+    for q, b in zip(qubits, bits):
+        keep &= ((idx >> q) & 1) == b
+    return float(np.sum(np.abs(psi[keep]) ** 2))
+
+
+def test_projected_terms_give_dense_marginals():
+    rng = np.random.default_rng(14)
+    n = 6
+    g = W.random_clifford_gates(n, 70, rng)
+    circ = W.from_list(n, g[:25] + [(W.OP_CCZ, 0, 2, 5)] + g[25:50] + [(OP_SLOT, 3, 0, 1.3)] + g[50:])
+    psi = dense.run(circ)
+    T = O.Terms(circ, 16, O.EXACT)
+    xs = np.arange(2**n, dtype=np.uint64)
+    for qubits in ([0], [4, 1], [5, 0, 3]):
+        for bits in itertools.product((0, 1), repeat=len(qubits)):
+            c = T.clone()
+            c.project(qubits, list(bits))
+            a = c.amplitudes(xs)
+            assert abs(np.sum(np.abs(a) ** 2) - _dense_marginal(psi, n, qubits, bits)) < 1e-12
+    # the copy is independent: the original terms still give psi
+    np.testing.assert_allclose(T.amplitudes(xs), psi, atol=1e-12)
+
+
+def test_chain_rule_sampler_with_exact_norms():
+    """n = 3 with every A in M_3, so each norm estimate is exact: the sampler's
+    conditional probabilities are the dense ones along every path."""
+    circ = W.from_list(3, [(OP_H, 0, 0), (OP_H, 1, 0), (OP_H, 2, 0), (OP_SLOT, 1, 0, 0.8), (OP_CX, 1, 2),
+                           (W.OP_CCZ, 0, 1, 2), (OP_H, 0, 0), (OP_SLOT, 2, 0, 2.9), (OP_H, 2, 0)])
+    psi = dense.run(circ)
+    T = O.Terms(circ, 2 * 8 * 2, O.EXACT)
+    Aoff, Adiag = _all_equatorial(3)
+    qubits = [2, 0]
+    for path in itertools.product((0, 1), repeat=2):
+        u = [0.0 if b == 0 else 1.0 - 1e-12 for b in path]
+        bits, probs, e0, e1 = T.sample_marginal(qubits, Aoff, Adiag, u)
+        prefix = []
+        for j, b in enumerate(bits):
+            p_prev = _dense_marginal(psi, 3, qubits[:j], prefix)
+            p_b = _dense_marginal(psi, 3, qubits[: j + 1], prefix + [b])
+            assert abs(e0[j] - _dense_marginal(psi, 3, qubits[: j + 1], prefix + [0])) < 1e-12
+            assert abs(e1[j] - _dense_marginal(psi, 3, qubits[: j + 1], prefix + [1])) < 1e-12
+            assert abs(probs[j] - p_b / p_prev) < 1e-12
+            prefix.append(b)
+        if all(_dense_marginal(psi, 3, qubits[: j + 1], list(path[: j + 1])) > 1e-9 for j in range(2)):
+            assert bits == list(path)
