@@ -425,7 +425,7 @@ def bench_hidden_shift(torch, B, W, steps=5, warmup=2):
     n, chi = circ.n, cfg["chi"]
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
-    ctx = B.Context([cfg])
+    ctx = B.Context([cfg, cfg])  # instance 1: scratch store for the marginal sampler
     ctx.set_evolve_lanes(-1)
     ctx.set_amp_strings(-1)
     gates = B.gate_array(circ)
@@ -463,6 +463,15 @@ def bench_hidden_shift(torch, B, W, steps=5, warmup=2):
     t0 = time.perf_counter()
     est, sem, delta2, bound = ctx.sparsification_bound(Aoff, Adiag)
     t_bound = time.perf_counter() - t0
+    # Chain-rule sampling of 8 output bits by norm estimation (256 equatorial
+    # states per estimate, two estimates per bit); psi = |s>, so the bits are s's.
+    mq = list(range(8))
+    Am, Dm = W.random_equatorial(n, 256, rng)
+    um = rng.uniform(size=len(mq))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mbits, mprob, _ = ctx.sample_marginal(mq, Am, Dm, um)
+    t_marg = time.perf_counter() - t0
     a64 = out64.cpu().numpy()
     a32 = out32.cpu().numpy()
     c64 = a64[:, 0] + 1j * a64[:, 1]
@@ -490,6 +499,11 @@ def bench_hidden_shift(torch, B, W, steps=5, warmup=2):
                                      # psi = |s>: ||psi - Omega||^2 = <Omega|Omega> - 2 Re<s|Omega> + 1
                                      "psi_minus_omega_sq_from_estimate": est - 2 * float(c64[0].real) + 1,
                                      "equatorial_states": 1024, "seconds": t_bound},
+            "marginal_sampling": {"qubits": mq, "bits": mbits.tolist(),
+                                  "shift_bits": [int(cfg["s"] >> q & 1) for q in mq],
+                                  "conditional_probabilities": [round(float(p), 4) for p in mprob],
+                                  "equatorial_states_per_estimate": 256, "norm_estimates": 2 * len(mq),
+                                  "seconds": t_marg},
             "fp32c_vs_fp64_normwise": float(np.max(np.abs(c32 - c64)) / rms) if rms > 0 else 0.0,
             "evolve_shape": shape_name(lanes),
             "evolve_prefix_share": {"mode": pf_mode, "checkpoint_levels": pf_levels,

@@ -163,6 +163,38 @@ chsim_status chsim_inner_products(chsim_ctx* ctx, uint32_t inst, const uint64_t*
                                   const uint8_t* A_diag, size_t L, double* overlap, double* eta,
                                   double* eta_mean, uint32_t flags, void* stream);
 
+/* Projective gates (I + (-1)^{bits[j]} Z_{qubits[j]}) / 2, j < w, applied in order
+ * to every term of the instance in place (end of Sec. "Phase-sensitive Clifford
+ * simulator": Gamma|phi> = (1/2) U_C U_H (I + Q)|s>, with Q from the tableau
+ * row G_q and the CH form of the result by Prop. H).  A term is kept, scaled by
+ * 2^{-1/2} (b_alpha and its CH form updated), or projected to zero (b_alpha = 0),
+ * so the instance then holds Pi psi.  qubits, bits: host arrays of w entries.
+ * EINVAL: w > 64, a qubit >= n, a bit > 1, null arrays with w > 0. */
+chsim_status chsim_project_z(chsim_ctx* ctx, uint32_t inst, const uint32_t* qubits, const uint8_t* bits,
+                             uint32_t w, void* stream);
+
+/* Copy the term store (CH forms, b_alpha, and the branch choices when both
+ * have the same slot count) of src_inst into dst_inst, device to device.
+ * EINVAL: the instances differ in n or chi. */
+chsim_status chsim_terms_copy(chsim_ctx* ctx, uint32_t src_inst, uint32_t dst_inst, void* stream);
+
+/* Chain-rule sampling of w output bits by norm estimation (Sec. "Fast norm
+ * estimation", sampling paragraph: P_w(x) = ||Pi psi||^2 / ||psi||^2,
+ * Pi = prod_j (I + (-1)^{x_j} Z_j) / 2, bits drawn one by one).  For bit j the
+ * terms are copied into scratch_inst (same n and chi), projected onto
+ * (x_0..x_{j-1}, b) for b = 0 and 1, and their norms estimated over the L
+ * equatorial states (layout of chsim_inner_products, host arrays); the
+ * conditional probability of 0 is e_0 / (e_0 + e_1) (1/2 if both are zero),
+ * and x_j = 0 iff u[j] < it.  Writes bits_out[w], prob_out[w] (probability of
+ * each chosen bit given the previous ones) and, if est_out is not NULL,
+ * est_out[2j + b] = e_b.  Host arrays; synchronous; scratch_inst's terms are
+ * overwritten.  EINVAL: w not in 1..64, a qubit >= n, u[j] not in [0, 1),
+ * scratch_inst == inst or of another shape, null arrays, L == 0. */
+chsim_status chsim_sample_marginal(chsim_ctx* ctx, uint32_t inst, uint32_t scratch_inst, const uint32_t* qubits,
+                                   uint32_t w, const uint64_t* A_off, const uint8_t* A_diag, size_t L,
+                                   const double* u, uint8_t* bits_out, double* prob_out, double* est_out,
+                                   void* stream);
+
 /* Sparsification tail bound (Lemma (Sparsification tail bound), Eq. (event)):
  * for a normalised psi and chi >= ||c||_1^2 / delta^2 sparsified terms,
  * ||psi - Omega||^2 <= <Omega|Omega> - 1 + delta^2 with probability at least

@@ -32,6 +32,7 @@ MAX_BRANCH = 8
 EXPORTED = [
     "chsim_terms_init", "chsim_terms_reset", "chsim_apply_clifford", "chsim_amplitudes",
     "chsim_amplitudes_batch", "chsim_inner_products", "chsim_sparsification_bound",
+    "chsim_project_z", "chsim_terms_copy", "chsim_sample_marginal",
     "chsim_metropolis_init", "chsim_metropolis_step", "chsim_sample_terms", "chsim_get_terms",
     "chsim_set_terms", "chsim_decompose_phase", "chsim_decompose_ccz", "chsim_set_tuning", "chsim_get_tuning",
     "chsim_instance_info", "chsim_evolution_stats", "chsim_destroy", "chsim_mlp_create", "chsim_mlp_destroy",
@@ -112,6 +113,9 @@ def lib():
     L.chsim_amplitudes.argtypes = [vp, u32, vp, C.c_size_t, vp, u32, vp]
     L.chsim_inner_products.argtypes = [vp, u32, vp, vp, C.c_size_t, vp, vp, vp, u32, vp]
     L.chsim_sparsification_bound.argtypes = [vp, u32, vp, vp, C.c_size_t, C.POINTER(C.c_double), vp]
+    L.chsim_project_z.argtypes = [vp, u32, vp, vp, u32, vp]
+    L.chsim_terms_copy.argtypes = [vp, u32, u32, vp]
+    L.chsim_sample_marginal.argtypes = [vp, u32, u32, vp, u32, vp, vp, C.c_size_t, vp, vp, vp, vp, vp]
     L.chsim_metropolis_init.argtypes = [vp, u32, u32, vp, vp, u32, vp]
     L.chsim_metropolis_step.argtypes = [vp, u32, u32, vp, vp, vp, vp, vp, u32, vp]
     L.chsim_sample_terms.argtypes = [vp, u32, C.c_size_t, vp, vp, vp]
@@ -407,6 +411,29 @@ class Context:
                                           _ptr(ov)[0], _ptr(eta)[0], C.byref(mean), 0,
                                           _stream(stream)))
         return ov[0::2] + 1j * ov[1::2], eta, mean.value
+
+    def project_z(self, qubits, bits, inst=0, stream=None):
+        """Apply prod_j (I + (-1)^{bits_j} Z_{qubits_j}) / 2 to every term in place."""
+        qs = np.ascontiguousarray(qubits, np.uint32)
+        bs = np.ascontiguousarray(bits, np.uint8)
+        _check(lib().chsim_project_z(self._h, inst, _ptr(qs)[0], _ptr(bs)[0], qs.size, _stream(stream)))
+
+    def copy_terms(self, src_inst, dst_inst, stream=None):
+        _check(lib().chsim_terms_copy(self._h, src_inst, dst_inst, _stream(stream)))
+
+    def sample_marginal(self, qubits, Aoff, Adiag, u, inst=0, scratch_inst=1, stream=None):
+        """(bits, probability of each chosen bit, estimates [w, 2]) by the chain rule."""
+        qs = np.ascontiguousarray(qubits, np.uint32)
+        Aoff = np.ascontiguousarray(Aoff, np.uint64)
+        Adiag = np.ascontiguousarray(Adiag, np.uint8)
+        u = np.ascontiguousarray(u, np.float64)
+        bits = np.zeros(qs.size, np.uint8)
+        prob = np.zeros(qs.size)
+        est = np.zeros(2 * qs.size)
+        _check(lib().chsim_sample_marginal(self._h, inst, scratch_inst, _ptr(qs)[0], qs.size, _ptr(Aoff)[0],
+                                           _ptr(Adiag)[0], Aoff.shape[0], _ptr(u)[0], _ptr(bits)[0],
+                                           _ptr(prob)[0], _ptr(est)[0], _stream(stream)))
+        return bits, prob, est.reshape(-1, 2)
 
     def sparsification_bound(self, Aoff, Adiag, inst=0, stream=None):
         """(<Omega|Omega> estimate, its standard error, delta^2, bound on

@@ -1707,6 +1707,111 @@ chsim_status chsim_sparsification_bound(chsim_ctx* ctx, uint32_t inst, const uin
   return CHSIM_OK;
 }
 
+chsim_status chsim_project_z(chsim_ctx* ctx, uint32_t inst, const uint32_t* qubits, const uint8_t* bits,
+                             uint32_t w, void* stream) {
+  g_err.clear();
+  chsim_status st = check_ctx(ctx, inst);
+  if (st) return st;
+  if (w == 0) return CHSIM_OK;
+  if (!qubits || !bits) return fail(CHSIM_EINVAL, "null input");
+  Instance& I = ctx->inst[inst];
+  if (w > 64) return fail(CHSIM_EINVAL, "at most 64 projectors per call");
+  ProjGates P;
+  std::memset(&P, 0, sizeof P);
+  P.count = w;
+  for (uint32_t j = 0; j < w; ++j) {
+    if (qubits[j] >= I.n) return fail(CHSIM_EINVAL, "projector %u: qubit %u >= n %u", j, qubits[j], I.n);
+    if (bits[j] > 1) return fail(CHSIM_EINVAL, "projector %u: bit must be 0 or 1", j);
+    P.q[j] = (uint8_t)qubits[j];
+    P.bit[j] = bits[j];
+  }
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t s = as_stream(stream);
+  st = ensure_materialised(I, s);
+  if (st) return st;
+  HIP_TRY(launch_project(I.view(), P, s));
+  I.amp_ready = false;
+  return CHSIM_OK;
+}
+
+chsim_status chsim_terms_copy(chsim_ctx* ctx, uint32_t src_inst, uint32_t dst_inst, void* stream) {
+  g_err.clear();
+  chsim_status st = check_ctx(ctx, src_inst);
+  if (st) return st;
+  st = check_ctx(ctx, dst_inst);
+  if (st) return st;
+  if (src_inst == dst_inst) return CHSIM_OK;
+  Instance& A = ctx->inst[src_inst];
+  Instance& D = ctx->inst[dst_inst];
+  if (A.n != D.n || A.chi != D.chi) return fail(CHSIM_EINVAL, "instances differ in n or chi");
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t s = as_stream(stream);
+  st = ensure_materialised(A, s);
+  if (st) return st;
+  const TermsView a = A.view(), d = D.view();
+  const size_t rows = (size_t)A.n * A.chi;
+  HIP_TRY(hipMemcpyAsync(d.F, a.F, rows * 8, hipMemcpyDeviceToDevice, s));
+  HIP_TRY(hipMemcpyAsync(d.G, a.G, rows * 8, hipMemcpyDeviceToDevice, s));
+  HIP_TRY(hipMemcpyAsync(d.M, a.M, rows * 8, hipMemcpyDeviceToDevice, s));
+  HIP_TRY(hipMemcpyAsync(d.gamma, a.gamma, rows, hipMemcpyDeviceToDevice, s));
+  HIP_TRY(hipMemcpyAsync(d.v, a.v, A.chi * 8, hipMemcpyDeviceToDevice, s));
+  HIP_TRY(hipMemcpyAsync(d.s, a.s, A.chi * 8, hipMemcpyDeviceToDevice, s));
+  HIP_TRY(hipMemcpyAsync(d.omega, a.omega, A.chi, hipMemcpyDeviceToDevice, s));
+  HIP_TRY(hipMemcpyAsync(d.b, a.b, A.chi * sizeof(double2), hipMemcpyDeviceToDevice, s));
+  if (A.n_slot == D.n_slot && A.n_slot)
+    HIP_TRY(hipMemcpyAsync(d.branch, a.branch, (size_t)A.n_slot * A.chi, hipMemcpyDeviceToDevice, s));
+  D.at_zero = false;
+  D.amp_ready = false;
+  return CHSIM_OK;
+}
+
+chsim_status chsim_sample_marginal(chsim_ctx* ctx, uint32_t inst, uint32_t scratch_inst, const uint32_t* qubits,
+                                   uint32_t w, const uint64_t* A_off, const uint8_t* A_diag, size_t L,
+                                   const double* u, uint8_t* bits_out, double* prob_out, double* est_out,
+                                   void* stream) {
+  g_err.clear();
+  chsim_status st = check_ctx(ctx, inst);
+  if (st) return st;
+  st = check_ctx(ctx, scratch_inst);
+  if (st) return st;
+  if (scratch_inst == inst) return fail(CHSIM_EINVAL, "the scratch instance must differ from the sampled one");
+  if (w == 0 || w > 64) return fail(CHSIM_EINVAL, "w must be in 1..64");
+  if (!qubits || !u || !bits_out || !prob_out || !A_off || !A_diag || L == 0) return fail(CHSIM_EINVAL, "null input");
+  const Instance& I = ctx->inst[inst];
+  const Instance& S = ctx->inst[scratch_inst];
+  if (I.n != S.n || I.chi != S.chi) return fail(CHSIM_EINVAL, "scratch instance differs in n or chi");
+  for (uint32_t j = 0; j < w; ++j) {
+    if (qubits[j] >= I.n) return fail(CHSIM_EINVAL, "qubit %u >= n", qubits[j]);
+    if (!(u[j] >= 0.0 && u[j] < 1.0)) return fail(CHSIM_EINVAL, "uniform %u not in [0, 1)", j);
+  }
+  std::vector<double> ov(2 * L);
+  uint8_t bits[64];
+  for (uint32_t j = 0; j < w; ++j) {
+    // P(x_j = b | x_0..x_{j-1}) from the norm estimates of the terms projected
+    // onto (x_0..x_{j-1}, b), b = 0, 1.
+    double e[2];
+    for (uint8_t b = 0; b < 2; ++b) {
+      bits[j] = b;
+      st = chsim_terms_copy(ctx, inst, scratch_inst, stream);
+      if (st) return st;
+      st = chsim_project_z(ctx, scratch_inst, qubits, bits, j + 1, stream);
+      if (st) return st;
+      st = chsim_inner_products(ctx, scratch_inst, A_off, A_diag, L, ov.data(), nullptr, &e[b], 0u, stream);
+      if (st) return st;
+    }
+    const double tot = e[0] + e[1];
+    const double p0 = tot > 0.0 ? e[0] / tot : 0.5;
+    bits[j] = u[j] < p0 ? 0 : 1;
+    bits_out[j] = bits[j];
+    prob_out[j] = bits[j] ? 1.0 - p0 : p0;
+    if (est_out) {
+      est_out[2 * j] = e[0];
+      est_out[2 * j + 1] = e[1];
+    }
+  }
+  return CHSIM_OK;
+}
+
 chsim_status chsim_instance_info(chsim_ctx* ctx, uint32_t inst, uint32_t* n, uint64_t* chi, double* l1) {
   g_err.clear();
   chsim_status st = check_ctx(ctx, inst);

@@ -23,6 +23,98 @@ __device__ __forceinline__ uint32_t bmask(uint32_t x, uint32_t b) {
   return (uint32_t)__builtin_amdgcn_sbfe((int)x, b, 1u);
 }
 
+// CH form of (-1)^alpha 2^{-1/2} U_C U_H (|t> + i^delta |u>) for t != u, one
+// tableau row per lane (Prop. H and its proof): V_C's batches of right rules
+// applied to the lane's row, then the single-qubit part W_C = V_C S_q^a,
+// W_H = U_H H_q^{b xor v_q}, s' and omega'.  t, u, alpha, delta, v, s, w are
+// wave-uniform.
+__device__ __forceinline__ void superpose_w64(uint64_t& F, uint64_t& G, uint64_t& M, uint32_t& g, uint64_t& v,
+                                              uint64_t& s, uint32_t& w, uint64_t t, uint64_t u, uint32_t alpha,
+                                              uint32_t delta) {
+  const uint64_t nv = ~v;
+  const uint64_t d = t ^ u, V0 = d & nv, V1 = d & v;
+  const bool use0 = V0 != 0ull;
+  const uint32_t qh = (uint32_t)__builtin_ctzll(use0 ? V0 : V1);
+  const uint64_t qb = 1ull << qh;
+  const uint64_t W = (use0 ? V0 : V1) & ~qb;
+  // The lane's row as 32-bit halves; qs, hq locate bit qh.
+  const uint32_t qs = qh & 31u;
+  const bool hq = qh >= 32u;
+  const uint32_t qbl = (uint32_t)qb, qbh = (uint32_t)(qb >> 32);
+  const uint32_t Wl = (uint32_t)W, Wh = (uint32_t)(W >> 32);
+  uint32_t Fl = (uint32_t)F, Fh = (uint32_t)(F >> 32);
+  uint32_t Gl = (uint32_t)G, Gh = (uint32_t)(G >> 32);
+  uint32_t Ml = (uint32_t)M, Mh = (uint32_t)(M >> 32);
+  if (use0 && W == 0ull) {
+    // W empty (V_0 = {q}): only R[CZ_{q,i}], i in V_1.
+    const uint32_t V1l = (uint32_t)V1, V1h = (uint32_t)(V1 >> 32);
+    const uint32_t mf = bmask(hq ? Fh : Fl, qs);
+    const uint32_t c = (uint32_t)__popc(Fl & V1l) + (uint32_t)__popc(Fh & V1h);
+    const uint32_t mm = bmask(c, 0u);
+    Ml ^= (qbl & mm) ^ (V1l & mf);
+    Mh ^= (qbh & mm) ^ (V1h & mf);
+    g = (g + 2u * (mf & c & 1u)) & 3u;
+  } else if (use0) {
+    // R[CX_{q,i}], i in W: G_{.,q} ^= G_{.,i}; F_{.,i} ^= F_{.,q}; M_{.,q} ^= M_{.,i}.
+    // R[CZ_{q,i}], i in V_1: M_{.,q} ^= F_{.,i}; M_{.,i} ^= F_{.,q}; gamma += 2 F_{.,q} F_{.,i}.
+    const uint32_t V1l = (uint32_t)V1, V1h = (uint32_t)(V1 >> 32);
+    const uint32_t mf = bmask(hq ? Fh : Fl, qs);
+    const uint32_t mg = bmask((uint32_t)__popc(Gl & Wl) + (uint32_t)__popc(Gh & Wh), 0u);
+    Gl ^= qbl & mg;
+    Gh ^= qbh & mg;
+    Fl ^= Wl & mf;
+    Fh ^= Wh & mf;
+    const uint32_t c = (uint32_t)__popc(Fl & V1l) + (uint32_t)__popc(Fh & V1h);
+    const uint32_t mm = bmask(c + (uint32_t)__popc(Ml & Wl) + (uint32_t)__popc(Mh & Wh), 0u);
+    Ml ^= (qbl & mm) ^ (V1l & mf);
+    Mh ^= (qbh & mm) ^ (V1h & mf);
+    g = (g + 2u * (mf & c & 1u)) & 3u;
+  } else {
+    // R[CX_{i,q}], i in W: G_{.,i} ^= G_{.,q}; F_{.,q} ^= F_{.,i}; M_{.,i} ^= M_{.,q}.
+    const uint32_t mg = bmask(hq ? Gh : Gl, qs), mm = bmask(hq ? Mh : Ml, qs);
+    const uint32_t mf = bmask((uint32_t)__popc(Fl & Wl) + (uint32_t)__popc(Fh & Wh), 0u);
+    Gl ^= Wl & mg;
+    Gh ^= Wh & mg;
+    Fl ^= qbl & mf;
+    Fh ^= qbh & mf;
+    Ml ^= Wl & mm;
+    Mh ^= Wh & mm;
+  }
+  const uint32_t tq = (uint32_t)((t >> qh) & 1ull);
+  const uint64_t y = tq ? (u ^ qb) : t;  // y and z differ only in bit qh; y_qh = t_qh
+  const uint32_t vq = (uint32_t)((v >> qh) & 1ull);
+  // H^{v_q}(|y_q> + i^delta |1 - y_q>) = 2^{1/2} e^{i pi dw/4} S^a H^b |c>; for
+  // y_q = 1 factor out i^delta and use |0> + i^{-delta} |1>.
+  const uint32_t dp = tq ? ((4u - delta) & 3u) : delta;
+  const uint32_t ph = (2u * delta * tq) & 7u;
+  uint32_t a, b, cc, dw;
+  if (!vq) {
+    b = 1u;
+    a = dp & 1u;
+    cc = dp >> 1;
+    dw = ph;
+  } else {
+    b = dp & 1u;
+    a = dp & 1u;
+    cc = (dp == 2u || dp == 1u) ? 1u : 0u;
+    dw = ph + (dp == 1u ? 1u : (dp == 3u ? 7u : 0u));
+  }
+  if (a) {
+    // R[S_q]: M_{.,q} ^= F_{.,q}; gamma -= F_{.,q}.
+    const uint32_t fb = ((hq ? Fh : Fl) >> qs) & 1u;
+    const uint32_t mfb = 0u - fb;
+    Ml ^= qbl & mfb;
+    Mh ^= qbh & mfb;
+    g = (g - fb) & 3u;
+  }
+  F = ((uint64_t)Fh << 32) | Fl;
+  G = ((uint64_t)Gh << 32) | Gl;
+  M = ((uint64_t)Mh << 32) | Ml;
+  s = (y & ~qb) | ((uint64_t)cc << qh);
+  v = (v & ~qb) | ((uint64_t)b << qh);
+  w = (w + 4u * alpha + dw) & 7u;
+}
+
 template <bool kFromZero>
 __global__ __launch_bounds__(256) void k_evolve_w64(EvolveJob J, const DGate* __restrict__ gates,
                                                     uint32_t n_gates, uint32_t* __restrict__ err) {
@@ -104,87 +196,7 @@ __global__ __launch_bounds__(256) void k_evolve_w64(EvolveJob J, const DGate* __
           s = t;
           continue;
         }
-        const uint64_t d = t ^ u, V0 = d & nv, V1 = d & v;
-        const bool use0 = V0 != 0ull;
-        const uint32_t qh = (uint32_t)__builtin_ctzll(use0 ? V0 : V1);
-        const uint64_t qb = 1ull << qh;
-        const uint64_t W = (use0 ? V0 : V1) & ~qb;
-        // The lane's row as 32-bit halves; qs, hq locate bit qh.
-        const uint32_t qs = qh & 31u;
-        const bool hq = qh >= 32u;
-        const uint32_t qbl = (uint32_t)qb, qbh = (uint32_t)(qb >> 32);
-        const uint32_t Wl = (uint32_t)W, Wh = (uint32_t)(W >> 32);
-        uint32_t Fl = (uint32_t)F, Fh = (uint32_t)(F >> 32);
-        uint32_t Gl = (uint32_t)G, Gh = (uint32_t)(G >> 32);
-        uint32_t Ml = (uint32_t)M, Mh = (uint32_t)(M >> 32);
-        if (use0 && W == 0ull) {
-          // W empty (V_0 = {q}): only R[CZ_{q,i}], i in V_1.
-          const uint32_t V1l = (uint32_t)V1, V1h = (uint32_t)(V1 >> 32);
-          const uint32_t mf = bmask(hq ? Fh : Fl, qs);
-          const uint32_t c = (uint32_t)__popc(Fl & V1l) + (uint32_t)__popc(Fh & V1h);
-          const uint32_t mm = bmask(c, 0u);
-          Ml ^= (qbl & mm) ^ (V1l & mf);
-          Mh ^= (qbh & mm) ^ (V1h & mf);
-          g = (g + 2u * (mf & c & 1u)) & 3u;
-        } else if (use0) {
-          // R[CX_{q,i}], i in W: G_{.,q} ^= G_{.,i}; F_{.,i} ^= F_{.,q}; M_{.,q} ^= M_{.,i}.
-          // R[CZ_{q,i}], i in V_1: M_{.,q} ^= F_{.,i}; M_{.,i} ^= F_{.,q}; gamma += 2 F_{.,q} F_{.,i}.
-          const uint32_t V1l = (uint32_t)V1, V1h = (uint32_t)(V1 >> 32);
-          const uint32_t mf = bmask(hq ? Fh : Fl, qs);
-          const uint32_t mg = bmask((uint32_t)__popc(Gl & Wl) + (uint32_t)__popc(Gh & Wh), 0u);
-          Gl ^= qbl & mg;
-          Gh ^= qbh & mg;
-          Fl ^= Wl & mf;
-          Fh ^= Wh & mf;
-          const uint32_t c = (uint32_t)__popc(Fl & V1l) + (uint32_t)__popc(Fh & V1h);
-          const uint32_t mm = bmask(c + (uint32_t)__popc(Ml & Wl) + (uint32_t)__popc(Mh & Wh), 0u);
-          Ml ^= (qbl & mm) ^ (V1l & mf);
-          Mh ^= (qbh & mm) ^ (V1h & mf);
-          g = (g + 2u * (mf & c & 1u)) & 3u;
-        } else {
-          // R[CX_{i,q}], i in W: G_{.,i} ^= G_{.,q}; F_{.,q} ^= F_{.,i}; M_{.,i} ^= M_{.,q}.
-          const uint32_t mg = bmask(hq ? Gh : Gl, qs), mm = bmask(hq ? Mh : Ml, qs);
-          const uint32_t mf = bmask((uint32_t)__popc(Fl & Wl) + (uint32_t)__popc(Fh & Wh), 0u);
-          Gl ^= Wl & mg;
-          Gh ^= Wh & mg;
-          Fl ^= qbl & mf;
-          Fh ^= qbh & mf;
-          Ml ^= Wl & mm;
-          Mh ^= Wh & mm;
-        }
-        const uint32_t tq = (uint32_t)((t >> qh) & 1ull);
-        const uint64_t y = tq ? (u ^ qb) : t;  // y and z differ only in bit qh; y_qh = t_qh
-        const uint32_t vq = (uint32_t)((v >> qh) & 1ull);
-        // H^{v_q}(|y_q> + i^delta |1 - y_q>) = 2^{1/2} e^{i pi dw/4} S^a H^b |c>; for
-        // y_q = 1 factor out i^delta and use |0> + i^{-delta} |1>.
-        const uint32_t dp = tq ? ((4u - delta) & 3u) : delta;
-        const uint32_t ph = (2u * delta * tq) & 7u;
-        uint32_t a, b, cc, dw;
-        if (!vq) {
-          b = 1u;
-          a = dp & 1u;
-          cc = dp >> 1;
-          dw = ph;
-        } else {
-          b = dp & 1u;
-          a = dp & 1u;
-          cc = (dp == 2u || dp == 1u) ? 1u : 0u;
-          dw = ph + (dp == 1u ? 1u : (dp == 3u ? 7u : 0u));
-        }
-        if (a) {
-          // R[S_q]: M_{.,q} ^= F_{.,q}; gamma -= F_{.,q}.
-          const uint32_t fb = ((hq ? Fh : Fl) >> qs) & 1u;
-          const uint32_t mfb = 0u - fb;
-          Ml ^= qbl & mfb;
-          Mh ^= qbh & mfb;
-          g = (g - fb) & 3u;
-        }
-        F = ((uint64_t)Fh << 32) | Fl;
-        G = ((uint64_t)Gh << 32) | Gl;
-        M = ((uint64_t)Mh << 32) | Ml;
-        s = (y & ~qb) | ((uint64_t)cc << qh);
-        v = (v & ~qb) | ((uint64_t)b << qh);
-        w = (w + 4u * alpha + dw) & 7u;
+        superpose_w64(F, G, M, g, v, s, w, t, u, alpha, delta);
       } else if (op == OP_CX) {
         // gamma_q += gamma_r + 2 (M_q . F_r) (M_q before the update);
         // G_r ^= G_q; F_q ^= F_r; M_q ^= M_r.
@@ -230,6 +242,59 @@ __global__ __launch_bounds__(256) void k_evolve_w64(EvolveJob J, const DGate* __
   }
 }
 
+// Projective gates prod_j (I + (-1)^{bit_j} Z_{q_j}) / 2 on every term of the
+// store (end of Sec. "Phase-sensitive Clifford simulator"), one term per wave,
+// lane p holding row p.  U_C^{-1} Z_q U_C = Z(G_q), and conjugation by
+// U_H = H(v) turns the Z on qubits with v_j = 1 into X, so the Pauli acting on
+// |s> is Q = (-1)^bit X(G_q & v) Z(G_q & ~v) and (I + Q)|s> = |s> + i^delta |t>
+// with t = s ^ (G_q & v), i^delta = (-1)^{bit + par(G_q & ~v & s)}.  t = s: the
+// term stays (i^delta = 1) or is projected to zero (b = 0); otherwise Prop. H
+// gives the CH form of 2^{-1/2} U_C U_H (|s> + i^delta |t>) and b is scaled by
+// 2^{-1/2}.  A term with b = 0 is left as it is.
+__global__ __launch_bounds__(256) void k_project_w64(TermsView T, ProjGates P) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint64_t item = (uint64_t)blockIdx.x * 4u + uniform32(threadIdx.x >> 6);
+  if (item >= T.chi) return;  // whole waves; the kernel has no barrier
+  const uint32_t n = T.n;
+  const bool act = lane < n;
+  const uint64_t off = (uint64_t)lane * T.chi + item;
+  uint64_t F = act ? T.F[off] : 0ull, G = act ? T.G[off] : 0ull, M = act ? T.M[off] : 0ull;
+  uint32_t g = act ? (uint32_t)T.gamma[off] : 0u;
+  uint64_t v = uniform64(T.v[item]), s = uniform64(T.s[item]);
+  uint32_t w = uniform32(T.omega[item]);
+  double2 b = T.b[item];
+  bool zero = b.x == 0.0 && b.y == 0.0;
+  bool changed = false;
+  for (uint32_t j = 0; j < P.count && !zero; ++j) {
+    const uint32_t q = P.q[j];
+    const uint64_t Gq = rl64(G, q);
+    const uint64_t t = s ^ (Gq & v);
+    const uint32_t odd = ((uint32_t)P.bit[j] + par64(Gq & ~v & s)) & 1u;
+    if (t == s) {
+      zero = odd != 0u;
+      continue;
+    }
+    superpose_w64(F, G, M, g, v, s, w, s, t, 0u, 2u * odd);
+    b.x *= 0.70710678118654752440;
+    b.y *= 0.70710678118654752440;
+    changed = true;
+  }
+  if (changed) {
+    if (act) {
+      T.F[off] = F;
+      T.G[off] = G;
+      T.M[off] = M;
+      T.gamma[off] = (uint8_t)g;
+    }
+    if (lane == 0) {
+      T.v[item] = v;
+      T.s[item] = s;
+      T.omega[item] = (uint8_t)w;
+    }
+  }
+  if (lane == 0) T.b[item] = zero ? make_double2(0.0, 0.0) : b;
+}
+
 }  // namespace
 
 hipError_t launch_evolve_w64(const EvolveJob& J, const DGate* gates, uint32_t n_gates, bool from_zero,
@@ -240,6 +305,13 @@ hipError_t launch_evolve_w64(const EvolveJob& J, const DGate* gates, uint32_t n_
     hipLaunchKernelGGL(k_evolve_w64<true>, dim3(blocks), dim3(256), 0, st, J, gates, n_gates, err);
   else
     hipLaunchKernelGGL(k_evolve_w64<false>, dim3(blocks), dim3(256), 0, st, J, gates, n_gates, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_project(const TermsView& T, const ProjGates& P, hipStream_t st) {
+  const uint64_t blocks = (T.chi + 3) / 4;
+  if (blocks == 0 || P.count == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_project_w64, dim3((uint32_t)blocks), dim3(256), 0, st, T, P);
   return hipGetLastError();
 }
 

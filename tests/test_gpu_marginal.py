@@ -1,0 +1,194 @@
+"""GPU parity for projective gates (I + (-1)^b Z_q) / 2 on the term store and
+chain-rule marginal sampling by norm estimation, through the C ABI against the
+CPU oracle.
+
+Projected CH forms are bit-exact and b_alpha equal to the oracle's (the same
+products by 2^{-1/2} in the same order); amplitudes within 1e-12 normwise;
+norm estimates within 1e-12 relative.  The hidden-shift circuits add a closed
+form: the output is |s>, so every sampled bit is the shift's.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import dense
+import oracle as O
+from paper_1808_00128_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1808_00128_amd import binding
+
+    binding.lib()
+    return binding
+
+
+def compare_terms(ctx, T, idx):
+    for k, a in enumerate(idx):
+        g = ctx.get_terms(int(a), 1)
+        o = T.term(k).export()
+        for f in ("F", "G", "M", "gamma"):
+            assert np.array_equal(g[f][0], o[f]), (f, a)
+        for f in ("v", "s", "omega"):
+            assert int(g[f][0]) == o[f], (f, a)
+        ob = T.b(k)
+        assert abs(g["b"][0] - ob) <= 1e-15 * max(abs(ob), 1e-300), ("b", a)
+
+
+@pytest.mark.parametrize("n,chi,w", [(1, 4, 1), (12, 300, 3), (40, 1000, 6), (64, 257, 5)])
+def test_projection_bit_exact(B, n, chi, w):
+    """Every term projected on the GPU equals the oracle's projected term."""
+    rng = np.random.default_rng(500 + n)
+    circ = W.random_circuit(n, 20 * n + 10, rng.uniform(0, 2 * np.pi, size=min(6, 2 + n)), rng)
+    spec = dict(circuit=circ, chi=chi, mode="sparsify", seed=9 + n)
+    qubits = rng.choice(n, size=w, replace=w > n).tolist()
+    bits = rng.integers(0, 2, size=w).tolist()
+    say(f"projection n={n} chi={chi} qubits={qubits} bits={bits}")
+    ctx = B.Context([spec])
+    ctx.apply_circuit(circ)
+    ctx.project_z(qubits, bits)
+    T = O.Terms(circ, chi, O.SPARSIFY, seed=spec["seed"])
+    T.project(qubits, bits)
+    idx = np.arange(chi, dtype=np.uint64) if chi <= 300 else np.unique(
+        np.concatenate([[0, chi - 1], rng.integers(0, chi, size=200)])).astype(np.uint64)
+    Ts = O.Terms(circ, chi, O.SPARSIFY, seed=spec["seed"], alphas=idx)
+    Ts.project(qubits, bits)
+    compare_terms(ctx, Ts, idx)
+    zeros = sum(ctx.get_terms(int(a), 1)["b"][0] == 0 for a in idx)
+    say(f"projection n={n}: {zeros} of {idx.size} sampled terms projected to zero")
+    ctx.close()
+
+
+def _shallow_circuit(n, rng):
+    """H on three qubits, then only S, CX, CZ and phase slots: small |v|, so the
+    projections keep or zero many terms instead of superposing two basis states."""
+    gates = [(W.OP_H, q, 0) for q in rng.choice(n, size=3, replace=False).tolist()]
+    body = W.random_clifford_gates(n, 12 * n, rng, ops=(W.OP_S, W.OP_CX, W.OP_CZ))
+    for i, g in enumerate(body):
+        gates.append(g)
+        if i % (3 * n) == 0:
+            gates.append((W.OP_SLOT, int(rng.integers(n)), 0, float(rng.uniform(0, 2 * np.pi))))
+    return W.from_list(n, gates)
+
+
+@pytest.mark.parametrize("case", ["shallow-n50", "shallow-n64", "hidden-shift-n10"])
+def test_projection_keeps_zeroes_and_superposes(B, case):
+    """Circuits whose terms are close to basis states, every single-qubit
+    projection on a copy of the store (chsim_terms_copy): GPU terms equal the
+    oracle's, and over the sweep all three outcomes occur (term kept, projected
+    to zero, superposed and scaled by 2^{-1/2})."""
+    rng = np.random.default_rng(71)
+    if case.startswith("shallow"):
+        n = int(case.split("n")[-1])
+        circ = _shallow_circuit(n, rng)
+        chi, mode = 96, O.SPARSIFY
+    else:
+        n = 10
+        circ, _ = W.hidden_shift_circuit(n, 4, rng)
+        chi, mode = 8**4, O.EXACT
+    spec = dict(circuit=circ, chi=chi, mode="sparsify" if mode == O.SPARSIFY else "exact", seed=3)
+    idx = np.arange(chi, dtype=np.uint64) if chi <= 96 else np.unique(
+        np.concatenate([[0, chi - 1], rng.integers(0, chi, size=60)])).astype(np.uint64)
+    T = O.Terms(circ, chi, mode, seed=3, alphas=idx)
+    b0 = np.array([abs(T.b(k)) for k in range(idx.size)])
+    ctx = B.Context([spec, spec])
+    ctx.apply_circuit(circ)
+    kinds = np.zeros(3, int)
+    for q in rng.choice(n, size=min(n, 6), replace=False).tolist():
+        for bit in (0, 1):
+            say(f"projection {case}: qubit {q} bit {bit}")
+            Tp = T.clone()
+            Tp.project([q], [bit])
+            b1 = np.array([abs(Tp.b(k)) for k in range(idx.size)])
+            kinds += [(b1 == 0).sum(), (b1 == b0).sum(), ((b1 > 0) & (b1 < b0)).sum()]
+            ctx.copy_terms(0, 1)
+            ctx.project_z([q], [bit], inst=1)
+            for k, a in enumerate(idx):
+                g = ctx.get_terms(int(a), 1, inst=1)
+                o = Tp.term(k).export()
+                for f in ("F", "G", "M", "gamma"):
+                    assert np.array_equal(g[f][0], o[f]), (f, a, q, bit)
+                for f in ("v", "s", "omega"):
+                    assert int(g[f][0]) == o[f], (f, a, q, bit)
+                assert abs(g["b"][0] - Tp.b(k)) <= 1e-15 * max(abs(Tp.b(k)), 1e-300), ("b", a, q, bit)
+            del Tp
+    say(f"projection {case}: zero/kept/scaled = {kinds.tolist()}")
+    assert kinds.min() > 0
+    ctx.close()
+
+
+def test_projected_amplitudes_are_dense_projection(B):
+    rng = np.random.default_rng(31)
+    n = 10
+    circ = W.random_circuit(n, 200, rng.uniform(0, 2 * np.pi, size=6), rng)
+    spec = dict(circuit=circ, chi=64, mode="exact", seed=0)
+    psi = dense.run(circ)
+    idx = np.arange(2**n)
+    for qubits, bits in (([3], [1]), ([0, 7, 9], [0, 1, 1]), ([5, 5], [0, 1])):
+        ctx = B.Context([spec])
+        ctx.apply_circuit(circ)
+        ctx.project_z(qubits, bits)
+        keep = np.ones(2**n, bool)
+        for q, b in zip(qubits, bits):
+            keep &= ((idx >> q) & 1) == b
+        a = ctx.amplitudes(np.arange(2**n, dtype=np.uint64))
+        assert np.max(np.abs(a - psi * keep)) < 1e-12
+        ctx.close()
+
+
+def test_sample_marginal_matches_oracle(B):
+    rng = np.random.default_rng(77)
+    n, chi, L = 10, 300, 64
+    circ = W.random_circuit(n, 150, rng.uniform(0, 2 * np.pi, size=8), rng)
+    spec = dict(circuit=circ, chi=chi, mode="sparsify", seed=21)
+    Aoff, Adiag = W.random_equatorial(n, L, rng)
+    qubits = [4, 0, 9, 2]
+    u = rng.uniform(size=len(qubits))
+    say("sample marginal n=10 chi=300 L=64 w=4")
+    ctx = B.Context([spec, spec])
+    ctx.apply_circuit(circ)
+    bits, prob, est = ctx.sample_marginal(qubits, Aoff, Adiag, u)
+    T = O.Terms(circ, chi, O.SPARSIFY, seed=21)
+    obits, oprob, e0, e1 = T.sample_marginal(qubits, Aoff, Adiag, u)
+    np.testing.assert_allclose(est[:, 0], e0, rtol=1e-12, atol=1e-300)
+    np.testing.assert_allclose(est[:, 1], e1, rtol=1e-12, atol=1e-300)
+    assert bits.tolist() == obits
+    np.testing.assert_allclose(prob, oprob, rtol=1e-12)
+    # the sampled instance is untouched
+    a0 = ctx.amplitudes(W.random_bitstrings(n, 8, rng))
+    assert np.all(np.isfinite(a0))
+    with pytest.raises(B.ChsimError):
+        ctx.sample_marginal(qubits, Aoff, Adiag, u, scratch_inst=0)
+    with pytest.raises(B.ChsimError):
+        ctx.sample_marginal(qubits, Aoff, Adiag, np.array([0.5, 1.0, 0.1, 0.2]))
+    ctx.close()
+
+
+def test_sample_marginal_hidden_shift_recovers_s(B):
+    """n = 40, sixteen CCZ, chi = 110610 (the benchmark's workload): psi = |s>,
+    so the chain rule must return the shift's bits with probability near 1."""
+    cfg = W.config_hidden_shift()
+    rng = np.random.default_rng(5)
+    qubits = [0, 7, 19, 20, 33, 39]
+    Aoff, Adiag = W.random_equatorial(40, 64, rng)
+    say("sample marginal hidden shift n=40 chi=110610 L=64 w=6")
+    ctx = B.Context([cfg, cfg])
+    ctx.apply_circuit(cfg["circuit"])
+    bits, prob, est = ctx.sample_marginal(qubits, Aoff, Adiag, rng.uniform(size=len(qubits)))
+    want = [(cfg["s"] >> q) & 1 for q in qubits]
+    assert bits.tolist() == want
+    assert np.all(prob > 0.8)
+    ctx.close()
