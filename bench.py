@@ -532,7 +532,7 @@ def main():
                          "repeat the launches of a timed run")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is design-only",
+        print(json.dumps({"error": "bench.py runs on one GPU; sharding the terms over several GPUs is designed but not built",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
 
