@@ -61,6 +61,12 @@ def algorithmic_ops_amp(xs):
     return float(np.mean(6 * pc + 20))
 
 
+def progress(msg):
+    """One flushed line on stderr per bench section, so that a run that stops
+    early shows how far it got (the JSON result stays the only stdout line)."""
+    print(f"[bench] {time.strftime('%H:%M:%S')} {msg}", file=sys.stderr, flush=True)
+
+
 def cpu_baseline(cfg, sample_terms, threads):
     import oracle as O
 
@@ -277,6 +283,7 @@ def bench_learned(torch, B, W, stats, steps=1000, n_chain=64, chi=1 << 20, eps=0
     x0 = start_points(ctx, n, chi, n_chain, rng)
     burn = steps // 5
     graph = {}
+    progress("metropolis: plain chains (launches, then graph record and replay)")
     tr, ac, ms = run_plain(torch, ctx, x0, cfg["jstream"], cfg["ustream"], graph=graph)
     cost = stats.qaoa_cost(tr[:, burn:], cfg["triples"], cfg["d"])
     plain = chain_report(stats, tr, ac, ms, burn, cost)
@@ -288,8 +295,10 @@ def bench_learned(torch, B, W, stats, steps=1000, n_chain=64, chi=1 << 20, eps=0
                          "frac": round(achieved / 8000.0, 4), "traffic": None,
                          "bytes_per_step": bytes_step}
     delta = max(1, int(round(plain["tau_int"])))
+    progress("metropolis: training the proposal")
     net, train = train_proposal(B, W, ctx, n, tr, burn, delta)
     streams = W.learned_streams(n, n_chain, steps, np.random.default_rng(cfg["seed"] + 2))
+    progress("metropolis: learned chains")
     ltr, lac, lfl, lms = run_learned(torch, ctx, net, x0, streams, eps, pi_min, pi_max)
     lcost = stats.qaoa_cost(ltr[:, burn:], cfg["triples"], cfg["d"])
     learned = chain_report(stats, ltr, lac, lms, burn, lcost, lfl)
@@ -677,21 +686,29 @@ def main():
     }
     ctx.close()
     del ctx
+    progress(f"amplitudes step done: {ms_step:.3f} ms per step")
     sections = set(args.sections.split(","))
     if "norm" in sections:
+        progress("section norm")
         result["norm_estimation"] = bench_norm(torch, B, W)
     if "uneven" in sections:
+        progress("section uneven")
         result["uneven_batch"] = bench_uneven(torch, B, W)
     if "hidden_shift" in sections:
+        progress("section hidden_shift")
         result["hidden_shift_ccz"] = bench_hidden_shift(torch, B, W)
     if "metropolis" in sections:
         from paper_1808_00128_amd import stats
 
+        progress("section metropolis (QAOA n=50, plain, training, learned)")
         result["metropolis"] = bench_learned(torch, B, W, stats)
+        progress("section metropolis matched TV (n=12 twin)")
         result["metropolis"]["matched_tv"] = bench_matched_tv(torch, B, W, stats)
     if not args.no_cpu_baseline:
         threads = max(1, min(16, os.cpu_count() or 1))
+        progress(f"cpu baseline ({threads} threads)")
         result["cpu_baseline"] = cpu_baseline(cfg, args.cpu_sample_terms, threads)
+    progress("done")
     print(json.dumps(result), flush=True)
 
 

@@ -212,7 +212,11 @@ chsim_status chsim_sparsification_bound(chsim_ctx* ctx, uint32_t inst, const uin
 /* Start n_chain Metropolis chains at x0[c] (Sec. "Heuristic Metropolis
  * simulator"): caches, per chain and term, the Pauli Q_x as (u, mu) and
  * writes amp[2c..2c+1] = <x0_c|psi>.  Requires n <= 62.  EINVAL: some
- * <x0_c|psi> == 0 (P(x0) must be > 0). */
+ * <x0_c|psi> == 0 (P(x0) must be > 0).  The cache describes the terms as
+ * they are now: every call that changes them (chsim_apply_clifford,
+ * chsim_set_terms, chsim_project_z, chsim_terms_copy into the instance,
+ * chsim_terms_reset) drops the chains, and a later step returns EINVAL until
+ * chsim_metropolis_init runs again. */
 chsim_status chsim_metropolis_init(chsim_ctx* ctx, uint32_t inst, uint32_t n_chain,
                                    const uint64_t* x0, double* amp, uint32_t flags, void* stream);
 
@@ -304,11 +308,34 @@ chsim_status chsim_get_terms(chsim_ctx* ctx, uint32_t inst, uint64_t first, uint
                              uint64_t* s, uint8_t* omega, double* b, uint8_t* branch);
 
 /* Upload terms (same layout as chsim_get_terms; every field required except
- * branch).  Lets the query kernels run on CH-forms built elsewhere. */
+ * branch).  Lets the query kernels run on CH-forms built elsewhere.  EINVAL:
+ * a row, v or s with a bit >= n, gamma > 3 or omega > 7 (nothing is written
+ * then).  The invariants of Eq. (tableaux) are not checked here (see
+ * chsim_validate).  Chains started on the instance are dropped. */
 chsim_status chsim_set_terms(chsim_ctx* ctx, uint32_t inst, uint64_t first, uint64_t count,
                              const uint64_t* F, const uint64_t* G, const uint64_t* M,
                              const uint8_t* gamma, const uint64_t* v, const uint64_t* s,
                              const uint8_t* omega, const double* b);
+
+/* Debug check of the CH-form invariants of terms [first, first + count) of
+ * instance `inst` (Sec. "Phase-sensitive Clifford simulator", Eq. (tableaux):
+ * U_C^{-1} Z_p U_C = Z(G_p), U_C^{-1} X_p U_C = i^{gamma_p} X(F_p) Z(M_p)).
+ * Conjugation by U_C preserves the Pauli commutation relations and
+ * Hermiticity, so every term reachable by unitary evolution satisfies
+ *   CHSIM_BAD_TABLEAU:  F G^T = I over GF(2);
+ *   CHSIM_BAD_SYMMETRY: M F^T symmetric over GF(2);
+ *   CHSIM_BAD_GAMMA:    gamma_p = F_p . M_p (mod 2) for every row p;
+ *   CHSIM_BAD_RANGE:    rows, v and s have no bit >= n, gamma_p < 4, omega < 8.
+ * Writes *n_bad = number of terms violating at least one, *first_bad = the
+ * smallest such index (UINT64_MAX if none) and *what = OR of the flags seen;
+ * each output may be NULL.  Synchronous.  Returns CHSIM_ESTATE if some term
+ * is bad (outputs still written), EINVAL for a range beyond chi. */
+#define CHSIM_BAD_TABLEAU 1u
+#define CHSIM_BAD_SYMMETRY 2u
+#define CHSIM_BAD_GAMMA 4u
+#define CHSIM_BAD_RANGE 8u
+chsim_status chsim_validate(chsim_ctx* ctx, uint32_t inst, uint64_t first, uint64_t count,
+                            uint64_t* n_bad, uint64_t* first_bad, uint32_t* what);
 
 /* Decomposition of the phase gate diag(1, e^{i theta}) on `qubit`, Eq. (Rtheta)
  * after writing theta = theta' + k pi/2 with theta' in [0, pi/2):

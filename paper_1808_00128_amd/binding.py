@@ -25,6 +25,7 @@ CHSIM_TUNE_EVOLVE_LANES = 1
 CHSIM_TUNE_PREFIX_SHARE = 2
 CHSIM_TUNE_AMP_STRINGS = 3
 CHSIM_EVOLVE_LDS = 0x100
+CHSIM_BAD_TABLEAU, CHSIM_BAD_SYMMETRY, CHSIM_BAD_GAMMA, CHSIM_BAD_RANGE = 1, 2, 4, 8
 # evolution shapes the autotuner times, in the order of its timings
 TUNE_SHAPES = (4, 8, 16, 32, 64, 4 | CHSIM_EVOLVE_LDS, 8 | CHSIM_EVOLVE_LDS, 16 | CHSIM_EVOLVE_LDS)
 MAX_BRANCH = 8
@@ -34,7 +35,7 @@ EXPORTED = [
     "chsim_amplitudes_batch", "chsim_inner_products", "chsim_sparsification_bound",
     "chsim_project_z", "chsim_terms_copy", "chsim_sample_marginal",
     "chsim_metropolis_init", "chsim_metropolis_step", "chsim_sample_terms", "chsim_get_terms",
-    "chsim_set_terms", "chsim_decompose_phase", "chsim_decompose_ccz", "chsim_set_tuning", "chsim_get_tuning",
+    "chsim_set_terms", "chsim_validate", "chsim_decompose_phase", "chsim_decompose_ccz", "chsim_set_tuning", "chsim_get_tuning",
     "chsim_instance_info", "chsim_evolution_stats", "chsim_destroy", "chsim_mlp_create", "chsim_mlp_destroy",
     "chsim_mlp_get_params", "chsim_mlp_set_params", "chsim_mlp_forward", "chsim_mlp_loss_grad",
     "chsim_mlp_train", "chsim_metropolis_step_learned",
@@ -121,6 +122,8 @@ def lib():
     L.chsim_sample_terms.argtypes = [vp, u32, C.c_size_t, vp, vp, vp]
     L.chsim_get_terms.argtypes = [vp, u32, u64, u64, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.chsim_set_terms.argtypes = [vp, u32, u64, u64, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.chsim_validate.argtypes = [vp, u32, u64, u64, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64),
+                                 C.POINTER(C.c_uint32)]
     L.chsim_decompose_phase.argtypes = [dbl, u32, C.POINTER(C.c_double), C.POINTER(C.c_uint32),
                                         C.POINTER(Gate), C.POINTER(Decomp)]
     L.chsim_decompose_ccz.argtypes = [u32, u32, u32, C.POINTER(C.c_double), C.POINTER(C.c_uint32),
@@ -516,6 +519,17 @@ class Context:
         _check(lib().chsim_set_terms(self._h, inst, first, count, *[_ptr(a)[0] for a in arrs],
                                      _ptr(bb)[0]))
 
+    def validate(self, first=0, count=None, inst=0):
+        """CH-form invariants of terms [first, first + count): (bad terms, first
+        bad index or None, OR of the CHSIM_BAD_* flags).  Raises nothing for
+        bad terms (the call's ESTATE is reported through the counts)."""
+        if count is None:
+            count = self.info(inst)[1] - first
+        nb, fb, what = C.c_uint64(), C.c_uint64(), C.c_uint32()
+        st = lib().chsim_validate(self._h, inst, first, count, C.byref(nb), C.byref(fb), C.byref(what))
+        if st not in (CHSIM_OK, CHSIM_ESTATE):
+            _check(st)
+        return nb.value, (fb.value if nb.value else None), what.value
 
     def metropolis_step_learned(self, mlp, u_mix, j, u_bits, u, eps, pi_min, pi_max, inst=0,
                                 stream=None):

@@ -119,7 +119,10 @@ struct Instance {
   };
   std::vector<SpanStat> last_spans;
   // Metropolis steps recorded as a graph, and what they were recorded with.
+  // metro_done is recorded after every launch of the graph, so the graph is
+  // destroyed only once its last launch has finished.
   hipGraphExec_t metro_exec = nullptr;
+  hipEvent_t metro_done = nullptr;
   MetroView metro_key{};
   TermsView metro_tkey{};
   uint32_t metro_steps = 0;
@@ -152,9 +155,24 @@ struct Instance {
     t.branch = branch.p;
     return t;
   }
-  void release() {
-    if (metro_exec) hipGraphExecDestroy(metro_exec);
+  void drop_graph() {
+    if (metro_exec) {
+      if (metro_done) hipEventSynchronize(metro_done);
+      hipGraphExecDestroy(metro_exec);
+    }
     metro_exec = nullptr;
+  }
+  // The chain cache (Q_x per chain and term, the chain amplitudes and the
+  // recorded steps) describes the terms at chsim_metropolis_init; every call
+  // that changes the terms drops it.
+  void drop_chains() {
+    n_chain = 0;
+    drop_graph();
+  }
+  void release() {
+    drop_graph();
+    if (metro_done) hipEventDestroy(metro_done);
+    metro_done = nullptr;
     F.release(); G.release(); M.release(); v.release(); s.release();
     gamma.release(); omega.release(); branch.release(); b.release();
     slots.release();
@@ -180,6 +198,7 @@ struct chsim_ctx {
   DevBuf<uint8_t> adiag;
   DevBuf<double> eta;
   DevBuf<double> eta_sum;
+  DevBuf<unsigned long long> vcheck;  // chsim_validate: bad count, first bad index, flags
   // Amplitude work queue: device copies of the last plan, and its host key.
   DevBuf<AmpInst> amp_insts;
   DevBuf<AmpItem> amp_items;
@@ -443,7 +462,7 @@ chsim_status chsim_terms_reset(chsim_ctx* ctx, uint32_t inst, uint64_t seed, voi
   HIP_TRY(launch_choose(I.view(), I.slots.p, I.mode, I.seed, scale, as_stream(stream)));
   I.at_zero = true;
   I.amp_ready = false;
-  I.n_chain = 0;
+  I.drop_chains();
   return CHSIM_OK;
 }
 
@@ -901,6 +920,7 @@ chsim_status chsim_apply_clifford(chsim_ctx* ctx, uint32_t inst, const chsim_gat
     ctx->dg_in.assign(gates, gates + n_gates);
     ctx->dg_inst = inst;
   }
+  I.drop_chains();
   HIP_TRY(hipMemsetAsync(ctx->err.p, 0, sizeof(uint32_t), s));
   if (I.autotune && I.at_zero) {
     // Every shape computes the same terms from |0^n>, so timing all of them in
@@ -1361,8 +1381,7 @@ chsim_status chsim_metropolis_step(chsim_ctx* ctx, uint32_t inst, uint32_t n_ste
                       std::memcmp(&I.metro_key, &mv, sizeof mv) == 0 &&
                       std::memcmp(&I.metro_tkey, &tv, sizeof tv) == 0;
     if (!same) {
-      if (I.metro_exec) HIP_TRY(hipGraphExecDestroy(I.metro_exec));
-      I.metro_exec = nullptr;
+      I.drop_graph();
       if (!ctx->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
       hipGraph_t g = nullptr;
       HIP_TRY(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
@@ -1378,6 +1397,8 @@ chsim_status chsim_metropolis_step(chsim_ctx* ctx, uint32_t inst, uint32_t n_ste
       I.metro_steps = n_steps;
     }
     HIP_TRY(hipGraphLaunch(I.metro_exec, s));
+    if (!I.metro_done) HIP_TRY(hipEventCreateWithFlags(&I.metro_done, hipEventDisableTiming));
+    HIP_TRY(hipEventRecord(I.metro_done, s));
   } else {
     HIP_TRY(launch_metro_steps(I.view(), mv, n_steps, s));
   }
@@ -1472,11 +1493,27 @@ chsim_status chsim_set_terms(chsim_ctx* ctx, uint32_t inst, uint64_t first, uint
   if (first > I.chi || count > I.chi - first) return fail(CHSIM_EINVAL, "term range out of bounds");
   if (!F || !G || !M || !gamma || !v || !s || !omega || !b) return fail(CHSIM_EINVAL, "null field");
   if (count == 0) return CHSIM_OK;
+  const uint32_t n = I.n;
+  {
+    // Words the kernels index by (ctz of v-derived masks, row selections)
+    // must stay below bit n; gamma is in Z_4 and omega in Z_8.
+    const uint64_t hi = (n == 64) ? 0ull : ~((1ull << n) - 1ull);
+    for (uint64_t a = 0; a < count; ++a) {
+      if ((v[a] | s[a]) & hi) return fail(CHSIM_EINVAL, "term %llu: v or s has a bit >= n", (unsigned long long)a);
+      if (omega[a] > 7) return fail(CHSIM_EINVAL, "term %llu: omega %u not in Z_8", (unsigned long long)a, omega[a]);
+      for (uint32_t p = 0; p < n; ++p) {
+        const size_t i = (size_t)a * n + p;
+        if ((F[i] | G[i] | M[i]) & hi)
+          return fail(CHSIM_EINVAL, "term %llu row %u has a bit >= n", (unsigned long long)a, p);
+        if (gamma[i] > 3) return fail(CHSIM_EINVAL, "term %llu: gamma_%u not in Z_4", (unsigned long long)a, p);
+      }
+    }
+  }
   HIP_TRY(hipSetDevice(ctx->device));
   st = ensure_materialised(I, nullptr);
   if (st) return st;
+  I.drop_chains();
   HIP_TRY(hipDeviceSynchronize());
-  const uint32_t n = I.n;
   auto rows = [&](uint64_t* dst, const uint64_t* src) -> chsim_status {
     std::vector<uint64_t> tmp((size_t)n * count);
     for (uint32_t p = 0; p < n; ++p)
@@ -1490,7 +1527,7 @@ chsim_status chsim_set_terms(chsim_ctx* ctx, uint32_t inst, uint64_t first, uint
   {
     std::vector<uint8_t> tmp((size_t)n * count);
     for (uint32_t p = 0; p < n; ++p)
-      for (uint64_t a = 0; a < count; ++a) tmp[(size_t)p * count + a] = gamma[a * n + p] & 3;
+      for (uint64_t a = 0; a < count; ++a) tmp[(size_t)p * count + a] = gamma[a * n + p];
     HIP_TRY(hipMemcpy2D(I.gamma.p + first, I.chi, tmp.data(), count, count, n, hipMemcpyHostToDevice));
   }
   HIP_TRY(hipMemcpy(I.v.p + first, v, count * 8, hipMemcpyHostToDevice));
@@ -1498,6 +1535,28 @@ chsim_status chsim_set_terms(chsim_ctx* ctx, uint32_t inst, uint64_t first, uint
   HIP_TRY(hipMemcpy(I.omega.p + first, omega, count, hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(I.b.p + first, b, count * 16, hipMemcpyHostToDevice));
   I.amp_ready = false;
+  return CHSIM_OK;
+}
+
+chsim_status chsim_validate(chsim_ctx* ctx, uint32_t inst, uint64_t first, uint64_t count,
+                            uint64_t* n_bad, uint64_t* first_bad, uint32_t* what) {
+  g_err.clear();
+  chsim_status st = check_ctx(ctx, inst);
+  if (st) return st;
+  Instance& I = ctx->inst[inst];
+  if (first > I.chi || count > I.chi - first) return fail(CHSIM_EINVAL, "term range out of bounds");
+  HIP_TRY(hipSetDevice(ctx->device));
+  st = ensure_materialised(I, nullptr);
+  if (st) return st;
+  HIP_TRY(ctx->vcheck.ensure(3));
+  HIP_TRY(launch_validate(I.view(), first, count, ctx->vcheck.p, nullptr));
+  unsigned long long h[3] = {0ull, ~0ull, 0ull};
+  HIP_TRY(hipMemcpy(h, ctx->vcheck.p, sizeof h, hipMemcpyDeviceToHost));
+  if (n_bad) *n_bad = h[0];
+  if (first_bad) *first_bad = h[1];
+  if (what) *what = (uint32_t)h[2];
+  if (h[0]) return fail(CHSIM_ESTATE, "%llu of %llu terms violate a CH-form invariant (first %llu, flags %llu)",
+                        h[0], (unsigned long long)count, h[1], h[2]);
   return CHSIM_OK;
 }
 
@@ -1729,6 +1788,7 @@ chsim_status chsim_project_z(chsim_ctx* ctx, uint32_t inst, const uint32_t* qubi
   hipStream_t s = as_stream(stream);
   st = ensure_materialised(I, s);
   if (st) return st;
+  I.drop_chains();
   HIP_TRY(launch_project(I.view(), P, s));
   I.amp_ready = false;
   return CHSIM_OK;
@@ -1748,6 +1808,7 @@ chsim_status chsim_terms_copy(chsim_ctx* ctx, uint32_t src_inst, uint32_t dst_in
   hipStream_t s = as_stream(stream);
   st = ensure_materialised(A, s);
   if (st) return st;
+  D.drop_chains();
   const TermsView a = A.view(), d = D.view();
   const size_t rows = (size_t)A.n * A.chi;
   HIP_TRY(hipMemcpyAsync(d.F, a.F, rows * 8, hipMemcpyDeviceToDevice, s));
@@ -1860,6 +1921,7 @@ chsim_status chsim_destroy(chsim_ctx* ctx) {
   ctx->adiag.release();
   ctx->eta.release();
   ctx->eta_sum.release();
+  ctx->vcheck.release();
   delete ctx;
   return CHSIM_OK;
 }

@@ -177,6 +177,11 @@ struct PrefixLevelArgs {
 hipError_t launch_prefix_level(const PrefixLevelArgs& A, hipStream_t st);
 hipError_t launch_sample(const TermsView& T, const uint64_t* alpha, const uint64_t* flips,
                          uint64_t* x_out, uint32_t count, hipStream_t st);
+// CH-form invariants of terms [first, first + count): out[0] = terms that
+// violate one, out[1] = the smallest such index (~0 if none), out[2] = OR of
+// the CHSIM_BAD_* flags seen.
+hipError_t launch_validate(const TermsView& T, uint64_t first, uint64_t count, unsigned long long* out,
+                           hipStream_t st);
 
 // Amplitudes.  Per-term values the amplitude kernel reads, computed by a
 // prologue kernel from the term store: ~v masked to n bits, the value folded

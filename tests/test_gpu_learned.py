@@ -187,6 +187,39 @@ def test_learned_chain_matches_oracle_until_near_tie(B):
     assert fl.mean() > 1.0  # multi-bit moves happen
 
 
+def test_learned_chain_full_grid_matches_oracle(B):
+    """chi = 2^19 (2048 tiles of 256 terms, as many as the QAOA workload's
+    grid holds per 2^20 / 2): the flip-mask proposal kernel and the
+    corrected accept step against the oracle chain until the first near tie."""
+    n, chi, C_, steps = 10, 1 << 19, 4, 30
+    rng = np.random.default_rng(6200)
+    circ = W.random_circuit(n, 60, rng.uniform(0, 2 * np.pi, size=20), rng)
+    spec = dict(circuit=circ, chi=chi, mode="sparsify", seed=612)
+    say(f"learned chain full grid n={n} chi={chi} chains={C_} steps={steps}")
+    ctx = B.Context([spec])
+    ctx.apply_circuit(circ)
+    T = O.Terms(circ, chi, O.SPARSIFY, seed=612)
+    x0 = start_states(T, n, C_, rng, chi)
+    p = varied_params(n, 32, seed=5)
+    net = B.MLP(ctx, n, 32, 64, p)
+    ref = OM.MLPRef(p, n, 32)
+    u_mix, j, u_bits, u = W.learned_streams(n, C_, steps, rng)
+    ctx.metropolis_init(x0)
+    tr, acc, fl, amp = ctx.metropolis_step_learned(net, u_mix, j, u_bits, u, 0.2, 0.01, 0.5)
+    otr, oacc, ofl, tie = OM.learned_chain(T, ref, x0, u_mix, j, u_bits, u, 0.2, 0.01, 0.5)
+    compared = 0
+    for c in range(C_):
+        k = int(tie[c])
+        assert np.array_equal(tr[c, :k], otr[c, :k]), c
+        assert np.array_equal(acc[c, :k], oacc[c, :k]), c
+        assert np.array_equal(fl[c, :k], ofl[c, :k]), c
+        compared += k
+    assert compared >= 0.9 * C_ * steps
+    assert fl.mean() > 1.0
+    net.close()
+    ctx.close()
+
+
 def test_learned_chain_stationary_law(B):
     """The corrected chain samples P: TV to the exact law at n = 8."""
     n, chi = 8, 64
