@@ -151,6 +151,24 @@ typedef struct chsim_amp_request {
 chsim_status chsim_amplitudes_batch(chsim_ctx* ctx, const chsim_amp_request* reqs, size_t n_req,
                                     uint32_t flags, void* stream);
 
+/* chsim_amplitudes for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same formula, kernels and results as chsim_amplitudes with the same
+ * flags, but every intermediate (the prologue rows and term constants, the
+ * per-range partial sums, the work items and the queue counter) lives in a
+ * fixed device array of 64 MiB that the library's code object holds on each
+ * GPU until the process ends; no hipMalloc, hipFree or other allocating call
+ * is made.  Requires CHSIM_DEVICE_PTRS (x and out are device pointers) and
+ * enqueues only.  Uses the context's current bitstrings-per-item value and
+ * never runs the autotuner.  The array is shared by every call on one GPU and
+ * keeps the last call's contents: two calls that overlap in time on the same
+ * GPU (different streams, threads or contexts) race and give wrong results.
+ * EINVAL: host pointers, n_x == 0, null arrays, or a request whose
+ * intermediates exceed the array (about 8 n chi + 64 chi + 16 n_x ranges
+ * bytes; n = 50, chi = 2^16, 4096 strings needs 47 MB). */
+chsim_status chsim_amplitudes_noalloc(chsim_ctx* ctx, uint32_t inst, const uint64_t* x, size_t n_x,
+                                      double* out, uint32_t flags, void* stream);
+
 /* Norm estimation with equatorial states phi_A, A in M_n (Eq. (eqa1)):
  * A_off[l*n + a] = row a of the off-diagonal part of A_l (bit b = A_ab; bit a
  * ignored), A_diag[l*n + a] = A_aa in {0..3}.  overlap[2l..2l+1] = <phi_{A_l}|psi>

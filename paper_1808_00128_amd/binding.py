@@ -32,7 +32,7 @@ MAX_BRANCH = 8
 
 EXPORTED = [
     "chsim_terms_init", "chsim_terms_reset", "chsim_apply_clifford", "chsim_amplitudes",
-    "chsim_amplitudes_batch", "chsim_inner_products", "chsim_sparsification_bound",
+    "chsim_amplitudes_batch", "chsim_amplitudes_noalloc", "chsim_inner_products", "chsim_sparsification_bound",
     "chsim_project_z", "chsim_terms_copy", "chsim_sample_marginal",
     "chsim_metropolis_init", "chsim_metropolis_step", "chsim_sample_terms", "chsim_get_terms",
     "chsim_set_terms", "chsim_validate", "chsim_decompose_phase", "chsim_decompose_ccz", "chsim_set_tuning", "chsim_get_tuning",
@@ -112,6 +112,7 @@ def lib():
     L.chsim_terms_reset.argtypes = [vp, u32, u64, vp]
     L.chsim_apply_clifford.argtypes = [vp, u32, vp, C.c_size_t, vp]
     L.chsim_amplitudes.argtypes = [vp, u32, vp, C.c_size_t, vp, u32, vp]
+    L.chsim_amplitudes_noalloc.argtypes = [vp, u32, vp, C.c_size_t, vp, u32, vp]
     L.chsim_inner_products.argtypes = [vp, u32, vp, vp, C.c_size_t, vp, vp, vp, u32, vp]
     L.chsim_sparsification_bound.argtypes = [vp, u32, vp, vp, C.c_size_t, C.POINTER(C.c_double), vp]
     L.chsim_project_z.argtypes = [vp, u32, vp, vp, u32, vp]
@@ -367,6 +368,17 @@ class Context:
             raise ValueError("torch inputs must be on the GPU")
         _check(lib().chsim_amplitudes(self._h, inst, px, x.numel(), po, flags | CHSIM_DEVICE_PTRS,
                                       _stream(stream)))
+        return out
+
+    def amplitudes_noalloc(self, x, out, inst=0, fp32c=False, stream=None):
+        """chsim_amplitudes_noalloc: x a CUDA int64 tensor, out a CUDA float64
+        tensor [n_x, 2] the caller allocated; the library allocates nothing."""
+        flags = (CHSIM_FP32C if fp32c else CHSIM_FP64) | CHSIM_DEVICE_PTRS
+        px, f1 = _ptr(x)
+        po, f2 = _ptr(out)
+        if not (f1 and f2):
+            raise ValueError("chsim_amplitudes_noalloc takes device tensors")
+        _check(lib().chsim_amplitudes_noalloc(self._h, inst, px, x.numel(), po, flags, _stream(stream)))
         return out
 
     def amplitudes_batch(self, requests, fp32c=False, stream=None):

@@ -452,6 +452,55 @@ void amp_plan(const std::vector<AmpRequestPlan>& reqs, uint32_t target_items, ui
                    [&](const AmpItem& a, const AmpItem& b) { return cost(a) > cost(b); });
 }
 
+namespace {
+
+// Plan of one request written on the device: the request record, the
+// bitstring prefix [0, n_x], and item i = (range i / chunks, chunk i % chunks).
+// Items are independent (each writes its own partials), so their order does
+// not change the result.
+__global__ __launch_bounds__(256) void k_fill_single_plan(AmpInst inst, AmpInst* insts_d, AmpItem* items_d,
+                                                          uint64_t* prefix_d, uint32_t n_items,
+                                                          uint32_t chunks, uint32_t x_chunk) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) {
+    insts_d[0] = inst;
+    prefix_d[0] = 0ull;
+    prefix_d[1] = inst.n_x;
+  }
+  if (i >= n_items) return;
+  const uint32_t rg = i / chunks, c = i % chunks;
+  const uint32_t x0 = c * x_chunk;
+  const uint32_t x1 = x0 + x_chunk < inst.n_x ? x0 + x_chunk : inst.n_x;
+  items_d[i] = AmpItem{0u, rg, x0, x1};
+}
+
+}  // namespace
+
+void amp_plan_single(uint64_t chi, uint32_t n_x, uint32_t target_items, uint32_t xpl, uint32_t* tiles_per_range,
+                     uint32_t* n_ranges, uint32_t* chunks) {
+  // The range length amp_plan chooses for one request.
+  const uint32_t x_chunk = 256u * xpl;
+  const uint64_t tiles = (chi + kTT - 1) / kTT;
+  const uint64_t ch = (n_x + x_chunk - 1) / x_chunk;
+  uint64_t per = 1;
+  if (tiles > 0 && ch > 0) {
+    const double want_ranges = (double)target_items / (double)ch;
+    per = (uint64_t)((double)tiles / want_ranges);
+    per = std::min<uint64_t>(std::max<uint64_t>(per, 1), 512);
+  }
+  *tiles_per_range = (uint32_t)per;
+  *n_ranges = (uint32_t)((tiles + per - 1) / per);
+  *chunks = (uint32_t)ch;
+}
+
+hipError_t launch_amp_fill_single(const AmpInst& inst, AmpInst* insts_d, AmpItem* items_d, uint64_t* prefix_d,
+                                  uint32_t n_items, uint32_t chunks, uint32_t xpl, hipStream_t st) {
+  const uint32_t blocks = (n_items + 255u) / 256u;
+  hipLaunchKernelGGL(k_fill_single_plan, dim3(blocks ? blocks : 1), dim3(256), 0, st, inst, insts_d, items_d,
+                     prefix_d, n_items, chunks, 256u * xpl);
+  return hipGetLastError();
+}
+
 hipError_t launch_amp_items(const AmpInst* insts_d, const AmpItem* items_d, uint32_t n_items,
                             uint32_t* counter, bool fp32c, uint32_t xpl, const uint64_t* prefix_d,
                             uint32_t n_inst, uint64_t total_x, hipStream_t st) {

@@ -12,6 +12,7 @@
 #include <cstring>
 #include <string>
 #include <map>
+#include <mutex>
 #include <vector>
 
 #include "chsim.h"
@@ -23,6 +24,16 @@ using namespace chsim;
 namespace {
 
 thread_local std::string g_err;
+
+// Device scratch of chsim_amplitudes_noalloc: one array per GPU, part of the
+// code object (no allocation call), shared by every call on that GPU.
+constexpr size_t kNoAllocScratch = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratch];
+// Its device address on each GPU, taken once with that GPU current.  In host
+// code `scratch` names a host-side stand-in, never the device memory.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
 
 chsim_status fail(chsim_status st, const char* fmt, ...) {
   char buf[512];
@@ -374,6 +385,21 @@ chsim_status ensure_materialised(Instance& I, hipStream_t st) {
   return CHSIM_OK;
 }
 
+// Device address of `scratch` on the current device `device` (taken once).
+chsim_status scratch_address(int device, void** out) {
+  if (device < 0 || device >= kMaxDevices) return fail(CHSIM_EUNSUPPORTED, "device %d beyond %d", device, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(CHSIM_EDEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", device, hipGetErrorString(e));
+    g_scratch_ptr[device] = p;
+  }
+  *out = g_scratch_ptr[device];
+  return CHSIM_OK;
+}
+
 chsim_status check_err_flag(chsim_ctx* ctx, hipStream_t st, const char* what) {
   uint32_t flag = 0;
   HIP_TRY(hipMemcpyAsync(&flag, ctx->err.p, sizeof flag, hipMemcpyDeviceToHost, st));
@@ -412,6 +438,11 @@ chsim_status chsim_terms_init(chsim_ctx** out, int device, uint32_t n_inst,
   HIP_TRY(hipGetDeviceCount(&ndev));
   if (device < 0 || device >= ndev) return fail(CHSIM_EINVAL, "device %d not present", device);
   HIP_TRY(hipSetDevice(device));
+  {
+    void* sp = nullptr;
+    chsim_status sst = scratch_address(device, &sp);
+    if (sst) return sst;
+  }
   chsim_ctx* ctx = new chsim_ctx();
   ctx->device = device;
   ctx->inst.resize(n_inst);
@@ -1183,6 +1214,65 @@ chsim_status chsim_amplitudes_batch(chsim_ctx* ctx, const chsim_amp_request* req
       HIP_TRY(hipMemcpyAsync(reqs[q].out, rq[q].out, reqs[q].n_x * sizeof(double2), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
   }
+  return CHSIM_OK;
+}
+
+chsim_status chsim_amplitudes_noalloc(chsim_ctx* ctx, uint32_t inst, const uint64_t* x, size_t n_x,
+                                      double* out, uint32_t flags, void* stream) {
+  g_err.clear();
+  chsim_status st = check_ctx(ctx, inst);
+  if (st) return st;
+  if (!(flags & CHSIM_DEVICE_PTRS)) return fail(CHSIM_EINVAL, "chsim_amplitudes_noalloc takes device pointers only");
+  if (n_x == 0 || !x || !out) return fail(CHSIM_EINVAL, "empty or null bitstring/output arrays");
+  if (n_x > 0xFFFFFFFFull) return fail(CHSIM_EINVAL, "too many bitstrings");
+  Instance& I = ctx->inst[inst];
+  // Scratch layout: prologue rows [n][chi], term constants [chi], partial
+  // sums [ranges][n_x], the request record, the work items, the bitstring
+  // prefix and the queue counter, each 256-byte aligned.
+  const uint32_t xpl = ctx->amp_xpl;
+  uint32_t tpr = 0, n_ranges = 0, chunks = 0;
+  amp_plan_single(I.chi, (uint32_t)n_x, kAmpTargetItems, xpl, &tpr, &n_ranges, &chunks);
+  const uint64_t n_items = (uint64_t)n_ranges * chunks;
+  auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  const size_t o_crow = 0;
+  const size_t o_cst = o_crow + up((size_t)I.n * I.chi * sizeof(uint64_t));
+  const size_t o_part = o_cst + up((size_t)I.chi * sizeof(AmpTerm));
+  const size_t o_inst = o_part + up((size_t)n_ranges * n_x * sizeof(double2));
+  const size_t o_items = o_inst + up(sizeof(AmpInst));
+  const size_t o_prefix = o_items + up((size_t)n_items * sizeof(AmpItem));
+  const size_t o_counter = o_prefix + up(2 * sizeof(uint64_t));
+  const size_t need = o_counter + up(sizeof(uint32_t));
+  if (n_items > 0xFFFFFFFFull || need > kNoAllocScratch)
+    return fail(CHSIM_EINVAL, "request needs %zu bytes of scratch (n = %u, chi = %llu, %zu strings); the limit is %zu",
+                need, I.n, (unsigned long long)I.chi, n_x, kNoAllocScratch);
+  HIP_TRY(hipSetDevice(ctx->device));
+  void* base = nullptr;
+  if ((st = scratch_address(ctx->device, &base))) return st;
+  unsigned char* sp = static_cast<unsigned char*>(base);
+  hipStream_t s = as_stream(stream);
+  st = ensure_materialised(I, s);
+  if (st) return st;
+  uint64_t* crow = reinterpret_cast<uint64_t*>(sp + o_crow);
+  AmpTerm* cst = reinterpret_cast<AmpTerm*>(sp + o_cst);
+  HIP_TRY(launch_amp_prep(I.view(), crow, cst, s));
+  AmpInst a;
+  std::memset(&a, 0, sizeof a);
+  a.T = I.view();
+  a.crow = crow;
+  a.cst = cst;
+  a.x = x;
+  a.partial = reinterpret_cast<double2*>(sp + o_part);
+  a.out = reinterpret_cast<double2*>(out);
+  a.n_x = (uint32_t)n_x;
+  a.tiles_per_range = tpr;
+  a.n_ranges = n_ranges;
+  AmpInst* insts_d = reinterpret_cast<AmpInst*>(sp + o_inst);
+  AmpItem* items_d = reinterpret_cast<AmpItem*>(sp + o_items);
+  uint64_t* prefix_d = reinterpret_cast<uint64_t*>(sp + o_prefix);
+  uint32_t* counter_d = reinterpret_cast<uint32_t*>(sp + o_counter);
+  HIP_TRY(launch_amp_fill_single(a, insts_d, items_d, prefix_d, (uint32_t)n_items, chunks, xpl, s));
+  HIP_TRY(launch_amp_items(insts_d, items_d, (uint32_t)n_items, counter_d, (flags & CHSIM_FP32C) != 0, xpl,
+                           prefix_d, 1u, n_x, s));
   return CHSIM_OK;
 }
 

@@ -228,6 +228,14 @@ hipError_t launch_amp_prep(const TermsView& T, uint64_t* crow, AmpTerm* cst, hip
 void amp_plan(const std::vector<AmpRequestPlan>& reqs, uint32_t target_items, uint32_t xpl,
               std::vector<AmpItem>& items, std::vector<uint32_t>& tiles_per_range,
               std::vector<uint32_t>& n_ranges);
+// The plan amp_plan makes for a single request (tiles per range, ranges,
+// bitstring chunks of 256 xpl), computed without containers.
+void amp_plan_single(uint64_t chi, uint32_t n_x, uint32_t target_items, uint32_t xpl, uint32_t* tiles_per_range,
+                     uint32_t* n_ranges, uint32_t* chunks);
+// Write that plan's request record, prefix and n_items = ranges x chunks
+// work items into device memory with a kernel (no host copy).
+hipError_t launch_amp_fill_single(const AmpInst& inst, AmpInst* insts_d, AmpItem* items_d, uint64_t* prefix_d,
+                                  uint32_t n_items, uint32_t chunks, uint32_t xpl, hipStream_t st);
 // Reset the queue counter, run the persistent kernel, reduce.  prefix_d[q] =
 // bitstrings of requests before q (n_inst + 1 entries).
 hipError_t launch_amp_items(const AmpInst* insts_d, const AmpItem* items_d, uint32_t n_items,
