@@ -304,6 +304,55 @@ struct CH {
     return 2;
   }
 
+  // ---- projective gate (I + P) / 2 for any Hermitian Pauli P = i^a X(x) Z(z)
+  // (a = x.z mod 2; X part left of the Z part), end of Sec. "Phase-sensitive
+  // Clifford simulator" ----
+  // Gamma U_C U_H |s> = (1/2) U_C U_H (I + Q) |s>, Q = U_H^-1 U_C^-1 P U_C U_H.
+  // By Eq. (tableaux), U_C^-1 P U_C = i^a prod_{p in x} i^{gamma_p} X(F_p) Z(M_p)
+  // prod_{p in z} Z(G_p); the product is kept as i^c X(u) Z(w), using
+  // X(u) Z(w) X(f) Z(m) = (-1)^{w.f} X(u + f) Z(w + m).  U_H = H(v) swaps X and
+  // Z on the qubits with v_j = 1 (H X^u Z^w H = (-1)^{u w} X^w Z^u), so
+  // Q = i^c (-1)^{sum_{j: v_j = 1} u_j w_j} X(u') Z(w') and
+  // (I + Q)|s> = |s> + i^delta |t>, t = s + u', i^delta = i^c (-1)^{... + w'.s}.
+  // Returns 1 (state unchanged), 0 (projected to zero) or 2 (the state becomes
+  // 2^{-1/2} times the CH form of 2^{-1/2} U_C U_H (|s> + i^delta |t>), Prop. H).
+  int project_pauli(int a, const std::vector<uint8_t>& px, const std::vector<uint8_t>& pz) {
+    std::vector<uint8_t> u(n, 0), w(n, 0);
+    int c = ((a % 4) + 4) % 4;
+    for (int p = 0; p < n; ++p) {
+      if (!px[p]) continue;
+      int dot = 0;
+      for (int j = 0; j < n; ++j) dot += w[j] * f(p, j);
+      c = (c + gamma[p] + 2 * (dot % 2)) % 4;
+      for (int j = 0; j < n; ++j) {
+        u[j] ^= f(p, j);
+        w[j] ^= m(p, j);
+      }
+    }
+    for (int p = 0; p < n; ++p)
+      if (pz[p])
+        for (int j = 0; j < n; ++j) w[j] ^= g(p, j);
+    std::vector<uint8_t> u2(n), w2(n), t(n);
+    int sw = 0, ws = 0;
+    bool same = true;
+    for (int j = 0; j < n; ++j) {
+      if (v[j]) { u2[j] = w[j]; w2[j] = u[j]; sw += u[j] * w[j]; }
+      else { u2[j] = u[j]; w2[j] = w[j]; }
+      t[j] = s[j] ^ u2[j];
+      if (u2[j]) same = false;
+      ws += w2[j] * s[j];
+    }
+    int delta = (c + 2 * (sw % 2) + 2 * (ws % 2)) % 4;
+    if (same) {
+      // Q|s> = i^delta |s>: a Hermitian Q has eigenvalue +1 or -1.
+      if (delta % 2) { error = 4; return -1; }
+      return delta == 0 ? 1 : 0;
+    }
+    std::vector<uint8_t> s0 = s;
+    superpose(s0, t, 0, delta);
+    return 2;
+  }
+
   // ---- amplitude <x|phi>, Eqs. (amplitude), (amplitude1) ----
   // Returns 1 if nonzero; then <x|phi> = e^{i pi k8/4} 2^{-vcount/2}.
   int amplitude(uint64_t x, int* k8, int* vcount) const {
@@ -916,6 +965,42 @@ int orc_terms_project(void* h, int w, const int32_t* qubits, const uint8_t* bits
   int nb = 0;
   for (int x : bad) nb += x;
   return nb;
+}
+// Apply prod_j (I + P_j) / 2, P_j = i^{a[j]} X(x[j]) Z(z[j]) (Hermitian), to every
+// built term in order, as orc_terms_project does for Z-type projectors.
+int orc_terms_project_pauli(void* h, int w, const uint8_t* a, const uint64_t* x, const uint64_t* z,
+                            int threads) {
+  Terms* T = (Terms*)h;
+  const int n = T->n;
+  std::vector<int> bad(T->ch.size(), 0);
+  parallel_for(T->ch.size(), threads, [&](size_t t, int) {
+    for (int j = 0; j < w; ++j) {
+      if (T->b[t] == cplx(0.0, 0.0)) break;  // already projected away
+      std::vector<uint8_t> px(n), pz(n);
+      for (int q = 0; q < n; ++q) {
+        px[q] = (uint8_t)((x[j] >> q) & 1);
+        pz[q] = (uint8_t)((z[j] >> q) & 1);
+      }
+      int code = T->ch[t].project_pauli(a[j], px, pz);
+      if (T->ch[t].error || code < 0) { bad[t] = 1; return; }
+      if (code == 0) T->b[t] = 0.0;
+      else if (code == 2) T->b[t] *= 1.0 / std::sqrt(2.0);
+    }
+  });
+  int nb = 0;
+  for (int e : bad) nb += e;
+  return nb;
+}
+// One CH form: code of project_pauli (-1 on an invalid state or a non-Hermitian P).
+int orc_ch_project_pauli(void* h, int a, uint64_t x, uint64_t z) {
+  CH* c = (CH*)h;
+  std::vector<uint8_t> px(c->n), pz(c->n);
+  for (int q = 0; q < c->n; ++q) {
+    px[q] = (uint8_t)((x >> q) & 1);
+    pz[q] = (uint8_t)((z >> q) & 1);
+  }
+  int code = c->project_pauli(a, px, pz);
+  return c->error ? -1 : code;
 }
 // One CH form: returns the code of project_z (and -1 on an invalid state).
 int orc_ch_project(void* h, int q, int bit) {

@@ -153,12 +153,16 @@ class MLPRef:
 
 
 def log_q(pi, m_bits, eps, n):
-    """log q(y|x) for flip mask m (bits [n]) under flip probabilities pi [n]."""
+    """log q(y|x) for flip mask m (bits [n]) under flip probabilities pi [n]:
+    q = eps [|m| = 1] / n + (1 - eps) prod_j pi_j^{m_j} (1 - pi_j)^{1 - m_j},
+    evaluated as a log-sum-exp of the two terms' logs (a zero term is -inf),
+    so that a product far below the smallest double keeps its exact log."""
     pi = pi.astype(np.float64)
-    lp = np.where(m_bits > 0, np.log(pi), np.log1p(-pi)).sum()
-    prod = np.exp(lp)
-    single = (eps / n) if int(m_bits.sum()) == 1 else 0.0
-    return float(np.log(single + (1.0 - eps) * prod))
+    eps = float(eps)
+    lp = float(np.where(m_bits > 0, np.log(pi), np.log1p(-pi)).sum())
+    a = np.log(eps / n) if (int(m_bits.sum()) == 1 and eps > 0.0) else -np.inf
+    b = np.log1p(-eps) + lp if eps < 1.0 else -np.inf
+    return float(np.logaddexp(a, b))
 
 
 def learned_chain(terms, mlp: MLPRef, x0, u_mix, jstream, u_bits, ustream, eps, pi_min, pi_max,

@@ -56,6 +56,8 @@ def lib():
     L.orc_ccz_decomp.argtypes = [C.c_int, C.c_int, C.c_int, f64p, u32p, i32p]
     L.orc_terms_project.argtypes = [C.c_void_p, C.c_int, i32p, u8p, C.c_int]
     L.orc_ch_project.argtypes = [C.c_void_p, C.c_int, C.c_int]
+    L.orc_terms_project_pauli.argtypes = [C.c_void_p, C.c_int, u8p, u64p, u64p, C.c_int]
+    L.orc_ch_project_pauli.argtypes = [C.c_void_p, C.c_int, C.c_uint64, C.c_uint64]
     L.orc_terms_clone.argtypes = [C.c_void_p]
     L.orc_terms_clone.restype = C.c_void_p
     L.orc_ccz_decomp.restype = C.c_int
@@ -169,6 +171,15 @@ class CHForm:
         code = lib().orc_ch_project(self._h, int(q), int(bit))
         if code < 0:
             raise RuntimeError("projection produced an invalid CH form")
+        return code
+
+    def project_pauli(self, a: int, x: int, z: int) -> int:
+        """(I + P) / 2 in place for the Hermitian Pauli P = i^a X(x) Z(z) (end of
+        Sec. "Phase-sensitive Clifford simulator"): returns 1 (unchanged), 0
+        (projected to zero) or 2 (the state is now 2^{-1/2} times this CH form)."""
+        code = lib().orc_ch_project_pauli(self._h, int(a), int(x), int(z))
+        if code < 0:
+            raise RuntimeError("projection produced an invalid CH form (or P is not Hermitian)")
         return code
 
     def sample(self, flips: int) -> int:
@@ -312,6 +323,16 @@ class Terms:
         qs = np.ascontiguousarray(qubits, np.int32)
         bs = np.ascontiguousarray(bits, np.uint8)
         if lib().orc_terms_project(self._h, qs.size, qs, bs, self.threads):
+            raise RuntimeError("projection produced an invalid CH form")
+
+    def project_pauli(self, a, x, z) -> None:
+        """Apply prod_j (I + P_j) / 2, P_j = i^{a_j} X(x_j) Z(z_j) Hermitian, to
+        every term in order (CH forms updated, b_alpha scaled by 2^{-1/2} or set
+        to zero)."""
+        a = np.ascontiguousarray(a, np.uint8)
+        x = np.ascontiguousarray(x, np.uint64)
+        z = np.ascontiguousarray(z, np.uint64)
+        if lib().orc_terms_project_pauli(self._h, a.size, a, x, z, self.threads):
             raise RuntimeError("projection produced an invalid CH form")
 
     def sample_marginal(self, qubits, Aoff, Adiag, u):

@@ -200,13 +200,17 @@ def config_norm(seed: int = 1003, chi: int = 1 << 18, L: int = 1024) -> dict:
 
 
 def qaoa_circuit(n: int, n_triples: int, rng: np.random.Generator, gamma=None, beta=None) -> tuple:
-    """p = 1 QAOA for Max-E3LIN2: H on all qubits, exp(-i gamma d Z_a Z_b Z_c) for
-    random distinct triples with d = +-1, then exp(-i beta X_j) on every qubit.
+    """p = 1 QAOA for Max-E3LIN2 (Sec. "Quantum approximate optimization
+    algorithm"): U = exp(-i beta B) exp(-i gamma C^) H^n with
+    C^ = (1/2) sum_t d_t Z_a Z_b Z_c over random distinct triples, d = +-1, and
+    B = sum_j X_j.
 
-    exp(-i g Z_a Z_b Z_c) = CX_{a,c} CX_{b,c} exp(-i g Z_c) CX_{b,c} CX_{a,c}, and
-    exp(-i g Z) = e^{-i g} diag(1, e^{2 i g}): a phase slot with theta = 2 g.
-    exp(-i beta X) = H exp(-i beta Z) H: a slot with theta = 2 beta between two H.
-    Global phases are dropped.  Returns (circuit, triples, d)."""
+    exp(-i (gamma d / 2) Z_a Z_b Z_c) = CX_{a,c} CX_{b,c} exp(-i g Z_c) CX_{b,c} CX_{a,c}
+    with g = gamma d / 2, and exp(-i g Z) = e^{-i g} diag(1, e^{2 i g}): a phase
+    slot with theta = gamma d.  exp(-i beta X) = H exp(-i beta Z) H: a slot with
+    theta = 2 beta between two H.  The global phases e^{-i g} and e^{-i beta}
+    are dropped, so the circuit prepares e^{i (gamma sum_t d_t / 2 + n beta)}
+    times U|0^n>.  Returns (circuit, triples, d, gamma, beta)."""
     if gamma is None:
         gamma = rng.uniform(0.0, np.pi)
     if beta is None:
@@ -222,7 +226,7 @@ def qaoa_circuit(n: int, n_triples: int, rng: np.random.Generator, gamma=None, b
         triples.append(t)
     d = rng.choice([-1, 1], size=n_triples)
     for (a, b, c), dd in zip(triples, d.tolist()):
-        gates += [(OP_CX, a, c), (OP_CX, b, c), (OP_SLOT, c, 0, 2 * gamma * dd), (OP_CX, b, c),
+        gates += [(OP_CX, a, c), (OP_CX, b, c), (OP_SLOT, c, 0, gamma * dd), (OP_CX, b, c),
                   (OP_CX, a, c)]
     for j in range(n):
         gates += [(OP_H, j, 0), (OP_SLOT, j, 0, 2 * beta), (OP_H, j, 0)]

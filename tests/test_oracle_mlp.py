@@ -128,3 +128,37 @@ def test_learned_chain_stationary_law():
     tv = 0.5 * np.abs(hist - Pc).sum()
     assert tv < 0.06, tv
     assert flips.mean() > 1.0
+
+
+def test_mixture_density_at_extreme_flip_probabilities():
+    """log q of the mixture proposal stays exact where the product of flip
+    probabilities underflows a double: |m| = 62 bits at pi = 1e-6 gives a
+    product of 1e-372.  Closed forms: for |m| != 1, log q = log(1 - eps) + lp;
+    for |m| = 1, log q = log(eps / n + (1 - eps) e^{lp}); eps = 1 leaves only
+    the single-flip term."""
+    n, eps = 62, 0.1
+    pi = np.full(n, 1e-6)
+    m = np.ones(n, np.float32)
+    lp = n * np.log(1e-6)
+    assert lp < -745  # exp(lp) is 0 in double precision
+    got = OM.log_q(pi, m, eps, n)
+    assert np.isfinite(got)
+    assert abs(got - (np.log1p(-eps) + lp)) <= 1e-12 * abs(lp)
+    # the Metropolis-Hastings factor between two such masks is finite and exact
+    pi2 = np.full(n, 2e-6)
+    r = np.exp(OM.log_q(pi2, m, eps, n) - got)
+    assert abs(r - 2.0**n) <= 1e-9 * 2.0**n
+    one = np.zeros(n, np.float32)
+    one[5] = 1
+    lp1 = np.log(1e-6) + (n - 1) * np.log1p(-1e-6)
+    assert abs(OM.log_q(pi, one, eps, n) - np.log(eps / n + (1 - eps) * np.exp(lp1))) < 1e-12
+    assert abs(OM.log_q(pi, one, 1.0, n) - np.log(1.0 / n)) < 1e-15
+    assert OM.log_q(pi, m, 1.0, n) == -np.inf  # eps = 1 never proposes a multi-bit mask
+    # moderate values agree with the direct formula
+    rng = np.random.default_rng(0)
+    for _ in range(100):
+        p = rng.uniform(0.01, 0.5, size=10)
+        mm = (rng.random(10) < 0.3).astype(np.float32)
+        lpp = float(np.where(mm > 0, np.log(p), np.log1p(-p)).sum())
+        single = 0.2 / 10 if mm.sum() == 1 else 0.0
+        assert abs(OM.log_q(p, mm, 0.2, 10) - np.log(single + 0.8 * np.exp(lpp))) < 1e-12

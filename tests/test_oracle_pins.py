@@ -713,3 +713,149 @@ def test_chain_rule_sampler_with_exact_norms():
             prefix.append(b)
         if all(_dense_marginal(psi, 3, qubits[: j + 1], list(path[: j + 1])) > 1e-9 for j in range(2)):
             assert bits == list(path)
+
+
+# ---------------------------------------------------------------------------
+# Projective gates (I + P) / 2 for a general Hermitian Pauli P = i^a X(x) Z(z).
+# ---------------------------------------------------------------------------
+def _dense_pauli(psi, n, a, x, z):
+    """P psi for P = i^a X(x) Z(z): X(x) Z(z)|b> = (-1)^{z.b} |b ^ x>."""
+    idx = np.arange(2**n)
+    src = idx ^ x
+    sign = np.array([(-1) ** bin(int(z) & int(b)).count("1") for b in src])
+    return (1j**a) * sign * psi[src]
+
+
+def _random_hermitian_pauli(n, rng):
+    x = int(rng.integers(0, 2**n))
+    z = int(rng.integers(0, 2**n))
+    a = bin(x & z).count("1") % 2 + 2 * int(rng.integers(2))  # a = x.z (mod 2) makes P Hermitian
+    return a, x, z
+
+
+def test_pauli_projector_matches_dense():
+    rng = np.random.default_rng(31)
+    cover = {0: 0, 1: 0, 2: 0}
+    for trial in range(900):
+        n = int(rng.integers(1, 7))
+        g = W.random_clifford_gates(n, int(rng.integers(0, 40)), rng)
+        ch = O.CHForm(n)
+        for gg in g:
+            ch.apply(*gg)
+        psi = dense.run_gates(n, g)
+        if trial % 3 == 0:
+            # a stabilizer of the state or its negative: the kept and zero cases
+            a, x, z = _random_hermitian_pauli(n, rng)
+            Ppsi = _dense_pauli(psi, n, a, x, z)
+            if np.allclose(Ppsi, -psi, atol=1e-12):
+                a = (a + 2) % 4
+        else:
+            a, x, z = _random_hermitian_pauli(n, rng)
+        want = (psi + _dense_pauli(psi, n, a, x, z)) / 2
+        code = ch.project_pauli(a, x, z)
+        cover[code] += 1
+        got = np.array([ch.amplitude(int(b)) for b in range(2**n)]) * {0: 0.0, 1: 1.0, 2: 2**-0.5}[code]
+        np.testing.assert_allclose(got, want, atol=1e-13)
+        assert ch.check() == 0
+    assert min(cover.values()) >= 40, cover
+
+
+def test_pauli_projector_z_case_is_the_z_projector():
+    """P = (-1)^b Z_q, i.e. a = 2b, x = 0, z = e_q, gives the CH form the
+    Z-type projector gives, code for code."""
+    rng = np.random.default_rng(32)
+    for _ in range(300):
+        n = int(rng.integers(1, 9))
+        g = W.random_clifford_gates(n, int(rng.integers(0, 60)), rng)
+        c1, c2 = O.CHForm(n), O.CHForm(n)
+        for gg in g:
+            c1.apply(*gg)
+            c2.apply(*gg)
+        q, b = int(rng.integers(n)), int(rng.integers(2))
+        assert c1.project(q, b) == c2.project_pauli(2 * b, 0, 1 << q)
+        e1, e2 = c1.export(), c2.export()
+        for k in e1:
+            assert np.array_equal(np.asarray(e1[k]), np.asarray(e2[k])), k
+
+
+def test_pauli_projected_terms_match_dense_sum():
+    """Exact sum over Cliffords (phase and CCZ slots) projected by three random
+    Hermitian Paulis in turn equals the dense prod_j (I + P_j)/2 psi."""
+    rng = np.random.default_rng(33)
+    n = 5
+    g = W.random_clifford_gates(n, 50, rng)
+    circ = W.from_list(n, g[:20] + [(W.OP_CCZ, 0, 2, 4)] + g[20:35] + [(OP_SLOT, 3, 0, 0.7)] + g[35:])
+    psi = dense.run(circ)
+    xs = np.arange(2**n, dtype=np.uint64)
+    for trial in range(20):
+        ps = [_random_hermitian_pauli(n, rng) for _ in range(3)]
+        T = O.Terms(circ, 16, O.EXACT)
+        T.project_pauli([p[0] for p in ps], [p[1] for p in ps], [p[2] for p in ps])
+        want = psi
+        for a, x, z in ps:
+            want = (want + _dense_pauli(want, n, a, x, z)) / 2
+        np.testing.assert_allclose(T.amplitudes(xs), want, atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# QAOA for Max-E3LIN2 (Sec. "Quantum approximate optimization algorithm"):
+# U = exp(-i beta B) exp(-i gamma C^) H^n, C^ = (1/2) sum d_t Z_a Z_b Z_c.
+# ---------------------------------------------------------------------------
+def _qaoa_cost_bits(n, triples, d):
+    idx = np.arange(2**n)
+    c = np.zeros(2**n)
+    for (a, b, cc), dd in zip(triples, d):
+        par = ((idx >> a) ^ (idx >> b) ^ (idx >> cc)) & 1
+        c += 0.5 * dd * (1 - 2 * par)
+    return c
+
+
+def _qaoa_dense(n, triples, d, gamma, beta):
+    """The paper's U|0^n> written out: uniform superposition, the diagonal
+    phase e^{-i gamma C(z)}, then e^{-i beta X_j} = cos(beta) I - i sin(beta) X_j
+    on every qubit."""
+    psi = np.full(2**n, 2.0 ** (-n / 2), np.complex128)
+    psi = psi * np.exp(-1j * gamma * _qaoa_cost_bits(n, triples, d))
+    idx = np.arange(2**n)
+    for j in range(n):
+        psi = np.cos(beta) * psi - 1j * np.sin(beta) * psi[idx ^ (1 << j)]
+    return psi
+
+
+@pytest.mark.parametrize("gamma,beta", [(0.37, np.pi / 4), (-1.1, np.pi / 4), (2.3, 0.61), (0.0, 1.9)])
+def test_qaoa_circuit_prepares_the_paper_state(gamma, beta):
+    """The compiled workload circuit (CX-conjugated phase slots, H-conjugated
+    mixer slots) run by the dense simulator equals the paper's U|0^n> up to the
+    dropped global phase e^{i (gamma sum d / 2 + n beta)}."""
+    n = 10
+    rng = np.random.default_rng(55)
+    circ, triples, d, g, b = W.qaoa_circuit(n, 12, rng, gamma=gamma, beta=beta)
+    assert (g, b) == (gamma, beta)
+    ref = _qaoa_dense(n, triples.tolist(), d.tolist(), gamma, beta)
+    got = dense.run(circ)
+    phase = np.exp(1j * (gamma * float(np.sum(d)) / 2 + n * beta))
+    np.testing.assert_allclose(got, phase * ref, atol=1e-12)
+
+
+def test_qaoa_expectation_through_the_oracle_and_its_symmetry():
+    """E(gamma) = sum_z P(z) C(z) from the oracle's exact sum over Cliffords
+    equals the dense value, and E(-gamma) = -E(gamma) (C(-z) = -C(z) with all
+    spins flipped, which commutes with B and fixes H^n|0^n>)."""
+    n = 8
+    rng = np.random.default_rng(56)
+    xs = np.arange(2**n, dtype=np.uint64)
+    for gamma, beta in ((0.83, np.pi / 4), (1.7, 0.4)):
+        E = {}
+        for sgn in (1, -1):
+            r = np.random.default_rng(57)
+            circ, triples, d, _, _ = W.qaoa_circuit(n, 6, r, gamma=sgn * gamma, beta=beta)
+            T = O.Terms(circ, 1 << circ.n_slot, O.EXACT)
+            a = T.amplitudes(xs)
+            P = np.abs(a) ** 2
+            assert abs(P.sum() - 1) < 1e-12
+            cost = _qaoa_cost_bits(n, triples.tolist(), d.tolist())
+            E[sgn] = float(np.dot(P, cost))
+            ref = _qaoa_dense(n, triples.tolist(), d.tolist(), sgn * gamma, beta)
+            assert abs(E[sgn] - float(np.dot(np.abs(ref) ** 2, cost))) < 1e-12
+        assert abs(E[1] + E[-1]) < 1e-12, E
+        assert abs(E[1]) > 1e-3  # not the trivial zero
