@@ -187,9 +187,24 @@ chsim_status chsim_inner_products(chsim_ctx* ctx, uint32_t inst, const uint64_t*
  * row G_q and the CH form of the result by Prop. H).  A term is kept, scaled by
  * 2^{-1/2} (b_alpha and its CH form updated), or projected to zero (b_alpha = 0),
  * so the instance then holds Pi psi.  qubits, bits: host arrays of w entries.
+ * The same as chsim_project_pauli with a = 2 bits[j], x = 0, z = e_{qubits[j]}.
  * EINVAL: w > 64, a qubit >= n, a bit > 1, null arrays with w > 0. */
 chsim_status chsim_project_z(chsim_ctx* ctx, uint32_t inst, const uint32_t* qubits, const uint8_t* bits,
                              uint32_t w, void* stream);
+
+/* Projective gates (I + P_j) / 2 for Hermitian Paulis P_j = i^{a[j]} X(x[j]) Z(z[j])
+ * (X part left of the Z part; bit q of x[j], z[j] = qubit q), j < w, applied in
+ * order to every term of the instance in place (end of Sec. "Phase-sensitive
+ * Clifford simulator": Gamma|phi> = (1/2) U_C U_H (I + Q)|s> with
+ * Q = U_H^{-1} U_C^{-1} P U_C U_H, U_C^{-1} P U_C read off the tableaux of Eq.
+ * (tableaux) in O(n^2), and the CH form of the result by Prop. H).  A term is
+ * kept, scaled by 2^{-1/2} (b_alpha and its CH form updated), or projected to
+ * zero (b_alpha = 0), so the instance then holds prod_j (I + P_j)/2 psi.
+ * a, x, z: host arrays of w entries.  EINVAL: w > 64, a[j] > 3, a bit >= n in
+ * x[j] or z[j], a[j] != popcount(x[j] & z[j]) mod 2 (P_j not Hermitian), null
+ * arrays with w > 0.  Chains started on the instance are dropped. */
+chsim_status chsim_project_pauli(chsim_ctx* ctx, uint32_t inst, const uint8_t* a, const uint64_t* x,
+                                 const uint64_t* z, uint32_t w, void* stream);
 
 /* Copy the term store (CH forms, b_alpha, and the branch choices when both
  * have the same slot count) of src_inst into dst_inst, device to device.

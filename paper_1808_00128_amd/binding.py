@@ -33,7 +33,7 @@ MAX_BRANCH = 8
 EXPORTED = [
     "chsim_terms_init", "chsim_terms_reset", "chsim_apply_clifford", "chsim_amplitudes",
     "chsim_amplitudes_batch", "chsim_amplitudes_noalloc", "chsim_inner_products", "chsim_sparsification_bound",
-    "chsim_project_z", "chsim_terms_copy", "chsim_sample_marginal",
+    "chsim_project_z", "chsim_project_pauli", "chsim_terms_copy", "chsim_sample_marginal",
     "chsim_metropolis_init", "chsim_metropolis_step", "chsim_sample_terms", "chsim_get_terms",
     "chsim_set_terms", "chsim_validate", "chsim_decompose_phase", "chsim_decompose_ccz", "chsim_set_tuning", "chsim_get_tuning",
     "chsim_instance_info", "chsim_evolution_stats", "chsim_destroy", "chsim_mlp_create", "chsim_mlp_destroy",
@@ -116,6 +116,7 @@ def lib():
     L.chsim_inner_products.argtypes = [vp, u32, vp, vp, C.c_size_t, vp, vp, vp, u32, vp]
     L.chsim_sparsification_bound.argtypes = [vp, u32, vp, vp, C.c_size_t, C.POINTER(C.c_double), vp]
     L.chsim_project_z.argtypes = [vp, u32, vp, vp, u32, vp]
+    L.chsim_project_pauli.argtypes = [vp, u32, vp, vp, vp, u32, vp]
     L.chsim_terms_copy.argtypes = [vp, u32, u32, vp]
     L.chsim_sample_marginal.argtypes = [vp, u32, u32, vp, u32, vp, vp, C.c_size_t, vp, vp, vp, vp, vp]
     L.chsim_metropolis_init.argtypes = [vp, u32, u32, vp, vp, u32, vp]
@@ -432,6 +433,14 @@ class Context:
         qs = np.ascontiguousarray(qubits, np.uint32)
         bs = np.ascontiguousarray(bits, np.uint8)
         _check(lib().chsim_project_z(self._h, inst, _ptr(qs)[0], _ptr(bs)[0], qs.size, _stream(stream)))
+
+    def project_pauli(self, a, x, z, inst=0, stream=None):
+        """Apply prod_j (I + i^{a_j} X(x_j) Z(z_j)) / 2 (Hermitian Paulis) to every term in place."""
+        a = np.ascontiguousarray(a, np.uint8)
+        x = np.ascontiguousarray(x, np.uint64)
+        z = np.ascontiguousarray(z, np.uint64)
+        _check(lib().chsim_project_pauli(self._h, inst, _ptr(a)[0], _ptr(x)[0], _ptr(z)[0], a.size,
+                                         _stream(stream)))
 
     def copy_terms(self, src_inst, dst_inst, stream=None):
         _check(lib().chsim_terms_copy(self._h, src_inst, dst_inst, _stream(stream)))

@@ -1856,6 +1856,48 @@ chsim_status chsim_sparsification_bound(chsim_ctx* ctx, uint32_t inst, const uin
   return CHSIM_OK;
 }
 
+namespace {
+
+chsim_status run_projection(chsim_ctx* ctx, uint32_t inst, const ProjGates& P, void* stream) {
+  Instance& I = ctx->inst[inst];
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t s = as_stream(stream);
+  chsim_status st = ensure_materialised(I, s);
+  if (st) return st;
+  I.drop_chains();
+  HIP_TRY(hipMemsetAsync(ctx->err.p, 0, sizeof(uint32_t), s));
+  HIP_TRY(launch_project(I.view(), P, ctx->err.p, s));
+  I.amp_ready = false;
+  return check_err_flag(ctx, s, "projection");
+}
+
+}  // namespace
+
+chsim_status chsim_project_pauli(chsim_ctx* ctx, uint32_t inst, const uint8_t* a, const uint64_t* x,
+                                 const uint64_t* z, uint32_t w, void* stream) {
+  g_err.clear();
+  chsim_status st = check_ctx(ctx, inst);
+  if (st) return st;
+  if (w == 0) return CHSIM_OK;
+  if (!a || !x || !z) return fail(CHSIM_EINVAL, "null input");
+  if (w > 64) return fail(CHSIM_EINVAL, "at most 64 projectors per call");
+  const Instance& I = ctx->inst[inst];
+  const uint64_t hi = (I.n == 64) ? 0ull : ~((1ull << I.n) - 1ull);
+  ProjGates P;
+  std::memset(&P, 0, sizeof P);
+  P.count = w;
+  for (uint32_t j = 0; j < w; ++j) {
+    if ((x[j] | z[j]) & hi) return fail(CHSIM_EINVAL, "projector %u: X or Z part has a qubit >= n %u", j, I.n);
+    if (a[j] > 3) return fail(CHSIM_EINVAL, "projector %u: phase exponent %u not in Z_4", j, a[j]);
+    if ((a[j] & 1u) != ((uint32_t)__builtin_popcountll(x[j] & z[j]) & 1u))
+      return fail(CHSIM_EINVAL, "projector %u: i^a X(x) Z(z) is not Hermitian (a != x.z mod 2)", j);
+    P.a[j] = a[j];
+    P.x[j] = x[j];
+    P.z[j] = z[j];
+  }
+  return run_projection(ctx, inst, P, stream);
+}
+
 chsim_status chsim_project_z(chsim_ctx* ctx, uint32_t inst, const uint32_t* qubits, const uint8_t* bits,
                              uint32_t w, void* stream) {
   g_err.clear();
@@ -1863,25 +1905,20 @@ chsim_status chsim_project_z(chsim_ctx* ctx, uint32_t inst, const uint32_t* qubi
   if (st) return st;
   if (w == 0) return CHSIM_OK;
   if (!qubits || !bits) return fail(CHSIM_EINVAL, "null input");
-  Instance& I = ctx->inst[inst];
+  const Instance& I = ctx->inst[inst];
   if (w > 64) return fail(CHSIM_EINVAL, "at most 64 projectors per call");
+  // (I + (-1)^b Z_q) / 2 is the Pauli projector with a = 2 b, x = 0, z = e_q.
   ProjGates P;
   std::memset(&P, 0, sizeof P);
   P.count = w;
   for (uint32_t j = 0; j < w; ++j) {
     if (qubits[j] >= I.n) return fail(CHSIM_EINVAL, "projector %u: qubit %u >= n %u", j, qubits[j], I.n);
     if (bits[j] > 1) return fail(CHSIM_EINVAL, "projector %u: bit must be 0 or 1", j);
-    P.q[j] = (uint8_t)qubits[j];
-    P.bit[j] = bits[j];
+    P.a[j] = (uint8_t)(2u * bits[j]);
+    P.x[j] = 0ull;
+    P.z[j] = 1ull << qubits[j];
   }
-  HIP_TRY(hipSetDevice(ctx->device));
-  hipStream_t s = as_stream(stream);
-  st = ensure_materialised(I, s);
-  if (st) return st;
-  I.drop_chains();
-  HIP_TRY(launch_project(I.view(), P, s));
-  I.amp_ready = false;
-  return CHSIM_OK;
+  return run_projection(ctx, inst, P, stream);
 }
 
 chsim_status chsim_terms_copy(chsim_ctx* ctx, uint32_t src_inst, uint32_t dst_inst, void* stream) {

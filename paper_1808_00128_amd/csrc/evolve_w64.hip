@@ -242,16 +242,21 @@ __global__ __launch_bounds__(256) void k_evolve_w64(EvolveJob J, const DGate* __
   }
 }
 
-// Projective gates prod_j (I + (-1)^{bit_j} Z_{q_j}) / 2 on every term of the
-// store (end of Sec. "Phase-sensitive Clifford simulator"), one term per wave,
-// lane p holding row p.  U_C^{-1} Z_q U_C = Z(G_q), and conjugation by
-// U_H = H(v) turns the Z on qubits with v_j = 1 into X, so the Pauli acting on
-// |s> is Q = (-1)^bit X(G_q & v) Z(G_q & ~v) and (I + Q)|s> = |s> + i^delta |t>
-// with t = s ^ (G_q & v), i^delta = (-1)^{bit + par(G_q & ~v & s)}.  t = s: the
-// term stays (i^delta = 1) or is projected to zero (b = 0); otherwise Prop. H
-// gives the CH form of 2^{-1/2} U_C U_H (|s> + i^delta |t>) and b is scaled by
-// 2^{-1/2}.  A term with b = 0 is left as it is.
-__global__ __launch_bounds__(256) void k_project_w64(TermsView T, ProjGates P) {
+// Projective gates prod_j (I + P_j) / 2 on every term of the store (end of Sec.
+// "Phase-sensitive Clifford simulator"), P_j = i^a X(x) Z(z) Hermitian, one
+// term per wave, lane p holding row p.  By Eq. (tableaux)
+//   U_C^{-1} P U_C = i^a prod_{p in x} i^{gamma_p} X(F_p) Z(M_p) prod_{p in z} Z(G_p),
+// accumulated on the scalar unit as i^c X(u) Z(w) over the set bits of x
+// (rows by readlane; X(u) Z(w) X(f) Z(m) = (-1)^{w.f} X(u ^ f) Z(w ^ m)).
+// Conjugation by U_H = H(v) swaps X and Z on the qubits in v (with a sign
+// (-1)^{u_j w_j} each), so Q = U_H^{-1} U_C^{-1} P U_C U_H acts on |s> as
+// (I + Q)|s> = |s> + i^delta |t>, t = s ^ u', u' = (u & ~v) | (w & v),
+// delta = c + 2 par(u & w & v) + 2 par(w' & s), w' = (w & ~v) | (u & v).
+// t = s: the term stays (delta = 0) or is projected to zero (delta = 2);
+// otherwise Prop. H gives the CH form of 2^{-1/2} U_C U_H (|s> + i^delta |t>)
+// and b is scaled by 2^{-1/2}.  A term with b = 0 is left as it is.  An odd
+// delta with t = s (P not Hermitian) sets the error flag.
+__global__ __launch_bounds__(256) void k_project_w64(TermsView T, ProjGates P, uint32_t* __restrict__ err) {
   const uint32_t lane = threadIdx.x & 63u;
   const uint64_t item = (uint64_t)blockIdx.x * 4u + uniform32(threadIdx.x >> 6);
   if (item >= T.chi) return;  // whole waves; the kernel has no barrier
@@ -266,15 +271,27 @@ __global__ __launch_bounds__(256) void k_project_w64(TermsView T, ProjGates P) {
   bool zero = b.x == 0.0 && b.y == 0.0;
   bool changed = false;
   for (uint32_t j = 0; j < P.count && !zero; ++j) {
-    const uint32_t q = P.q[j];
-    const uint64_t Gq = rl64(G, q);
-    const uint64_t t = s ^ (Gq & v);
-    const uint32_t odd = ((uint32_t)P.bit[j] + par64(Gq & ~v & s)) & 1u;
-    if (t == s) {
-      zero = odd != 0u;
+    uint32_t c = P.a[j];
+    uint64_t xu = 0ull, zw = 0ull;
+    for (uint64_t xm = P.x[j]; xm; xm &= xm - 1ull) {
+      const uint32_t p = (uint32_t)__builtin_ctzll(xm);
+      const uint64_t Fp = rl64(F, p);
+      c += rl32(g, p) + 2u * par64(zw & Fp);
+      xu ^= Fp;
+      zw ^= rl64(M, p);
+    }
+    for (uint64_t zm = P.z[j]; zm; zm &= zm - 1ull) zw ^= rl64(G, (uint32_t)__builtin_ctzll(zm));
+    const uint64_t up = (xu & ~v) | (zw & v), wp = (zw & ~v) | (xu & v);
+    const uint32_t delta = (c + 2u * par64(xu & zw & v) + 2u * par64(wp & s)) & 3u;
+    if (up == 0ull) {
+      if (delta & 1u) {
+        if (lane == 0) atomicOr(err, 1u);
+        break;
+      }
+      zero = delta == 2u;
       continue;
     }
-    superpose_w64(F, G, M, g, v, s, w, s, t, 0u, 2u * odd);
+    superpose_w64(F, G, M, g, v, s, w, s, s ^ up, 0u, delta);
     b.x *= 0.70710678118654752440;
     b.y *= 0.70710678118654752440;
     changed = true;
@@ -308,10 +325,10 @@ hipError_t launch_evolve_w64(const EvolveJob& J, const DGate* gates, uint32_t n_
   return hipGetLastError();
 }
 
-hipError_t launch_project(const TermsView& T, const ProjGates& P, hipStream_t st) {
+hipError_t launch_project(const TermsView& T, const ProjGates& P, uint32_t* err, hipStream_t st) {
   const uint64_t blocks = (T.chi + 3) / 4;
   if (blocks == 0 || P.count == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_project_w64, dim3((uint32_t)blocks), dim3(256), 0, st, T, P);
+  hipLaunchKernelGGL(k_project_w64, dim3((uint32_t)blocks), dim3(256), 0, st, T, P, err);
   return hipGetLastError();
 }
 

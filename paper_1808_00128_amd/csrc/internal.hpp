@@ -134,14 +134,16 @@ hipError_t launch_evolve_wide(int lanes, int rows, const EvolveJob& J, const DGa
                               uint32_t n_gates, bool from_zero, uint32_t* err, hipStream_t st);
 hipError_t launch_evolve_lds(int lanes, const EvolveJob& J, const DGate* gates, uint32_t n_gates,
                              bool from_zero, uint32_t* err, hipStream_t st);
-// Projective gates (I + (-1)^bit[j] Z_q[j]) / 2, j < count, applied in order to
-// every term of T in place (CH forms and b).
+// Projective gates (I + P_j) / 2, j < count, applied in order to every term of
+// T in place (CH forms and b), with the Hermitian Pauli
+// P_j = i^{a[j]} X(x[j]) Z(z[j]) (a[j] = popcount(x[j] & z[j]) mod 2).
 struct ProjGates {
   uint32_t count;
-  uint8_t q[64];
-  uint8_t bit[64];
+  uint8_t a[64];
+  uint64_t x[64];
+  uint64_t z[64];
 };
-hipError_t launch_project(const TermsView& T, const ProjGates& P, hipStream_t st);
+hipError_t launch_project(const TermsView& T, const ProjGates& P, uint32_t* err, hipStream_t st);
 hipError_t launch_evolve_w64(const EvolveJob& J, const DGate* gates, uint32_t n_gates, bool from_zero,
                              uint32_t* err, hipStream_t st);
 uint64_t evolve_lds_capacity(int lanes, uint32_t n);

@@ -418,10 +418,19 @@ __device__ __forceinline__ double log_q_bit(float l, bool flip, float lo, float 
   return flip ? log(p) : log1p(-p);
 }
 
-// log q(y|x) of the mixture from the product's log lp for mask m.
+// log q(y|x) of the mixture eps [|m| = 1] / n + (1 - eps) exp(lp), lp the
+// product's log, in the log domain: log(e^A + e^B) = max + log1p(e^{min - max})
+// with A = log(eps / n) (only for |m| = 1) and B = log1p(-eps) + lp.  A term
+// that is zero (eps = 0, |m| != 1, eps = 1) is -inf and drops out, so exp(lp)
+// never underflows to a 0 / 0 ratio.
 __device__ __forceinline__ double log_q_mix(double lp, uint64_t m, uint32_t n, float eps) {
-  const double single = (__popcll(m) == 1) ? (double)eps / (double)n : 0.0;
-  return log(single + (1.0 - (double)eps) * exp(lp));
+  const double e = (double)eps;
+  const double ninf = -__builtin_huge_val();
+  const double A = (__popcll(m) == 1 && e > 0.0) ? log(e / (double)n) : ninf;
+  const double Bt = (e < 1.0) ? log1p(-e) + lp : ninf;
+  const double hi = fmax(A, Bt), lo = fmin(A, Bt);
+  if (hi == ninf) return ninf;
+  return hi + log1p(exp(lo - hi));
 }
 
 // Flip mask of chain c at this step, drawn from pi(x); also stores the mask

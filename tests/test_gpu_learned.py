@@ -242,3 +242,50 @@ def test_learned_chain_stationary_law(B):
     from paper_1808_00128_amd import stats
     tv = stats.total_variation(tr[:, 500:].ravel(), P)
     assert tv < 0.05, tv
+
+
+def test_learned_chain_with_underflowing_proposal_density(B):
+    """pi_min = pi_max = 1e-6 and u_bits = 0: every step proposes the mask of
+    all n = 62 bits, whose proposal density (1 - eps) 1e-6^62 ~ 1e-372 is
+    below the smallest double.  The density ratio is evaluated in the log
+    domain on both sides, so the chain still accepts iff U < P(y)/P(x), step
+    for step as the oracle chain (a 0/0 ratio would reject every move).
+
+    The circuit is H on every qubit followed by diagonal gates and phase
+    slots.  Each sparsified term then contributes b_alpha i^{q(x)} with the
+    branch phases of the phase-gate decomposition, and complementing every bit
+    conjugates the branch-dependent part, so P(y) = P(x) for y = x ^ 1...1 and
+    every proposal is accepted."""
+    n, chi, C_, steps = 62, 128, 4, 40
+    say("learned chain, underflowing proposal density n=62")
+    # H on every qubit, then diagonal gates: every term has |v| = n, so every
+    # string (the all-flip proposals included) has a nonzero amplitude.
+    rng = np.random.default_rng(14)
+    gates = [(W.OP_H, q, 0) for q in range(n)]
+    gates += W.random_clifford_gates(n, 4 * n, rng, ops=(W.OP_S, W.OP_CZ))
+    for q in rng.choice(n, size=6, replace=False).tolist():
+        gates.append((W.OP_SLOT, q, 0, float(rng.uniform(0, 2 * np.pi))))
+    circ = W.from_list(n, gates)
+    ctx = B.Context([dict(circuit=circ, chi=chi, mode="sparsify", seed=14)])
+    ctx.apply_circuit(circ)
+    T = O.Terms(circ, chi, O.SPARSIFY, seed=14)
+    x0 = start_states(T, n, C_, rng, chi)
+    p = varied_params(n, 32, seed=6)
+    net = B.MLP(ctx, n, 32, 64, p)
+    ref = OM.MLPRef(p, n, 32)
+    u_mix = np.full((C_, steps), 0.99)
+    j = rng.integers(0, n, size=(C_, steps), dtype=np.uint32)
+    u_bits = np.zeros((C_, steps, n))
+    u = rng.random(size=(C_, steps))
+    ctx.metropolis_init(x0)
+    tr, acc, fl, amp = ctx.metropolis_step_learned(net, u_mix, j, u_bits, u, 0.1, 1e-6, 1e-6)
+    otr, oacc, ofl, tie = OM.learned_chain(T, ref, x0, u_mix, j, u_bits, u, 0.1, 1e-6, 1e-6, tie=1e-9)
+    assert np.all(fl == n) and np.all(ofl == n)
+    for c in range(C_):
+        k = int(tie[c])
+        assert k >= steps - 2, (c, k)
+        assert np.array_equal(tr[c, :k], otr[c, :k]), c
+        assert np.array_equal(acc[c, :k], oacc[c, :k]), c
+    assert acc.mean() == 1.0 and oacc.mean() == 1.0
+    net.close()
+    ctx.close()
