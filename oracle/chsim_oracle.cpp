@@ -810,6 +810,205 @@ static int inner_record(const CH& c, const uint64_t* Aoff, const uint8_t* Adiag,
 }
 
 // ---------------------------------------------------------------------------
+// Inner product <a|b> of two CH forms (general stabilizer states).  The paper
+// states the O(n^3) cost and defers the method to earlier work (Sec. "Fast
+// norm estimation" and the introduction); the definition is the sum
+// <a|b> = sum_x conj(<x|a>) <x|b> with each amplitude from Eqs. (amplitude),
+// (amplitude1).  Two routes:
+//   ch_inner_brute: that sum over all 2^n strings (small n; the definition).
+//   ch_inner: the same sum restricted to where both amplitudes are non-zero.
+// <x|a> != 0 iff x = (s_a + y) G_a^T with y supported on v_a (the three-step
+// sampler's parametrization; u = x F_a = s_a + y since F_a G_a^T = I), and
+// <x|b> != 0 iff (x F_b)_j = (s_b)_j for every j outside v_b.  Their
+// intersection is x(z) = x_0 + sum_k z_k d_k (Gaussian elimination over GF(2)
+// in y), an affine space of dimension N.  On it the phase
+// conj(<x|a>) <x|b> / |.| = e^{i pi h(x)/4} has h(x(z)) - h(x_0) even, and
+// q(z) = (h(x(z)) - h(x_0)) / 2 (mod 4) is a quadratic form of the kind of
+// Lemma (Exponential Sum) (each amplitude's exponent is, and composing with an
+// affine map keeps that form), so
+//   <a|b> = e^{i pi h(x_0)/4} 2^{-(|v_a| + |v_b|)/2} Z(B_q),
+// with B_q read off q at z = 0, e_k and e_k + e_l, and Z by the exponential
+// sum of Lemma (Exponential Sum).  q is checked against B_q on further points.
+// ---------------------------------------------------------------------------
+static cplx ch_inner_brute(const CH& a, const CH& b) {
+  const int n = a.n;
+  CSum sr, si;
+  for (uint64_t x = 0; x < ((uint64_t)1 << n); ++x) {
+    int ka, va, kb, vb;
+    if (!a.amplitude(x, &ka, &va) || !b.amplitude(x, &kb, &vb)) continue;
+    ldbl re, im;
+    record_value(cplx(1.0, 0.0), kb - ka, va + vb, &re, &im);
+    sr.add(re);
+    si.add(im);
+  }
+  return cplx((double)sr.value(), (double)si.value());
+}
+
+// Returns 1 with <a|b> = e^{i pi k8/4} 2^{e2/2}, 0 if <a|b> = 0, < 0 on an
+// internal inconsistency.
+static int ch_inner(const CH& a, const CH& b, int* k8, int* e2) {
+  const int n = a.n;
+  if (b.n != n) return -1;
+  // Columns of G_a: x(y) = sum_j (s_a + y)_j colG_j.
+  auto colG = [&](int j) {
+    std::vector<uint8_t> c(n);
+    for (int i = 0; i < n; ++i) c[i] = a.G[i * n + j];
+    return c;
+  };
+  std::vector<uint8_t> x1(n, 0);
+  for (int j = 0; j < n; ++j)
+    if (a.s[j]) {
+      std::vector<uint8_t> c = colG(j);
+      for (int i = 0; i < n; ++i) x1[i] ^= c[i];
+    }
+  // Unknowns y_i, i in v_a; equations (x(y) F_b)_j = s_b[j] for j outside v_b.
+  std::vector<int> var;
+  for (int i = 0; i < n; ++i)
+    if (a.v[i]) var.push_back(i);
+  const int nv = (int)var.size();
+  std::vector<std::vector<uint8_t>> eq;  // nv coefficients + rhs
+  for (int j = 0; j < n; ++j) {
+    if (b.v[j]) continue;
+    std::vector<uint8_t> row(nv + 1, 0);
+    for (int k = 0; k < nv; ++k) {
+      std::vector<uint8_t> c = colG(var[k]);
+      int acc = 0;
+      for (int p = 0; p < n; ++p) acc += c[p] * b.F[p * n + j];
+      row[k] = (uint8_t)(acc & 1);
+    }
+    int acc = 0;
+    for (int p = 0; p < n; ++p) acc += x1[p] * b.F[p * n + j];
+    row[nv] = (uint8_t)((b.s[j] + acc) & 1);
+    eq.push_back(row);
+  }
+  // Reduced row echelon form.
+  std::vector<int> pivcol;
+  int r = 0;
+  for (int k = 0; k < nv && r < (int)eq.size(); ++k) {
+    int piv = -1;
+    for (int i = r; i < (int)eq.size(); ++i)
+      if (eq[i][k]) { piv = i; break; }
+    if (piv < 0) continue;
+    std::swap(eq[r], eq[piv]);
+    for (int i = 0; i < (int)eq.size(); ++i)
+      if (i != r && eq[i][k])
+        for (int c = 0; c <= nv; ++c) eq[i][c] ^= eq[r][c];
+    pivcol.push_back(k);
+    ++r;
+  }
+  for (int i = r; i < (int)eq.size(); ++i)
+    if (eq[i][nv]) return 0;  // the supports do not meet
+  std::vector<uint8_t> is_piv(nv, 0);
+  for (int k : pivcol) is_piv[k] = 1;
+  // y_0: pivots from the right-hand side, free variables 0.  Null vector of
+  // free variable f: e_f plus the pivots whose row has f.
+  std::vector<uint8_t> y0(nv, 0);
+  for (int i = 0; i < r; ++i) y0[pivcol[i]] = eq[i][nv];
+  std::vector<std::vector<uint8_t>> dirs;  // in x-space
+  auto x_of_y = [&](const std::vector<uint8_t>& y, bool affine) {
+    std::vector<uint8_t> x = affine ? x1 : std::vector<uint8_t>(n, 0);
+    for (int k = 0; k < nv; ++k)
+      if (y[k]) {
+        std::vector<uint8_t> c = colG(var[k]);
+        for (int i = 0; i < n; ++i) x[i] ^= c[i];
+      }
+    return x;
+  };
+  for (int f = 0; f < nv; ++f) {
+    if (is_piv[f]) continue;
+    std::vector<uint8_t> y(nv, 0);
+    y[f] = 1;
+    for (int i = 0; i < r; ++i)
+      if (eq[i][f]) y[pivcol[i]] = 1;
+    dirs.push_back(x_of_y(y, false));
+  }
+  const std::vector<uint8_t> x0 = x_of_y(y0, true);
+  const int N = (int)dirs.size();
+  auto pack = [&](const std::vector<uint8_t>& x) {
+    uint64_t w = 0;
+    for (int i = 0; i < n; ++i) w |= (uint64_t)x[i] << i;
+    return w;
+  };
+  // h(x) = phase of conj(<x|a>) <x|b> in units of pi/4.
+  int va = 0, vb = 0;
+  auto h = [&](const std::vector<uint8_t>& x, int* out) {
+    int ka, kb;
+    if (!a.amplitude(pack(x), &ka, &va) || !b.amplitude(pack(x), &kb, &vb)) return false;
+    *out = ((kb - ka) % 8 + 8) % 8;
+    return true;
+  };
+  auto point = [&](const std::vector<int>& on) {
+    std::vector<uint8_t> x = x0;
+    for (int k : on)
+      for (int i = 0; i < n; ++i) x[i] ^= dirs[k][i];
+    return x;
+  };
+  int h0;
+  if (!h(x0, &h0)) return -2;
+  auto qval = [&](const std::vector<int>& on, int* out) {
+    int hz;
+    if (!h(point(on), &hz)) return false;
+    int d = ((hz - h0) % 8 + 8) % 8;
+    if (d % 2) return false;
+    *out = d / 2;
+    return true;
+  };
+  std::vector<uint8_t> Bq(N * N, 0);
+  std::vector<int> qk(N);
+  for (int k = 0; k < N; ++k) {
+    if (!qval({k}, &qk[k])) return -3;
+    Bq[k * N + k] = (uint8_t)qk[k];
+  }
+  for (int k = 0; k < N; ++k)
+    for (int l = k + 1; l < N; ++l) {
+      int q2;
+      if (!qval({k, l}, &q2)) return -3;
+      int c = ((q2 - qk[k] - qk[l]) % 4 + 4) % 4;
+      if (c % 2) return -4;
+      Bq[k * N + l] = Bq[l * N + k] = (uint8_t)(c / 2);
+    }
+  // Check q(z) = z^T B_q z (mod 4) on every z (N <= 10) or on 64 pseudo-random z.
+  const int checks = N <= 10 ? (1 << N) : 64;
+  uint64_t st = 0x9E3779B97F4A7C15ull ^ (uint64_t)N;
+  for (int c = 0; c < checks; ++c) {
+    std::vector<int> on;
+    if (N <= 10) {
+      for (int k = 0; k < N; ++k)
+        if ((c >> k) & 1) on.push_back(k);
+    } else {
+      st ^= st << 13; st ^= st >> 7; st ^= st << 17;
+      for (int k = 0; k < N; ++k)
+        if ((st >> (k % 64)) & 1) on.push_back(k);
+    }
+    int qz;
+    if (!qval(on, &qz)) return -3;
+    int form = 0;
+    for (size_t i = 0; i < on.size(); ++i) {
+      form += Bq[on[i] * N + on[i]];
+      for (size_t j = i + 1; j < on.size(); ++j) form += 2 * Bq[on[i] * N + on[j]];
+    }
+    if ((form - qz) % 4 != 0) return -5;
+  }
+  int rs, re, is, ie;
+  expsum(N, Bq.data(), &rs, &re, &is, &ie);
+  int kz, ez;
+  if (rs == 0 && is == 0) return 0;
+  if (is == 0) { kz = rs > 0 ? 0 : 4; ez = 2 * re; }
+  else if (rs == 0) { kz = is > 0 ? 2 : 6; ez = 2 * ie; }
+  else {
+    if (re != ie) return -6;
+    if (rs > 0 && is > 0) kz = 1;
+    else if (rs < 0 && is > 0) kz = 3;
+    else if (rs < 0 && is < 0) kz = 5;
+    else kz = 7;
+    ez = 2 * re + 1;
+  }
+  *k8 = (h0 + kz) % 8;
+  *e2 = ez - (va + vb);
+  return 1;
+}
+
+// ---------------------------------------------------------------------------
 // C interface (ctypes).
 // ---------------------------------------------------------------------------
 extern "C" {
@@ -855,6 +1054,17 @@ uint64_t orc_ch_sample(void* h, uint64_t flips) { return ((CH*)h)->sample(flips)
 int orc_ch_check(void* h) { return ((CH*)h)->check(); }
 int orc_ch_inner(void* h, const uint64_t* Aoff, const uint8_t* Adiag, int* k8, int* e2) {
   return inner_record(*(CH*)h, Aoff, Adiag, k8, e2);
+}
+
+// <a|b> of two CH forms: rc 1 with e^{i pi k8/4} 2^{e2/2}, 0 for zero, < 0 on error.
+int orc_ch_inner_ch(void* ha, void* hb, int* k8, int* e2) {
+  return ch_inner(*(CH*)ha, *(CH*)hb, k8, e2);
+}
+// The same by the definition, summing over all 2^n strings.
+void orc_ch_inner_brute(void* ha, void* hb, double* out) {
+  cplx z = ch_inner_brute(*(CH*)ha, *(CH*)hb);
+  out[0] = z.real();
+  out[1] = z.imag();
 }
 
 // ---- decomposition and exponential sum ----
@@ -1070,6 +1280,44 @@ int orc_terms_inner(void* h, const uint64_t* Aoff, const uint8_t* Adiag, uint64_
   });
   int nb = 0;
   for (uint64_t l = 0; l < L; ++l) nb += bad[l];
+  return nb;
+}
+
+// overlap_l = <theta_l|psi> = sum_alpha b_alpha <theta_l|phi_alpha>, theta_l the
+// CH form of term l of hb (its b not included), psi the terms of ha; and
+// *total = sum_l conj(b^hb_l) overlap_l = <psi_hb|psi_ha>.  Returns the number
+// of failed pair records (0 expected).
+int orc_terms_inner_ch(void* ha, void* hb, double* overlap, double* total, int threads) {
+  Terms* A = (Terms*)ha;
+  Terms* Bt = (Terms*)hb;
+  const size_t L = Bt->ch.size();
+  std::vector<int> bad(L, 0);
+  parallel_for(L, threads, [&](size_t l, int) {
+    CSum sr, si;
+    for (size_t a = 0; a < A->ch.size(); ++a) {
+      int k, e2;
+      int rc = ch_inner(Bt->ch[l], A->ch[a], &k, &e2);
+      if (rc < 0) { bad[l] = 1; continue; }
+      if (rc == 0) continue;
+      ldbl re, im;
+      record_value(A->b[a], k, -e2, &re, &im);
+      sr.add(re);
+      si.add(im);
+    }
+    overlap[2 * l] = (double)sr.value();
+    overlap[2 * l + 1] = (double)si.value();
+  });
+  CSum tr, ti;
+  for (size_t l = 0; l < L; ++l) {
+    const cplx c = std::conj(Bt->b[l]);
+    const ldbl orr = overlap[2 * l], oi = overlap[2 * l + 1];
+    tr.add((ldbl)c.real() * orr - (ldbl)c.imag() * oi);
+    ti.add((ldbl)c.real() * oi + (ldbl)c.imag() * orr);
+  }
+  total[0] = (double)tr.value();
+  total[1] = (double)ti.value();
+  int nb = 0;
+  for (int e : bad) nb += e;
   return nb;
 }
 

@@ -58,6 +58,9 @@ def lib():
     L.orc_ch_project.argtypes = [C.c_void_p, C.c_int, C.c_int]
     L.orc_terms_project_pauli.argtypes = [C.c_void_p, C.c_int, u8p, u64p, u64p, C.c_int]
     L.orc_ch_project_pauli.argtypes = [C.c_void_p, C.c_int, C.c_uint64, C.c_uint64]
+    L.orc_ch_inner_ch.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int)]
+    L.orc_ch_inner_brute.argtypes = [C.c_void_p, C.c_void_p, f64p]
+    L.orc_terms_inner_ch.argtypes = [C.c_void_p, C.c_void_p, f64p, f64p, C.c_int]
     L.orc_terms_clone.argtypes = [C.c_void_p]
     L.orc_terms_clone.restype = C.c_void_p
     L.orc_ccz_decomp.restype = C.c_int
@@ -197,6 +200,30 @@ class CHForm:
         return rc, k.value, e2.value
 
 
+def inner_ch_record(bra: CHForm, ket: CHForm):
+    """<bra|ket> of two CH forms as (rc, k8, e2): 0, or e^{i pi k8/4} 2^{e2/2}
+    (the sum over the intersection of the two supports by Lemma (Exponential
+    Sum)); rc < 0 flags an inconsistency."""
+    k = C.c_int(0)
+    e2 = C.c_int(0)
+    rc = lib().orc_ch_inner_ch(bra._h, ket._h, C.byref(k), C.byref(e2))
+    return rc, k.value, e2.value
+
+
+def inner_ch(bra: CHForm, ket: CHForm) -> complex:
+    rc, k, e2 = inner_ch_record(bra, ket)
+    if rc < 0:
+        raise RuntimeError(f"inner product record failed ({rc})")
+    return 0j if rc == 0 else complex(np.exp(1j * np.pi * k / 4) * 2.0 ** (e2 / 2))
+
+
+def inner_ch_brute(bra: CHForm, ket: CHForm) -> complex:
+    """<bra|ket> = sum_x conj(<x|bra>) <x|ket> over all 2^n strings."""
+    out = np.zeros(2)
+    lib().orc_ch_inner_brute(bra._h, ket._h, out)
+    return complex(out[0], out[1])
+
+
 def phase_decomp(theta: float):
     """diag(1, e^{i theta}) = c0 S^k + c1 S^{k+1}; Eq. (Rtheta) after the theta reduction."""
     c = np.zeros(4)
@@ -308,6 +335,16 @@ class Terms:
         if bad:
             raise RuntimeError("oracle inner product produced an invalid record")
         return ov[0::2] + 1j * ov[1::2], eta
+
+    def inner_ch(self, bra: "Terms"):
+        """overlap_l = <theta_l|psi> = sum_alpha b_alpha <theta_l|phi_alpha> with
+        theta_l the CH form of bra's term l (its coefficient not included), and
+        total = sum_l conj(b_l) overlap_l = <psi_bra|psi>."""
+        ov = np.zeros(2 * bra.count)
+        tot = np.zeros(2)
+        if lib().orc_terms_inner_ch(self._h, bra._h, ov, tot, self.threads):
+            raise RuntimeError("oracle CH x CH inner product produced an invalid record")
+        return ov[0::2] + 1j * ov[1::2], complex(tot[0], tot[1])
 
     def clone(self) -> "Terms":
         """An independent copy of the built terms (CH forms, b, branches)."""

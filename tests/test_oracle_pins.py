@@ -859,3 +859,115 @@ def test_qaoa_expectation_through_the_oracle_and_its_symmetry():
             assert abs(E[sgn] - float(np.dot(np.abs(ref) ** 2, cost))) < 1e-12
         assert abs(E[1] + E[-1]) < 1e-12, E
         assert abs(E[1]) > 1e-3  # not the trivial zero
+
+
+# ---------------------------------------------------------------------------
+# General CH x CH inner product <a|b> (stabilizer states in CH form).
+# ---------------------------------------------------------------------------
+def _random_ch(n, depth, rng, gates_out=None):
+    g = W.random_clifford_gates(n, depth, rng)
+    ch = O.CHForm(n)
+    for gg in g:
+        ch.apply(*gg)
+    if gates_out is not None:
+        gates_out.extend(g)
+    return ch
+
+
+def _basis_ch(n, x, extra, rng):
+    """|x> prepared with X = H S S H, then `extra` random S/CZ/CX gates (small |v|,
+    so supports of two such states often miss each other)."""
+    ch = O.CHForm(n)
+    for q in range(n):
+        if (x >> q) & 1:
+            for op in (OP_H, OP_S, OP_S, OP_H):
+                ch.apply(op, q, 0)
+    for gg in W.random_clifford_gates(n, extra, rng, ops=(OP_S, OP_CX, OP_CZ)):
+        ch.apply(*gg)
+    return ch
+
+
+def test_inner_ch_matches_dense_and_brute_force():
+    rng = np.random.default_rng(90)
+    zeros = 0
+    for trial in range(300):
+        n = int(rng.integers(1, 7))
+        ga, gb = [], []
+        if trial % 4 == 0:
+            a = _basis_ch(n, int(rng.integers(2**n)), 10, rng)
+            b = _basis_ch(n, int(rng.integers(2**n)), 10, rng)
+            pa = np.array([a.amplitude(x) for x in range(2**n)])
+            pb = np.array([b.amplitude(x) for x in range(2**n)])
+        else:
+            a = _random_ch(n, int(rng.integers(0, 40)), rng, ga)
+            b = _random_ch(n, int(rng.integers(0, 40)), rng, gb)
+            pa, pb = dense.run_gates(n, ga), dense.run_gates(n, gb)
+        want = complex(np.vdot(pa, pb))
+        brute = O.inner_ch_brute(a, b)
+        got = O.inner_ch(a, b)
+        assert abs(brute - want) < 1e-12, (trial, brute, want)
+        assert abs(got - want) < 1e-12, (trial, got, want)
+        zeros += abs(want) < 1e-12
+    assert zeros >= 20  # orthogonal pairs (disjoint supports or cancelling phases) occur
+
+
+@pytest.mark.parametrize("n", [8, 12])
+def test_inner_ch_matches_brute_force_larger(n):
+    rng = np.random.default_rng(91 + n)
+    for trial in range(40):
+        a = _random_ch(n, int(rng.integers(5, 12 * n)), rng)
+        b = _random_ch(n, int(rng.integers(5, 12 * n)), rng)
+        assert abs(O.inner_ch(a, b) - O.inner_ch_brute(a, b)) < 1e-12
+
+
+@pytest.mark.parametrize("n", [20, 40, 64])
+def test_inner_ch_norm_clifford_invariance_and_equatorial_lemma(n):
+    """<phi|phi> = 1; <C a|C b> = <a|b> for a Clifford C applied to both;
+    <phi_A|phi> equals Lemma (Inner Product) when phi_A is built as a CH form
+    (H on every qubit, S^{A_aa}, CZ for A_ab = 1)."""
+    rng = np.random.default_rng(92 + n)
+    for trial in range(6):
+        ga, gb = [], []
+        a = _random_ch(n, 8 * n, rng, ga)
+        b = _random_ch(n, 8 * n, rng, gb)
+        assert abs(O.inner_ch(a, a) - 1) < 1e-12
+        ab = O.inner_ch(a, b)
+        cg = W.random_clifford_gates(n, 4 * n, rng)
+        for gg in cg:
+            a.apply(*gg)
+            b.apply(*gg)
+        assert abs(O.inner_ch(a, b) - ab) < 1e-12
+        Aoff, Adiag = W.random_equatorial(n, 1, rng)
+        th = O.CHForm(n)
+        for q in range(n):
+            th.apply(OP_H, q, 0)
+        for q in range(n):
+            for _ in range(int(Adiag[0, q])):
+                th.apply(OP_S, q, 0)
+            for r in range(q + 1, n):
+                if (int(Aoff[0, q]) >> r) & 1:
+                    th.apply(OP_CZ, q, r)
+        rc, k, e2 = a.inner_record(Aoff[0], Adiag[0])
+        lemma = 0j if rc == 0 else complex(np.exp(1j * np.pi * k / 4) * 2.0 ** (e2 / 2))
+        assert abs(O.inner_ch(th, a) - lemma) < 1e-12 * max(1.0, abs(lemma)) + 1e-300
+
+
+def test_inner_ch_exact_omega_norm():
+    """<Omega|Omega> of a sparsified sum by all chi^2 pair inner products
+    equals the dense norm of the sum (n = 8), and the overlaps with a second
+    term set equal the dense overlaps."""
+    rng = np.random.default_rng(93)
+    n = 8
+    circ = W.random_circuit(n, 60, rng.uniform(0, 2 * np.pi, size=5), rng)
+    T = O.Terms(circ, 40, O.SPARSIFY, seed=3)
+    xs = np.arange(2**n, dtype=np.uint64)
+    omega = T.amplitudes(xs)
+    ov, tot = T.inner_ch(T)
+    assert abs(tot - np.vdot(omega, omega)) < 1e-12
+    other = W.random_circuit(n, 60, rng.uniform(0, 2 * np.pi, size=3), rng)
+    Tb = O.Terms(other, 11, O.SPARSIFY, seed=4)
+    ov, tot = T.inner_ch(Tb)
+    for l in range(Tb.count):
+        th = np.array([Tb.term(l).amplitude(int(x)) for x in xs])
+        assert abs(ov[l] - np.vdot(th, omega)) < 1e-12
+    assert abs(tot - np.vdot(Tb.amplitudes(xs), omega)) < 1e-12
