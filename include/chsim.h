@@ -181,6 +181,22 @@ chsim_status chsim_inner_products(chsim_ctx* ctx, uint32_t inst, const uint64_t*
                                   const uint8_t* A_diag, size_t L, double* overlap, double* eta,
                                   double* eta_mean, uint32_t flags, void* stream);
 
+/* Inner products with general stabilizer states given as CH forms: for every
+ * term l of instance bra_inst (its CH form theta_l; its coefficient b_l not
+ * included), overlap[2l], overlap[2l+1] = <theta_l|psi> = sum_alpha b_alpha
+ * <theta_l|phi_alpha> over the terms of instance inst, and, if total is not
+ * NULL, total[0..1] = sum_l conj(b_l) <theta_l|psi> = <psi_bra|psi> (with
+ * bra_inst == inst: <psi|psi> exactly, chi^2 pairs).  Each pair is the sum of
+ * conj(<x|theta>) <x|phi> (Eqs. (amplitude), (amplitude1)) over the
+ * intersection of the two supports, an exponential sum of Lemma (Exponential
+ * Sum); the paper gives its O(n^3) cost (Sec. "Fast norm estimation") and
+ * defers the method to earlier work.  overlap has 2 chi_bra doubles; with
+ * CHSIM_DEVICE_PTRS overlap and total are device pointers and the call only
+ * enqueues, else it returns after copying.  EINVAL: instances of different n,
+ * null overlap.  EUNSUPPORTED: n = 64 with a ket term whose |v| = 64. */
+chsim_status chsim_inner_products_ch(chsim_ctx* ctx, uint32_t inst, uint32_t bra_inst, double* overlap,
+                                     double* total, uint32_t flags, void* stream);
+
 /* Projective gates (I + (-1)^{bits[j]} Z_{qubits[j]}) / 2, j < w, applied in order
  * to every term of the instance in place (end of Sec. "Phase-sensitive Clifford
  * simulator": Gamma|phi> = (1/2) U_C U_H (I + Q)|s>, with Q from the tableau

@@ -32,7 +32,7 @@ MAX_BRANCH = 8
 
 EXPORTED = [
     "chsim_terms_init", "chsim_terms_reset", "chsim_apply_clifford", "chsim_amplitudes",
-    "chsim_amplitudes_batch", "chsim_amplitudes_noalloc", "chsim_inner_products", "chsim_sparsification_bound",
+    "chsim_amplitudes_batch", "chsim_amplitudes_noalloc", "chsim_inner_products", "chsim_inner_products_ch", "chsim_sparsification_bound",
     "chsim_project_z", "chsim_project_pauli", "chsim_terms_copy", "chsim_sample_marginal",
     "chsim_metropolis_init", "chsim_metropolis_step", "chsim_sample_terms", "chsim_get_terms",
     "chsim_set_terms", "chsim_validate", "chsim_decompose_phase", "chsim_decompose_ccz", "chsim_set_tuning", "chsim_get_tuning",
@@ -114,6 +114,7 @@ def lib():
     L.chsim_amplitudes.argtypes = [vp, u32, vp, C.c_size_t, vp, u32, vp]
     L.chsim_amplitudes_noalloc.argtypes = [vp, u32, vp, C.c_size_t, vp, u32, vp]
     L.chsim_inner_products.argtypes = [vp, u32, vp, vp, C.c_size_t, vp, vp, vp, u32, vp]
+    L.chsim_inner_products_ch.argtypes = [vp, u32, u32, vp, vp, u32, vp]
     L.chsim_sparsification_bound.argtypes = [vp, u32, vp, vp, C.c_size_t, C.POINTER(C.c_double), vp]
     L.chsim_project_z.argtypes = [vp, u32, vp, vp, u32, vp]
     L.chsim_project_pauli.argtypes = [vp, u32, vp, vp, vp, u32, vp]
@@ -427,6 +428,16 @@ class Context:
                                           _ptr(ov)[0], _ptr(eta)[0], C.byref(mean), 0,
                                           _stream(stream)))
         return ov[0::2] + 1j * ov[1::2], eta, mean.value
+
+    def inner_products_ch(self, bra_inst, inst=0, stream=None):
+        """(overlap complex[chi_bra], total): overlap_l = <theta_l|psi_inst> with
+        theta_l the CH form of term l of bra_inst; total = <psi_bra|psi_inst>."""
+        chi_b = self.info(bra_inst)[1]
+        ov = np.zeros(2 * chi_b)
+        tot = np.zeros(2)
+        _check(lib().chsim_inner_products_ch(self._h, inst, bra_inst, _ptr(ov)[0], _ptr(tot)[0], 0,
+                                             _stream(stream)))
+        return ov[0::2] + 1j * ov[1::2], complex(tot[0], tot[1])
 
     def project_z(self, qubits, bits, inst=0, stream=None):
         """Apply prod_j (I + (-1)^{bits_j} Z_{qubits_j}) / 2 to every term in place."""

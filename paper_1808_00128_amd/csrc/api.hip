@@ -210,6 +210,8 @@ struct chsim_ctx {
   DevBuf<double> eta;
   DevBuf<double> eta_sum;
   DevBuf<unsigned long long> vcheck;  // chsim_validate: bad count, first bad index, flags
+  DevBuf<uint64_t> chrec_k, chrec_b;   // CH x CH inner products: per-term records
+  DevBuf<double2> chtotal;
   // Amplitude work queue: device copies of the last plan, and its host key.
   DevBuf<AmpInst> amp_insts;
   DevBuf<AmpItem> amp_items;
@@ -1359,6 +1361,62 @@ chsim_status chsim_inner_products(chsim_ctx* ctx, uint32_t inst, const uint64_t*
   return CHSIM_OK;
 }
 
+chsim_status chsim_inner_products_ch(chsim_ctx* ctx, uint32_t inst, uint32_t bra_inst, double* overlap,
+                                     double* total, uint32_t flags, void* stream) {
+  g_err.clear();
+  chsim_status st = check_ctx(ctx, inst);
+  if (st) return st;
+  st = check_ctx(ctx, bra_inst);
+  if (st) return st;
+  if (!overlap) return fail(CHSIM_EINVAL, "null overlap array");
+  Instance& K = ctx->inst[inst];
+  Instance& Bt = ctx->inst[bra_inst];
+  if (K.n != Bt.n) return fail(CHSIM_EINVAL, "instances differ in n (%u, %u)", K.n, Bt.n);
+  if (Bt.chi > 0x7FFFFFF0ull) return fail(CHSIM_EUNSUPPORTED, "bra instance has more than 2^31 terms");
+  const bool dev = flags & CHSIM_DEVICE_PTRS;
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t s = as_stream(stream);
+  if ((st = ensure_materialised(K, s))) return st;
+  if ((st = ensure_materialised(Bt, s))) return st;
+  const uint32_t n = K.n, L = (uint32_t)Bt.chi;
+  HIP_TRY(ctx->chrec_k.ensure(inner_ch_record_words(n, K.chi)));
+  HIP_TRY(launch_inner_ch_records(K.view(), ctx->chrec_k.p, s));
+  const uint64_t* rec_b = ctx->chrec_k.p;
+  if (bra_inst != inst) {
+    HIP_TRY(ctx->chrec_b.ensure(inner_ch_record_words(n, Bt.chi)));
+    HIP_TRY(launch_inner_ch_records(Bt.view(), ctx->chrec_b.p, s));
+    rec_b = ctx->chrec_b.p;
+  }
+  const uint32_t groups = inner_ch_groups(K.chi, L);
+  HIP_TRY(ctx->partial.ensure((size_t)groups * L));
+  double2* ovd;
+  if (dev) ovd = reinterpret_cast<double2*>(overlap);
+  else {
+    HIP_TRY(ctx->out.ensure(L));
+    ovd = ctx->out.p;
+  }
+  double2* totd = nullptr;
+  if (total) {
+    if (dev) totd = reinterpret_cast<double2*>(total);
+    else {
+      HIP_TRY(ctx->chtotal.ensure(1));
+      totd = ctx->chtotal.p;
+    }
+  }
+  HIP_TRY(hipMemsetAsync(ctx->err.p, 0, sizeof(uint32_t), s));
+  HIP_TRY(launch_inner_ch(ctx->chrec_k.p, K.b.p, K.chi, rec_b, Bt.b.p, L, n, groups, ctx->partial.p, ovd, totd,
+                          ctx->err.p, s));
+  if (!dev) {
+    HIP_TRY(hipMemcpyAsync(overlap, ovd, (size_t)L * sizeof(double2), hipMemcpyDeviceToHost, s));
+    if (total) HIP_TRY(hipMemcpyAsync(total, totd, sizeof(double2), hipMemcpyDeviceToHost, s));
+  }
+  uint32_t flag = 0;
+  HIP_TRY(hipMemcpyAsync(&flag, ctx->err.p, sizeof flag, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (flag) return fail(CHSIM_EUNSUPPORTED, "a ket term has |v| = 64 (no free index for the Z_2 lift)");
+  return CHSIM_OK;
+}
+
 static MetroView metro_view(Instance& I) {
   MetroView m;
   m.n_chain = I.n_chain;
@@ -2049,6 +2107,9 @@ chsim_status chsim_destroy(chsim_ctx* ctx) {
   ctx->eta.release();
   ctx->eta_sum.release();
   ctx->vcheck.release();
+  ctx->chrec_k.release();
+  ctx->chrec_b.release();
+  ctx->chtotal.release();
   delete ctx;
   return CHSIM_OK;
 }

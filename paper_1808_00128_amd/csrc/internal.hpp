@@ -256,6 +256,18 @@ hipError_t launch_inner(const TermsView& T, const uint64_t* Aoff, const uint8_t*
                         const InnerPlan& P, double2* partial, uint64_t* work, double2* overlap,
                         double* eta, double* eta_sum, uint32_t* err, hipStream_t st);
 
+// Inner products of two CH forms: per-term records (inner_ch_record_words
+// words for chi terms), then overlap_l = sum_a b_k[a] <theta_l|phi_a> over
+// `groups` ket-term groups (partial: groups x L), and optionally
+// total = sum_l conj(b_bra[l]) overlap_l.  err: a ket term with |v| = n = 64
+// and no free index for the Z_2 lift.
+size_t inner_ch_record_words(uint32_t n, uint64_t chi);
+hipError_t launch_inner_ch_records(const TermsView& T, uint64_t* rec, hipStream_t st);
+uint32_t inner_ch_groups(uint64_t chi_k, uint32_t L);
+hipError_t launch_inner_ch(const uint64_t* rec_k, const double2* b_k, uint64_t chi_k, const uint64_t* rec_b,
+                           const double2* b_bra, uint32_t L, uint32_t n, uint32_t groups, double2* partial,
+                           double2* overlap, double2* total, uint32_t* err, hipStream_t st);
+
 // Metropolis.
 hipError_t launch_metro_init(const TermsView& T, MetroView& Mv, hipStream_t st);
 hipError_t launch_metro_steps(const TermsView& T, MetroView& Mv, uint32_t n_steps, hipStream_t st);
