@@ -24,21 +24,49 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X: 256 CUs x 64 lanes x 2.4 GHz of 32-bit integer VALU issue.
-INT32_PEAK_OPS = 256 * 64 * 2.4e9
+# MI355X 32-bit VALU lane rate: the FP32 vector peak (157.3 TFLOP/s, an FMA
+# being 2 flops) is 78.6 T lane-operations/s = 256 CUs x 128 lanes/clk x
+# 2.4 GHz.  32-bit integer ops issue at that lane rate: the in-run
+# microbenchmark (chsim_measure_peaks) measures about 63 T int32 ops/s, above
+# the 64 lanes/clk/CU (39.3 T) figure, which therefore is not a bound.
+INT32_PEAK_OPS = 256 * 128 * 2.4e9
 HBM_PEAK_BPS = 8.0e12
 
 
 def algorithmic_ops_evolve(stats, n):
     """Int32 operations of one evolution on bit-packed rows, from the gate
-    applications it executed (per term, or per shared prefix state):
-    S-type 3, CZ 4, CX 12, H 28 n + 40, a general-branch gate 12."""
+    applications it executed (per term, or per shared prefix state), counted
+    per rule of this implementation: S-type 3, CZ 4, CX 12, H 28 n + 40, a
+    general-branch gate 12."""
     return float(stats["H"] * (28 * n + 40) + stats["CX"] * 12 + stats["CZ"] * 4 + stats["S"] * 3
                  + stats["cond"] * 12)
 
 
+def survey_ops_evolve(stats, n):
+    """The same executed gate applications at the hot-path table's per-unit
+    figure: 35 int32 operations per tableau row (n rows) per Hadamard and 10
+    per other gate."""
+    return float(stats["H"] * 35 * n + (stats["CX"] + stats["CZ"] + stats["S"] + stats["cond"]) * 10)
+
+
 # MI355X LDS: 256 CUs x 128 B/clk x 2.4 GHz.
 LDS_PEAK_BPS = 256 * 128 * 2.4e9
+
+# Peaks measured in this run by chsim_measure_peaks (int32 VALU in TOP/s, HBM
+# copy in GB/s, LDS reads in TB/s); filled in main() before any section.
+MEASURED = {}
+
+
+def roof(bound, achieved, peak, unit, measured=None, **extra):
+    """A roofline record: achieved against the chip's published (or unit-count
+    derived) peak, and against the peak measured in this run."""
+    d = {"bound": bound, "achieved": round(achieved, 4), "peak": round(peak, 3), "unit": unit,
+         "frac": round(achieved / peak, 4)}
+    if measured:
+        d["peak_measured"] = round(measured, 3)
+        d["frac_of_measured"] = round(achieved / measured, 4)
+    d.update(extra)
+    return d
 
 
 def amp_lds_bytes_per_pair(n, v_words):
@@ -67,20 +95,31 @@ def progress(msg):
     print(f"[bench] {time.strftime('%H:%M:%S')} {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(cfg, sample_terms, threads):
+def cpu_baseline(cfg, sample_terms, threads, single_terms=2048):
+    """The oracle on the host cores: `sample_terms` terms on `threads` threads
+    (std::thread over terms and strings), and `single_terms` terms on one
+    thread; both evolve their terms and evaluate them on all strings."""
     import oracle as O
 
     circ = cfg["circuit"]
-    t0 = time.perf_counter()
-    T = O.Terms(circ, cfg["chi"], O.SPARSIFY, seed=cfg["seed"],
-                alphas=np.arange(sample_terms, dtype=np.uint64), threads=threads)
-    t1 = time.perf_counter()
-    T.amplitudes(cfg["x"])
-    t2 = time.perf_counter()
-    evals = sample_terms * cfg["x"].size
-    return dict(value=evals / (t2 - t0), unit="evals/s", cores=threads, kind="oracle",
+
+    def leg(count, th):
+        t0 = time.perf_counter()
+        T = O.Terms(circ, cfg["chi"], O.SPARSIFY, seed=cfg["seed"],
+                    alphas=np.arange(count, dtype=np.uint64), threads=th)
+        t1 = time.perf_counter()
+        T.amplitudes(cfg["x"])
+        t2 = time.perf_counter()
+        return count * cfg["x"].size / (t2 - t0), t1 - t0, t2 - t1
+
+    v, te, ta = leg(sample_terms, threads)
+    v1, te1, ta1 = leg(single_terms, 1)
+    return dict(value=v, unit="evals/s", cores=threads, kind="oracle", nproc=os.cpu_count(),
                 sample=f"first {sample_terms} of {cfg['chi']} terms evolved + their amplitudes on all "
-                       f"{cfg['x'].size} strings ({t1 - t0:.2f} s evolve, {t2 - t1:.2f} s amplitudes)")
+                       f"{cfg['x'].size} strings ({te:.2f} s evolve, {ta:.2f} s amplitudes)",
+                single_thread={"value": v1, "unit": "evals/s", "cores": 1,
+                               "sample": f"first {single_terms} terms, all {cfg['x'].size} strings "
+                                         f"({te1:.2f} s evolve, {ta1:.2f} s amplitudes)"})
 
 
 # Sources each counter-measured kernel is built from (its launch planning in
@@ -152,16 +191,60 @@ def bench_norm(torch, B, W, L=1024):
     t1 = time.perf_counter()
     ctx.close()
     pairs = chi * L
+    # The hot-path table's count per (term, A): 4 n^2 (off-diagonal K_A) + 2 n^2
+    # (its mod-4 diagonal) + 2 N^2 (elimination, N = |v| + 1).
     ops_pair = 6 * n * n + 2 * (mean_v + 1) ** 2
     achieved = ops_pair * pairs / (t1 - t0) / 1e12
     return {"workload": cfg["name"] + ": n=40, 200 Clifford + 30 phase slots, chi=2^18, L=1024",
             "seconds": t1 - t0, "inner_products_per_s": pairs / (t1 - t0),
             "eta_mean": eta_mean, "eta_sem": float(np.std(eta, ddof=1) / np.sqrt(L)),
             "mean_v_weight": mean_v,
-            "roofline": {"bound": "alu", "kernel": "k_inner_prep + k_inner_pairs (lane = equatorial state)",
-                         "achieved": round(achieved, 3), "peak": round(INT32_PEAK_OPS / 1e12, 2),
-                         "unit": "TOP/s (int32)", "frac": round(achieved / (INT32_PEAK_OPS / 1e12), 4),
-                         "traffic": counter_traffic("k_inner_pairs"), "ops_per_pair": ops_pair}}
+            "roofline": roof("alu", achieved, INT32_PEAK_OPS / 1e12, "TOP/s (int32)", MEASURED.get("valu"),
+                             kernel="k_inner_prep + k_inner_pairs (lane = equatorial state)",
+                             traffic=counter_traffic("k_inner_pairs"), ops_per_pair=ops_pair,
+                             count="6 n^2 + 2 (|v| + 1)^2 int32 ops per (term, A)")}
+
+
+def bench_inner_ch(torch, B, W, L=256):
+    """Norm-estimation workload (n = 40, chi = 2^18) against L random stabilizer
+    states given as CH forms (the terms of a random Clifford circuit with 30
+    phase slots): every <theta_l|phi_alpha>, chi * L pairs, and the mean of
+    2^n |<theta_l|psi>|^2."""
+    cfg = W.config_norm(L=8)
+    circ = cfg["circuit"]
+    n, chi = circ.n, cfg["chi"]
+    rng = np.random.default_rng(1500)
+    cb = W.random_circuit(n, 400, rng.uniform(0, 2 * np.pi, size=30), rng)
+    ctx = B.Context([cfg, dict(circuit=cb, chi=L, mode="sparsify", seed=1501)])
+    ctx.set_evolve_lanes(-1)
+    ctx.apply_circuit(circ, inst=0)
+    ctx.apply_circuit(cb, inst=1)
+    ctx.inner_products_ch(1, inst=0)  # warm-up (records, kernels)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ov, _ = ctx.inner_products_ch(1, inst=0)
+    t1 = time.perf_counter()
+    vb = ctx.get_terms(0, L, inst=1)["v"]
+    vk = ctx.get_terms(0, 256, inst=0)["v"]
+    ctx.close()
+    pairs = chi * L
+    # Per pair: the equations of the bra's support (n rows of G selected by a
+    # column of F: n^2 bit-ANDs/XORs on 64-bit words), the bilinear form on the
+    # free directions (n^2), their Gram rows (N^2) and the elimination (2 N^2),
+    # N = |v| + 1, as 64-bit word operations (2 int32 ops each).
+    N = mean_popcount(vk) + 1
+    ops_pair = 2 * (2 * n * n + 3 * N * N)
+    achieved = ops_pair * pairs / (t1 - t0) / 1e12
+    eta = (2.0 ** n) * np.abs(ov) ** 2
+    return {"workload": f"{cfg['name']} terms (n=40, chi=2^18) x {L} stabilizer states from a random "
+                        "400-gate Clifford circuit with 30 phase slots",
+            "seconds": t1 - t0, "inner_products_per_s": pairs / (t1 - t0),
+            "eta_mean": float(eta.mean()), "eta_sem": float(eta.std(ddof=1) / np.sqrt(L)),
+            "mean_v_weight_bra": mean_popcount(vb), "mean_v_weight_ket": mean_popcount(vk),
+            "roofline": roof("alu", achieved, INT32_PEAK_OPS / 1e12, "TOP/s (int32)", MEASURED.get("valu"),
+                             kernel="k_chrec + k_inner_ch_pairs (one wave per pair, lane = row)",
+                             ops_per_pair=ops_pair,
+                             count="2 (2 n^2 + 3 (|v| + 1)^2) int32 ops per pair (64-bit word operations x 2)")}
 
 
 def start_points(ctx, n, chi, count, rng):
@@ -254,10 +337,18 @@ def train_proposal(B, W, ctx, n, trace, burn, delta, epochs=20, hidden=256, batc
 
 
 def chain_step_bytes(chi, n, n_chain):
-    """HBM bytes of one chain step: per term, its n rows (F_p, M_p 8 B each,
-    gamma_p 1 B) read once for all chains, each chain's cached word read and
-    the proposal word written (16 B), and the term's constants (33 B)."""
+    """HBM bytes of one chain step when every row of a term is read (the
+    flip-mask kernel stages all n rows: F_p, M_p 8 B each, gamma_p 1 B), each
+    chain's cached word read and the proposal word written (16 B), and the
+    term's constants (33 B)."""
     return float(chi * (17 * n + 16 * n_chain + 33))
+
+
+def survey_chain_step_bytes(chi, n_chain):
+    """The hot-path table's per-step bytes for single flips with one j per step
+    shared by all chains: 16 B of state read + write per chain, 17 B for row j
+    of F, M, gamma and 33 B of term constants per term."""
+    return float(chi * (16 * n_chain + 17 + 33))
 
 
 def chain_report(stats, trace, acc, ms, burn, obs, flips=None):
@@ -270,10 +361,20 @@ def chain_report(stats, trace, acc, ms, burn, obs, flips=None):
     return out
 
 
+# QAOA instance of the Metropolis sections: the paper's beta = pi/4 (its
+# Clifford mixer line) and gamma near the extremum of E(gamma) on that line
+# (E(0.367) is the minimum of the n = 12..14 instances of the same shape,
+# scanned densely; E(-gamma) = -E(gamma)).
+QAOA_BETA = float(np.pi / 4)
+QAOA_GAMMA = 0.35
+
+
 def bench_learned(torch, B, W, stats, steps=1000, n_chain=64, chi=1 << 20, eps=0.1,
                   pi_min=0.002, pi_max=0.5):
-    """QAOA n = 50, chi = 2^20: plain chains, proposal trained on them, learned chains."""
-    cfg = W.config_qaoa(chi=chi, n_chain=n_chain, steps=steps)
+    """QAOA n = 50, chi = 2^20 (beta = pi/4, gamma = 0.35, one flip bit per step
+    shared by the chains): plain chains, a proposal trained on them, learned
+    chains with the trained and with the untrained network."""
+    cfg = W.config_qaoa(chi=chi, n_chain=n_chain, steps=steps, gamma=QAOA_GAMMA, beta=QAOA_BETA, shared_j=True)
     circ = cfg["circuit"]
     n = circ.n
     ctx = B.Context([cfg])
@@ -288,12 +389,13 @@ def bench_learned(torch, B, W, stats, steps=1000, n_chain=64, chi=1 << 20, eps=0
     cost = stats.qaoa_cost(tr[:, burn:], cfg["triples"], cfg["d"])
     plain = chain_report(stats, tr, ac, ms, burn, cost)
     plain["hip_graph"] = graph
-    bytes_step = chain_step_bytes(chi, n, n_chain)
-    achieved = bytes_step * steps / (ms / 1e3) / 1e9
-    plain["roofline"] = {"bound": "hbm", "kernel": "k_propose_gather (single flips) + k_metro_accept",
-                         "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
-                         "frac": round(achieved / 8000.0, 4), "traffic": None,
-                         "bytes_per_step": bytes_step}
+    sbytes = survey_chain_step_bytes(chi, n_chain)
+    achieved = sbytes * steps / (ms / 1e3) / 1e9
+    plain["roofline"] = roof("hbm", achieved, HBM_PEAK_BPS / 1e9, "GB/s", MEASURED.get("hbm"),
+                             kernel="k_propose_gather (single flips, shared j) + k_metro_accept",
+                             traffic=None, bytes_per_step=sbytes,
+                             count="chi (16 chains + 17 + 33) B per step (state r/w, row j, constants)",
+                             bytes_per_step_all_rows=chain_step_bytes(chi, n, n_chain))
     delta = max(1, int(round(plain["tau_int"])))
     progress("metropolis: training the proposal")
     net, train = train_proposal(B, W, ctx, n, tr, burn, delta)
@@ -304,33 +406,46 @@ def bench_learned(torch, B, W, stats, steps=1000, n_chain=64, chi=1 << 20, eps=0
     learned = chain_report(stats, ltr, lac, lms, burn, lcost, lfl)
     lbytes = chain_step_bytes(chi, n, n_chain)
     lach = lbytes * steps / (lms / 1e3) / 1e9
-    learned["roofline"] = {"bound": "hbm", "kernel": "k_propose<masks> + k_mlp_fused (masks and network) + k_learned_accept",
-                           "achieved": round(lach, 1), "peak": 8000.0, "unit": "GB/s",
-                           "frac": round(lach / 8000.0, 4), "traffic": None,
-                           "bytes_per_step": lbytes}
+    learned["roofline"] = roof("hbm", lach, HBM_PEAK_BPS / 1e9, "GB/s", MEASURED.get("hbm"),
+                               kernel="k_propose<masks> + k_mlp_fused (masks and network) + k_learned_accept",
+                               traffic=None, bytes_per_step=lbytes,
+                               count="chi (17 n + 16 chains + 33) B per step (every row staged for the masks)")
     net.close()
+    progress("metropolis: learned chains with the untrained network")
+    unet = B.MLP(ctx, n, 256, max(1024, n_chain), W.mlp_init(n, 256))
+    utr, uac, ufl, ums = run_learned(torch, ctx, unet, x0, streams, eps, pi_min, pi_max)
+    unet.close()
+    ucost = stats.qaoa_cost(utr[:, burn:], cfg["triples"], cfg["d"])
+    untrained = chain_report(stats, utr, uac, ums, burn, ucost, ufl)
     ctx.close()
-    return {"plain": dict(plain, mean_cost=float(cost.mean())),
+    return {"workload": f"{cfg['name']}: QAOA p=1, {len(cfg['triples'])} triples, gamma={QAOA_GAMMA}, "
+                        f"beta=pi/4, {n_chain} chains x {steps} steps, one flip bit per step for all chains",
+            "gamma": QAOA_GAMMA, "beta": QAOA_BETA,
+            "plain": dict(plain, mean_cost=float(cost.mean())),
             "learned": dict(learned, mean_cost=float(lcost.mean()), eps=eps, pi_min=pi_min,
                             pi_max=pi_max, network="50-256-256-50 ReLU, BF16 MFMA", training=train),
-            "ess_per_s_learned_over_plain": learned["ess_per_s"] / plain["ess_per_s"]}
+            "learned_untrained": dict(untrained, mean_cost=float(ucost.mean())),
+            "ess_per_s_learned_over_plain": learned["ess_per_s"] / plain["ess_per_s"],
+            "ess_per_step_trained_over_untrained": (learned["ess"] / untrained["ess"])
+            if untrained["ess"] > 0 else None}
 
 
 def bench_matched_tv(torch, B, W, stats, n=12, triples=16, chi=1 << 16, n_chain=64, steps=3200,
                      eps=0.1, pi_min=0.002, pi_max=0.5, target=0.10):
-    """n = 12 twin of the QAOA workload: steps and seconds until the pooled
-    samples of 64 chains are within `target` total variation of the exact law
-    (all 4096 amplitudes), plain vs learned proposal.  `iid_floor` is the TV of
-    the same number of independent exact samples: no chain can go below it."""
+    """n = 12 twin of the QAOA workload (beta = pi/4, gamma = 0.35): steps and
+    seconds until the pooled samples of 64 chains are within `target` total
+    variation of the exact law (all 4096 amplitudes), plain vs learned proposal
+    (trained on the plain chains) vs the untrained network.  `iid_floor` is the
+    TV of the same number of independent exact samples: no chain can go below it."""
     rng = np.random.default_rng(2012)
-    circ = W.qaoa_circuit(n, triples, rng)[0]
+    circ = W.qaoa_circuit(n, triples, rng, gamma=QAOA_GAMMA, beta=QAOA_BETA)[0]
     spec = dict(circuit=circ, chi=chi, mode="sparsify", seed=2012)
     ctx = B.Context([spec])
     ctx.apply_circuit(circ)
     P = np.abs(ctx.amplitudes(np.arange(2**n, dtype=np.uint64))) ** 2
     P /= P.sum()
     x0 = np.array(rng.choice(2**n, size=n_chain, p=P), np.uint64)  # start in equilibrium
-    j, u = W.metropolis_streams(n, n_chain, steps, rng)
+    j, u = W.metropolis_streams(n, n_chain, steps, rng, shared_j=True)
     graph = {}
     tr, ac, ms = run_plain(torch, ctx, x0, j, u, graph=graph)
     tau, _, _ = stats.tau_int(np.array([bin(int(v)).count("1") for v in tr.ravel()],
@@ -339,13 +454,16 @@ def bench_matched_tv(torch, B, W, stats, n=12, triples=16, chi=1 << 16, n_chain=
     streams = W.learned_streams(n, n_chain, steps, rng)
     ltr, lac, lfl, lms = run_learned(torch, ctx, net, x0, streams, eps, pi_min, pi_max)
     net.close()
+    unet = B.MLP(ctx, n, 128, 1024, W.mlp_init(n, 128))
+    utr, uac, ufl, ums = run_learned(torch, ctx, unet, x0, streams, eps, pi_min, pi_max)
+    unet.close()
     ctx.close()
     checkpoints = [25, 50, 100, 200, 400, 800, 1600, 3200]
 
     def curve(t):
         return {c: stats.total_variation(t[:, :c].ravel(), P) for c in checkpoints if c <= steps}
 
-    cp, cl = curve(tr), curve(ltr)
+    cp, cl, cu = curve(tr), curve(ltr), curve(utr)
     iid = rng.choice(2**n, size=(n_chain, steps), p=P).astype(np.uint64)
     floor = curve(iid)
 
@@ -353,17 +471,28 @@ def bench_matched_tv(torch, B, W, stats, n=12, triples=16, chi=1 << 16, n_chain=
         hit = [k for k, v in c.items() if v <= target]
         return min(hit) if hit else None
 
-    sp, sl = first(cp), first(cl)
-    per_p, per_l = ms / steps, lms / steps
-    return {"workload": f"qaoa-n{n}-{triples}triples-chi{chi}, {n_chain} chains started from P",
+    def ess_per_step(t):
+        obs = np.array([bin(int(v)).count("1") for v in t.ravel()], np.float64).reshape(t.shape)
+        tt, _, _ = stats.tau_int(obs)
+        return 1.0 / (2.0 * tt)
+
+    sp, sl, su = first(cp), first(cl), first(cu)
+    per_p, per_l, per_u = ms / steps, lms / steps, ums / steps
+    return {"workload": f"qaoa-n{n}-{triples}triples-chi{chi}, gamma={QAOA_GAMMA}, beta=pi/4, "
+                        f"{n_chain} chains started from P",
             "tv_target": target, "iid_floor": floor,
             "plain": {"tv_by_steps": cp, "steps_to_target": sp, "ms_per_step": per_p,
                       "seconds_to_target": (sp * per_p / 1e3) if sp else None,
-                      "acceptance": float(ac.mean()), "hip_graph": graph},
+                      "acceptance": float(ac.mean()), "ess_per_step_weight": ess_per_step(tr),
+                      "hip_graph": graph},
             "learned": {"tv_by_steps": cl, "steps_to_target": sl, "ms_per_step": per_l,
                         "seconds_to_target": (sl * per_l / 1e3) if sl else None,
                         "acceptance": float(lac.mean()), "mean_flips": float(lfl.mean()),
-                        "training": train}}
+                        "ess_per_step_weight": ess_per_step(ltr), "training": train},
+            "learned_untrained": {"tv_by_steps": cu, "steps_to_target": su, "ms_per_step": per_u,
+                                  "seconds_to_target": (su * per_u / 1e3) if su else None,
+                                  "acceptance": float(uac.mean()), "mean_flips": float(ufl.mean()),
+                                  "ess_per_step_weight": ess_per_step(utr)}}
 
 
 def bench_uneven(torch, B, W, steps=2, warmup=1):
@@ -417,9 +546,8 @@ def bench_uneven(torch, B, W, steps=2, warmup=1):
             "evals_per_s_batched": evals / (ms_b / 1e3), "evals_per_s_per_instance": evals / (ms_s / 1e3),
             "evals_per_s_step": evals / ((ms_e + ms_b) / 1e3),
             "amplitude_strings_per_item": amp_strings,
-            "amplitude_roofline": {"bound": "lds", "achieved": lds / (ms_b / 1e3) / 1e12,
-                                   "peak": LDS_PEAK_BPS / 1e12, "unit": "TB/s (LDS table reads)",
-                                   "frac": lds / (ms_b / 1e3) / LDS_PEAK_BPS},
+            "amplitude_roofline": roof("lds", lds / (ms_b / 1e3) / 1e12, LDS_PEAK_BPS / 1e12,
+                                       "TB/s (LDS table reads)", MEASURED.get("lds")),
             "finite": ok}
 
 
@@ -494,8 +622,9 @@ def bench_hidden_shift(torch, B, W, steps=5, warmup=2):
     # = 8.25 int32 ops per CCZ per evolved state.
     ops_ev = float(st["H"] * (28 * n + 40) + st["CX"] * 12 + st["CZ"] * 4 + st["S"] * 3
                    + st["cond"] / 6 * 8.25)
+    ops_sv = survey_ops_evolve(st, n)
     evals = float(chi * n_x)
-    achieved = ops_ev / (ms_ev / 1e3) / 1e12
+    achieved = ops_sv / (ms_ev / 1e3) / 1e12
     return {"workload": cfg["name"] + f": n={n}, {cfg['n_ccz']} CCZ (8 Clifford branches each), "
                                       f"{int((circ.op != W.OP_CCZ).sum())} Clifford gates, chi={chi} sparsified "
                                       "(delta=0.3), s + 4095 strings drawn from the terms",
@@ -518,9 +647,11 @@ def bench_hidden_shift(torch, B, W, steps=5, warmup=2):
             "evolve_prefix_share": {"mode": pf_mode, "checkpoint_levels": pf_levels,
                                     "estimated_work_fraction": round(pf_frac, 4), "distinct_prefixes": st["distinct"],
                                     "gate_applications": {k: st[k] for k in ("H", "CX", "CZ", "S", "cond")}},
-            "evolve_roofline": {"bound": "alu", "achieved": round(achieved, 3),
-                                "peak": round(INT32_PEAK_OPS / 1e12, 2), "unit": "TOP/s (int32)",
-                                "frac": round(achieved / (INT32_PEAK_OPS / 1e12), 4), "ops_per_launch": ops_ev}}
+            "evolve_roofline": roof("alu", achieved, INT32_PEAK_OPS / 1e12, "TOP/s (int32)", MEASURED.get("valu"),
+                                    ops_per_launch=ops_sv,
+                                    count="35 n per executed Hadamard, 10 per other gate application",
+                                    ops_own_count=ops_ev,
+                                    frac_own_count=round(ops_ev / (ms_ev / 1e3) / INT32_PEAK_OPS, 4))}
 
 
 def main():
@@ -530,8 +661,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-terms", type=int, default=32768)
-    ap.add_argument("--sections", default="amplitudes,norm,metropolis,uneven,hidden_shift",
-                    help="comma list: amplitudes (the timed step), norm, metropolis, uneven, hidden_shift")
+    ap.add_argument("--sections", default="amplitudes,norm,inner_ch,metropolis,uneven,hidden_shift",
+                    help="comma list: amplitudes (the timed step), norm, inner_ch, metropolis, uneven, "
+                         "hidden_shift")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 1 GiB device copy first (outside the timed region), so that "
                          "hardware byte counters can be scaled against a kernel of known traffic")
@@ -553,6 +685,10 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.init()
     dev = torch.device("cuda:0")
+    progress("measuring peaks (int32 VALU, HBM copy, LDS reads)")
+    pk = B.measure_peaks(0)
+    MEASURED.update(valu=pk["int32_valu_ops_per_s"] / 1e12, hbm=pk["hbm_copy_bytes_per_s"] / 1e9,
+                    lds=pk["lds_read_bytes_per_s"] / 1e12)
     cfg = W.config_amplitudes()
     circ = cfg["circuit"]
     n, chi, xs = circ.n, cfg["chi"], cfg["x"]
@@ -626,22 +762,31 @@ def main():
     ev_stats = ctx.evolution_stats()
     lds_pair, packed_frac = amp_lds_bytes_per_pair(n, ctx.get_terms(0, min(chi, 4096))["v"])
     ops_ev = algorithmic_ops_evolve(ev_stats, n)
+    ops_sv = survey_ops_evolve(ev_stats, n)
     ops_amp = algorithmic_ops_amp(xs) * chi * n_x
     ms_ev = float(np.mean(phase["evolve"]))
     ms_amp = float(np.mean(phase["amplitudes"]))
     ms_reset = float(np.mean(phase["reset"]))
+    executed_apps = sum(ev_stats[k] for k in ("H", "CX", "CZ", "S", "cond"))
     if ms_ev >= ms_amp:
-        dom, ops, ms = f"{'k_evolve_lds' if lanes & B.CHSIM_EVOLVE_LDS else 'k_evolve'}<{lanes & 0xff},...> (CH-form evolution, {shape_name(lanes)})", ops_ev, ms_ev
+        dom = (f"{'k_evolve_lds' if lanes & B.CHSIM_EVOLVE_LDS else 'k_evolve'}<{lanes & 0xff},...> "
+               f"(CH-form evolution, {shape_name(lanes)}; all evolution launches of one step)")
         traffic = counter_traffic("k_evolve_lds" if lanes & B.CHSIM_EVOLVE_LDS else "k_evolve")
+        roofline = roof("alu", ops_sv / (ms_ev / 1e3) / 1e12, INT32_PEAK_OPS / 1e12, "TOP/s (int32)",
+                        MEASURED.get("valu"), kernel=dom, traffic=traffic,
+                        traffic_unit="bytes per launch (rocprofv3 FETCH_SIZE x 2 + WRITE_SIZE)",
+                        ops_per_launch=ops_sv, ms_per_launch=round(ms_ev, 4),
+                        count="35 n int32 ops per executed Hadamard application, 10 per other gate "
+                              "application (executed: per term or per shared prefix state)",
+                        ops_own_count=ops_ev,
+                        own_count="per rule as implemented: H 28 n + 40, CX 12, CZ 4, S-type 3, general 12",
+                        frac_own_count=round(ops_ev / (ms_ev / 1e3) / INT32_PEAK_OPS, 4))
     else:
-        dom, ops, ms = f"k_amp<float, {amp_strings // 256}> + k_reduce_ranges (amplitudes, FP32C)", ops_amp, ms_amp
-        traffic = counter_traffic("k_amp<float>")
-    achieved = ops / (ms / 1e3) / 1e12
-    roofline = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3),
-                "peak": round(INT32_PEAK_OPS / 1e12, 2), "unit": "TOP/s (int32)",
-                "frac": round(achieved / (INT32_PEAK_OPS / 1e12), 4), "traffic": traffic,
-                "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x 2 + WRITE_SIZE)",
-                "ops_per_launch": ops, "ms_per_launch": round(ms, 4)}
+        dom = f"k_amp<float, {amp_strings // 256}> + k_reduce_ranges (amplitudes, FP32C)"
+        roofline = roof("alu", ops_amp / (ms_amp / 1e3) / 1e12, INT32_PEAK_OPS / 1e12, "TOP/s (int32)",
+                        MEASURED.get("valu"), kernel=dom, traffic=counter_traffic("k_amp<float>"),
+                        ops_per_launch=ops_amp, ms_per_launch=round(ms_amp, 4),
+                        count="8 |x| + 35 int32 ops per (term, x)")
 
     result = {
         "metric": "term-amplitude evals/s (chi*|x|/s)",
@@ -673,16 +818,20 @@ def main():
         "amplitude_autotune": {"strings_per_item": amp_strings,
                                "ms_by_value": {"256": round(amp_tune_ms[0], 4), "512": round(amp_tune_ms[1], 4)}},
         "amplitude_kernel_evals_per_s": chi * n_x / (ms_amp / 1e3),
-        "evolve_gates_per_s": chi * circ.n_gates / (ms_ev / 1e3),
+        "evolve_gates_per_s_per_term_count": chi * circ.n_gates / (ms_ev / 1e3),
+        "evolve_gates_per_s_executed": executed_apps / (ms_ev / 1e3),
+        "peaks_measured": dict(MEASURED),
         "fp32c_vs_fp64_normwise": fp32c_vs_fp64,
         "roofline": roofline,
-        "amplitude_roofline": {"bound": "lds",
-                               "kernel": f"k_amp<float, {amp_strings // 256}> (with k_amp_prep, k_reduce_ranges)",
-                               "achieved": round(lds_pair * chi * n_x / (ms_amp / 1e3) / 1e12, 3),
-                               "peak": round(LDS_PEAK_BPS / 1e12, 2), "unit": "TB/s (LDS table reads)",
-                               "frac": round(lds_pair * chi * n_x / (ms_amp / 1e3) / LDS_PEAK_BPS, 4),
-                               "lds_bytes_per_pair": lds_pair, "packed_fraction": packed_frac,
-                               "paper_ops_per_s": round(ops_amp / (ms_amp / 1e3) / 1e12, 3)},
+        "amplitude_roofline": roof("lds", lds_pair * chi * n_x / (ms_amp / 1e3) / 1e12, LDS_PEAK_BPS / 1e12,
+                                   "TB/s (LDS table reads)", MEASURED.get("lds"),
+                                   kernel=f"k_amp<float, {amp_strings // 256}> (with k_amp_prep, k_reduce_ranges)",
+                                   lds_bytes_per_pair=lds_pair, packed_fraction=packed_frac,
+                                   count="8-byte table reads per (term, x): ceil(n/4) + 1 packed, "
+                                         "2 ceil(n/4) + 1 otherwise (lookup-table algorithm)",
+                                   paper_ops_per_s=round(ops_amp / (ms_amp / 1e3) / 1e12, 3),
+                                   paper_count="8 |x| + 35 int32 ops per (term, x) (set-bit loop; this "
+                                               "kernel does less work per pair)"),
     }
     ctx.close()
     del ctx
@@ -697,6 +846,9 @@ def main():
     if "hidden_shift" in sections:
         progress("section hidden_shift")
         result["hidden_shift_ccz"] = bench_hidden_shift(torch, B, W)
+    if "inner_ch" in sections:
+        progress("section inner_ch (general stabilizer states)")
+        result["inner_products_ch"] = bench_inner_ch(torch, B, W)
     if "metropolis" in sections:
         from paper_1808_00128_amd import stats
 

@@ -461,6 +461,18 @@ chsim_status chsim_evolution_stats(chsim_ctx* ctx, uint32_t inst, uint64_t apps[
 chsim_status chsim_instance_info(chsim_ctx* ctx, uint32_t inst, uint32_t* n, uint64_t* chi,
                                  double* l1);
 
+/* Roofline peaks of HIP device `device`, measured by microbenchmarks (they
+ * measure the machine, not the method): out[0] = int32 VALU operations per
+ * second (independent v_xor_b32 / v_add_u32 chains in every lane of a full
+ * grid, one operation per lane per instruction), out[1] = HBM bytes per
+ * second of a device-to-device copy of 1 GiB (bytes read plus bytes written;
+ * the faster of a streaming copy kernel and the runtime's copy),
+ * out[2] = LDS bytes per second of conflict-free 8-byte reads.  Each is the
+ * best of three timed runs after a warm-up run.  Allocates and frees about
+ * 2 GiB of device memory; synchronous; changes the current device.  EINVAL:
+ * no such device or a null out; ENOMEM, EDEVICE on runtime failures. */
+chsim_status chsim_measure_peaks(int device, double out[3]);
+
 /* Release the context and its device memory.  NULL is accepted. */
 chsim_status chsim_destroy(chsim_ctx* ctx);
 

@@ -36,7 +36,7 @@ EXPORTED = [
     "chsim_project_z", "chsim_project_pauli", "chsim_terms_copy", "chsim_sample_marginal",
     "chsim_metropolis_init", "chsim_metropolis_step", "chsim_sample_terms", "chsim_get_terms",
     "chsim_set_terms", "chsim_validate", "chsim_decompose_phase", "chsim_decompose_ccz", "chsim_set_tuning", "chsim_get_tuning",
-    "chsim_instance_info", "chsim_evolution_stats", "chsim_destroy", "chsim_mlp_create", "chsim_mlp_destroy",
+    "chsim_instance_info", "chsim_evolution_stats", "chsim_measure_peaks", "chsim_destroy", "chsim_mlp_create", "chsim_mlp_destroy",
     "chsim_mlp_get_params", "chsim_mlp_set_params", "chsim_mlp_forward", "chsim_mlp_loss_grad",
     "chsim_mlp_train", "chsim_metropolis_step_learned",
     "chsim_last_error",
@@ -136,6 +136,7 @@ def lib():
     L.chsim_instance_info.argtypes = [vp, u32, C.POINTER(C.c_uint32), C.POINTER(C.c_uint64),
                                       C.POINTER(C.c_double)]
     L.chsim_destroy.argtypes = [vp]
+    L.chsim_measure_peaks.argtypes = [C.c_int, C.POINTER(C.c_double)]
     L.chsim_mlp_create.argtypes = [vp, u32, u32, u32, vp, C.POINTER(C.c_void_p)]
     L.chsim_mlp_destroy.argtypes = [vp]
     L.chsim_mlp_get_params.argtypes = [vp, vp]
@@ -184,6 +185,16 @@ def _stream(stream):
     except Exception:  # noqa: BLE001
         pass
     return None
+
+
+def measure_peaks(device: int = 0) -> dict:
+    """Microbenchmarked peaks of the device: int32 VALU ops/s, HBM copy
+    bytes/s (read + write), LDS 8-byte-read bytes/s (chsim_measure_peaks)."""
+    out = (C.c_double * 3)()
+    st = lib().chsim_measure_peaks(int(device), out)
+    if st != CHSIM_OK:
+        raise ChsimError(st, "chsim_measure_peaks failed")
+    return {"int32_valu_ops_per_s": out[0], "hbm_copy_bytes_per_s": out[1], "lds_read_bytes_per_s": out[2]}
 
 
 def gate_array(circuit: W.Circuit) -> np.ndarray:

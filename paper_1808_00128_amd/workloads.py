@@ -157,10 +157,16 @@ def random_equatorial(n: int, L: int, rng: np.random.Generator):
     return Aoff, Adiag
 
 
-def metropolis_streams(n: int, n_chain: int, steps: int, rng: np.random.Generator):
+def metropolis_streams(n: int, n_chain: int, steps: int, rng: np.random.Generator, shared_j: bool = False):
     """Random inputs a single-bit-flip chain consumes: the bit to flip and the
-    uniform for the accept test, per chain and step."""
-    j = rng.integers(0, n, size=(n_chain, steps), dtype=np.uint32)
+    uniform for the accept test, per chain and step.  shared_j: one bit per
+    step for every chain (each chain is still the paper's chain: its proposal
+    is a uniform bit independent of its state), so a step reads one row of
+    every term's tableau for all chains."""
+    if shared_j:
+        j = np.repeat(rng.integers(0, n, size=(1, steps), dtype=np.uint32), n_chain, axis=0)
+    else:
+        j = rng.integers(0, n, size=(n_chain, steps), dtype=np.uint32)
     u = rng.random(size=(n_chain, steps))
     return j, u
 
@@ -234,10 +240,13 @@ def qaoa_circuit(n: int, n_triples: int, rng: np.random.Generator, gamma=None, b
 
 
 def config_qaoa(seed: int = 1004, n: int = 50, n_triples: int = 60, chi: int = 1 << 20,
-                n_chain: int = 64, steps: int = 1000) -> dict:
+                n_chain: int = 64, steps: int = 1000, gamma=None, beta=None, shared_j: bool = False) -> dict:
+    """QAOA workload: the p = 1 circuit of qaoa_circuit (gamma, beta drawn
+    uniformly in (0, pi) unless given), chi sparsified terms, and the random
+    inputs of n_chain single-flip chains of `steps` steps."""
     rng = np.random.default_rng(seed)
-    circ, triples, d, gamma, beta = qaoa_circuit(n, n_triples, rng)
-    j, u = metropolis_streams(n, n_chain, steps, rng)
+    circ, triples, d, gamma, beta = qaoa_circuit(n, n_triples, rng, gamma=gamma, beta=beta)
+    j, u = metropolis_streams(n, n_chain, steps, rng, shared_j=shared_j)
     return dict(name=f"qaoa-n{n}-chi{chi}-chains{n_chain}x{steps}", circuit=circ, chi=chi,
                 mode="sparsify", triples=triples, d=d, gamma=gamma, beta=beta, jstream=j,
                 ustream=u, seed=seed, n_chain=n_chain, steps=steps)
