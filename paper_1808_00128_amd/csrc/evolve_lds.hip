@@ -171,59 +171,53 @@ __global__ __launch_bounds__(256) void k_evolve_lds(EvolveJob J, const DGate* __
       // all ones or zero by a sign-extending bit-field extract.
       const uint32_t qs = qh & 31u;
       const bool hq = qh >= 32u;
-      const uint32_t qbl = hq ? 0u : (1u << qs), qbh = hq ? (1u << qs) : 0u;
-      const uint32_t Wl = (uint32_t)W, Wh = (uint32_t)(W >> 32);
-      const uint32_t V1l = (uint32_t)V1, V1h = (uint32_t)(V1 >> 32);
+      // One branch-free row update for both cases of Prop. H, with per-term
+      // masks (a wave's terms usually take both cases):
+      //   V_1 case, R[CX_{i,q}] for i in W:  G ^= W G_pq; F ^= e_q par(F & W); M ^= W M_pq.
+      //   V_0 case, R[CX_{q,i}] for i in W, then R[CZ_{q,i}] for i in V_1:
+      //     G ^= e_q par(G & W); F ^= W F_pq; M ^= e_q par((F & V_1) + (M & W)) + V_1 F_pq;
+      //     gamma += 2 F_pq par(F & V_1)   (W and V_1 are disjoint, so F & V_1
+      //     is the same before and after F's update).
+      //   Then R[S_q] if a: M ^= e_q F'_pq, gamma -= F'_pq, F'_pq = F_pq + [V_1 case] par(F & W).
+      // P1 = par(F & X1) with X1 = W (V_1 case) or V_1 (V_0 case) serves both.
+      const uint64_t u1m = use0 ? 0ull : ~0ull, u0m = ~u1m;
+      const uint64_t W1 = W & u1m, W0 = W & u0m, V1m = V1 & u0m, X1 = use0 ? V1 : W;
+      const uint64_t qb0 = qb & u0m, qb1 = qb & u1m, qba = a ? qb : 0ull;
+      const uint32_t W1l = (uint32_t)W1, W1h = (uint32_t)(W1 >> 32), W0l = (uint32_t)W0, W0h = (uint32_t)(W0 >> 32);
+      const uint32_t V1ml = (uint32_t)V1m, V1mh = (uint32_t)(V1m >> 32);
+      const uint32_t X1l = (uint32_t)X1, X1h = (uint32_t)(X1 >> 32);
+      const uint32_t qb0l = (uint32_t)qb0, qb0h = (uint32_t)(qb0 >> 32), qb1l = (uint32_t)qb1,
+                     qb1h = (uint32_t)(qb1 >> 32), qbal = (uint32_t)qba, qbah = (uint32_t)(qba >> 32);
+      const uint32_t u0 = use0 ? ~0u : 0u, u1 = ~u0, am = a ? ~0u : 0u;
       // When no term of the wave in the V_0 case has W != 0 (|v| close to n
-      // leaves V_0 with at most one bit), R[CX_{q,i}] is empty for all of
-      // them and their rows take only R[CZ_{q,i}] (wave-uniform test).
+      // leaves V_0 with at most one bit), the parities of G & W and M & W
+      // vanish for every term (wave-uniform test).
       const bool w_empty = __ballot(use0 && W != 0ull) == 0ull;
       auto row = [&](uint32_t j) {
         const uint64_t F = LF[j * 64u], G = LG[j * 64u], M = LM[j * 64u];
         uint32_t Fl = (uint32_t)F, Fh = (uint32_t)(F >> 32);
         uint32_t Gl = (uint32_t)G, Gh = (uint32_t)(G >> 32);
         uint32_t Ml = (uint32_t)M, Mh = (uint32_t)(M >> 32);
-        if (use0 && w_empty) {
-          // R[CZ_{q,i}], i in V_1: M_{.,q} ^= F_{.,i}; M_{.,i} ^= F_{.,q}; gamma += 2 F_{.,q} F_{.,i}.
-          const uint32_t mf = bit_mask(hq ? Fh : Fl, qs);
-          const uint32_t c = (uint32_t)__popc(Fl & V1l) + (uint32_t)__popc(Fh & V1h);
-          const uint32_t mm = bit_mask(c, 0u);
-          Ml ^= (qbl & mm) ^ (V1l & mf);
-          Mh ^= (qbh & mm) ^ (V1h & mf);
-          gw ^= (mf & c & 1u) << (16u + j);
-        } else if (use0) {
-          // R[CX_{q,i}], i in W: G_{.,q} ^= G_{.,i}; F_{.,i} ^= F_{.,q}; M_{.,q} ^= M_{.,i}.
-          // R[CZ_{q,i}], i in V_1: M_{.,q} ^= F_{.,i}; M_{.,i} ^= F_{.,q}; gamma += 2 F_{.,q} F_{.,i}.
-          const uint32_t mf = bit_mask(hq ? Fh : Fl, qs);
-          const uint32_t mg = bit_mask((uint32_t)__popc(Gl & Wl) + (uint32_t)__popc(Gh & Wh), 0u);
-          Gl ^= qbl & mg;
-          Gh ^= qbh & mg;
-          Fl ^= Wl & mf;
-          Fh ^= Wh & mf;
-          const uint32_t c = (uint32_t)__popc(Fl & V1l) + (uint32_t)__popc(Fh & V1h);
-          const uint32_t mm = bit_mask(c + (uint32_t)__popc(Ml & Wl) + (uint32_t)__popc(Mh & Wh), 0u);
-          Ml ^= (qbl & mm) ^ (V1l & mf);
-          Mh ^= (qbh & mm) ^ (V1h & mf);
-          gw ^= (mf & c & 1u) << (16u + j);
-        } else {
-          // R[CX_{i,q}], i in W: G_{.,i} ^= G_{.,q}; F_{.,q} ^= F_{.,i}; M_{.,i} ^= M_{.,q}.
-          const uint32_t mg = bit_mask(hq ? Gh : Gl, qs), mm = bit_mask(hq ? Mh : Ml, qs);
-          const uint32_t mf = bit_mask((uint32_t)__popc(Fl & Wl) + (uint32_t)__popc(Fh & Wh), 0u);
-          Gl ^= Wl & mg;
-          Gh ^= Wh & mg;
-          Fl ^= qbl & mf;
-          Fh ^= qbh & mf;
-          Ml ^= Wl & mm;
-          Mh ^= Wh & mm;
+        const uint32_t fqm = bit_mask(hq ? Fh : Fl, qs);
+        const uint32_t gqm = bit_mask(hq ? Gh : Gl, qs);
+        const uint32_t mqm = bit_mask(hq ? Mh : Ml, qs);
+        const uint32_t p1 = bit_mask((uint32_t)__popc(Fl & X1l) + (uint32_t)__popc(Fh & X1h), 0u);
+        uint32_t pg = 0u, pm = p1;
+        if (!w_empty) {
+          pg = bit_mask((uint32_t)__popc(Gl & W0l) + (uint32_t)__popc(Gh & W0h), 0u);
+          pm ^= bit_mask((uint32_t)__popc(Ml & W0l) + (uint32_t)__popc(Mh & W0h), 0u);
+          Fl ^= W0l & fqm;
+          Fh ^= W0h & fqm;
         }
-        if (a) {
-          // R[S_q]: M_{.,q} ^= F_{.,q}; gamma -= F_{.,q}.
-          const uint32_t fb = ((hq ? Fh : Fl) >> qs) & 1u;
-          const uint32_t mfb = 0u - fb;
-          Ml ^= qbl & mfb;
-          Mh ^= qbh & mfb;
-          fbits |= fb << j;
-        }
+        Gl ^= (W1l & gqm) ^ (qb0l & pg);
+        Gh ^= (W1h & gqm) ^ (qb0h & pg);
+        Fl ^= qb1l & p1;
+        Fh ^= qb1h & p1;
+        const uint32_t fq2 = fqm ^ (u1 & p1);  // F_pq after V_C
+        Ml ^= (W1l & mqm) ^ (V1ml & fqm) ^ (qb0l & pm) ^ (qbal & fq2);
+        Mh ^= (W1h & mqm) ^ (V1mh & fqm) ^ (qb0h & pm) ^ (qbah & fq2);
+        gw ^= (u0 & fqm & p1 & 1u) << (16u + j);
+        fbits |= (am & fq2 & 1u) << j;
         LF[j * 64u] = ((uint64_t)Fh << 32) | Fl;
         LG[j * 64u] = ((uint64_t)Gh << 32) | Gl;
         LM[j * 64u] = ((uint64_t)Mh << 32) | Ml;
