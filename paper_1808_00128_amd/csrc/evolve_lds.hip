@@ -15,6 +15,8 @@
 // p = li, li + LPT, ...: load, apply the batch of commuting right rules of
 // V_C, store.  gamma stays in a register: bit j of one word is the low bit of
 // gamma of row li + LPT j and bit 16 + j its high bit.
+#include <type_traits>
+
 #include "device_common.hpp"
 #include "internal.hpp"
 
@@ -182,18 +184,22 @@ __global__ __launch_bounds__(256) void k_evolve_lds(EvolveJob J, const DGate* __
       // P1 = par(F & X1) with X1 = W (V_1 case) or V_1 (V_0 case) serves both.
       const uint64_t u1m = use0 ? 0ull : ~0ull, u0m = ~u1m;
       const uint64_t W1 = W & u1m, W0 = W & u0m, V1m = V1 & u0m, X1 = use0 ? V1 : W;
-      const uint64_t qb0 = qb & u0m, qb1 = qb & u1m, qba = a ? qb : 0ull;
+      const uint64_t qb0 = qb & u0m, qb1 = qb & u1m;
       const uint32_t W1l = (uint32_t)W1, W1h = (uint32_t)(W1 >> 32), W0l = (uint32_t)W0, W0h = (uint32_t)(W0 >> 32);
       const uint32_t V1ml = (uint32_t)V1m, V1mh = (uint32_t)(V1m >> 32);
       const uint32_t X1l = (uint32_t)X1, X1h = (uint32_t)(X1 >> 32);
       const uint32_t qb0l = (uint32_t)qb0, qb0h = (uint32_t)(qb0 >> 32), qb1l = (uint32_t)qb1,
-                     qb1h = (uint32_t)(qb1 >> 32), qbal = (uint32_t)qba, qbah = (uint32_t)(qba >> 32);
+                     qb1h = (uint32_t)(qb1 >> 32);
+      const uint32_t qbl = hq ? 0u : (1u << qs), qbh = hq ? (1u << qs) : 0u;
       const uint32_t u0 = use0 ? ~0u : 0u, u1 = ~u0, am = a ? ~0u : 0u;
       // When no term of the wave in the V_0 case has W != 0 (|v| close to n
       // leaves V_0 with at most one bit), the parities of G & W and M & W
       // vanish for every term (wave-uniform test).
       const bool w_empty = __ballot(use0 && W != 0ull) == 0ull;
-      auto row = [&](uint32_t j) {
+      // Bit q of each matrix's row, the parity P1, then the masked XORs; the
+      // two single-bit terms on bit q of M share one mask z.
+      uint32_t gam2 = 0u;  // rows whose gamma gains 2
+      auto row = [&](uint32_t j, auto general) {
         const uint64_t F = LF[j * 64u], G = LG[j * 64u], M = LM[j * 64u];
         uint32_t Fl = (uint32_t)F, Fh = (uint32_t)(F >> 32);
         uint32_t Gl = (uint32_t)G, Gh = (uint32_t)(G >> 32);
@@ -201,22 +207,25 @@ __global__ __launch_bounds__(256) void k_evolve_lds(EvolveJob J, const DGate* __
         const uint32_t fqm = bit_mask(hq ? Fh : Fl, qs);
         const uint32_t gqm = bit_mask(hq ? Gh : Gl, qs);
         const uint32_t mqm = bit_mask(hq ? Mh : Ml, qs);
-        const uint32_t p1 = bit_mask((uint32_t)__popc(Fl & X1l) + (uint32_t)__popc(Fh & X1h), 0u);
-        uint32_t pg = 0u, pm = p1;
-        if (!w_empty) {
-          pg = bit_mask((uint32_t)__popc(Gl & W0l) + (uint32_t)__popc(Gh & W0h), 0u);
-          pm ^= bit_mask((uint32_t)__popc(Ml & W0l) + (uint32_t)__popc(Mh & W0h), 0u);
+        const uint32_t p1 = bit_mask(__popc(Fh & X1h) + __popc(Fl & X1l), 0u);
+        uint32_t pm = p1;
+        if constexpr (decltype(general)::value) {
+          const uint32_t pg = bit_mask(__popc(Gh & W0h) + __popc(Gl & W0l), 0u);
+          pm ^= bit_mask(__popc(Mh & W0h) + __popc(Ml & W0l), 0u);
           Fl ^= W0l & fqm;
           Fh ^= W0h & fqm;
+          Gl ^= qb0l & pg;
+          Gh ^= qb0h & pg;
         }
-        Gl ^= (W1l & gqm) ^ (qb0l & pg);
-        Gh ^= (W1h & gqm) ^ (qb0h & pg);
+        Gl ^= W1l & gqm;
+        Gh ^= W1h & gqm;
         Fl ^= qb1l & p1;
         Fh ^= qb1h & p1;
-        const uint32_t fq2 = fqm ^ (u1 & p1);  // F_pq after V_C
-        Ml ^= (W1l & mqm) ^ (V1ml & fqm) ^ (qb0l & pm) ^ (qbal & fq2);
-        Mh ^= (W1h & mqm) ^ (V1mh & fqm) ^ (qb0h & pm) ^ (qbah & fq2);
-        gw ^= (u0 & fqm & p1 & 1u) << (16u + j);
+        const uint32_t fq2 = fqm ^ (u1 & p1);      // F_pq after V_C
+        const uint32_t z = (u0 & pm) ^ (am & fq2);  // bit q of M flips
+        Ml = Ml ^ (W1l & mqm) ^ (V1ml & fqm) ^ (qbl & z);
+        Mh = Mh ^ (W1h & mqm) ^ (V1mh & fqm) ^ (qbh & z);
+        gam2 |= (u0 & fqm & p1 & 1u) << j;
         fbits |= (am & fq2 & 1u) << j;
         LF[j * 64u] = ((uint64_t)Fh << 32) | Fl;
         LG[j * 64u] = ((uint64_t)Gh << 32) | Gl;
@@ -224,9 +233,16 @@ __global__ __launch_bounds__(256) void k_evolve_lds(EvolveJob J, const DGate* __
       };
       // Rows j < n / LPT exist in every lane (no per-lane bound in the loop);
       // row n / LPT only in lanes li < n % LPT.
+      if (w_empty) {
 #pragma unroll 2
-      for (uint32_t j = 0; j < nfull; ++j) row(j);
-      if (li < ntail) row(nfull);
+        for (uint32_t j = 0; j < nfull; ++j) row(j, std::false_type{});
+        if (li < ntail) row(nfull, std::false_type{});
+      } else {
+#pragma unroll 2
+        for (uint32_t j = 0; j < nfull; ++j) row(j, std::true_type{});
+        if (li < ntail) row(nfull, std::true_type{});
+      }
+      gw ^= gam2 << 16;
       // gamma -= 1 on the rows in fbits: low bit flips, high bit borrows.
       gw ^= fbits ^ ((fbits & ~gw) << 16);
       s = (y & ~qb) | ((uint64_t)cc << qh);
