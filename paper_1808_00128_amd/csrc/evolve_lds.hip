@@ -18,6 +18,7 @@
 #include <type_traits>
 
 #include "device_common.hpp"
+#include "hrow.hpp"
 #include "internal.hpp"
 
 namespace chsim {
@@ -39,11 +40,6 @@ __device__ __forceinline__ uint32_t gam_get(uint32_t gw, uint32_t j) {
 __device__ __forceinline__ uint32_t gam_add(uint32_t gw, uint32_t j, uint32_t a) {
   const uint32_t lo = (gw >> j) & 1u, a0 = a & 1u, a1 = (a >> 1) & 1u;
   return gw ^ (a0 << j) ^ ((a1 ^ (lo & a0)) << (16u + j));
-}
-
-// All ones if bit b (< 32) of x is set, else zero.
-__device__ __forceinline__ uint32_t bit_mask(uint32_t x, uint32_t b) {
-  return (uint32_t)__builtin_amdgcn_sbfe((int)x, b, 1u);
 }
 
 template <int LPT, bool kFromZero>
@@ -168,65 +164,24 @@ __global__ __launch_bounds__(256) void k_evolve_lds(EvolveJob J, const DGate* __
         cc = (dp == 2u || dp == 1u) ? 1u : 0u;
         dw = ph + (dp == 1u ? 1u : (dp == 3u ? 7u : 0u));
       }
-      uint32_t fbits = 0u;  // F_{p,q} after V_C for the lane's rows, if a
-      // Rows are updated as 32-bit halves: qs, hq locate bit qh, a mask is
-      // all ones or zero by a sign-extending bit-field extract.
-      const uint32_t qs = qh & 31u;
-      const bool hq = qh >= 32u;
-      // One branch-free row update for both cases of Prop. H, with per-term
-      // masks (a wave's terms usually take both cases):
-      //   V_1 case, R[CX_{i,q}] for i in W:  G ^= W G_pq; F ^= e_q par(F & W); M ^= W M_pq.
-      //   V_0 case, R[CX_{q,i}] for i in W, then R[CZ_{q,i}] for i in V_1:
-      //     G ^= e_q par(G & W); F ^= W F_pq; M ^= e_q par((F & V_1) + (M & W)) + V_1 F_pq;
-      //     gamma += 2 F_pq par(F & V_1)   (W and V_1 are disjoint, so F & V_1
-      //     is the same before and after F's update).
-      //   Then R[S_q] if a: M ^= e_q F'_pq, gamma -= F'_pq, F'_pq = F_pq + [V_1 case] par(F & W).
-      // P1 = par(F & X1) with X1 = W (V_1 case) or V_1 (V_0 case) serves both.
-      const uint64_t u1m = use0 ? 0ull : ~0ull, u0m = ~u1m;
-      const uint64_t W1 = W & u1m, W0 = W & u0m, V1m = V1 & u0m, X1 = use0 ? V1 : W;
-      const uint64_t qb0 = qb & u0m, qb1 = qb & u1m;
-      const uint32_t W1l = (uint32_t)W1, W1h = (uint32_t)(W1 >> 32), W0l = (uint32_t)W0, W0h = (uint32_t)(W0 >> 32);
-      const uint32_t V1ml = (uint32_t)V1m, V1mh = (uint32_t)(V1m >> 32);
-      const uint32_t X1l = (uint32_t)X1, X1h = (uint32_t)(X1 >> 32);
-      const uint32_t qb0l = (uint32_t)qb0, qb0h = (uint32_t)(qb0 >> 32), qb1l = (uint32_t)qb1,
-                     qb1h = (uint32_t)(qb1 >> 32);
-      const uint32_t qbl = hq ? 0u : (1u << qs), qbh = hq ? (1u << qs) : 0u;
-      const uint32_t u0 = use0 ? ~0u : 0u, u1 = ~u0, am = a ? ~0u : 0u;
+      // V_C on the lane's rows (hrow.hpp); gamma's changes are collected as
+      // bit j of gam2 (+2) and fbits (-1) and applied after the loop.
+      const HRowMasks K = h_row_masks(W, V1, qh, use0, a);
       // When no term of the wave in the V_0 case has W != 0 (|v| close to n
-      // leaves V_0 with at most one bit), the parities of G & W and M & W
-      // vanish for every term (wave-uniform test).
+      // leaves V_0 with at most one bit), the W terms of that case vanish for
+      // every term (wave-uniform test).
       const bool w_empty = __ballot(use0 && W != 0ull) == 0ull;
-      // Bit q of each matrix's row, the parity P1, then the masked XORs; the
-      // two single-bit terms on bit q of M share one mask z.
-      uint32_t gam2 = 0u;  // rows whose gamma gains 2
+      uint32_t gam2 = 0u, fbits = 0u;
       auto row = [&](uint32_t j, auto general) {
         const uint64_t F = LF[j * 64u], G = LG[j * 64u], M = LM[j * 64u];
         uint32_t Fl = (uint32_t)F, Fh = (uint32_t)(F >> 32);
         uint32_t Gl = (uint32_t)G, Gh = (uint32_t)(G >> 32);
         uint32_t Ml = (uint32_t)M, Mh = (uint32_t)(M >> 32);
-        const uint32_t fqm = bit_mask(hq ? Fh : Fl, qs);
-        const uint32_t gqm = bit_mask(hq ? Gh : Gl, qs);
-        const uint32_t mqm = bit_mask(hq ? Mh : Ml, qs);
-        const uint32_t p1 = bit_mask(__popc(Fh & X1h) + __popc(Fl & X1l), 0u);
-        uint32_t pm = p1;
-        if constexpr (decltype(general)::value) {
-          const uint32_t pg = bit_mask(__popc(Gh & W0h) + __popc(Gl & W0l), 0u);
-          pm ^= bit_mask(__popc(Mh & W0h) + __popc(Ml & W0l), 0u);
-          Fl ^= W0l & fqm;
-          Fh ^= W0h & fqm;
-          Gl ^= qb0l & pg;
-          Gh ^= qb0h & pg;
-        }
-        Gl ^= W1l & gqm;
-        Gh ^= W1h & gqm;
-        Fl ^= qb1l & p1;
-        Fh ^= qb1h & p1;
-        const uint32_t fq2 = fqm ^ (u1 & p1);      // F_pq after V_C
-        const uint32_t z = (u0 & pm) ^ (am & fq2);  // bit q of M flips
-        Ml = Ml ^ (W1l & mqm) ^ (V1ml & fqm) ^ (qbl & z);
-        Mh = Mh ^ (W1h & mqm) ^ (V1mh & fqm) ^ (qbh & z);
-        gam2 |= (u0 & fqm & p1 & 1u) << j;
-        fbits |= (am & fq2 & 1u) << j;
+        uint32_t g2, f1;
+        h_row<decltype(general)::value>(K, Fl, Fh, Gl, Gh, Ml, Mh, g2, f1);
+        const uint32_t bj = 1u << j;
+        gam2 |= g2 & bj;
+        fbits |= f1 & bj;
         LF[j * 64u] = ((uint64_t)Fh << 32) | Fl;
         LG[j * 64u] = ((uint64_t)Gh << 32) | Gl;
         LM[j * 64u] = ((uint64_t)Mh << 32) | Ml;

@@ -1,0 +1,101 @@
+// One tableau row under the batch of right rules V_C that the Hadamard update
+// applies (Prop. H), shared by the evolution kernels that keep rows in LDS
+// and in registers.
+//
+// With d = t + u, V_0 = d & ~v, V_1 = d & v and q the lowest bit of V_0 if
+// V_0 != 0, else of V_1 (W = the rest of that set), V_C is, per row p:
+//   V_1 case, R[CX_{i,q}] for i in W:  G ^= W G_pq; F ^= e_q par(F & W); M ^= W M_pq.
+//   V_0 case, R[CX_{q,i}] for i in W, then R[CZ_{q,i}] for i in V_1:
+//     G ^= e_q par(G & W); F ^= W F_pq; M ^= e_q par((F & V_1) + (M & W)) + V_1 F_pq;
+//     gamma_p += 2 F_pq par(F & V_1)   (W and V_1 are disjoint, so F & V_1 is
+//     the same before and after F's update).
+//   Then R[S_q] if a: M ^= e_q F'_pq, gamma_p -= F'_pq, with F'_pq = F_pq
+//   plus, in the V_1 case, par(F & W).
+// One branch-free update serves both cases with per-term masks (a wave's
+// terms usually take both): P1 = par(F & X1) with X1 = W (V_1 case) or V_1
+// (V_0 case) is the parity of either case, and M's two column terms merge into
+// X1 times bit q of F (V_0 case) or of M (V_1 case).  Rows are 32-bit halves;
+// a mask is all ones or zero (a sign-extending one-bit field extract).
+#pragma once
+
+#include "device_common.hpp"
+
+namespace chsim {
+
+// All ones if bit b (< 32) of x is set, else zero.
+__device__ __forceinline__ uint32_t bit_mask(uint32_t x, uint32_t b) {
+  return (uint32_t)__builtin_amdgcn_sbfe((int)x, b, 1u);
+}
+
+// The per-term constants of V_C.
+struct HRowMasks {
+  uint32_t X1l, X1h;    // W (V_1 case) or V_1 (V_0 case)
+  uint32_t W1l, W1h;    // W in the V_1 case, else 0
+  uint32_t W0l, W0h;    // W in the V_0 case, else 0
+  uint32_t qb0l, qb0h;  // e_q in the V_0 case, else 0
+  uint32_t qb1l, qb1h;  // e_q in the V_1 case, else 0
+  uint32_t qbl, qbh;    // e_q
+  uint32_t qs;          // q mod 32
+  uint32_t u0;          // all ones in the V_0 case
+  uint32_t am;          // all ones if R[S_q] follows
+  bool hq;              // q >= 32
+};
+
+__device__ __forceinline__ HRowMasks h_row_masks(uint64_t W, uint64_t V1, uint32_t q, bool use0, uint32_t a) {
+  HRowMasks k;
+  const uint64_t u1m = use0 ? 0ull : ~0ull, u0m = ~u1m, qb = 1ull << q;
+  const uint64_t X1 = use0 ? V1 : W, W1 = W & u1m, W0 = W & u0m, qb0 = qb & u0m, qb1 = qb & u1m;
+  k.X1l = (uint32_t)X1;
+  k.X1h = (uint32_t)(X1 >> 32);
+  k.W1l = (uint32_t)W1;
+  k.W1h = (uint32_t)(W1 >> 32);
+  k.W0l = (uint32_t)W0;
+  k.W0h = (uint32_t)(W0 >> 32);
+  k.qb0l = (uint32_t)qb0;
+  k.qb0h = (uint32_t)(qb0 >> 32);
+  k.qb1l = (uint32_t)qb1;
+  k.qb1h = (uint32_t)(qb1 >> 32);
+  k.qbl = (uint32_t)qb;
+  k.qbh = (uint32_t)(qb >> 32);
+  k.qs = q & 31u;
+  k.hq = q >= 32u;
+  k.u0 = use0 ? ~0u : 0u;
+  k.am = a ? ~0u : 0u;
+  return k;
+}
+
+// Updates one row in place.  g2: all ones if gamma_p gains 2; f1: all ones if
+// gamma_p loses 1 (R[S_q]).  kGeneral = false drops the terms in W of the
+// V_0 case (valid when W is empty for every V_0-case term of the wave).
+template <bool kGeneral>
+__device__ __forceinline__ void h_row(const HRowMasks& k, uint32_t& Fl, uint32_t& Fh, uint32_t& Gl, uint32_t& Gh,
+                                      uint32_t& Ml, uint32_t& Mh, uint32_t& g2, uint32_t& f1) {
+  const uint32_t fx = k.hq ? Fh : Fl, gx = k.hq ? Gh : Gl, mx = k.hq ? Mh : Ml;
+  const uint32_t fqm = bit_mask(fx, k.qs);
+  const uint32_t gqm = bit_mask(gx, k.qs);
+  const uint32_t sel = bit_mask((k.u0 & fx) | (~k.u0 & mx), k.qs);  // F_pq (V_0) or M_pq (V_1)
+  // par(a) + par(b) = par(a ^ b): one population count per parity.
+  const uint32_t fx1 = (Fl & k.X1l) ^ (Fh & k.X1h);
+  const uint32_t p1 = bit_mask(__popc(fx1), 0u);
+  uint32_t pm = p1;
+  if constexpr (kGeneral) {
+    const uint32_t pg = bit_mask(__popc((Gl & k.W0l) ^ (Gh & k.W0h)), 0u);
+    pm = bit_mask(__popc(fx1 ^ (Ml & k.W0l) ^ (Mh & k.W0h)), 0u);
+    Fl ^= k.W0l & fqm;
+    Fh ^= k.W0h & fqm;
+    Gl ^= k.qb0l & pg;
+    Gh ^= k.qb0h & pg;
+  }
+  Gl ^= k.W1l & gqm;
+  Gh ^= k.W1h & gqm;
+  Fl ^= k.qb1l & p1;
+  Fh ^= k.qb1h & p1;
+  const uint32_t fq2 = fqm ^ (~k.u0 & p1);  // F_pq after V_C
+  f1 = k.am & fq2;
+  const uint32_t z = (k.u0 & pm) ^ f1;  // bit q of M flips
+  Ml ^= (k.X1l & sel) ^ (k.qbl & z);
+  Mh ^= (k.X1h & sel) ^ (k.qbh & z);
+  g2 = k.u0 & fqm & p1;
+}
+
+}  // namespace chsim
