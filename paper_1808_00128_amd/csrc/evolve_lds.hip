@@ -32,16 +32,6 @@ __device__ __forceinline__ uint32_t grp32(uint32_t x, uint32_t src, uint32_t tw)
   return (uint32_t)__builtin_amdgcn_ds_bpermute((int)((src * T + tw) << 2), (int)x);
 }
 
-// gamma (Z_4) of row j of a lane from its packed word.
-__device__ __forceinline__ uint32_t gam_get(uint32_t gw, uint32_t j) {
-  return ((gw >> j) & 1u) | (((gw >> (16u + j)) & 1u) << 1);
-}
-// gamma_j += a (mod 4).
-__device__ __forceinline__ uint32_t gam_add(uint32_t gw, uint32_t j, uint32_t a) {
-  const uint32_t lo = (gw >> j) & 1u, a0 = a & 1u, a1 = (a >> 1) & 1u;
-  return gw ^ (a0 << j) ^ ((a1 ^ (lo & a0)) << (16u + j));
-}
-
 template <int LPT, bool kFromZero>
 __global__ __launch_bounds__(256) void k_evolve_lds(EvolveJob J, const DGate* __restrict__ gates,
                                                     uint32_t n_gates, uint32_t* __restrict__ err) {
@@ -197,9 +187,7 @@ __global__ __launch_bounds__(256) void k_evolve_lds(EvolveJob J, const DGate* __
         for (uint32_t j = 0; j < nfull; ++j) row(j, std::true_type{});
         if (li < ntail) row(nfull, std::true_type{});
       }
-      gw ^= gam2 << 16;
-      // gamma -= 1 on the rows in fbits: low bit flips, high bit borrows.
-      gw ^= fbits ^ ((fbits & ~gw) << 16);
+      gw = gam_apply(gw, gam2, fbits);
       s = (y & ~qb) | ((uint64_t)cc << qh);
       v = (v & ~qb) | ((uint64_t)b << qh);
       w = (w + 4u * alpha + dw) & 7u;

@@ -27,6 +27,23 @@ __device__ __forceinline__ uint32_t bit_mask(uint32_t x, uint32_t b) {
   return (uint32_t)__builtin_amdgcn_sbfe((int)x, b, 1u);
 }
 
+// A lane's gamma values (Z_4) packed in one word: bit j is the low bit of
+// the lane's j-th row, bit 16 + j its high bit (at most 16 rows per lane).
+__device__ __forceinline__ uint32_t gam_get(uint32_t gw, uint32_t j) {
+  return ((gw >> j) & 1u) | (((gw >> (16u + j)) & 1u) << 1);
+}
+// gamma_j += a (mod 4).
+__device__ __forceinline__ uint32_t gam_add(uint32_t gw, uint32_t j, uint32_t a) {
+  const uint32_t lo = (gw >> j) & 1u, a0 = a & 1u, a1 = (a >> 1) & 1u;
+  return gw ^ (a0 << j) ^ ((a1 ^ (lo & a0)) << (16u + j));
+}
+// gamma += 2 on the rows in g2, then -= 1 on the rows in f1 (bit j = row j):
+// the low bit flips, the high bit borrows.
+__device__ __forceinline__ uint32_t gam_apply(uint32_t gw, uint32_t g2, uint32_t f1) {
+  gw ^= g2 << 16;
+  return gw ^ f1 ^ ((f1 & ~gw) << 16);
+}
+
 // The per-term constants of V_C.
 struct HRowMasks {
   uint32_t X1l, X1h;    // W (V_1 case) or V_1 (V_0 case)
