@@ -510,6 +510,34 @@ def test_inner_single_term_values(B, n):
     np.testing.assert_allclose(eta, eta_ref, rtol=1e-13, atol=0)
 
 
+@pytest.mark.parametrize("k", [0, 1, 30, 31, 32, 33, 39])
+def test_inner_widths_at_the_word_boundary(B, k):
+    """Every term with |v| = k (H on k qubits, then diagonal Cliffords and
+    phase slots, which leave v alone), n = 40: the Z_2 form has k + 1
+    variables, so k = 31 is the widest form on 32-bit words and k = 32 the
+    narrowest on 64-bit words."""
+    n = 40
+    rng = np.random.default_rng(950 + k)
+    gates = [(W.OP_H, q, 0) for q in rng.choice(n, size=k, replace=False).tolist()]
+    body = W.random_clifford_gates(n, 6 * n, rng, ops=(W.OP_S, W.OP_CZ))
+    pos = set(rng.choice(len(body), size=5, replace=False).tolist())
+    for i, g in enumerate(body):
+        gates.append(g)
+        if i in pos:
+            gates.append((W.OP_SLOT, int(rng.integers(n)), 0, float(rng.uniform(0, 2 * np.pi))))
+    circ = W.from_list(n, gates)
+    spec = dict(circuit=circ, chi=96, mode="sparsify", seed=950 + k)
+    say(f"inner width |v|={k} n={n}")
+    ctx = gpu_ctx(B, spec)
+    T = O.Terms(circ, 96, O.SPARSIFY, seed=950 + k)
+    assert all(bin(int(T.term(a).export()["v"])).count("1") == k for a in range(0, 96, 17))
+    Aoff, Adiag = W.random_equatorial(n, 70, rng)
+    ov, eta, mean = ctx.inner_products(Aoff, Adiag)
+    ref, eta_ref = T.inner(Aoff, Adiag)
+    assert normwise(ov, ref) < TOL64
+    np.testing.assert_allclose(eta, eta_ref, rtol=1e-9, atol=1e-12 * eta_ref.max())
+
+
 def test_inner_rejects_full_v(B):
     """n = 64 with every qubit in v: no free index for the Z_2 lift."""
     n = 64
