@@ -86,8 +86,8 @@ __global__ __launch_bounds__(256) void k_evolve_lds(EvolveJob J, const DGate* __
     LM[j * 64u] = m;
     gw |= ((ga & 1u) << j) | (((ga >> 1) & 1u) << (16u + j));
   }
-  uint64_t v = kFromZero ? 0ull : J.src.v[sa];
-  uint64_t s = kFromZero ? 0ull : J.src.s[sa];
+  const uint64_t v0 = kFromZero ? 0ull : J.src.v[sa], s0 = kFromZero ? 0ull : J.src.s[sa];
+  uint32_t vl = (uint32_t)v0, vh = (uint32_t)(v0 >> 32), sl = (uint32_t)s0, sh = (uint32_t)(s0 >> 32);
   uint32_t w = kFromZero ? 0u : (uint32_t)J.src.omega[sa];
   uint32_t e = 0u;
 
@@ -114,30 +114,38 @@ __global__ __launch_bounds__(256) void k_evolve_lds(EvolveJob J, const DGate* __
     if (op == OP_H) {
       if (!on) continue;
       // Hadamard on qubit q (the gate's p): Eqs. (H2), (H4), the t = u case,
-      // Prop. H with V_C applied to the lane's rows.
+      // Prop. H with V_C applied to the lane's rows.  On 32-bit halves, and
+      // branch-free over the two outcomes of (H4): a term with t = u gets
+      // e_q = 0 and no R[S_q], which makes V_C the identity on its rows.
       const uint64_t Fp = RF[q * T], Gp = RG[q * T], Mp = RM[q * T];
       const uint32_t gp = gam_get(grp32<T>(gw, lq, tw), kq);
-      const uint64_t nv = ~v;
-      const uint64_t t = s ^ (Gp & v);
-      const uint64_t u = s ^ (Fp & nv) ^ (Mp & v);
-      const uint32_t alpha = par64(Gp & nv & s);
-      const uint32_t beta = par64(Mp & nv & s) ^ par64(Fp & v & (Mp ^ s));
-      const uint32_t delta = (gp + 2u * (alpha + beta)) & 3u;
-      if (t == u) {
-        // omega' = 2^{-1/2} (-1)^alpha (1 + i^delta), delta odd.
-        if (!(delta & 1u)) e = 1u;
-        w = (w + 4u * alpha + (delta == 1u ? 1u : 7u)) & 7u;
-        s = t;
-        continue;
-      }
-      const uint64_t d = t ^ u, V0 = d & nv, V1 = d & v;
-      const bool use0 = V0 != 0ull;
-      const uint32_t qh = (uint32_t)__builtin_ctzll(use0 ? V0 : V1);
-      const uint64_t qb = 1ull << qh;
-      const uint64_t W = (use0 ? V0 : V1) & ~qb;
-      const uint32_t tq = (uint32_t)((t >> qh) & 1ull);
-      const uint64_t y = tq ? (u ^ qb) : t;  // y and z differ only in bit qh; y_qh = t_qh
-      const uint32_t vq = (uint32_t)((v >> qh) & 1ull);
+      const uint32_t Fl = (uint32_t)Fp, Fh = (uint32_t)(Fp >> 32), Gl = (uint32_t)Gp, Gh = (uint32_t)(Gp >> 32);
+      const uint32_t Ml = (uint32_t)Mp, Mh = (uint32_t)(Mp >> 32);
+      // t = s + G_q v, u = s + F_q ~v + M_q v: d = t + u is F_q on ~v (V_0)
+      // and G_q + M_q on v (V_1).
+      const uint32_t GMl = Gl ^ Ml, GMh = Gh ^ Mh;
+      const uint32_t V0l = Fl & ~vl, V0h = Fh & ~vh, V1l = GMl & vl, V1h = GMh & vh;
+      const uint32_t tl = sl ^ (Gl & vl), th = sh ^ (Gh & vh);
+      // alpha = G_q ~v s; alpha + beta = (G_q + M_q) ~v s + F_q v (M_q + s)
+      // (mod 2), each one population count of the halves' XOR.
+      const uint32_t alpha = (uint32_t)__popc((Gl & ~vl & sl) ^ (Gh & ~vh & sh)) & 1u;
+      const uint32_t ab = (uint32_t)__popc((GMl & ~vl & sl) ^ (GMh & ~vh & sh) ^ (Fl & vl & (Ml ^ sl)) ^
+                                           (Fh & vh & (Mh ^ sh))) & 1u;
+      const uint32_t delta = (gp + 2u * ab) & 3u;
+      const uint32_t dl = V0l | V1l, dh = V0h | V1h;
+      const bool same = (dl | dh) == 0u;  // t = u
+      const bool use0 = (V0l | V0h) != 0u;
+      const uint32_t Xl = use0 ? V0l : V1l, Xh = use0 ? V0h : V1h;
+      // q = lowest bit of X (ffbl of zero is all ones, so a zero low half
+      // defers to the high one; t = u leaves q = 31, masked below).
+      const uint32_t qh = Xl ? (uint32_t)__builtin_ctz(Xl) : 32u + (uint32_t)__builtin_ctz(Xh | 0x80000000u);
+      const uint32_t qs = qh & 31u;
+      const bool hq = qh >= 32u;
+      const uint32_t qm = same ? 0u : (1u << qs);  // e_q, zero when t = u
+      const uint32_t qbl = hq ? 0u : qm, qbh = hq ? qm : 0u;
+      const uint32_t Wl = Xl & ~qbl, Wh = Xh & ~qbh;
+      const uint32_t tq = ((hq ? th : tl) >> qs) & 1u;
+      const uint32_t vq = ((hq ? vh : vl) >> qs) & 1u;
       // H^{v_q}(|y_q> + i^delta |1 - y_q>) = 2^{1/2} e^{i pi dw/4} S^a H^b |c>; for
       // y_q = 1 factor out i^delta and use |0> + i^{-delta} |1>.
       const uint32_t dp = tq ? ((4u - delta) & 3u) : delta;
@@ -154,13 +162,19 @@ __global__ __launch_bounds__(256) void k_evolve_lds(EvolveJob J, const DGate* __
         cc = (dp == 2u || dp == 1u) ? 1u : 0u;
         dw = ph + (dp == 1u ? 1u : (dp == 3u ? 7u : 0u));
       }
+      if (same) {
+        // omega' = 2^{-1/2} (-1)^alpha (1 + i^delta), delta odd; s' = t.
+        if (!(delta & 1u)) e = 1u;
+        a = 0u;
+        dw = delta == 1u ? 1u : 7u;
+      }
       // V_C on the lane's rows (hrow.hpp); gamma's changes are collected as
       // bit j of gam2 (+2) and fbits (-1) and applied after the loop.
-      const HRowMasks K = h_row_masks(W, V1, qh, use0, a);
+      const HRowMasks K = h_row_masks32(Wl, Wh, V1l, V1h, qbl, qbh, qs, hq, use0, a);
       // When no term of the wave in the V_0 case has W != 0 (|v| close to n
       // leaves V_0 with at most one bit), the W terms of that case vanish for
       // every term (wave-uniform test).
-      const bool w_empty = __ballot(use0 && W != 0ull) == 0ull;
+      const bool w_empty = __ballot(use0 && (Wl | Wh) != 0u) == 0ull;
       uint32_t gam2 = 0u, fbits = 0u;
       auto row = [&](uint32_t j, auto general) {
         const uint64_t F = LF[j * 64u], G = LG[j * 64u], M = LM[j * 64u];
@@ -178,7 +192,9 @@ __global__ __launch_bounds__(256) void k_evolve_lds(EvolveJob J, const DGate* __
       };
       // Rows j < n / LPT exist in every lane (no per-lane bound in the loop);
       // row n / LPT only in lanes li < n % LPT.
-      if (w_empty) {
+      if (__ballot(!same) == 0ull) {
+        // t = u for every term of the wave: no row changes.
+      } else if (w_empty) {
 #pragma unroll 2
         for (uint32_t j = 0; j < nfull; ++j) row(j, std::false_type{});
         if (li < ntail) row(nfull, std::false_type{});
@@ -188,8 +204,13 @@ __global__ __launch_bounds__(256) void k_evolve_lds(EvolveJob J, const DGate* __
         if (li < ntail) row(nfull, std::true_type{});
       }
       gw = gam_apply(gw, gam2, fbits);
-      s = (y & ~qb) | ((uint64_t)cc << qh);
-      v = (v & ~qb) | ((uint64_t)b << qh);
+      // s' = y with bit q set to c, where y = t, or u + e_q when t_q = 1 (so
+      // y agrees with t + t_q d off bit q); v' = v with bit q set to b.
+      const uint32_t tqm = tq ? ~0u : 0u, ccm = cc ? ~0u : 0u, bm = b ? ~0u : 0u;
+      sl = ((tl ^ (tqm & dl)) & ~qbl) | (ccm & qbl);
+      sh = ((th ^ (tqm & dh)) & ~qbh) | (ccm & qbh);
+      vl = (vl & ~qbl) | (bm & qbl);
+      vh = (vh & ~qbh) | (bm & qbh);
       w = (w + 4u * alpha + dw) & 7u;
       continue;
     }
@@ -235,8 +256,8 @@ __global__ __launch_bounds__(256) void k_evolve_lds(EvolveJob J, const DGate* __
       J.dst.gamma[off] = (uint8_t)gam_get(gw, j);
     }
     if (li == 0) {
-      J.dst.v[item] = v;
-      J.dst.s[item] = s;
+      J.dst.v[item] = ((uint64_t)vh << 32) | vl;
+      J.dst.s[item] = ((uint64_t)sh << 32) | sl;
       J.dst.omega[item] = (uint8_t)w;
       if (e) atomicOr(err, 1u);
     }

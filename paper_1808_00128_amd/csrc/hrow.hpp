@@ -81,6 +81,32 @@ __device__ __forceinline__ HRowMasks h_row_masks(uint64_t W, uint64_t V1, uint32
   return k;
 }
 
+// The same from 32-bit halves: W and V_1, e_q (zero for a term that takes
+// no V_C) and its position (qs, hq).
+__device__ __forceinline__ HRowMasks h_row_masks32(uint32_t Wl, uint32_t Wh, uint32_t V1l, uint32_t V1h,
+                                                   uint32_t qbl, uint32_t qbh, uint32_t qs, bool hq, bool use0,
+                                                   uint32_t a) {
+  HRowMasks k;
+  const uint32_t u0 = use0 ? ~0u : 0u, u1 = ~u0;
+  k.X1l = use0 ? V1l : Wl;
+  k.X1h = use0 ? V1h : Wh;
+  k.W1l = Wl & u1;
+  k.W1h = Wh & u1;
+  k.W0l = Wl & u0;
+  k.W0h = Wh & u0;
+  k.qb0l = qbl & u0;
+  k.qb0h = qbh & u0;
+  k.qb1l = qbl & u1;
+  k.qb1h = qbh & u1;
+  k.qbl = qbl;
+  k.qbh = qbh;
+  k.qs = qs;
+  k.hq = hq;
+  k.u0 = u0;
+  k.am = a ? ~0u : 0u;
+  return k;
+}
+
 // Updates one row in place.  g2: all ones if gamma_p gains 2; f1: all ones if
 // gamma_p loses 1 (R[S_q]).  kGeneral = false drops the terms in W of the
 // V_0 case (valid when W is empty for every V_0-case term of the wave).
