@@ -128,10 +128,11 @@ KERNEL_SOURCES = {
     "k_evolve": ["evolve_kernel.hpp", "evolve.hip", "evolve_l4.hip", "evolve_l8.hip",
                  "evolve_wide.hip", "evolve_w64.hip", "prefix.hip", "device_common.hpp", "internal.hpp",
                  "api.hip"],
-    "k_evolve_lds": ["evolve_lds.hip", "evolve_w64.hip", "evolve.hip", "prefix.hip", "device_common.hpp",
-                     "internal.hpp", "api.hip"],
+    "k_evolve_lds": ["evolve_lds.hip", "hrow.hpp", "evolve_w64.hip", "evolve.hip", "prefix.hip",
+                     "device_common.hpp", "internal.hpp", "api.hip"],
     "k_amp<float>": ["amplitude.hip", "device_common.hpp", "internal.hpp", "api.hip"],
     "k_inner_pairs": ["inner.hip", "device_common.hpp", "internal.hpp", "api.hip"],
+    "k_inner_ch_pairs": ["inner_ch.hip", "device_common.hpp", "internal.hpp", "api.hip"],
 }
 
 
@@ -243,7 +244,7 @@ def bench_inner_ch(torch, B, W, L=256):
             "mean_v_weight_bra": mean_popcount(vb), "mean_v_weight_ket": mean_popcount(vk),
             "roofline": roof("alu", achieved, INT32_PEAK_OPS / 1e12, "TOP/s (int32)", MEASURED.get("valu"),
                              kernel="k_chrec + k_inner_ch_pairs (one wave per pair, lane = row)",
-                             ops_per_pair=ops_pair,
+                             traffic=counter_traffic("k_inner_ch_pairs"), ops_per_pair=ops_pair,
                              count="2 (2 n^2 + 3 (|v| + 1)^2) int32 ops per pair (64-bit word operations x 2)")}
 
 
