@@ -184,8 +184,8 @@ __global__ __launch_bounds__(256) void k_evolve_lds(EvolveJob J, const DGate* __
         uint32_t g2, f1;
         h_row<decltype(general)::value>(K, Fl, Fh, Gl, Gh, Ml, Mh, g2, f1);
         const uint32_t bj = 1u << j;
-        gam2 |= g2 & bj;
-        fbits |= f1 & bj;
+        gam2 = bop3<kAndOr>(g2, bj, gam2);
+        fbits = bop3<kAndOr>(f1, bj, fbits);
         LF[j * 64u] = ((uint64_t)Fh << 32) | Fl;
         LG[j * 64u] = ((uint64_t)Gh << 32) | Gl;
         LM[j * 64u] = ((uint64_t)Mh << 32) | Ml;

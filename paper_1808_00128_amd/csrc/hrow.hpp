@@ -27,6 +27,22 @@ __device__ __forceinline__ uint32_t bit_mask(uint32_t x, uint32_t b) {
   return (uint32_t)__builtin_amdgcn_sbfe((int)x, b, 1u);
 }
 
+// Three-input bitwise operations by truth table (operands A, B, C; the table
+// is the function's value on A = 0xF0, B = 0xCC, C = 0xAA).  On gfx950 these
+// issue at twice the rate of selects, bit-field extracts and and-or, which
+// the compiler would otherwise pick for masks derived from booleans.
+enum : uint32_t {
+  kSel = 0xCA,     // A ? B : C (bitwise)
+  kAndXor = 0x6A,  // (A & B) ^ C
+  kAnd3 = 0x80,    // A & B & C
+  kAndOr = 0xEA,   // (A & B) | C
+  kNandXor = 0xA6  // (~A & B) ^ C
+};
+template <uint32_t TT>
+__device__ __forceinline__ uint32_t bop3(uint32_t a, uint32_t b, uint32_t c) {
+  return __builtin_amdgcn_bitop3_b32(a, b, c, TT);
+}
+
 // A lane's gamma values (Z_4) packed in one word: bit j is the low bit of
 // the lane's j-th row, bit 16 + j its high bit (at most 16 rows per lane).
 __device__ __forceinline__ uint32_t gam_get(uint32_t gw, uint32_t j) {
@@ -55,7 +71,7 @@ struct HRowMasks {
   uint32_t qs;          // q mod 32
   uint32_t u0;          // all ones in the V_0 case
   uint32_t am;          // all ones if R[S_q] follows
-  bool hq;              // q >= 32
+  uint32_t hqm;         // all ones if q >= 32
 };
 
 __device__ __forceinline__ HRowMasks h_row_masks(uint64_t W, uint64_t V1, uint32_t q, bool use0, uint32_t a) {
@@ -75,7 +91,7 @@ __device__ __forceinline__ HRowMasks h_row_masks(uint64_t W, uint64_t V1, uint32
   k.qbl = (uint32_t)qb;
   k.qbh = (uint32_t)(qb >> 32);
   k.qs = q & 31u;
-  k.hq = q >= 32u;
+  k.hqm = q >= 32u ? ~0u : 0u;
   k.u0 = use0 ? ~0u : 0u;
   k.am = a ? ~0u : 0u;
   return k;
@@ -101,7 +117,7 @@ __device__ __forceinline__ HRowMasks h_row_masks32(uint32_t Wl, uint32_t Wh, uin
   k.qbl = qbl;
   k.qbh = qbh;
   k.qs = qs;
-  k.hq = hq;
+  k.hqm = hq ? ~0u : 0u;
   k.u0 = u0;
   k.am = a ? ~0u : 0u;
   return k;
@@ -113,32 +129,33 @@ __device__ __forceinline__ HRowMasks h_row_masks32(uint32_t Wl, uint32_t Wh, uin
 template <bool kGeneral>
 __device__ __forceinline__ void h_row(const HRowMasks& k, uint32_t& Fl, uint32_t& Fh, uint32_t& Gl, uint32_t& Gh,
                                       uint32_t& Ml, uint32_t& Mh, uint32_t& g2, uint32_t& f1) {
-  const uint32_t fx = k.hq ? Fh : Fl, gx = k.hq ? Gh : Gl, mx = k.hq ? Mh : Ml;
+  // The halves holding bit q, then bit q of F, of G, and of F (V_0) or M (V_1).
+  const uint32_t fx = bop3<kSel>(k.hqm, Fh, Fl), gx = bop3<kSel>(k.hqm, Gh, Gl), mx = bop3<kSel>(k.hqm, Mh, Ml);
   const uint32_t fqm = bit_mask(fx, k.qs);
   const uint32_t gqm = bit_mask(gx, k.qs);
-  const uint32_t sel = bit_mask((k.u0 & fx) | (~k.u0 & mx), k.qs);  // F_pq (V_0) or M_pq (V_1)
+  const uint32_t sel = bit_mask(bop3<kSel>(k.u0, fx, mx), k.qs);
   // par(a) + par(b) = par(a ^ b): one population count per parity.
-  const uint32_t fx1 = (Fl & k.X1l) ^ (Fh & k.X1h);
+  const uint32_t fx1 = bop3<kAndXor>(Fl, k.X1l, Fh & k.X1h);
   const uint32_t p1 = bit_mask(__popc(fx1), 0u);
   uint32_t pm = p1;
   if constexpr (kGeneral) {
-    const uint32_t pg = bit_mask(__popc((Gl & k.W0l) ^ (Gh & k.W0h)), 0u);
-    pm = bit_mask(__popc(fx1 ^ (Ml & k.W0l) ^ (Mh & k.W0h)), 0u);
-    Fl ^= k.W0l & fqm;
-    Fh ^= k.W0h & fqm;
-    Gl ^= k.qb0l & pg;
-    Gh ^= k.qb0h & pg;
+    const uint32_t pg = bit_mask(__popc(bop3<kAndXor>(Gl, k.W0l, Gh & k.W0h)), 0u);
+    pm = bit_mask(__popc(fx1 ^ bop3<kAndXor>(Ml, k.W0l, Mh & k.W0h)), 0u);
+    Fl = bop3<kAndXor>(k.W0l, fqm, Fl);
+    Fh = bop3<kAndXor>(k.W0h, fqm, Fh);
+    Gl = bop3<kAndXor>(k.qb0l, pg, Gl);
+    Gh = bop3<kAndXor>(k.qb0h, pg, Gh);
   }
-  Gl ^= k.W1l & gqm;
-  Gh ^= k.W1h & gqm;
-  Fl ^= k.qb1l & p1;
-  Fh ^= k.qb1h & p1;
-  const uint32_t fq2 = fqm ^ (~k.u0 & p1);  // F_pq after V_C
+  Gl = bop3<kAndXor>(k.W1l, gqm, Gl);
+  Gh = bop3<kAndXor>(k.W1h, gqm, Gh);
+  Fl = bop3<kAndXor>(k.qb1l, p1, Fl);
+  Fh = bop3<kAndXor>(k.qb1h, p1, Fh);
+  const uint32_t fq2 = bop3<kNandXor>(k.u0, p1, fqm);  // F_pq after V_C
   f1 = k.am & fq2;
-  const uint32_t z = (k.u0 & pm) ^ f1;  // bit q of M flips
-  Ml ^= (k.X1l & sel) ^ (k.qbl & z);
-  Mh ^= (k.X1h & sel) ^ (k.qbh & z);
-  g2 = k.u0 & fqm & p1;
+  const uint32_t z = bop3<kAndXor>(k.u0, pm, f1);  // bit q of M flips
+  Ml = bop3<kAndXor>(k.qbl, z, bop3<kAndXor>(k.X1l, sel, Ml));
+  Mh = bop3<kAndXor>(k.qbh, z, bop3<kAndXor>(k.X1h, sel, Mh));
+  g2 = bop3<kAnd3>(k.u0, fqm, p1);
 }
 
 }  // namespace chsim
