@@ -284,25 +284,35 @@ __global__ __launch_bounds__(64 * kGWaves) void k_propose_gather(TermsView T, Me
     if (live[sb]) c[sb] = load_const(T, a);
   }
   // CP chains per pass: all their state words and rows are requested before
-  // any is combined (more loads in flight when the grid is small).
+  // any is combined (more loads in flight when the grid is small).  A chain
+  // whose flip bit equals the previous chain's (one bit per step shared by
+  // the chains) reuses the rows already loaded.
+  uint64_t Fr[CP][kGSub], Mr[CP][kGSub];
+  uint32_t gr[CP][kGSub], jprev[CP];
+#pragma unroll
+  for (int h = 0; h < CP; ++h) jprev[h] = ~0u;
   for (uint32_t c0 = wave; c0 < Mv.n_chain; c0 += (uint32_t)CP * kGWaves) {
-    uint64_t st[CP][kGSub], Fr[CP][kGSub], Mr[CP][kGSub];
-    uint32_t gr[CP][kGSub], cur[CP];
+    uint64_t st[CP][kGSub];
+    uint32_t cur[CP];
 #pragma unroll
     for (int h = 0; h < CP; ++h) {
       const bool on = c0 + (uint32_t)h * kGWaves < Mv.n_chain;  // wave-uniform
       const uint32_t ch = on ? c0 + (uint32_t)h * kGWaves : c0;
       const uint32_t j = uniform32(Mv.jstream[(uint64_t)ch * Mv.n_steps + step]) % n;
       cur[h] = uniform32(Mv.parity[ch]);
+      const bool rows = j != jprev[h];  // wave-uniform
+      jprev[h] = j;
 #pragma unroll
       for (uint32_t sb = 0; sb < kGSub; ++sb) {
         const uint64_t a = tile0 + sb * 64u + lane;
         const bool ld = on && live[sb];
         const uint64_t off = (uint64_t)j * chi + a;
         st[h][sb] = ld ? Mv.state[cur[h]][(uint64_t)ch * chi + a] : 0ull;
-        Fr[h][sb] = ld ? T.F[off] : 0ull;
-        Mr[h][sb] = ld ? T.M[off] : 0ull;
-        gr[h][sb] = ld ? (uint32_t)T.gamma[off] : 0u;
+        if (rows) {
+          Fr[h][sb] = live[sb] ? T.F[off] : 0ull;
+          Mr[h][sb] = live[sb] ? T.M[off] : 0ull;
+          gr[h][sb] = live[sb] ? (uint32_t)T.gamma[off] : 0u;
+        }
       }
     }
 #pragma unroll
