@@ -68,6 +68,31 @@ __device__ __forceinline__ double2 term_value(const TermAmpConst& c, uint64_t u,
 
 constexpr uint64_t kUMask = (1ull << 62) - 1ull;
 
+// A double moved between lanes by DPP (two 32-bit moves on the VALU).
+template <int kCtrl>
+__device__ __forceinline__ double dpp_f64(double x) {
+  const uint64_t b = (uint64_t)__double_as_longlong(x);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)b, kCtrl, 0xF, 0xF, true);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(b >> 32), kCtrl, 0xF, 0xF, true);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// Sum of x over the wave's 64 lanes, valid in lane 0, in a fixed order:
+// within quads (lane ^ 1, lane ^ 2) and rows of 16 (half-row and row
+// mirrors) by DPP moves, across the two rows of each half by one swizzle,
+// and the halves by a read of lane 32.
+__device__ __forceinline__ double wave_sum0(double x) {
+  x += dpp_f64<0xB1>(x);   // quad_perm [1, 0, 3, 2]
+  x += dpp_f64<0x4E>(x);   // quad_perm [2, 3, 0, 1]
+  x += dpp_f64<0x141>(x);  // row_half_mirror
+  x += dpp_f64<0x140>(x);  // row_mirror
+  x += __shfl_xor(x, 16);
+  const uint64_t b = (uint64_t)__double_as_longlong(x);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, 32);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), 32);
+  return x + __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
 // Sum of a double2 over the 256-thread block (fixed order); result in thread 0.
 __device__ __forceinline__ double2 block_sum(double2 v, double2* scratch) {
   for (int m = 32; m >= 1; m >>= 1) {
@@ -249,10 +274,8 @@ __global__ __launch_bounds__(kPThreads) void k_propose(TermsView T, MetroView Mv
       const uint32_t ch = cg + wave + kPWaves * (uint32_t)k;
       if (ch >= Mv.n_chain) continue;  // wave-uniform
       double re = accr[k], im = acci[k];
-      for (int o = 32; o >= 1; o >>= 1) {
-        re += __shfl_xor(re, o);
-        im += __shfl_xor(im, o);
-      }
+      re = wave_sum0(re);
+      im = wave_sum0(im);
       if (lane == 0) Mv.partial[(uint64_t)ch * Mv.n_tiles + blockIdx.x] = make_double2(re, im);
     }
   }
@@ -334,10 +357,8 @@ __global__ __launch_bounds__(64 * kGWaves) void k_propose_gather(TermsView T, Me
         re += val.x;
         im += val.y;
       }
-      for (int o = 32; o >= 1; o >>= 1) {
-        re += __shfl_xor(re, o);
-        im += __shfl_xor(im, o);
-      }
+      re = wave_sum0(re);
+      im = wave_sum0(im);
       if (lane == 0) Mv.partial[(uint64_t)ch * Mv.n_tiles + blockIdx.x] = make_double2(re, im);
     }
   }
