@@ -9,8 +9,16 @@ with the FP32 compensated sum.  Inputs are resident in HBM before the timed
 region.  value = chi * |x| / (seconds per step).
 
 Prints one JSON line.  Extra keys: per-phase times measured with HIP events
-on the library's stream, the roofline of the dominant kernel, the FP64 path,
-and the CPU oracle timed on a bounded sample of the same workload.
+on the library's stream, the roofline of the dominant kernel (against the
+chip's published peak and against the int32 issue, HBM copy and LDS read
+rates measured in the same run), the FP64 path, and the CPU oracle timed on
+a bounded sample of the same workload (all host threads, and one thread).
+Further sections (`--sections`): norm estimation with equatorial states,
+inner products with stabilizer states given as CH forms, Metropolis chains
+(plain and learned proposals on the n = 50 QAOA instance, and the matched
+total-variation comparison on its n = 12 twin), a batch of 64 uneven
+instances, and the hidden-shift circuit with CCZ gates (sparsification bound
+and chain-rule sampling of output bits).  Progress lines go to stderr.
 """
 import argparse
 import hashlib
