@@ -439,8 +439,8 @@ def bench_learned(torch, B, W, stats, steps=1000, n_chain=64, chi=1 << 20, eps=0
             if untrained["ess"] > 0 else None}
 
 
-def bench_matched_tv(torch, B, W, stats, n=12, triples=16, chi=1 << 16, n_chain=64, steps=3200,
-                     eps=0.1, pi_min=0.002, pi_max=0.5, target=0.10):
+def bench_matched_tv(torch, B, W, stats, n=12, triples=16, chi=1 << 16, n_chain=64, steps=12800,
+                     eps=0.1, pi_min=0.002, pi_max=0.5, target=0.05):
     """n = 12 twin of the QAOA workload (beta = pi/4, gamma = 0.35): steps and
     seconds until the pooled samples of 64 chains are within `target` total
     variation of the exact law (all 4096 amplitudes), plain vs learned proposal
@@ -467,7 +467,7 @@ def bench_matched_tv(torch, B, W, stats, n=12, triples=16, chi=1 << 16, n_chain=
     utr, uac, ufl, ums = run_learned(torch, ctx, unet, x0, streams, eps, pi_min, pi_max)
     unet.close()
     ctx.close()
-    checkpoints = [25, 50, 100, 200, 400, 800, 1600, 3200]
+    checkpoints = [25, 50, 100, 200, 400, 800, 1600, 3200, 6400, 12800]
 
     def curve(t):
         return {c: stats.total_variation(t[:, :c].ravel(), P) for c in checkpoints if c <= steps}
