@@ -140,7 +140,7 @@ struct Instance {
   // metropolis
   uint32_t n_chain = 0;
   DevBuf<uint64_t> mstate0, mstate1, mx, mtrace;
-  DevBuf<uint32_t> mparity, mj;
+  DevBuf<uint32_t> mparity, mpend, mj;
   DevBuf<double2> mamp, mpartial;
   DevBuf<double> mu;
   DevBuf<uint8_t> macc;
@@ -190,7 +190,7 @@ struct Instance {
     acrow.release(); acst.release();
     plan_slot.release(); plan_width.release(); plan_count.release();
     mstate0.release(); mstate1.release(); mx.release(); mtrace.release();
-    mparity.release(); mj.release(); mamp.release(); mpartial.release(); mu.release(); macc.release();
+    mparity.release(); mpend.release(); mj.release(); mamp.release(); mpartial.release(); mu.release(); macc.release();
     ly.release(); lmask.release(); logit_x.release(); logit_y.release(); lumix.release();
     lubits.release(); lj.release(); lflips.release();
   }
@@ -1424,6 +1424,7 @@ static MetroView metro_view(Instance& I) {
   m.state[0] = I.mstate0.p;
   m.state[1] = I.mstate1.p;
   m.parity = I.mparity.p;
+  m.pend = I.mpend.p;
   m.x = I.mx.p;
   m.amp = I.mamp.p;
   m.partial = I.mpartial.p;
@@ -1460,6 +1461,8 @@ chsim_status chsim_metropolis_init(chsim_ctx* ctx, uint32_t inst, uint32_t n_cha
   if (I.mstate0.ensure(cells) != hipSuccess || I.mstate1.ensure(cells) != hipSuccess)
     return fail(CHSIM_ENOMEM, "chain state (%zu words x 2) does not fit", cells);
   HIP_TRY(I.mparity.ensure(n_chain));
+  HIP_TRY(I.mpend.ensure(n_chain));
+  HIP_TRY(hipMemsetAsync(I.mpend.p, 0, n_chain * sizeof(uint32_t), s));
   HIP_TRY(I.mx.ensure(n_chain));
   HIP_TRY(I.mamp.ensure(n_chain));
   HIP_TRY(I.mpartial.ensure((size_t)n_chain * tiles));

@@ -71,6 +71,7 @@ struct MetroView {
   uint32_t n_tiles;       // term tiles of kMetroTile terms
   uint64_t* state[2];     // [n_chain][chi]: u | mu << 62
   uint32_t* parity;       // per chain: which state buffer is current
+  uint32_t* pend;         // per chain: accepted steps of the open window (bit w: step t0 + w)
   uint64_t* x;            // per chain
   double2* amp;           // per chain: <x|psi>
   double2* partial;       // [n_chain][n_tiles]
@@ -83,6 +84,8 @@ struct MetroView {
 };
 
 constexpr int kMetroTile = 256;
+// Steps per window of deferred chain-cache updates (single-flip chains).
+constexpr uint32_t kMetroWin = 4;
 constexpr int kAmpTile = 64;
 
 // ---- launchers (each returns the first HIP error) ----

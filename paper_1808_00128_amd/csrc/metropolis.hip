@@ -6,16 +6,15 @@
 // the two factors commute, so Q_x P_j = P_j Q_x).  A step proposes y = x ^ e_j:
 //   u' = u ^ F_j,  mu' = mu + gamma_j + 2 par(u' & M_j),
 // and <y|phi_alpha> follows from (u', mu') as in Eq. (amplitude1), O(1) words
-// per term and chain.  The proposal words are written to the chain's second
-// buffer; accepting the move flips which buffer is current, so no term data
-// is rewritten at accept time.
+// per term and chain.
 //
-// Kernels per step: (1) k_propose_gather (single flips: each chain gathers
-// its one row) or k_propose (flip masks: the tile's rows staged in LDS):
-// lanes over terms, waves over chains: propose, write the proposal word, and
-// reduce sum_alpha b_alpha <y|phi_alpha> over the 256-term tile in FP64; (2) one
-// workgroup per chain: add the tiles' partials in a fixed order,
-// r = |A(y)|^2 / |A(x)|^2 in FP64, accept iff U < r.
+// Kernels per step: (1) k_propose_gather (single flips; the cache is brought
+// up to date once per window of kMetroWin steps, in place) or k_propose (flip
+// masks: the tile's rows staged in LDS; the proposal words are written to the
+// chain's second buffer and accepting flips which buffer is current): lanes
+// over terms, reduce sum_alpha b_alpha <y|phi_alpha> over the 256-term tile in
+// FP64; (2) one workgroup per chain: add the tiles' partials in a fixed
+// order, r = |A(y)|^2 / |A(x)|^2 in FP64, accept iff U < r.
 #include "device_common.hpp"
 #include "internal.hpp"
 
@@ -24,46 +23,40 @@ namespace chsim {
 namespace {
 
 struct TermAmpConst {
-  uint64_t s, nv, vs;
+  uint64_t v, s;
   uint32_t w;
-  double w0r, w0i, w1r, w1i;
+  double w0r, w0i;  // b_alpha 2^{-|v|/2}
 };
 
 __device__ __forceinline__ TermAmpConst load_const(const TermsView& T, uint64_t a) {
   TermAmpConst c;
-  const uint64_t v = T.v[a], s = T.s[a];
-  const uint32_t n = T.n;
-  const uint64_t nmask = (n == 64) ? ~0ull : ((1ull << n) - 1ull);
-  c.s = s;
-  c.nv = ~v & nmask;
-  c.vs = v & s;
+  c.v = T.v[a];
+  c.s = T.s[a];
   c.w = T.omega[a];
   const double2 b = T.b[a];
-  const int vc = __popcll(v);
+  const int vc = __popcll(c.v);
   const double h = 0.70710678118654752440;
   const double mag = ldexp(1.0, -(vc >> 1)) * ((vc & 1) ? h : 1.0);
   c.w0r = b.x * mag;
   c.w0i = b.y * mag;
-  c.w1r = (c.w0r - c.w0i) * h;
-  c.w1i = (c.w0r + c.w0i) * h;
   return c;
 }
 
-// b <x|phi> from the cached (u, mu).
+// b <x|phi> from the cached (u, mu), without branches: the rotation by
+// e^{i pi k / 4} (an odd k first multiplies by e^{i pi / 4}, then i^{k >> 1}
+// swaps and negates), and zero when x is outside the term's support.
 __device__ __forceinline__ double2 term_value(const TermAmpConst& c, uint64_t u, uint32_t mu) {
-  if ((u ^ c.s) & c.nv) return make_double2(0.0, 0.0);
-  const uint32_t k = (c.w + 2u * mu + 4u * par64(u & c.vs)) & 7u;
-  double re = (k & 1u) ? c.w1r : c.w0r;
-  double im = (k & 1u) ? c.w1i : c.w0i;
+  // u and s have no bits at or above n, so outside supp(v) is ~v.
+  const bool off = ((u ^ c.s) & ~c.v) != 0ull;
+  const uint32_t k = (c.w + 2u * mu + 4u * __popcll(u & c.v & c.s)) & 7u;
+  const double h = 0.70710678118654752440;
+  const double a = (k & 1u) ? (c.w0r - c.w0i) * h : c.w0r;
+  const double b = (k & 1u) ? (c.w0r + c.w0i) * h : c.w0i;
   const uint32_t m = k >> 1;
-  if (m & 1u) {
-    const double t = re;
-    re = im;
-    im = t;
-  }
-  if ((m ^ (m >> 1)) & 1u) re = -re;
-  if (m & 2u) im = -im;
-  return make_double2(re, im);
+  double re = (m & 1u) ? b : a, im = (m & 1u) ? a : b;
+  re = __longlong_as_double(__double_as_longlong(re) ^ ((long long)((m ^ (m >> 1)) & 1u) << 63));
+  im = __longlong_as_double(__double_as_longlong(im) ^ ((long long)(m >> 1) << 63));
+  return make_double2(off ? 0.0 : re, off ? 0.0 : im);
 }
 
 constexpr uint64_t kUMask = (1ull << 62) - 1ull;
@@ -281,102 +274,181 @@ __global__ __launch_bounds__(kPThreads) void k_propose(TermsView T, MetroView Mv
   }
 }
 
-// Single-flip proposal step without LDS: lanes over terms, waves over
-// chains; each chain gathers the words of its flipped row F_j, M_j, gamma_j
-// straight from the term store (rows that several chains flip are served by
-// L2), so no barrier separates loading from computing and only the touched
-// rows are read.  Each lane adds its terms of the 256-term tile in the same
-// order, and the lane sums are reduced with the same butterfly, as k_propose.
+// Single-flip proposal step with deferred cache updates.  Lanes over terms
+// (each lane takes four terms of the 256-term tile), waves over chains.  A
+// chain's cached (u, mu) is brought up to date only once per window of
+// kMetroWin steps: step t of the window that starts at t0 reads the cache as
+// of t0, applies the flips the chain accepted at steps t0 .. t-1 (right
+// products by their P_j in step order: the same arithmetic as updating after
+// every accepted step), then the proposal's P_j.  The first step of the next
+// window (and a final pass without a proposal at the end of a call) writes
+// the brought-up-to-date cache back in place.  The tile's rows of chain 0's
+// flip bits at the pending steps are staged in LDS once and serve every
+// chain whose bit at that step is the same (every chain, when the chains
+// share the flip bit of a step); a chain with another bit reads its row from
+// the term store.  So per chain and step only the 8-byte cache word of each
+// term is read, and it is written once per window.
 constexpr uint32_t kGWaves = 4;
-constexpr uint32_t kGSub = kMetroTile / 64;  // 64-term sub-tiles per tile
+constexpr uint32_t kGSub = kMetroTile / 64;  // terms per lane
+constexpr uint32_t kModeWrite = 1u, kModePropose = 2u;
 
 template <int CP>
 __global__ __launch_bounds__(64 * kGWaves) void k_propose_gather(TermsView T, MetroView Mv,
-                                                                 uint32_t step) {
+                                                                 uint32_t step, uint32_t pbase,
+                                                                 uint32_t npend, uint32_t mode) {
+  // Slots 0 .. npend-1: rows of chain 0's bits at the pending steps; slot
+  // kMetroWin: the row of chain 0's proposal bit.
+  constexpr uint32_t kSlots = kMetroWin + 1;
+  __shared__ uint64_t sF[kSlots][kMetroTile], sM[kSlots][kMetroTile];
+  __shared__ uint8_t sG[kSlots][kMetroTile];
   const uint32_t lane = threadIdx.x & 63u, wave = uniform32(threadIdx.x >> 6);
-  const uint32_t n = T.n;
+  const uint32_t n = T.n, nc = Mv.n_chain;
   const uint64_t chi = T.chi;
   const uint64_t tile0 = (uint64_t)blockIdx.x * kMetroTile;
+  const bool full = tile0 + kMetroTile <= chi;  // block-uniform
+  const bool write = mode & kModeWrite, prop = mode & kModePropose;
+  // Term offsets within the tile, clamped to the last term in a partial tile:
+  // past chi a lane reads that term's words and contributes zero (its
+  // weight is zero) and writes nothing.
+  const uint32_t last = (uint32_t)(chi - 1ull - tile0);
+  uint32_t ao[kGSub];
+#pragma unroll
+  for (uint32_t sb = 0; sb < kGSub; ++sb) ao[sb] = min(sb * 64u + lane, last);
+  uint32_t Wj[kSlots];
+#pragma unroll
+  for (uint32_t s = 0; s < kSlots; ++s) {
+    Wj[s] = ~0u;
+    const bool use = s < kMetroWin ? s < npend : prop;
+    if (use) {
+      Wj[s] = uniform32(Mv.jstream[s < kMetroWin ? pbase + s : step]) % n;
+      const uint64_t off = (uint64_t)Wj[s] * chi + tile0 + min(threadIdx.x, last);
+      sF[s][threadIdx.x] = T.F[off];
+      sM[s][threadIdx.x] = T.M[off];
+      sG[s][threadIdx.x] = T.gamma[off];
+    }
+  }
+  __syncthreads();
   TermAmpConst c[kGSub];
-  bool live[kGSub];
 #pragma unroll
   for (uint32_t sb = 0; sb < kGSub; ++sb) {
-    const uint64_t a = tile0 + sb * 64u + lane;
-    live[sb] = a < chi;
-    c[sb] = TermAmpConst{};
-    if (live[sb]) c[sb] = load_const(T, a);
+    if (prop) c[sb] = load_const(T, tile0 + ao[sb]);
+    if (sb * 64u + lane > last) c[sb].w0r = c[sb].w0i = 0.0;
   }
-  // CP chains per pass: all their state words and rows are requested before
-  // any is combined (more loads in flight when the grid is small).  A chain
-  // whose flip bit equals the previous chain's (one bit per step shared by
-  // the chains) reuses the rows already loaded.
-  uint64_t Fr[CP][kGSub], Mr[CP][kGSub];
-  uint32_t gr[CP][kGSub], jprev[CP];
-#pragma unroll
-  for (int h = 0; h < CP; ++h) jprev[h] = ~0u;
-  for (uint32_t c0 = wave; c0 < Mv.n_chain; c0 += (uint32_t)CP * kGWaves) {
-    uint64_t st[CP][kGSub];
-    uint32_t cur[CP];
-#pragma unroll
-    for (int h = 0; h < CP; ++h) {
-      const bool on = c0 + (uint32_t)h * kGWaves < Mv.n_chain;  // wave-uniform
-      const uint32_t ch = on ? c0 + (uint32_t)h * kGWaves : c0;
-      const uint32_t j = uniform32(Mv.jstream[(uint64_t)ch * Mv.n_steps + step]) % n;
-      cur[h] = uniform32(Mv.parity[ch]);
-      const bool rows = j != jprev[h];  // wave-uniform
-      jprev[h] = j;
+  const uint32_t pmask = (1u << npend) - 1u;  // npend <= kMetroWin < 32
+  // Right product by P_j of step slot s for the lane's terms: the staged row
+  // when the chain's bit j is chain 0's, else the term store's.
+  auto flip = [&](uint64_t (&u)[kGSub], uint32_t (&mu)[kGSub], uint32_t s, uint32_t j) {
+    if (j == Wj[s]) {  // wave-uniform
 #pragma unroll
       for (uint32_t sb = 0; sb < kGSub; ++sb) {
-        const uint64_t a = tile0 + sb * 64u + lane;
-        const bool ld = on && live[sb];
-        const uint64_t off = (uint64_t)j * chi + a;
-        st[h][sb] = ld ? Mv.state[cur[h]][(uint64_t)ch * chi + a] : 0ull;
-        if (rows) {
-          Fr[h][sb] = live[sb] ? T.F[off] : 0ull;
-          Mr[h][sb] = live[sb] ? T.M[off] : 0ull;
-          gr[h][sb] = live[sb] ? (uint32_t)T.gamma[off] : 0u;
-        }
+        u[sb] ^= sF[s][sb * 64u + lane];
+        mu[sb] += (uint32_t)sG[s][sb * 64u + lane] + 2u * __popcll(u[sb] & sM[s][sb * 64u + lane]);
+      }
+    } else {
+      const uint64_t* F = T.F + ((uint64_t)j * chi + tile0);
+      const uint64_t* M = T.M + ((uint64_t)j * chi + tile0);
+      const uint8_t* g = T.gamma + ((uint64_t)j * chi + tile0);
+#pragma unroll
+      for (uint32_t sb = 0; sb < kGSub; ++sb) {
+        u[sb] ^= F[ao[sb]];
+        mu[sb] += (uint32_t)g[ao[sb]] + 2u * __popcll(u[sb] & M[ao[sb]]);
       }
     }
+  };
+  // The wave's chains are ch = wave + kGWaves i.  Their per-chain words (which
+  // cache buffer is current, the pending mask, the proposal bit and the
+  // pending steps' bits) are read for 64 chains at once, chain i % 64 in lane
+  // i % 64, and taken from there by lane reads, so that no wait for them
+  // also waits for the cache words in flight.
+  const uint32_t n_mine = nc > wave ? (nc - wave + kGWaves - 1u) / kGWaves : 0u;
+  uint32_t m_cur = 0u, m_pm = 0u, m_j = 0u, m_js[kMetroWin];
+  for (uint32_t i0 = 0; i0 < n_mine; i0 += 64u) {
+    {
+      const uint32_t i = i0 + lane;
+      const bool ok = i < n_mine;
+      const uint32_t ch = ok ? wave + kGWaves * i : wave;
+      const uint64_t jrow = (uint64_t)ch * Mv.n_steps;
+      m_cur = Mv.parity[ch];
+      m_pm = npend ? Mv.pend[ch] & pmask : 0u;
+      m_j = prop ? Mv.jstream[jrow + step] % n : 0u;
 #pragma unroll
-    for (int h = 0; h < CP; ++h) {
-      const uint32_t ch = c0 + (uint32_t)h * kGWaves;
-      if (ch >= Mv.n_chain) break;
-      double re = 0.0, im = 0.0;
+      for (uint32_t s = 0; s < kMetroWin; ++s) m_js[s] = s < npend ? Mv.jstream[jrow + pbase + s] % n : 0u;
+    }
+    const uint32_t i_end = min(n_mine - i0, 64u);
+    // CP chains per pass: all their cache words are requested before any is
+    // combined.
+    for (uint32_t k0 = 0; k0 < i_end; k0 += (uint32_t)CP) {
+      uint64_t st[CP][kGSub];
 #pragma unroll
-      for (uint32_t sb = 0; sb < kGSub; ++sb) {
-        if (!live[sb]) continue;
-        const uint64_t a = tile0 + sb * 64u + lane;
-        uint64_t u = st[h][sb] & kUMask;
-        uint32_t mu = (uint32_t)(st[h][sb] >> 62);
-        u ^= Fr[h][sb];
-        mu += gr[h][sb] + 2u * par64(u & Mr[h][sb]);
-        mu &= 3u;
-        Mv.state[cur[h] ^ 1u][(uint64_t)ch * chi + a] = u | ((uint64_t)mu << 62);
-        const double2 val = term_value(c[sb], u, mu);
-        re += val.x;
-        im += val.y;
+      for (int h = 0; h < CP; ++h) {
+        const uint32_t k = k0 + (uint32_t)h < i_end ? k0 + (uint32_t)h : k0;
+        const uint32_t ch = wave + kGWaves * (i0 + k);
+        const uint32_t cur = (uint32_t)__builtin_amdgcn_readlane((int)m_cur, (int)k);
+        const uint64_t* sp = Mv.state[cur & 1u] + ((uint64_t)ch * chi + tile0);
+#pragma unroll
+        for (uint32_t sb = 0; sb < kGSub; ++sb) st[h][sb] = sp[ao[sb]];
       }
-      re = wave_sum0(re);
-      im = wave_sum0(im);
-      if (lane == 0) Mv.partial[(uint64_t)ch * Mv.n_tiles + blockIdx.x] = make_double2(re, im);
+#pragma unroll
+      for (int h = 0; h < CP; ++h) {
+        const uint32_t k = k0 + (uint32_t)h;
+        if (k >= i_end) break;  // wave-uniform
+        const uint32_t ch = wave + kGWaves * (i0 + k);
+        uint64_t u[kGSub];
+        uint32_t mu[kGSub];
+#pragma unroll
+        for (uint32_t sb = 0; sb < kGSub; ++sb) {
+          u[sb] = st[h][sb] & kUMask;
+          mu[sb] = (uint32_t)(st[h][sb] >> 62);
+        }
+        const uint32_t pm = (uint32_t)__builtin_amdgcn_readlane((int)m_pm, (int)k);
+#pragma unroll
+        for (uint32_t s = 0; s < kMetroWin; ++s)
+          if ((pm >> s) & 1u) flip(u, mu, s, (uint32_t)__builtin_amdgcn_readlane((int)m_js[s], (int)k));
+        if (write) {
+          const uint32_t cur = (uint32_t)__builtin_amdgcn_readlane((int)m_cur, (int)k);
+          uint64_t* sp = Mv.state[cur & 1u] + ((uint64_t)ch * chi + tile0);
+          if (full) {
+#pragma unroll
+            for (uint32_t sb = 0; sb < kGSub; ++sb) sp[sb * 64u + lane] = u[sb] | ((uint64_t)(mu[sb] & 3u) << 62);
+          } else {
+#pragma unroll
+            for (uint32_t sb = 0; sb < kGSub; ++sb)
+              if (sb * 64u + lane <= last) sp[sb * 64u + lane] = u[sb] | ((uint64_t)(mu[sb] & 3u) << 62);
+          }
+        }
+        if (!prop) continue;
+        flip(u, mu, kMetroWin, (uint32_t)__builtin_amdgcn_readlane((int)m_j, (int)k));
+        double re = 0.0, im = 0.0;
+#pragma unroll
+        for (uint32_t sb = 0; sb < kGSub; ++sb) {
+          const double2 val = term_value(c[sb], u[sb], mu[sb] & 3u);
+          re += val.x;
+          im += val.y;
+        }
+        re = wave_sum0(re);
+        im = wave_sum0(im);
+        if (lane == 0) Mv.partial[(uint64_t)ch * Mv.n_tiles + blockIdx.x] = make_double2(re, im);
+      }
     }
   }
 }
 
-// Single flips gather their one row per chain; flip masks (several rows per
-// chain) read the tile's rows once through LDS.
-template <bool kSingle>
-hipError_t launch_propose_t(const TermsView& T, MetroView& Mv, const uint64_t* mask, uint32_t step,
-                            hipStream_t st) {
-  if (kSingle) {
-    // Small grids (fewer than 2048 tiles) take two chains per pass per wave.
-    if (Mv.n_tiles < 2048u)
-      hipLaunchKernelGGL(k_propose_gather<2>, dim3(Mv.n_tiles), dim3(64 * kGWaves), 0, st, T, Mv, step);
-    else
-      hipLaunchKernelGGL(k_propose_gather<1>, dim3(Mv.n_tiles), dim3(64 * kGWaves), 0, st, T, Mv, step);
-    return hipGetLastError();
-  }
+// Single flips gather rows per term (deferred cache updates); flip masks
+// (several rows per chain) read the tile's rows once through LDS.
+hipError_t launch_gather(const TermsView& T, MetroView& Mv, uint32_t step, uint32_t pbase,
+                         uint32_t npend, uint32_t mode, hipStream_t st) {
+  // Small grids (fewer than 2048 tiles) take two chains per pass per wave.
+  if (Mv.n_tiles < 2048u)
+    hipLaunchKernelGGL(k_propose_gather<2>, dim3(Mv.n_tiles), dim3(64 * kGWaves), 0, st, T, Mv,
+                       step, pbase, npend, mode);
+  else
+    hipLaunchKernelGGL(k_propose_gather<1>, dim3(Mv.n_tiles), dim3(64 * kGWaves), 0, st, T, Mv,
+                       step, pbase, npend, mode);
+  return hipGetLastError();
+}
+
+hipError_t launch_masks(const TermsView& T, MetroView& Mv, const uint64_t* mask, uint32_t step,
+                        hipStream_t st) {
   const size_t sm = (size_t)T.n * kSub * 17;
   if (sm > 64 * 1024) {
     const hipError_t e = hipFuncSetAttribute((const void*)k_propose<false>,
@@ -406,12 +478,16 @@ __global__ __launch_bounds__(256) void k_metro_accept(MetroView Mv, uint32_t ste
     const double U = Mv.ustream[idx];
     const uint32_t acc_ = (px > 0.0) && (r >= 1.0 || U < r);
     uint64_t x = Mv.x[ch];
+    // The step's bit in the chain's window of deferred cache updates.
+    const uint32_t w = step % kMetroWin;
+    uint32_t pend = w ? Mv.pend[ch] : 0u;
     if (acc_) {
       x ^= 1ull << (Mv.jstream[idx] % Mv.n_qubits);
       Mv.x[ch] = x;
       Mv.amp[ch] = ay;
-      Mv.parity[ch] ^= 1u;
+      pend |= 1u << w;
     }
+    Mv.pend[ch] = pend;
     if (Mv.trace) Mv.trace[idx] = x;
     if (Mv.accepted) Mv.accepted[idx] = (uint8_t)acc_;
   }
@@ -429,19 +505,30 @@ hipError_t launch_metro_init(const TermsView& T, MetroView& Mv, hipStream_t st) 
 }
 
 hipError_t launch_metro_steps(const TermsView& T, MetroView& Mv, uint32_t n_steps, hipStream_t st) {
+  if (n_steps == 0) return hipSuccess;
   for (uint32_t t = 0; t < n_steps; ++t) {
-    hipError_t e = launch_propose_t<true>(T, Mv, nullptr, t, st);
+    // Step t applies the accepted flips of its window's earlier steps; the
+    // first step of a window (t > 0) applies the whole previous window and
+    // writes the caches back.
+    const uint32_t w = t % kMetroWin;
+    const bool close = w == 0 && t > 0;
+    const uint32_t pbase = close ? t - kMetroWin : t - w, npend = close ? kMetroWin : w;
+    hipError_t e = launch_gather(T, Mv, t, pbase, npend,
+                                 kModePropose | (close ? kModeWrite : 0u), st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_metro_accept, dim3(Mv.n_chain), dim3(256), 0, st, Mv, t);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  return hipSuccess;
+  // The last window's accepted flips, so that every chain's current cache is
+  // up to date when the call returns.
+  const uint32_t t0 = (n_steps - 1u) / kMetroWin * kMetroWin;
+  return launch_gather(T, Mv, 0, t0, n_steps - t0, kModeWrite, st);
 }
 
 hipError_t launch_propose(const TermsView& T, MetroView& Mv, const uint64_t* mask, uint32_t step,
                           hipStream_t st) {
-  return launch_propose_t<false>(T, Mv, mask, step, st);
+  return launch_masks(T, Mv, mask, step, st);
 }
 
 }  // namespace chsim

@@ -626,11 +626,13 @@ def test_metropolis_trajectories(B, n, chi, mode, chains, steps):
     assert 0 < acc.mean() <= 1
 
 
-@pytest.mark.parametrize("chi", [1 << 19, (1 << 19) + 37])
-def test_metropolis_trajectories_full_grid(B, chi):
-    """At least 2048 tiles of 256 terms: the single-flip gather kernel that
-    the QAOA workload (chi = 2^20) runs, one chain per pass, against the
-    oracle chain step for step; chi = 2^19 + 37 ends in a partial tile."""
+@pytest.mark.parametrize("chi,shared", [(1 << 19, False), ((1 << 19) + 37, False),
+                                        ((1 << 19) + 37, True)])
+def test_metropolis_trajectories_full_grid(B, chi, shared):
+    """At least 2048 tiles of 256 terms: the single-flip gather kernel in the
+    launch shape the QAOA workload (chi = 2^20) runs, against the oracle chain
+    step for step; chi = 2^19 + 37 ends in a partial tile; shared: one flip
+    bit per step for every chain, as in that workload."""
     n, chains, steps = 10, 8, 30
     rng = np.random.default_rng(6100 + chi % 97)
     circ = W.random_circuit(n, 60, rng.uniform(0, 2 * np.pi, size=20), rng)
@@ -645,7 +647,7 @@ def test_metropolis_trajectories_full_grid(B, chi):
         if x not in x0 and abs(T.amplitudes(np.array([x], np.uint64))[0]) > 0:
             x0.append(x)
     x0 = np.array(x0, np.uint64)
-    j, u = W.metropolis_streams(n, chains, steps, rng)
+    j, u = W.metropolis_streams(n, chains, steps, rng, shared_j=shared)
     a0 = ctx.metropolis_init(x0)
     assert normwise(a0, T.amplitudes(x0)) < TOL64
     tr, acc, amp = ctx.metropolis_step(j, u)
@@ -658,6 +660,58 @@ def test_metropolis_trajectories_full_grid(B, chi):
     ctx.metropolis_init(x0)
     tr_g, acc_g, _ = ctx.metropolis_step(j, u, graph=True)
     assert np.array_equal(tr_g, otr) and np.array_equal(acc_g, oacc)
+
+
+@pytest.mark.parametrize("chi", [1 << 19, 4099])
+def test_metropolis_windows_across_calls(B, chi):
+    """Calls of 7, 1, 4, 13 and 3 steps (windows of deferred cache updates cut
+    at every call boundary and at every offset within a window), with chains
+    0-4 sharing each step's flip bit and chains 5-7 drawing their own (both
+    ways of reading a pending flip's rows in one launch), and 5 steps of the
+    learned-proposal entry point at eps = 1 (the same chain, so it must start
+    from brought-up-to-date caches) in between, against one oracle chain over
+    the concatenated streams."""
+    n, chains = 10, 8
+    calls = [7, 1, "learned", 4, 13, 3]
+    lsteps = 5
+    steps = sum(k for k in calls if k != "learned") + lsteps
+    rng = np.random.default_rng(6200 + chi % 89)
+    circ = W.random_circuit(n, 60, rng.uniform(0, 2 * np.pi, size=20), rng)
+    spec = dict(circuit=circ, chi=chi, mode="sparsify", seed=621)
+    say(f"metropolis windows across calls n={n} chi={chi} calls={calls}")
+    ctx = gpu_ctx(B, spec)
+    T = O.Terms(circ, chi, O.SPARSIFY, seed=621)
+    x0 = []
+    while len(x0) < chains:
+        a = int(rng.integers(chi))
+        x = T.term(a).sample(int(W.random_bitstrings(n, 1, rng)[0]))
+        if x not in x0 and abs(T.amplitudes(np.array([x], np.uint64))[0]) > 0:
+            x0.append(x)
+    x0 = np.array(x0, np.uint64)
+    j, u = W.metropolis_streams(n, chains, steps, rng, shared_j=True)
+    j[5:] = rng.integers(0, n, size=(3, steps), dtype=np.uint32)
+    net = B.MLP(ctx, n, 32, 64, W.mlp_init(n, 32))
+    ctx.metropolis_init(x0)
+    trs, accs = [], []
+    t = 0
+    for k in calls:
+        if k == "learned":
+            u_mix, jl, u_bits, ul = W.learned_streams(n, chains, lsteps, rng)
+            j[:, t:t + lsteps], u[:, t:t + lsteps] = jl, ul
+            tr, acc, fl, amp = ctx.metropolis_step_learned(net, u_mix, jl, u_bits, ul, 1.0, 0.01, 0.5)
+            assert np.all(fl == 1)
+            k = lsteps
+        else:
+            tr, acc, amp = ctx.metropolis_step(j[:, t:t + k], u[:, t:t + k], graph=(k == 4))
+        trs.append(tr)
+        accs.append(acc)
+        t += k
+    otr, oacc, oamp = T.metropolis(x0, j, u)
+    assert np.array_equal(np.concatenate(trs, axis=1), otr)
+    assert np.array_equal(np.concatenate(accs, axis=1), oacc)
+    assert normwise(amp, oamp) < 1e-10
+    assert 0 < oacc.mean() < 1
+    net.close()
 
 
 def test_metropolis_graph_replays_match_eager_and_oracle(B):
