@@ -418,9 +418,10 @@ __global__ __launch_bounds__(64 * kGWaves) void k_propose_gather(TermsView T, Me
         }
         if (!prop) continue;
         flip(u, mu, kMetroWin, (uint32_t)__builtin_amdgcn_readlane((int)m_j, (int)k));
-        double re = 0.0, im = 0.0;
+        double2 t0 = term_value(c[0], u[0], mu[0] & 3u);
+        double re = t0.x, im = t0.y;
 #pragma unroll
-        for (uint32_t sb = 0; sb < kGSub; ++sb) {
+        for (uint32_t sb = 1; sb < kGSub; ++sb) {
           const double2 val = term_value(c[sb], u[sb], mu[sb] & 3u);
           re += val.x;
           im += val.y;
@@ -437,13 +438,8 @@ __global__ __launch_bounds__(64 * kGWaves) void k_propose_gather(TermsView T, Me
 // (several rows per chain) read the tile's rows once through LDS.
 hipError_t launch_gather(const TermsView& T, MetroView& Mv, uint32_t step, uint32_t pbase,
                          uint32_t npend, uint32_t mode, hipStream_t st) {
-  // Small grids (fewer than 2048 tiles) take two chains per pass per wave.
-  if (Mv.n_tiles < 2048u)
-    hipLaunchKernelGGL(k_propose_gather<2>, dim3(Mv.n_tiles), dim3(64 * kGWaves), 0, st, T, Mv,
-                       step, pbase, npend, mode);
-  else
-    hipLaunchKernelGGL(k_propose_gather<1>, dim3(Mv.n_tiles), dim3(64 * kGWaves), 0, st, T, Mv,
-                       step, pbase, npend, mode);
+  hipLaunchKernelGGL(k_propose_gather<2>, dim3(Mv.n_tiles), dim3(64 * kGWaves), 0, st, T, Mv, step,
+                     pbase, npend, mode);
   return hipGetLastError();
 }
 
