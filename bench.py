@@ -353,6 +353,19 @@ def chain_step_bytes(chi, n, n_chain):
     return float(chi * (17 * n + 16 * n_chain + 33))
 
 
+# Steps per window of deferred chain-cache updates in the single-flip kernel.
+METRO_WINDOW = 4
+
+
+def own_chain_step_bytes(chi, n_chain, win=METRO_WINDOW):
+    """HBM bytes of one single-flip step as the kernel moves them (one flip bit
+    per step shared by the chains): each chain's cached word read (8 B) and
+    written once per window (8 / win B), the rows F_j, M_j, gamma_j (17 B) of
+    the proposal bit and of the window's pending steps ((win + 1) / 2 on
+    average), and the term's constants (33 B)."""
+    return float(chi * (8 * n_chain + 8 * n_chain / win + 17 * (1 + (win + 1) / 2) + 33))
+
+
 def survey_chain_step_bytes(chi, n_chain):
     """The hot-path table's per-step bytes for single flips with one j per step
     shared by all chains: 16 B of state read + write per chain, 17 B for row j
@@ -400,10 +413,17 @@ def bench_learned(torch, B, W, stats, steps=1000, n_chain=64, chi=1 << 20, eps=0
     plain["hip_graph"] = graph
     sbytes = survey_chain_step_bytes(chi, n_chain)
     achieved = sbytes * steps / (ms / 1e3) / 1e9
+    obytes = own_chain_step_bytes(chi, n_chain)
     plain["roofline"] = roof("hbm", achieved, HBM_PEAK_BPS / 1e9, "GB/s", MEASURED.get("hbm"),
-                             kernel="k_propose_gather (single flips, shared j) + k_metro_accept",
+                             kernel="k_propose_gather (single flips, shared j, cache writes deferred "
+                                    f"over windows of {METRO_WINDOW} steps) + k_metro_accept",
                              traffic=None, bytes_per_step=sbytes,
                              count="chi (16 chains + 17 + 33) B per step (state r/w, row j, constants)",
+                             bytes_per_step_own=obytes,
+                             own_count=f"chi (8 chains + 8 chains / {METRO_WINDOW} + 17 (1 + "
+                                       f"{(METRO_WINDOW + 1) / 2}) + 33) B per step (state read, "
+                                       "state written once per window, proposal and pending rows, constants)",
+                             frac_own_count=round(obytes * steps / (ms / 1e3) / HBM_PEAK_BPS, 4),
                              bytes_per_step_all_rows=chain_step_bytes(chi, n, n_chain))
     delta = max(1, int(round(plain["tau_int"])))
     progress("metropolis: training the proposal")
@@ -415,10 +435,15 @@ def bench_learned(torch, B, W, stats, steps=1000, n_chain=64, chi=1 << 20, eps=0
     learned = chain_report(stats, ltr, lac, lms, burn, lcost, lfl)
     lbytes = chain_step_bytes(chi, n, n_chain)
     lach = lbytes * steps / (lms / 1e3) / 1e9
+    lown = float(chi * (17 * n + 8 * n_chain * (1 + learned["acceptance"]) + 33))
     learned["roofline"] = roof("hbm", lach, HBM_PEAK_BPS / 1e9, "GB/s", MEASURED.get("hbm"),
-                               kernel="k_propose<masks> + k_mlp_fused (masks and network) + k_learned_accept",
+                               kernel="k_propose (flip masks) + k_mlp_fused (masks and network) + k_learned_accept",
                                traffic=None, bytes_per_step=lbytes,
-                               count="chi (17 n + 16 chains + 33) B per step (every row staged for the masks)")
+                               count="chi (17 n + 16 chains + 33) B per step (every row staged for the masks)",
+                               bytes_per_step_own=lown,
+                               own_count="chi (17 n + 8 chains (1 + acceptance) + 33) B per step (a chain's "
+                                         "cache word is written only after an accepted move)",
+                               frac_own_count=round(lown * steps / (lms / 1e3) / HBM_PEAK_BPS, 4))
     net.close()
     progress("metropolis: learned chains with the untrained network")
     unet = B.MLP(ctx, n, 256, max(1024, n_chain), W.mlp_init(n, 256))

@@ -139,8 +139,8 @@ struct Instance {
   uint32_t metro_steps = 0;
   // metropolis
   uint32_t n_chain = 0;
-  DevBuf<uint64_t> mstate0, mstate1, mx, mtrace;
-  DevBuf<uint32_t> mparity, mpend, mj;
+  DevBuf<uint64_t> mstate0, mpmask, mx, mtrace;
+  DevBuf<uint32_t> mpend, mj;
   DevBuf<double2> mamp, mpartial;
   DevBuf<double> mu;
   DevBuf<uint8_t> macc;
@@ -189,8 +189,8 @@ struct Instance {
     slots.release();
     acrow.release(); acst.release();
     plan_slot.release(); plan_width.release(); plan_count.release();
-    mstate0.release(); mstate1.release(); mx.release(); mtrace.release();
-    mparity.release(); mpend.release(); mj.release(); mamp.release(); mpartial.release(); mu.release(); macc.release();
+    mstate0.release(); mpmask.release(); mx.release(); mtrace.release();
+    mpend.release(); mj.release(); mamp.release(); mpartial.release(); mu.release(); macc.release();
     ly.release(); lmask.release(); logit_x.release(); logit_y.release(); lumix.release();
     lubits.release(); lj.release(); lflips.release();
   }
@@ -1421,10 +1421,9 @@ static MetroView metro_view(Instance& I) {
   MetroView m;
   m.n_chain = I.n_chain;
   m.n_tiles = (uint32_t)((I.chi + kMetroTile - 1) / kMetroTile);
-  m.state[0] = I.mstate0.p;
-  m.state[1] = I.mstate1.p;
-  m.parity = I.mparity.p;
+  m.state = I.mstate0.p;
   m.pend = I.mpend.p;
+  m.pmask = I.mpmask.p;
   m.x = I.mx.p;
   m.amp = I.mamp.p;
   m.partial = I.mpartial.p;
@@ -1458,11 +1457,12 @@ chsim_status chsim_metropolis_init(chsim_ctx* ctx, uint32_t inst, uint32_t n_cha
   I.n_chain = n_chain;
   const size_t cells = (size_t)n_chain * I.chi;
   const uint32_t tiles = (uint32_t)((I.chi + kMetroTile - 1) / kMetroTile);
-  if (I.mstate0.ensure(cells) != hipSuccess || I.mstate1.ensure(cells) != hipSuccess)
-    return fail(CHSIM_ENOMEM, "chain state (%zu words x 2) does not fit", cells);
-  HIP_TRY(I.mparity.ensure(n_chain));
+  if (I.mstate0.ensure(cells) != hipSuccess)
+    return fail(CHSIM_ENOMEM, "chain state (%zu words) does not fit", cells);
   HIP_TRY(I.mpend.ensure(n_chain));
+  HIP_TRY(I.mpmask.ensure(n_chain));
   HIP_TRY(hipMemsetAsync(I.mpend.p, 0, n_chain * sizeof(uint32_t), s));
+  HIP_TRY(hipMemsetAsync(I.mpmask.p, 0, n_chain * sizeof(uint64_t), s));
   HIP_TRY(I.mx.ensure(n_chain));
   HIP_TRY(I.mamp.ensure(n_chain));
   HIP_TRY(I.mpartial.ensure((size_t)n_chain * tiles));

@@ -69,9 +69,9 @@ struct TermsView {
 struct MetroView {
   uint32_t n_chain;
   uint32_t n_tiles;       // term tiles of kMetroTile terms
-  uint64_t* state[2];     // [n_chain][chi]: u | mu << 62
-  uint32_t* parity;       // per chain: which state buffer is current
+  uint64_t* state;        // [n_chain][chi]: u | mu << 62, brought up to date lazily
   uint32_t* pend;         // per chain: accepted steps of the open window (bit w: step t0 + w)
+  uint64_t* pmask;        // per chain: flip mask accepted at the previous flip-mask step, or 0
   uint64_t* x;            // per chain
   double2* amp;           // per chain: <x|psi>
   double2* partial;       // [n_chain][n_tiles]
@@ -275,7 +275,11 @@ hipError_t launch_inner_ch(const uint64_t* rec_k, const double2* b_k, uint64_t c
 hipError_t launch_metro_init(const TermsView& T, MetroView& Mv, hipStream_t st);
 hipError_t launch_metro_steps(const TermsView& T, MetroView& Mv, uint32_t n_steps, hipStream_t st);
 // One proposal step for every chain with flip masks mask[c] (0: no move).
-hipError_t launch_propose(const TermsView& T, MetroView& Mv, const uint64_t* mask, uint32_t step,
+// Flip-mask proposals (mask per chain; mode: kProposeApplyPending applies
+// each chain's pmask first and writes its cache back, kProposeMasks proposes
+// the masks).
+constexpr uint32_t kProposeApplyPending = 1u, kProposeMasks = 2u;
+hipError_t launch_propose(const TermsView& T, MetroView& Mv, const uint64_t* mask, uint32_t mode,
                           hipStream_t st);
 
 }  // namespace chsim

@@ -10,10 +10,9 @@
 //
 // Kernels per step: (1) k_propose_gather (single flips; the cache is brought
 // up to date once per window of kMetroWin steps, in place) or k_propose (flip
-// masks: the tile's rows staged in LDS; the proposal words are written to the
-// chain's second buffer and accepting flips which buffer is current): lanes
-// over terms, reduce sum_alpha b_alpha <y|phi_alpha> over the 256-term tile in
-// FP64; (2) one workgroup per chain: add the tiles' partials in a fixed
+// masks: the tile's rows staged in LDS; the cache is brought up to date with
+// an accepted mask at the next step, in place): lanes over terms, reduce
+// sum_alpha b_alpha <y|phi_alpha> over the 256-term tile in FP64; (2) one workgroup per chain: add the tiles' partials in a fixed
 // order, r = |A(y)|^2 / |A(x)|^2 in FP64, accept iff U < r.
 #include "device_common.hpp"
 #include "internal.hpp"
@@ -129,7 +128,7 @@ __global__ __launch_bounds__(256) void k_metro_init(TermsView T, MetroView Mv) {
         mu += T.gamma[(uint64_t)p * chi + a] + 2u * par64(u & T.M[(uint64_t)p * chi + a]);
       }
       mu &= 3u;
-      Mv.state[0][(uint64_t)ch * chi + a] = (u & kUMask) | ((uint64_t)mu << 62);
+      Mv.state[(uint64_t)ch * chi + a] = (u & kUMask) | ((uint64_t)mu << 62);
       val = term_value(c, u, mu);
     }
     const double2 tot = block_sum(val, scratch);
@@ -147,23 +146,22 @@ __global__ __launch_bounds__(256) void k_chain_amp(MetroView Mv) {
     acc.y += v.y;
   }
   const double2 tot = block_sum(acc, scratch);
-  if (threadIdx.x == 0) {
-    Mv.amp[ch] = tot;
-    Mv.parity[ch] = 0u;
-  }
+  if (threadIdx.x == 0) Mv.amp[ch] = tot;
 }
 
 
-// Proposal step y = x ^ m for every chain, per term: Q_y = Q_x prod_{j in m} P_j
-// (right products), the new cached (u, mu) into the other state buffer, and
+// Flip-mask proposal step y = x ^ m for every chain, per term: the chain's
+// cache is first brought up to date with the mask it accepted at the
+// previous step (pmask, when the mode says so; written back in place, so a
+// cache word is written only after an accepted move), then Q_y = Q_x
+// prod_{j in m} P_j (right products; the factors commute) and
 // sum_a b_a <y|phi_a> per chain over the block's 256 terms.  The block walks
 // its tile in sub-tiles of 64 terms: the rows F_p, M_p, gamma_p of the
-// sub-tile are staged in LDS once ([p][term], so a wave reading row j for its
-// 64 terms is conflict-free), and wave w of 8 takes the chains c = w,
-// w + 8, ...; a chain's mask is wave-uniform, so the loop over its set bits does not
-// diverge and each term's rows leave HBM once per step for all chains.  The
-// masks are an array (learned proposal) or the single flips e_{j % n} of the
-// chains' j stream at `step` (the paper's chain).
+// sub-tile are staged in LDS once ([p][term], so a wave reading row j for
+// its 64 terms is conflict-free), and wave w of 8 takes the chains c = w,
+// w + 8, ...; a chain's masks are wave-uniform, so the loops over their set
+// bits do not diverge and each term's rows leave HBM once per step for all
+// chains.
 constexpr uint32_t kSub = 64;
 constexpr int kCW = 8;           // chains per wave in one pass
 constexpr uint32_t kPWaves = 8;  // waves per block: kPWaves * kCW = 64 chains per pass
@@ -171,10 +169,9 @@ constexpr uint32_t kPThreads = 64 * kPWaves;
 constexpr int kStage = (int)((64 * kSub + kPThreads - 1) / kPThreads);  // staging loads per thread
 static_assert(kStage % 2 == 0, "staged in two halves");
 
-template <bool kSingle>
 __global__ __launch_bounds__(kPThreads) void k_propose(TermsView T, MetroView Mv,
                                                        const uint64_t* __restrict__ mask,
-                                                       uint32_t step) {
+                                                       uint32_t mode) {
   extern __shared__ __align__(16) uint8_t smem[];
   const uint32_t n = T.n;
   uint64_t* sF = reinterpret_cast<uint64_t*>(smem);  // [n][64]
@@ -182,20 +179,26 @@ __global__ __launch_bounds__(kPThreads) void k_propose(TermsView T, MetroView Mv
   uint8_t* sG = reinterpret_cast<uint8_t*>(sM + (size_t)n * kSub);  // [n][64]
   const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = uniform32(tid >> 6);
   const uint64_t chi = T.chi;
+  const bool pend = mode & kProposeApplyPending, prop = mode & kProposeMasks;
+  // Right product by P_j for every set bit j of mm.
+  auto apply = [&](uint64_t& u, uint32_t& mu, uint64_t mm) {
+    while (mm) {
+      const uint32_t j = (uint32_t)__builtin_ctzll(mm);
+      mm &= mm - 1ull;
+      u ^= sF[j * kSub + lane];
+      mu += (uint32_t)sG[j * kSub + lane] + 2u * par64(u & sM[j * kSub + lane]);
+    }
+  };
   for (uint32_t cg = 0; cg < Mv.n_chain; cg += kPWaves * kCW) {
     // This wave's chains in the pass: cg + wave + kPWaves k, k < kCW (wave-uniform).
-    uint64_t m[kCW];
-    uint32_t cur[kCW];
+    uint64_t m[kCW], pm[kCW];
     double accr[kCW], acci[kCW];
 #pragma unroll
     for (int k = 0; k < kCW; ++k) {
       const uint32_t ch = cg + wave + kPWaves * (uint32_t)k;
-      m[k] = 0ull;
-      if (ch < Mv.n_chain) {
-        if (kSingle) m[k] = 1ull << (uniform32(Mv.jstream[(uint64_t)ch * Mv.n_steps + step]) % n);
-        else m[k] = uniform64(mask[ch]);
-      }
-      cur[k] = ch < Mv.n_chain ? uniform32(Mv.parity[ch]) : 0u;
+      const bool on = ch < Mv.n_chain;
+      m[k] = on && prop ? uniform64(mask[ch]) : 0ull;
+      pm[k] = on && pend ? uniform64(Mv.pmask[ch]) : 0ull;
       accr[k] = 0.0;
       acci[k] = 0.0;
     }
@@ -231,32 +234,30 @@ __global__ __launch_bounds__(kPThreads) void k_propose(TermsView T, MetroView Mv
       }
       const uint64_t a = base + lane;
       const bool live = a < chi;
-      // Every state word of this wave's chains is requested before any is used.
+      // Every cache word of this wave's chains is requested before any is used.
       uint64_t st[kCW];
 #pragma unroll
       for (int k = 0; k < kCW; ++k) {
         const uint32_t ch = cg + wave + kPWaves * (uint32_t)k;
-        st[k] = (live && m[k] != 0ull) ? Mv.state[cur[k]][(uint64_t)ch * chi + a] : 0ull;
+        st[k] = (live && (m[k] | pm[k]) != 0ull) ? Mv.state[(uint64_t)ch * chi + a] : 0ull;
       }
       TermAmpConst c{};
-      if (live) c = load_const(T, a);
+      if (live && prop) c = load_const(T, a);
       __syncthreads();
 #pragma unroll
       for (int k = 0; k < kCW; ++k) {
-        if (m[k] == 0ull || !live) continue;  // y = x, no such chain, or past chi
+        if ((m[k] | pm[k]) == 0ull || !live) continue;  // nothing to do, no such chain, or past chi
         const uint32_t ch = cg + wave + kPWaves * (uint32_t)k;
         uint64_t u = st[k] & kUMask;
         uint32_t mu = (uint32_t)(st[k] >> 62);
-        uint64_t mm = m[k];
-        while (mm) {
-          const uint32_t j = (uint32_t)__builtin_ctzll(mm);
-          mm &= mm - 1ull;
-          u ^= sF[j * kSub + lane];
-          mu += (uint32_t)sG[j * kSub + lane] + 2u * par64(u & sM[j * kSub + lane]);
+        if (pm[k]) {
+          apply(u, mu, pm[k]);
+          mu &= 3u;
+          Mv.state[(uint64_t)ch * chi + a] = u | ((uint64_t)mu << 62);
         }
-        mu &= 3u;
-        Mv.state[cur[k] ^ 1u][(uint64_t)ch * chi + a] = u | ((uint64_t)mu << 62);
-        const double2 val = term_value(c, u, mu);
+        if (m[k] == 0ull) continue;  // y = x: no proposal
+        apply(u, mu, m[k]);
+        const double2 val = term_value(c, u, mu & 3u);
         accr[k] += val.x;
         acci[k] += val.y;
       }
@@ -265,7 +266,7 @@ __global__ __launch_bounds__(kPThreads) void k_propose(TermsView T, MetroView Mv
 #pragma unroll
     for (int k = 0; k < kCW; ++k) {
       const uint32_t ch = cg + wave + kPWaves * (uint32_t)k;
-      if (ch >= Mv.n_chain) continue;  // wave-uniform
+      if (ch >= Mv.n_chain || !prop) continue;  // wave-uniform
       double re = accr[k], im = acci[k];
       re = wave_sum0(re);
       im = wave_sum0(im);
@@ -355,20 +356,19 @@ __global__ __launch_bounds__(64 * kGWaves) void k_propose_gather(TermsView T, Me
       }
     }
   };
-  // The wave's chains are ch = wave + kGWaves i.  Their per-chain words (which
-  // cache buffer is current, the pending mask, the proposal bit and the
-  // pending steps' bits) are read for 64 chains at once, chain i % 64 in lane
-  // i % 64, and taken from there by lane reads, so that no wait for them
-  // also waits for the cache words in flight.
+  // The wave's chains are ch = wave + kGWaves i.  Their per-chain words (the
+  // pending mask, the proposal bit and the pending steps' bits) are read for
+  // 64 chains at once, chain i % 64 in lane i % 64, and taken from there by
+  // lane reads, so that no wait for them also waits for the cache words in
+  // flight.
   const uint32_t n_mine = nc > wave ? (nc - wave + kGWaves - 1u) / kGWaves : 0u;
-  uint32_t m_cur = 0u, m_pm = 0u, m_j = 0u, m_js[kMetroWin];
+  uint32_t m_pm = 0u, m_j = 0u, m_js[kMetroWin];
   for (uint32_t i0 = 0; i0 < n_mine; i0 += 64u) {
     {
       const uint32_t i = i0 + lane;
       const bool ok = i < n_mine;
       const uint32_t ch = ok ? wave + kGWaves * i : wave;
       const uint64_t jrow = (uint64_t)ch * Mv.n_steps;
-      m_cur = Mv.parity[ch];
       m_pm = npend ? Mv.pend[ch] & pmask : 0u;
       m_j = prop ? Mv.jstream[jrow + step] % n : 0u;
 #pragma unroll
@@ -383,8 +383,7 @@ __global__ __launch_bounds__(64 * kGWaves) void k_propose_gather(TermsView T, Me
       for (int h = 0; h < CP; ++h) {
         const uint32_t k = k0 + (uint32_t)h < i_end ? k0 + (uint32_t)h : k0;
         const uint32_t ch = wave + kGWaves * (i0 + k);
-        const uint32_t cur = (uint32_t)__builtin_amdgcn_readlane((int)m_cur, (int)k);
-        const uint64_t* sp = Mv.state[cur & 1u] + ((uint64_t)ch * chi + tile0);
+        const uint64_t* sp = Mv.state + ((uint64_t)ch * chi + tile0);
 #pragma unroll
         for (uint32_t sb = 0; sb < kGSub; ++sb) st[h][sb] = sp[ao[sb]];
       }
@@ -405,8 +404,7 @@ __global__ __launch_bounds__(64 * kGWaves) void k_propose_gather(TermsView T, Me
         for (uint32_t s = 0; s < kMetroWin; ++s)
           if ((pm >> s) & 1u) flip(u, mu, s, (uint32_t)__builtin_amdgcn_readlane((int)m_js[s], (int)k));
         if (write) {
-          const uint32_t cur = (uint32_t)__builtin_amdgcn_readlane((int)m_cur, (int)k);
-          uint64_t* sp = Mv.state[cur & 1u] + ((uint64_t)ch * chi + tile0);
+          uint64_t* sp = Mv.state + ((uint64_t)ch * chi + tile0);
           if (full) {
 #pragma unroll
             for (uint32_t sb = 0; sb < kGSub; ++sb) sp[sb * 64u + lane] = u[sb] | ((uint64_t)(mu[sb] & 3u) << 62);
@@ -443,15 +441,15 @@ hipError_t launch_gather(const TermsView& T, MetroView& Mv, uint32_t step, uint3
   return hipGetLastError();
 }
 
-hipError_t launch_masks(const TermsView& T, MetroView& Mv, const uint64_t* mask, uint32_t step,
+hipError_t launch_masks(const TermsView& T, MetroView& Mv, const uint64_t* mask, uint32_t mode,
                         hipStream_t st) {
   const size_t sm = (size_t)T.n * kSub * 17;
   if (sm > 64 * 1024) {
-    const hipError_t e = hipFuncSetAttribute((const void*)k_propose<false>,
+    const hipError_t e = hipFuncSetAttribute((const void*)k_propose,
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_propose<false>, dim3(Mv.n_tiles), dim3(kPThreads), sm, st, T, Mv, mask, step);
+  hipLaunchKernelGGL(k_propose, dim3(Mv.n_tiles), dim3(kPThreads), sm, st, T, Mv, mask, mode);
   return hipGetLastError();
 }
 
@@ -522,9 +520,9 @@ hipError_t launch_metro_steps(const TermsView& T, MetroView& Mv, uint32_t n_step
   return launch_gather(T, Mv, 0, t0, n_steps - t0, kModeWrite, st);
 }
 
-hipError_t launch_propose(const TermsView& T, MetroView& Mv, const uint64_t* mask, uint32_t step,
+hipError_t launch_propose(const TermsView& T, MetroView& Mv, const uint64_t* mask, uint32_t mode,
                           hipStream_t st) {
-  return launch_masks(T, Mv, mask, step, st);
+  return launch_masks(T, Mv, mask, mode, st);
 }
 
 }  // namespace chsim

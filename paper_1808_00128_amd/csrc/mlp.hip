@@ -664,9 +664,11 @@ __global__ __launch_bounds__(256) void k_learned_accept(MetroView Mv, LearnedVie
           Mv.x[ch] = Lv.y[ch];
           Lv.x[ch] = Lv.y[ch];
           Mv.amp[ch] = make_double2(yr, yi);
-          Mv.parity[ch] ^= 1u;
         }
       }
+      // The chain's cache is brought up to date with an accepted mask by the
+      // next proposal step (or the final pass of the call).
+      Mv.pmask[ch] = (acc && m != 0ull) ? m : 0ull;
       acc_s = acc && (m != 0ull);
       if (Mv.trace) Mv.trace[idx] = Mv.x[ch];
       if (Mv.accepted) Mv.accepted[idx] = (uint8_t)acc;
@@ -694,11 +696,14 @@ hipError_t launch_learned_steps(const TermsView& T, MetroView& Mv, LearnedView& 
       if ((e = hipGetLastError()) != hipSuccess) return e;
       if ((e = mlp_forward(d, Lv.y, Lv.n_chain, Lv.logit_y, st)) != hipSuccess) return e;
     }
-    if ((e = launch_propose(T, Mv, Lv.mask, 0, st)) != hipSuccess) return e;
+    const uint32_t mode = kProposeMasks | (t > 0 ? kProposeApplyPending : 0u);
+    if ((e = launch_propose(T, Mv, Lv.mask, mode, st)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_learned_accept, dim3(Mv.n_chain), dim3(256), 0, st, Mv, Lv, t);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  return hipSuccess;
+  // The last step's accepted masks, so that the caches are up to date when the
+  // call returns.
+  return n_steps ? launch_propose(T, Mv, Lv.mask, kProposeApplyPending, st) : hipSuccess;
 }
 
 }  // namespace chsim
