@@ -142,10 +142,22 @@ __global__ __launch_bounds__(64 * kCHWaves) void k_inner_ch_pairs(
     const uint32_t om_k = uniform32((uint32_t)rk[4u * n + 5u]);
     // Equations: lane j (j outside v_b): E_j = XOR of G rows p with F_b[p][j] = 1,
     // restricted to the unknowns v_k; rhs_j = s_b,j + par(x1 & colF_b,j).
+    // E_j restricted to v_k has bit i = par(column j of F_b & column i of G_k):
+    // with few equations, one ballot per equation over the lanes i; else
+    // lane j adds the G rows p its column selects.
     const bool eq = ((neq_mask >> lane) & 1ull) != 0ull;
     uint64_t E = 0;
-    for (uint32_t p = 0; p < n; ++p) E ^= rl64(Growk, p) & bitmask64(colFb, p);
-    E &= v_k;
+    if (5u * (uint32_t)__popcll(neq_mask) < 4u * n) {
+      const bool unk = ((v_k >> lane) & 1ull) != 0ull;
+      for (uint64_t em = neq_mask; em; em &= em - 1ull) {
+        const uint32_t j = (uint32_t)__builtin_ctzll(em);
+        const uint64_t Ej = ballot64(unk && par64(rl64(colFb, j) & colGk));
+        if (lane == j) E = Ej;
+      }
+    } else {
+      for (uint32_t p = 0; p < n; ++p) E ^= rl64(Growk, p) & bitmask64(colFb, p);
+      E &= v_k;
+    }
     uint32_t rhs = (uint32_t)((s_b >> lane) & 1ull) ^ par64(x1 & colFb);
     if (!eq) {
       E = 0;
