@@ -40,10 +40,12 @@ namespace {
 
 constexpr int kCHWaves = 4;
 
-__host__ __device__ constexpr uint32_t chrec_words(uint32_t n) { return 4u * n + 6u; }
+__host__ __device__ constexpr uint32_t chrec_words(uint32_t n) { return 6u * n + 6u; }
 
 // Record of one term: colG [0, n), rows of G [n, 2n), colF [2n, 3n), rows of
-// Bs [3n, 4n), then diag(B), glo, x1 = s G^T, s, v, omega.
+// Bs [3n, 4n), Bs colG_i [4n, 5n), Bu colG_i [5n, 6n) (Bu: the strictly
+// upper part of Bs, row q below bit q), then diag(B), glo, x1 = s G^T, s, v,
+// omega.
 __global__ __launch_bounds__(64 * kCHWaves) void k_chrec(TermsView T, uint64_t* __restrict__ rec) {
   const uint32_t lane = threadIdx.x & 63u;
   const uint64_t term = (uint64_t)blockIdx.x * kCHWaves + uniform32(threadIdx.x >> 6);
@@ -74,20 +76,30 @@ __global__ __launch_bounds__(64 * kCHWaves) void k_chrec(TermsView T, uint64_t* 
                                          (uint64_t)par64(F & v & s)) != 0ull);
   const uint64_t glo = ballot64(act && (g & 1u));
   const uint64_t x1 = ballot64(act && par64(G & s));
+  // The term's own part of t = Bs d and tu = Bu d for d = column i of G
+  // (lane i); a pair's directions are sums of such columns.
+  uint64_t W = 0, Wu = 0;
+  for (uint32_t q = 0; q < n; ++q) {
+    const uint64_t Bq = rl64(Bs, q) & bitmask64(colG, q);
+    W ^= Bq;
+    Wu ^= Bq & ((1ull << q) - 1ull);
+  }
   uint64_t* r = rec + term * chrec_words(n);
   if (act) {
     r[lane] = colG;
     r[n + lane] = G;
     r[2u * n + lane] = colF;
     r[3u * n + lane] = Bs;
+    r[4u * n + lane] = W;
+    r[5u * n + lane] = Wu;
   }
   if (lane == 0) {
-    r[4u * n] = diag;
-    r[4u * n + 1u] = glo;
-    r[4u * n + 2u] = x1;
-    r[4u * n + 3u] = s;
-    r[4u * n + 4u] = v;
-    r[4u * n + 5u] = T.omega[term];
+    r[6u * n] = diag;
+    r[6u * n + 1u] = glo;
+    r[6u * n + 2u] = x1;
+    r[6u * n + 3u] = s;
+    r[6u * n + 4u] = v;
+    r[6u * n + 5u] = T.omega[term];
   }
 }
 
@@ -125,10 +137,33 @@ __global__ __launch_bounds__(64 * kCHWaves) void k_inner_ch_pairs(
   const uint64_t* rb = rec_b + (uint64_t)l * R;
   const uint64_t colFb = act ? rb[2u * n + lane] : 0ull;
   const uint64_t Bsb = act ? rb[3u * n + lane] : 0ull;
-  const uint64_t diag_b = uniform64(rb[4u * n]), glo_b = uniform64(rb[4u * n + 1u]);
-  const uint64_t s_b = uniform64(rb[4u * n + 3u]), v_b = uniform64(rb[4u * n + 4u]);
-  const uint32_t om_b = uniform32((uint32_t)rb[4u * n + 5u]);
+  const uint64_t diag_b = uniform64(rb[6u * n]), glo_b = uniform64(rb[6u * n + 1u]);
+  const uint64_t s_b = uniform64(rb[6u * n + 3u]), v_b = uniform64(rb[6u * n + 4u]);
+  const uint32_t om_b = uniform32((uint32_t)rb[6u * n + 5u]);
   const uint64_t neq_mask = ~v_b & ((n == 64u) ? ~0ull : ((1ull << n) - 1ull));  // equations j outside v_b
+  // The bra's part of t = Bs d and tu = Bu d by nibbles of d: tables of the
+  // XOR of each subset of 4 consecutive rows of Bs_b (and of Bu_b), built once
+  // for the wave's bra state and read with a lane's own index (t_d = XOR over
+  // nibble groups g of tab[g][nibble g of d]).
+  __shared__ uint64_t tabs[kCHWaves][2][16][16];
+  uint64_t(*const tab)[16][16] = tabs[uniform32(threadIdx.x >> 6)];
+  const uint32_t ngrp = (n + 3u) / 4u;
+  for (uint32_t g = 0; g < ngrp; ++g) {
+    uint64_t acc = 0;
+    for (uint32_t b = 0; b < 4u; ++b) {
+      const uint32_t q = 4u * g + b;
+      if (q >= n) break;
+      const uint64_t R = rl64(Bsb, q);
+      const uint64_t val = lane < 16u ? R : (R & ((1ull << q) - 1ull));
+      if (((lane & 15u) >> b) & 1u) acc ^= val;
+    }
+    if (lane < 32u) tab[lane >> 4][g][lane & 15u] = acc;
+  }
+  auto lookup = [&](uint32_t which, uint64_t x) {
+    uint64_t r = 0;
+    for (uint32_t g = 0; g < ngrp; ++g) r ^= tab[which][g][(x >> (4u * g)) & 15u];
+    return r;
+  };
   double accr = 0.0, acci = 0.0;
   uint32_t bad = 0;
   for (uint64_t a = blockIdx.y; a < chi_k; a += groups) {
@@ -136,10 +171,11 @@ __global__ __launch_bounds__(64 * kCHWaves) void k_inner_ch_pairs(
     const uint64_t colGk = act ? rk[lane] : 0ull;
     const uint64_t Growk = act ? rk[n + lane] : 0ull;
     const uint64_t Bsk = act ? rk[3u * n + lane] : 0ull;
-    const uint64_t diag_k = uniform64(rk[4u * n]), glo_k = uniform64(rk[4u * n + 1u]);
-    const uint64_t x1 = uniform64(rk[4u * n + 2u]);
-    const uint64_t v_k = uniform64(rk[4u * n + 4u]);
-    const uint32_t om_k = uniform32((uint32_t)rk[4u * n + 5u]);
+    const uint64_t Wk = act ? rk[4u * n + lane] : 0ull, Wuk = act ? rk[5u * n + lane] : 0ull;
+    const uint64_t diag_k = uniform64(rk[6u * n]), glo_k = uniform64(rk[6u * n + 1u]);
+    const uint64_t x1 = uniform64(rk[6u * n + 2u]);
+    const uint64_t v_k = uniform64(rk[6u * n + 4u]);
+    const uint32_t om_k = uniform32((uint32_t)rk[6u * n + 5u]);
     // Equations: lane j (j outside v_b): E_j = XOR of G rows p with F_b[p][j] = 1,
     // restricted to the unknowns v_k; rhs_j = s_b,j + par(x1 & colF_b,j).
     // E_j restricted to v_k has bit i = par(column j of F_b & column i of G_k):
@@ -183,27 +219,30 @@ __global__ __launch_bounds__(64 * kCHWaves) void k_inner_ch_pairs(
     }
     if (ballot64(eq && E == 0ull && rhs != 0u)) continue;  // the supports do not meet
     // Free variables f (lanes) and their directions d_f in x-space; x0.
+    // Directions d_f of the free variables f (column f of G plus the pivot
+    // columns its equations bring in), with the ket's parts of Bs d_f and
+    // Bu d_f from the same columns' record words.
     const uint64_t Fr = v_k & ~pivmask;
-    uint64_t d = ((Fr >> lane) & 1ull) ? colGk : 0ull;
+    const bool fr = ((Fr >> lane) & 1ull) != 0ull;
+    uint64_t d = fr ? colGk : 0ull, tk = fr ? Wk : 0ull, tuk = fr ? Wuk : 0ull;
     uint64_t x0 = x1;
     for (uint64_t u = used; u; u &= u - 1ull) {
       const uint32_t j = (uint32_t)__builtin_ctzll(u);
       const uint64_t Ej = rl64(E, j);
       const uint32_t pv = rl32(pivvar, j);
-      const uint64_t cg = rl64(colGk, pv);
-      if (((Fr >> lane) & 1ull) && ((Ej >> lane) & 1ull)) d ^= cg;
+      const uint64_t cg = rl64(colGk, pv), cw = rl64(Wk, pv), cwu = rl64(Wuk, pv);
+      if (fr && ((Ej >> lane) & 1ull)) {
+        d ^= cg;
+        tk ^= cw;
+        tuk ^= cwu;
+      }
       if (rl32(rhs, j)) x0 ^= cg;
     }
     // t_f = Bs d_f with Bs = Bs_ket + Bs_bra (the bilinear form), and
     // tu_f = Bu d_f with Bu its strictly upper part (column q of Bu is row q of
     // Bs below bit q), so that d^T B d = par(d & diag) + par(d & Bu d).
     const uint64_t Bs = Bsk ^ Bsb;
-    uint64_t t = 0, tu = 0;
-    for (uint32_t q = 0; q < n; ++q) {
-      const uint64_t Bq = rl64(Bs, q) & bitmask64(d, q);
-      t ^= Bq;
-      tu ^= Bq & ((1ull << q) - 1ull);
-    }
+    const uint64_t t = tk ^ lookup(0, d), tu = tuk ^ lookup(1, d);
     const uint64_t above = (lane >= 63u) ? 0ull : (~0ull << (lane + 1u));
     const uint64_t tu0 = ballot64(act && par64(Bs & above & x0));
     const uint64_t Bd = diag_k ^ diag_b, gd = glo_k ^ glo_b;
