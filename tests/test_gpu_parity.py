@@ -714,6 +714,54 @@ def test_metropolis_windows_across_calls(B, chi):
     net.close()
 
 
+def test_metropolis_many_chains(B):
+    """300 chains: a wave of the single-flip kernel takes 75 of them, so the
+    per-chain words are read in two groups of 64, and the flip-mask kernel
+    walks the chains in five passes of 64; calls of 5, 3 (learned entry point
+    at eps = 1) and 6 steps, chains 0-199 sharing each step's flip bit,
+    against one oracle chain over the concatenated streams."""
+    n, chi, chains = 8, 300, 300
+    calls = [5, "learned", 6]
+    lsteps = 3
+    steps = 5 + lsteps + 6
+    rng = np.random.default_rng(6300)
+    circ = W.random_circuit(n, 60, rng.uniform(0, 2 * np.pi, size=8), rng)
+    spec = dict(circuit=circ, chi=chi, mode="sparsify", seed=630)
+    say(f"metropolis many chains n={n} chi={chi} chains={chains}")
+    ctx = gpu_ctx(B, spec)
+    T = O.Terms(circ, chi, O.SPARSIFY, seed=630)
+    x0 = []
+    while len(x0) < chains:
+        a = int(rng.integers(chi))
+        x = T.term(a).sample(int(W.random_bitstrings(n, 1, rng)[0]))
+        if abs(T.amplitudes(np.array([x], np.uint64))[0]) > 0:
+            x0.append(x)
+    x0 = np.array(x0, np.uint64)
+    j, u = W.metropolis_streams(n, chains, steps, rng, shared_j=True)
+    j[200:] = rng.integers(0, n, size=(chains - 200, steps), dtype=np.uint32)
+    net = B.MLP(ctx, n, 32, 512, W.mlp_init(n, 32))
+    ctx.metropolis_init(x0)
+    trs, accs = [], []
+    t = 0
+    for k in calls:
+        if k == "learned":
+            u_mix, jl, u_bits, ul = W.learned_streams(n, chains, lsteps, rng)
+            j[:, t:t + lsteps], u[:, t:t + lsteps] = jl, ul
+            tr, acc, fl, amp = ctx.metropolis_step_learned(net, u_mix, jl, u_bits, ul, 1.0, 0.01, 0.5)
+            k = lsteps
+        else:
+            tr, acc, amp = ctx.metropolis_step(j[:, t:t + k], u[:, t:t + k])
+        trs.append(tr)
+        accs.append(acc)
+        t += k
+    otr, oacc, oamp = T.metropolis(x0, j, u)
+    assert np.array_equal(np.concatenate(trs, axis=1), otr)
+    assert np.array_equal(np.concatenate(accs, axis=1), oacc)
+    assert normwise(amp, oamp) < 1e-10
+    assert 0 < oacc.mean() < 1
+    net.close()
+
+
 def test_metropolis_graph_replays_match_eager_and_oracle(B):
     """The steps recorded as a HIP graph, replayed four times with eager work
     (amplitudes, eager steps on another instance) and synchronisations in
