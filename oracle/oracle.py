@@ -12,7 +12,8 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liboracle.so")
+# A sanitizer build of the same source can be substituted for checking runs.
+LIB_PATH = os.environ.get("CHSIM_ORACLE_LIB") or os.path.join(HERE, "liboracle.so")
 
 _lib = None
 

@@ -15,7 +15,9 @@ import numpy as np
 from . import workloads as W
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(PKG, "libchsim.so")
+# CHSIM_LIB names another build of the same sources (the host-only sanitizer
+# build used for checking runs); by default the in-tree library.
+LIB_PATH = os.environ.get("CHSIM_LIB") or os.path.join(PKG, "libchsim.so")
 
 CHSIM_OK, CHSIM_EINVAL, CHSIM_ENOMEM, CHSIM_EDEVICE, CHSIM_EUNSUPPORTED, CHSIM_ESTATE = range(6)
 STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "EUNSUPPORTED", 5: "ESTATE"}

@@ -65,6 +65,63 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+# Host code with AddressSanitizer and UndefinedBehaviorSanitizer (the device
+# code objects unsanitized and at -O1): the same sources, for checking the
+# library's host paths (argument validation, decompositions, planning) on a
+# machine without a GPU.  Load it with the clang ASan runtime preloaded.
+SAN_BUILD = os.path.join(ROOT, "_build", "chsim_san")
+SAN_LIB = os.path.join(SAN_BUILD, "libchsim_san.so")
+SAN_FLAGS = [
+    f"--offload-arch={ARCH}", "-O1", "-g", "-std=c++17", "-fPIC", "-Wall",
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+    "-Xarch_host", "-fno-sanitize-recover=all", "-Xarch_host", "-fno-omit-frame-pointer",
+    f"-I{INCLUDE}", f"-I{CSRC}",
+]
+
+
+def build_host_sanitized(verbose: bool = False) -> str:
+    os.makedirs(SAN_BUILD, exist_ok=True)
+
+    def one(src):
+        obj = os.path.join(SAN_BUILD, os.path.basename(src) + ".o")
+        cmd = [HIPCC, *SAN_FLAGS, *EXTRA_FLAGS.get(os.path.basename(src), []), "-c", src, "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"hipcc failed on {src}:\n{r.stdout}\n{r.stderr}")
+        return obj
+
+    srcs = sources()
+    with ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
+        objs = list(ex.map(one, srcs))
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", SAN_LIB]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
+    return SAN_LIB
+
+
+def asan_runtime() -> str:
+    """The clang ASan runtime that matches hipcc's host compiler."""
+    out = subprocess.run([HIPCC, "--print-file-name=libclang_rt.asan-x86_64.so"], capture_output=True,
+                         text=True).stdout.strip()
+    if out and os.path.isabs(out) and os.path.exists(out):
+        return out
+    import glob
+
+    hits = sorted(glob.glob("/opt/rocm/llvm/lib/clang/*/lib/linux/libclang_rt.asan-x86_64.so"))
+    if not hits:
+        raise RuntimeError("clang ASan runtime not found")
+    return hits[-1]
+
+
 if __name__ == "__main__":
-    build(verbose="-v" in sys.argv)
-    print(LIB)
+    if "--sanitize-host" in sys.argv:
+        print(build_host_sanitized(verbose="-v" in sys.argv))
+    else:
+        build(verbose="-v" in sys.argv)
+        print(LIB)
