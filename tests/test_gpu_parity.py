@@ -822,6 +822,38 @@ def test_metropolis_rejects_zero_probability_start(B):
     assert e.value.status == B.CHSIM_EINVAL
 
 
+def test_two_runs_are_byte_identical(B):
+    """The same seeds and inputs in two fresh contexts give byte-identical
+    terms, FP64 and FP32C amplitudes, inner products and chain trajectories
+    (every reduction runs in a fixed order; nothing depends on timing)."""
+    n, chi = 20, 3000
+    rng = np.random.default_rng(6400)
+    circ = W.random_circuit(n, 300, rng.uniform(0, 2 * np.pi, size=12), rng)
+    spec = dict(circuit=circ, chi=chi, mode="sparsify", seed=640)
+    xs = W.random_bitstrings(n, 777, rng)
+    Aoff, Adiag = W.random_equatorial(n, 96, rng)
+    j, u = W.metropolis_streams(n, 6, 25, rng, shared_j=True)
+    say(f"two runs byte-identical n={n} chi={chi}")
+    out = []
+    for run in range(2):
+        ctx = gpu_ctx(B, spec)
+        t = ctx.get_terms(0, chi)
+        a64 = ctx.amplitudes(xs)
+        a32 = ctx.amplitudes(xs, fp32c=True)
+        ov, eta, mean = ctx.inner_products(Aoff, Adiag)
+        alpha = np.arange(6, dtype=np.uint64) * 101
+        x0 = ctx.sample_terms(alpha, np.zeros(6, np.uint64))
+        amp0 = ctx.amplitudes(x0)
+        keep = np.abs(amp0) > 0
+        ctx.metropolis_init(x0[keep])
+        tr, acc, amp = ctx.metropolis_step(j[keep], u[keep])
+        out.append([np.ascontiguousarray(t[k]).tobytes() for k in sorted(t)] +
+                   [a.tobytes() for a in (a64, a32, ov, eta, np.float64(mean), tr, acc, amp)])
+        ctx.close()
+    for k, (p0, p1) in enumerate(zip(out[0], out[1])):
+        assert p0 == p1, k
+
+
 def test_bad_gates_rejected(B):
     circ = W.from_list(4, [(W.OP_H, 0, 0)])
     ctx = B.Context([dict(circuit=circ, chi=2, mode="sparsify", seed=0)])
