@@ -822,6 +822,36 @@ def test_metropolis_rejects_zero_probability_start(B):
     assert e.value.status == B.CHSIM_EINVAL
 
 
+def test_metropolis_resume_from_x(B):
+    """Checkpoint and resume: a chain is described by its x and the position
+    in its random streams, so stopping after 12 steps and re-initialising from
+    the last x (the cached Paulis recomputed from scratch) continues the same
+    chain: the 12 + 13 steps equal the oracle's uninterrupted 25."""
+    n, chi, chains = 10, 5000, 6
+    rng = np.random.default_rng(6500)
+    circ = W.random_circuit(n, 80, rng.uniform(0, 2 * np.pi, size=10), rng)
+    spec = dict(circuit=circ, chi=chi, mode="sparsify", seed=650)
+    say(f"metropolis resume from x n={n} chi={chi}")
+    ctx = gpu_ctx(B, spec)
+    T = O.Terms(circ, chi, O.SPARSIFY, seed=650)
+    x0 = []
+    while len(x0) < chains:
+        a = int(rng.integers(chi))
+        x = T.term(a).sample(int(W.random_bitstrings(n, 1, rng)[0]))
+        if abs(T.amplitudes(np.array([x], np.uint64))[0]) > 0:
+            x0.append(x)
+    x0 = np.array(x0, np.uint64)
+    j, u = W.metropolis_streams(n, chains, 25, rng, shared_j=True)
+    ctx.metropolis_init(x0)
+    tr1, acc1, _ = ctx.metropolis_step(j[:, :12], u[:, :12])
+    ctx.metropolis_init(tr1[:, -1].copy())
+    tr2, acc2, amp2 = ctx.metropolis_step(j[:, 12:], u[:, 12:])
+    otr, oacc, oamp = T.metropolis(x0, j, u)
+    assert np.array_equal(np.concatenate([tr1, tr2], axis=1), otr)
+    assert np.array_equal(np.concatenate([acc1, acc2], axis=1), oacc)
+    assert normwise(amp2, oamp) < 1e-10
+
+
 def test_two_runs_are_byte_identical(B):
     """The same seeds and inputs in two fresh contexts give byte-identical
     terms, FP64 and FP32C amplitudes, inner products and chain trajectories
