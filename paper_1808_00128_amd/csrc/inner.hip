@@ -33,6 +33,17 @@ namespace {
 
 constexpr int kWaves = 4;
 
+// OR of x over the wave's lanes (a superset when some lanes are inactive:
+// DPP and swizzles read their registers as they are).
+__device__ __forceinline__ uint32_t wave_or32(uint32_t x) {
+  x |= (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xB1, 0xF, 0xF, true);
+  x |= (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x4E, 0xF, 0xF, true);
+  x |= (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x141, 0xF, 0xF, true);
+  x |= (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x140, 0xF, 0xF, true);
+  x |= (uint32_t)__shfl_xor((int)x, 16);
+  return (uint32_t)__builtin_amdgcn_readlane((int)x, 0) | (uint32_t)__builtin_amdgcn_readlane((int)x, 32);
+}
+
 // K = G^T X G for X in M_n given by rows: lane c holds Xoff_c (bit d = X_cd,
 // d != c) and Xdiag_c in Z_4.  G: lane c holds row G_c; Gt: lane a holds
 // column a of G (bit c = G_ca).  Returns lane a's row of K (off-diagonal bits)
@@ -341,6 +352,10 @@ __device__ __forceinline__ void pair_term(const uint64_t* __restrict__ r, uint32
         rem &= ~((Word)1 << a);
       }
       if (!__builtin_amdgcn_ballot_w64(rem != 0)) break;
+      // Rows that no lane still holds are zero in every lane: only the
+      // union of the remaining variables needs the update.
+      const uint32_t remUl = wave_or32((uint32_t)rem);
+      const uint32_t remUh = kWide ? wave_or32((uint32_t)((uint64_t)rem >> 32)) : 0u;
       if (rem != 0) {
         const uint32_t b = kWide ? (uint32_t)__builtin_ctzll((uint64_t)Sa) : (uint32_t)__builtin_ctz((uint32_t)Sa);
         const Word Sb = S[b * stride + slot];
@@ -359,16 +374,16 @@ __device__ __forceinline__ void pair_term(const uint64_t* __restrict__ r, uint32
             const uint32_t Sh = ((uint32_t)(Sc >> 32) ^ (m2h & k1) ^ (m1h & k2)) & nabh;
             S[c * stride + slot] = (Word)(((uint64_t)Sh << 32) | Sl);
           };
-          for (uint32_t m = (uint32_t)Rset; m; m &= m - 1u) {
+          for (uint32_t m = (uint32_t)Rset & remUl; m; m &= m - 1u) {
             const uint32_t c = (uint32_t)__builtin_ctz(m);
             upd(c, bit_mask32(m1l, c), bit_mask32(m2l, c));
           }
-          for (uint32_t m = (uint32_t)((uint64_t)Rset >> 32); m; m &= m - 1u) {
+          for (uint32_t m = (uint32_t)((uint64_t)Rset >> 32) & remUh; m; m &= m - 1u) {
             const uint32_t c = (uint32_t)__builtin_ctz(m);
             upd(32u + c, bit_mask32(m1h, c), bit_mask32(m2h, c));
           }
         } else {
-          for (uint32_t m = (uint32_t)Rset; m; m &= m - 1u) {
+          for (uint32_t m = (uint32_t)Rset & remUl; m; m &= m - 1u) {
             const uint32_t c = (uint32_t)__builtin_ctz(m);
             const uint32_t Sc = (uint32_t)S[c * stride + slot];
             S[c * stride + slot] = (Word)((Sc ^ (m2l & bit_mask32(m1l, c)) ^ (m1l & bit_mask32(m2l, c))) & nabl);
