@@ -40,13 +40,34 @@ __global__ __launch_bounds__(256) void k_prefix_clear(PrefixLevelArgs A) {
 
 __global__ __launch_bounds__(256) void k_prefix_insert(PrefixLevelArgs A) {
   const uint64_t a = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (a >= A.chi) return;
+  const bool live = a < A.chi;
+  const uint32_t lane = threadIdx.x & 63u;
+  // The span's slots and widths, 64 at a time, one per lane, taken by lane
+  // reads (a wait for them would also wait for the branch bytes in flight);
+  // the branch bytes themselves eight slots at a time.
   uint32_t bits = 0, sh = 0;
-  for (uint32_t i = 0; i < A.n_span; ++i) {
-    if (A.width[i] == 0) continue;  // a one-branch slot carries no choice
-    bits |= (uint32_t)A.branch[(uint64_t)A.slot[i] * A.chi + a] << sh;
-    sh += A.width[i];
+  for (uint32_t c0 = 0; c0 < A.n_span; c0 += 64u) {
+    const uint32_t cn = min(A.n_span - c0, 64u);
+    const uint32_t my_slot = lane < cn ? (uint32_t)A.slot[c0 + lane] : 0u;
+    const uint32_t my_w = lane < cn ? (uint32_t)A.width[c0 + lane] : 0u;
+    for (uint32_t k0 = 0; k0 < cn; k0 += 8u) {
+      uint32_t bv[8], wv[8];
+#pragma unroll
+      for (uint32_t k = 0; k < 8u; ++k) {
+        const uint32_t i = k0 + k < cn ? k0 + k : cn - 1u;
+        const uint32_t sl = (uint32_t)__builtin_amdgcn_readlane((int)my_slot, (int)i);
+        wv[k] = k0 + k < cn ? (uint32_t)__builtin_amdgcn_readlane((int)my_w, (int)i) : 0u;
+        // A one-branch slot (width 0) carries no choice.
+        bv[k] = (live && wv[k] != 0u) ? (uint32_t)A.branch[(uint64_t)sl * A.chi + a] : 0u;
+      }
+#pragma unroll
+      for (uint32_t k = 0; k < 8u; ++k) {
+        bits |= bv[k] << sh;
+        sh += wv[k];
+      }
+    }
   }
+  if (!live) return;
   const uint64_t prev = A.prev_id ? (uint64_t)A.prev_id[a] : 0ull;
   const uint64_t key = (prev << 32) | bits;  // prev < 2^32 - 1, so key != kEmpty
   uint64_t h = mix64(key) & A.table_mask;
