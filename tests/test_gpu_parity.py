@@ -595,7 +595,9 @@ def test_inner_products_norm_config_subset(B):
 # Metropolis chains: trajectories bit-identical given the same random streams.
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("n,chi,mode,chains,steps", [(8, 64, "exact", 4, 300),
-                                                     (50, 2048, "sparsify", 8, 120)])
+                                                     (50, 2048, "sparsify", 8, 120),
+                                                     (62, 700, "sparsify", 6, 90),
+                                                     (1, 64, "exact", 3, 40)])
 def test_metropolis_trajectories(B, n, chi, mode, chains, steps):
     rng = np.random.default_rng(60 + n)
     if n == 50:
