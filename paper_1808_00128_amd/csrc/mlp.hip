@@ -9,10 +9,11 @@
 // accepted iff U < P(y) q(x|y) / (P(x) q(y|x)) with the exact amplitude ratio
 // of the sum over Cliffords, so the stationary law is unchanged.
 //
-// Matrix products: v_mfma_f32_16x16x16_bf16 (BF16 operands, FP32 accumulate),
-// 32x32 output tile per 256-thread workgroup (2 x 2 waves, one 16x16 MFMA
-// tile each), operands staged through LDS in BF16 with arbitrary source
-// strides, so forward and backward products use the same kernel.
+// Matrix products: v_mfma_f32_16x16x32_bf16 (gfx950: BF16 operands, FP32
+// accumulate, K = 32 per instruction), 32x32 output tile per 256-thread
+// workgroup (2 x 2 waves, one 16x16 MFMA tile each), operands staged through
+// LDS in BF16 with arbitrary source strides, so forward and backward products
+// use the same kernel.
 #include <algorithm>
 
 #include "device_common.hpp"
@@ -22,7 +23,18 @@
 namespace chsim {
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef short bf16x8s __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// Eight BF16 values from two 8-byte halves (LDS rows are 8-byte aligned).
+__device__ __forceinline__ bf16x8 join8(bf16x4 lo, bf16x4 hi) {
+  const bf16x8s v = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+  return __builtin_bit_cast(bf16x8, v);
+}
+__device__ __forceinline__ bf16x8 lds8(const uint16_t* p) {
+  return join8(*reinterpret_cast<const bf16x4*>(p), *reinterpret_cast<const bf16x4*>(p + 4));
+}
 
 __device__ __forceinline__ uint16_t f2bf(float f) {
   uint32_t u = __float_as_uint(f);
@@ -147,9 +159,11 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
   uint16_t va[8], vb[8];
   stage_load(g.A, g.sai, g.sak, g.M, m0, kbeg, kend, a_kf, va);
   stage_load(g.B, g.sbj, g.sbk, g.N, n0, kbeg, kend, b_kf, vb);
-  // 16x16x16 operand layout: lane l holds A[l % 16][4 (l / 16) .. +3] and
-  // B[4 (l / 16) .. +3][l % 16]; the result C[4 (l / 16) + r][l % 16], r = 0..3.
-  const int r16 = lane & 15, kq = (lane >> 4) * 4;
+  // 16x16x32 operands: lane l holds A[l % 16][k] and B[k][l % 16] for the
+  // eight k = 8 (l / 16) .. +7 of each 32-wide step (the same k for both, so
+  // the contraction does not depend on their order inside the instruction);
+  // the result C[4 (l / 16) + r][l % 16], r = 0..3.
+  const int r16 = lane & 15, kq = (lane >> 4) * 8;
   f32x4 acc = {0.f, 0.f, 0.f, 0.f};
   for (int k0 = kbeg; k0 < kend; k0 += kGK) {
     __syncthreads();
@@ -161,10 +175,10 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
       stage_load(g.B, g.sbj, g.sbk, g.N, n0, k0 + kGK, kend, b_kf, vb);
     }
 #pragma unroll
-    for (int kk = 0; kk < kGK; kk += 16) {
-      const bf16x4 a = *reinterpret_cast<const bf16x4*>(&As[wm * 16 + r16][kk + kq]);
-      const bf16x4 b = *reinterpret_cast<const bf16x4*>(&Bs[wn * 16 + r16][kk + kq]);
-      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+    for (int kk = 0; kk < kGK; kk += 32) {
+      const bf16x8 a = lds8(&As[wm * 16 + r16][kk + kq]);
+      const bf16x8 b = lds8(&Bs[wn * 16 + r16][kk + kq]);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
     }
   }
   const int col = n0 + wn * 16 + (lane & 15);
@@ -486,33 +500,36 @@ __device__ __forceinline__ void fused_layer(const uint16_t* As, int pa, int K,
                                             int po, float* zf, uint16_t* zb, float* out, int ldo,
                                             int rows) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int r16 = lane & 15, kq = (lane >> 4) * 4;
-  const int kb_n = ((K + kGK - 1) / kGK) * (kGK / 16);  // 16-wide k blocks
+  const int r16 = lane & 15, kq = (lane >> 4) * 8;
+  const int kb_n = ((K + kGK - 1) / kGK) * (kGK / 32);  // 32-wide k blocks
   const bool vec = (K % 4) == 0;                        // rows of W 8-byte aligned
   for (int ct = wave; ct * 16 < N; ct += kFWaves) {
     const int col = ct * 16 + r16;
-    bf16x4 b[kFMaxH / 16];
+    bf16x8 b[kFMaxH / 32];
 #pragma unroll
-    for (int kb = 0; kb < kFMaxH / 16; ++kb) {
-      const int k = kb * 16 + kq;
-      bf16x4 v = {0, 0, 0, 0};
-      if (kb < kb_n && col < N && k < K) {
-        const uint16_t* w = W + (int64_t)col * K + k;
-        if (vec) {
-          v = *reinterpret_cast<const bf16x4*>(w);
-        } else {
+    for (int kb = 0; kb < kFMaxH / 32; ++kb) {
+      bf16x4 v[2] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
 #pragma unroll
-          for (int i = 0; i < 4; ++i) v[i] = (k + i < K) ? (short)w[i] : (short)0;
+      for (int hf = 0; hf < 2; ++hf) {
+        const int k = kb * 32 + kq + 4 * hf;
+        if (kb < kb_n && col < N && k < K) {
+          const uint16_t* w = W + (int64_t)col * K + k;
+          if (vec) {
+            v[hf] = *reinterpret_cast<const bf16x4*>(w);
+          } else {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) v[hf][i] = (k + i < K) ? (short)w[i] : (short)0;
+          }
         }
       }
-      b[kb] = v;
+      b[kb] = join8(v[0], v[1]);
     }
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int kb = 0; kb < kFMaxH / 16; ++kb) {
+    for (int kb = 0; kb < kFMaxH / 32; ++kb) {
       if (kb < kb_n) {  // kb_n is wave-uniform
-        const bf16x4 a = *reinterpret_cast<const bf16x4*>(&As[r16 * pa + kb * 16 + kq]);
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b[kb], acc, 0, 0, 0);
+        const bf16x8 a = lds8(&As[r16 * pa + kb * 32 + kq]);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[kb], acc, 0, 0, 0);
       }
     }
     if (col >= N) continue;
