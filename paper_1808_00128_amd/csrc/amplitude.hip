@@ -122,30 +122,39 @@ struct TileTerm {
 
 // Prologue: per term, the rows c_q of B (stored like F: c[q * chi + a]), for
 // a packed term with F_q gathered from the ~v positions above bit n, and the
-// constants.  Four threads per term, thread (quarter, lane) of a 256-thread
-// block taking rows q = quarter (mod 4) of term 64 block + lane; F rows of the
-// 64 terms are parked in LDS.
-constexpr uint32_t kPrepTerms = 64;
+// constants.  kPrepSplit threads per term, thread (part, lane) of a 256-thread
+// block taking rows q = part (mod kPrepSplit) of term kPrepTerms block + lane
+// (short serial chains: a row costs q + 1 parities); F rows of the block's
+// terms are parked in LDS, and the low bits of gamma are gathered by the same
+// split and combined through LDS.
+constexpr uint32_t kPrepTerms = 16;
+constexpr uint32_t kPrepSplit = 256 / kPrepTerms;
 __global__ __launch_bounds__(256) void k_amp_prep(TermsView T, uint64_t* __restrict__ crow,
                                                   AmpTerm* __restrict__ cst) {
   extern __shared__ __align__(16) uint8_t smem[];
-  uint64_t* Fs = reinterpret_cast<uint64_t*>(smem);  // [n][64]
-  const uint32_t lane = threadIdx.x % kPrepTerms, quarter = threadIdx.x / kPrepTerms;
+  uint64_t* gpart = reinterpret_cast<uint64_t*>(smem);  // [kPrepSplit][kPrepTerms]
+  uint64_t* Fs = gpart + kPrepSplit * kPrepTerms;       // [n][kPrepTerms]
+  const uint32_t lane = threadIdx.x % kPrepTerms, part = threadIdx.x / kPrepTerms;
   const uint64_t chi = T.chi;
   const uint64_t a = (uint64_t)blockIdx.x * kPrepTerms + lane;
   const bool on = a < chi;
   const uint32_t n = T.n;
+  uint64_t glo = 0;
   if (on)
-    for (uint32_t p = quarter; p < n; p += 4) Fs[p * kPrepTerms + lane] = T.F[(uint64_t)p * chi + a];
+    for (uint32_t p = part; p < n; p += kPrepSplit) {
+      Fs[p * kPrepTerms + lane] = T.F[(uint64_t)p * chi + a];
+      glo |= (uint64_t)(T.gamma[(uint64_t)p * chi + a] & 1u) << p;
+    }
+  gpart[part * kPrepTerms + lane] = glo;
   __syncthreads();
-  if (!on) return;
+  if (!on) return;  // no barrier follows
   const uint64_t xm = (n == 64) ? ~0ull : ((1ull << n) - 1ull);
   const uint64_t v = T.v[a], s = T.s[a];
   const uint64_t vs = v & s;
   const uint64_t nv = ~v & xm;
   const uint32_t nfree = (uint32_t)__popcll(nv);
   const bool packed = nfree <= 64u - n;  // n + nfree <= 64; nfree > 0 implies n < 64
-  for (uint32_t q = quarter; q < n; q += 4) {
+  for (uint32_t q = part; q < n; q += kPrepSplit) {
     const uint64_t Mq = T.M[(uint64_t)q * chi + a];
     const uint32_t ghi_q = (T.gamma[(uint64_t)q * chi + a] >> 1) & 1u;
     uint64_t col = 0;
@@ -154,9 +163,9 @@ __global__ __launch_bounds__(256) void k_amp_prep(TermsView T, uint64_t* __restr
     if (packed && nfree != 0u) col |= gather_bits(Fs[q * kPrepTerms + lane], nv) << n;
     crow[(uint64_t)q * chi + a] = col;
   }
-  if (quarter != 0) return;
-  uint64_t glo = 0;
-  for (uint32_t p = 0; p < n; ++p) glo |= (uint64_t)(T.gamma[(uint64_t)p * chi + a] & 1u) << p;
+  if (part != 0) return;
+  glo = 0;
+  for (uint32_t k = 0; k < kPrepSplit; ++k) glo |= gpart[k * kPrepTerms + lane];
   AmpTerm c;
   c.nv = nv;
   c.snv = !packed ? (s & nv) : (nfree != 0u ? gather_bits(s, nv) << n : 0ull);
@@ -405,7 +414,7 @@ __global__ __launch_bounds__(256) void k_reduce_ranges(const AmpInst* __restrict
 
 hipError_t launch_amp_prep(const TermsView& T, uint64_t* crow, AmpTerm* cst, hipStream_t st) {
   const uint32_t blocks = (uint32_t)((T.chi + kPrepTerms - 1) / kPrepTerms);
-  const size_t sm = (size_t)T.n * kPrepTerms * sizeof(uint64_t);
+  const size_t sm = ((size_t)T.n + kPrepSplit) * kPrepTerms * sizeof(uint64_t);
   hipLaunchKernelGGL(k_amp_prep, dim3(blocks), dim3(256), sm, st, T, crow, cst);
   return hipGetLastError();
 }
