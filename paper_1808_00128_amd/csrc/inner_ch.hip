@@ -120,9 +120,92 @@ __device__ __forceinline__ double2 scaled_root(uint32_t k8, int e2, double2 b) {
   return make_double2(mag * (b.x * cr - b.y * ci), mag * (b.x * ci + b.y * cr));
 }
 
+// What the pair elimination of a lifted form leaves: eliminated pairs, the
+// isolated variables, the two lifted sums' signs and which of them vanish.
+struct LiftOut {
+  uint32_t nel, sr, si;
+  int niso;
+  bool re_nz, im_nz;
+};
+
+template <typename Word>
+__device__ __forceinline__ Word rl_word(Word x, uint32_t src) {
+  if constexpr (sizeof(Word) == 4) return rl32(x, src);
+  else return rl64(x, src);
+}
+template <typename Word>
+__device__ __forceinline__ uint32_t ctz_word(Word x) {
+  if constexpr (sizeof(Word) == 4) return (uint32_t)__builtin_ctz(x);
+  else return (uint32_t)__builtin_ctzll(x);
+}
+
+// Z of the Z_2 form of Eq. (Q) that lifts a Z_4 form (kap: odd diagonal,
+// lam: diagonal high bits, S: off-diagonal rows, lane v holding row v) onto
+// the variables Rset, of which e is the extra one, by pair elimination
+// (Eqs. (identity), (eq5)); Word holds a row (bit v = variable v, lane v < its
+// width).
+template <typename Word>
+__device__ __forceinline__ LiftOut lift_eliminate(Word S, Word kap, Word lam, Word Rset, uint32_t e, uint32_t lane) {
+  constexpr uint32_t kBits = sizeof(Word) * 8u;
+  const bool inw = lane < kBits;
+  const Word lbw = inw ? (Word)((Word)1 << (lane & (kBits - 1u))) : (Word)0;
+  const Word eb = (Word)((Word)1 << e);
+  const Word odd = inw ? (Word)((kap >> (lane & (kBits - 1u))) & (Word)1) : (Word)0;
+  const bool var = (Rset & ~eb & lbw) != (Word)0;
+  Word row = var ? (Word)(((S ^ (kap & (Word)((Word)0 - odd))) & ~lbw) | (Word)(odd << e)) : (Word)0;
+  if (lane == e) row = kap;
+  Word lr = lam, li = lam | eb, rem = Rset, iso = 0;
+  LiftOut o{0u, 0u, 0u, 0, false, false};
+  for (;;) {
+    // First remaining variable with a non-zero row; variables with zero rows
+    // are isolated for good.
+    const Word nz = (Word)ballot64((rem & lbw) != (Word)0 && row != (Word)0);
+    const Word zr = rem & ~nz;
+    if (nz == (Word)0) {
+      iso |= zr;
+      break;
+    }
+    const uint32_t va = ctz_word(nz);
+    const Word below = (Word)(((Word)1 << va) - (Word)1);
+    iso |= zr & below;
+    rem &= ~(zr & below);
+    const Word Sa = rl_word(row, va);
+    const uint32_t vb = ctz_word(Sa);
+    const Word Sb = rl_word(row, vb);
+    const Word ab = (Word)(((Word)1 << va) | ((Word)1 << vb));
+    const Word m1 = Sa & ~ab, m2 = Sb & ~ab;
+    const Word b1 = inw ? (Word)((Word)0 - ((m1 >> (lane & (kBits - 1u))) & (Word)1)) : (Word)0;
+    const Word b2 = inw ? (Word)((Word)0 - ((m2 >> (lane & (kBits - 1u))) & (Word)1)) : (Word)0;
+    row ^= (m2 & b1) ^ (m1 & b2);
+    row &= ~ab;
+    if (lane == va || lane == vb) row = 0;
+    {
+      const Word la = (lr >> va) & (Word)1, lbb = (lr >> vb) & (Word)1;
+      o.sr ^= (uint32_t)(la & lbb);
+      lr ^= (m2 & (Word)((Word)0 - la)) ^ (m1 & (Word)((Word)0 - lbb)) ^ (m1 & m2);
+      lr &= ~ab;
+    }
+    {
+      const Word la = (li >> va) & (Word)1, lbb = (li >> vb) & (Word)1;
+      o.si ^= (uint32_t)(la & lbb);
+      li ^= (m2 & (Word)((Word)0 - la)) ^ (m1 & (Word)((Word)0 - lbb)) ^ (m1 & m2);
+      li &= ~ab;
+    }
+    rem &= ~ab;
+    ++o.nel;
+  }
+  o.niso = __popcll((uint64_t)iso);
+  o.re_nz = (lr & iso) == (Word)0;
+  o.im_nz = (li & iso) == (Word)0;
+  return o;
+}
+
 // One wave per (bra state l = blockIdx.x * kCHWaves + wave, ket group g =
-// blockIdx.y): the ket terms g, g + groups, ...; lane i holds row/variable i.
-__global__ __launch_bounds__(64 * kCHWaves) void k_inner_ch_pairs(
+// blockIdx.y): the ket terms g, g + groups, ...; lane i holds row/variable i
+// (a pair's free variables are moved to lanes 0, 1, ... when at most 31 of
+// them, so that the Z_4 form's rows and its elimination use 32-bit words).
+// Seven waves per SIMD (the LDS of the tables and the scratch allows seven).
+__global__ __launch_bounds__(64 * kCHWaves, 7) void k_inner_ch_pairs(
     const uint64_t* __restrict__ rec_k, const double2* __restrict__ b_k, uint64_t chi_k,
     const uint64_t* __restrict__ rec_b, uint32_t L, uint32_t n, double2* __restrict__ partial,
     uint32_t* __restrict__ err) {
@@ -147,6 +230,12 @@ __global__ __launch_bounds__(64 * kCHWaves) void k_inner_ch_pairs(
   // nibble groups g of tab[g][nibble g of d]).
   __shared__ uint64_t tabs[kCHWaves][2][16][16];
   uint64_t(*const tab)[16][16] = tabs[uniform32(threadIdx.x >> 6)];
+  // Scratch for moving a pair's free variables to lanes 0, 1, ...
+  __shared__ uint64_t cds[kCHWaves][64], cws[kCHWaves][64];
+  __shared__ uint32_t ces[kCHWaves][64];
+  uint64_t* const cd = cds[uniform32(threadIdx.x >> 6)];
+  uint64_t* const cw = cws[uniform32(threadIdx.x >> 6)];
+  uint32_t* const ce = ces[uniform32(threadIdx.x >> 6)];
   const uint32_t ngrp = (n + 3u) / 4u;
   for (uint32_t g = 0; g < ngrp; ++g) {
     uint64_t acc = 0;
@@ -257,77 +346,60 @@ __global__ __launch_bounds__(64 * kCHWaves) void k_inner_ch_pairs(
     const uint32_t lf = ((uint32_t)__popcll(d & Pp) + 3u * (uint32_t)__popcll(d & Pm)) & 3u;
     const uint32_t qd = par64(Bd & d) ^ par64(d & tu);
     const uint32_t ef = (lf + 2u * (par64(x0 & t) ^ qd)) & 3u;
-    uint64_t S = 0;
-    for (uint64_t u = Fr; u; u &= u - 1ull) {
-      const uint32_t f2 = (uint32_t)__builtin_ctzll(u);
-      const uint64_t w = (rl64(d, f2) & gd) ^ rl64(t, f2);
-      S |= (uint64_t)par64(d & w) << f2;
-    }
-    S = fv ? (S & ~lb) : 0ull;
-    // Lift (Eq. (Q)): variables Fr and one extra index e; kap = odd diagonal,
-    // lam = diagonal high bits.
     if (Fr == ~0ull) {
       bad = 1u;
       continue;
     }
-    const uint64_t kap = ballot64(fv && (ef & 1u)), lam = ballot64(fv && (ef & 2u));
-    const uint32_t e = (uint32_t)__builtin_ctzll(~Fr);
-    const uint64_t eb = 1ull << e;
-    const uint64_t odd = (kap >> lane) & 1ull;
-    uint64_t row = fv ? (((S ^ (kap & (0ull - odd))) & ~lb) | (odd << e)) : 0ull;
-    if (lane == e) row = kap;
-    const uint64_t Rset = Fr | eb;
-    uint64_t lr = lam, li = lam | eb, rem = Rset, iso = 0;
-    uint32_t sr = 0, si = 0, nel = 0;
-    for (;;) {
-      // First remaining variable with a non-zero row; variables with zero rows
-      // are isolated for good.
-      const uint64_t nz = ballot64(((rem >> lane) & 1ull) && row != 0ull);
-      const uint64_t zr = rem & ~nz;
-      if (nz == 0ull) {
-        iso |= zr;
-        break;
+    // S_fg = par(d_f & w_g) with w_g = (d_g & gd) ^ t_g, formed by each lane
+    // for its own variable.
+    const uint64_t wv = (d & gd) ^ t;
+    const uint32_t nf = (uint32_t)__popcll(Fr);
+    LiftOut lo;
+    if (nf < 32u) {
+      // At most 31 free variables: move variable f to lane c = (its rank in
+      // Fr), so that rows are 32-bit words over c and the extra variable is
+      // c = nf.
+      const uint32_t c = (uint32_t)__popcll(Fr & (lb - 1ull));
+      if (fv) {
+        cd[c] = d;
+        cw[c] = wv;
+        ce[c] = ef;
       }
-      const uint32_t va = (uint32_t)__builtin_ctzll(nz);
-      iso |= zr & ((1ull << va) - 1ull);
-      rem &= ~(zr & ((1ull << va) - 1ull));
-      const uint64_t Sa = rl64(row, va);
-      const uint32_t vb = (uint32_t)__builtin_ctzll(Sa);
-      const uint64_t Sb = rl64(row, vb);
-      const uint64_t ab = (1ull << va) | (1ull << vb);
-      const uint64_t m1 = Sa & ~ab, m2 = Sb & ~ab;
-      row ^= (m2 & bitmask64(m1, lane)) ^ (m1 & bitmask64(m2, lane));
-      row &= ~ab;
-      if (lane == va || lane == vb) row = 0ull;
-      {
-        const uint64_t la = (lr >> va) & 1ull, lbb = (lr >> vb) & 1ull;
-        sr ^= (uint32_t)(la & lbb);
-        lr ^= (m2 & (0ull - la)) ^ (m1 & (0ull - lbb)) ^ (m1 & m2);
-        lr &= ~ab;
+      __builtin_amdgcn_wave_barrier();
+      const bool fc = lane < nf;
+      const uint64_t dc = fc ? cd[lane] : 0ull, wc = fc ? cw[lane] : 0ull;
+      const uint32_t ec = fc ? ce[lane] : 0u;
+      __builtin_amdgcn_wave_barrier();
+      uint32_t S = 0;
+      for (uint32_t c2 = 0; c2 < nf; ++c2) S |= par64(dc & rl64(wc, c2)) << c2;
+      const uint32_t lb32 = lane < 32u ? (1u << lane) : 0u;
+      S = fc ? (S & ~lb32) : 0u;
+      lo = lift_eliminate<uint32_t>(S, (uint32_t)ballot64(fc && (ec & 1u)), (uint32_t)ballot64(fc && (ec & 2u)),
+                                    (2u << nf) - 1u, nf, lane);
+    } else {
+      uint64_t S = 0;
+      for (uint64_t u = Fr; u; u &= u - 1ull) {
+        const uint32_t f2 = (uint32_t)__builtin_ctzll(u);
+        S |= (uint64_t)par64(d & rl64(wv, f2)) << f2;
       }
-      {
-        const uint64_t la = (li >> va) & 1ull, lbb = (li >> vb) & 1ull;
-        si ^= (uint32_t)(la & lbb);
-        li ^= (m2 & (0ull - la)) ^ (m1 & (0ull - lbb)) ^ (m1 & m2);
-        li &= ~ab;
-      }
-      rem &= ~ab;
-      ++nel;
+      S = fv ? (S & ~lb) : 0ull;
+      const uint32_t e = (uint32_t)__builtin_ctzll(~Fr);
+      lo = lift_eliminate<uint64_t>(S, ballot64(fv && (ef & 1u)), ballot64(fv && (ef & 2u)), Fr | (1ull << e), e,
+                                    lane);
     }
-    const int rr = __popcll(iso);
-    const bool re_nz = (lr & iso) == 0ull, im_nz = (li & iso) == 0ull;
+    const bool re_nz = lo.re_nz, im_nz = lo.im_nz;
     if (!(re_nz || im_nz)) continue;
-    const int ez0 = (int)nel + rr - 1;
+    const int ez0 = (int)lo.nel + lo.niso - 1;
     uint32_t kz;
     int ez;
     if (re_nz && im_nz) {
-      kz = sr ? (si ? 5u : 3u) : (si ? 7u : 1u);
+      kz = lo.sr ? (lo.si ? 5u : 3u) : (lo.si ? 7u : 1u);
       ez = 2 * ez0 + 1;
     } else if (re_nz) {
-      kz = sr ? 4u : 0u;
+      kz = lo.sr ? 4u : 0u;
       ez = 2 * ez0;
     } else {
-      kz = si ? 6u : 2u;
+      kz = lo.si ? 6u : 2u;
       ez = 2 * ez0;
     }
     const int e2 = ez - (int)((uint32_t)__popcll(v_k) + (uint32_t)__popcll(v_b));
