@@ -200,19 +200,30 @@ __device__ __forceinline__ LiftOut lift_eliminate(Word S, Word kap, Word lam, Wo
   return o;
 }
 
-// One wave per (bra state l = blockIdx.x * kCHWaves + wave, ket group g =
-// blockIdx.y): the ket terms g, g + groups, ...; lane i holds row/variable i
+// One wave per (bra state l = bra block * kCHWaves + wave, ket group g):
+// the ket terms g, g + groups, ...; lane i holds row/variable i
 // (a pair's free variables are moved to lanes 0, 1, ... when at most 31 of
 // them, so that the Z_4 form's rows and its elimination use 32-bit words).
 // Seven waves per SIMD (the LDS of the tables and the scratch allows seven).
+// The block index maps XCD-aware: workgroups are dealt to the 8 XCDs in turn,
+// and the bra blocks of one ket group are consecutive on one XCD, so a ket
+// record is read from HBM about once per XCD-resident group.
 __global__ __launch_bounds__(64 * kCHWaves, 7) void k_inner_ch_pairs(
     const uint64_t* __restrict__ rec_k, const double2* __restrict__ b_k, uint64_t chi_k,
-    const uint64_t* __restrict__ rec_b, uint32_t L, uint32_t n, double2* __restrict__ partial,
-    uint32_t* __restrict__ err) {
+    const uint64_t* __restrict__ rec_b, uint32_t L, uint32_t n, uint32_t groups, uint32_t bra_blocks,
+    double2* __restrict__ partial, uint32_t* __restrict__ err) {
   const uint32_t lane = threadIdx.x & 63u;
-  const uint32_t l = blockIdx.x * kCHWaves + uniform32(threadIdx.x >> 6);
+  uint32_t group, bblock;
+  if (groups % 8u == 0u) {
+    const uint32_t xcd = blockIdx.x % 8u, k = blockIdx.x / 8u;
+    group = (k / bra_blocks) * 8u + xcd;
+    bblock = k % bra_blocks;
+  } else {
+    group = blockIdx.x % groups;
+    bblock = blockIdx.x / groups;
+  }
+  const uint32_t l = bblock * kCHWaves + uniform32(threadIdx.x >> 6);
   if (l >= L) return;  // whole waves
-  const uint32_t groups = gridDim.y;
   const uint32_t R = chrec_words(n);
   const bool act = lane < n;
   const uint64_t lb = 1ull << lane;
@@ -255,7 +266,7 @@ __global__ __launch_bounds__(64 * kCHWaves, 7) void k_inner_ch_pairs(
   };
   double accr = 0.0, acci = 0.0;
   uint32_t bad = 0;
-  for (uint64_t a = blockIdx.y; a < chi_k; a += groups) {
+  for (uint64_t a = group; a < chi_k; a += groups) {
     const uint64_t* rk = rec_k + a * R;
     const uint64_t colGk = act ? rk[lane] : 0ull;
     const uint64_t Growk = act ? rk[n + lane] : 0ull;
@@ -408,7 +419,7 @@ __global__ __launch_bounds__(64 * kCHWaves, 7) void k_inner_ch_pairs(
     acci += val.y;
   }
   if (bad && lane == 0u) atomicOr(err, 1u);
-  if (lane == 0u) partial[(uint64_t)blockIdx.y * L + l] = make_double2(accr, acci);
+  if (lane == 0u) partial[(uint64_t)group * L + l] = make_double2(accr, acci);
 }
 
 __global__ __launch_bounds__(256) void k_inner_ch_reduce(const double2* __restrict__ partial, uint32_t groups,
@@ -461,17 +472,22 @@ hipError_t launch_inner_ch_records(const TermsView& T, uint64_t* rec, hipStream_
 }
 
 uint32_t inner_ch_groups(uint64_t chi_k, uint32_t L) {
-  // About 2^17 waves in all, at least one ket term per group (grid y <= 65535).
+  // About 2^17 waves in all, at least one ket term per group, a multiple of
+  // 8 groups when there are 8 or more (the XCD-aware block order).
   const uint64_t want = std::max<uint64_t>(1, (uint64_t)(1u << 17) / std::max<uint32_t>(L, 1u));
-  return (uint32_t)std::min<uint64_t>(std::min<uint64_t>(want, 4096), chi_k);
+  const uint64_t g = std::min<uint64_t>(std::min<uint64_t>(want, 4096), chi_k);
+  return (uint32_t)(g >= 8 ? g & ~7ull : g);
 }
 
 hipError_t launch_inner_ch(const uint64_t* rec_k, const double2* b_k, uint64_t chi_k, const uint64_t* rec_b,
                            const double2* b_bra, uint32_t L, uint32_t n, uint32_t groups, double2* partial,
                            double2* overlap, double2* total, uint32_t* err, hipStream_t st) {
-  const dim3 grid((L + kCHWaves - 1) / kCHWaves, groups);
-  hipLaunchKernelGGL(k_inner_ch_pairs, grid, dim3(64 * kCHWaves), 0, st, rec_k, b_k, chi_k, rec_b, L, n, partial,
-                     err);
+  const uint32_t bra_blocks = (L + kCHWaves - 1) / kCHWaves;
+  const uint64_t blocks = (uint64_t)bra_blocks * groups;
+  if (blocks == 0) return hipSuccess;
+  if (blocks > 0x7FFFFFFFull) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_inner_ch_pairs, dim3((uint32_t)blocks), dim3(64 * kCHWaves), 0, st, rec_k, b_k, chi_k, rec_b,
+                     L, n, groups, bra_blocks, partial, err);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_inner_ch_reduce, dim3((L + 255u) / 256u), dim3(256), 0, st, partial, groups, L, overlap);
