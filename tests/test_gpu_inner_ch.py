@@ -126,6 +126,48 @@ def test_inner_ch_equatorial_case_matches_equatorial_path(B, n):
     ctx.close()
 
 
+def _with_slots(n, gates, rng, slots):
+    """The gates with phase slots (S-power branches, left rules) inserted at
+    random positions after the first gate."""
+    out = list(gates)
+    for _ in range(slots):
+        pos = int(rng.integers(1, len(out) + 1))
+        out.insert(pos, (W.OP_SLOT, int(rng.integers(n)), 0, float(rng.uniform(0, 2 * np.pi))))
+    return out
+
+
+@pytest.mark.parametrize("k", [30, 31, 32, 33])
+def test_inner_ch_free_variable_count_boundary(B, k):
+    """Kets with v = {0, ..., k-1} (Hadamards on k fresh qubits of |0^n>, then
+    only S, CX, CZ and phase slots, which are left rules and keep v) against
+    bras with v = every qubit (no equations): every pair has exactly k free
+    variables, on both sides of the 31 at which the pair kernel changes from
+    32-bit to 64-bit rows."""
+    n = 40
+    rng = np.random.default_rng(1600 + k)
+    left = (W.OP_S, W.OP_CX, W.OP_CZ)
+    kg = [(W.OP_H, q, 0) for q in range(k)]
+    kg += _with_slots(n, W.random_clifford_gates(n, 300, rng, ops=left), rng, 6)
+    bg = [(W.OP_H, q, 0) for q in range(n)]
+    bg += _with_slots(n, W.random_clifford_gates(n, 200, rng, ops=left), rng, 4)
+    ck, cb = W.from_list(n, kg), W.from_list(n, bg)
+    sk = dict(circuit=ck, chi=64, mode="sparsify", seed=1610 + k)
+    sb = dict(circuit=cb, chi=8, mode="sparsify", seed=1620 + k)
+    say(f"inner CH x CH free-variable boundary k={k}")
+    ctx = B.Context([sk, sb])
+    ctx.apply_circuit(ck, inst=0)
+    ctx.apply_circuit(cb, inst=1)
+    Tk = O.Terms(ck, 64, O.SPARSIFY, seed=sk["seed"])
+    Tb = O.Terms(cb, 8, O.SPARSIFY, seed=sb["seed"])
+    assert all(int(Tk.term(a).export()["v"]) == (1 << k) - 1 for a in range(64))
+    assert all(int(Tb.term(l).export()["v"]) == (1 << n) - 1 for l in range(8))
+    ov, tot = ctx.inner_products_ch(1, inst=0)
+    ref, rtot = Tk.inner_ch(Tb)
+    assert normwise(ov, ref) < TOL64
+    assert abs(tot - rtot) <= TOL64 * max(1.0, np.sqrt(np.sum(np.abs(ref) ** 2)))
+    ctx.close()
+
+
 def test_inner_ch_norm_config_subset(B):
     """The norm-estimation workload's circuit (n = 40, 30 slots), its first 256
     terms against 8 random stabilizer states (terms of a random Clifford +
