@@ -204,11 +204,11 @@ __device__ __forceinline__ LiftOut lift_eliminate(Word S, Word kap, Word lam, Wo
 // the ket terms g, g + groups, ...; lane i holds row/variable i
 // (a pair's free variables are moved to lanes 0, 1, ... when at most 31 of
 // them, so that the Z_4 form's rows and its elimination use 32-bit words).
-// Seven waves per SIMD (the LDS of the tables and the scratch allows seven).
+// Eight waves per SIMD (the LDS of the tables and the scratch allows eight).
 // The block index maps XCD-aware: workgroups are dealt to the 8 XCDs in turn,
 // and the bra blocks of one ket group are consecutive on one XCD, so a ket
 // record is read from HBM about once per XCD-resident group.
-__global__ __launch_bounds__(64 * kCHWaves, 7) void k_inner_ch_pairs(
+__global__ __launch_bounds__(64 * kCHWaves, 8) void k_inner_ch_pairs(
     const uint64_t* __restrict__ rec_k, const double2* __restrict__ b_k, uint64_t chi_k,
     const uint64_t* __restrict__ rec_b, uint32_t L, uint32_t n, uint32_t groups, uint32_t bra_blocks,
     double2* __restrict__ partial, uint32_t* __restrict__ err) {
@@ -242,8 +242,8 @@ __global__ __launch_bounds__(64 * kCHWaves, 7) void k_inner_ch_pairs(
   __shared__ uint64_t tabs[kCHWaves][2][16][16];
   uint64_t(*const tab)[16][16] = tabs[uniform32(threadIdx.x >> 6)];
   // Scratch for moving a pair's free variables to lanes 0, 1, ...
-  __shared__ uint64_t cds[kCHWaves][64], cws[kCHWaves][64];
-  __shared__ uint32_t ces[kCHWaves][64];
+  __shared__ uint64_t cds[kCHWaves][32], cws[kCHWaves][32];
+  __shared__ uint32_t ces[kCHWaves][32];
   uint64_t* const cd = cds[uniform32(threadIdx.x >> 6)];
   uint64_t* const cw = cws[uniform32(threadIdx.x >> 6)];
   uint32_t* const ce = ces[uniform32(threadIdx.x >> 6)];
