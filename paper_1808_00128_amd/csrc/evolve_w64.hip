@@ -160,67 +160,76 @@ __global__ __launch_bounds__(256) void k_evolve_w64(EvolveJob J, const DGate* __
   uint32_t next_b = n_occ ? uniform32(branch[(uint64_t)seq[0] * chb + ba]) : 0u;
   uint32_t cur_b = 0u, occ = 1u;
   const uint2* __restrict__ g2 = reinterpret_cast<const uint2*>(gates);
-  __shared__ uint2 sg[kW64Chunk];
+  __shared__ uint2 sg[kW64Chunk + 1];  // one entry past the chunk, so the next gate is always read in bounds
   for (uint32_t c0 = 0; c0 < n_gates; c0 += kW64Chunk) {
     const uint32_t cn = min(kW64Chunk, n_gates - c0);
     __syncthreads();
     for (uint32_t t = threadIdx.x; t < cn; t += 256u) sg[t] = g2[c0 + t];
+    if (threadIdx.x == 0) sg[cn] = make_uint2(0u, 0u);
     __syncthreads();
     uint2 nxt = sg[0];
     for (uint32_t i = 0; i < cn; ++i) {
       const uint32_t w0 = uniform32(nxt.x), w1 = uniform32(nxt.y);
-      nxt = sg[i + 1 < cn ? i + 1 : i];
+      nxt = sg[i + 1];
       const uint32_t op = w0 & 0xffu, q = (w0 >> 8) & 0xffu, r = (w0 >> 16) & 0xffu;
       const uint32_t cond = (w1 >> 16) & 0xffu;
-      if (cond & kSlotStart) {
-        cur_b = next_b;
-        if (occ < n_occ) next_b = uniform32(branch[(uint64_t)seq[occ] * chb + ba]);
-        ++occ;
+      if (cond) {  // a slot's first gate, or a gate of some branches only (uniform here)
+        if (cond & kSlotStart) {
+          cur_b = next_b;
+          if (occ < n_occ) next_b = uniform32(branch[(uint64_t)seq[occ] * chb + ba]);
+          ++occ;
+        }
+        if ((cond & kCondApply) && !(((w1 >> 24) >> cur_b) & 1u)) continue;
       }
-      const bool on = !(cond & kCondApply) || ((w1 >> 24) >> cur_b & 1u);
-      if (!on) continue;
-      if (op == OP_H) {
-        // Hadamard on qubit q: Eqs. (H2), (H4), the t = u case, Prop. H.
-        const uint64_t Fp = rl64(F, q), Gp = rl64(G, q), Mp = rl64(M, q);
-        const uint32_t gp = rl32(g, q);
-        const uint64_t nv = ~v;
-        const uint64_t t = s ^ (Gp & v);
-        const uint64_t u = s ^ (Fp & nv) ^ (Mp & v);
-        const uint32_t alpha = par64(Gp & nv & s);
-        const uint32_t beta = par64(Mp & nv & s) ^ par64(Fp & v & (Mp ^ s));
-        const uint32_t delta = (gp + 2u * (alpha + beta)) & 3u;
-        if (t == u) {
-          // omega' = 2^{-1/2} (-1)^alpha (1 + i^delta), delta odd.
-          if (!(delta & 1u)) e = 1u;
-          w = (w + 4u * alpha + (delta == 1u ? 1u : 7u)) & 7u;
-          s = t;
-          continue;
+      switch (op) {
+        case OP_CZ: {
+          // M_q ^= G_r, M_r ^= G_q.
+          const uint64_t Gq = rl64(G, q), Gr = rl64(G, r);
+          if (lane == q) M ^= Gr;
+          if (lane == r) M ^= Gq;
+          break;
         }
-        superpose_w64(F, G, M, g, v, s, w, t, u, alpha, delta);
-      } else if (op == OP_CX) {
-        // gamma_q += gamma_r + 2 (M_q . F_r) (M_q before the update);
-        // G_r ^= G_q; F_q ^= F_r; M_q ^= M_r.
-        const uint64_t Fr = rl64(F, r), Mr = rl64(M, r), Gq = rl64(G, q), Mq = rl64(M, q);
-        const uint32_t gr = rl32(g, r);
-        if (lane == q) {
-          g = (g + gr + 2u * par64(Mq & Fr)) & 3u;
-          F ^= Fr;
-          M ^= Mr;
+        case OP_CX: {
+          // gamma_q += gamma_r + 2 (M_q . F_r) (M_q before the update);
+          // G_r ^= G_q; F_q ^= F_r; M_q ^= M_r.
+          const uint64_t Fr = rl64(F, r), Mr = rl64(M, r), Gq = rl64(G, q), Mq = rl64(M, q);
+          const uint32_t gr = rl32(g, r);
+          if (lane == q) {
+            g = (g + gr + 2u * par64(Mq & Fr)) & 3u;
+            F ^= Fr;
+            M ^= Mr;
+          }
+          if (lane == r) G ^= Gq;
+          break;
         }
-        if (lane == r) G ^= Gq;
-      } else if (op == OP_CZ) {
-        // M_q ^= G_r, M_r ^= G_q.
-        const uint64_t Gq = rl64(G, q), Gr = rl64(G, r);
-        if (lane == q) M ^= Gr;
-        if (lane == r) M ^= Gq;
-      } else {
-        // S^pw on q: M_q ^= G_q pw times, gamma_q -= pw.
-        uint32_t pw = 1u;
-        if (op == OP_SLOT_SPOW) pw = ((w0 >> 16) >> (2u * cur_b)) & 3u;
-        else if (op == OP_SPOW) pw = w0 >> 24;
-        if (lane == q) {
-          if (pw & 1u) M ^= G;
-          g = (g - pw) & 3u;
+        case OP_H: {
+          // Hadamard on qubit q: Eqs. (H2), (H4), the t = u case, Prop. H.
+          const uint64_t Fp = rl64(F, q), Gp = rl64(G, q), Mp = rl64(M, q);
+          const uint32_t gp = rl32(g, q);
+          const uint64_t nv = ~v;
+          const uint64_t t = s ^ (Gp & v);
+          const uint64_t u = s ^ (Fp & nv) ^ (Mp & v);
+          const uint32_t alpha = par64(Gp & nv & s);
+          const uint32_t beta = par64(Mp & nv & s) ^ par64(Fp & v & (Mp ^ s));
+          const uint32_t delta = (gp + 2u * (alpha + beta)) & 3u;
+          if (t == u) {
+            // omega' = 2^{-1/2} (-1)^alpha (1 + i^delta), delta odd.
+            if (!(delta & 1u)) e = 1u;
+            w = (w + 4u * alpha + (delta == 1u ? 1u : 7u)) & 7u;
+            s = t;
+            break;
+          }
+          superpose_w64(F, G, M, g, v, s, w, t, u, alpha, delta);
+          break;
+        }
+        default: {
+          // S^pw on q: M_q ^= G_q pw times, gamma_q -= pw.
+          const uint32_t pw = op == OP_SLOT_SPOW ? ((w0 >> 16) >> (2u * cur_b)) & 3u : op == OP_SPOW ? (w0 >> 24) : 1u;
+          if (lane == q) {
+            if (pw & 1u) M ^= G;
+            g = (g - pw) & 3u;
+          }
+          break;
         }
       }
     }
