@@ -936,8 +936,12 @@ chsim_status chsim_apply_clifford(chsim_ctx* ctx, uint32_t inst, const chsim_gat
         push_gate(dg, g);
       }
     }
-    HIP_TRY(ctx->gates.ensure(dg.size()));
+    // One padding entry past the last gate: the LDS kernel reads the gate
+    // after the current one without a bound check.
+    static const DGate kPadGate = {OP_S, 0, 0, 0, 0, 0, 0};
+    HIP_TRY(ctx->gates.ensure(dg.size() + 1));
     HIP_TRY(hipMemcpyAsync(ctx->gates.p, dg.data(), dg.size() * sizeof(DGate), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(ctx->gates.p + dg.size(), &kPadGate, sizeof(DGate), hipMemcpyHostToDevice, s));
     ctx->occ_start.clear();
     ctx->slotseq_h.clear();
     for (size_t i = 0; i < dg.size(); ++i)

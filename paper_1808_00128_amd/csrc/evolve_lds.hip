@@ -97,11 +97,13 @@ __global__ __launch_bounds__(256) void k_evolve_lds(EvolveJob J, const DGate* __
   uint32_t next_b = n_occ ? (uint32_t)branch[(uint64_t)seq[0] * chb + ba] : 0u;
   uint32_t cur_b = 0u, occ = 1u;
   // Gates are two 32-bit words read on the scalar unit, the next one in
-  // flight while the current one is applied.
+  // flight while the current one is applied (the device list has one
+  // padding entry past its last gate, so the read past a span's end is in
+  // bounds).
   uint2 nxt = n_gates ? g2[0] : make_uint2(0u, 0u);
   for (uint32_t i = 0; i < n_gates; ++i) {
     const uint32_t w0 = uniform32(nxt.x), w1 = uniform32(nxt.y);
-    nxt = g2[i + 1 < n_gates ? i + 1 : i];
+    nxt = g2[i + 1];  // the device list holds one entry past its end
     const uint32_t op = w0 & 0xffu, q = (w0 >> 8) & 0xffu;
     const uint32_t cond = (w1 >> 16) & 0xffu;
     if (cond & kSlotStart) {
@@ -109,7 +111,8 @@ __global__ __launch_bounds__(256) void k_evolve_lds(EvolveJob J, const DGate* __
       if (occ < n_occ) next_b = (uint32_t)branch[(uint64_t)seq[occ] * chb + ba];
       ++occ;
     }
-    const bool on = !(cond & kCondApply) || ((w1 >> 24) >> cur_b & 1u);
+    bool on = true;  // per lane: the term's branch choice decides a conditional gate
+    if (cond & kCondApply) on = ((w1 >> 24) >> cur_b & 1u) != 0u;
     const uint32_t kq = q / LPT, lq = q % LPT;
     if (op == OP_H) {
       if (!on) continue;
