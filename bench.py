@@ -50,7 +50,7 @@ def algorithmic_ops_evolve(stats, n):
                  + stats["cond"] * 12)
 
 
-def survey_ops_evolve(stats, n):
+def table_ops_evolve(stats, n):
     """The same executed gate applications at the hot-path table's per-unit
     figure: 35 int32 operations per tableau row (n rows) per Hadamard and 10
     per other gate."""
@@ -366,7 +366,7 @@ def own_chain_step_bytes(chi, n_chain, win=METRO_WINDOW):
     return float(chi * (8 * n_chain + 8 * n_chain / win + 17 * (1 + (win + 1) / 2) + 33))
 
 
-def survey_chain_step_bytes(chi, n_chain):
+def table_chain_step_bytes(chi, n_chain):
     """The hot-path table's per-step bytes for single flips with one j per step
     shared by all chains: 16 B of state read + write per chain, 17 B for row j
     of F, M, gamma and 33 B of term constants per term."""
@@ -411,7 +411,7 @@ def bench_learned(torch, B, W, stats, steps=1000, n_chain=64, chi=1 << 20, eps=0
     cost = stats.qaoa_cost(tr[:, burn:], cfg["triples"], cfg["d"])
     plain = chain_report(stats, tr, ac, ms, burn, cost)
     plain["hip_graph"] = graph
-    sbytes = survey_chain_step_bytes(chi, n_chain)
+    sbytes = table_chain_step_bytes(chi, n_chain)
     achieved = sbytes * steps / (ms / 1e3) / 1e9
     obytes = own_chain_step_bytes(chi, n_chain)
     plain["roofline"] = roof("hbm", achieved, HBM_PEAK_BPS / 1e9, "GB/s", MEASURED.get("hbm"),
@@ -656,7 +656,7 @@ def bench_hidden_shift(torch, B, W, steps=5, warmup=2):
     # = 8.25 int32 ops per CCZ per evolved state.
     ops_ev = float(st["H"] * (28 * n + 40) + st["CX"] * 12 + st["CZ"] * 4 + st["S"] * 3
                    + st["cond"] / 6 * 8.25)
-    ops_sv = survey_ops_evolve(st, n)
+    ops_sv = table_ops_evolve(st, n)
     evals = float(chi * n_x)
     achieved = ops_sv / (ms_ev / 1e3) / 1e12
     return {"workload": cfg["name"] + f": n={n}, {cfg['n_ccz']} CCZ (8 Clifford branches each), "
@@ -796,7 +796,7 @@ def main():
     ev_stats = ctx.evolution_stats()
     lds_pair, packed_frac = amp_lds_bytes_per_pair(n, ctx.get_terms(0, min(chi, 4096))["v"])
     ops_ev = algorithmic_ops_evolve(ev_stats, n)
-    ops_sv = survey_ops_evolve(ev_stats, n)
+    ops_sv = table_ops_evolve(ev_stats, n)
     ops_amp = algorithmic_ops_amp(xs) * chi * n_x
     ms_ev = float(np.mean(phase["evolve"]))
     ms_amp = float(np.mean(phase["amplitudes"]))

@@ -54,9 +54,9 @@ def test_evolution_counts():
                              ("cond", 12, 10)):
         st = dict(one, **{kind: 1})
         assert bench.algorithmic_ops_evolve(st, 50) == own
-        assert bench.survey_ops_evolve(st, 50) == table
+        assert bench.table_ops_evolve(st, 50) == table
     st = dict(H=3, CX=5, CZ=7, S=11, cond=13)
-    assert bench.survey_ops_evolve(st, 40) == 3 * 35 * 40 + (5 + 7 + 11 + 13) * 10
+    assert bench.table_ops_evolve(st, 40) == 3 * 35 * 40 + (5 + 7 + 11 + 13) * 10
 
 
 def test_amplitude_lds_bytes_per_pair():
@@ -73,7 +73,7 @@ def test_amplitude_lds_bytes_per_pair():
 
 def test_chain_step_bytes():
     chi, n, c = 1 << 20, 50, 64
-    assert bench.survey_chain_step_bytes(chi, c) == chi * (16 * c + 50)
+    assert bench.table_chain_step_bytes(chi, c) == chi * (16 * c + 50)
     assert bench.chain_step_bytes(chi, n, c) == chi * (17 * n + 16 * c + 33)
     # window of 4: word read every step, written once per window, 2.5 pending rows
     assert bench.own_chain_step_bytes(chi, c, 4) == chi * (8 * c + 2 * c + 17 * 3.5 + 33)
