@@ -87,10 +87,12 @@ CASES = [
     (50, 800, 20, 1000, "sparsify"),
     (63, 800, 12, 129, "sparsify"),
     (64, 900, 12, 200, "sparsify"),
+    # longer than the 2048 gates the one-term-per-wave kernel stages at a time
+    (20, 4500, 8, 64, "sparsify"),
 ]
 
 
-@pytest.mark.parametrize("case", CASES, ids=[f"n{c[0]}-chi{c[3]}" for c in CASES])
+@pytest.mark.parametrize("case", CASES, ids=[f"n{c[0]}-g{c[1]}-chi{c[3]}" for c in CASES])
 def test_evolution_bit_exact(B, case):
     """Every evolution shape (lanes per term 4, 8, 16, 32, 64 with ceil(n / lanes)
     rows per lane in registers; 4, 8, 16 lanes with the rows in LDS) gives the
