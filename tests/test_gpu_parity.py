@@ -204,15 +204,21 @@ def test_evolution_autotune_keeps_results(B):
     compare_terms(ctx, T, idx)
 
 
-def test_evolution_in_segments_matches_one_pass(B):
-    """apply_clifford on consecutive segments equals one call on the whole circuit."""
+@pytest.mark.parametrize("lanes", [None, 8 | 0x100, 64], ids=["tuned", "lds8", "wave"])
+def test_evolution_in_segments_matches_one_pass(B, lanes):
+    """apply_clifford on consecutive segments (one-gate segments among them:
+    the kernels read the gate after a segment's last from the list's padding)
+    equals one call on the whole circuit, in the tuned, the LDS and the
+    one-term-per-wave mappings."""
     rng = np.random.default_rng(5)
     circ = W.random_circuit(20, 300, rng.uniform(0, 2 * np.pi, size=6), rng)
     spec = dict(circuit=circ, chi=96, mode="sparsify", seed=3)
-    say("evolution segments")
+    say(f"evolution segments lanes={lanes}")
     ctx = B.Context([spec])
+    if lanes is not None:
+        ctx.set_evolve_lanes(lanes)
     g = B.gate_array(circ)
-    for lo, hi in ((0, 50), (50, 51), (51, 200), (200, g.size)):
+    for lo, hi in ((0, 1), (1, 50), (50, 51), (51, 200), (200, g.size - 1), (g.size - 1, g.size)):
         ctx.apply_gates(g[lo:hi])
     T = O.Terms(circ, 96, O.SPARSIFY, seed=3)
     compare_terms(ctx, T, np.arange(96, dtype=np.uint64))
