@@ -238,9 +238,10 @@ __global__ __launch_bounds__(64 * kCHWaves, 8) void k_inner_ch_pairs(
   // The bra's part of t = Bs d and tu = Bu d by nibbles of d: tables of the
   // XOR of each subset of 4 consecutive rows of Bs_b (and of Bu_b), built once
   // for the wave's bra state and read with a lane's own index (t_d = XOR over
-  // nibble groups g of tab[g][nibble g of d]).
-  __shared__ uint64_t tabs[kCHWaves][2][16][16];
-  uint64_t(*const tab)[16][16] = tabs[uniform32(threadIdx.x >> 6)];
+  // nibble groups g of tab[g][nibble g of d]); an entry holds the Bs and Bu
+  // words side by side, so one 16-byte read serves both.
+  __shared__ __align__(16) uint64_t tabs[kCHWaves][16][16][2];
+  uint64_t(*const tab)[16][2] = tabs[uniform32(threadIdx.x >> 6)];
   // Scratch for moving a pair's free variables to lanes 0, 1, ...
   __shared__ uint64_t cds[kCHWaves][32], cws[kCHWaves][32];
   __shared__ uint32_t ces[kCHWaves][32];
@@ -257,12 +258,17 @@ __global__ __launch_bounds__(64 * kCHWaves, 8) void k_inner_ch_pairs(
       const uint64_t val = lane < 16u ? R : (R & ((1ull << q) - 1ull));
       if (((lane & 15u) >> b) & 1u) acc ^= val;
     }
-    if (lane < 32u) tab[lane >> 4][g][lane & 15u] = acc;
+    if (lane < 32u) tab[g][lane & 15u][lane >> 4] = acc;
   }
-  auto lookup = [&](uint32_t which, uint64_t x) {
-    uint64_t r = 0;
-    for (uint32_t g = 0; g < ngrp; ++g) r ^= tab[which][g][(x >> (4u * g)) & 15u];
-    return r;
+  // (Bs_b d, Bu_b d) for one d.
+  auto lookup2 = [&](uint64_t x, uint64_t& rs, uint64_t& ru) {
+    rs = 0;
+    ru = 0;
+    for (uint32_t g = 0; g < ngrp; ++g) {
+      const ulonglong2 e = *reinterpret_cast<const ulonglong2*>(tab[g][(x >> (4u * g)) & 15u]);
+      rs ^= e.x;
+      ru ^= e.y;
+    }
   };
   double accr = 0.0, acci = 0.0;
   uint32_t bad = 0;
@@ -342,7 +348,9 @@ __global__ __launch_bounds__(64 * kCHWaves, 8) void k_inner_ch_pairs(
     // tu_f = Bu d_f with Bu its strictly upper part (column q of Bu is row q of
     // Bs below bit q), so that d^T B d = par(d & diag) + par(d & Bu d).
     const uint64_t Bs = Bsk ^ Bsb;
-    const uint64_t t = tk ^ lookup(0, d), tu = tuk ^ lookup(1, d);
+    uint64_t tb, tub;
+    lookup2(d, tb, tub);
+    const uint64_t t = tk ^ tb, tu = tuk ^ tub;
     const uint64_t above = (lane >= 63u) ? 0ull : (~0ull << (lane + 1u));
     const uint64_t tu0 = ballot64(act && par64(Bs & above & x0));
     const uint64_t Bd = diag_k ^ diag_b, gd = glo_k ^ glo_b;
